@@ -1,0 +1,125 @@
+"""Pins of the oracle FGMRES and block preconditioner (Sections 2.2 and 4)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import synth
+from oracle import cnn, fem, krylov
+
+
+def random_spd(n, seed):
+    rng = np.random.default_rng(seed)
+    B = rng.normal(size=(n, n))
+    return B @ B.T + n * np.eye(n)
+
+
+@pytest.mark.parametrize("n", [4, 7, 20, 50])
+def test_gmres_textbook_finite_termination(n):
+    """P = I, m >= n: converges in at most n steps, to the dense solution."""
+    A = random_spd(n, n)
+    b = np.random.default_rng(1).normal(size=n)
+    r = krylov.fgmres(sp.csr_matrix(A), b, restart=n, tol=1e-12, max_iters=n)
+    assert r.converged and r.iters <= n
+    assert np.allclose(r.x, np.linalg.solve(A, b), rtol=1e-9, atol=1e-12)
+
+
+def test_residual_estimate_equals_true_residual():
+    """rho_j = |g_{j+1}| equals ||b - A x_j|| (x_j the j-step iterate) and is monotone."""
+    A = random_spd(40, 3) + np.triu(np.random.default_rng(4).normal(size=(40, 40)), 1)  # non-symmetric
+    b = np.random.default_rng(5).normal(size=40)
+    full = krylov.fgmres(sp.csr_matrix(A), b, restart=25, tol=1e-30, max_iters=25)
+    assert np.all(np.diff(full.history) <= 1e-15)
+    for k in range(1, 25):
+        part = krylov.fgmres(sp.csr_matrix(A), b, restart=k, tol=1e-30, max_iters=k)
+        true = np.linalg.norm(b - A @ part.x) / np.linalg.norm(b)
+        assert full.history[k - 1] == pytest.approx(true, rel=1e-9)
+
+
+def test_exact_preconditioner_one_step():
+    A = random_spd(30, 8)
+    b = np.ones(30)
+    Ainv = np.linalg.inv(A)
+    r = krylov.fgmres(sp.csr_matrix(A), b, precond=lambda v: Ainv @ v, restart=10, tol=1e-12)
+    assert r.iters == 1 and r.converged
+
+
+def test_hessenberg_matches_arnoldi_relation():
+    """Unrotated Arnoldi relation A Z_j = V_{j+1} H_j checked through a second,
+    dense computation of the least-squares minimiser."""
+    A = random_spd(25, 9) + 0.3 * np.random.default_rng(2).normal(size=(25, 25))
+    b = np.random.default_rng(6).normal(size=25)
+    D = np.diag(A).copy()
+    r = krylov.fgmres(sp.csr_matrix(A), b, precond=lambda v: v / D, restart=8, tol=1e-30,
+                      max_iters=8)
+    # the 8-step iterate minimises ||b - A x|| over x in span(D^-1 K_8(A D^-1, b))
+    Kb = [b / np.linalg.norm(b)]
+    for _ in range(7):
+        Kb.append(A @ (Kb[-1] / D))
+        Kb[-1] /= np.linalg.norm(Kb[-1])
+    Q, _ = np.linalg.qr(np.stack(Kb, axis=1))
+    Zs = Q / D[:, None]
+    y, *_ = np.linalg.lstsq(A @ Zs, b, rcond=None)
+    assert np.allclose(r.x, Zs @ y, rtol=1e-8, atol=1e-10)
+
+
+def _c1():
+    return fem.assemble(synth.workload_single_fp64()[0])
+
+
+def test_jacobi_gmres_c1_converges_to_direct_solution():
+    s = _c1()
+    r = krylov.fgmres(s.A, s.F, precond=krylov.jacobi(s.A), restart=50, tol=1e-8, max_iters=20000)
+    assert r.converged and r.rel_res <= 1e-8
+    xs = krylov.direct_solve(s)
+    # error bounded by cond(A) * residual
+    assert np.linalg.norm(r.x - xs) / np.linalg.norm(xs) < 1e-5
+
+
+def test_block_preconditioner_exact_blocks_spectrum():
+    """With exact A00^-1 and A11^-1, A Q has eigenvalue 1 (multiplicity N3D) and the
+    eigenvalues of S A11^-1 (S = A11 - A10 A00^-1 A01), all in (0, 1]; FGMRES then
+    terminates in at most N1D + 1 steps."""
+    inst = synth.make_instance(5, 8, n_segments=3, elems_per_segment=3, radius=0.02, beta=1.0)
+    s = fem.assemble(inst)
+    A00, A01, A10, A11 = (b.toarray() for b in s.blocks())
+    Q = krylov.BlockPreconditioner(s, krylov.p3d_exact(s))
+    n = s.n
+    AQ = np.stack([s.A @ Q(e) for e in np.eye(n)], axis=1)
+    ev = np.sort(np.linalg.eigvals(AQ).real)
+    S = A11 - A10 @ np.linalg.solve(A00, A01)
+    evS = np.sort(np.linalg.eigvals(S @ np.linalg.inv(A11)).real)
+    assert evS.min() > 0 and evS.max() <= 1 + 1e-12
+    expect = np.sort(np.concatenate([np.ones(s.n3d), evS]))
+    assert np.allclose(ev, expect, atol=1e-9)
+    r = krylov.fgmres(s.A, s.F, precond=Q, restart=s.n1d + 5, tol=1e-10, max_iters=s.n1d + 5)
+    assert r.converged and r.iters <= s.n1d + 1
+
+
+def test_fgmres_invariant_to_rescaled_preconditioner():
+    """FGMRES iterates depend on span(Z) only: multiplying each z_j of a nonlinear
+    (random-network) block preconditioner by a different positive factor leaves
+    the residual history and the solution unchanged."""
+    inst = synth.make_instance(3, 8, n_segments=4, elems_per_segment=3, radius=0.02, beta=1.0)
+    s = fem.assemble(inst)
+    theta = cnn.init_params(1)
+    net = lambda X: cnn.forward(theta, X)[0]
+    p1 = krylov.p3d_neural(s, net)
+    Q1 = krylov.BlockPreconditioner(s, p1)
+    scales = iter([7.3, 0.25, 3.0] * 20)
+    Q2 = lambda v: next(scales) * Q1(v)
+    r1 = krylov.fgmres(s.A, s.F, precond=Q1, restart=10, tol=1e-8, max_iters=30)
+    r2 = krylov.fgmres(s.A, s.F, precond=Q2, restart=10, tol=1e-8, max_iters=30)
+    assert r1.iters == r2.iters
+    assert np.allclose(r1.history, r2.history, rtol=1e-7)
+    assert np.allclose(r1.x, r2.x, rtol=1e-7, atol=1e-12)
+
+
+def test_tree_solve_block_is_exact():
+    s = _c1()
+    A00, A01, A10, A11 = s.blocks()
+    Q = krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s))
+    v1 = np.random.default_rng(0).normal(size=s.n1d)
+    z = Q.solve_1d(v1)
+    zd = np.linalg.solve(A11.toarray(), v1)
+    assert np.linalg.norm(z - zd) / np.linalg.norm(zd) < 1e-13
