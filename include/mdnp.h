@@ -1,0 +1,265 @@
+/*
+ * mdnp.h -- C ABI of the MI355X library for the neural-preconditioned flexible
+ * GMRES solve of the coupled 3D-1D finite-element system.
+ *
+ * The problem (Section 2 of the paper): for a parameter mu, i.e. a 1D vessel
+ * tree Lambda inside the unit cube, solve A^mu u = F^mu where
+ *     A = [K00 0; 0 K11] + 2 pi eps [M00 M01; M10 M11]      (eq. "mainsys")
+ * with K00 the 3D stiffness, K11 the 1D stiffness on the tree and M the
+ * averaging/extension coupling.  The solver is right-preconditioned,
+ * restarted flexible GMRES (Section 4), stopped on ||b - A x|| / ||b|| <= tol
+ * (Section 5.1), with the block upper-triangular preconditioner of Section 2.2
+ * (eq. "twosteps"): an exact 1D solve, then the 3D correction handed to the
+ * neural operator P(v, d) (eq. "decoupled_3d_problem"), a U-net of Section 4.2
+ * whose second input channel is the distance field d of the tree.
+ *
+ * Conventions for every call:
+ *   - the return value is an mdnp_status; 0 means success; no C++ exception
+ *     crosses this boundary; mdnp_last_error() gives a message;
+ *   - "host" pointers are read (or written) during the call only and stay
+ *     owned by the caller; "device" pointers are borrowed, must be valid
+ *     device memory on the context's GPU, and are used in stream order on
+ *     the given HIP stream (NULL = the context's stream);
+ *   - one context per thread; calls on one context are not thread-safe;
+ *   - non-convergence is not an error (see mdnp_inst_stats.converged).
+ *
+ * Vector layout of a system of n_inst instances: instances are concatenated;
+ * instance i occupies [offset_i, offset_i + n3d + n1d_i), its 3D unknowns first
+ * (grid node i + n j + n^2 k, n = n_cells + 1, x fastest), then its 1D
+ * unknowns (tree vertices, then the interior nodes of segment s numbered
+ * V + s (E - 1) + t from the parent end).
+ */
+#ifndef MDNP_H
+#define MDNP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mdnp_ctx mdnp_ctx;
+typedef struct mdnp_sys mdnp_sys;
+
+typedef enum {
+  MDNP_OK = 0,
+  MDNP_E_ARG = -1,        /* invalid argument or size                       */
+  MDNP_E_HIP = -2,        /* a HIP runtime call failed                      */
+  MDNP_E_OOM = -3,        /* device allocation failed                       */
+  MDNP_E_GEOM = -4,       /* invalid geometry (vertex outside, R <= 0, ...) */
+  MDNP_E_NONFINITE = -5,  /* NaN/Inf in b, x0 or the weights                */
+  MDNP_E_STATE = -6       /* call out of order (e.g. no preconditioner set) */
+} mdnp_status;
+
+typedef enum {
+  MDNP_PREC_NONE = 0,         /* z = v                                                    */
+  MDNP_PREC_JACOBI = 1,       /* z = diag(A)^-1 v  (Jacobi-preconditioned GMRES)           */
+  MDNP_PREC_NEURAL = 2,       /* block preconditioner of eq. "twosteps", 3D block by the U-net */
+  MDNP_PREC_BLOCK_JACOBI = 3  /* same block preconditioner with diag(A00)^-1 for the 3D block
+                                 (the method without the network)                          */
+} mdnp_prec_kind;
+
+typedef enum { MDNP_F64 = 0, MDNP_F32 = 1, MDNP_BF16 = 2, MDNP_FP8E4M3 = 3 } mdnp_dtype;
+
+/* One parameter instance mu (Section 2.1).  All arrays are host memory, copied
+ * by mdnp_upload.  The segments must form a tree rooted at vertex 0 with
+ * seg_vertices[2s] the parent end and seg_vertices[2s+1] the child end of
+ * segment s; every vertex lies strictly inside the unit cube. */
+typedef struct {
+  int32_t n_cells;                 /* 3D cells per side; n = n_cells + 1 grid nodes per side   */
+  double k_omega, sigma_omega;     /* 3D diffusion and reaction coefficients (eq. "aomega")    */
+  int32_t n_vertices;
+  const double* vertex_xyz;        /* [n_vertices * 3]                                         */
+  int32_t n_segments;
+  const int32_t* seg_vertices;     /* [n_segments * 2] (parent, child)                         */
+  const double* seg_radius;        /* [n_segments] vessel radius R (eps of the paper)           */
+  const double* seg_beta;          /* [n_segments] wall permeability; coupling c = 2 pi R beta  */
+  int32_t elems_per_segment;       /* P1 elements per segment                                   */
+  double k_lambda;                 /* 1D diffusion; the 1D operator carries the area pi R^2     */
+  double f_lambda;                 /* line source on the tree; F = [0; int f phi]               */
+  int32_t n_circle;                /* points of the cross-section average T_Lambda (>= 3)       */
+} mdnp_instance_desc;
+
+typedef struct {
+  int32_t restart;            /* m, Arnoldi steps per cycle                                  */
+  int32_t max_iters;          /* cap on Arnoldi steps per instance (all cycles)              */
+  int32_t fallback_restart;   /* restart used once every active instance is on the fallback  */
+  int32_t fallback_max_iters; /* extra steps allowed on the Jacobi fallback (0 = none)       */
+  double tol;                 /* stop when ||b - A x|| <= tol ||b||                          */
+  int32_t record_history;     /* keep rho_j / ||b|| per step for mdnp_history               */
+  int32_t use_graph;          /* capture one restart cycle in a HIP graph and replay it      */
+} mdnp_solve_opts;
+
+typedef struct {
+  int32_t iters;            /* Arnoldi steps (= preconditioner applications) before fallback */
+  int32_t fallback_iters;   /* Arnoldi steps taken on the Jacobi fallback                  */
+  int32_t converged;        /* 1 when the true relative residual met tol                   */
+  int32_t used_fallback;    /* 1 when the stall detector switched this instance to Jacobi  */
+  double final_rel_res;     /* true ||b - A x|| / ||b|| recomputed in FP64 at the end      */
+} mdnp_inst_stats;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `hip_device`; `hip_stream` (may be NULL) is the
+ * default stream of all calls.  The caller keeps ownership of the stream. */
+mdnp_status mdnp_create(mdnp_ctx** out, int hip_device, void* hip_stream);
+mdnp_status mdnp_destroy(mdnp_ctx* ctx);
+/* Message of the last failed call on this context (never NULL). */
+const char* mdnp_last_error(const mdnp_ctx* ctx);
+
+/* ---------------------------------------------------------------- systems */
+
+/* Assemble A, F, the distance field d and the 1D factorisation for n_inst
+ * instances (Section 2.1, eq. "mainsys"; distance channel of Section 2.1) and
+ * copy them to the device.  All instances must share n_cells.  vec_dtype is
+ * the storage type of the Krylov vectors and of the inner SpMV values:
+ * MDNP_F64 (all FP64) or MDNP_F32 (FP32 vectors, FP64 orthogonalisation,
+ * least squares, solution and true residual).  Errors: MDNP_E_ARG, MDNP_E_GEOM,
+ * MDNP_E_OOM, MDNP_E_HIP.  *out is owned by the context; free with
+ * mdnp_sys_free. */
+mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* descs, int32_t n_inst,
+                        mdnp_dtype vec_dtype, mdnp_sys** out);
+mdnp_status mdnp_sys_free(mdnp_ctx* ctx, mdnp_sys* sys);
+
+/* Sizes of instance `inst`: 3D and 1D unknowns, nonzeros of its CSR block and
+ * its offset in the concatenated vectors. */
+mdnp_status mdnp_sys_sizes(const mdnp_sys* sys, int32_t inst, int32_t* n3d, int32_t* n1d,
+                           int64_t* nnz, int64_t* offset);
+
+/* Host copy of the assembled matrix of one instance in CSR with local indices
+ * (row_ptr [n+1], col [nnz], val [nnz], n = n3d + n1d): columns ascending,
+ * duplicates merged, zero values kept where the pattern has them, Dirichlet
+ * rows equal to the unit row.  Any output pointer may be NULL. */
+mdnp_status mdnp_export_csr(const mdnp_sys* sys, int32_t inst, int32_t* row_ptr, int32_t* col,
+                            double* val);
+
+/* Host copy of the right-hand side F [n], the distance field d [n3d] and the
+ * network normalisation alpha = RMS of diag(A00) over the free 3D nodes
+ * (Section 5.1).  Any output pointer may be NULL. */
+mdnp_status mdnp_export_rhs(const mdnp_sys* sys, int32_t inst, double* F, double* dist,
+                            double* alpha);
+
+/* ---------------------------------------------------------------- preconditioner */
+
+/* Select the right preconditioner of the solve.  For MDNP_PREC_NEURAL, `weights`
+ * (host, FP32, n_weights = 353713) holds the U-net parameters layer by layer,
+ * each as [Cout][kz][ky][kx][Cin] then the bias, layers in the order
+ * L0a L0b L1a L1b L2a L2b U1 D1 U0 D0 H; cnn_dtype is the arithmetic of the
+ * network (MDNP_F32 or MDNP_BF16; FP32 accumulation).  alpha <= 0 keeps each
+ * instance's own alpha.  Requires n_cells divisible by 4.  Errors: MDNP_E_ARG,
+ * MDNP_E_NONFINITE. */
+mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* sys, mdnp_prec_kind kind,
+                                    const float* weights, int64_t n_weights, double alpha,
+                                    mdnp_dtype cnn_dtype);
+
+/* ---------------------------------------------------------------- solve */
+
+/* Restarted right-preconditioned FGMRES(m) on every instance at once (Section
+ * 4; stopping rule of Section 5.1 with x0 as given): b and x are host arrays of
+ * the concatenated length, x holds x0 on entry and the solution on return;
+ * stats [n_inst] may be NULL.  An instance whose true relative residual falls
+ * by less than 10% over a cycle, becomes non-finite, or reaches max_iters
+ * unconverged is switched to Jacobi-preconditioned GMRES from its current x
+ * for up to fallback_max_iters more steps.  Errors: MDNP_E_ARG,
+ * MDNP_E_NONFINITE (b or x0), MDNP_E_STATE (no preconditioner set). */
+mdnp_status mdnp_solve(mdnp_ctx* ctx, mdnp_sys* sys, const double* b, double* x,
+                       const mdnp_solve_opts* opts, mdnp_inst_stats* stats);
+
+/* Same with device buffers d_b, d_x (FP64, concatenated) on `hip_stream`. */
+mdnp_status mdnp_solve_device(mdnp_ctx* ctx, mdnp_sys* sys, const double* d_b, double* d_x,
+                              const mdnp_solve_opts* opts, mdnp_inst_stats* stats,
+                              void* hip_stream);
+
+/* Residual history of the last solve of instance `inst`: rho_j / ||b|| after
+ * every Arnoldi step, and the true relative residual at the start of every
+ * cycle stored negated.  Copies at most cap values to out (host); *n_out
+ * receives the number available. */
+mdnp_status mdnp_history(const mdnp_sys* sys, int32_t inst, double* out, int32_t cap,
+                         int32_t* n_out);
+
+/* Copy Arnoldi vector v_k (0 <= k <= restart) of the last cycle of the last
+ * solve into d_out (device, vec_dtype, concatenated length): the
+ * solver-generated residual samples used to train the network (Section 4.1,
+ * Krylov augmentation).  Errors: MDNP_E_STATE before any solve. */
+mdnp_status mdnp_export_basis(mdnp_ctx* ctx, const mdnp_sys* sys, int32_t k, void* d_out, void* hip_stream);
+
+/* ---------------------------------------------------------------- path steps (device) */
+
+/* y = A x (block 0) or y = A00 x on the 3D unknowns only (block 1, vectors of
+ * length n_inst * n3d), for every instance.  dtype MDNP_F64 or MDNP_F32 selects
+ * the value array and the vector type. */
+mdnp_status mdnp_spmv(mdnp_ctx* ctx, mdnp_sys* sys, int32_t block, const void* d_x, void* d_y,
+                      mdnp_dtype dtype, void* hip_stream);
+
+/* z1 = A11^-1 v1 for every instance: the exact 1D solve of eq. "twosteps" by a
+ * leaves-first LDL^T factorisation of the tree matrix (no fill).  d_v and d_z
+ * are full concatenated vectors of the system's vec_dtype; only the 1D parts
+ * are read and written. */
+mdnp_status mdnp_tree_solve(mdnp_ctx* ctx, mdnp_sys* sys, const void* d_v, void* d_z,
+                            void* hip_stream);
+
+/* z = Q(v): one application of the selected preconditioner to one vector per
+ * instance (vec_dtype, concatenated).  For the block kinds: the 1D solve, the
+ * extension b0 = v0 - A01 z1 (eq. "decoupled_3d_problem"), then the 3D block
+ * operator. */
+mdnp_status mdnp_precond_apply(mdnp_ctx* ctx, mdnp_sys* sys, const void* d_v, void* d_z,
+                               void* hip_stream);
+
+/* U-net forward on a batch: d_x is [batch][n][n][n][2] FP32 (channel 0 the
+ * normalised residual, channel 1 the distance), d_y is [batch][n][n][n] FP32.
+ * d_w is the flat FP32 weight vector (device).  When d_saved is non-NULL the
+ * layer activations needed by mdnp_cnn_backward are written there (size from
+ * mdnp_cnn_saved_bytes).  dtype MDNP_F32 or MDNP_BF16. */
+mdnp_status mdnp_cnn_forward(mdnp_ctx* ctx, const float* d_w, const float* d_x, float* d_y,
+                             void* d_saved, int32_t batch, int32_t n, mdnp_dtype dtype,
+                             void* hip_stream);
+int64_t mdnp_cnn_saved_bytes(int32_t batch, int32_t n, mdnp_dtype dtype);
+
+/* Adjoint of mdnp_cnn_forward: given dy [batch][n^3] FP32, accumulate nothing,
+ * write the weight gradient d_dw [353713] (FP32, overwritten) and, when d_dx
+ * is non-NULL, the input gradient [batch][n^3][2]. */
+mdnp_status mdnp_cnn_backward(mdnp_ctx* ctx, const float* d_w, const void* d_saved,
+                              const float* d_dy, float* d_dx, float* d_dw, int32_t batch,
+                              int32_t n, mdnp_dtype dtype, void* hip_stream);
+
+/* Training objective of Section 5.1 for a batch of unit samples: slot k uses
+ * instance d_inst[k] of the system; r [n_slots][n3d] and the network output
+ * u [n_slots][n3d] (FP32).  Writes loss[k] = || r_k - alpha_k^-1 C_k mask(u_k) ||^2
+ * (C = A00, mask zeroes the Dirichlet entries) and its gradient du [n_slots][n3d]. */
+mdnp_status mdnp_loss_grad(mdnp_ctx* ctx, mdnp_sys* sys, const int32_t* d_inst, int32_t n_slots,
+                           const float* d_r, const float* d_u, float* d_du, double* d_loss,
+                           void* hip_stream);
+
+/* Network input for training slots: X[k] = [r_k, d_{inst[k]}] as
+ * [n_slots][n][n][n][2] FP32. */
+mdnp_status mdnp_pack_input(mdnp_ctx* ctx, mdnp_sys* sys, const int32_t* d_inst, int32_t n_slots,
+                            const float* d_r, float* d_x, void* hip_stream);
+
+/* Adam (Kingma and Ba) on FP32 master weights, step counted from 1. */
+mdnp_status mdnp_adam_step(mdnp_ctx* ctx, float* d_w, const float* d_g, float* d_m, float* d_v,
+                           int64_t n, float lr, float beta1, float beta2, float eps, int32_t step,
+                           void* hip_stream);
+
+/* ---------------------------------------------------------------- host-only assembly */
+
+/* Assemble one instance on the host without touching any GPU (the same code
+ * mdnp_upload runs), for inspection and CPU-side checks.  Errors: MDNP_E_ARG,
+ * MDNP_E_GEOM.  Free with mdnp_host_free. */
+typedef struct mdnp_host_sys mdnp_host_sys;
+mdnp_status mdnp_host_assemble(const mdnp_instance_desc* desc, mdnp_host_sys** out, char* err,
+                               int32_t err_len);
+mdnp_status mdnp_host_sizes(const mdnp_host_sys* hs, int32_t* n3d, int32_t* n1d, int64_t* nnz,
+                            int32_t* n_levels);
+/* CSR (local indices) as in mdnp_export_csr, F [n], dist [n3d], alpha; any may be NULL. */
+mdnp_status mdnp_host_export(const mdnp_host_sys* hs, int32_t* row_ptr, int32_t* col, double* val,
+                             double* F, float* dist, double* alpha);
+/* z1 = A11^-1 v1 on the host with the factorisation used by the GPU 1D solve
+ * (v1, z1 of length n1d). */
+mdnp_status mdnp_host_tree_solve(const mdnp_host_sys* hs, const double* v1, double* z1);
+void mdnp_host_free(mdnp_host_sys* hs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDNP_H */

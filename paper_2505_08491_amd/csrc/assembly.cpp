@@ -1,0 +1,397 @@
+// Host assembly of the coupled 3D-1D block system of one instance (Section 2.1,
+// eq. "mainsys"), its right-hand side, the distance field and the tree
+// factorisation of the 1D block used by the exact 1D solve of eq. "twosteps".
+//
+//  * 3D: trilinear elements on N^3 uniform cells of the unit cube.  The
+//    assembled stiffness at an interior node is the 27-point stencil
+//    k h {8/3 centre, 0 faces, -1/6 edges, -1/12 corners} (tensor products of
+//    the 1D P1 stiffness and mass); the reaction term adds
+//    sigma h^3 {8/27, 2/27, 1/54, 1/216}.  Face entries are kept in the pattern.
+//  * 1D: P1 elements on every straight segment, stiffness k_Lambda pi R^2 / l.
+//  * Coupling: 2-point Gauss per 1D element; at each Gauss point the 3D field
+//    is averaged over n_circle equispaced points of the circle of radius R in
+//    the plane normal to the segment (T_Lambda).  With p the averaging weights
+//    and Phi the two P1 values, the point adds W (p, -Phi)(p, -Phi)^T,
+//    W = 2 pi R beta (l / 2).
+//  * Homogeneous Dirichlet conditions on the cube boundary by symmetric
+//    elimination with unit diagonal.
+#include "assembly.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <queue>
+
+namespace mdnp {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct Trip {
+  int32_t row, col;
+  double v;
+};
+
+inline void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Normal frame of a unit tangent: n1 = normalise(tau x e_a), a the axis of the
+// smallest |tau_k| (first one on ties), n2 = tau x n1.
+void wall_frame(const double tau[3], double n1[3], double n2[3]) {
+  int a = 0;
+  for (int k = 1; k < 3; ++k)
+    if (std::fabs(tau[k]) < std::fabs(tau[a])) a = k;
+  double e[3] = {0, 0, 0};
+  e[a] = 1.0;
+  cross3(tau, e, n1);
+  double nn = std::sqrt(n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
+  for (int k = 0; k < 3; ++k) n1[k] /= nn;
+  cross3(tau, n1, n2);
+}
+
+}  // namespace
+
+std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool& geom) {
+  geom = false;
+  if (d.n_cells < 2 || d.n_cells > 1024) return "n_cells must be in [2, 1024]";
+  if (!d.vertex_xyz || !d.seg_vertices || !d.seg_radius || !d.seg_beta) return "null geometry array";
+  if (d.elems_per_segment < 1 || d.elems_per_segment > 4096) return "elems_per_segment must be in [1, 4096]";
+  if (d.n_circle < 3 || d.n_circle > 4096) return "n_circle must be in [3, 4096]";
+  if (!(std::isfinite(d.k_omega) && std::isfinite(d.sigma_omega) && std::isfinite(d.k_lambda) &&
+        std::isfinite(d.f_lambda)) || d.k_omega < 0 || d.sigma_omega < 0 || d.k_lambda < 0)
+    return "coefficients must be finite and non-negative";
+  const int V = d.n_vertices, S = d.n_segments, E = d.elems_per_segment;
+  geom = true;
+  if (V < 2 || S != V - 1) return "the segments must form a tree: n_segments = n_vertices - 1 >= 1";
+  for (int v = 0; v < V; ++v)
+    for (int k = 0; k < 3; ++k) {
+      double x = d.vertex_xyz[3 * v + k];
+      if (!(std::isfinite(x) && x > 0.0 && x < 1.0)) return "vertex outside the open unit cube";
+    }
+  std::vector<int32_t> parent_seg(V, -1);
+  for (int s = 0; s < S; ++s) {
+    int p = d.seg_vertices[2 * s], q = d.seg_vertices[2 * s + 1];
+    if (p < 0 || p >= V || q < 0 || q >= V || p == q) return "segment vertex index out of range";
+    if (q == 0 || parent_seg[q] >= 0) return "every vertex except the root 0 must be the child end of exactly one segment";
+    parent_seg[q] = s;
+    if (!(std::isfinite(d.seg_radius[s]) && d.seg_radius[s] > 0.0)) return "segment radius must be positive";
+    if (!(std::isfinite(d.seg_beta[s]) && d.seg_beta[s] >= 0.0)) return "segment permeability must be non-negative";
+    double L2 = 0;
+    for (int k = 0; k < 3; ++k) {
+      double dd = d.vertex_xyz[3 * q + k] - d.vertex_xyz[3 * p + k];
+      L2 += dd * dd;
+    }
+    if (!(L2 > 0.0)) return "zero-length segment";
+  }
+  {  // connectivity from the root
+    std::vector<std::vector<int>> kids(V);
+    for (int s = 0; s < S; ++s) kids[d.seg_vertices[2 * s]].push_back(d.seg_vertices[2 * s + 1]);
+    std::vector<char> seen(V, 0);
+    std::vector<int> st{0};
+    seen[0] = 1;
+    int cnt = 1;
+    while (!st.empty()) {
+      int v = st.back();
+      st.pop_back();
+      for (int c : kids[v])
+        if (!seen[c]) { seen[c] = 1; ++cnt; st.push_back(c); }
+    }
+    if (cnt != V) return "the segments do not connect every vertex to the root";
+  }
+  geom = false;
+
+  const int N = d.n_cells, n = N + 1;
+  const double h = 1.0 / N;
+  const int64_t n3d64 = (int64_t)n * n * n;
+  const int64_t n1d64 = (int64_t)V + (int64_t)S * (E - 1);
+  if (n3d64 + n1d64 >= (int64_t)1 << 31) return "system too large for 32-bit indices";
+  const int n3d = (int)n3d64, n1d = (int)n1d64, nt = n3d + n1d;
+  H.n_cells = N; H.n = n; H.n3d = n3d; H.n1d = n1d;
+
+  auto is_bnd = [&](int r) -> bool {
+    if (r >= n3d) return false;
+    int i = r % n, j = (r / n) % n, k = r / (n * n);
+    return i == 0 || j == 0 || k == 0 || i == n - 1 || j == n - 1 || k == n - 1;
+  };
+
+  // 1D mesh: vertices, then segment interiors from the parent end
+  std::vector<double> pos((size_t)n1d * 3);
+  std::memcpy(pos.data(), d.vertex_xyz, sizeof(double) * 3 * V);
+  std::vector<int32_t> ea, eb, es;
+  ea.reserve((size_t)S * E); eb.reserve((size_t)S * E); es.reserve((size_t)S * E);
+  for (int s = 0; s < S; ++s) {
+    int p = d.seg_vertices[2 * s], q = d.seg_vertices[2 * s + 1];
+    const double* P = d.vertex_xyz + 3 * p;
+    const double* Q = d.vertex_xyz + 3 * q;
+    for (int t = 1; t < E; ++t) {
+      double f = (double)t / E;
+      for (int k = 0; k < 3; ++k) pos[3 * ((size_t)V + (size_t)s * (E - 1) + t - 1) + k] = P[k] + f * (Q[k] - P[k]);
+    }
+    int prev = p;
+    for (int e = 0; e < E; ++e) {
+      int nxt = (e == E - 1) ? q : V + s * (E - 1) + e;
+      ea.push_back(prev); eb.push_back(nxt); es.push_back(s);
+      prev = nxt;
+    }
+  }
+  const int ne = (int)ea.size();
+
+  // coupling and 1D triplets (Dirichlet rows/columns dropped)
+  std::vector<Trip> trips;
+  trips.reserve((size_t)ne * 2 * 500 + (size_t)ne * 4);
+  H.F.assign(nt, 0.0);
+  const double g2[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  const int nc = d.n_circle;
+  std::vector<double> cth(nc), sth(nc);
+  for (int k = 0; k < nc; ++k) {
+    double th = 2.0 * kPi * k / nc;
+    cth[k] = std::cos(th);
+    sth[k] = std::sin(th);
+  }
+  std::vector<std::pair<int32_t, double>> pis;
+  std::vector<int32_t> nodes;
+  std::vector<double> coef;
+  for (int e = 0; e < ne; ++e) {
+    const double* Pa = &pos[3 * (size_t)ea[e]];
+    const double* Pb = &pos[3 * (size_t)eb[e]];
+    double D[3] = {Pb[0] - Pa[0], Pb[1] - Pa[1], Pb[2] - Pa[2]};
+    double ell = std::sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    double tau[3] = {D[0] / ell, D[1] / ell, D[2] / ell};
+    double n1[3], n2[3];
+    wall_frame(tau, n1, n2);
+    const int s = es[e];
+    const double R = d.seg_radius[s];
+    const double W = 2.0 * kPi * R * d.seg_beta[s] * ell / 2.0;
+    // 1D stiffness and load
+    const double kk = d.k_lambda * kPi * R * R / ell;
+    const int A1 = n3d + ea[e], B1 = n3d + eb[e];
+    trips.push_back({A1, A1, kk}); trips.push_back({A1, B1, -kk});
+    trips.push_back({B1, A1, -kk}); trips.push_back({B1, B1, kk});
+    H.F[A1] += d.f_lambda * ell / 2;
+    H.F[B1] += d.f_lambda * ell / 2;
+    for (int qi = 0; qi < 2; ++qi) {
+      const double t = g2[qi];
+      double g[3];
+      for (int k = 0; k < 3; ++k) g[k] = Pa[k] + t * D[k];
+      pis.clear();
+      for (int k = 0; k < nc; ++k) {
+        double x[3];
+        int cell[3];
+        double xi[3];
+        for (int c = 0; c < 3; ++c) {
+          x[c] = g[c] + R * (cth[k] * n1[c] + sth[k] * n2[c]);
+          double fl = std::floor(x[c] / h);
+          int ci = (int)fl;
+          ci = std::min(std::max(ci, 0), N - 1);
+          cell[c] = ci;
+          xi[c] = x[c] / h - ci;
+        }
+        for (int l = 0; l < 8; ++l) {
+          int a = l & 1, b = (l >> 1) & 1, cc = (l >> 2) & 1;
+          double fx = a ? xi[0] : 1.0 - xi[0];
+          double fy = b ? xi[1] : 1.0 - xi[1];
+          double fz = cc ? xi[2] : 1.0 - xi[2];
+          int node = (cell[0] + a) + n * (cell[1] + b) + n * n * (cell[2] + cc);
+          pis.push_back({node, fx * fy * fz / nc});
+        }
+      }
+      std::sort(pis.begin(), pis.end(),
+                [](const std::pair<int32_t, double>& u, const std::pair<int32_t, double>& v) {
+                  return u.first < v.first;
+                });
+      nodes.clear();
+      coef.clear();
+      for (size_t k = 0; k < pis.size();) {
+        size_t k2 = k;
+        double acc = 0.0;
+        while (k2 < pis.size() && pis[k2].first == pis[k].first) acc += pis[k2++].second;
+        nodes.push_back(pis[k].first);
+        coef.push_back(acc);
+        k = k2;
+      }
+      nodes.push_back(A1); coef.push_back(-(1.0 - t));
+      nodes.push_back(B1); coef.push_back(-t);
+      const int m = (int)nodes.size();
+      for (int u = 0; u < m; ++u) {
+        if (is_bnd(nodes[u])) continue;
+        for (int v = 0; v < m; ++v) {
+          if (is_bnd(nodes[v])) continue;
+          trips.push_back({nodes[u], nodes[v], W * (coef[u] * coef[v])});
+        }
+      }
+    }
+  }
+
+  // bucket the triplets by row, sort each row by column, merge duplicates
+  std::vector<int64_t> tptr((size_t)nt + 1, 0);
+  for (const Trip& t : trips) ++tptr[t.row + 1];
+  for (int r = 0; r < nt; ++r) tptr[r + 1] += tptr[r];
+  std::vector<std::pair<int32_t, double>> rowt(trips.size());
+  {
+    std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+    for (const Trip& t : trips) rowt[fill[t.row]++] = {t.col, t.v};
+  }
+  std::vector<Trip>().swap(trips);
+
+  // stencil values
+  const double kh = d.k_omega * h, sh3 = d.sigma_omega * h * h * h;
+  const double kst[4] = {kh * (8.0 / 3.0), 0.0, kh * (-1.0 / 6.0), kh * (-1.0 / 12.0)};
+  const double mst[4] = {sh3 * (8.0 / 27.0), sh3 * (2.0 / 27.0), sh3 * (1.0 / 54.0), sh3 * (1.0 / 216.0)};
+
+  H.row_ptr.assign((size_t)nt + 1, 0);
+  H.col.clear();
+  H.val.clear();
+  H.col.reserve((size_t)n3d * 27 + rowt.size());
+  H.val.reserve((size_t)n3d * 27 + rowt.size());
+  H.a01_start.assign(n3d, 0);
+  H.diag.assign(nt, 0.0);
+  std::vector<std::pair<int32_t, double>> merged;
+  for (int r = 0; r < nt; ++r) {
+    auto b0 = rowt.begin() + tptr[r], b1 = rowt.begin() + tptr[r + 1];
+    std::sort(b0, b1, [](const std::pair<int32_t, double>& u, const std::pair<int32_t, double>& v) {
+      return u.first < v.first;
+    });
+    merged.clear();
+    if (r < n3d && is_bnd(r)) {
+      merged.push_back({r, 1.0});
+    } else {
+      if (r < n3d) {
+        const int i = r % n, j = (r / n) % n, k = r / (n * n);
+        (void)i; (void)j; (void)k;
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              int c = r + dx + n * dy + n * n * dz;
+              if (is_bnd(c)) continue;
+              int nd = (dx != 0) + (dy != 0) + (dz != 0);
+              merged.push_back({c, kst[nd] + mst[nd]});
+            }
+      }
+      // merge the (sorted) coupling entries of the row into the (sorted) stencil entries
+      std::vector<std::pair<int32_t, double>> out;
+      out.reserve(merged.size() + (b1 - b0));
+      size_t a = 0;
+      auto it = b0;
+      while (a < merged.size() || it != b1) {
+        int32_t ca = a < merged.size() ? merged[a].first : INT32_MAX;
+        int32_t cb = it != b1 ? it->first : INT32_MAX;
+        int32_t cmin = std::min(ca, cb);
+        double acc = 0.0;
+        if (ca == cmin) acc += merged[a++].second;
+        while (it != b1 && it->first == cmin) acc += (it++)->second;
+        out.push_back({cmin, acc});
+      }
+      merged.swap(out);
+    }
+    bool found01 = false;
+    for (const auto& e : merged) {
+      if (r < n3d && !found01 && e.first >= n3d) {
+        H.a01_start[r] = (int32_t)H.col.size();
+        found01 = true;
+      }
+      if (e.first == r) H.diag[r] = e.second;
+      H.col.push_back(e.first);
+      H.val.push_back(e.second);
+    }
+    if (r < n3d && !found01) H.a01_start[r] = (int32_t)H.col.size();
+    H.row_ptr[r + 1] = (int32_t)H.col.size();
+    if (H.col.size() >= (size_t)INT32_MAX) return "too many nonzeros for 32-bit indices";
+  }
+
+  // normalisation of the network input/output: RMS of diag(A00) on free nodes
+  {
+    double acc = 0.0;
+    int64_t cnt = 0;
+    for (int r = 0; r < n3d; ++r)
+      if (!is_bnd(r)) { acc += H.diag[r] * H.diag[r]; ++cnt; }
+    H.alpha = cnt ? std::sqrt(acc / cnt) : 1.0;
+  }
+
+  // distance field d(x) = min_s |x - proj_[P,Q] x|
+  H.dist.assign(n3d, 0.0f);
+  for (int r = 0; r < n3d; ++r) {
+    const double X[3] = {(r % n) * h, ((r / n) % n) * h, (r / (n * n)) * h};
+    double best = INFINITY;
+    for (int s = 0; s < S; ++s) {
+      const double* P = d.vertex_xyz + 3 * d.seg_vertices[2 * s];
+      const double* Q = d.vertex_xyz + 3 * d.seg_vertices[2 * s + 1];
+      double Dv[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
+      double t = ((X[0] - P[0]) * Dv[0] + (X[1] - P[1]) * Dv[1] + (X[2] - P[2]) * Dv[2]) /
+                 (Dv[0] * Dv[0] + Dv[1] * Dv[1] + Dv[2] * Dv[2]);
+      t = std::min(std::max(t, 0.0), 1.0);
+      double e0 = X[0] - (P[0] + t * Dv[0]), e1 = X[1] - (P[1] + t * Dv[1]), e2 = X[2] - (P[2] + t * Dv[2]);
+      best = std::min(best, e0 * e0 + e1 * e1 + e2 * e2);
+    }
+    H.dist[r] = (float)std::sqrt(best);
+  }
+
+  // tree factorisation of A11 (1D block incl. coupling mass), leaves first
+  TreeFactor& T = H.tree;
+  T.parent.assign(n1d, -1);
+  for (int s = 0; s < S; ++s) {
+    int p = d.seg_vertices[2 * s], q = d.seg_vertices[2 * s + 1];
+    int prev = p;
+    for (int t = 0; t < E - 1; ++t) {
+      int node = V + s * (E - 1) + t;
+      T.parent[node] = prev;
+      prev = node;
+    }
+    T.parent[q] = prev;
+  }
+  std::vector<std::vector<int32_t>> kids(n1d);
+  for (int c = 0; c < n1d; ++c)
+    if (T.parent[c] >= 0) kids[T.parent[c]].push_back(c);
+  std::vector<int32_t> bfs;
+  bfs.reserve(n1d);
+  bfs.push_back(0);
+  for (size_t k = 0; k < bfs.size(); ++k)
+    for (int c : kids[bfs[k]]) bfs.push_back(c);
+  if ((int)bfs.size() != n1d) return "internal error: 1D mesh is not a tree";
+  auto a11 = [&](int row, int colj) -> double {
+    const int r = n3d + row, c = n3d + colj;
+    const int32_t* b = H.col.data() + H.row_ptr[r];
+    const int32_t* e = H.col.data() + H.row_ptr[r + 1];
+    const int32_t* f = std::lower_bound(b, e, c);
+    return (f != e && *f == c) ? H.val[f - H.col.data()] : 0.0;
+  };
+  std::vector<double> piv(n1d);
+  std::vector<int32_t> level(n1d, 0);
+  T.lval.assign(n1d, 0.0);
+  T.dinv.assign(n1d, 0.0);
+  for (int k = n1d - 1; k >= 0; --k) {
+    int c = bfs[k];
+    double dc = a11(c, c);
+    int lv = 0;
+    for (int kid : kids[c]) {
+      double acl = a11(c, kid);
+      dc -= acl * acl / piv[kid];
+      lv = std::max(lv, level[kid] + 1);
+    }
+    if (!(dc > 0.0)) return "1D block is not positive definite (check R, beta and k_lambda)";
+    piv[c] = dc;
+    level[c] = lv;
+    T.dinv[c] = 1.0 / dc;
+    if (T.parent[c] >= 0) T.lval[c] = a11(T.parent[c], c) / dc;
+  }
+  T.child_ptr.assign(n1d + 1, 0);
+  for (int c = 0; c < n1d; ++c) T.child_ptr[c + 1] = T.child_ptr[c] + (int32_t)kids[c].size();
+  T.child_idx.clear();
+  for (int c = 0; c < n1d; ++c) for (int kid : kids[c]) T.child_idx.push_back(kid);
+  int nlev = 0;
+  for (int c = 0; c < n1d; ++c) nlev = std::max(nlev, level[c] + 1);
+  T.lvl_ptr.assign(nlev + 1, 0);
+  for (int c = 0; c < n1d; ++c) ++T.lvl_ptr[level[c] + 1];
+  for (int l = 0; l < nlev; ++l) T.lvl_ptr[l + 1] += T.lvl_ptr[l];
+  T.lvl_nodes.assign(n1d, 0);
+  {
+    std::vector<int32_t> fill(T.lvl_ptr.begin(), T.lvl_ptr.end() - 1);
+    for (int c = 0; c < n1d; ++c) T.lvl_nodes[fill[level[c]]++] = c;
+  }
+  return std::string();
+}
+
+}  // namespace mdnp

@@ -1,0 +1,40 @@
+// Host-side assembly of one instance of the coupled 3D-1D system (Section 2.1).
+// Independent implementation used by the library at upload time.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mdnp.h"
+
+namespace mdnp {
+
+struct TreeFactor {
+  // Leaves-first LDL^T of the tree matrix A11 (no fill).  Local 1D indices.
+  std::vector<int32_t> parent;      // parent node, -1 at the root
+  std::vector<double> lval;         // L[parent(c), c] = a_{p c} / d_c
+  std::vector<double> dinv;         // 1 / d_c
+  std::vector<int32_t> child_ptr;   // children of each node (CSR)
+  std::vector<int32_t> child_idx;
+  std::vector<int32_t> lvl_ptr;     // nodes grouped by level: level(c) = 1 + max level(children)
+  std::vector<int32_t> lvl_nodes;
+};
+
+struct HostInstance {
+  int n_cells = 0, n = 0, n3d = 0, n1d = 0;
+  std::vector<int32_t> row_ptr, col;   // CSR of A, local indices, sorted columns
+  std::vector<double> val;
+  std::vector<int32_t> a01_start;      // per 3D row: first entry with a 1D column
+  std::vector<double> F;               // right-hand side [n3d + n1d]
+  std::vector<float> dist;             // distance field at the 3D nodes
+  std::vector<double> diag;            // diag(A)
+  double alpha = 0.0;                  // RMS of diag(A00) over the free 3D nodes
+  TreeFactor tree;
+};
+
+// Validates and assembles; returns an empty string on success or an error message.
+// `geom_error` is set when the failure is a geometry error.
+std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& out, bool& geom_error);
+
+}  // namespace mdnp

@@ -1,0 +1,861 @@
+// C ABI of the library: contexts, systems (upload of assembled instances),
+// preconditioner selection, the restarted FGMRES driver and the entry points of
+// the individual steps of the path.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <thread>
+#include <atomic>
+
+#include "conv_common.hpp"
+#include "kernels.hpp"
+
+using namespace mdnp;
+
+namespace {
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIPCHK(call)                                   \
+  do {                                                 \
+    hipError_t _e = (call);                            \
+    if (_e != hipSuccess) throw HipError{_e, #call};   \
+  } while (0)
+
+struct ArgError {
+  mdnp_status st;
+  std::string msg;
+};
+
+[[noreturn]] void fail(mdnp_status st, const std::string& msg) { throw ArgError{st, msg}; }
+
+template <typename F>
+mdnp_status guarded(mdnp_ctx* ctx, F&& f) {
+  try {
+    f();
+    if (ctx) ctx->err.clear();
+    return MDNP_OK;
+  } catch (const ArgError& a) {
+    if (ctx) ctx->err = a.msg;
+    return a.st;
+  } catch (const HipError& h) {
+    if (ctx) ctx->err = std::string("HIP error: ") + hipGetErrorString(h.e) + " in " + h.what;
+    return h.e == hipErrorOutOfMemory ? MDNP_E_OOM : MDNP_E_HIP;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "host allocation failed";
+    return MDNP_E_OOM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    return MDNP_E_ARG;
+  } catch (...) {
+    if (ctx) ctx->err = "unknown error";
+    return MDNP_E_ARG;
+  }
+}
+
+template <typename T>
+T* dalloc(size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+  return (T*)p;
+}
+
+template <typename T>
+T* dupload(const std::vector<T>& v, hipStream_t s) {
+  T* p = dalloc<T>(v.size());
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return p;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+hipStream_t pick(mdnp_ctx* ctx, void* s) { return s ? (hipStream_t)s : ctx->stream; }
+
+void build_blocks(Blocks& B, const std::vector<int64_t>& start_i, const std::vector<int64_t>& len_i,
+                  int64_t total_len, hipStream_t s) {
+  const int n_inst = (int)start_i.size();
+  int chunk = 256;
+  while (chunk < 8192 && total_len / chunk > 2048) chunk *= 2;
+  B.chunk = chunk;
+  std::vector<int32_t> bi;
+  std::vector<int64_t> bs, be;
+  B.h_first.assign(n_inst + 1, 0);
+  for (int i = 0; i < n_inst; ++i) {
+    B.h_first[i] = (int32_t)bi.size();
+    for (int64_t a = 0; a < len_i[i]; a += chunk) {
+      bi.push_back(i);
+      bs.push_back(start_i[i] + a);
+      be.push_back(start_i[i] + std::min(len_i[i], a + chunk));
+    }
+  }
+  B.h_first[n_inst] = (int32_t)bi.size();
+  B.nblk = (int)bi.size();
+  B.inst = dupload(bi, s);
+  B.start = dupload(bs, s);
+  B.end = dupload(be, s);
+  B.first = dupload(B.h_first, s);
+}
+
+void free_blocks(Blocks& B) {
+  dfree(B.inst); dfree(B.start); dfree(B.end); dfree(B.first);
+  B = Blocks();
+}
+
+void free_work(SolveWork& w) {
+  dfree(w.V); dfree(w.Z); dfree(w.r); dfree(w.H); dfree(w.cs); dfree(w.sn); dfree(w.g); dfree(w.y);
+  dfree(w.part); dfree(w.hist); dfree(w.st);
+  if (w.graph) (void)hipGraphExecDestroy(w.graph);
+  w = SolveWork();
+}
+
+void free_sys(mdnp_sys* s) {
+  void* ptrs[] = {s->d_off, s->d_rowptr, s->d_col, s->d_val64, s->d_val32, s->d_a01, s->d_dinv, s->d_dist,
+                  s->d_alpha, s->d_t_off, s->d_t_lvloff, s->d_t_lvlptr, s->d_t_lvlnodes, s->d_t_parent,
+                  s->d_t_childptr, s->d_t_childidx, s->d_t_lval, s->d_t_dinv};
+  for (void* p : ptrs) dfree(p);
+  free_blocks(s->blk);
+  free_blocks(s->blk3);
+  free_work(s->work);
+  cnn_release(s->cnn);
+  delete s;
+}
+
+size_t vsize(mdnp_dtype d) { return d == MDNP_F64 ? 8 : 4; }
+
+}  // namespace
+
+// ============================================================================ context
+
+extern "C" mdnp_status mdnp_create(mdnp_ctx** out, int hip_device, void* hip_stream) {
+  if (!out) return MDNP_E_ARG;
+  *out = nullptr;
+  mdnp_ctx* ctx = new (std::nothrow) mdnp_ctx();
+  if (!ctx) return MDNP_E_OOM;
+  mdnp_status st = guarded(ctx, [&] {
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (hip_device < 0 || hip_device >= ndev) fail(MDNP_E_ARG, "no such HIP device");
+    HIPCHK(hipSetDevice(hip_device));
+    ctx->device = hip_device;
+    if (hip_stream) {
+      ctx->stream = (hipStream_t)hip_stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+      ctx->own_stream = true;
+    }
+  });
+  if (st != MDNP_OK) {
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return MDNP_OK;
+}
+
+extern "C" mdnp_status mdnp_destroy(mdnp_ctx* ctx) {
+  if (!ctx) return MDNP_E_ARG;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (mdnp_sys* s : ctx->systems) free_sys(s);
+  cnn_release(ctx->cnn);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return MDNP_OK;
+}
+
+extern "C" const char* mdnp_last_error(const mdnp_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+// ============================================================================ host assembly
+
+struct mdnp_host_sys {
+  HostInstance h;
+};
+
+extern "C" mdnp_status mdnp_host_assemble(const mdnp_instance_desc* desc, mdnp_host_sys** out, char* err,
+                                          int32_t err_len) {
+  auto seterr = [&](const std::string& m) {
+    if (err && err_len > 0) {
+      std::snprintf(err, (size_t)err_len, "%s", m.c_str());
+    }
+  };
+  if (!desc || !out) {
+    seterr("null argument");
+    return MDNP_E_ARG;
+  }
+  *out = nullptr;
+  try {
+    mdnp_host_sys* hs = new mdnp_host_sys();
+    bool geom = false;
+    std::string e = assemble_instance(*desc, hs->h, geom);
+    if (!e.empty()) {
+      delete hs;
+      seterr(e);
+      return geom ? MDNP_E_GEOM : MDNP_E_ARG;
+    }
+    *out = hs;
+    seterr("");
+    return MDNP_OK;
+  } catch (const std::bad_alloc&) {
+    seterr("host allocation failed");
+    return MDNP_E_OOM;
+  }
+}
+
+extern "C" mdnp_status mdnp_host_sizes(const mdnp_host_sys* hs, int32_t* n3d, int32_t* n1d, int64_t* nnz,
+                                       int32_t* n_levels) {
+  if (!hs) return MDNP_E_ARG;
+  if (n3d) *n3d = hs->h.n3d;
+  if (n1d) *n1d = hs->h.n1d;
+  if (nnz) *nnz = (int64_t)hs->h.col.size();
+  if (n_levels) *n_levels = (int32_t)hs->h.tree.lvl_ptr.size() - 1;
+  return MDNP_OK;
+}
+
+extern "C" mdnp_status mdnp_host_export(const mdnp_host_sys* hs, int32_t* row_ptr, int32_t* col, double* val,
+                                        double* F, float* dist, double* alpha) {
+  if (!hs) return MDNP_E_ARG;
+  const HostInstance& h = hs->h;
+  if (row_ptr) std::memcpy(row_ptr, h.row_ptr.data(), h.row_ptr.size() * sizeof(int32_t));
+  if (col) std::memcpy(col, h.col.data(), h.col.size() * sizeof(int32_t));
+  if (val) std::memcpy(val, h.val.data(), h.val.size() * sizeof(double));
+  if (F) std::memcpy(F, h.F.data(), h.F.size() * sizeof(double));
+  if (dist) std::memcpy(dist, h.dist.data(), h.dist.size() * sizeof(float));
+  if (alpha) *alpha = h.alpha;
+  return MDNP_OK;
+}
+
+extern "C" mdnp_status mdnp_host_tree_solve(const mdnp_host_sys* hs, const double* v1, double* z1) {
+  if (!hs || !v1 || !z1) return MDNP_E_ARG;
+  const TreeFactor& T = hs->h.tree;
+  const int n1d = hs->h.n1d;
+  std::vector<double> y(v1, v1 + n1d);
+  const int nlev = (int)T.lvl_ptr.size() - 1;
+  for (int L = 0; L < nlev; ++L)
+    for (int k = T.lvl_ptr[L]; k < T.lvl_ptr[L + 1]; ++k) {
+      const int c = T.lvl_nodes[k];
+      for (int q = T.child_ptr[c]; q < T.child_ptr[c + 1]; ++q) y[c] -= T.lval[T.child_idx[q]] * y[T.child_idx[q]];
+    }
+  for (int c = 0; c < n1d; ++c) y[c] *= T.dinv[c];
+  for (int L = nlev - 1; L >= 0; --L)
+    for (int k = T.lvl_ptr[L]; k < T.lvl_ptr[L + 1]; ++k) {
+      const int c = T.lvl_nodes[k];
+      if (T.parent[c] >= 0) y[c] -= T.lval[c] * y[T.parent[c]];
+    }
+  std::memcpy(z1, y.data(), sizeof(double) * n1d);
+  return MDNP_OK;
+}
+
+extern "C" void mdnp_host_free(mdnp_host_sys* hs) { delete hs; }
+
+// ============================================================================ upload
+
+extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* descs, int32_t n_inst,
+                                   mdnp_dtype vec_dtype, mdnp_sys** out) {
+  if (!ctx) return MDNP_E_ARG;
+  mdnp_sys* s = nullptr;
+  mdnp_status st = guarded(ctx, [&] {
+    if (!descs || !out || n_inst < 1) fail(MDNP_E_ARG, "mdnp_upload: null argument or n_inst < 1");
+    if (vec_dtype != MDNP_F64 && vec_dtype != MDNP_F32) fail(MDNP_E_ARG, "vec_dtype must be MDNP_F64 or MDNP_F32");
+    for (int i = 1; i < n_inst; ++i)
+      if (descs[i].n_cells != descs[0].n_cells) fail(MDNP_E_ARG, "all instances of a system must share n_cells");
+    HIPCHK(hipSetDevice(ctx->device));
+    s = new mdnp_sys();
+    s->ctx = ctx;
+    s->n_inst = n_inst;
+    s->vec_dtype = vec_dtype;
+    s->host.resize(n_inst);
+    // assemble on the host in parallel
+    std::vector<std::string> errs(n_inst);
+    std::vector<char> geoms(n_inst, 0);
+    int nth = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+    nth = std::min(nth, n_inst);
+    std::vector<std::thread> pool;
+    std::atomic<int> next{0};
+    for (int t = 0; t < nth; ++t)
+      pool.emplace_back([&] {
+        for (int i = next++; i < n_inst; i = next++) {
+          bool g = false;
+          try {
+            errs[i] = assemble_instance(descs[i], s->host[i], g);
+          } catch (const std::bad_alloc&) {
+            errs[i] = "host allocation failed";
+          }
+          geoms[i] = g;
+        }
+      });
+    for (auto& th : pool) th.join();
+    for (int i = 0; i < n_inst; ++i)
+      if (!errs[i].empty()) fail(geoms[i] ? MDNP_E_GEOM : MDNP_E_ARG, "instance " + std::to_string(i) + ": " + errs[i]);
+    const HostInstance& h0 = s->host[0];
+    s->n_cells = h0.n_cells;
+    s->n = h0.n;
+    s->n3d = h0.n3d;
+    // offsets
+    s->off.assign(n_inst + 1, 0);
+    s->nnz_off.assign(n_inst + 1, 0);
+    for (int i = 0; i < n_inst; ++i) {
+      s->off[i + 1] = s->off[i] + s->host[i].n3d + s->host[i].n1d;
+      s->nnz_off[i + 1] = s->nnz_off[i] + (int64_t)s->host[i].col.size();
+      s->max_n1d = std::max(s->max_n1d, s->host[i].n1d);
+    }
+    s->ntot = s->off[n_inst];
+    s->nnz_tot = s->nnz_off[n_inst];
+    if (s->ntot >= INT32_MAX || s->nnz_tot >= INT32_MAX) fail(MDNP_E_ARG, "system too large for 32-bit indices");
+    if ((size_t)s->max_n1d * 8 > 160 * 1024) fail(MDNP_E_ARG, "1D block too large for the on-chip tree solve");
+    hipStream_t stream = ctx->stream;
+    // concatenated CSR with global indices
+    std::vector<int32_t> rp(s->ntot + 1), col(s->nnz_tot), a01((size_t)n_inst * s->n3d);
+    std::vector<double> v64(s->nnz_tot), dinv(s->ntot), alpha(n_inst);
+    std::vector<float> v32(s->nnz_tot), dist((size_t)n_inst * s->n3d);
+    for (int i = 0; i < n_inst; ++i) {
+      const HostInstance& h = s->host[i];
+      const int64_t o = s->off[i], no = s->nnz_off[i];
+      const int nr = h.n3d + h.n1d;
+      for (int r = 0; r <= nr; ++r) rp[o + r] = (int32_t)(no + h.row_ptr[r]);
+      for (size_t k = 0; k < h.col.size(); ++k) {
+        col[no + k] = (int32_t)(o + h.col[k]);
+        v64[no + k] = h.val[k];
+        v32[no + k] = (float)h.val[k];
+      }
+      for (int r = 0; r < h.n3d; ++r) a01[(size_t)i * s->n3d + r] = (int32_t)(no + h.a01_start[r]);
+      for (int r = 0; r < nr; ++r) dinv[o + r] = 1.0 / h.diag[r];
+      std::memcpy(&dist[(size_t)i * s->n3d], h.dist.data(), sizeof(float) * h.n3d);
+      alpha[i] = h.alpha;
+    }
+    s->d_off = dupload(s->off, stream);
+    s->d_rowptr = dupload(rp, stream);
+    s->d_col = dupload(col, stream);
+    s->d_val64 = dupload(v64, stream);
+    s->d_val32 = dupload(v32, stream);
+    s->d_a01 = dupload(a01, stream);
+    s->d_dinv = dupload(dinv, stream);
+    s->d_dist = dupload(dist, stream);
+    s->d_alpha = dupload(alpha, stream);
+    // tree factorisation
+    std::vector<int32_t> toff(n_inst + 1, 0), lvloff(n_inst + 1, 0), lvlptr, lvlnodes, parent, childptr, childidx;
+    std::vector<double> lval, tdinv;
+    for (int i = 0; i < n_inst; ++i) {
+      const TreeFactor& T = s->host[i].tree;
+      const int n1d = s->host[i].n1d;
+      toff[i + 1] = toff[i] + n1d;
+      lvloff[i + 1] = lvloff[i] + (int32_t)T.lvl_ptr.size();
+      lvlptr.insert(lvlptr.end(), T.lvl_ptr.begin(), T.lvl_ptr.end());
+      lvlnodes.insert(lvlnodes.end(), T.lvl_nodes.begin(), T.lvl_nodes.end());
+      parent.insert(parent.end(), T.parent.begin(), T.parent.end());
+      const int32_t cbase = (int32_t)childidx.size();
+      for (int c = 0; c <= n1d; ++c) childptr.push_back(cbase + T.child_ptr[c]);
+      childidx.insert(childidx.end(), T.child_idx.begin(), T.child_idx.end());
+      lval.insert(lval.end(), T.lval.begin(), T.lval.end());
+      tdinv.insert(tdinv.end(), T.dinv.begin(), T.dinv.end());
+    }
+    s->d_t_off = dupload(toff, stream);
+    s->d_t_lvloff = dupload(lvloff, stream);
+    s->d_t_lvlptr = dupload(lvlptr, stream);
+    s->d_t_lvlnodes = dupload(lvlnodes, stream);
+    s->d_t_parent = dupload(parent, stream);
+    s->d_t_childptr = dupload(childptr, stream);
+    s->d_t_childidx = dupload(childidx, stream);
+    s->d_t_lval = dupload(lval, stream);
+    s->d_t_dinv = dupload(tdinv, stream);
+    tree_solve_setup(sizeof(double) * (size_t)s->max_n1d);
+    // reduction tilings
+    std::vector<int64_t> st_all(n_inst), len_all(n_inst), st3(n_inst), len3(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+      st_all[i] = s->off[i];
+      len_all[i] = s->off[i + 1] - s->off[i];
+      st3[i] = 0;  // 3D blocks use local row indices
+      len3[i] = s->n3d;
+    }
+    build_blocks(s->blk, st_all, len_all, s->ntot, stream);
+    build_blocks(s->blk3, st3, len3, (int64_t)n_inst * s->n3d, stream);
+    HIPCHK(hipStreamSynchronize(stream));
+    // drop the host copies that are not needed any more (keep CSR, F, dist for export)
+    for (auto& h : s->host) {
+      std::vector<int32_t>().swap(h.a01_start);
+      h.tree = TreeFactor();
+    }
+    ctx->systems.push_back(s);
+    *out = s;
+  });
+  if (st != MDNP_OK && s) {
+    auto it = std::find(ctx->systems.begin(), ctx->systems.end(), s);
+    if (it == ctx->systems.end()) free_sys(s);
+  }
+  return st;
+}
+
+extern "C" mdnp_status mdnp_sys_free(mdnp_ctx* ctx, mdnp_sys* s) {
+  if (!ctx || !s) return MDNP_E_ARG;
+  auto it = std::find(ctx->systems.begin(), ctx->systems.end(), s);
+  if (it == ctx->systems.end()) return MDNP_E_ARG;
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->systems.erase(it);
+  free_sys(s);
+  return MDNP_OK;
+}
+
+extern "C" mdnp_status mdnp_sys_sizes(const mdnp_sys* s, int32_t inst, int32_t* n3d, int32_t* n1d, int64_t* nnz,
+                                      int64_t* offset) {
+  if (!s || inst < 0 || inst >= s->n_inst) return MDNP_E_ARG;
+  if (n3d) *n3d = s->host[inst].n3d;
+  if (n1d) *n1d = s->host[inst].n1d;
+  if (nnz) *nnz = (int64_t)s->host[inst].col.size();
+  if (offset) *offset = s->off[inst];
+  return MDNP_OK;
+}
+
+extern "C" mdnp_status mdnp_export_csr(const mdnp_sys* s, int32_t inst, int32_t* row_ptr, int32_t* col, double* val) {
+  if (!s || inst < 0 || inst >= s->n_inst) return MDNP_E_ARG;
+  const HostInstance& h = s->host[inst];
+  if (row_ptr) std::memcpy(row_ptr, h.row_ptr.data(), h.row_ptr.size() * sizeof(int32_t));
+  if (col) std::memcpy(col, h.col.data(), h.col.size() * sizeof(int32_t));
+  if (val) std::memcpy(val, h.val.data(), h.val.size() * sizeof(double));
+  return MDNP_OK;
+}
+
+extern "C" mdnp_status mdnp_export_rhs(const mdnp_sys* s, int32_t inst, double* F, double* dist, double* alpha) {
+  if (!s || inst < 0 || inst >= s->n_inst) return MDNP_E_ARG;
+  const HostInstance& h = s->host[inst];
+  if (F) std::memcpy(F, h.F.data(), h.F.size() * sizeof(double));
+  if (dist)
+    for (int r = 0; r < h.n3d; ++r) dist[r] = (double)h.dist[r];
+  if (alpha) *alpha = h.alpha;
+  return MDNP_OK;
+}
+
+// ============================================================================ preconditioner
+
+extern "C" mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* s, mdnp_prec_kind kind, const float* weights,
+                                               int64_t n_weights, double alpha, mdnp_dtype cnn_dtype) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s) fail(MDNP_E_ARG, "null system");
+    if (kind < MDNP_PREC_NONE || kind > MDNP_PREC_BLOCK_JACOBI) fail(MDNP_E_ARG, "unknown preconditioner kind");
+    HIPCHK(hipSetDevice(ctx->device));
+    s->kind = kind;
+    s->alpha_override = alpha > 0.0 ? alpha : 0.0;
+    s->prec_set = true;
+    if (s->work.graph) {
+      (void)hipGraphExecDestroy(s->work.graph);
+      s->work.graph = nullptr;
+      s->work.graph_m = -1;
+    }
+    if (kind != MDNP_PREC_NEURAL) return;
+    s->prec_set = false;
+    if (!weights) fail(MDNP_E_ARG, "neural preconditioner needs weights");
+    int64_t np = 0;
+    for (int l = 0; l < kNumLayers; ++l) {
+      const int taps = kLayers[l].kind == KIND_PT ? 1 : 27;
+      np += (int64_t)kLayers[l].cout * taps * kLayers[l].cin + kLayers[l].cout;
+    }
+    if (n_weights != np) fail(MDNP_E_ARG, "expected " + std::to_string(np) + " weights");
+    if (cnn_dtype != MDNP_F32 && cnn_dtype != MDNP_BF16) fail(MDNP_E_ARG, "cnn_dtype must be MDNP_F32 or MDNP_BF16");
+    if (s->n_cells % 4 != 0 || s->n_cells < 4) fail(MDNP_E_ARG, "the network needs n_cells divisible by 4");
+    for (int64_t k = 0; k < n_weights; ++k)
+      if (!std::isfinite(weights[k])) fail(MDNP_E_NONFINITE, "non-finite network weight");
+    CnnState& c = s->cnn;
+    if (!c.w_own) c.w_own = dalloc<float>((size_t)np);
+    HIPCHK(hipMemcpyAsync(c.w_own, weights, sizeof(float) * np, hipMemcpyHostToDevice, ctx->stream));
+    c.w = c.w_own;
+    c.dtype = cnn_dtype;
+    if (!c.inv_s) c.inv_s = dalloc<double>(2 * (size_t)s->n_inst);
+    cnn_prepare_weights(c, c.w, ctx->stream);
+    if (!cnn_reserve(c, s->n_inst, s->n, cnn_dtype)) fail(MDNP_E_OOM, "network activation buffers");
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    c.ready = true;
+    s->prec_set = true;
+  });
+}
+
+// ============================================================================ solve
+
+namespace {
+
+void ensure_work(mdnp_sys* s, int m, int hist_cap) {
+  SolveWork& w = s->work;
+  if (w.m >= m && w.hist_cap >= hist_cap && w.V) return;
+  free_work(w);
+  const size_t es = vsize(s->vec_dtype);
+  const size_t nt = (size_t)s->ntot, ni = (size_t)s->n_inst;
+  w.V = dalloc<char>(es * nt * (m + 1));
+  w.Z = dalloc<char>(es * nt * m);
+  w.r = dalloc<double>(nt);
+  w.H = dalloc<double>(ni * (m + 1) * m);
+  w.cs = dalloc<double>(ni * m);
+  w.sn = dalloc<double>(ni * m);
+  w.g = dalloc<double>(ni * (m + 1));
+  w.y = dalloc<double>(ni * m);
+  w.part = dalloc<double>(3 * (size_t)s->blk.nblk + (size_t)s->blk3.nblk);
+  w.hist = dalloc<double>(ni * hist_cap);
+  w.st = dalloc<InstState>(ni);
+  w.m = m;
+  w.hist_cap = hist_cap;
+  if (!s->cnn.inv_s) s->cnn.inv_s = dalloc<double>(2 * ni);
+}
+
+// Preconditioner application z = Q(v) for the Arnoldi step (mode-masked).
+template <typename T>
+void apply_prec(mdnp_sys* s, const T* v, T* z, const InstState* st, bool any_fb, hipStream_t stream) {
+  double* part3 = s->work.part ? s->work.part + 3 * (size_t)s->blk.nblk : nullptr;
+  switch (s->kind) {
+    case MDNP_PREC_NONE:
+      launch_prec_copy<T>(s, v, z, st, stream);
+      break;
+    case MDNP_PREC_JACOBI:
+      launch_prec_jacobi<T>(s, v, z, st, -1, stream);
+      any_fb = false;
+      break;
+    case MDNP_PREC_BLOCK_JACOBI:
+    case MDNP_PREC_NEURAL:
+      launch_tree_solve<T>(s, v, z, st, 0, stream);
+      launch_extension<T>(s, v, z, part3, st, 0, stream);
+      if (s->kind == MDNP_PREC_BLOCK_JACOBI) {
+        launch_block_jacobi3d<T>(s, z, st, 0, stream);
+      } else {
+        launch_inv_scale(s, part3, s->cnn.inv_s, const_cast<InstState*>(st), 0, stream);
+        cnn_apply_in_solver<T>(s, z, st, stream);
+      }
+      break;
+  }
+  if (any_fb) launch_prec_jacobi<T>(s, v, z, st, 1, stream);
+}
+
+template <typename T>
+void arnoldi_cycle(mdnp_sys* s, int m, bool any_fb, double* x, hipStream_t stream) {
+  SolveWork& w = s->work;
+  T* V = (T*)w.V;
+  T* Z = (T*)w.Z;
+  const int64_t nt = s->ntot;
+  double* pA = w.part;
+  double* pB = w.part + s->blk.nblk;
+  double* pW = w.part + 2 * (size_t)s->blk.nblk;
+  for (int j = 0; j < m; ++j) {
+    apply_prec<T>(s, V + j * nt, Z + j * nt, w.st, any_fb, stream);
+    launch_spmv<T>(s, Z + j * nt, V + (j + 1) * nt, w.st, true, stream);
+    for (int k = 0; k <= j + 1; ++k) {
+      double* cur = (k % 2 == 0) ? pA : pB;
+      double* prev = (k % 2 == 0) ? pB : pA;
+      launch_mgs<T>(s, V, j, k, prev, cur, pW, w.H, w.m, w.st, stream);
+    }
+    double* last = ((j + 1) % 2 == 0) ? pA : pB;
+    launch_mgs_finish<T>(s, V, j, last, pW, w.H, w.cs, w.sn, w.g, w.hist, w.hist_cap, w.m, w.st, stream);
+  }
+  launch_solve_y(s, w.H, w.g, w.y, w.m, w.st, stream);
+  launch_update_x<T>(s, Z, w.y, x, w.m, w.st, stream);
+}
+
+template <typename T>
+void solve_impl(mdnp_ctx* ctx, mdnp_sys* s, const double* d_b, double* d_x, const mdnp_solve_opts& o,
+                mdnp_inst_stats* stats, hipStream_t stream) {
+  const int m0 = o.restart;
+  const int mf = o.fallback_restart > 0 ? o.fallback_restart : o.restart;
+  const int mmax = std::max(m0, mf);
+  const bool fb_allowed = o.fallback_max_iters > 0 && s->kind != MDNP_PREC_JACOBI;
+  const int total_cap = o.max_iters + (fb_allowed ? o.fallback_max_iters : 0);
+  const int hist_cap = 2 * total_cap + 8;
+  ensure_work(s, mmax, hist_cap);
+  SolveWork& w = s->work;
+  const int ni = s->n_inst;
+  launch_norm2_partials(s, d_b, w.part, stream);
+  launch_init_state(s, w.st, w.part, o.tol, o.max_iters, stream);
+  std::vector<InstState> hs(ni);
+  HIPCHK(hipMemcpyAsync(hs.data(), w.st, sizeof(InstState) * ni, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  for (int i = 0; i < ni; ++i)  // b = 0: the solution is 0
+    if (hs[i].done)
+      HIPCHK(hipMemsetAsync(d_x + s->off[i], 0, sizeof(double) * (s->off[i + 1] - s->off[i]), stream));
+  std::vector<char> used_fb(ni, 0);
+  int cycles = 0;
+  const int max_cycles = total_cap + 4;
+  while (true) {
+    launch_residual(s, d_b, d_x, w.r, w.part, w.st, stream);
+    launch_cycle_start(s, w.st, w.part, w.g, w.hist, w.hist_cap, w.m, stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hs.data(), w.st, sizeof(InstState) * ni, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    bool changed = false, any_active = false, any_fb = false, all_fb = true;
+    for (int i = 0; i < ni; ++i) {
+      InstState& z = hs[i];
+      if (z.done || !z.active) continue;
+      if (z.stalled) {
+        if (z.mode == 0 && fb_allowed) {
+          z.mode = 1;
+          z.max_iters = o.fallback_max_iters;
+          z.stalled = 0;
+          used_fb[i] = 1;
+          changed = true;
+        } else if (z.stalled >= 2) {  // non-finite or out of steps
+          z.done = 1;
+          z.active = 0;
+          changed = true;
+          continue;
+        }
+      }
+      any_active = true;
+      if (z.mode == 1) any_fb = true; else all_fb = false;
+    }
+    if (changed) HIPCHK(hipMemcpyAsync(w.st, hs.data(), sizeof(InstState) * ni, hipMemcpyHostToDevice, stream));
+    if (!any_active || ++cycles > max_cycles) break;
+    const int m = all_fb ? mf : m0;
+    launch_scale_to<T>(s, w.r, (T*)w.V, w.st, stream);
+    if (o.use_graph) {
+      if (!w.graph || w.graph_m != m || w.graph_fb != (int)any_fb) {
+        if (w.graph) HIPCHK(hipGraphExecDestroy(w.graph));
+        w.graph = nullptr;
+        hipGraph_t g;
+        HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
+        arnoldi_cycle<T>(s, m, any_fb, d_x, stream);
+        HIPCHK(hipStreamEndCapture(stream, &g));
+        HIPCHK(hipGraphInstantiate(&w.graph, g, nullptr, nullptr, 0));
+        HIPCHK(hipGraphDestroy(g));
+        w.graph_m = m;
+        w.graph_fb = (int)any_fb;
+      }
+      HIPCHK(hipGraphLaunch(w.graph, stream));
+    } else {
+      arnoldi_cycle<T>(s, m, any_fb, d_x, stream);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  // history and statistics
+  w.h_nhist.assign(ni, 0);
+  w.h_hist.assign((size_t)ni * w.hist_cap, 0.0);
+  HIPCHK(hipMemcpyAsync(w.h_hist.data(), w.hist, sizeof(double) * w.h_hist.size(), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(hs.data(), w.st, sizeof(InstState) * ni, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  for (int i = 0; i < ni; ++i) {
+    w.h_nhist[i] = std::min(hs[i].nhist, w.hist_cap);
+    if (stats) {
+      stats[i].iters = hs[i].iters;
+      stats[i].fallback_iters = hs[i].fb_iters;
+      stats[i].converged = hs[i].converged;
+      stats[i].used_fallback = used_fb[i];
+      stats[i].final_rel_res = hs[i].rel;
+    }
+  }
+  (void)ctx;
+}
+
+void check_opts(const mdnp_solve_opts* o) {
+  if (!o) fail(MDNP_E_ARG, "null options");
+  if (o->restart < 1 || o->restart > 512) fail(MDNP_E_ARG, "restart must be in [1, 512]");
+  if (o->fallback_restart < 0 || o->fallback_restart > 512) fail(MDNP_E_ARG, "fallback_restart must be in [0, 512]");
+  if (o->max_iters < 1 || o->fallback_max_iters < 0) fail(MDNP_E_ARG, "invalid iteration caps");
+  if ((int64_t)o->max_iters + o->fallback_max_iters > 100000000) fail(MDNP_E_ARG, "iteration caps too large");
+  if (!(o->tol > 0.0) || !std::isfinite(o->tol)) fail(MDNP_E_ARG, "tol must be positive");
+}
+
+}  // namespace
+
+extern "C" mdnp_status mdnp_solve_device(mdnp_ctx* ctx, mdnp_sys* s, const double* d_b, double* d_x,
+                                         const mdnp_solve_opts* opts, mdnp_inst_stats* stats, void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !d_b || !d_x) fail(MDNP_E_ARG, "null argument");
+    check_opts(opts);
+    if (!s->prec_set) fail(MDNP_E_STATE, "no preconditioner set (mdnp_set_preconditioner)");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t stream = pick(ctx, hip_stream);
+    if (s->vec_dtype == MDNP_F64) solve_impl<double>(ctx, s, d_b, d_x, *opts, stats, stream);
+    else solve_impl<float>(ctx, s, d_b, d_x, *opts, stats, stream);
+  });
+}
+
+extern "C" mdnp_status mdnp_solve(mdnp_ctx* ctx, mdnp_sys* s, const double* b, double* x, const mdnp_solve_opts* opts,
+                                  mdnp_inst_stats* stats) {
+  if (!ctx) return MDNP_E_ARG;
+  double* db = nullptr;
+  double* dx = nullptr;
+  mdnp_status st = guarded(ctx, [&] {
+    if (!s || !b || !x) fail(MDNP_E_ARG, "null argument");
+    check_opts(opts);
+    for (int64_t k = 0; k < s->ntot; ++k)
+      if (!std::isfinite(b[k]) || !std::isfinite(x[k])) fail(MDNP_E_NONFINITE, "non-finite entry in b or x0");
+    HIPCHK(hipSetDevice(ctx->device));
+    db = dalloc<double>(s->ntot);
+    dx = dalloc<double>(s->ntot);
+    HIPCHK(hipMemcpyAsync(db, b, sizeof(double) * s->ntot, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(dx, x, sizeof(double) * s->ntot, hipMemcpyHostToDevice, ctx->stream));
+  });
+  if (st != MDNP_OK) {
+    dfree(db);
+    dfree(dx);
+    return st;
+  }
+  st = mdnp_solve_device(ctx, s, db, dx, opts, stats, ctx->stream);
+  if (st == MDNP_OK) {
+    st = guarded(ctx, [&] {
+      HIPCHK(hipMemcpyAsync(x, dx, sizeof(double) * s->ntot, hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  dfree(db);
+  dfree(dx);
+  return st;
+}
+
+extern "C" mdnp_status mdnp_history(const mdnp_sys* s, int32_t inst, double* out, int32_t cap, int32_t* n_out) {
+  if (!s || inst < 0 || inst >= s->n_inst) return MDNP_E_ARG;
+  const SolveWork& w = s->work;
+  const int n = (int)w.h_nhist.size() > inst ? w.h_nhist[inst] : 0;
+  if (n_out) *n_out = n;
+  if (out)
+    for (int k = 0; k < std::min(n, cap); ++k) out[k] = w.h_hist[(size_t)inst * w.hist_cap + k];
+  return MDNP_OK;
+}
+
+extern "C" mdnp_status mdnp_export_basis(mdnp_ctx* ctx, const mdnp_sys* s, int32_t k, void* d_out, void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !d_out) fail(MDNP_E_ARG, "null argument");
+    if (!s->work.V) fail(MDNP_E_STATE, "no solve has run on this system");
+    if (k < 0 || k > s->work.m) fail(MDNP_E_ARG, "basis index out of range");
+    HIPCHK(hipSetDevice(ctx->device));
+    const size_t es = vsize(s->vec_dtype);
+    HIPCHK(hipMemcpyAsync(d_out, (const char*)s->work.V + es * (size_t)s->ntot * k, es * (size_t)s->ntot,
+                          hipMemcpyDeviceToDevice, pick(ctx, hip_stream)));
+  });
+}
+
+// ============================================================================ path steps
+
+extern "C" mdnp_status mdnp_spmv(mdnp_ctx* ctx, mdnp_sys* s, int32_t block, const void* d_x, void* d_y,
+                                 mdnp_dtype dtype, void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !d_x || !d_y) fail(MDNP_E_ARG, "null argument");
+    if (block != 0 && block != 1) fail(MDNP_E_ARG, "block must be 0 (A) or 1 (A00)");
+    if (dtype != MDNP_F32 && dtype != MDNP_F64) fail(MDNP_E_ARG, "dtype must be MDNP_F32 or MDNP_F64");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t stream = pick(ctx, hip_stream);
+    if (block == 0) {
+      if (dtype == MDNP_F64) launch_spmv<double>(s, (const double*)d_x, (double*)d_y, nullptr, false, stream);
+      else launch_spmv<float>(s, (const float*)d_x, (float*)d_y, nullptr, false, stream);
+    } else {
+      if (dtype == MDNP_F64) launch_spmv_a00_all<double>(s, (const double*)d_x, (double*)d_y, stream);
+      else launch_spmv_a00_all<float>(s, (const float*)d_x, (float*)d_y, stream);
+    }
+    HIPCHK(hipGetLastError());
+  });
+}
+
+extern "C" mdnp_status mdnp_tree_solve(mdnp_ctx* ctx, mdnp_sys* s, const void* d_v, void* d_z, void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !d_v || !d_z) fail(MDNP_E_ARG, "null argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t stream = pick(ctx, hip_stream);
+    if (s->vec_dtype == MDNP_F64) launch_tree_solve<double>(s, (const double*)d_v, (double*)d_z, nullptr, 0, stream);
+    else launch_tree_solve<float>(s, (const float*)d_v, (float*)d_z, nullptr, 0, stream);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+extern "C" mdnp_status mdnp_precond_apply(mdnp_ctx* ctx, mdnp_sys* s, const void* d_v, void* d_z, void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !d_v || !d_z) fail(MDNP_E_ARG, "null argument");
+    if (!s->prec_set) fail(MDNP_E_STATE, "no preconditioner set");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t stream = pick(ctx, hip_stream);
+    if (!s->work.part) {
+      s->work.part = dalloc<double>(3 * (size_t)s->blk.nblk + (size_t)s->blk3.nblk);
+    }
+    if (!s->cnn.inv_s) s->cnn.inv_s = dalloc<double>(2 * (size_t)s->n_inst);
+    if (s->vec_dtype == MDNP_F64) apply_prec<double>(s, (const double*)d_v, (double*)d_z, nullptr, false, stream);
+    else apply_prec<float>(s, (const float*)d_v, (float*)d_z, nullptr, false, stream);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+extern "C" int64_t mdnp_cnn_saved_bytes(int32_t batch, int32_t n, mdnp_dtype dtype) {
+  return cnn_saved_bytes(batch, n, dtype);
+}
+
+extern "C" mdnp_status mdnp_cnn_forward(mdnp_ctx* ctx, const float* d_w, const float* d_x, float* d_y, void* d_saved,
+                                        int32_t batch, int32_t n, mdnp_dtype dtype, void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!d_w || !d_x || !d_y) fail(MDNP_E_ARG, "null argument");
+    if (batch < 1 || n < 5 || (n - 1) % 4 != 0) fail(MDNP_E_ARG, "need batch >= 1 and n = 1 (mod 4), n >= 5");
+    if (dtype != MDNP_F32 && dtype != MDNP_BF16) fail(MDNP_E_ARG, "dtype must be MDNP_F32 or MDNP_BF16");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t stream = pick(ctx, hip_stream);
+    CnnState& c = ctx->cnn;
+    c.w = d_w;
+    c.dtype = dtype;
+    cnn_prepare_weights(c, d_w, stream);
+    if (!d_saved && !cnn_reserve(c, batch, n, dtype)) fail(MDNP_E_OOM, "network activation buffers");
+    cnn_forward_batch(c, d_x, d_y, d_saved, batch, n, dtype, stream);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+extern "C" mdnp_status mdnp_cnn_backward(mdnp_ctx* ctx, const float* d_w, const void* d_saved, const float* d_dy,
+                                         float* d_dx, float* d_dw, int32_t batch, int32_t n, mdnp_dtype dtype,
+                                         void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!d_w || !d_saved || !d_dy || !d_dw) fail(MDNP_E_ARG, "null argument");
+    if (batch < 1 || n < 5 || (n - 1) % 4 != 0) fail(MDNP_E_ARG, "need batch >= 1 and n = 1 (mod 4), n >= 5");
+    if (dtype != MDNP_F32 && dtype != MDNP_BF16) fail(MDNP_E_ARG, "dtype must be MDNP_F32 or MDNP_BF16");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t stream = pick(ctx, hip_stream);
+    CnnState& c = ctx->cnn;
+    c.w = d_w;
+    if (c.w_off.empty()) cnn_prepare_weights(c, d_w, stream);
+    cnn_backward_batch(c, d_saved, d_dy, d_dx, d_dw, batch, n, dtype, stream);
+    if (!c.bwd) fail(MDNP_E_OOM, "backward scratch allocation failed");
+    HIPCHK(hipGetLastError());
+  });
+}
+
+extern "C" mdnp_status mdnp_loss_grad(mdnp_ctx* ctx, mdnp_sys* s, const int32_t* d_inst, int32_t n_slots,
+                                      const float* d_r, const float* d_u, float* d_du, double* d_loss,
+                                      void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !d_inst || !d_r || !d_u || !d_du || !d_loss || n_slots < 1) fail(MDNP_E_ARG, "bad argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    launch_loss_grad(s, d_inst, n_slots, d_r, d_u, d_du, d_loss, pick(ctx, hip_stream));
+    if (!s->cnn.loss) fail(MDNP_E_OOM, "loss scratch allocation failed");
+    HIPCHK(hipGetLastError());
+  });
+}
+
+extern "C" mdnp_status mdnp_pack_input(mdnp_ctx* ctx, mdnp_sys* s, const int32_t* d_inst, int32_t n_slots,
+                                       const float* d_r, float* d_x, void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !d_inst || !d_r || !d_x || n_slots < 1) fail(MDNP_E_ARG, "bad argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    launch_pack_input(s, d_inst, n_slots, d_r, d_x, pick(ctx, hip_stream));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+extern "C" mdnp_status mdnp_adam_step(mdnp_ctx* ctx, float* d_w, const float* d_g, float* d_m, float* d_v, int64_t n,
+                                      float lr, float b1, float b2, float eps, int32_t step, void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!d_w || !d_g || !d_m || !d_v || n < 1 || step < 1) fail(MDNP_E_ARG, "bad argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    launch_adam(d_w, d_g, d_m, d_v, n, lr, b1, b2, eps, step, pick(ctx, hip_stream));
+    HIPCHK(hipGetLastError());
+  });
+}

@@ -1,0 +1,771 @@
+// The U-net preconditioner of Section 4.2 (three levels, 16/32/64 channels,
+// 3x3x3 kernels, stride-2 convolutions down, stride-2 transposed convolutions
+// up, skip connections by channel stacking) and its training objective of
+// Section 5.1, on channels-last [batch][z][y][x][channel] activations.
+//
+// This file holds the direct (non-MFMA) kernels: FP32 arithmetic on FP32 or
+// BF16 storage, used for the FP32 network, for the first and last layers of
+// every network, for the backward pass, the loss and Adam.  The matrix-core
+// kernels of the BF16 network live in conv_mfma.hip.
+#include <cmath>
+
+#include "conv_common.hpp"
+#include "kernels.hpp"
+
+namespace mdnp {
+
+namespace {
+
+constexpr int BS = 256;
+
+__device__ __forceinline__ float ld(const float* p) { return *p; }
+__device__ __forceinline__ float ld(const bf16* p) { return __bfloat162float(*p); }
+__device__ __forceinline__ void st_(float* p, float v) { *p = v; }
+__device__ __forceinline__ void st_(bf16* p, float v) { *p = __float2bfloat16(v); }
+
+__device__ __forceinline__ bool is_bnd(int r, int n) {
+  int i = r % n, j = (r / n) % n, k = r / (n * n);
+  return i == 0 || j == 0 || k == 0 || i == n - 1 || j == n - 1 || k == n - 1;
+}
+
+// Input voxel of output voxel o for tap t along one axis, or -1.
+template <int MODE>
+__device__ __forceinline__ int in_coord(int o, int t, int n_in) {
+  if (MODE == KIND_S1) {
+    int i = o + t - 1;
+    return (i >= 0 && i < n_in) ? i : -1;
+  } else if (MODE == KIND_S2) {
+    int i = 2 * o + t - 1;
+    return (i >= 0 && i < n_in) ? i : -1;
+  } else if (MODE == KIND_T2) {
+    int num = o + 1 - t;
+    if (num < 0 || (num & 1)) return -1;
+    int i = num >> 1;
+    return i < n_in ? i : -1;
+  } else {
+    return o;
+  }
+}
+
+// Direct convolution: one thread per output voxel, CO output channels per block
+// row; weights [taps][cin][cout] read with block-uniform addresses.
+template <typename Tin, typename Tout, int MODE, int CO>
+__global__ void __launch_bounds__(BS) k_conv(ConvP p) {
+  const int64_t nvox = (int64_t)p.n_out * p.n_out * p.n_out;
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int co0 = blockIdx.y * CO;
+  const int bt = blockIdx.z;
+  if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
+  if (v >= nvox) return;
+  const int ox = (int)(v % p.n_out), oy = (int)((v / p.n_out) % p.n_out), oz = (int)(v / ((int64_t)p.n_out * p.n_out));
+  const int cin = p.ca + p.cb;
+  float acc[CO];
+#pragma unroll
+  for (int c = 0; c < CO; ++c) acc[c] = p.bias ? p.bias[co0 + c] : 0.0f;
+  const Tin* A = (const Tin*)p.a + (int64_t)bt * p.a_bs;
+  const Tin* B = (const Tin*)p.b + (int64_t)bt * p.b_bs;
+  const int ntap = (MODE == KIND_PT) ? 1 : 27;
+  for (int t = 0; t < ntap; ++t) {
+    const int tz = t / 9, ty = (t / 3) % 3, tx = t % 3;
+    const int iz = in_coord<MODE>(oz, tz, p.n_in);
+    const int iy = in_coord<MODE>(oy, ty, p.n_in);
+    const int ix = in_coord<MODE>(ox, tx, p.n_in);
+    if (iz < 0 || iy < 0 || ix < 0) continue;
+    const int64_t vin = ((int64_t)iz * p.n_in + iy) * p.n_in + ix;
+    const float* wt = p.wt + (int64_t)t * cin * p.cout + co0;
+    const Tin* xa = A + vin * p.lda;
+    for (int ci = 0; ci < p.ca; ++ci) {
+      const float x = ld(xa + ci);
+      const float* w = wt + (int64_t)ci * p.cout;
+#pragma unroll
+      for (int c = 0; c < CO; ++c) acc[c] = fmaf(w[c], x, acc[c]);
+    }
+    if (p.cb) {
+      const Tin* xb = B + vin * p.ldb;
+      for (int ci = 0; ci < p.cb; ++ci) {
+        const float x = ld(xb + ci);
+        const float* w = wt + (int64_t)(p.ca + ci) * p.cout;
+#pragma unroll
+        for (int c = 0; c < CO; ++c) acc[c] = fmaf(w[c], x, acc[c]);
+      }
+    }
+  }
+  Tout* y = (Tout*)p.y + (int64_t)bt * p.y_bs + v * p.ldy + p.y_choff + co0;
+#pragma unroll
+  for (int c = 0; c < CO; ++c) {
+    float r = acc[c];
+    if (p.relu) r = fmaxf(r, 0.0f);
+    if (p.accumulate) r += ld(y + c);
+    st_(y + c, r);
+  }
+}
+
+// First layer inside the solver: input channel 0 = z0 * inv_s (3D part of a
+// Krylov vector), channel 1 = distance field; 2 -> 16, ReLU.
+template <typename Tv, typename Tout>
+__global__ void __launch_bounds__(BS) k_conv_in0(const Tv* __restrict__ z, const int64_t* off,
+                                                 const double* inv_s, const float* __restrict__ dist,
+                                                 const float* __restrict__ wt, const float* __restrict__ bias,
+                                                 int n, Tout* __restrict__ y, const InstState* st) {
+  const int64_t nvox = (int64_t)n * n * n;
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int i = blockIdx.z;
+  if (st && !(st[i].active && st[i].mode == 0)) return;
+  if (v >= nvox) return;
+  const int ox = (int)(v % n), oy = (int)((v / n) % n), oz = (int)(v / ((int64_t)n * n));
+  const float sc = (float)inv_s[i];
+  const Tv* zi = z + off[i];
+  const float* di = dist + (int64_t)i * nvox;
+  float acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = bias[c];
+  for (int t = 0; t < 27; ++t) {
+    const int iz = oz + t / 9 - 1, iy = oy + (t / 3) % 3 - 1, ix = ox + t % 3 - 1;
+    if (iz < 0 || iy < 0 || ix < 0 || iz >= n || iy >= n || ix >= n) continue;
+    const int64_t vin = ((int64_t)iz * n + iy) * n + ix;
+    const float x0 = (float)zi[vin] * sc;
+    const float x1 = di[vin];
+    const float* w = wt + t * 2 * 16;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = fmaf(w[c], x0, fmaf(w[16 + c], x1, acc[c]));
+  }
+  Tout* yo = y + ((int64_t)i * nvox + v) * 16;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) st_(yo + c, fmaxf(acc[c], 0.0f));
+}
+
+// Last layer inside the solver: 1x1 16 -> 1, then z0 = s / alpha * U on the free
+// nodes (Dirichlet nodes keep b0).
+template <typename Tv, typename Tin>
+__global__ void __launch_bounds__(BS) k_head_out(const Tin* __restrict__ d0, const float* __restrict__ wt,
+                                                 const float* __restrict__ bias, int n, Tv* __restrict__ z,
+                                                 const int64_t* off, const double* alpha, double alpha_override,
+                                                 const double* scale, const InstState* st) {
+  const int64_t nvox = (int64_t)n * n * n;
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int i = blockIdx.z;
+  if (st && !(st[i].active && st[i].mode == 0)) return;
+  if (v >= nvox) return;
+  if (is_bnd((int)v, n)) return;
+  const Tin* x = d0 + ((int64_t)i * nvox + v) * 16;
+  float acc = bias[0];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc = fmaf(wt[c], ld(x + c), acc);
+  const double a = alpha_override > 0.0 ? alpha_override : alpha[i];
+  const double s = scale[i];
+  z[off[i] + v] = (Tv)((s / a) * (double)acc);
+}
+
+// Weight copies: forward [taps][cin][cout]; adjoint [taps][cout][cin] with the
+// taps reversed for the stride-1 convolution (the transpose of a correlation
+// is the correlation with the flipped kernel).
+__global__ void k_wt_fwd(const float* __restrict__ w, float* __restrict__ wt, int cout, int taps, int cin) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)cout * taps * cin;
+  if (k >= tot) return;
+  const int co = (int)(k / ((int64_t)taps * cin));
+  const int t = (int)((k / cin) % taps);
+  const int ci = (int)(k % cin);
+  wt[((int64_t)t * cin + ci) * cout + co] = w[k];
+}
+
+__global__ void k_wt_adj(const float* __restrict__ w, float* __restrict__ wt, int cout, int taps, int cin, int flip) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)cout * taps * cin;
+  if (k >= tot) return;
+  const int co = (int)(k / ((int64_t)taps * cin));
+  const int t = (int)((k / cin) % taps);
+  const int ci = (int)(k % cin);
+  const int tt = flip ? taps - 1 - t : t;
+  // adjoint layer: input channels = cout, output channels = cin
+  wt[((int64_t)tt * cout + co) * cin + ci] = w[k];
+}
+
+__global__ void k_wt_adj_split(const float* __restrict__ w, float* __restrict__ w1, float* __restrict__ w2,
+                               int cout, int taps, int cin, int ca, int flip) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)cout * taps * cin;
+  if (k >= tot) return;
+  const int co = (int)(k / ((int64_t)taps * cin));
+  const int t = (int)((k / cin) % taps);
+  const int ci = (int)(k % cin);
+  const int tt = flip ? taps - 1 - t : t;
+  const int cb = cin - ca;
+  if (ci < ca) w1[((int64_t)tt * cout + co) * ca + ci] = w[k];
+  else w2[((int64_t)tt * cout + co) * cb + (ci - ca)] = w[k];
+}
+
+__global__ void k_relu_mask(float* __restrict__ g, const void* __restrict__ out, int out_is_bf16, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float o = out_is_bf16 ? __bfloat162float(((const bf16*)out)[k]) : ((const float*)out)[k];
+  if (!(o > 0.0f)) g[k] = 0.0f;
+}
+
+// Weight gradient dW[co][t][ci] = sum over batch and voxels of dz[p][co] * x_in(p, t)[ci]
+// for one 16x16 (co, ci) tile and one tap per block; the voxel range is split
+// over blockIdx.z and the partial tiles are summed in a second kernel.
+template <typename Tin, int MODE>
+__global__ void __launch_bounds__(BS) k_dw(const float* __restrict__ dz, int cout, const void* xa_, int ca, int lda,
+                                           const void* xb_, int cb, int ldb, int n_in, int n_out, int batch,
+                                           int64_t a_bs, int64_t b_bs, float* __restrict__ part, int nsplit) {
+  __shared__ float sdz[64][17];
+  __shared__ float sx[64][17];
+  const int ntap = MODE == KIND_PT ? 1 : 27;
+  const int t = blockIdx.x % ntap;
+  const int tile = blockIdx.x / ntap;
+  const int cin = ca + cb;
+  const int nci_t = (cin + 15) / 16;
+  const int co0 = (tile / nci_t) * 16, ci0 = (tile % nci_t) * 16;
+  const int split = blockIdx.z;
+  const int tz = t / 9, ty = (t / 3) % 3, tx = t % 3;
+  const int64_t nvo = (int64_t)n_out * n_out * n_out;
+  // for the transposed convolution iterate over input voxels (o = 2 i + t - 1)
+  const int64_t nit = (MODE == KIND_T2) ? (int64_t)n_in * n_in * n_in : nvo;
+  const int64_t total = nit * batch;
+  const int64_t per = (total + nsplit - 1) / nsplit;
+  const int64_t e0 = (int64_t)split * per, e1 = min(total, e0 + per);
+  const int tco = threadIdx.x / 16, tci = threadIdx.x % 16;
+  const Tin* xa = (const Tin*)xa_;
+  const Tin* xb = (const Tin*)xb_;
+  float acc = 0.0f;
+  for (int64_t base = e0; base < e1; base += 64) {
+    // stage 64 (dz, x) voxel pairs
+    for (int q = threadIdx.x; q < 64 * 16; q += BS) {
+      const int vv = q / 16, c = q % 16;
+      const int64_t e = base + vv;
+      float dv = 0.0f, xv = 0.0f;
+      if (e < e1) {
+        const int bt = (int)(e / nit);
+        const int64_t u = e % nit;
+        int64_t vo = -1, vi = -1;
+        if (MODE == KIND_T2) {
+          const int ix = (int)(u % n_in), iy = (int)((u / n_in) % n_in), iz = (int)(u / ((int64_t)n_in * n_in));
+          const int ox = 2 * ix + tx - 1, oy = 2 * iy + ty - 1, oz = 2 * iz + tz - 1;
+          if (ox >= 0 && oy >= 0 && oz >= 0 && ox < n_out && oy < n_out && oz < n_out) {
+            vo = ((int64_t)oz * n_out + oy) * n_out + ox;
+            vi = u;
+          }
+        } else {
+          const int ox = (int)(u % n_out), oy = (int)((u / n_out) % n_out), oz = (int)(u / ((int64_t)n_out * n_out));
+          int ix, iy, iz;
+          if (MODE == KIND_PT) { ix = ox; iy = oy; iz = oz; }
+          else {
+            const int s = MODE == KIND_S2 ? 2 : 1;
+            ix = s * ox + tx - 1; iy = s * oy + ty - 1; iz = s * oz + tz - 1;
+          }
+          if (ix >= 0 && iy >= 0 && iz >= 0 && ix < n_in && iy < n_in && iz < n_in) {
+            vo = u;
+            vi = ((int64_t)iz * n_in + iy) * n_in + ix;
+          }
+        }
+        if (vo >= 0) {
+          const int co = co0 + c, ci = ci0 + c;
+          if (co < cout) dv = dz[((int64_t)bt * nvo + vo) * cout + co];
+          if (ci < ca) xv = ld(xa + (int64_t)bt * a_bs + vi * lda + ci);
+          else if (ci < cin) xv = ld(xb + (int64_t)bt * b_bs + vi * ldb + (ci - ca));
+        }
+      }
+      sdz[vv][c] = dv;
+      sx[vv][c] = xv;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int vv = 0; vv < 64; ++vv) acc = fmaf(sdz[vv][tco], sx[vv][tci], acc);
+    __syncthreads();
+  }
+  // part layout [split][cout][ntap][cin]
+  const int co = co0 + tco, ci = ci0 + tci;
+  if (co < cout && ci < cin) part[(((int64_t)split * cout + co) * ntap + t) * cin + ci] = acc;
+}
+
+__global__ void k_sum_splits(const float* __restrict__ part, float* __restrict__ out, int64_t n, int nsplit) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  float s = 0.0f;
+  for (int q = 0; q < nsplit; ++q) s += part[(int64_t)q * n + k];
+  out[k] = s;
+}
+
+// db[co] = sum over batch and voxels of dz[.][co]; one block per channel.
+__global__ void __launch_bounds__(BS) k_db(const float* __restrict__ dz, int cout, int64_t nrows, float* __restrict__ db) {
+  __shared__ float sh[BS];
+  const int co = blockIdx.x;
+  float s = 0.0f;
+  for (int64_t r = threadIdx.x; r < nrows; r += BS) s += dz[r * cout + co];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = BS / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[co] = sh[0];
+}
+
+// ---------------------------------------------------------------- training objective
+
+__global__ void __launch_bounds__(BS) k_mask_bnd(const float* __restrict__ u, float* __restrict__ um, int n,
+                                                 int64_t n3d) {
+  const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int slot = blockIdx.y;
+  if (k >= n3d) return;
+  const int64_t g = (int64_t)slot * n3d + k;
+  um[g] = is_bnd((int)k, n) ? 0.0f : u[g];
+}
+
+// e = r - Cu / alpha, partial sums of e^2 (one row of partials per slot).
+__global__ void __launch_bounds__(BS) k_loss_e(const float* __restrict__ r, float* __restrict__ cu_e,
+                                               const int32_t* inst, const double* alpha, int64_t n3d,
+                                               double* __restrict__ part, int nbx) {
+  __shared__ double sh[BS / 64];
+  const int slot = blockIdx.y;
+  const double ia = 1.0 / alpha[inst[slot]];
+  double loc = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x; k < n3d; k += (int64_t)nbx * BS) {
+    const int64_t g = (int64_t)slot * n3d + k;
+    const double e = (double)r[g] - (double)cu_e[g] * ia;
+    cu_e[g] = (float)e;
+    loc += e * e;
+  }
+  // block sum
+  for (int o = 32; o > 0; o >>= 1) loc += __shfl_xor(loc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = loc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < BS / 64; ++w) t += sh[w];
+    part[(int64_t)slot * nbx + blockIdx.x] = t;
+  }
+}
+
+__global__ void k_loss_sum(const double* part, int nbx, int n_slots, double* loss) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_slots) return;
+  double t = 0.0;
+  for (int b = 0; b < nbx; ++b) t += part[(int64_t)s * nbx + b];
+  loss[s] = t;
+}
+
+// du = -2 C e / alpha on the free nodes, 0 on the Dirichlet nodes.
+__global__ void __launch_bounds__(BS) k_loss_grad_fin(const float* __restrict__ ce, float* __restrict__ du,
+                                                      const int32_t* inst, const double* alpha, int n,
+                                                      int64_t n3d) {
+  const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int slot = blockIdx.y;
+  if (k >= n3d) return;
+  const int64_t g = (int64_t)slot * n3d + k;
+  du[g] = is_bnd((int)k, n) ? 0.0f : (float)(-2.0 * (double)ce[g] / alpha[inst[slot]]);
+}
+
+__global__ void __launch_bounds__(BS) k_pack_input(const float* __restrict__ r, const float* __restrict__ dist,
+                                                   const int32_t* inst, int64_t n3d, float* __restrict__ x) {
+  const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int slot = blockIdx.y;
+  if (k >= n3d) return;
+  const int64_t g = (int64_t)slot * n3d + k;
+  x[2 * g] = r[g];
+  x[2 * g + 1] = dist[(int64_t)inst[slot] * n3d + k];
+}
+
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float gk = g[k];
+  const float mk = b1 * m[k] + (1.0f - b1) * gk;
+  const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+int64_t cnn_layer_count() { return kNumLayers; }
+
+static inline int64_t cube(int n) { return (int64_t)n * n * n; }
+
+void cnn_prepare_weights(CnnState& c, const float* d_w, hipStream_t stream) {
+  int64_t off = 0, toff = 0;
+  c.w_off.assign(kNumLayers, 0);
+  c.b_off.assign(kNumLayers, 0);
+  c.wt_off.assign(kNumLayers, 0);
+  for (int l = 0; l < kNumLayers; ++l) {
+    const LayerSpec& L = kLayers[l];
+    const int taps = L.kind == KIND_PT ? 1 : 27;
+    const int64_t nw = (int64_t)L.cout * taps * L.cin;
+    c.w_off[l] = off;
+    c.b_off[l] = off + nw;
+    c.wt_off[l] = toff;
+    off += nw + L.cout;
+    toff += nw;
+  }
+  if (!c.wt) hipMalloc(&c.wt, sizeof(float) * (size_t)toff);
+  for (int l = 0; l < kNumLayers; ++l) {
+    const LayerSpec& L = kLayers[l];
+    const int taps = L.kind == KIND_PT ? 1 : 27;
+    const int64_t nw = (int64_t)L.cout * taps * L.cin;
+    hipLaunchKernelGGL(k_wt_fwd, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, stream, d_w + c.w_off[l],
+                       c.wt + c.wt_off[l], L.cout, taps, L.cin);
+  }
+  cnn_prepare_mfma_weights(c, d_w, stream);
+}
+
+// Offsets of the saved tensors (bytes, 256-aligned) in the order
+// X a0 s0 a1 s1 a2 b2 u1 d1 u0 d0 y.
+// offs[12] receives the total size.
+void saved_layout(int batch, int n, mdnp_dtype dtype, int64_t offs[13]) {
+  const int n1 = (n + 1) / 2, n2 = (n1 + 1) / 2;
+  const int64_t es = dtype == MDNP_BF16 ? 2 : 4;
+  const int64_t sz[12] = {4 * batch * cube(n) * 2, es * batch * cube(n) * 16, es * batch * cube(n) * 16,
+                          es * batch * cube(n1) * 32, es * batch * cube(n1) * 32, es * batch * cube(n2) * 64,
+                          es * batch * cube(n2) * 64, es * batch * cube(n1) * 32, es * batch * cube(n1) * 32,
+                          es * batch * cube(n) * 16, es * batch * cube(n) * 16, 4 * batch * cube(n)};
+  int64_t o = 0;
+  for (int k = 0; k < 12; ++k) {
+    offs[k] = o;
+    o += (sz[k] + 255) / 256 * 256;
+  }
+  offs[12] = o;
+}
+
+int64_t cnn_saved_bytes(int batch, int n, mdnp_dtype dtype) {
+  int64_t offs[13];
+  saved_layout(batch, n, dtype, offs);
+  return offs[12];
+}
+
+template <typename Tin, typename Tout>
+static void conv_direct(const ConvP& p, int kind, int batch, hipStream_t stream) {
+  const int64_t nvox = cube(p.n_out);
+  const int co_chunk = p.cout >= 16 ? 16 : 1;
+  dim3 grid((unsigned)((nvox + BS - 1) / BS), p.cout / co_chunk, batch);
+#define LAUNCH_K(MODE)                                                                              \
+  do {                                                                                              \
+    if (co_chunk == 16) hipLaunchKernelGGL((k_conv<Tin, Tout, MODE, 16>), grid, dim3(BS), 0, stream, p); \
+    else hipLaunchKernelGGL((k_conv<Tin, Tout, MODE, 1>), grid, dim3(BS), 0, stream, p);            \
+  } while (0)
+  switch (kind) {
+    case KIND_S1: LAUNCH_K(KIND_S1); break;
+    case KIND_S2: LAUNCH_K(KIND_S2); break;
+    case KIND_T2: LAUNCH_K(KIND_T2); break;
+    default: LAUNCH_K(KIND_PT); break;
+  }
+#undef LAUNCH_K
+}
+
+// Dispatch one layer: MFMA kernels for the BF16 interior layers, direct otherwise.
+template <typename Tin, typename Tout>
+static void conv_layer(const ConvP& p, int kind, int batch, mdnp_dtype dtype, int layer, CnnState& c,
+                       hipStream_t stream) {
+  if (dtype == MDNP_BF16 && conv_mfma_supported(layer) && std::is_same<Tin, bf16>::value &&
+      std::is_same<Tout, bf16>::value) {
+    conv_mfma_layer(p, kind, batch, layer, c, stream);
+    return;
+  }
+  conv_direct<Tin, Tout>(p, kind, batch, stream);
+}
+
+// Layers 1..9 (L0b .. D0) on activations of type T, given the buffer set.
+template <typename T>
+static void unet_middle(CnnState& c, const float* d_w, void* const* act, int batch, int n, mdnp_dtype dtype,
+                        const InstState* st, hipStream_t stream) {
+  const int n1 = (n + 1) / 2, n2 = (n1 + 1) / 2;
+  const int nn[3] = {n, n1, n2};
+  // act indices: 1 a0, 2 s0, 3 a1, 4 s1, 5 a2, 6 b2, 7 u1, 8 d1, 9 u0, 10 d0
+  struct Step { int layer, src_a, src_b, dst, lvl_in, lvl_out; };
+  const Step steps[] = {{1, 1, -1, 2, 0, 0}, {2, 2, -1, 3, 0, 1}, {3, 3, -1, 4, 1, 1}, {4, 4, -1, 5, 1, 2},
+                        {5, 5, -1, 6, 2, 2}, {6, 6, -1, 7, 2, 1}, {7, 7, 4, 8, 1, 1},  {8, 8, -1, 9, 1, 0},
+                        {9, 9, 2, 10, 0, 0}};
+  for (const Step& s : steps) {
+    const LayerSpec& L = kLayers[s.layer];
+    ConvP p{};
+    const int ca = s.src_b >= 0 ? L.cin / 2 : L.cin;
+    p.a = act[s.src_a];
+    p.ca = ca;
+    p.lda = ca;
+    p.a_bs = cube(nn[s.lvl_in]) * ca;
+    if (s.src_b >= 0) {
+      p.b = act[s.src_b];
+      p.cb = L.cin - ca;
+      p.ldb = p.cb;
+      p.b_bs = cube(nn[s.lvl_in]) * p.cb;
+    }
+    p.n_in = nn[s.lvl_in];
+    p.n_out = nn[s.lvl_out];
+    p.wt = c.wt + c.wt_off[s.layer];
+    p.bias = d_w + c.b_off[s.layer];
+    p.cout = L.cout;
+    p.y = act[s.dst];
+    p.ldy = L.cout;
+    p.y_bs = cube(nn[s.lvl_out]) * L.cout;
+    p.relu = L.relu;
+    p.st = st;
+    p.want_mode = 0;
+    conv_layer<T, T>(p, L.kind, batch, dtype, s.layer, c, stream);
+  }
+}
+
+template <typename T>
+static void forward_t(CnnState& c, const float* in, float* out, void* saved, int batch, int n, mdnp_dtype dtype,
+                      hipStream_t stream) {
+  int64_t offs[13];
+  saved_layout(batch, n, dtype, offs);
+  char* base = (char*)saved;
+  void* act[12];
+  for (int k = 0; k < 12; ++k) act[k] = base + offs[k];
+  hipMemcpyAsync(act[0], in, sizeof(float) * 2 * batch * cube(n), hipMemcpyDeviceToDevice, stream);
+  const float* d_w = c.w;
+  {  // L0a: FP32 input
+    const LayerSpec& L = kLayers[0];
+    ConvP p{};
+    p.a = act[0]; p.ca = 2; p.lda = 2; p.a_bs = cube(n) * 2;
+    p.n_in = n; p.n_out = n;
+    p.wt = c.wt + c.wt_off[0]; p.bias = d_w + c.b_off[0]; p.cout = L.cout;
+    p.y = act[1]; p.ldy = 16; p.y_bs = cube(n) * 16; p.relu = 1;
+    conv_direct<float, T>(p, KIND_S1, batch, stream);
+  }
+  unet_middle<T>(c, d_w, act, batch, n, dtype, nullptr, stream);
+  {  // H: 16 -> 1, FP32 output
+    ConvP p{};
+    p.a = act[10]; p.ca = 16; p.lda = 16; p.a_bs = cube(n) * 16;
+    p.n_in = n; p.n_out = n;
+    p.wt = c.wt + c.wt_off[10]; p.bias = d_w + c.b_off[10]; p.cout = 1;
+    p.y = act[11]; p.ldy = 1; p.y_bs = cube(n); p.relu = 0;
+    conv_direct<T, float>(p, KIND_PT, batch, stream);
+  }
+  if (out) hipMemcpyAsync(out, act[11], sizeof(float) * batch * cube(n), hipMemcpyDeviceToDevice, stream);
+}
+
+static bool ensure_scratch(CnnState& c, size_t bytes) {
+  if (c.act_bytes >= bytes) return true;
+  if (c.act[0]) hipFree(c.act[0]);
+  c.act[0] = nullptr;
+  c.act_bytes = 0;
+  if (hipMalloc(&c.act[0], bytes) != hipSuccess) { c.act[0] = nullptr; return false; }
+  c.act_bytes = bytes;
+  return true;
+}
+
+bool cnn_reserve(CnnState& c, int batch, int n, mdnp_dtype dtype) {
+  return ensure_scratch(c, (size_t)cnn_saved_bytes(batch, n, dtype));
+}
+
+void cnn_forward_batch(CnnState& c, const float* in, float* out, void* saved, int batch, int n, mdnp_dtype dtype,
+                       hipStream_t stream) {
+  if (!saved) {
+    if (!ensure_scratch(c, (size_t)cnn_saved_bytes(batch, n, dtype))) return;
+    saved = c.act[0];
+  }
+  if (dtype == MDNP_BF16) forward_t<bf16>(c, in, out, saved, batch, n, dtype, stream);
+  else forward_t<float>(c, in, out, saved, batch, n, dtype, stream);
+}
+
+template <typename Tv>
+void cnn_apply_in_solver(mdnp_sys* s, Tv* z, const InstState* st, hipStream_t stream) {
+  CnnState& c = s->cnn;
+  const int n = s->n, batch = s->n_inst;
+  if (!ensure_scratch(c, (size_t)cnn_saved_bytes(batch, n, c.dtype))) return;
+  int64_t offs[13];
+  saved_layout(batch, n, c.dtype, offs);
+  void* act[12];
+  for (int k = 0; k < 12; ++k) act[k] = (char*)c.act[0] + offs[k];
+  const dim3 grid((unsigned)((cube(n) + BS - 1) / BS), 1, batch);
+  if (c.dtype == MDNP_BF16) {
+    hipLaunchKernelGGL((k_conv_in0<Tv, bf16>), grid, dim3(BS), 0, stream, z, s->d_off, c.inv_s, s->d_dist,
+                       c.wt + c.wt_off[0], c.w + c.b_off[0], n, (bf16*)act[1], st);
+    unet_middle<bf16>(c, c.w, act, batch, n, c.dtype, st, stream);
+    hipLaunchKernelGGL((k_head_out<Tv, bf16>), grid, dim3(BS), 0, stream, (const bf16*)act[10],
+                       c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override, c.inv_s + s->n_inst, st);
+  } else {
+    hipLaunchKernelGGL((k_conv_in0<Tv, float>), grid, dim3(BS), 0, stream, z, s->d_off, c.inv_s, s->d_dist,
+                       c.wt + c.wt_off[0], c.w + c.b_off[0], n, (float*)act[1], st);
+    unet_middle<float>(c, c.w, act, batch, n, c.dtype, st, stream);
+    hipLaunchKernelGGL((k_head_out<Tv, float>), grid, dim3(BS), 0, stream, (const float*)act[10],
+                       c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override, c.inv_s + s->n_inst, st);
+  }
+}
+template void cnn_apply_in_solver<float>(mdnp_sys*, float*, const InstState*, hipStream_t);
+template void cnn_apply_in_solver<double>(mdnp_sys*, double*, const InstState*, hipStream_t);
+
+// ---------------------------------------------------------------- backward
+
+namespace {
+struct BwdBufs {
+  float* g[12];     // gradients w.r.t. the saved tensors (FP32), same shapes
+  float* wadj;      // adjoint weights scratch
+  float* part;      // split partials
+  int64_t part_n;
+};
+}  // namespace
+
+template <typename T>
+static void backward_t(CnnState& c, const void* saved, const float* dy, float* dx, float* dw, int batch, int n,
+                       mdnp_dtype dtype, hipStream_t stream) {
+  const int n1 = (n + 1) / 2, n2 = (n1 + 1) / 2;
+  const int nn[3] = {n, n1, n2};
+  int64_t offs[13];
+  saved_layout(batch, n, dtype, offs);
+  const void* act[12];
+  for (int k = 0; k < 12; ++k) act[k] = (const char*)saved + offs[k];
+  // gradient buffers: one FP32 tensor per saved tensor (except y)
+  const int chans[12] = {2, 16, 16, 32, 32, 64, 64, 32, 32, 16, 16, 1};
+  const int lvl[12] = {0, 0, 0, 1, 1, 2, 2, 1, 1, 0, 0, 0};
+  int64_t goff[12], gtot = 0;
+  for (int k = 0; k < 12; ++k) {
+    goff[k] = gtot;
+    gtot += ((int64_t)batch * cube(nn[lvl[k]]) * chans[k] + 63) / 64 * 64;
+  }
+  const int nsplit = 64;
+  const int64_t part_n = (int64_t)nsplit * 27 * 64 * 64;
+  const int64_t wadj_n = 27 * 64 * 64;
+  const size_t need = sizeof(float) * (size_t)(gtot + part_n + wadj_n);
+  if (c.bwd_bytes < need) {
+    if (c.bwd) hipFree(c.bwd);
+    c.bwd = nullptr;
+    if (hipMalloc(&c.bwd, need) != hipSuccess) { c.bwd = nullptr; c.bwd_bytes = 0; return; }
+    c.bwd_bytes = need;
+  }
+  float* scratch = (float*)c.bwd;
+  float* G[12];
+  for (int k = 0; k < 12; ++k) G[k] = scratch + goff[k];
+  float* part = scratch + gtot;
+  float* wadj = part + part_n;
+  hipMemsetAsync(scratch, 0, sizeof(float) * (size_t)gtot, stream);
+  // dy -> G[11]
+  hipMemcpyAsync(G[11], dy, sizeof(float) * batch * cube(n), hipMemcpyDeviceToDevice, stream);
+
+  struct BStep { int layer, in_a, in_b, out; };
+  // reverse order; inputs as in the forward
+  const BStep steps[] = {{10, 10, -1, 11}, {9, 9, 2, 10}, {8, 8, -1, 9}, {7, 7, 4, 8}, {6, 6, -1, 7},
+                         {5, 5, -1, 6},   {4, 4, -1, 5}, {3, 3, -1, 4}, {2, 2, -1, 3}, {1, 1, -1, 2},
+                         {0, 0, -1, 1}};
+  for (const BStep& s : steps) {
+    const LayerSpec& L = kLayers[s.layer];
+    const int taps = L.kind == KIND_PT ? 1 : 27;
+    const int lin = lvl[s.in_a], lout = lvl[s.out];
+    const int64_t nout_vox = (int64_t)batch * cube(nn[lout]);
+    float* dz = G[s.out];
+    // ReLU mask from the saved output
+    if (L.relu)
+      hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)((nout_vox * L.cout + 255) / 256)), dim3(256), 0, stream, dz,
+                         act[s.out], dtype == MDNP_BF16 ? 1 : 0, nout_vox * L.cout);
+    // weight gradient
+    const int ca = s.in_b >= 0 ? L.cin / 2 : L.cin;
+    const int cb = L.cin - ca;
+    const bool in_fp32 = (s.in_a == 0);  // X is stored in FP32
+    const int ntiles = ((L.cout + 15) / 16) * ((L.cin + 15) / 16);
+    dim3 g((unsigned)(taps * ntiles), 1, nsplit);
+#define DW_LAUNCH(TIN, MODE)                                                                                   \
+  hipLaunchKernelGGL((k_dw<TIN, MODE>), g, dim3(BS), 0, stream, dz, L.cout, act[s.in_a], ca, ca,                \
+                     s.in_b >= 0 ? act[s.in_b] : nullptr, cb, cb, nn[lin], nn[lout], batch,                    \
+                     cube(nn[lin]) * ca, cube(nn[lin]) * cb, part, nsplit)
+    if (in_fp32) {
+      DW_LAUNCH(float, KIND_S1);
+    } else {
+      switch (L.kind) {
+        case KIND_S1: DW_LAUNCH(T, KIND_S1); break;
+        case KIND_S2: DW_LAUNCH(T, KIND_S2); break;
+        case KIND_T2: DW_LAUNCH(T, KIND_T2); break;
+        default: DW_LAUNCH(T, KIND_PT); break;
+      }
+    }
+#undef DW_LAUNCH
+    const int64_t nw = (int64_t)L.cout * taps * L.cin;
+    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, stream, part,
+                       dw + c.w_off[s.layer], nw, nsplit);
+    hipLaunchKernelGGL(k_db, dim3(L.cout), dim3(BS), 0, stream, dz, L.cout, nout_vox, dw + c.b_off[s.layer]);
+    // data gradient: adjoint layer (input channels = cout, output channels = cin)
+    if (s.layer == 0 && !dx) continue;
+    const int flip = L.kind == KIND_S1 ? 1 : 0;
+    hipLaunchKernelGGL(k_wt_adj, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, stream, c.w + c.w_off[s.layer],
+                       wadj, L.cout, taps, L.cin, flip);
+    ConvP p{};
+    p.a = dz; p.ca = L.cout; p.lda = L.cout; p.a_bs = cube(nn[lout]) * L.cout;
+    p.n_in = nn[lout]; p.n_out = nn[lin];
+    p.wt = wadj; p.bias = nullptr; p.relu = 0; p.accumulate = 1;
+    const int adj_kind = L.kind == KIND_S1 ? KIND_S1 : L.kind == KIND_S2 ? KIND_T2 : L.kind == KIND_T2 ? KIND_S2 : KIND_PT;
+    if (s.in_b < 0) {
+      p.cout = L.cin;
+      p.y = (s.layer == 0) ? (void*)dx : (void*)G[s.in_a];
+      p.ldy = L.cin;
+      p.y_bs = cube(nn[lin]) * L.cin;
+      if (s.layer == 0) p.accumulate = 0;
+      conv_direct<float, float>(p, adj_kind, batch, stream);
+    } else {
+      // channel-stacked input: the adjoint output channels [0, ca) go to source A's
+      // gradient and [ca, cin) to source B's; two compact adjoint weight copies
+      float* w1 = wadj;
+      float* w2 = wadj + (int64_t)taps * L.cout * ca;
+      hipLaunchKernelGGL(k_wt_adj_split, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, stream,
+                         c.w + c.w_off[s.layer], w1, w2, L.cout, taps, L.cin, ca, flip);
+      ConvP pa = p;
+      pa.wt = w1; pa.cout = ca; pa.y = G[s.in_a]; pa.ldy = ca; pa.y_bs = cube(nn[lin]) * ca;
+      conv_direct<float, float>(pa, adj_kind, batch, stream);
+      ConvP pb = p;
+      pb.wt = w2; pb.cout = cb; pb.y = G[s.in_b]; pb.ldy = cb; pb.y_bs = cube(nn[lin]) * cb;
+      conv_direct<float, float>(pb, adj_kind, batch, stream);
+    }
+  }
+}
+
+void cnn_backward_batch(CnnState& c, const void* saved, const float* dy, float* dx, float* dw, int batch, int n,
+                        mdnp_dtype dtype, hipStream_t stream) {
+  if (dtype == MDNP_BF16) backward_t<bf16>(c, saved, dy, dx, dw, batch, n, dtype, stream);
+  else backward_t<float>(c, saved, dy, dx, dw, batch, n, dtype, stream);
+}
+
+void launch_loss_grad(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u, float* du,
+                      double* loss, hipStream_t stream) {
+  const int64_t n3d = s->n3d;
+  const int nbx = 64;
+  const size_t need = (size_t)n_slots * n3d * 2 * sizeof(float) + (size_t)n_slots * nbx * sizeof(double);
+  CnnState& c = s->cnn;
+  if (c.loss_bytes < need) {
+    if (c.loss) hipFree(c.loss);
+    c.loss = nullptr;
+    if (hipMalloc(&c.loss, need) != hipSuccess) { c.loss = nullptr; c.loss_bytes = 0; return; }
+    c.loss_bytes = need;
+  }
+  float* buf = (float*)c.loss;
+  float* um = buf;
+  float* ce = buf + (size_t)n_slots * n3d;
+  double* part = (double*)(buf + (size_t)n_slots * n3d * 2);
+  const dim3 g2((unsigned)((n3d + BS - 1) / BS), n_slots);
+  hipLaunchKernelGGL(k_mask_bnd, g2, dim3(BS), 0, stream, u, um, s->n, n3d);
+  launch_spmv_a00_slots(s, inst, n_slots, um, ce, stream);
+  hipLaunchKernelGGL(k_loss_e, dim3(nbx, n_slots), dim3(BS), 0, stream, r, ce, inst, s->d_alpha, n3d, part, nbx);
+  hipLaunchKernelGGL(k_loss_sum, dim3((n_slots + 63) / 64), dim3(64), 0, stream, part, nbx, n_slots, loss);
+  launch_spmv_a00_slots(s, inst, n_slots, ce, um, stream);
+  hipLaunchKernelGGL(k_loss_grad_fin, g2, dim3(BS), 0, stream, um, du, inst, s->d_alpha, s->n, n3d);
+}
+
+void launch_pack_input(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, float* x,
+                       hipStream_t stream) {
+  const int64_t n3d = s->n3d;
+  const dim3 g2((unsigned)((n3d + BS - 1) / BS), n_slots);
+  hipLaunchKernelGGL(k_pack_input, g2, dim3(BS), 0, stream, r, s->d_dist, inst, n3d, x);
+}
+
+void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                 int step, hipStream_t stream) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, w, g, m, v, n, lr, b1, b2,
+                     eps, c1, c2);
+}
+
+void cnn_release(CnnState& c) {
+  if (c.w_own) hipFree(c.w_own);
+  if (c.bwd) hipFree(c.bwd);
+  if (c.loss) hipFree(c.loss);
+  if (c.wt) hipFree(c.wt);
+  if (c.wmf) hipFree(c.wmf);
+  if (c.act[0]) hipFree(c.act[0]);
+  if (c.inv_s) hipFree(c.inv_s);
+  c = CnnState();
+}
+
+}  // namespace mdnp

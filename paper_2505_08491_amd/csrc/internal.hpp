@@ -1,0 +1,138 @@
+// Internal structures shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "assembly.hpp"
+#include "mdnp.h"
+
+namespace mdnp {
+
+typedef __hip_bfloat16 bf16;
+
+// Per-instance solver state, kept in device memory and read by every kernel of
+// an Arnoldi step (masking of converged or inactive instances).
+struct InstState {
+  int32_t active;      // takes part in the Arnoldi steps of the current cycle
+  int32_t done;        // finished (converged or given up)
+  int32_t converged;
+  int32_t mode;        // 0 = configured preconditioner, 1 = Jacobi fallback
+  int32_t jend;        // Arnoldi steps taken in the current cycle
+  int32_t iters;       // steps before the fallback
+  int32_t fb_iters;    // steps on the fallback
+  int32_t stalled;     // set by the cycle-start kernel when the stall rule fires
+  int32_t nhist;       // entries written to the history
+  int32_t cycles;
+  int32_t max_iters;   // step cap of the current mode
+  int32_t pad;
+  double bnorm;        // ||b||
+  double beta;         // ||r|| at the start of the current cycle
+  double rel;          // true relative residual at the start of the current cycle
+  double prev_rel;     // same, one cycle earlier
+  double tol;
+  double scale3d;      // ||b0|| of the current preconditioner input (network normalisation)
+};
+
+// Reduction tiling: contiguous element chunks, each inside one instance.
+struct Blocks {
+  int nblk = 0;
+  int chunk = 0;
+  int32_t* inst = nullptr;     // [nblk]
+  int64_t* start = nullptr;    // [nblk] element start (global)
+  int64_t* end = nullptr;      // [nblk]
+  int32_t* first = nullptr;    // [n_inst + 1] first block of each instance
+  std::vector<int32_t> h_first;
+};
+
+struct CnnState {
+  bool ready = false;
+  mdnp_dtype dtype = MDNP_F32;
+  const float* w = nullptr;    // flat weights in use [353713] (owned copy or borrowed)
+  float* w_own = nullptr;      // owned copy set by mdnp_set_preconditioner
+  float* wt = nullptr;         // per-layer [taps][cin][cout] copies for the direct kernels
+  bf16* wmf = nullptr;         // per-layer bf16 [cout][taps][cin] copies for the MFMA kernels
+  std::vector<int64_t> w_off, wt_off, b_off;  // per-layer offsets
+  int batch = 0, n = 0;
+  void* act[12] = {};          // activation buffers
+  size_t act_bytes = 0;
+  double* inv_s = nullptr;     // [n_inst] 1 / ||b0||, followed by [n_inst] ||b0||
+  void* bwd = nullptr;         // backward scratch
+  size_t bwd_bytes = 0;
+  void* loss = nullptr;        // loss scratch
+  size_t loss_bytes = 0;
+};
+
+struct SolveWork {
+  int m = 0;                   // restart the buffers were sized for
+  int hist_cap = 0;
+  void* V = nullptr;           // (m+1) x ntot vectors
+  void* Z = nullptr;           // m x ntot
+  double* r = nullptr;         // ntot
+  double* H = nullptr;         // n_inst x (m+1) x m
+  double* cs = nullptr;
+  double* sn = nullptr;
+  double* g = nullptr;         // n_inst x (m+1)
+  double* y = nullptr;         // n_inst x m
+  double* part = nullptr;      // 3 x nblk partial sums
+  double* hist = nullptr;      // n_inst x hist_cap
+  InstState* st = nullptr;     // n_inst
+  hipGraphExec_t graph = nullptr;
+  int graph_m = -1, graph_fb = -1;
+  std::vector<double> h_hist;
+  std::vector<int32_t> h_nhist;
+};
+
+}  // namespace mdnp
+
+struct mdnp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<mdnp_sys*> systems;
+  mdnp::CnnState cnn;              // state of the stand-alone network calls
+};
+
+struct mdnp_sys {
+  mdnp_ctx* ctx = nullptr;
+  int n_inst = 0, n_cells = 0, n = 0, n3d = 0;
+  mdnp_dtype vec_dtype = MDNP_F32;
+  std::vector<mdnp::HostInstance> host;
+  std::vector<int64_t> off;        // [n_inst + 1] vector offsets
+  std::vector<int64_t> nnz_off;    // [n_inst + 1]
+  int64_t ntot = 0, nnz_tot = 0;
+  int max_n1d = 0;
+  // device arrays
+  int64_t* d_off = nullptr;
+  int32_t* d_rowptr = nullptr;     // [ntot + 1], global entry offsets
+  int32_t* d_col = nullptr;        // global column indices
+  double* d_val64 = nullptr;
+  float* d_val32 = nullptr;
+  int32_t* d_a01 = nullptr;        // [n_inst * n3d] first entry of each 3D row with a 1D column
+  double* d_dinv = nullptr;        // [ntot] 1 / diag(A)
+  float* d_dist = nullptr;         // [n_inst * n3d]
+  double* d_alpha = nullptr;       // [n_inst]
+  // tree factorisation
+  int32_t* d_t_off = nullptr;      // [n_inst + 1] node offsets (cumulative n1d)
+  int32_t* d_t_lvloff = nullptr;   // [n_inst + 1] offsets into lvl_ptr
+  int32_t* d_t_lvlptr = nullptr;   // level pointers, local to each instance's node block
+  int32_t* d_t_lvlnodes = nullptr; // local node ids, per instance block
+  int32_t* d_t_parent = nullptr;   // local
+  int32_t* d_t_childptr = nullptr; // [node + 1] absolute into child_idx (per instance n1d+1 entries)
+  int32_t* d_t_childidx = nullptr; // local node ids
+  double* d_t_lval = nullptr;
+  double* d_t_dinv = nullptr;
+  mdnp::Blocks blk;                // whole vectors
+  mdnp::Blocks blk3;               // 3D parts only
+  // preconditioner
+  mdnp_prec_kind kind = MDNP_PREC_NONE;
+  bool prec_set = false;
+  double alpha_override = 0.0;
+  mdnp::CnnState cnn;
+  mdnp::SolveWork work;
+};

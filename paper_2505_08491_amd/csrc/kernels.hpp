@@ -1,0 +1,88 @@
+// Host-side launchers of the HIP kernels (implemented in krylov.hip and conv.hip).
+#pragma once
+
+#include "internal.hpp"
+
+namespace mdnp {
+
+// ---------------------------------------------------------------- Krylov (krylov.hip)
+// y = A x over the whole system (CSR, block diagonal over instances).  When
+// `mask` is set, instances whose state is not active are skipped.
+template <typename T>
+void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, hipStream_t stream);
+// y = A00 x on slots [n_slots][n3d] that map to instances `inst` (device).
+void launch_spmv_a00_slots(mdnp_sys* s, const int32_t* inst, int n_slots, const float* x, float* y,
+                           hipStream_t stream);
+template <typename T>
+void launch_spmv_a00_all(mdnp_sys* s, const T* x, T* y, hipStream_t stream);
+
+// r = b - A x in FP64 with per-block partial sums of r^2 (instances not done).
+void launch_residual(mdnp_sys* s, const double* b, const double* x, double* r, double* part,
+                     const InstState* st, hipStream_t stream);
+// per-block partial sums of x^2 over whole vectors
+void launch_norm2_partials(mdnp_sys* s, const double* x, double* part, hipStream_t stream);
+void launch_init_state(mdnp_sys* s, InstState* st, const double* part, double tol, int max_iters,
+                       hipStream_t stream);
+void launch_cycle_start(mdnp_sys* s, InstState* st, const double* part, double* g, double* hist,
+                        int hist_cap, int m, hipStream_t stream);
+template <typename T>
+void launch_scale_to(mdnp_sys* s, const double* r, T* v0, const InstState* st, hipStream_t stream);
+
+// preconditioner pieces
+template <typename T>
+void launch_prec_copy(mdnp_sys* s, const T* v, T* z, const InstState* st, hipStream_t stream);
+template <typename T>
+void launch_prec_jacobi(mdnp_sys* s, const T* v, T* z, const InstState* st, int want_mode,
+                        hipStream_t stream);
+void tree_solve_setup(size_t shm_bytes);
+template <typename T>
+void launch_tree_solve(mdnp_sys* s, const T* v, T* z, const InstState* st, int want_mode,
+                       hipStream_t stream);
+template <typename T>
+void launch_extension(mdnp_sys* s, const T* v, T* z, double* part3, const InstState* st, int want_mode,
+                      hipStream_t stream);
+template <typename T>
+void launch_block_jacobi3d(mdnp_sys* s, T* z, const InstState* st, int want_mode, hipStream_t stream);
+void launch_inv_scale(mdnp_sys* s, const double* part3, double* inv_s, InstState* st, int want_mode,
+                      hipStream_t stream);
+
+// Arnoldi
+template <typename T>
+void launch_mgs(mdnp_sys* s, T* V, int j, int k, const double* part_prev, double* part_cur,
+                double* part_w0, double* H, int m, const InstState* st, hipStream_t stream);
+template <typename T>
+void launch_mgs_finish(mdnp_sys* s, T* V, int j, const double* part_last, const double* part_w0,
+                       double* H, double* cs, double* sn, double* g, double* hist, int hist_cap,
+                       int m, InstState* st, hipStream_t stream);
+void launch_solve_y(mdnp_sys* s, const double* H, const double* g, double* y, int m, const InstState* st,
+                    hipStream_t stream);
+template <typename T>
+void launch_update_x(mdnp_sys* s, const T* Z, const double* y, double* x, int m, const InstState* st,
+                     hipStream_t stream);
+
+// ---------------------------------------------------------------- network (conv.hip)
+int64_t cnn_layer_count();
+// Prepare weight copies for the given flat FP32 weights (device pointer).
+void cnn_prepare_weights(CnnState& c, const float* d_w, hipStream_t stream);
+// Whole U-net on a batch; `in` FP32 [batch][n^3][2]; `out` FP32 [batch][n^3];
+// `saved` non-null: keep every activation for the backward pass.
+void cnn_forward_batch(CnnState& c, const float* in, float* out, void* saved, int batch, int n,
+                       mdnp_dtype dtype, hipStream_t stream);
+int64_t cnn_saved_bytes(int batch, int n, mdnp_dtype dtype);
+// Allocate the activation scratch of a batch; false when the allocation fails.
+bool cnn_reserve(CnnState& c, int batch, int n, mdnp_dtype dtype);
+void cnn_backward_batch(CnnState& c, const void* saved, const float* dy, float* dx, float* dw,
+                        int batch, int n, mdnp_dtype dtype, hipStream_t stream);
+// In-solver application on the 3D parts of vector Z (type T): reads z0 * inv_s,
+// the distance field, writes z0 = s / alpha * U on the free nodes.
+template <typename T>
+void cnn_apply_in_solver(mdnp_sys* s, T* z, const InstState* st, hipStream_t stream);
+void cnn_release(CnnState& c);
+void launch_loss_grad(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u,
+                      float* du, double* loss, hipStream_t stream);
+void launch_pack_input(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, float* x,
+                       hipStream_t stream);
+void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                 float eps, int step, hipStream_t stream);
+
+}  // namespace mdnp

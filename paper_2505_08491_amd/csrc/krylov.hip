@@ -1,0 +1,650 @@
+// Krylov kernels of the flexible GMRES iteration (Section 4, restarted FGMRES
+// with right preconditioning) and of the block preconditioner of Section 2.2.
+//
+// Layout: the vectors of all instances are concatenated; reductions are done
+// per contiguous chunk ("block") inside one instance, each block writing one
+// FP64 partial sum; every consumer sums the partials of its instance in a
+// fixed order, so results are bitwise reproducible run to run.
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace mdnp {
+
+namespace {
+
+constexpr int BS = 256;  // threads per block for vector kernels
+
+template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
+template <> __device__ __forceinline__ double to_d<bf16>(bf16 v) { return (double)__bfloat162float(v); }
+template <typename T> __device__ __forceinline__ T from_d(double v) { return (T)v; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the block; result valid in every thread.
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < nw; ++k) t += sh[k];
+  __syncthreads();
+  return t;
+}
+
+// Sum of the partials of instance i (fixed order), result in every thread.
+__device__ double inst_sum(const double* part, const int32_t* first, int i, double* sh) {
+  double t = 0.0;
+  for (int b = first[i] + threadIdx.x; b < first[i + 1]; b += blockDim.x) t += part[b];
+  return block_sum(t, sh);
+}
+
+__device__ __forceinline__ int find_inst(const int64_t* off, int n_inst, int64_t g) {
+  int lo = 0, hi = n_inst;  // off[lo] <= g < off[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool is_boundary(int r, int n) {
+  int i = r % n, j = (r / n) % n, k = r / (n * n);
+  return i == 0 || j == 0 || k == 0 || i == n - 1 || j == n - 1 || k == n - 1;
+}
+
+// ---------------------------------------------------------------- SpMV
+
+// CSR with G lanes per row; rows of each block are the block's element chunk.
+template <typename Tv, typename Tm, typename Tacc, int G>
+__global__ void __launch_bounds__(BS) k_spmv(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                             const Tm* __restrict__ val, const Tv* __restrict__ x,
+                                             Tv* __restrict__ y, const int32_t* binst, const int64_t* bstart,
+                                             const int64_t* bend, const InstState* st, int mask) {
+  const int b = blockIdx.x;
+  if (mask && !st[binst[b]].active) return;
+  const int64_t r0 = bstart[b], r1 = bend[b];
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = blockDim.x / G;
+  for (int64_t r = r0 + grp; r < r1; r += ng) {
+    Tacc acc = 0;
+    const int e = rp[r + 1];
+    for (int k = rp[r] + lane; k < e; k += G) acc += (Tacc)val[k] * (Tacc)x[col[k]];
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+    if (lane == 0) y[r] = (Tv)acc;
+  }
+}
+
+// y = A00 x for the 3D unknowns of instance inst[slot], vectors [slot][n3d].
+template <typename T, typename Tm, int G>
+__global__ void __launch_bounds__(BS) k_spmv_a00(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                 const Tm* __restrict__ val, const int64_t* off,
+                                                 const int32_t* a01, const int32_t* inst, int n3d,
+                                                 const T* __restrict__ x, T* __restrict__ y) {
+  const int slot = blockIdx.y;
+  const int i = inst ? inst[slot] : slot;
+  const int64_t base = off[i];
+  const T* xs = x + (int64_t)slot * n3d;
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = blockDim.x / G;
+  const int rows_per_block = ng * 16;
+  const int r0 = blockIdx.x * rows_per_block;
+  const int r1 = min(r0 + rows_per_block, n3d);
+  for (int r = r0 + grp; r < r1; r += ng) {
+    const int64_t g = base + r;
+    double acc = 0.0;
+    const int e = a01[(int64_t)i * n3d + r];  // 3D columns end where the 1D ones start
+    for (int k = rp[g] + lane; k < e; k += G) acc += (double)val[k] * (double)xs[col[k] - base];
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+    if (lane == 0) y[(int64_t)slot * n3d + r] = (T)acc;
+  }
+}
+
+// r = b - A x (FP64) and partial sums of r^2 per block.
+template <int G>
+__global__ void __launch_bounds__(BS) k_residual(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                 const double* __restrict__ val, const double* __restrict__ x,
+                                                 const double* __restrict__ bvec, double* __restrict__ r,
+                                                 const int32_t* binst, const int64_t* bstart,
+                                                 const int64_t* bend, const InstState* st, double* part) {
+  __shared__ double sh[BS / 64];
+  const int b = blockIdx.x;
+  if (st && st[binst[b]].done) {
+    if (threadIdx.x == 0) part[b] = 0.0;
+    return;
+  }
+  const int64_t r0 = bstart[b], r1 = bend[b];
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = blockDim.x / G;
+  double loc = 0.0;
+  for (int64_t row = r0 + grp; row < r1; row += ng) {
+    double acc = 0.0;
+    const int e = rp[row + 1];
+    for (int k = rp[row] + lane; k < e; k += G) acc += val[k] * x[col[k]];
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+    if (lane == 0) {
+      double rv = bvec[row] - acc;
+      r[row] = rv;
+      loc += rv * rv;
+    }
+  }
+  double t = block_sum(loc, sh);
+  if (threadIdx.x == 0) part[b] = t;
+}
+
+__global__ void __launch_bounds__(BS) k_norm2_part(const double* __restrict__ x, const int64_t* bstart,
+                                                   const int64_t* bend, double* part) {
+  __shared__ double sh[BS / 64];
+  const int b = blockIdx.x;
+  double loc = 0.0;
+  for (int64_t e = bstart[b] + threadIdx.x; e < bend[b]; e += blockDim.x) loc += x[e] * x[e];
+  double t = block_sum(loc, sh);
+  if (threadIdx.x == 0) part[b] = t;
+}
+
+// ---------------------------------------------------------------- cycle control
+
+__global__ void k_init_state(InstState* st, const double* part, const int32_t* first, int n_inst,
+                             double tol, int max_iters) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  double s = 0.0;
+  for (int b = first[i]; b < first[i + 1]; ++b) s += part[b];
+  InstState z{};
+  z.bnorm = sqrt(s);
+  z.tol = tol;
+  z.max_iters = max_iters;
+  z.rel = 1.0;
+  z.prev_rel = 1.0;
+  if (!(z.bnorm > 0.0)) {  // b = 0: x = 0 is exact
+    z.done = 1;
+    z.converged = 1;
+  }
+  st[i] = z;
+}
+
+// Start of a restart cycle: beta = ||r||, convergence and stall tests.
+__global__ void k_cycle_start(InstState* st, const double* part, const int32_t* first, int n_inst,
+                              double* g, double* hist, int hist_cap, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  InstState z = st[i];
+  z.active = 0;
+  z.jend = 0;
+  if (z.done) {
+    st[i] = z;
+    return;
+  }
+  double s = 0.0;
+  for (int b = first[i]; b < first[i + 1]; ++b) s += part[b];
+  const double beta = sqrt(s);
+  const double rel = beta / z.bnorm;
+  if (z.nhist < hist_cap) hist[(int64_t)i * hist_cap + z.nhist++] = -rel;
+  z.prev_rel = z.cycles > 0 ? z.rel : 1.0;
+  z.rel = rel;
+  z.beta = beta;
+  z.stalled = 0;
+  if (rel <= z.tol) {
+    z.done = 1;
+    z.converged = 1;
+  } else if (!isfinite(rel)) {
+    z.stalled = 2;
+  } else {
+    const int used = z.mode ? z.fb_iters : z.iters;
+    if (used >= z.max_iters) z.stalled = 3;
+    else if (z.cycles > 0 && !(rel <= 0.9 * z.prev_rel)) z.stalled = 1;
+    z.active = 1;
+  }
+  g[(int64_t)i * (m + 1)] = beta;
+  z.cycles++;
+  st[i] = z;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BS) k_scale_to(const double* __restrict__ r, T* __restrict__ v,
+                                                 const int32_t* binst, const int64_t* bstart,
+                                                 const int64_t* bend, const InstState* st) {
+  const int b = blockIdx.x;
+  const InstState& z = st[binst[b]];
+  if (!z.active) return;
+  const double inv = 1.0 / z.beta;
+  for (int64_t e = bstart[b] + threadIdx.x; e < bend[b]; e += blockDim.x) v[e] = from_d<T>(r[e] * inv);
+}
+
+// ---------------------------------------------------------------- preconditioner
+
+__device__ __forceinline__ bool mode_ok(const InstState& z, int want_mode) {
+  return z.active && (want_mode < 0 || z.mode == want_mode);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BS) k_prec_copy(const T* __restrict__ v, T* __restrict__ z,
+                                                  const int32_t* binst, const int64_t* bstart,
+                                                  const int64_t* bend, const InstState* st) {
+  const int b = blockIdx.x;
+  if (st && !mode_ok(st[binst[b]], 0)) return;
+  for (int64_t e = bstart[b] + threadIdx.x; e < bend[b]; e += blockDim.x) z[e] = v[e];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BS) k_prec_jacobi(const T* __restrict__ v, T* __restrict__ z,
+                                                    const double* __restrict__ dinv, const int32_t* binst,
+                                                    const int64_t* bstart, const int64_t* bend,
+                                                    const InstState* st, int want_mode) {
+  const int b = blockIdx.x;
+  if (st && !mode_ok(st[binst[b]], want_mode)) return;
+  for (int64_t e = bstart[b] + threadIdx.x; e < bend[b]; e += blockDim.x)
+    z[e] = from_d<T>(to_d(v[e]) * dinv[e]);
+}
+
+// Exact 1D solve z1 = A11^-1 v1 of one instance per block: forward elimination
+// level by level from the leaves (each node gathers its children), diagonal
+// scaling, back substitution from the root.  Values live in LDS in FP64.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_tree_solve(const T* __restrict__ v, T* __restrict__ z,
+                                                   const int64_t* off, int n3d, const int32_t* t_off,
+                                                   const int32_t* lvloff, const int32_t* lvlptr,
+                                                   const int32_t* lvlnodes, const int32_t* parent,
+                                                   const int32_t* childptr, const int32_t* childidx,
+                                                   const double* lval, const double* tdinv,
+                                                   const InstState* st, int want_mode) {
+  extern __shared__ double ys[];
+  const int i = blockIdx.x;
+  if (st && !mode_ok(st[i], want_mode)) return;
+  const int nb = t_off[i];
+  const int n1d = t_off[i + 1] - nb;
+  const int64_t g0 = off[i] + n3d;
+  for (int c = threadIdx.x; c < n1d; c += blockDim.x) ys[c] = to_d(v[g0 + c]);
+  __syncthreads();
+  const int l0 = lvloff[i], nlev = lvloff[i + 1] - l0 - 1;
+  for (int L = 0; L < nlev; ++L) {
+    const int a = lvlptr[l0 + L], e = lvlptr[l0 + L + 1];
+    for (int k = a + threadIdx.x; k < e; k += blockDim.x) {
+      const int c = lvlnodes[nb + k];
+      double acc = ys[c];
+      const int cp0 = childptr[nb + i + c], cp1 = childptr[nb + i + c + 1];
+      for (int q = cp0; q < cp1; ++q) {
+        const int kid = childidx[q];
+        acc -= lval[nb + kid] * ys[kid];
+      }
+      ys[c] = acc;
+    }
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < n1d; c += blockDim.x) ys[c] *= tdinv[nb + c];
+  __syncthreads();
+  for (int L = nlev - 1; L >= 0; --L) {
+    const int a = lvlptr[l0 + L], e = lvlptr[l0 + L + 1];
+    for (int k = a + threadIdx.x; k < e; k += blockDim.x) {
+      const int c = lvlnodes[nb + k];
+      const int p = parent[nb + c];
+      if (p >= 0) ys[c] -= lval[nb + c] * ys[p];
+    }
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < n1d; c += blockDim.x) z[g0 + c] = from_d<T>(ys[c]);
+}
+
+// b0 = v0 - A01 z1 on the 3D rows (z1 already in z), partial sums of b0^2.
+template <typename T, typename Tm>
+__global__ void __launch_bounds__(BS) k_extension(const T* __restrict__ v, T* __restrict__ z,
+                                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                  const Tm* __restrict__ val, const int32_t* __restrict__ a01,
+                                                  const int64_t* off, int n3d, const int32_t* binst,
+                                                  const int64_t* bstart, const int64_t* bend,
+                                                  const InstState* st, int want_mode, double* part) {
+  __shared__ double sh[BS / 64];
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (st && !mode_ok(st[i], want_mode)) {
+    if (threadIdx.x == 0) part[b] = 0.0;
+    return;
+  }
+  const int64_t base = off[i];
+  double loc = 0.0;
+  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += blockDim.x) {
+    const int64_t g = base + r;
+    double acc = to_d(v[g]);
+    const int e = rp[g + 1];
+    for (int k = a01[(int64_t)i * n3d + r]; k < e; ++k) acc -= (double)val[k] * to_d(z[col[k]]);
+    const T stored = from_d<T>(acc);
+    z[g] = stored;
+    const double sv = to_d(stored);
+    loc += sv * sv;
+  }
+  double t = block_sum(loc, sh);
+  if (threadIdx.x == 0) part[b] = t;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BS) k_block_jacobi3d(T* __restrict__ z, const double* __restrict__ dinv,
+                                                       const int64_t* off, const int32_t* binst,
+                                                       const int64_t* bstart, const int64_t* bend,
+                                                       const InstState* st, int want_mode) {
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (st && !mode_ok(st[i], want_mode)) return;
+  const int64_t base = off[i];
+  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += blockDim.x)
+    z[base + r] = from_d<T>(to_d(z[base + r]) * dinv[base + r]);
+}
+
+__global__ void k_inv_scale(const double* part3, const int32_t* first, int n_inst, double* inv_s,
+                            InstState* st, int want_mode) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  if (st && !mode_ok(st[i], want_mode)) return;
+  double s = 0.0;
+  for (int b = first[i]; b < first[i + 1]; ++b) s += part3[b];
+  s = sqrt(s);
+  inv_s[i] = s > 0.0 ? 1.0 / s : 0.0;
+  inv_s[n_inst + i] = s;
+  if (st) st[i].scale3d = s;
+}
+
+// ---------------------------------------------------------------- Arnoldi (modified Gram-Schmidt)
+
+// Step k of the MGS sweep for the new vector w = V[j+1] (k = 0..j+1):
+//   k >= 1: h_{k-1,j} = <w, v_{k-1}> from the partials of step k-1; w -= h v_{k-1};
+//   k <= j: partials of <w, v_k>;   k = j+1: partials of <w, w>;
+//   k == 0: also partials of <w, w> before orthogonalisation (breakdown test).
+// Arithmetic in FP64; w is stored back in the vector type.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_mgs(T* __restrict__ V, int64_t ld, int j, int k,
+                                            const double* __restrict__ part_prev, double* __restrict__ part_cur,
+                                            double* __restrict__ part_w0, double* __restrict__ H, int m,
+                                            const int32_t* binst, const int64_t* bstart, const int64_t* bend,
+                                            const int32_t* first, const InstState* st) {
+  __shared__ double sh[BS / 64];
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (!st[i].active) return;
+  T* w = V + (int64_t)(j + 1) * ld;
+  double h = 0.0;
+  if (k >= 1) {
+    h = inst_sum(part_prev, first, i, sh);
+    if (b == first[i] && threadIdx.x == 0) H[((int64_t)i * (m + 1) + (k - 1)) * m + j] = h;
+  }
+  const T* vp = V + (int64_t)(k - 1) * ld;
+  const T* vk = V + (int64_t)k * ld;
+  double acc = 0.0, acc0 = 0.0;
+  for (int64_t e = bstart[b] + threadIdx.x; e < bend[b]; e += blockDim.x) {
+    double wv = to_d(w[e]);
+    if (k == 0) acc0 += wv * wv;
+    if (k >= 1) {
+      wv -= h * to_d(vp[e]);
+      const T ws = from_d<T>(wv);
+      w[e] = ws;
+      wv = to_d(ws);
+    }
+    if (k <= j) acc += wv * to_d(vk[e]);
+    else acc += wv * wv;
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part_cur[b] = t;
+  if (k == 0) {
+    double t0 = block_sum(acc0, sh);
+    if (threadIdx.x == 0) part_w0[b] = t0;
+  }
+}
+
+// End of Arnoldi step j: h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}; the first
+// block of each instance applies the previous Givens rotations to column j,
+// forms rotation j, updates g and the residual estimate rho = |g_{j+1}|, and
+// retires the instance on convergence, happy breakdown or the step cap.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_mgs_finish(T* __restrict__ V, int64_t ld, int j,
+                                                   const double* __restrict__ part_last,
+                                                   const double* __restrict__ part_w0, double* __restrict__ H,
+                                                   double* __restrict__ cs, double* __restrict__ sn,
+                                                   double* __restrict__ g, double* __restrict__ hist, int hist_cap,
+                                                   int m, const int32_t* binst, const int64_t* bstart,
+                                                   const int64_t* bend, const int32_t* first, InstState* st) {
+  __shared__ double sh[BS / 64];
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (!st[i].active) return;
+  const double hn = sqrt(inst_sum(part_last, first, i, sh));
+  const double w0 = sqrt(inst_sum(part_w0, first, i, sh));
+  T* w = V + (int64_t)(j + 1) * ld;
+  const double sc = hn > 0.0 ? 1.0 / hn : 0.0;
+  for (int64_t e = bstart[b] + threadIdx.x; e < bend[b]; e += blockDim.x) w[e] = from_d<T>(to_d(w[e]) * sc);
+  if (b != first[i] || threadIdx.x != 0) return;
+  double* Hc = H + (int64_t)i * (m + 1) * m;  // Hc[row * m + col]
+  double* c = cs + (int64_t)i * m;
+  double* s = sn + (int64_t)i * m;
+  double* gi = g + (int64_t)i * (m + 1);
+  Hc[(j + 1) * m + j] = hn;
+  for (int q = 0; q < j; ++q) {
+    const double a = Hc[q * m + j], bb = Hc[(q + 1) * m + j];
+    Hc[q * m + j] = c[q] * a + s[q] * bb;
+    Hc[(q + 1) * m + j] = -s[q] * a + c[q] * bb;
+  }
+  const double a = Hc[j * m + j], bb = hn;
+  const double den = hypot(a, bb);
+  const double cj = den == 0.0 ? 1.0 : a / den, sj = den == 0.0 ? 0.0 : bb / den;
+  c[j] = cj;
+  s[j] = sj;
+  Hc[j * m + j] = cj * a + sj * bb;
+  Hc[(j + 1) * m + j] = 0.0;
+  gi[j + 1] = -sj * gi[j];
+  gi[j] = cj * gi[j];
+  const double rho = fabs(gi[j + 1]);
+  InstState z = st[i];
+  if (z.mode) z.fb_iters++; else z.iters++;
+  z.jend = j + 1;
+  if (z.nhist < hist_cap) hist[(int64_t)i * hist_cap + z.nhist++] = rho / z.bnorm;
+  const int used = z.mode ? z.fb_iters : z.iters;
+  if (rho <= z.tol * z.bnorm || hn <= 1e-14 * w0 || used >= z.max_iters || !isfinite(rho)) z.active = 0;
+  st[i] = z;
+}
+
+// y = R^-1 g (upper triangular, FP64), one thread per instance.
+__global__ void k_solve_y(const double* H, const double* g, double* y, int m, int n_inst, const InstState* st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  const int je = st[i].jend;
+  const double* Hc = H + (int64_t)i * (m + 1) * m;
+  const double* gi = g + (int64_t)i * (m + 1);
+  double* yi = y + (int64_t)i * m;
+  for (int q = je - 1; q >= 0; --q) {
+    double acc = gi[q];
+    for (int p = q + 1; p < je; ++p) acc -= Hc[q * m + p] * yi[p];
+    const double d = Hc[q * m + q];
+    yi[q] = d != 0.0 ? acc / d : 0.0;
+  }
+}
+
+// x += Z y over the Arnoldi steps taken in this cycle.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_update_x(const T* __restrict__ Z, int64_t ld, const double* __restrict__ y,
+                                                 double* __restrict__ x, int m, const int32_t* binst,
+                                                 const int64_t* bstart, const int64_t* bend,
+                                                 const InstState* st) {
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  const int je = st[i].jend;
+  if (je == 0) return;
+  const double* yi = y + (int64_t)i * m;
+  for (int64_t e = bstart[b] + threadIdx.x; e < bend[b]; e += blockDim.x) {
+    double acc = x[e];
+    for (int q = 0; q < je; ++q) acc += yi[q] * to_d(Z[(int64_t)q * ld + e]);
+    x[e] = acc;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+#define BLK(s) (s)->blk.inst, (s)->blk.start, (s)->blk.end
+#define BLK3(s) (s)->blk3.inst, (s)->blk3.start, (s)->blk3.end
+
+template <typename T>
+void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, hipStream_t stream) {
+  if (sizeof(T) == 8)
+    hipLaunchKernelGGL((k_spmv<T, double, double, 8>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_rowptr,
+                       s->d_col, s->d_val64, x, y, BLK(s), st, mask ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_spmv<T, float, float, 8>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_rowptr,
+                       s->d_col, s->d_val32, x, y, BLK(s), st, mask ? 1 : 0);
+}
+template void launch_spmv<float>(mdnp_sys*, const float*, float*, const InstState*, bool, hipStream_t);
+template void launch_spmv<double>(mdnp_sys*, const double*, double*, const InstState*, bool, hipStream_t);
+
+void launch_spmv_a00_slots(mdnp_sys* s, const int32_t* inst, int n_slots, const float* x, float* y,
+                           hipStream_t stream) {
+  const int rows_per_block = (BS / 8) * 16;
+  dim3 grid((s->n3d + rows_per_block - 1) / rows_per_block, n_slots);
+  hipLaunchKernelGGL((k_spmv_a00<float, float, 8>), grid, dim3(BS), 0, stream, s->d_rowptr, s->d_col,
+                     s->d_val32, s->d_off, s->d_a01, inst, s->n3d, x, y);
+}
+
+template <typename T>
+void launch_spmv_a00_all(mdnp_sys* s, const T* x, T* y, hipStream_t stream) {
+  const int rows_per_block = (BS / 8) * 16;
+  dim3 grid((s->n3d + rows_per_block - 1) / rows_per_block, s->n_inst);
+  if (sizeof(T) == 8)
+    hipLaunchKernelGGL((k_spmv_a00<T, double, 8>), grid, dim3(BS), 0, stream, s->d_rowptr, s->d_col, s->d_val64,
+                       s->d_off, s->d_a01, (const int32_t*)nullptr, s->n3d, x, y);
+  else
+    hipLaunchKernelGGL((k_spmv_a00<T, float, 8>), grid, dim3(BS), 0, stream, s->d_rowptr, s->d_col, s->d_val32,
+                       s->d_off, s->d_a01, (const int32_t*)nullptr, s->n3d, x, y);
+}
+template void launch_spmv_a00_all<float>(mdnp_sys*, const float*, float*, hipStream_t);
+template void launch_spmv_a00_all<double>(mdnp_sys*, const double*, double*, hipStream_t);
+
+void launch_residual(mdnp_sys* s, const double* b, const double* x, double* r, double* part,
+                     const InstState* st, hipStream_t stream) {
+  hipLaunchKernelGGL((k_residual<8>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_rowptr, s->d_col, s->d_val64,
+                     x, b, r, BLK(s), st, part);
+}
+
+void launch_norm2_partials(mdnp_sys* s, const double* x, double* part, hipStream_t stream) {
+  hipLaunchKernelGGL(k_norm2_part, dim3(s->blk.nblk), dim3(BS), 0, stream, x, s->blk.start, s->blk.end, part);
+}
+
+void launch_init_state(mdnp_sys* s, InstState* st, const double* part, double tol, int max_iters,
+                       hipStream_t stream) {
+  hipLaunchKernelGGL(k_init_state, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, st, part, s->blk.first,
+                     s->n_inst, tol, max_iters);
+}
+
+void launch_cycle_start(mdnp_sys* s, InstState* st, const double* part, double* g, double* hist, int hist_cap,
+                        int m, hipStream_t stream) {
+  hipLaunchKernelGGL(k_cycle_start, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, st, part, s->blk.first,
+                     s->n_inst, g, hist, hist_cap, m);
+}
+
+template <typename T>
+void launch_scale_to(mdnp_sys* s, const double* r, T* v0, const InstState* st, hipStream_t stream) {
+  hipLaunchKernelGGL((k_scale_to<T>), dim3(s->blk.nblk), dim3(BS), 0, stream, r, v0, BLK(s), st);
+}
+template void launch_scale_to<float>(mdnp_sys*, const double*, float*, const InstState*, hipStream_t);
+template void launch_scale_to<double>(mdnp_sys*, const double*, double*, const InstState*, hipStream_t);
+
+template <typename T>
+void launch_prec_copy(mdnp_sys* s, const T* v, T* z, const InstState* st, hipStream_t stream) {
+  hipLaunchKernelGGL((k_prec_copy<T>), dim3(s->blk.nblk), dim3(BS), 0, stream, v, z, BLK(s), st);
+}
+template void launch_prec_copy<float>(mdnp_sys*, const float*, float*, const InstState*, hipStream_t);
+template void launch_prec_copy<double>(mdnp_sys*, const double*, double*, const InstState*, hipStream_t);
+
+template <typename T>
+void launch_prec_jacobi(mdnp_sys* s, const T* v, T* z, const InstState* st, int want_mode, hipStream_t stream) {
+  hipLaunchKernelGGL((k_prec_jacobi<T>), dim3(s->blk.nblk), dim3(BS), 0, stream, v, z, s->d_dinv, BLK(s), st,
+                     want_mode);
+}
+template void launch_prec_jacobi<float>(mdnp_sys*, const float*, float*, const InstState*, int, hipStream_t);
+template void launch_prec_jacobi<double>(mdnp_sys*, const double*, double*, const InstState*, int, hipStream_t);
+
+void tree_solve_setup(size_t shm_bytes) {
+  if (shm_bytes > 65536) {
+    hipFuncSetAttribute((const void*)k_tree_solve<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_bytes);
+    hipFuncSetAttribute((const void*)k_tree_solve<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_bytes);
+  }
+}
+
+template <typename T>
+void launch_tree_solve(mdnp_sys* s, const T* v, T* z, const InstState* st, int want_mode, hipStream_t stream) {
+  const size_t shm = sizeof(double) * (size_t)s->max_n1d;
+  hipLaunchKernelGGL((k_tree_solve<T>), dim3(s->n_inst), dim3(BS), shm, stream, v, z, s->d_off, s->n3d,
+                     s->d_t_off, s->d_t_lvloff, s->d_t_lvlptr, s->d_t_lvlnodes, s->d_t_parent, s->d_t_childptr,
+                     s->d_t_childidx, s->d_t_lval, s->d_t_dinv, st, want_mode);
+}
+template void launch_tree_solve<float>(mdnp_sys*, const float*, float*, const InstState*, int, hipStream_t);
+template void launch_tree_solve<double>(mdnp_sys*, const double*, double*, const InstState*, int, hipStream_t);
+
+template <typename T>
+void launch_extension(mdnp_sys* s, const T* v, T* z, double* part3, const InstState* st, int want_mode,
+                      hipStream_t stream) {
+  if (sizeof(T) == 8)
+    hipLaunchKernelGGL((k_extension<T, double>), dim3(s->blk3.nblk), dim3(BS), 0, stream, v, z, s->d_rowptr,
+                       s->d_col, s->d_val64, s->d_a01, s->d_off, s->n3d, BLK3(s), st, want_mode, part3);
+  else
+    hipLaunchKernelGGL((k_extension<T, float>), dim3(s->blk3.nblk), dim3(BS), 0, stream, v, z, s->d_rowptr,
+                       s->d_col, s->d_val32, s->d_a01, s->d_off, s->n3d, BLK3(s), st, want_mode, part3);
+}
+template void launch_extension<float>(mdnp_sys*, const float*, float*, double*, const InstState*, int, hipStream_t);
+template void launch_extension<double>(mdnp_sys*, const double*, double*, double*, const InstState*, int,
+                                       hipStream_t);
+
+template <typename T>
+void launch_block_jacobi3d(mdnp_sys* s, T* z, const InstState* st, int want_mode, hipStream_t stream) {
+  hipLaunchKernelGGL((k_block_jacobi3d<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, s->d_dinv, s->d_off,
+                     BLK3(s), st, want_mode);
+}
+template void launch_block_jacobi3d<float>(mdnp_sys*, float*, const InstState*, int, hipStream_t);
+template void launch_block_jacobi3d<double>(mdnp_sys*, double*, const InstState*, int, hipStream_t);
+
+void launch_inv_scale(mdnp_sys* s, const double* part3, double* inv_s, InstState* st, int want_mode,
+                      hipStream_t stream) {
+  hipLaunchKernelGGL(k_inv_scale, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, part3, s->blk3.first,
+                     s->n_inst, inv_s, st, want_mode);
+}
+
+template <typename T>
+void launch_mgs(mdnp_sys* s, T* V, int j, int k, const double* part_prev, double* part_cur, double* part_w0,
+                double* H, int m, const InstState* st, hipStream_t stream) {
+  hipLaunchKernelGGL((k_mgs<T>), dim3(s->blk.nblk), dim3(BS), 0, stream, V, (int64_t)s->ntot, j, k, part_prev,
+                     part_cur, part_w0, H, m, BLK(s), s->blk.first, st);
+}
+template void launch_mgs<float>(mdnp_sys*, float*, int, int, const double*, double*, double*, double*, int,
+                                const InstState*, hipStream_t);
+template void launch_mgs<double>(mdnp_sys*, double*, int, int, const double*, double*, double*, double*, int,
+                                 const InstState*, hipStream_t);
+
+template <typename T>
+void launch_mgs_finish(mdnp_sys* s, T* V, int j, const double* part_last, const double* part_w0, double* H,
+                       double* cs, double* sn, double* g, double* hist, int hist_cap, int m, InstState* st,
+                       hipStream_t stream) {
+  hipLaunchKernelGGL((k_mgs_finish<T>), dim3(s->blk.nblk), dim3(BS), 0, stream, V, (int64_t)s->ntot, j, part_last,
+                     part_w0, H, cs, sn, g, hist, hist_cap, m, BLK(s), s->blk.first, st);
+}
+template void launch_mgs_finish<float>(mdnp_sys*, float*, int, const double*, const double*, double*, double*,
+                                       double*, double*, double*, int, int, InstState*, hipStream_t);
+template void launch_mgs_finish<double>(mdnp_sys*, double*, int, const double*, const double*, double*, double*,
+                                        double*, double*, double*, int, int, InstState*, hipStream_t);
+
+void launch_solve_y(mdnp_sys* s, const double* H, const double* g, double* y, int m, const InstState* st,
+                    hipStream_t stream) {
+  hipLaunchKernelGGL(k_solve_y, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, H, g, y, m, s->n_inst, st);
+}
+
+template <typename T>
+void launch_update_x(mdnp_sys* s, const T* Z, const double* y, double* x, int m, const InstState* st,
+                     hipStream_t stream) {
+  hipLaunchKernelGGL((k_update_x<T>), dim3(s->blk.nblk), dim3(BS), 0, stream, Z, (int64_t)s->ntot, y, x, m,
+                     BLK(s), st);
+}
+template void launch_update_x<float>(mdnp_sys*, const float*, const double*, double*, int, const InstState*,
+                                     hipStream_t);
+template void launch_update_x<double>(mdnp_sys*, const double*, const double*, double*, int, const InstState*,
+                                      hipStream_t);
+
+}  // namespace mdnp

@@ -1,0 +1,316 @@
+"""GPU parity of every step of the path against the FP64 oracle (called through the C ABI).
+
+Sizes are small enough for the oracle (seconds) but span several reduction
+chunks and ragged instance sizes.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+import synth
+from oracle import cnn as ocnn
+from oracle import fem, krylov
+
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    import paper_2505_08491_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    P = _P()
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def ragged_instances():
+    return [synth.make_instance(500 + i, 12, n_segments=s, elems_per_segment=3, radius=0.01, beta=1.0)
+            for i, s in enumerate((4, 11, 7))]
+
+
+def oracle_block(systems):
+    A = sp.block_diag([s.A for s in systems]).tocsr()
+    F = np.concatenate([s.F for s in systems])
+    return A, F
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+# ---------------------------------------------------------------- SpMV (rows a1, a6)
+
+@pytest.mark.parametrize("vec", ["f64", "f32"])
+def test_spmv_matches_oracle(ctx, vec):
+    P = _P()
+    insts = ragged_instances()
+    S = P.System(ctx, insts, vec_dtype=vec)
+    A, _ = oracle_block([fem.assemble(i) for i in insts])
+    x = synth.fast_normal(1, A.shape[0])
+    td = torch.float64 if vec == "f64" else torch.float32
+    y = S.spmv(dev(x, td)).cpu().double().numpy()
+    ref = A @ (x if vec == "f64" else x.astype(np.float32).astype(np.float64))
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    assert err <= (1e-14 if vec == "f64" else 1e-6), err
+    # exported CSR is the uploaded one
+    for i, inst in enumerate(insts):
+        rp, col, val = S.export_csr(i)
+        o = fem.assemble(inst)
+        assert np.array_equal(rp, o.A.indptr) and np.array_equal(col, o.A.indices)
+
+
+def test_spmv_a00_block(ctx):
+    P = _P()
+    insts = ragged_instances()
+    S = P.System(ctx, insts, vec_dtype="f64")
+    sy = [fem.assemble(i) for i in insts]
+    x = synth.fast_normal(2, S.n3d * len(insts))
+    y = S.spmv(dev(x, torch.float64), block=1).cpu().numpy()
+    for k, s in enumerate(sy):
+        A00 = s.blocks()[0]
+        ref = A00 @ x[k * S.n3d:(k + 1) * S.n3d]
+        assert np.linalg.norm(y[k * S.n3d:(k + 1) * S.n3d] - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------- 1D solve and extension (rows a2, a3)
+
+@pytest.mark.parametrize("vec", ["f64", "f32"])
+def test_tree_solve_matches_oracle(ctx, vec):
+    P = _P()
+    insts = ragged_instances() + [synth.workload_transfer(16, 1)[0]] if False else ragged_instances()
+    S = P.System(ctx, insts, vec_dtype=vec)
+    sy = [fem.assemble(i) for i in insts]
+    v = synth.fast_normal(3, S.ntot)
+    td = torch.float64 if vec == "f64" else torch.float32
+    z = S.tree_solve(dev(v, td)).cpu().double().numpy()
+    for k, s in enumerate(sy):
+        o = S.offsets[k] + s.n3d
+        v1 = v[o:o + s.n1d] if vec == "f64" else v[o:o + s.n1d].astype(np.float32).astype(np.float64)
+        ref = krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s)).solve_1d(v1)
+        err = np.linalg.norm(z[o:o + s.n1d] - ref) / np.linalg.norm(ref)
+        assert err <= (1e-12 if vec == "f64" else 1e-5), err
+
+
+def test_tree_solve_large_tree(ctx):
+    """8,193-node tree of 512 segments x 16 elements (needs > 64 KB of LDS)."""
+    P = _P()
+    inst = synth.workload_transfer(16, 1)[0]   # 16^3 cells keep the oracle fast
+    S = P.System(ctx, [inst], vec_dtype="f64")
+    s = fem.assemble(inst)
+    v = synth.fast_normal(4, S.ntot)
+    z = S.tree_solve(dev(v, torch.float64)).cpu().numpy()
+    ref = krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s)).solve_1d(v[s.n3d:])
+    assert np.linalg.norm(z[s.n3d:] - ref) / np.linalg.norm(ref) <= 1e-12
+
+
+def test_block_jacobi_preconditioner(ctx):
+    """Q(v) with the Jacobi stand-in for the 3D block (the method without the network)."""
+    P = _P()
+    insts = ragged_instances()
+    S = P.System(ctx, insts, vec_dtype="f64")
+    S.set_preconditioner("block_jacobi")
+    sy = [fem.assemble(i) for i in insts]
+    v = synth.fast_normal(5, S.ntot)
+    z = S.precond_apply(dev(v, torch.float64)).cpu().numpy()
+    for k, s in enumerate(sy):
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        ref = krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s))(v[o0:o1])
+        assert np.linalg.norm(z[o0:o1] - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------- network (row a4, a5)
+
+def _theta(seed=0, bias=0.05):
+    th = ocnn.init_params(seed)
+    off = 0
+    rng = np.random.default_rng(seed)
+    for a, b in ocnn.layer_sizes():
+        th[off + a:off + a + b] = rng.uniform(-bias, bias, b)
+        off += a + b
+    return th
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 4e-2)])
+def test_cnn_forward_matches_oracle(ctx, dtype, tol):
+    n, batch = 17, 2
+    th = _theta(1)
+    rng = np.random.default_rng(7)
+    X = np.stack([rng.normal(size=(n, n, n)) / n ** 1.5, rng.uniform(0, 0.5, (n, n, n))], axis=-1)
+    X = np.stack([X, X[::-1].copy()])
+    w = dev(th, torch.float32)
+    y = ctx.cnn_forward(w, dev(X.reshape(batch, -1, 2), torch.float32), n, dtype).cpu().double().numpy()
+    for k in range(batch):
+        ref = ocnn.forward(th.astype(np.float32).astype(np.float64), X[k].astype(np.float32).astype(np.float64))[0]
+        err = np.linalg.norm(y[k] - ref.ravel()) / np.linalg.norm(ref)
+        assert err <= tol, (k, err)
+
+
+def test_cnn_backward_matches_oracle(ctx):
+    n, batch = 9, 2
+    th = _theta(2)
+    rng = np.random.default_rng(8)
+    X = np.stack([np.stack([rng.normal(size=(n, n, n)) / 27.0, rng.uniform(0, 0.5, (n, n, n))], axis=-1)
+                  for _ in range(batch)])
+    G = rng.normal(size=(batch, n, n, n))
+    w = dev(th, torch.float32)
+    saved = torch.empty(ctx.saved_bytes(batch, n, "f32"), dtype=torch.uint8, device="cuda")
+    ctx.cnn_forward(w, dev(X.reshape(batch, -1, 2), torch.float32), n, "f32", saved=saved)
+    dw, dx = ctx.cnn_backward(w, saved, dev(G.reshape(batch, -1), torch.float32), batch, n, "f32", want_dx=True)
+    gref = np.zeros(ocnn.n_params())
+    dxref = []
+    th64 = th.astype(np.float32).astype(np.float64)
+    for k in range(batch):
+        _, cache = ocnn.forward(th64, X[k].astype(np.float32).astype(np.float64))
+        g, dX = ocnn.backward(th64, cache, G[k].astype(np.float32).astype(np.float64))
+        gref += g
+        dxref.append(dX)
+    dw = dw.cpu().double().numpy()
+    assert np.linalg.norm(dw - gref) / np.linalg.norm(gref) <= 1e-4
+    dx = dx.cpu().double().numpy().reshape(batch, n, n, n, 2)
+    dxref = np.stack(dxref)
+    assert np.linalg.norm(dx - dxref) / np.linalg.norm(dxref) <= 1e-4
+
+
+@pytest.mark.parametrize("vec,cnn_dtype,tol", [("f64", "f32", 2e-5), ("f32", "f32", 2e-5), ("f32", "bf16", 5e-2)])
+def test_neural_block_preconditioner(ctx, vec, cnn_dtype, tol):
+    """Q(v) = [P3D(v0 - A01 A11^-1 v1); A11^-1 v1] with the network 3D block."""
+    P = _P()
+    insts = [synth.make_instance(900 + i, 16, n_segments=s, elems_per_segment=3, radius=0.01, beta=1.0)
+             for i, s in enumerate((5, 9))]
+    S = P.System(ctx, insts, vec_dtype=vec)
+    th = _theta(3)
+    S.set_preconditioner("neural", weights=th.astype(np.float32), cnn_dtype=cnn_dtype)
+    th64 = th.astype(np.float32).astype(np.float64)
+    net = lambda X: ocnn.forward(th64, X)[0]
+    v = synth.fast_normal(6, S.ntot)
+    td = torch.float64 if vec == "f64" else torch.float32
+    z = S.precond_apply(dev(v, td)).cpu().double().numpy()
+    for k, inst in enumerate(insts):
+        s = fem.assemble(inst)
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        vk = v[o0:o1] if vec == "f64" else v[o0:o1].astype(np.float32).astype(np.float64)
+        ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(vk)
+        err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
+        assert err <= tol, (k, err)
+
+
+# ---------------------------------------------------------------- solves (rows a1, a6-a9, a11)
+
+def test_jacobi_gmres_fp64_matches_oracle(ctx):
+    """P8-P10 on the 16^3 single-instance case: equal iteration count, every
+    history entry, and the solution after exactly k* steps within 1e-8."""
+    P = _P()
+    inst = synth.workload_single_fp64()[0]
+    s = fem.assemble(inst)
+    ref = krylov.fgmres(s.A, s.F, precond=krylov.jacobi(s.A), restart=50, tol=1e-8, max_iters=100000)
+    S = P.System(ctx, [inst], vec_dtype="f64")
+    S.set_preconditioner("jacobi")
+    x, st = S.solve(s.F, restart=50, max_iters=100000, tol=1e-8)
+    assert st[0]["converged"]
+    assert abs(st[0]["iters"] - ref.iters) <= 1
+    rel = np.linalg.norm(s.F - s.A @ x) / np.linalg.norm(s.F)
+    assert rel <= 1e-8
+    # exact-count comparison
+    k = min(st[0]["iters"], ref.iters)
+    ref_k = krylov.fgmres(s.A, s.F, precond=krylov.jacobi(s.A), restart=50, tol=1e-30, max_iters=k)
+    xk, _ = S.solve(s.F, restart=50, max_iters=k, tol=1e-30)
+    assert np.linalg.norm(xk - ref_k.x) / np.linalg.norm(ref_k.x) <= 1e-8
+    h = S.history(0)
+    steps = h[h >= 0]
+    assert np.allclose(steps[:len(ref_k.history)], ref_k.history, rtol=1e-6)
+    xd = krylov.direct_solve(s)
+    print("jacobi fp64: iters", st[0]["iters"], "oracle", ref.iters, "err vs direct",
+          np.linalg.norm(x - xd) / np.linalg.norm(xd))
+
+
+def varied_instances():
+    return [synth.make_instance(600 + i, 12, n_segments=s, elems_per_segment=e, radius=r, beta=bt)
+            for i, (s, e, r, bt) in enumerate(((4, 3, 0.004, 0.5), (11, 5, 0.012, 2.0), (7, 2, 0.02, 1.0)))]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_masked_solve(ctx, graph):
+    """Ragged batch, FP32 vectors: every instance reaches the tolerance with its own
+    iteration count (within 2 of the FP64 oracle's count for the same
+    preconditioner); solution error vs the direct solve <= 1e-6."""
+    P = _P()
+    insts = varied_instances()
+    S = P.System(ctx, insts, vec_dtype="f32")
+    S.set_preconditioner("block_jacobi")
+    b = S.rhs()
+    x, st = S.solve(b, restart=20, max_iters=5000, tol=1e-8, use_graph=graph)
+    iters = []
+    for k, inst in enumerate(insts):
+        s = fem.assemble(inst)
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        rel = np.linalg.norm(s.F - s.A @ x[o0:o1]) / np.linalg.norm(s.F)
+        assert st[k]["converged"] and rel <= 1e-8, (k, st[k], rel)
+        xd = krylov.direct_solve(s)
+        assert np.linalg.norm(x[o0:o1] - xd) / np.linalg.norm(xd) <= 1e-6
+        ref = krylov.fgmres(s.A, s.F, precond=krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s)), restart=20,
+                            tol=1e-8, max_iters=5000)
+        assert abs(st[k]["iters"] - ref.iters) <= 2, (k, st[k]["iters"], ref.iters)
+        iters.append(st[k]["iters"])
+    print("batched block-Jacobi iterations", iters)
+
+
+def test_graph_replay_matches_eager(ctx):
+    P = _P()
+    insts = ragged_instances()
+    S = P.System(ctx, insts, vec_dtype="f64")
+    S.set_preconditioner("jacobi")
+    b = S.rhs()
+    xa, sa = S.solve(b, restart=15, max_iters=3000, tol=1e-9, use_graph=False)
+    xb, sb = S.solve(b, restart=15, max_iters=3000, tol=1e-9, use_graph=True)
+    assert [a["iters"] for a in sa] == [q["iters"] for q in sb]
+    assert np.array_equal(xa, xb)
+
+
+def test_neural_fgmres_solve(ctx):
+    P = _P()
+    inst = synth.make_instance(42, 16, n_segments=12, elems_per_segment=4, radius=0.008, beta=1.0)
+    s = fem.assemble(inst)
+    S = P.System(ctx, [inst], vec_dtype="f32")
+    S.set_preconditioner("neural", weights=ocnn.init_params(0).astype(np.float32), cnn_dtype="f32")
+    x, st = S.solve(s.F, restart=30, max_iters=3000, tol=1e-8, fallback_max_iters=5000)
+    rel = np.linalg.norm(s.F - s.A @ x) / np.linalg.norm(s.F)
+    assert st[0]["converged"] and rel <= 1e-8, (st, rel)
+    xd = krylov.direct_solve(s)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 1e-6
+
+
+# ---------------------------------------------------------------- training objective (row a10)
+
+def test_loss_grad_matches_oracle(ctx):
+    P = _P()
+    insts = [synth.make_instance(700 + i, 8, n_segments=6, elems_per_segment=3, radius=0.01, beta=1.0)
+             for i in range(3)]
+    S = P.System(ctx, insts, vec_dtype="f32")
+    sy = [fem.assemble(i) for i in insts]
+    slots = np.array([2, 0, 2, 1], dtype=np.int32)
+    n3d = S.n3d
+    rng = np.random.default_rng(1)
+    r = np.zeros((len(slots), n3d))
+    u = rng.normal(size=(len(slots), n3d))
+    for k, i in enumerate(slots):
+        r[k] = synth.fast_normal(10 + k, n3d)
+        r[k, sy[i].boundary] = 0
+        r[k] /= np.linalg.norm(r[k])
+    loss, du = S.loss_grad(dev(slots, torch.int32), dev(r, torch.float32), dev(u, torch.float32))
+    loss = loss.cpu().numpy()
+    du = du.cpu().double().numpy()
+    for k, i in enumerate(slots):
+        s = sy[i]
+        A00 = s.blocks()[0]
+        um = u[k].astype(np.float32).astype(np.float64).copy()
+        um[s.boundary] = 0
+        e = r[k].astype(np.float32) - (A00 @ um) / s.alpha
+        assert loss[k] == pytest.approx(float(e @ e), rel=1e-5)
+        g = -2 * (A00 @ e) / s.alpha
+        g[s.boundary] = 0
+        assert np.linalg.norm(du[k] - g) <= 1e-5 * np.linalg.norm(g)
