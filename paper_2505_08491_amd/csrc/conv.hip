@@ -8,6 +8,7 @@
 // every network, for the backward pass, the loss and Adam.  The matrix-core
 // kernels of the BF16 network live in conv_mfma.hip.
 #include <cmath>
+#include <type_traits>
 
 #include "conv_common.hpp"
 #include "kernels.hpp"
