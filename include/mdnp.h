@@ -126,6 +126,13 @@ mdnp_status mdnp_sys_free(mdnp_ctx* ctx, mdnp_sys* sys);
 mdnp_status mdnp_sys_sizes(const mdnp_sys* sys, int32_t inst, int32_t* n3d, int32_t* n1d,
                            int64_t* nnz, int64_t* offset);
 
+/* Sizes of the split operator of instance `inst` on the device, A = S + M
+ * (Section 2.1: S the trilinear stiffness/mass stencil of the free 3D nodes,
+ * identical at every interior node; M the coupling terms of Eq. (2.3)-(2.5)
+ * and the 1D rows): entries stored for M and rows of M that hold any entry
+ * (3D rows touched by the coupling plus every 1D row). */
+mdnp_status mdnp_sys_split_sizes(const mdnp_sys* sys, int32_t inst, int64_t* m_nnz, int64_t* m_rows);
+
 /* Host copy of the assembled matrix of one instance in CSR with local indices
  * (row_ptr [n+1], col [nnz], val [nnz], n = n3d + n1d): columns ascending,
  * duplicates merged, zero values kept where the pattern has them, Dirichlet

@@ -50,6 +50,7 @@ SIGNATURES = [
     ("mdnp_upload", C.c_int, [VP, P(InstanceDesc), C.c_int32, C.c_int, P(VP)]),
     ("mdnp_sys_free", C.c_int, [VP, VP]),
     ("mdnp_sys_sizes", C.c_int, [VP, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_int64), P(C.c_int64)]),
+    ("mdnp_sys_split_sizes", C.c_int, [VP, C.c_int32, P(C.c_int64), P(C.c_int64)]),
     ("mdnp_export_csr", C.c_int, [VP, C.c_int32, VP, VP, VP]),
     ("mdnp_export_rhs", C.c_int, [VP, C.c_int32, VP, VP, P(C.c_double)]),
     ("mdnp_set_preconditioner", C.c_int, [VP, VP, C.c_int, VP, C.c_int64, C.c_double, C.c_int]),

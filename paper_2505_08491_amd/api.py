@@ -201,6 +201,12 @@ class System:
         self.ctx._check(lib.mdnp_sys_sizes(self.h, i, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
         return a.value, b.value, c.value, d.value
 
+    def split_sizes(self, i):
+        """(entries, non-empty rows) of the coupling part M of A = S + M."""
+        a, b = C.c_int64(), C.c_int64()
+        self.ctx._check(lib.mdnp_sys_split_sizes(self.h, i, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def free(self):
         if getattr(self, "h", None) is not None and self.ctx.h is not None:
             lib.mdnp_sys_free(self.ctx.h, self.h)

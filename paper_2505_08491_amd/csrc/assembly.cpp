@@ -249,12 +249,32 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
   H.val.reserve((size_t)n3d * 27 + rowt.size());
   H.a01_start.assign(n3d, 0);
   H.diag.assign(nt, 0.0);
+  for (int q = 0; q < 4; ++q) H.stencil[q] = kst[q] + mst[q];
+  H.m_ptr.assign((size_t)nt + 1, 0);
+  H.m_col.clear();
+  H.m_val.clear();
+  H.m_a01.assign(n3d, 0);
   std::vector<std::pair<int32_t, double>> merged;
   for (int r = 0; r < nt; ++r) {
     auto b0 = rowt.begin() + tptr[r], b1 = rowt.begin() + tptr[r + 1];
     std::sort(b0, b1, [](const std::pair<int32_t, double>& u, const std::pair<int32_t, double>& v) {
       return u.first < v.first;
     });
+    // coupling / 1D part of the row on its own (duplicates merged)
+    bool m01 = false;
+    for (auto it = b0; it != b1;) {
+      const int32_t cc = it->first;
+      double acc = 0.0;
+      while (it != b1 && it->first == cc) acc += (it++)->second;
+      if (r < n3d && !m01 && cc >= n3d) {
+        H.m_a01[r] = (int32_t)H.m_col.size();
+        m01 = true;
+      }
+      H.m_col.push_back(cc);
+      H.m_val.push_back(acc);
+    }
+    if (r < n3d && !m01) H.m_a01[r] = (int32_t)H.m_col.size();
+    H.m_ptr[r + 1] = (int32_t)H.m_col.size();
     merged.clear();
     if (r < n3d && is_bnd(r)) {
       merged.push_back({r, 1.0});

@@ -26,6 +26,13 @@ struct HostInstance {
   std::vector<int32_t> row_ptr, col;   // CSR of A, local indices, sorted columns
   std::vector<double> val;
   std::vector<int32_t> a01_start;      // per 3D row: first entry with a 1D column
+  // Split form used by the device: A = S + M with S the constant 27-point
+  // stencil on the free 3D nodes (identity on Dirichlet nodes) and M the
+  // coupling entries of the 3D rows plus the whole 1D rows (CSR, sorted).
+  double stencil[4] = {0, 0, 0, 0};    // stencil value by number of differing coordinates
+  std::vector<int32_t> m_ptr, m_col;
+  std::vector<double> m_val;
+  std::vector<int32_t> m_a01;          // per 3D row: first M entry with a 1D column
   std::vector<double> F;               // right-hand side [n3d + n1d]
   std::vector<float> dist;             // distance field at the 3D nodes
   std::vector<double> diag;            // diag(A)

@@ -119,18 +119,42 @@ void free_work(SolveWork& w) {
 }
 
 void free_sys(mdnp_sys* s) {
-  void* ptrs[] = {s->d_off, s->d_rowptr, s->d_col, s->d_val64, s->d_val32, s->d_a01, s->d_dinv, s->d_dist,
+  void* ptrs[] = {s->d_off, s->d_stencil, s->d_mptr, s->d_mcol, s->d_mval64, s->d_mval32, s->d_ma01, s->d_mrows,
+                  s->d_dinv, s->d_dist,
                   s->d_alpha, s->d_t_off, s->d_t_lvloff, s->d_t_lvlptr, s->d_t_lvlnodes, s->d_t_parent,
                   s->d_t_childptr, s->d_t_childidx, s->d_t_lval, s->d_t_dinv};
   for (void* p : ptrs) dfree(p);
   free_blocks(s->blk);
   free_blocks(s->blk3);
+  free_blocks(s->mblk);
+  free_blocks(s->mblk3);
   free_work(s->work);
   cnn_release(s->cnn);
   delete s;
 }
 
 size_t vsize(mdnp_dtype d) { return d == MDNP_F64 ? 8 : 4; }
+
+// Partial-sum areas: ping-pong A/B and w0 over the whole-vector blocks, the
+// 3D-part blocks, and the coupling-row blocks (all rows, 3D rows).
+struct Parts {
+  double *pA, *pB, *pW, *p3, *pM, *pM3;
+};
+
+size_t parts_size(const mdnp_sys* s) {
+  return 3 * (size_t)s->blk.nblk + (size_t)s->blk3.nblk + (size_t)s->mblk.nblk + (size_t)s->mblk3.nblk;
+}
+
+Parts parts(const mdnp_sys* s, double* base) {
+  Parts p;
+  p.pA = base;
+  p.pB = p.pA + s->blk.nblk;
+  p.pW = p.pB + s->blk.nblk;
+  p.p3 = p.pW + s->blk.nblk;
+  p.pM = p.p3 + s->blk3.nblk;
+  p.pM3 = p.pM + s->mblk.nblk;
+  return p;
+}
 
 }  // namespace
 
@@ -316,34 +340,58 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
     if (s->ntot >= INT32_MAX || s->nnz_tot >= INT32_MAX) fail(MDNP_E_ARG, "system too large for 32-bit indices");
     if ((size_t)s->max_n1d * 8 > 160 * 1024) fail(MDNP_E_ARG, "1D block too large for the on-chip tree solve");
     hipStream_t stream = ctx->stream;
-    // concatenated CSR with global indices
-    std::vector<int32_t> rp(s->ntot + 1), col(s->nnz_tot), a01((size_t)n_inst * s->n3d);
-    std::vector<double> v64(s->nnz_tot), dinv(s->ntot), alpha(n_inst);
-    std::vector<float> v32(s->nnz_tot), dist((size_t)n_inst * s->n3d);
+    // concatenated operator in split form (stencil + coupling CSR), global indices
+    s->mnz_tot = 0;
+    for (int i = 0; i < n_inst; ++i) s->mnz_tot += (int64_t)s->host[i].m_col.size();
+    if (s->mnz_tot >= INT32_MAX) fail(MDNP_E_ARG, "coupling block too large for 32-bit indices");
+    std::vector<int32_t> mp(s->ntot + 1), mc(s->mnz_tot), ma01((size_t)n_inst * s->n3d);
+    std::vector<double> mv64(s->mnz_tot), dinv(s->ntot), alpha(n_inst), stn((size_t)n_inst * 4);
+    std::vector<float> mv32(s->mnz_tot), dist((size_t)n_inst * s->n3d);
+    int64_t mo = 0;
     for (int i = 0; i < n_inst; ++i) {
       const HostInstance& h = s->host[i];
-      const int64_t o = s->off[i], no = s->nnz_off[i];
+      const int64_t o = s->off[i];
       const int nr = h.n3d + h.n1d;
-      for (int r = 0; r <= nr; ++r) rp[o + r] = (int32_t)(no + h.row_ptr[r]);
-      for (size_t k = 0; k < h.col.size(); ++k) {
-        col[no + k] = (int32_t)(o + h.col[k]);
-        v64[no + k] = h.val[k];
-        v32[no + k] = (float)h.val[k];
+      for (int r = 0; r <= nr; ++r) mp[o + r] = (int32_t)(mo + h.m_ptr[r]);
+      for (size_t k = 0; k < h.m_col.size(); ++k) {
+        mc[mo + k] = (int32_t)(o + h.m_col[k]);
+        mv64[mo + k] = h.m_val[k];
+        mv32[mo + k] = (float)h.m_val[k];
       }
-      for (int r = 0; r < h.n3d; ++r) a01[(size_t)i * s->n3d + r] = (int32_t)(no + h.a01_start[r]);
+      for (int r = 0; r < h.n3d; ++r) ma01[(size_t)i * s->n3d + r] = (int32_t)(mo + h.m_a01[r]);
+      mo += (int64_t)h.m_col.size();
       for (int r = 0; r < nr; ++r) dinv[o + r] = 1.0 / h.diag[r];
       std::memcpy(&dist[(size_t)i * s->n3d], h.dist.data(), sizeof(float) * h.n3d);
       alpha[i] = h.alpha;
+      for (int q = 0; q < 4; ++q) stn[(size_t)i * 4 + q] = h.stencil[q];
     }
     s->d_off = dupload(s->off, stream);
-    s->d_rowptr = dupload(rp, stream);
-    s->d_col = dupload(col, stream);
-    s->d_val64 = dupload(v64, stream);
-    s->d_val32 = dupload(v32, stream);
-    s->d_a01 = dupload(a01, stream);
+    s->d_stencil = dupload(stn, stream);
+    s->d_mptr = dupload(mp, stream);
+    s->d_mcol = dupload(mc, stream);
+    s->d_mval64 = dupload(mv64, stream);
+    s->d_mval32 = dupload(mv32, stream);
+    s->d_ma01 = dupload(ma01, stream);
     s->d_dinv = dupload(dinv, stream);
     s->d_dist = dupload(dist, stream);
     s->d_alpha = dupload(alpha, stream);
+    // coupling-row lists: 3D rows with M entries, then all 1D rows
+    std::vector<int32_t> mrows;
+    std::vector<int64_t> ms(n_inst), ml(n_inst), ml3(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+      const HostInstance& h = s->host[i];
+      ms[i] = (int64_t)mrows.size();
+      for (int r = 0; r < h.n3d; ++r)
+        if (h.m_ptr[r + 1] > h.m_ptr[r]) mrows.push_back((int32_t)(s->off[i] + r));
+      ml3[i] = (int64_t)mrows.size() - ms[i];
+      for (int r = h.n3d; r < h.n3d + h.n1d; ++r) mrows.push_back((int32_t)(s->off[i] + r));
+      ml[i] = (int64_t)mrows.size() - ms[i];
+      s->m_rows.push_back(ml[i]);
+      s->m_nnz.push_back((int64_t)h.m_col.size());
+    }
+    s->d_mrows = dupload(mrows, stream);
+    build_blocks(s->mblk, ms, ml, (int64_t)mrows.size(), stream);
+    build_blocks(s->mblk3, ms, ml3, (int64_t)mrows.size(), stream);
     // tree factorisation
     std::vector<int32_t> toff(n_inst + 1, 0), lvloff(n_inst + 1, 0), lvlptr, lvlnodes, parent, childptr, childidx;
     std::vector<double> lval, tdinv;
@@ -385,6 +433,10 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
     // drop the host copies that are not needed any more (keep CSR, F, dist for export)
     for (auto& h : s->host) {
       std::vector<int32_t>().swap(h.a01_start);
+      std::vector<int32_t>().swap(h.m_ptr);
+      std::vector<int32_t>().swap(h.m_col);
+      std::vector<double>().swap(h.m_val);
+      std::vector<int32_t>().swap(h.m_a01);
       h.tree = TreeFactor();
     }
     ctx->systems.push_back(s);
@@ -414,6 +466,13 @@ extern "C" mdnp_status mdnp_sys_sizes(const mdnp_sys* s, int32_t inst, int32_t* 
   if (n1d) *n1d = s->host[inst].n1d;
   if (nnz) *nnz = (int64_t)s->host[inst].col.size();
   if (offset) *offset = s->off[inst];
+  return MDNP_OK;
+}
+
+extern "C" mdnp_status mdnp_sys_split_sizes(const mdnp_sys* s, int32_t inst, int64_t* m_nnz, int64_t* m_rows) {
+  if (!s || inst < 0 || inst >= s->n_inst) return MDNP_E_ARG;
+  if (m_nnz) *m_nnz = s->m_nnz[inst];
+  if (m_rows) *m_rows = s->m_rows[inst];
   return MDNP_OK;
 }
 
@@ -499,7 +558,7 @@ void ensure_work(mdnp_sys* s, int m, int hist_cap) {
   w.sn = dalloc<double>(ni * m);
   w.g = dalloc<double>(ni * (m + 1));
   w.y = dalloc<double>(ni * m);
-  w.part = dalloc<double>(3 * (size_t)s->blk.nblk + (size_t)s->blk3.nblk);
+  w.part = dalloc<double>(parts_size(s));
   w.hist = dalloc<double>(ni * hist_cap);
   w.st = dalloc<InstState>(ni);
   w.m = m;
@@ -510,7 +569,7 @@ void ensure_work(mdnp_sys* s, int m, int hist_cap) {
 // Preconditioner application z = Q(v) for the Arnoldi step (mode-masked).
 template <typename T>
 void apply_prec(mdnp_sys* s, const T* v, T* z, const InstState* st, bool any_fb, hipStream_t stream) {
-  double* part3 = s->work.part ? s->work.part + 3 * (size_t)s->blk.nblk : nullptr;
+  const Parts P = parts(s, s->work.part);
   switch (s->kind) {
     case MDNP_PREC_NONE:
       launch_prec_copy<T>(s, v, z, st, stream);
@@ -522,11 +581,11 @@ void apply_prec(mdnp_sys* s, const T* v, T* z, const InstState* st, bool any_fb,
     case MDNP_PREC_BLOCK_JACOBI:
     case MDNP_PREC_NEURAL:
       launch_tree_solve<T>(s, v, z, st, 0, stream);
-      launch_extension<T>(s, v, z, part3, st, 0, stream);
+      launch_extension<T>(s, v, z, P.p3, P.pM3, st, 0, stream);
       if (s->kind == MDNP_PREC_BLOCK_JACOBI) {
         launch_block_jacobi3d<T>(s, z, st, 0, stream);
       } else {
-        launch_inv_scale(s, part3, s->cnn.inv_s, const_cast<InstState*>(st), 0, stream);
+        launch_inv_scale(s, P.p3, P.pM3, s->cnn.inv_s, const_cast<InstState*>(st), 0, stream);
         cnn_apply_in_solver<T>(s, z, st, stream);
       }
       break;
@@ -582,8 +641,9 @@ void solve_impl(mdnp_ctx* ctx, mdnp_sys* s, const double* d_b, double* d_x, cons
   int cycles = 0;
   const int max_cycles = total_cap + 4;
   while (true) {
-    launch_residual(s, d_b, d_x, w.r, w.part, w.st, stream);
-    launch_cycle_start(s, w.st, w.part, w.g, w.hist, w.hist_cap, w.m, stream);
+    const Parts P = parts(s, w.part);
+    launch_residual(s, d_b, d_x, w.r, P.pA, P.pM, w.st, stream);
+    launch_cycle_start(s, w.st, P.pA, P.pM, w.g, w.hist, w.hist_cap, w.m, stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(hs.data(), w.st, sizeof(InstState) * ni, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
@@ -773,9 +833,7 @@ extern "C" mdnp_status mdnp_precond_apply(mdnp_ctx* ctx, mdnp_sys* s, const void
     if (!s->prec_set) fail(MDNP_E_STATE, "no preconditioner set");
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t stream = pick(ctx, hip_stream);
-    if (!s->work.part) {
-      s->work.part = dalloc<double>(3 * (size_t)s->blk.nblk + (size_t)s->blk3.nblk);
-    }
+    if (!s->work.part) s->work.part = dalloc<double>(parts_size(s));
     if (!s->cnn.inv_s) s->cnn.inv_s = dalloc<double>(2 * (size_t)s->n_inst);
     if (s->vec_dtype == MDNP_F64) apply_prec<double>(s, (const double*)d_v, (double*)d_z, nullptr, false, stream);
     else apply_prec<float>(s, (const float*)d_v, (float*)d_z, nullptr, false, stream);

@@ -473,7 +473,7 @@ static void conv_layer(const ConvP& p, int kind, int batch, mdnp_dtype dtype, in
 // Layers 1..9 (L0b .. D0) on activations of type T, given the buffer set.
 template <typename T>
 static void unet_middle(CnnState& c, const float* d_w, void* const* act, int batch, int n, mdnp_dtype dtype,
-                        const InstState* st, hipStream_t stream) {
+                        const InstState* st, hipStream_t stream, int last_layer = 9) {
   const int n1 = (n + 1) / 2, n2 = (n1 + 1) / 2;
   const int nn[3] = {n, n1, n2};
   // act indices: 1 a0, 2 s0, 3 a1, 4 s1, 5 a2, 6 b2, 7 u1, 8 d1, 9 u0, 10 d0
@@ -482,6 +482,7 @@ static void unet_middle(CnnState& c, const float* d_w, void* const* act, int bat
                         {5, 5, -1, 6, 2, 2}, {6, 6, -1, 7, 2, 1}, {7, 7, 4, 8, 1, 1},  {8, 8, -1, 9, 1, 0},
                         {9, 9, 2, 10, 0, 0}};
   for (const Step& s : steps) {
+    if (s.layer > last_layer) break;
     const LayerSpec& L = kLayers[s.layer];
     ConvP p{};
     const int ca = s.src_b >= 0 ? L.cin / 2 : L.cin;
@@ -576,11 +577,12 @@ void cnn_apply_in_solver(mdnp_sys* s, Tv* z, const InstState* st, hipStream_t st
   for (int k = 0; k < 12; ++k) act[k] = (char*)c.act[0] + offs[k];
   const dim3 grid((unsigned)((cube(n) + BS - 1) / BS), 1, batch);
   if (c.dtype == MDNP_BF16) {
-    hipLaunchKernelGGL((k_conv_in0<Tv, bf16>), grid, dim3(BS), 0, stream, z, s->d_off, c.inv_s, s->d_dist,
-                       c.wt + c.wt_off[0], c.w + c.b_off[0], n, (bf16*)act[1], st);
-    unet_middle<bf16>(c, c.w, act, batch, n, c.dtype, st, stream);
-    hipLaunchKernelGGL((k_head_out<Tv, bf16>), grid, dim3(BS), 0, stream, (const bf16*)act[10],
-                       c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override, c.inv_s + s->n_inst, st);
+    // first layer reads the Krylov vector directly; D0, ReLU, the 1x1 head and the
+    // unscaling are one kernel writing z0
+    conv_mfma_in0<Tv>(c, z, s->d_off, c.inv_s, s->d_dist, n, batch, (bf16*)act[1], st, stream);
+    unet_middle<bf16>(c, c.w, act, batch, n, c.dtype, st, stream, 8);
+    conv_mfma_d0_head<Tv>(c, (const bf16*)act[9], (const bf16*)act[2], n, batch, z, s->d_off, s->d_alpha,
+                          s->alpha_override, c.inv_s + s->n_inst, st, stream);
   } else {
     hipLaunchKernelGGL((k_conv_in0<Tv, float>), grid, dim3(BS), 0, stream, z, s->d_off, c.inv_s, s->d_dist,
                        c.wt + c.wt_off[0], c.w + c.b_off[0], n, (float*)act[1], st);

@@ -40,5 +40,13 @@ struct ConvP {
 void cnn_prepare_mfma_weights(CnnState& c, const float* d_w, hipStream_t stream);
 bool conv_mfma_supported(int layer);
 void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c, hipStream_t stream);
+// in-solver first layer (input built from the Krylov vector) and fused D0 + head + unscale
+template <typename Tv>
+void conv_mfma_in0(const CnnState& c, const Tv* z, const int64_t* off, const double* inv_s, const float* dist,
+                   int n, int batch, bf16* a0, const InstState* st, hipStream_t stream);
+template <typename Tv>
+void conv_mfma_d0_head(const CnnState& c, const bf16* u0, const bf16* s0, int n, int batch, Tv* z,
+                       const int64_t* off, const double* alpha, double alpha_override, const double* scale,
+                       const InstState* st, hipStream_t stream);
 
 }  // namespace mdnp

@@ -78,7 +78,7 @@ struct SolveWork {
   double* sn = nullptr;
   double* g = nullptr;         // n_inst x (m+1)
   double* y = nullptr;         // n_inst x m
-  double* part = nullptr;      // 3 x nblk partial sums
+  double* part = nullptr;      // partial sums: 3 x blk, blk3, mblk, mblk3
   double* hist = nullptr;      // n_inst x hist_cap
   InstState* st = nullptr;     // n_inst
   hipGraphExec_t graph = nullptr;
@@ -105,15 +105,20 @@ struct mdnp_sys {
   std::vector<mdnp::HostInstance> host;
   std::vector<int64_t> off;        // [n_inst + 1] vector offsets
   std::vector<int64_t> nnz_off;    // [n_inst + 1]
-  int64_t ntot = 0, nnz_tot = 0;
+  int64_t ntot = 0, nnz_tot = 0, mnz_tot = 0;
+  std::vector<int64_t> m_nnz, m_rows;  // per instance: entries and non-empty rows of M
   int max_n1d = 0;
   // device arrays
   int64_t* d_off = nullptr;
-  int32_t* d_rowptr = nullptr;     // [ntot + 1], global entry offsets
-  int32_t* d_col = nullptr;        // global column indices
-  double* d_val64 = nullptr;
-  float* d_val32 = nullptr;
-  int32_t* d_a01 = nullptr;        // [n_inst * n3d] first entry of each 3D row with a 1D column
+  // operator A = S + M: S the constant 27-point stencil of the free 3D nodes
+  // (unit rows on the Dirichlet nodes), M the coupling / 1D part in CSR
+  double* d_stencil = nullptr;     // [n_inst * 4] stencil value by differing coordinates
+  int32_t* d_mptr = nullptr;       // [ntot + 1], global entry offsets
+  int32_t* d_mcol = nullptr;       // global column indices
+  double* d_mval64 = nullptr;
+  float* d_mval32 = nullptr;
+  int32_t* d_ma01 = nullptr;       // [n_inst * n3d] first M entry of each 3D row with a 1D column
+  int32_t* d_mrows = nullptr;      // global ids of the rows with M entries (per instance: 3D rows, then 1D rows)
   double* d_dinv = nullptr;        // [ntot] 1 / diag(A)
   float* d_dist = nullptr;         // [n_inst * n3d]
   double* d_alpha = nullptr;       // [n_inst]
@@ -129,6 +134,8 @@ struct mdnp_sys {
   double* d_t_dinv = nullptr;
   mdnp::Blocks blk;                // whole vectors
   mdnp::Blocks blk3;               // 3D parts only
+  mdnp::Blocks mblk;               // coupling-row lists
+  mdnp::Blocks mblk3;              // coupling-row lists, 3D rows only
   // preconditioner
   mdnp_prec_kind kind = MDNP_PREC_NONE;
   bool prec_set = false;

@@ -17,14 +17,14 @@ template <typename T>
 void launch_spmv_a00_all(mdnp_sys* s, const T* x, T* y, hipStream_t stream);
 
 // r = b - A x in FP64 with per-block partial sums of r^2 (instances not done).
-void launch_residual(mdnp_sys* s, const double* b, const double* x, double* r, double* part,
+void launch_residual(mdnp_sys* s, const double* b, const double* x, double* r, double* part, double* partm,
                      const InstState* st, hipStream_t stream);
 // per-block partial sums of x^2 over whole vectors
 void launch_norm2_partials(mdnp_sys* s, const double* x, double* part, hipStream_t stream);
 void launch_init_state(mdnp_sys* s, InstState* st, const double* part, double tol, int max_iters,
                        hipStream_t stream);
-void launch_cycle_start(mdnp_sys* s, InstState* st, const double* part, double* g, double* hist,
-                        int hist_cap, int m, hipStream_t stream);
+void launch_cycle_start(mdnp_sys* s, InstState* st, const double* part, const double* partm, double* g,
+                        double* hist, int hist_cap, int m, hipStream_t stream);
 template <typename T>
 void launch_scale_to(mdnp_sys* s, const double* r, T* v0, const InstState* st, hipStream_t stream);
 
@@ -39,12 +39,12 @@ template <typename T>
 void launch_tree_solve(mdnp_sys* s, const T* v, T* z, const InstState* st, int want_mode,
                        hipStream_t stream);
 template <typename T>
-void launch_extension(mdnp_sys* s, const T* v, T* z, double* part3, const InstState* st, int want_mode,
-                      hipStream_t stream);
+void launch_extension(mdnp_sys* s, const T* v, T* z, double* part3, double* part3m, const InstState* st,
+                      int want_mode, hipStream_t stream);
 template <typename T>
 void launch_block_jacobi3d(mdnp_sys* s, T* z, const InstState* st, int want_mode, hipStream_t stream);
-void launch_inv_scale(mdnp_sys* s, const double* part3, double* inv_s, InstState* st, int want_mode,
-                      hipStream_t stream);
+void launch_inv_scale(mdnp_sys* s, const double* part3, const double* part3m, double* inv_s, InstState* st,
+                      int want_mode, hipStream_t stream);
 
 // Arnoldi
 template <typename T>

@@ -58,83 +58,130 @@ __device__ __forceinline__ bool is_boundary(int r, int n) {
   return i == 0 || j == 0 || k == 0 || i == n - 1 || j == n - 1 || k == n - 1;
 }
 
-// ---------------------------------------------------------------- SpMV
+// ---------------------------------------------------------------- operator A = S + M
 
-// CSR with G lanes per row; rows of each block are the block's element chunk.
-template <typename Tv, typename Tm, typename Tacc, int G>
-__global__ void __launch_bounds__(BS) k_spmv(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                             const Tm* __restrict__ val, const Tv* __restrict__ x,
-                                             Tv* __restrict__ y, const int32_t* binst, const int64_t* bstart,
-                                             const int64_t* bend, const InstState* st, int mask) {
+// (S x)[r] for 3D row r of the instance whose vector starts at x + base: the
+// constant 27-point stencil grouped by the number of differing coordinates
+// (centre, 6 faces, 12 edges, 8 corners); neighbours on the Dirichlet boundary
+// are eliminated, and a Dirichlet row is the unit row.
+template <typename Tv, typename Tacc>
+__device__ __forceinline__ Tacc stencil_row(const Tv* __restrict__ x, int64_t base, int r, int n,
+                                            const double* __restrict__ st4) {
+  const int ix = r % n, iy = (r / n) % n, iz = r / (n * n);
+  const Tv* xc = x + base + r;
+  if (ix == 0 || iy == 0 || iz == 0 || ix == n - 1 || iy == n - 1 || iz == n - 1) return (Tacc)xc[0];
+  const bool vx[3] = {ix > 1, true, ix < n - 2};
+  const bool vy[3] = {iy > 1, true, iy < n - 2};
+  const bool vz[3] = {iz > 1, true, iz < n - 2};
+  const int64_t nn = (int64_t)n * n;
+  Tacc grp[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int nd = (dx != 1) + (dy != 1) + (dz != 1);
+        if (vx[dx] && vy[dy] && vz[dz]) grp[nd] += (Tacc)xc[(dz - 1) * nn + (dy - 1) * n + (dx - 1)];
+      }
+  return (Tacc)st4[0] * grp[0] + (Tacc)st4[1] * grp[1] + (Tacc)st4[2] * grp[2] + (Tacc)st4[3] * grp[3];
+}
+
+// y = S x over whole concatenated vectors (one thread per row; 1D rows get 0).
+// RES = 1: r = b - S x, with partial sums of r^2 over the rows that have no
+// coupling entries (the coupling-row kernel completes and sums the others).
+template <typename Tv, typename Tacc, int RES>
+__global__ void __launch_bounds__(BS) k_stencil(const double* __restrict__ stencil, const int32_t* __restrict__ mptr,
+                                                const Tv* __restrict__ x, const double* __restrict__ bvec,
+                                                Tv* __restrict__ y, const int64_t* off, int n, int n3d,
+                                                const int32_t* binst, const int64_t* bstart, const int64_t* bend,
+                                                const InstState* st, int mask, double* part) {
+  __shared__ double sh[BS / 64];
   const int b = blockIdx.x;
-  if (mask && !st[binst[b]].active) return;
-  const int64_t r0 = bstart[b], r1 = bend[b];
-  const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = blockDim.x / G;
-  for (int64_t r = r0 + grp; r < r1; r += ng) {
+  const int i = binst[b];
+  if (mask == 1 && !st[i].active) return;
+  if (mask == 2 && st[i].done) {
+    if (RES && threadIdx.x == 0) part[b] = 0.0;
+    return;
+  }
+  const int64_t base = off[i];
+  const double* st4 = stencil + 4 * i;
+  double loc = 0.0;
+  for (int64_t row = bstart[b] + threadIdx.x; row < bend[b]; row += BS) {
+    const int r = (int)(row - base);
+    const Tacc sx = r < n3d ? stencil_row<Tv, Tacc>(x, base, r, n, st4) : (Tacc)0;
+    if (RES) {
+      const double rv = bvec[row] - (double)sx;
+      y[row] = (Tv)rv;
+      if (mptr[row + 1] == mptr[row]) loc += rv * rv;
+    } else {
+      y[row] = (Tv)sx;
+    }
+  }
+  if (RES) {
+    const double t = block_sum(loc, sh);
+    if (threadIdx.x == 0) part[b] = t;
+  }
+}
+
+// Coupling rows (3D rows touched by the averaging operator and all 1D rows),
+// G lanes per row: y[row] += (M x)[row] (RES = 0) or r[row] -= (M x)[row] with
+// partial sums of r^2 (RES = 1).
+template <typename Tv, typename Tm, typename Tacc, int G, int RES>
+__global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows, const int32_t* __restrict__ mptr,
+                                              const int32_t* __restrict__ mcol, const Tm* __restrict__ mval,
+                                              const Tv* __restrict__ x, Tv* __restrict__ y, const int32_t* binst,
+                                              const int64_t* bstart, const int64_t* bend, const InstState* st,
+                                              int mask, double* part) {
+  __shared__ double sh[BS / 64];
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (mask == 1 && !st[i].active) return;
+  if (mask == 2 && st[i].done) {
+    if (RES && threadIdx.x == 0) part[b] = 0.0;
+    return;
+  }
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = BS / G;
+  double loc = 0.0;
+  for (int64_t q = bstart[b] + grp; q < bend[b]; q += ng) {
+    const int row = mrows[q];
     Tacc acc = 0;
-    const int e = rp[r + 1];
-    for (int k = rp[r] + lane; k < e; k += G) acc += (Tacc)val[k] * (Tacc)x[col[k]];
+    const int e = mptr[row + 1];
+    for (int k = mptr[row] + lane; k < e; k += G) acc += (Tacc)mval[k] * (Tacc)x[mcol[k]];
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-    if (lane == 0) y[r] = (Tv)acc;
+    if (lane == 0) {
+      if (RES) {
+        const double rv = (double)y[row] - (double)acc;
+        y[row] = (Tv)rv;
+        loc += rv * rv;
+      } else {
+        y[row] = (Tv)((Tacc)y[row] + acc);
+      }
+    }
+  }
+  if (RES) {
+    const double t = block_sum(loc, sh);
+    if (threadIdx.x == 0) part[b] = t;
   }
 }
 
 // y = A00 x for the 3D unknowns of instance inst[slot], vectors [slot][n3d].
-template <typename T, typename Tm, int G>
-__global__ void __launch_bounds__(BS) k_spmv_a00(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                 const Tm* __restrict__ val, const int64_t* off,
-                                                 const int32_t* a01, const int32_t* inst, int n3d,
-                                                 const T* __restrict__ x, T* __restrict__ y) {
+template <typename T, typename Tm>
+__global__ void __launch_bounds__(BS) k_apply_a00(const double* __restrict__ stencil, const int32_t* __restrict__ mptr,
+                                                  const int32_t* __restrict__ mcol, const Tm* __restrict__ mval,
+                                                  const int64_t* off, const int32_t* ma01, const int32_t* inst,
+                                                  int n, int n3d, const T* __restrict__ x, T* __restrict__ y) {
   const int slot = blockIdx.y;
   const int i = inst ? inst[slot] : slot;
   const int64_t base = off[i];
   const T* xs = x + (int64_t)slot * n3d;
-  const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = blockDim.x / G;
-  const int rows_per_block = ng * 16;
-  const int r0 = blockIdx.x * rows_per_block;
-  const int r1 = min(r0 + rows_per_block, n3d);
-  for (int r = r0 + grp; r < r1; r += ng) {
-    const int64_t g = base + r;
-    double acc = 0.0;
-    const int e = a01[(int64_t)i * n3d + r];  // 3D columns end where the 1D ones start
-    for (int k = rp[g] + lane; k < e; k += G) acc += (double)val[k] * (double)xs[col[k] - base];
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-    if (lane == 0) y[(int64_t)slot * n3d + r] = (T)acc;
-  }
-}
-
-// r = b - A x (FP64) and partial sums of r^2 per block.
-template <int G>
-__global__ void __launch_bounds__(BS) k_residual(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                 const double* __restrict__ val, const double* __restrict__ x,
-                                                 const double* __restrict__ bvec, double* __restrict__ r,
-                                                 const int32_t* binst, const int64_t* bstart,
-                                                 const int64_t* bend, const InstState* st, double* part) {
-  __shared__ double sh[BS / 64];
-  const int b = blockIdx.x;
-  if (st && st[binst[b]].done) {
-    if (threadIdx.x == 0) part[b] = 0.0;
-    return;
-  }
-  const int64_t r0 = bstart[b], r1 = bend[b];
-  const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = blockDim.x / G;
-  double loc = 0.0;
-  for (int64_t row = r0 + grp; row < r1; row += ng) {
-    double acc = 0.0;
-    const int e = rp[row + 1];
-    for (int k = rp[row] + lane; k < e; k += G) acc += val[k] * x[col[k]];
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-    if (lane == 0) {
-      double rv = bvec[row] - acc;
-      r[row] = rv;
-      loc += rv * rv;
-    }
-  }
-  double t = block_sum(loc, sh);
-  if (threadIdx.x == 0) part[b] = t;
+  const int r = blockIdx.x * BS + threadIdx.x;
+  if (r >= n3d) return;
+  double acc = stencil_row<T, double>(xs, 0, r, n, stencil + 4 * i);
+  const int e = ma01[(int64_t)i * n3d + r];  // 3D columns end where the 1D ones start
+  for (int k = mptr[base + r]; k < e; ++k) acc += (double)mval[k] * (double)xs[mcol[k] - base];
+  y[(int64_t)slot * n3d + r] = (T)acc;
 }
 
 __global__ void __launch_bounds__(BS) k_norm2_part(const double* __restrict__ x, const int64_t* bstart,
@@ -169,8 +216,8 @@ __global__ void k_init_state(InstState* st, const double* part, const int32_t* f
 }
 
 // Start of a restart cycle: beta = ||r||, convergence and stall tests.
-__global__ void k_cycle_start(InstState* st, const double* part, const int32_t* first, int n_inst,
-                              double* g, double* hist, int hist_cap, int m) {
+__global__ void k_cycle_start(InstState* st, const double* part, const int32_t* first, const double* part2,
+                              const int32_t* first2, int n_inst, double* g, double* hist, int hist_cap, int m) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_inst) return;
   InstState z = st[i];
@@ -182,6 +229,7 @@ __global__ void k_cycle_start(InstState* st, const double* part, const int32_t* 
   }
   double s = 0.0;
   for (int b = first[i]; b < first[i + 1]; ++b) s += part[b];
+  for (int b = first2[i]; b < first2[i + 1]; ++b) s += part2[b];
   const double beta = sqrt(s);
   const double rel = beta / z.bnorm;
   if (z.nhist < hist_cap) hist[(int64_t)i * hist_cap + z.nhist++] = -rel;
@@ -290,14 +338,14 @@ __global__ void __launch_bounds__(BS) k_tree_solve(const T* __restrict__ v, T* _
   for (int c = threadIdx.x; c < n1d; c += blockDim.x) z[g0 + c] = from_d<T>(ys[c]);
 }
 
-// b0 = v0 - A01 z1 on the 3D rows (z1 already in z), partial sums of b0^2.
-template <typename T, typename Tm>
-__global__ void __launch_bounds__(BS) k_extension(const T* __restrict__ v, T* __restrict__ z,
-                                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                  const Tm* __restrict__ val, const int32_t* __restrict__ a01,
-                                                  const int64_t* off, int n3d, const int32_t* binst,
-                                                  const int64_t* bstart, const int64_t* bend,
-                                                  const InstState* st, int want_mode, double* part) {
+// Extension b0 = v0 - A01 z1 (z1 already in z), in two passes: every 3D row
+// copies v0 (partial sums of b0^2 over rows without coupling), then the
+// coupling rows subtract their A01 z1 part (partial sums over those rows).
+template <typename T>
+__global__ void __launch_bounds__(BS) k_ext_copy(const T* __restrict__ v, T* __restrict__ z,
+                                                 const int32_t* __restrict__ mptr, const int64_t* off,
+                                                 const int32_t* binst, const int64_t* bstart, const int64_t* bend,
+                                                 const InstState* st, int want_mode, double* part) {
   __shared__ double sh[BS / 64];
   const int b = blockIdx.x;
   const int i = binst[b];
@@ -309,13 +357,44 @@ __global__ void __launch_bounds__(BS) k_extension(const T* __restrict__ v, T* __
   double loc = 0.0;
   for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += blockDim.x) {
     const int64_t g = base + r;
-    double acc = to_d(v[g]);
-    const int e = rp[g + 1];
-    for (int k = a01[(int64_t)i * n3d + r]; k < e; ++k) acc -= (double)val[k] * to_d(z[col[k]]);
-    const T stored = from_d<T>(acc);
-    z[g] = stored;
-    const double sv = to_d(stored);
-    loc += sv * sv;
+    const T vv = v[g];
+    z[g] = vv;
+    if (mptr[g + 1] == mptr[g]) loc += to_d(vv) * to_d(vv);
+  }
+  double t = block_sum(loc, sh);
+  if (threadIdx.x == 0) part[b] = t;
+}
+
+template <typename T, typename Tm, int G>
+__global__ void __launch_bounds__(BS) k_ext_rows(const T* __restrict__ v, T* __restrict__ z,
+                                                 const int32_t* __restrict__ mrows, const int32_t* __restrict__ mptr,
+                                                 const int32_t* __restrict__ mcol, const Tm* __restrict__ mval,
+                                                 const int32_t* __restrict__ ma01, const int64_t* off, int n3d,
+                                                 const int32_t* binst, const int64_t* bstart, const int64_t* bend,
+                                                 const InstState* st, int want_mode, double* part) {
+  __shared__ double sh[BS / 64];
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (st && !mode_ok(st[i], want_mode)) {
+    if (threadIdx.x == 0) part[b] = 0.0;
+    return;
+  }
+  const int64_t base = off[i];
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = BS / G;
+  double loc = 0.0;
+  for (int64_t q = bstart[b] + grp; q < bend[b]; q += ng) {
+    const int row = mrows[q];
+    const int r = (int)(row - base);
+    double acc = 0.0;
+    const int e = mptr[row + 1];
+    for (int k = ma01[(int64_t)i * n3d + r] + lane; k < e; k += G) acc += (double)mval[k] * to_d(z[mcol[k]]);
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+    if (lane == 0) {
+      const T stored = from_d<T>(to_d(v[row]) - acc);
+      z[row] = stored;
+      loc += to_d(stored) * to_d(stored);
+    }
   }
   double t = block_sum(loc, sh);
   if (threadIdx.x == 0) part[b] = t;
@@ -334,13 +413,14 @@ __global__ void __launch_bounds__(BS) k_block_jacobi3d(T* __restrict__ z, const 
     z[base + r] = from_d<T>(to_d(z[base + r]) * dinv[base + r]);
 }
 
-__global__ void k_inv_scale(const double* part3, const int32_t* first, int n_inst, double* inv_s,
-                            InstState* st, int want_mode) {
+__global__ void k_inv_scale(const double* part3, const int32_t* first, const double* part4, const int32_t* first4,
+                            int n_inst, double* inv_s, InstState* st, int want_mode) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_inst) return;
   if (st && !mode_ok(st[i], want_mode)) return;
   double s = 0.0;
   for (int b = first[i]; b < first[i + 1]; ++b) s += part3[b];
+  for (int b = first4[i]; b < first4[i + 1]; ++b) s += part4[b];
   s = sqrt(s);
   inv_s[i] = s > 0.0 ? 1.0 / s : 0.0;
   inv_s[n_inst + i] = s;
@@ -485,44 +565,54 @@ __global__ void __launch_bounds__(BS) k_update_x(const T* __restrict__ Z, int64_
 #define BLK(s) (s)->blk.inst, (s)->blk.start, (s)->blk.end
 #define BLK3(s) (s)->blk3.inst, (s)->blk3.start, (s)->blk3.end
 
+#define MBLK(s) (s)->mblk.inst, (s)->mblk.start, (s)->mblk.end
+#define MBLK3(s) (s)->mblk3.inst, (s)->mblk3.start, (s)->mblk3.end
+
 template <typename T>
 void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, hipStream_t stream) {
-  if (sizeof(T) == 8)
-    hipLaunchKernelGGL((k_spmv<T, double, double, 8>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_rowptr,
-                       s->d_col, s->d_val64, x, y, BLK(s), st, mask ? 1 : 0);
-  else
-    hipLaunchKernelGGL((k_spmv<T, float, float, 8>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_rowptr,
-                       s->d_col, s->d_val32, x, y, BLK(s), st, mask ? 1 : 0);
+  const int mk = mask ? 1 : 0;
+  if (sizeof(T) == 8) {
+    hipLaunchKernelGGL((k_stencil<T, double, 0>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr, x,
+                       (const double*)nullptr, y, s->d_off, s->n, s->n3d, BLK(s), st, mk, (double*)nullptr);
+    hipLaunchKernelGGL((k_mrows<T, double, double, 8, 0>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
+                       s->d_mptr, s->d_mcol, s->d_mval64, x, y, MBLK(s), st, mk, (double*)nullptr);
+  } else {
+    hipLaunchKernelGGL((k_stencil<T, float, 0>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr, x,
+                       (const double*)nullptr, y, s->d_off, s->n, s->n3d, BLK(s), st, mk, (double*)nullptr);
+    hipLaunchKernelGGL((k_mrows<T, float, float, 8, 0>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
+                       s->d_mptr, s->d_mcol, s->d_mval32, x, y, MBLK(s), st, mk, (double*)nullptr);
+  }
 }
 template void launch_spmv<float>(mdnp_sys*, const float*, float*, const InstState*, bool, hipStream_t);
 template void launch_spmv<double>(mdnp_sys*, const double*, double*, const InstState*, bool, hipStream_t);
 
 void launch_spmv_a00_slots(mdnp_sys* s, const int32_t* inst, int n_slots, const float* x, float* y,
                            hipStream_t stream) {
-  const int rows_per_block = (BS / 8) * 16;
-  dim3 grid((s->n3d + rows_per_block - 1) / rows_per_block, n_slots);
-  hipLaunchKernelGGL((k_spmv_a00<float, float, 8>), grid, dim3(BS), 0, stream, s->d_rowptr, s->d_col,
-                     s->d_val32, s->d_off, s->d_a01, inst, s->n3d, x, y);
+  dim3 grid((s->n3d + BS - 1) / BS, n_slots);
+  hipLaunchKernelGGL((k_apply_a00<float, float>), grid, dim3(BS), 0, stream, s->d_stencil, s->d_mptr, s->d_mcol,
+                     s->d_mval32, s->d_off, s->d_ma01, inst, s->n, s->n3d, x, y);
 }
 
 template <typename T>
 void launch_spmv_a00_all(mdnp_sys* s, const T* x, T* y, hipStream_t stream) {
-  const int rows_per_block = (BS / 8) * 16;
-  dim3 grid((s->n3d + rows_per_block - 1) / rows_per_block, s->n_inst);
+  dim3 grid((s->n3d + BS - 1) / BS, s->n_inst);
   if (sizeof(T) == 8)
-    hipLaunchKernelGGL((k_spmv_a00<T, double, 8>), grid, dim3(BS), 0, stream, s->d_rowptr, s->d_col, s->d_val64,
-                       s->d_off, s->d_a01, (const int32_t*)nullptr, s->n3d, x, y);
+    hipLaunchKernelGGL((k_apply_a00<T, double>), grid, dim3(BS), 0, stream, s->d_stencil, s->d_mptr, s->d_mcol,
+                       s->d_mval64, s->d_off, s->d_ma01, (const int32_t*)nullptr, s->n, s->n3d, x, y);
   else
-    hipLaunchKernelGGL((k_spmv_a00<T, float, 8>), grid, dim3(BS), 0, stream, s->d_rowptr, s->d_col, s->d_val32,
-                       s->d_off, s->d_a01, (const int32_t*)nullptr, s->n3d, x, y);
+    hipLaunchKernelGGL((k_apply_a00<T, float>), grid, dim3(BS), 0, stream, s->d_stencil, s->d_mptr, s->d_mcol,
+                       s->d_mval32, s->d_off, s->d_ma01, (const int32_t*)nullptr, s->n, s->n3d, x, y);
 }
 template void launch_spmv_a00_all<float>(mdnp_sys*, const float*, float*, hipStream_t);
 template void launch_spmv_a00_all<double>(mdnp_sys*, const double*, double*, hipStream_t);
 
-void launch_residual(mdnp_sys* s, const double* b, const double* x, double* r, double* part,
+void launch_residual(mdnp_sys* s, const double* b, const double* x, double* r, double* part, double* partm,
                      const InstState* st, hipStream_t stream) {
-  hipLaunchKernelGGL((k_residual<8>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_rowptr, s->d_col, s->d_val64,
-                     x, b, r, BLK(s), st, part);
+  const int mk = st ? 2 : 0;
+  hipLaunchKernelGGL((k_stencil<double, double, 1>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr,
+                     x, b, r, s->d_off, s->n, s->n3d, BLK(s), st, mk, part);
+  hipLaunchKernelGGL((k_mrows<double, double, double, 8, 1>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
+                     s->d_mptr, s->d_mcol, s->d_mval64, x, r, MBLK(s), st, mk, partm);
 }
 
 void launch_norm2_partials(mdnp_sys* s, const double* x, double* part, hipStream_t stream) {
@@ -535,10 +625,10 @@ void launch_init_state(mdnp_sys* s, InstState* st, const double* part, double to
                      s->n_inst, tol, max_iters);
 }
 
-void launch_cycle_start(mdnp_sys* s, InstState* st, const double* part, double* g, double* hist, int hist_cap,
-                        int m, hipStream_t stream) {
-  hipLaunchKernelGGL(k_cycle_start, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, st, part, s->blk.first,
-                     s->n_inst, g, hist, hist_cap, m);
+void launch_cycle_start(mdnp_sys* s, InstState* st, const double* part, const double* partm, double* g, double* hist,
+                        int hist_cap, int m, hipStream_t stream) {
+  hipLaunchKernelGGL(k_cycle_start, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, st, part, s->blk.first, partm,
+                     s->mblk.first, s->n_inst, g, hist, hist_cap, m);
 }
 
 template <typename T>
@@ -581,17 +671,20 @@ template void launch_tree_solve<float>(mdnp_sys*, const float*, float*, const In
 template void launch_tree_solve<double>(mdnp_sys*, const double*, double*, const InstState*, int, hipStream_t);
 
 template <typename T>
-void launch_extension(mdnp_sys* s, const T* v, T* z, double* part3, const InstState* st, int want_mode,
-                      hipStream_t stream) {
+void launch_extension(mdnp_sys* s, const T* v, T* z, double* part3, double* part3m, const InstState* st,
+                      int want_mode, hipStream_t stream) {
+  hipLaunchKernelGGL((k_ext_copy<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, v, z, s->d_mptr, s->d_off, BLK3(s), st,
+                     want_mode, part3);
   if (sizeof(T) == 8)
-    hipLaunchKernelGGL((k_extension<T, double>), dim3(s->blk3.nblk), dim3(BS), 0, stream, v, z, s->d_rowptr,
-                       s->d_col, s->d_val64, s->d_a01, s->d_off, s->n3d, BLK3(s), st, want_mode, part3);
+    hipLaunchKernelGGL((k_ext_rows<T, double, 8>), dim3(s->mblk3.nblk), dim3(BS), 0, stream, v, z, s->d_mrows,
+                       s->d_mptr, s->d_mcol, s->d_mval64, s->d_ma01, s->d_off, s->n3d, MBLK3(s), st, want_mode, part3m);
   else
-    hipLaunchKernelGGL((k_extension<T, float>), dim3(s->blk3.nblk), dim3(BS), 0, stream, v, z, s->d_rowptr,
-                       s->d_col, s->d_val32, s->d_a01, s->d_off, s->n3d, BLK3(s), st, want_mode, part3);
+    hipLaunchKernelGGL((k_ext_rows<T, float, 8>), dim3(s->mblk3.nblk), dim3(BS), 0, stream, v, z, s->d_mrows,
+                       s->d_mptr, s->d_mcol, s->d_mval32, s->d_ma01, s->d_off, s->n3d, MBLK3(s), st, want_mode, part3m);
 }
-template void launch_extension<float>(mdnp_sys*, const float*, float*, double*, const InstState*, int, hipStream_t);
-template void launch_extension<double>(mdnp_sys*, const double*, double*, double*, const InstState*, int,
+template void launch_extension<float>(mdnp_sys*, const float*, float*, double*, double*, const InstState*, int,
+                                      hipStream_t);
+template void launch_extension<double>(mdnp_sys*, const double*, double*, double*, double*, const InstState*, int,
                                        hipStream_t);
 
 template <typename T>
@@ -602,10 +695,10 @@ void launch_block_jacobi3d(mdnp_sys* s, T* z, const InstState* st, int want_mode
 template void launch_block_jacobi3d<float>(mdnp_sys*, float*, const InstState*, int, hipStream_t);
 template void launch_block_jacobi3d<double>(mdnp_sys*, double*, const InstState*, int, hipStream_t);
 
-void launch_inv_scale(mdnp_sys* s, const double* part3, double* inv_s, InstState* st, int want_mode,
-                      hipStream_t stream) {
-  hipLaunchKernelGGL(k_inv_scale, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, part3, s->blk3.first,
-                     s->n_inst, inv_s, st, want_mode);
+void launch_inv_scale(mdnp_sys* s, const double* part3, const double* part3m, double* inv_s, InstState* st,
+                      int want_mode, hipStream_t stream) {
+  hipLaunchKernelGGL(k_inv_scale, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, part3, s->blk3.first, part3m,
+                     s->mblk3.first, s->n_inst, inv_s, st, want_mode);
 }
 
 template <typename T>

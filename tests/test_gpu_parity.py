@@ -135,9 +135,12 @@ def _theta(seed=0, bias=0.05):
     return th
 
 
-@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 4e-2)])
-def test_cnn_forward_matches_oracle(ctx, dtype, tol):
-    n, batch = 17, 2
+@pytest.mark.parametrize("dtype,tol,n", [("f32", 1e-5, 17), ("bf16", 4e-2, 17), ("bf16", 4e-2, 33),
+                                         ("bf16", 4e-2, 9)])
+def test_cnn_forward_matches_oracle(ctx, dtype, tol, n):
+    """Whole network on a batch of 2 (grids 9^3: direct MFMA path; 17^3, 33^3:
+    LDS-tiled stride-1 layers plus the edge column)."""
+    batch = 2
     th = _theta(1)
     rng = np.random.default_rng(7)
     X = np.stack([rng.normal(size=(n, n, n)) / n ** 1.5, rng.uniform(0, 0.5, (n, n, n))], axis=-1)
