@@ -13,6 +13,9 @@
 // per-lane validity mask for the zero padding.  The stride-2 transposed
 // convolution is split into its 8 output parity classes, inside each of which
 // every voxel has the same 1, 2, 4 or 8 taps and no padding.
+#include <algorithm>
+#include <type_traits>
+
 #include "conv_common.hpp"
 
 namespace mdnp {
@@ -59,6 +62,8 @@ struct MfmaArgs {
   const bf16* a = nullptr;      // source A [batch][vox][CA]
   const bf16* b = nullptr;      // source B [batch][vox][CB] (channel stacking)
   const bf16* w = nullptr;      // weights [COUT][27][CIN] bf16
+  const bf16* wrows = nullptr;  // 16-channel layers: weights [16][3 ty][KCT * 32] (k_conv16_rows)
+  const void* zero16 = nullptr; // 16 zero bytes in device memory (padding source of the LDS loads)
   const float* bias = nullptr;
   bf16* y = nullptr;            // output [batch][vox][COUT]
   int n_in = 0, n_out = 0, relu = 0;
@@ -431,63 +436,114 @@ __global__ void __launch_bounds__(512) k_conv_lds(MfmaArgs p) {
   }
 }
 
-// Stride-1 convolution sweeping along z.  A workgroup owns output rows
-// y0..y0+TY-1 for x in [0, n-1) (the column x = n-1 goes to the EDGE variant of
-// k_conv_mfma) and planes z0..z0+ZC-1.  LDS holds a ring of the three input
-// planes z-1, z, z+1 (rows y0-1..y0+TY, x = -1..n-1, zero outside the grid);
-// while the MFMAs of plane z run, every thread holds its share of input plane
-// z+2 in registers and writes it into the ring afterwards, so each input plane
-// is read from memory once per workgroup (halo only in y).  Tile voxels are
-// padded to CLP channels to spread LDS banks.
-template <int CA, int CB, int COUT, int TY, int MB, int IN, int EPI, typename Tv>
-__global__ void __launch_bounds__(512) k_conv_sweep(MfmaArgs p, int zc) {
-  constexpr int CIN = IN ? 8 : CA + CB;
+// Stride-1 convolution with 16 output channels (the full-resolution layers).
+//
+// A workgroup of XB = (n - 1) / 16 waves owns output rows y0 .. y0 + MB - 1
+// (x in [0, n - 1); the column x = n - 1 goes to the EDGE variant of
+// k_conv_mfma) and sweeps the planes z0 .. z0 + zc - 1.  LDS holds a ring of
+// input planes over rows y0 - 1 .. y0 + MB and x = -1 .. n - 1 (zero outside
+// the grid), so every input plane is read once per workgroup.  Stored layers
+// (IN = 0) fill the ring with direct global-to-LDS loads (16 bytes per lane,
+// lane l landing at base + 16 l): a ring of four planes lets plane z + 2
+// arrive while the matrix cores work on plane z.  The first layer (IN = 1)
+// builds its two channels on the fly, staging plane z + 2 in registers over a
+// ring of three planes.
+//
+// The weights stay in registers for the whole launch, ordered [ty][tz, tx, ci]
+// so that one K chunk of 32 belongs to a single ty: an input fragment (input
+// row j, taps (tz, tx), channels) then serves the output rows j - 2 .. j with
+// ty = 2 .. 0, and each wave reads MB + 2 fragments per chunk for 3 MB MFMAs.
+// IN = 1 packs the 3 tx taps of one tz into each lane group: one chunk per ty.
+// Tile voxels of 64 or more channels (128-byte stride) carry one 16-byte pad
+// slot: that stride would put the lanes of one read on the same LDS banks.
+template <int CIN, int IN>
+struct RowsK {
+  static constexpr int KCT = IN ? 1 : (9 * CIN + 31) / 32;  // K chunks per ty
+};
+
+template <int CL, int IN>
+struct RowsTile {
+  static constexpr int CPV = IN ? 1 : CL / 8;                 // 16-byte slots of data per voxel
+  static constexpr int SLOTS = IN ? 1 : CPV + (CL >= 64 ? 1 : 0);
+  static constexpr int CLP = IN ? 2 : SLOTS * 8;              // bf16 per tile voxel
+  static constexpr int NRING = IN ? 3 : 4;
+  // bytes of one ring plane (a multiple of 1 KiB, the span of one wave's load)
+  __host__ __device__ static size_t plane_bytes(int mb, int n) {
+    const size_t b = (size_t)(mb + 2) * (n + 1) * CLP * 2;
+    return (b + 1023) & ~(size_t)1023;
+  }
+};
+
+struct RowsGrid {
+  int ylo = 0, yhi = 0, zlo = 0, zhi = 0;  // output rows / planes computed
+  int zc = 0, ytiles = 0;
+};
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void gbl_void_t;
+
+template <int CA, int CB, int MB, int IN, int EPI, typename Tv, int NPF>
+__global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
+  constexpr int CIN = IN ? 2 : CA + CB;
   constexpr int CL = IN ? 2 : CA + CB;
-  constexpr int CLP = (CL >= 32) ? CL + 8 : CL;
-  constexpr int NB = COUT / 16;
-  constexpr int KCH = (27 * CIN + 31) / 32;
-  constexpr int YW = TY + 2;
-  constexpr int NPF = 8;  // prefetch registers (16 B each) per thread
-  extern __shared__ unsigned short ring[];
+  typedef RowsTile<CL, IN> T;
+  constexpr int CLP = T::CLP;
+  constexpr int KCT = RowsK<CIN, IN>::KCT;
+  constexpr int YW = MB + 2;
+  constexpr int NR = T::NRING;
+  extern __shared__ __attribute__((aligned(1024))) unsigned short ring[];
   int bxr, bt;
   xcd_remap(bxr, bt);
   if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
   const int n = p.n_out;
   const int XW = n + 1;
-  const int ytiles = (n + TY - 1) / TY;
-  const int y0 = (bxr % ytiles) * TY, z0 = (bxr / ytiles) * zc;
-  const int zend = min(n, z0 + zc);
+  const int y0 = q.ylo + (bxr % q.ytiles) * MB;
+  const int z0 = q.zlo + (bxr / q.ytiles) * q.zc;
+  const int zend = min(q.zhi, z0 + q.zc);
   const int64_t nv = (int64_t)n * n * n;
-  const int nthr = blockDim.x;
-  const int plane_elems = YW * XW * CLP;  // bf16 per ring plane
+  const int nthr = blockDim.x, nwaves = nthr >> 6;
+  const int plane_elems = (int)(T::plane_bytes(MB, n) / 2);
+  const int plane_items = YW * XW * T::SLOTS;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, r = lane & 15;
-  // ---- plane loader: element q of a plane = (row, x, 8-channel chunk) or (row, x) for IN
-  constexpr int CPV = IN ? 1 : CL / 8;
-  const int plane_items = YW * XW * CPV;
   const bf16* A = IN ? nullptr : p.a + (int64_t)bt * nv * CA;
   const bf16* B = CB ? p.b + (int64_t)bt * nv * CB : nullptr;
   const Tv* Z = IN ? (const Tv*)p.z + p.off[bt] : nullptr;
   const float* D = IN ? p.dist + (int64_t)bt * nv : nullptr;
   const float sc = IN ? (float)p.inv_s[bt] : 0.0f;
+  // ---- stored layers: one wave-wide DMA per 64 slots of a plane
+  auto dma_plane = [&](int gz, int slot) {
+    unsigned short* pl = ring + (size_t)slot * plane_elems;
+    const int nload = (plane_items + 63) >> 6;
+    for (int L = wave; L < nload; L += nwaves) {
+      const int it = L * 64 + lane;
+      const void* src = p.zero16;
+      if (it < plane_items) {
+        const int vt = it / T::SLOTS, ch = it - vt * T::SLOTS;
+        const int row = vt / XW, xx = vt - row * XW;
+        const int gx = xx - 1, gy = y0 + row - 1;
+        if (ch < T::CPV && gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0) {
+          const int64_t vv = ((int64_t)gz * n + gy) * n + gx;
+          constexpr int CPA = CA / 8;
+          src = (CB == 0 || ch < CPA) ? (const void*)(A + vv * CA + ch * 8)
+                                      : (const void*)(B + vv * CB + (ch - CPA) * 8);
+        }
+      }
+      __builtin_amdgcn_global_load_lds((gbl_void_t*)src, (lds_void_t*)(pl + L * 512), 16, 0, 0);
+    }
+  };
+  // ---- first layer: stage in registers
   auto load_plane = [&](int gz, u32x4 (&buf)[NPF]) {
 #pragma unroll
     for (int k = 0; k < NPF; ++k) {
-      const int q = threadIdx.x + k * nthr;
+      const int it = threadIdx.x + k * nthr;
       u32x4 v = {0u, 0u, 0u, 0u};
-      if (q < plane_items) {
-        const int vt = q / CPV, ch = q - vt * CPV;
-        const int row = vt / XW, xx = vt - row * XW;
+      if (it < plane_items) {
+        const int row = it / XW, xx = it - row * XW;
         const int gx = xx - 1, gy = y0 + row - 1;
         if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0) {
           const int64_t vv = ((int64_t)gz * n + gy) * n + gx;
-          if (IN) {
-            v.x = (unsigned)f2bf((float)Z[vv] * sc) | ((unsigned)f2bf(D[vv]) << 16);
-          } else {
-            constexpr int CPA = CA / 8;
-            v = (CB == 0 || ch < CPA) ? *(const u32x4*)(A + vv * CA + ch * 8)
-                                      : *(const u32x4*)(B + vv * CB + (ch - CPA) * 8);
-          }
+          v.x = (unsigned)f2bf((float)Z[vv] * sc) | ((unsigned)f2bf(D[vv]) << 16);
         }
       }
       buf[k] = v;
@@ -497,108 +553,126 @@ __global__ void __launch_bounds__(512) k_conv_sweep(MfmaArgs p, int zc) {
     unsigned short* pl = ring + (size_t)slot * plane_elems;
 #pragma unroll
     for (int k = 0; k < NPF; ++k) {
-      const int q = threadIdx.x + k * nthr;
-      if (q < plane_items) {
-        const int vt = q / CPV, ch = q - vt * CPV;
-        if (IN) *(unsigned*)(pl + (size_t)vt * CLP) = buf[k].x;
-        else *(u32x4*)(pl + (size_t)vt * CLP + ch * 8) = buf[k];
-      }
+      const int it = threadIdx.x + k * nthr;
+      if (it < plane_items) *(unsigned*)(pl + (size_t)it * CLP) = buf[k].x;
     }
   };
-  // M-block geometry inside a plane
-  const int XB = (n - 1) >> 4;
-  int tb[MB];
-  bool vrow[MB];
-  int64_t vrowbase[MB];
+  // weights [16 cout][3 ty][KCT * 32], lane (g, r) holds cout r, k = c * 32 + g * 8 ..
+  bf16x8 wr[3][KCT];
+  {
+    const unsigned short* wsrc = (const unsigned short*)p.wrows;
 #pragma unroll
-  for (int m = 0; m < MB; ++m) {
-    const int mb = wave * MB + m;
-    const int row = mb / XB, xq = mb - row * XB;
-    const int xl = xq * 16 + r;
-    tb[m] = row * XW + xl;  // tap (0, 0) position inside a ring plane
-    vrow[m] = y0 + row < n;
-    vrowbase[m] = (int64_t)(y0 + row) * n + xl;
+    for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+      for (int c = 0; c < KCT; ++c)
+        wr[ty][c] = __builtin_bit_cast(bf16x8, *(const u32x4*)(wsrc + (r * 3 + ty) * (KCT * 32) + c * 32 + g * 8));
   }
-  // prologue: planes z0-1 and z0 into the ring, z0+1 into registers
+  // per-lane tap decomposition of each chunk
+  int lofs[KCT], ltz[KCT];
+  bool lok[KCT];
+#pragma unroll
+  for (int c = 0; c < KCT; ++c) {
+    if (IN) {
+      ltz[c] = g;
+      lok[c] = g < 3;
+      lofs[c] = 0;
+    } else {
+      const int k = c * 32 + g * 8;
+      const int pp = k / CIN, ci = k - pp * CIN;
+      lok[c] = pp < 9;
+      ltz[c] = lok[c] ? pp / 3 : 0;
+      lofs[c] = (lok[c] ? pp % 3 : 0) * CLP + ci;
+    }
+  }
+  const int xl = wave * 16 + r;
   u32x4 pf[NPF];
-  load_plane(z0 - 1, pf);
-  store_plane(0, pf);
-  load_plane(z0, pf);
-  store_plane(1, pf);
-  load_plane(z0 + 1, pf);
-  __syncthreads();
-  const unsigned short* wsrc = (const unsigned short*)p.w;
-  for (int z = z0; z < zend; ++z) {
-    // ring slots: plane z-1 -> (z - z0) % 3, z -> +1, z+1 -> +2 (written below)
-    const int s0 = (z - z0) % 3;
-    store_plane((s0 + 2) % 3, pf);
+  if (IN) {
+    load_plane(z0 - 1, pf);
+    store_plane(0, pf);
+    load_plane(z0, pf);
+    store_plane(1, pf);
+    load_plane(z0 + 1, pf);
+  } else {
+    dma_plane(z0 - 1, 0);
+    dma_plane(z0, 1);
+    dma_plane(z0 + 1, 2);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    if (z + 2 < zend + 1) load_plane(z + 2, pf);
-    f32x4 acc[MB][NB];
+  }
+  for (int z = z0; z < zend; ++z) {
+    // ring slots: plane z - 1 at s0, z at s0 + 1, z + 1 at s0 + 2 (mod NR)
+    const int s0 = (z - z0) % NR;
+    if (IN) {
+      store_plane((s0 + 2) % NR, pf);
+      __syncthreads();
+      if (z + 1 < zend) load_plane(z + 2, pf);
+    } else {
+      if (z + 1 < zend) dma_plane(z + 2, (s0 + 3) % NR);
+    }
+    f32x4 acc[MB];
 #pragma unroll
-    for (int m = 0; m < MB; ++m)
+    for (int m = 0; m < MB; ++m) acc[m] = {0.f, 0.f, 0.f, 0.f};
+    // software pipeline over the K chunks: the MB + 2 fragments of chunk c + 1
+    // are in flight while the MFMAs of chunk c run
+    auto fetch = [&](int c, bf16x8 (&xf)[MB + 2]) {
+      const unsigned short* base =
+          ring + (size_t)((s0 + ltz[c]) % NR) * plane_elems + (size_t)xl * CLP + lofs[c];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[m][nb] = {0.f, 0.f, 0.f, 0.f};
-    auto fetch = [&](int c, bf16x8 (&wf)[NB], bf16x8 (&xf)[MB]) {
-      const int k0 = c * 32 + g * 8;
-      const int tap = k0 / CIN;
-      const int ci = k0 - tap * CIN;
-      const bool tap_ok = tap < 27;
-      const int tz = tap / 9, ty = (tap / 3) % 3, tx = tap % 3;
-      const unsigned short* pl = ring + (size_t)((s0 + tz) % 3) * plane_elems;
-      const int toff = ty * XW + tx;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        wf[nb] = tap_ok ? __builtin_bit_cast(bf16x8, *(const u32x4*)(wsrc + ((nb * 16 + r) * 27 + tap) * CIN + ci))
-                        : zero8();
-#pragma unroll
-      for (int m = 0; m < MB; ++m) {
-        if (!tap_ok) {
-          xf[m] = zero8();
-        } else if (IN) {
-          u32x4 v = {*(const unsigned*)(pl + (size_t)(tb[m] + toff) * CLP), 0u, 0u, 0u};
-          xf[m] = __builtin_bit_cast(bf16x8, v);
+      for (int j = 0; j < MB + 2; ++j) {
+        if (IN) {
+          const unsigned short* pj = base + (size_t)j * XW * CLP;
+          u32x4 v = {0u, 0u, 0u, 0u};
+          if (lok[c]) {
+            v.x = *(const unsigned*)(pj);
+            v.y = *(const unsigned*)(pj + CLP);
+            v.z = *(const unsigned*)(pj + 2 * CLP);
+          }
+          xf[j] = __builtin_bit_cast(bf16x8, v);
         } else {
-          xf[m] = __builtin_bit_cast(bf16x8, *(const u32x4*)(pl + (size_t)(tb[m] + toff) * CLP + ci));
+          xf[j] = lok[c] ? __builtin_bit_cast(bf16x8, *(const u32x4*)(base + (size_t)j * XW * CLP)) : zero8();
         }
       }
     };
-    auto mma = [&](const bf16x8 (&wf)[NB], const bf16x8 (&xf)[MB]) {
+    auto mma = [&](int c, const bf16x8 (&xf)[MB + 2]) {
 #pragma unroll
-      for (int m = 0; m < MB; ++m)
+      for (int j = 0; j < MB + 2; ++j)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[nb], xf[m], acc[m][nb], 0, 0, 0);
+        for (int ty = 0; ty < 3; ++ty) {
+          const int m = j - ty;
+          if (m >= 0 && m < MB) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[ty][c], xf[j], acc[m], 0, 0, 0);
+        }
     };
-    bf16x8 wA[NB], xA[MB], wB[NB], xB[MB];
-    fetch(0, wA, xA);
+    bf16x8 xa[MB + 2], xb[MB + 2];
+    fetch(0, xa);
 #pragma unroll
-    for (int c = 0; c < KCH; c += 2) {
-      if (c + 1 < KCH) fetch(c + 1, wB, xB);
-      mma(wA, xA);
-      if (c + 2 < KCH) fetch(c + 2, wA, xA);
-      if (c + 1 < KCH) mma(wB, xB);
+    for (int c = 0; c < KCT; c += 2) {
+      if (c + 1 < KCT) fetch(c + 1, xb);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(c, xa);
+      __builtin_amdgcn_sched_barrier(0);
+      if (c + 2 < KCT) fetch(c + 2, xa);
+      __builtin_amdgcn_sched_barrier(0);
+      if (c + 1 < KCT) mma(c + 1, xb);
+      __builtin_amdgcn_sched_barrier(0);
     }
     // epilogue for plane z
     if (EPI == 0) {
-      bf16* Y = p.y + (int64_t)bt * nv * COUT;
+      bf16* Y = p.y + (int64_t)bt * nv * 16;
+      const int co = g * 4;
 #pragma unroll
       for (int m = 0; m < MB; ++m) {
-        if (!vrow[m]) continue;
-        const int64_t v = (int64_t)z * n * n + vrowbase[m];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int co = nb * 16 + g * 4;
-          float y0v = acc[m][nb][0] + p.bias[co], y1v = acc[m][nb][1] + p.bias[co + 1];
-          float y2v = acc[m][nb][2] + p.bias[co + 2], y3v = acc[m][nb][3] + p.bias[co + 3];
-          if (p.relu) {
-            y0v = fmaxf(y0v, 0.f); y1v = fmaxf(y1v, 0.f); y2v = fmaxf(y2v, 0.f); y3v = fmaxf(y3v, 0.f);
-          }
-          uint2 pk;
-          pk.x = (unsigned)f2bf(y0v) | ((unsigned)f2bf(y1v) << 16);
-          pk.y = (unsigned)f2bf(y2v) | ((unsigned)f2bf(y3v) << 16);
-          *(uint2*)(Y + v * COUT + co) = pk;
+        const int y = y0 + m;
+        if (y >= q.yhi) continue;
+        const int64_t v = ((int64_t)z * n + y) * n + xl;
+        float y0v = acc[m][0] + p.bias[co], y1v = acc[m][1] + p.bias[co + 1];
+        float y2v = acc[m][2] + p.bias[co + 2], y3v = acc[m][3] + p.bias[co + 3];
+        if (p.relu) {
+          y0v = fmaxf(y0v, 0.f); y1v = fmaxf(y1v, 0.f); y2v = fmaxf(y2v, 0.f); y3v = fmaxf(y3v, 0.f);
         }
+        uint2 pk;
+        pk.x = (unsigned)f2bf(y0v) | ((unsigned)f2bf(y1v) << 16);
+        pk.y = (unsigned)f2bf(y2v) | ((unsigned)f2bf(y3v) << 16);
+        *(uint2*)(Y + v * 16 + co) = pk;
       }
     } else {
       const double a = p.alpha_override > 0.0 ? p.alpha_override : p.alpha[bt];
@@ -610,21 +684,270 @@ __global__ void __launch_bounds__(512) k_conv_sweep(MfmaArgs p, int zc) {
         float h = 0.f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float yj = __bfloat162float(__float2bfloat16(fmaxf(acc[m][0][j] + p.bias[co + j], 0.f)));
+          const float yj = __bfloat162float(__float2bfloat16(fmaxf(acc[m][j] + p.bias[co + j], 0.f)));
           h = fmaf(p.wh[co + j], yj, h);
         }
         h += __shfl_xor(h, 16, 64);
         h += __shfl_xor(h, 32, 64);
-        if (g == 0 && vrow[m]) {
-          const int64_t v = (int64_t)z * n * n + vrowbase[m];
-          const int ox = (int)(v % n), oy = (int)((v / n) % n);
-          const bool bnd = ox == 0 || oy == 0 || z == 0 || ox == n - 1 || oy == n - 1 || z == n - 1;
-          if (!bnd) zo[v] = (Tv)(f * (h + p.bh[0]));
+        const int y = y0 + m;
+        // Dirichlet nodes keep the value set before the network runs
+        if (g == 0 && y < q.yhi && y > 0 && y < n - 1 && xl > 0 && z > 0 && z < n - 1)
+          zo[((int64_t)z * n + y) * n + xl] = (Tv)(f * (h + p.bh[0]));
+      }
+    }
+    if (!IN) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  }
+}
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
+// and meets the other waves, without the wait for outstanding global memory
+// operations that __syncthreads() implies (the ring loads in flight).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Two-waves-per-SIMD form of the 16-channel stride-1 layer for stored inputs:
+// 2 XB waves per workgroup.  Waves w and w + XB share x block w and either
+// split the output rows (KS = 0: rows [0, MB) and [MB, 2 MB) of the tile) or
+// the K chunks (KS = 1: the upper wave runs chunks [0, KH), the lower one
+// [KH, KCT) and the epilogue, the partial sums crossing over through a
+// double-buffered LDS area).  The ring holds five planes and the loads run
+// two planes ahead: plane z + 3 is requested while plane z is computed and the
+// end-of-plane wait lets that newest batch stay in flight (vector memory
+// operations of a wave complete in issue order).  Every wave issues exactly
+// NLW ring loads per plane (surplus lanes and loads fetch the zero block), and
+// their source offsets are computed once.
+template <int CA, int CB, int MB, int KS, int EPI, typename Tv, int NLW>
+__global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
+  constexpr int CIN = CA + CB;
+  typedef RowsTile<CIN, 0> T;
+  constexpr int CLP = T::CLP;
+  constexpr int KCT = RowsK<CIN, 0>::KCT;
+  constexpr int KH = KS ? (KCT + 1) / 2 : KCT;   // chunk slots per wave
+  constexpr int TYR = KS ? MB : 2 * MB;          // output rows per workgroup
+  constexpr int YW = TYR + 2;
+  constexpr int NR = 5;
+  constexpr int CPA = CA / 8;
+  static_assert(NLW <= 4, "the end-of-plane wait covers at most 4 loads");
+  extern __shared__ __attribute__((aligned(1024))) unsigned short ring[];
+  int bxr, bt;
+  xcd_remap(bxr, bt);
+  if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
+  const int n = p.n_out;
+  const int XW = n + 1;
+  const int y0 = q.ylo + (bxr % q.ytiles) * TYR;
+  const int z0 = q.zlo + (bxr / q.ytiles) * q.zc;
+  const int zend = min(q.zhi, z0 + q.zc);
+  const int64_t nn = (int64_t)n * n, nv = nn * n;
+  const int nwaves = blockDim.x >> 6, xbn = nwaves >> 1;
+  const int plane_elems = (int)(T::plane_bytes(TYR, n) / 2);
+  const int plane_items = YW * XW * T::SLOTS;
+  const int nload = (plane_items + 63) >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int g = lane >> 4, r = lane & 15;
+  const int upper = wave >= xbn, xq = upper ? wave - xbn : wave;
+  const int rb0 = KS ? 0 : upper * MB;           // first tile row of this wave's outputs
+  // LDS after the ring: partial sums [2][xbn][MB][64] x float4 (KS)
+  float* red = (float*)(ring + (size_t)NR * plane_elems);
+  // ring loads of this wave per plane (wave-uniform, at most NLW)
+  const int nlw = min(NLW, (nload - wave + nwaves - 1) / nwaves);
+  // wait until at most nlw vector memory operations of this wave are outstanding
+  auto wait_vm_newest = [&]() {
+    switch (nlw) {
+      case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+      case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+      case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+      case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
+      default: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    }
+  };
+  const bf16* A = p.a + (int64_t)bt * nv * CA;
+  const bf16* B = CB ? p.b + (int64_t)bt * nv * CB : nullptr;
+  // ring-load sources: byte offset from A (or to the zero block) and bytes per plane (0 for zero slots)
+  const char* Ab = (const char*)A;
+  const int64_t zero_off = (const char*)p.zero16 - Ab;
+  const int64_t b_off = CB ? (const char*)B - Ab : 0;
+  int64_t doff[NLW];
+  int dstr[NLW];
+#pragma unroll
+  for (int k = 0; k < NLW; ++k) {
+    const int L = wave + k * nwaves;
+    const int it = L * 64 + lane;
+    int64_t o = zero_off;
+    int st = 0;
+    if (L < nload && it < plane_items) {
+      const int vt = it / T::SLOTS, ch = it - vt * T::SLOTS;
+      const int row = vt / XW, xx = vt - row * XW;
+      const int gx = xx - 1, gy = y0 + row - 1;
+      if (ch < T::CPV && gy >= 0 && gy < n && gx >= 0) {
+        const int64_t vv = (int64_t)gy * n + gx;
+        if (CB == 0 || ch < CPA) {
+          o = (vv * CA + ch * 8) * 2;
+          st = (int)(nn * CA * 2);
+        } else {
+          o = b_off + (vv * CB + (ch - CPA) * 8) * 2;
+          st = (int)(nn * CB * 2);
         }
       }
     }
-    __syncthreads();
+    doff[k] = o;
+    dstr[k] = st;
   }
+  auto dma_plane = [&](int gz, int slot) {
+    unsigned short* pl = ring + (size_t)slot * plane_elems;
+    const bool zok = gz >= 0 && gz < n;
+#pragma unroll
+    for (int k = 0; k < NLW; ++k) {
+      const int L = wave + k * nwaves;
+      if (L < nload) {
+        const int64_t o = zok ? doff[k] + (int64_t)gz * dstr[k] : zero_off;
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)(Ab + o), (lds_void_t*)(pl + L * 512), 16, 0, 0);
+      }
+    }
+  };
+  // this wave's K chunks: all (KS = 0); upper [0, KH), lower [KH, KCT) (KS = 1)
+  const int cb = (KS && !upper) ? KH : 0;
+  bf16x8 wr[3][KH];
+  int lofs[KH], ltz[KH];
+  bool lok[KH];
+  {
+    const unsigned short* wsrc = (const unsigned short*)p.wrows;
+#pragma unroll
+    for (int i = 0; i < KH; ++i) {
+      const int c = cb + i;
+      const bool cin = c < KCT;
+#pragma unroll
+      for (int ty = 0; ty < 3; ++ty)
+        wr[ty][i] = cin ? __builtin_bit_cast(bf16x8, *(const u32x4*)(wsrc + (r * 3 + ty) * (KCT * 32) + c * 32 + g * 8))
+                        : zero8();
+      const int k = c * 32 + g * 8;
+      const int pp = k / CIN, ci = k - pp * CIN;
+      lok[i] = cin && pp < 9;
+      ltz[i] = lok[i] ? pp / 3 : 0;
+      lofs[i] = (lok[i] ? pp % 3 : 0) * CLP + ci;
+    }
+  }
+  const int xl = xq * 16 + r;
+  // epilogue parameters, loaded before the sweep so that no load of the
+  // epilogue has to wait behind the ring loads in flight
+  const int co = g * 4;
+  float bia[4], whv[4] = {0.f, 0.f, 0.f, 0.f}, bhv = 0.f, fsc = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bia[j] = p.bias[co + j];
+  if (EPI) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) whv[j] = p.wh[co + j];
+    bhv = p.bh[0];
+    const double a = p.alpha_override > 0.0 ? p.alpha_override : p.alpha[bt];
+    fsc = (float)(p.scale[bt] / a);
+  }
+  bf16* Y = EPI ? nullptr : p.y + (int64_t)bt * nv * 16;
+  Tv* zo = EPI ? (Tv*)p.zout + p.off[bt] : nullptr;
+  const int relu = p.relu;
+  dma_plane(z0 - 1, 0);
+  dma_plane(z0, 1);
+  dma_plane(z0 + 1, 2);
+  dma_plane(z0 + 2, 3);
+  wait_vm_newest();
+  lds_barrier();
+  for (int z = z0; z < zend; ++z) {
+    const int s0 = (z - z0) % NR;
+    const int par = (z - z0) & 1;
+    // plane z + 3 into the slot of plane z - 2 (read before the previous barrier)
+    dma_plane(z + 3, (s0 + 4) % NR);
+    f32x4 acc[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) acc[m] = {0.f, 0.f, 0.f, 0.f};
+    auto fetch = [&](int i, bf16x8 (&xf)[MB + 2]) {
+      const unsigned short* base = ring + (size_t)((s0 + ltz[i]) % NR) * plane_elems +
+                                   ((size_t)rb0 * XW + xl) * CLP + lofs[i];
+#pragma unroll
+      for (int j = 0; j < MB + 2; ++j)
+        xf[j] = lok[i] ? __builtin_bit_cast(bf16x8, *(const u32x4*)(base + (size_t)j * XW * CLP)) : zero8();
+    };
+    auto mma = [&](int i, const bf16x8 (&xf)[MB + 2]) {
+#pragma unroll
+      for (int j = 0; j < MB + 2; ++j)
+#pragma unroll
+        for (int ty = 0; ty < 3; ++ty) {
+          const int m = j - ty;
+          if (m >= 0 && m < MB) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[ty][i], xf[j], acc[m], 0, 0, 0);
+        }
+    };
+    auto run = [&](auto nchc) {
+      constexpr int NCH = decltype(nchc)::value;
+      bf16x8 xa[MB + 2], xb[MB + 2];
+      fetch(0, xa);
+#pragma unroll
+      for (int i = 0; i < NCH; i += 2) {
+        if (i + 1 < NCH) fetch(i + 1, xb);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(i, xa);
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + 2 < NCH) fetch(i + 2, xa);
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + 1 < NCH) mma(i + 1, xb);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+    if (!KS || upper) run(std::integral_constant<int, KH>{});
+    else run(std::integral_constant<int, KCT - KH>{});
+    f32x4* rbuf = (f32x4*)red + ((size_t)(par * xbn + xq) * MB) * 64 + lane;
+    if (KS && upper) {
+#pragma unroll
+      for (int m = 0; m < MB; ++m) rbuf[m * 64] = acc[m];
+    }
+    // plane z + 2 (and everything older) has landed; z + 3 may still be in flight
+    wait_vm_newest();
+    lds_barrier();
+    if (!KS || !upper) {
+      if (KS) {
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+          const f32x4 o = rbuf[m * 64];
+          acc[m] += o;
+        }
+      }
+      if (EPI == 0) {
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+          const int y = y0 + rb0 + m;
+          if (y >= q.yhi) continue;
+          const int64_t v = ((int64_t)z * n + y) * n + xl;
+          float y0v = acc[m][0] + bia[0], y1v = acc[m][1] + bia[1];
+          float y2v = acc[m][2] + bia[2], y3v = acc[m][3] + bia[3];
+          if (relu) {
+            y0v = fmaxf(y0v, 0.f); y1v = fmaxf(y1v, 0.f); y2v = fmaxf(y2v, 0.f); y3v = fmaxf(y3v, 0.f);
+          }
+          uint2 pk;
+          pk.x = (unsigned)f2bf(y0v) | ((unsigned)f2bf(y1v) << 16);
+          pk.y = (unsigned)f2bf(y2v) | ((unsigned)f2bf(y3v) << 16);
+          *(uint2*)(Y + v * 16 + co) = pk;
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+          float h = 0.f;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float yj = __bfloat162float(__float2bfloat16(fmaxf(acc[m][j] + bia[j], 0.f)));
+            h = fmaf(whv[j], yj, h);
+          }
+          h += __shfl_xor(h, 16, 64);
+          h += __shfl_xor(h, 32, 64);
+          const int y = y0 + rb0 + m;
+          // Dirichlet nodes keep the value set before the network runs
+          if (g == 0 && y < q.yhi && y > 0 && y < n - 1 && xl > 0 && z > 0 && z < n - 1)
+            zo[((int64_t)z * n + y) * n + xl] = (Tv)(fsc * (h + bhv));
+        }
+      }
+    }
+  }
+  // drain the loads still in flight before the workgroup's LDS is released
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
 // Stride-2 transposed convolution, one output parity class (px, py, pz) per
@@ -776,11 +1099,93 @@ void launch_s1(const MfmaArgs& a, int batch, hipStream_t stream) {
                      a);
 }
 
-template <int CA, int CB, int COUT, int STRIDE, int MB>
-void launch_conv(const ConvP& p, int batch, const bf16* w, hipStream_t stream) {
-  const int64_t nvo = (int64_t)p.n_out * p.n_out * p.n_out;
-  const int64_t nmb = (nvo + 15) / 16;
-  const dim3 grid((unsigned)((nmb + WAVES * MB - 1) / (WAVES * MB)), 1, batch);
+// Full-resolution 16-channel layers: the row-reuse sweep for x < n - 1 plus the
+// EDGE kernel for x = n - 1 (not needed with the head: that column is
+// Dirichlet).  Falls back to launch_s1 where the grid does not fit the sweep.
+template <int CA, int CB, int MB, int IN, int EPI, typename Tv, int NPF>
+void launch_rows16_npf(const MfmaArgs& a, const RowsGrid& q, int batch, size_t lds, int xb, hipStream_t stream) {
+  auto kern = k_conv16_rows<CA, CB, MB, IN, EPI, Tv, NPF>;
+  if (lds > 65536) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const int nz = (q.zhi - q.zlo + q.zc - 1) / q.zc;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(q.ytiles * nz), 1, batch), dim3(xb * 64), lds, stream, a, q);
+}
+
+template <int CA, int CB, int MB, int IN, int EPI, typename Tv, int NPF0, int NPF1>
+void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream) {
+  constexpr int CL = IN ? 2 : CA + CB;
+  typedef RowsTile<CL, IN> T;
+  const int n = a.n_out;
+  const int xb = (n - 1) / 16;
+  const size_t lds = (size_t)T::NRING * T::plane_bytes(MB, n);
+  const bool fits = (n - 1) % 16 == 0 && xb >= 1 && xb <= 4 && lds <= 160 * 1024 && (IN || a.zero16);
+  const int need = fits ? ((MB + 2) * (n + 1) * T::SLOTS + xb * 64 - 1) / (xb * 64) : 0;
+  if (!fits || (IN && need > NPF1)) {
+    launch_s1<IN ? 8 : CA, CB, 16, IN, EPI, Tv>(a, batch, stream);
+    return;
+  }
+  RowsGrid q;
+  q.ylo = q.zlo = EPI ? 1 : 0;
+  q.yhi = q.zhi = EPI ? n - 1 : n;
+  q.ytiles = (q.yhi - q.ylo + MB - 1) / MB;
+  const int planes = q.zhi - q.zlo;
+  // about four workgroups per compute unit over the batch
+  int nz = (1024 + q.ytiles * batch - 1) / (q.ytiles * batch);
+  nz = std::max(1, std::min(nz, planes));
+  q.zc = (planes + nz - 1) / nz;
+  if constexpr (!IN) {
+    launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, 1>(a, q, batch, lds, xb, stream);
+  } else {
+    if (need <= NPF0) launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF0>(a, q, batch, lds, xb, stream);
+    else launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF1>(a, q, batch, lds, xb, stream);
+  }
+  if (!EPI) {
+    constexpr int MBE = 4;
+    const int64_t nmb = ((int64_t)n * n + 15) / 16;
+    const dim3 grid((unsigned)((nmb + WAVES * MBE - 1) / (WAVES * MBE)), 1, batch);
+    hipLaunchKernelGGL((k_conv_mfma<IN ? 8 : CA, CB, 16, 1, MBE, IN, EPI, Tv, 1>), grid, dim3(WAVES * 64), 0, stream,
+                       a);
+  }
+}
+
+// Stored 16-channel layers: the two-waves-per-SIMD sweep for x < n - 1 plus
+// the EDGE kernel for x = n - 1 (not needed with the head: that column is
+// Dirichlet).
+template <int CA, int CB, int MB, int KS, int EPI, typename Tv>
+void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream) {
+  constexpr int NLW = 4;
+  constexpr int TYR = KS ? MB : 2 * MB;
+  typedef RowsTile<CA + CB, 0> T;
+  const int n = a.n_out;
+  const int xb = (n - 1) / 16;
+  const size_t lds = 5 * T::plane_bytes(TYR, n) + (KS ? (size_t)2 * xb * MB * 64 * 16 : 0);
+  const int nload = ((TYR + 2) * (n + 1) * T::SLOTS + 63) / 64;
+  const bool fits = (n - 1) % 16 == 0 && xb >= 1 && xb <= 4 && lds <= 160 * 1024 && a.zero16 &&
+                    nload <= NLW * 2 * xb;
+  if (!fits) {
+    launch_s1<CA, CB, 16, 0, EPI, Tv>(a, batch, stream);
+    return;
+  }
+  RowsGrid q;
+  q.ylo = q.zlo = EPI ? 1 : 0;
+  q.yhi = q.zhi = EPI ? n - 1 : n;
+  q.ytiles = (q.yhi - q.ylo + TYR - 1) / TYR;
+  const int planes = q.zhi - q.zlo;
+  int nz = (1024 + q.ytiles * batch - 1) / (q.ytiles * batch);
+  nz = std::max(1, std::min(nz, planes));
+  q.zc = (planes + nz - 1) / nz;
+  nz = (planes + q.zc - 1) / q.zc;
+  auto kern = k_conv16_ks<CA, CB, MB, KS, EPI, Tv, NLW>;
+  if (lds > 65536) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(q.ytiles * nz), 1, batch), dim3(2 * xb * 64), lds, stream, a, q);
+  if (!EPI) {
+    constexpr int MBE = 4;
+    const int64_t nmb = ((int64_t)n * n + 15) / 16;
+    const dim3 grid((unsigned)((nmb + WAVES * MBE - 1) / (WAVES * MBE)), 1, batch);
+    hipLaunchKernelGGL((k_conv_mfma<CA, CB, 16, 1, MBE, 0, EPI, Tv, 1>), grid, dim3(WAVES * 64), 0, stream, a);
+  }
+}
+
+MfmaArgs args_from(const ConvP& p, const bf16* w) {
   MfmaArgs a;
   a.a = (const bf16*)p.a;
   a.b = (const bf16*)p.b;
@@ -792,6 +1197,15 @@ void launch_conv(const ConvP& p, int batch, const bf16* w, hipStream_t stream) {
   a.relu = p.relu;
   a.st = p.st;
   a.want_mode = p.want_mode;
+  return a;
+}
+
+template <int CA, int CB, int COUT, int STRIDE, int MB>
+void launch_conv(const ConvP& p, int batch, const bf16* w, hipStream_t stream) {
+  const int64_t nvo = (int64_t)p.n_out * p.n_out * p.n_out;
+  const int64_t nmb = (nvo + 15) / 16;
+  const dim3 grid((unsigned)((nmb + WAVES * MB - 1) / (WAVES * MB)), 1, batch);
+  const MfmaArgs a = args_from(p, w);
   if (STRIDE == 1) {
     launch_s1<CA, CB, COUT, 0, 0, float>(a, batch, stream);
     return;
@@ -827,13 +1241,64 @@ static int64_t mfma_weight_count() {
   return tot;
 }
 
+// Row-reuse weight layout [16][3 ty][KCT * 32] of a 16-channel stride-1 layer.
+// IN = 1 (two input channels): k = 8 tz + 2 tx + ch for tz < 3, else zero.
+// Otherwise k = (3 tz + tx) * CIN + ci, zero from 9 CIN on.
+template <int CIN, int IN>
+__global__ void k_w_rows(const float* __restrict__ w, bf16* __restrict__ o) {
+  constexpr int KCT = RowsK<CIN, IN>::KCT;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 16 * 3 * KCT * 32) return;
+  const int kk = k % (KCT * 32), ty = (k / (KCT * 32)) % 3, co = k / (3 * KCT * 32);
+  float v = 0.0f;
+  if (IN) {
+    const int tz = kk / 8, e = kk % 8, tx = e / 2, ch = e % 2;
+    if (tz < 3 && tx < 3) v = w[(co * 27 + tz * 9 + ty * 3 + tx) * 2 + ch];
+  } else {
+    const int pp = kk / CIN, ci = kk % CIN;
+    if (pp < 9) v = w[(co * 27 + (pp / 3) * 9 + ty * 3 + pp % 3) * CIN + ci];
+  }
+  o[k] = __float2bfloat16(v);
+}
+
+constexpr int64_t kIn8Count = 16 * 27 * 8;
+constexpr int64_t kRowsIn0 = 16 * 3 * RowsK<2, 1>::KCT * 32;
+constexpr int64_t kRowsL0b = 16 * 3 * RowsK<16, 0>::KCT * 32;
+constexpr int64_t kRowsD0 = 16 * 3 * RowsK<32, 0>::KCT * 32;
+
+constexpr int64_t kZeroCount = 128;  // 256 zero bytes
+
+struct MfmaWeights {
+  const bf16* in8;
+  const bf16* rows_in0;
+  const bf16* rows_l0b;
+  const bf16* rows_d0;
+  const bf16* zeros;
+};
+
+static MfmaWeights mfma_extra(const CnnState& c) {
+  const bf16* e = c.wmf + mfma_weight_count();
+  const bf16* r0 = e + kIn8Count;
+  return {e, r0, r0 + kRowsIn0, r0 + kRowsIn0 + kRowsL0b, r0 + kRowsIn0 + kRowsL0b + kRowsD0};
+}
+
 void cnn_prepare_mfma_weights(CnnState& c, const float* d_w, hipStream_t stream) {
   const int64_t tot = mfma_weight_count();
-  if (!c.wmf && hipMalloc(&c.wmf, sizeof(bf16) * (size_t)(tot + 16 * 27 * 8)) != hipSuccess) {
+  const int64_t extra = kIn8Count + kRowsIn0 + kRowsL0b + kRowsD0 + kZeroCount;
+  if (!c.wmf && hipMalloc(&c.wmf, sizeof(bf16) * (size_t)(tot + extra)) != hipSuccess) {
     c.wmf = nullptr;
     return;
   }
-  hipLaunchKernelGGL(k_w_in8, dim3((16 * 27 * 8 + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[0], c.wmf + tot);
+  const MfmaWeights x = mfma_extra(c);
+  (void)hipMemsetAsync((void*)x.zeros, 0, sizeof(bf16) * kZeroCount, stream);
+  hipLaunchKernelGGL(k_w_in8, dim3((kIn8Count + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[0],
+                     (bf16*)x.in8);
+  hipLaunchKernelGGL((k_w_rows<2, 1>), dim3((kRowsIn0 + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[0],
+                     (bf16*)x.rows_in0);
+  hipLaunchKernelGGL((k_w_rows<16, 0>), dim3((kRowsL0b + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[1],
+                     (bf16*)x.rows_l0b);
+  hipLaunchKernelGGL((k_w_rows<32, 0>), dim3((kRowsD0 + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[9],
+                     (bf16*)x.rows_d0);
   for (int l = 0; l < kNumLayers; ++l) {
     const LayerSpec& L = kLayers[l];
     const int64_t nw = (int64_t)L.cout * (L.kind == KIND_PT ? 1 : 27) * L.cin;
@@ -851,7 +1316,8 @@ void conv_mfma_in0(const CnnState& c, const Tv* z, const int64_t* off, const dou
   const int64_t nvo = (int64_t)n * n * n;
   const int64_t nmb = (nvo + 15) / 16;
   MfmaArgs a;
-  a.w = c.wmf + mfma_weight_count();
+  a.w = mfma_extra(c).in8;
+  a.wrows = mfma_extra(c).rows_in0;
   a.bias = c.w + c.b_off[0];
   a.y = a0;
   a.n_in = n;
@@ -863,7 +1329,7 @@ void conv_mfma_in0(const CnnState& c, const Tv* z, const int64_t* off, const dou
   a.inv_s = inv_s;
   a.dist = dist;
   (void)nmb;
-  launch_s1<8, 0, 16, 1, 0, Tv>(a, batch, stream);
+  launch_rows16<0, 0, 5, 1, 0, Tv, 2, 4>(a, batch, stream);
 }
 template void conv_mfma_in0<float>(const CnnState&, const float*, const int64_t*, const double*, const float*, int,
                                    int, bf16*, const InstState*, hipStream_t);
@@ -881,6 +1347,8 @@ void conv_mfma_d0_head(const CnnState& c, const bf16* u0, const bf16* s0, int n,
   a.a = u0;
   a.b = s0;
   a.w = c.wmf + c.wt_off[9];
+  a.wrows = mfma_extra(c).rows_d0;
+  a.zero16 = mfma_extra(c).zeros;
   a.bias = c.w + c.b_off[9];
   a.n_in = n;
   a.n_out = n;
@@ -894,7 +1362,7 @@ void conv_mfma_d0_head(const CnnState& c, const bf16* u0, const bf16* s0, int n,
   a.alpha_override = alpha_override;
   a.scale = scale;
   (void)nmb;
-  launch_s1<16, 16, 16, 0, 1, Tv>(a, batch, stream);
+  launch_ks16<16, 16, 4, 1, 1, Tv>(a, batch, stream);
 }
 template void conv_mfma_d0_head<float>(const CnnState&, const bf16*, const bf16*, int, int, float*, const int64_t*,
                                        const double*, double, const double*, const InstState*, hipStream_t);
@@ -907,7 +1375,13 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
   const bf16* w = c.wmf + c.wt_off[layer];
   (void)kind;
   switch (layer) {
-    case 1: launch_conv<16, 0, 16, 1, 4>(p, batch, w, stream); break;    // L0b
+    case 1: {                                                             // L0b
+      MfmaArgs a = args_from(p, w);
+      a.wrows = mfma_extra(c).rows_l0b;
+      a.zero16 = mfma_extra(c).zeros;
+      launch_ks16<16, 0, 4, 0, 0, float>(a, batch, stream);
+      break;
+    }
     case 2: launch_conv<16, 0, 32, 2, 4>(p, batch, w, stream); break;    // L1a
     case 3: launch_conv<32, 0, 32, 1, 4>(p, batch, w, stream); break;    // L1b
     case 4: launch_conv<32, 0, 64, 2, 2>(p, batch, w, stream); break;    // L2a
@@ -915,7 +1389,13 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
     case 6: launch_tconv<64, 32, 4>(p, batch, w, stream); break;         // U1
     case 7: launch_conv<32, 32, 32, 1, 4>(p, batch, w, stream); break;   // D1
     case 8: launch_tconv<32, 16, 4>(p, batch, w, stream); break;         // U0
-    case 9: launch_conv<16, 16, 16, 1, 4>(p, batch, w, stream); break;   // D0
+    case 9: {                                                             // D0
+      MfmaArgs a = args_from(p, w);
+      a.wrows = mfma_extra(c).rows_d0;
+      a.zero16 = mfma_extra(c).zeros;
+      launch_ks16<16, 16, 4, 1, 0, float>(a, batch, stream);
+      break;
+    }
     default: break;
   }
 }
