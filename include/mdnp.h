@@ -261,7 +261,9 @@ mdnp_status mdnp_host_sizes(const mdnp_host_sys* hs, int32_t* n3d, int32_t* n1d,
 mdnp_status mdnp_host_export(const mdnp_host_sys* hs, int32_t* row_ptr, int32_t* col, double* val,
                              double* F, float* dist, double* alpha);
 /* z1 = A11^-1 v1 on the host with the factorisation used by the GPU 1D solve
- * (v1, z1 of length n1d). */
+ * (v1, z1 of length n1d): the chain-compressed form (segment interiors as
+ * tridiagonal blocks, then the vertex Schur complement) when every segment has
+ * at most 32 interior nodes, else the leaves-first LDL^T of the whole tree. */
 mdnp_status mdnp_host_tree_solve(const mdnp_host_sys* hs, const double* v1, double* z1);
 void mdnp_host_free(mdnp_host_sys* hs);
 

@@ -411,6 +411,110 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
     std::vector<int32_t> fill(T.lvl_ptr.begin(), T.lvl_ptr.end() - 1);
     for (int c = 0; c < n1d; ++c) T.lvl_nodes[fill[level[c]]++] = c;
   }
+
+  // chain-compressed factorisation (same matrix, elimination grouped by segment)
+  ChainFactor& C = H.chain;
+  const int m = E - 1;
+  C.m = m;
+  C.fmul.assign((size_t)std::max(m - 1, 0) * S, 0.0);
+  C.eup.assign((size_t)std::max(m - 1, 0) * S, 0.0);
+  C.pinv.assign((size_t)m * S, 0.0);
+  C.gp.assign((size_t)m * S, 0.0);
+  C.gq.assign((size_t)m * S, 0.0);
+  C.ap.assign(S, 0.0);
+  C.aq.assign(S, 0.0);
+  C.sp.assign(S, 0);
+  C.sq.assign(S, 0);
+  C.vseg.assign(V, -1);
+  std::vector<double> vdiag(V), voff(V, 0.0);  // Schur complement: diagonal, entry to the parent vertex
+  for (int v = 0; v < V; ++v) vdiag[v] = a11(v, v);
+  std::vector<double> dd(std::max(m, 1)), ee(std::max(m, 1)), piv2(std::max(m, 1)), w(std::max(m, 1));
+  auto chain_solve = [&](int s, std::vector<double>& rhs) {  // rhs <- T_s^-1 rhs
+    for (int i = m - 2; i >= 0; --i) rhs[i] -= C.fmul[(size_t)i * S + s] * rhs[i + 1];
+    rhs[0] *= C.pinv[s];
+    for (int i = 1; i < m; ++i) rhs[i] = (rhs[i] - ee[i - 1] * rhs[i - 1]) * C.pinv[(size_t)i * S + s];
+  };
+  for (int s = 0; s < S; ++s) {
+    const int p = d.seg_vertices[2 * s], q = d.seg_vertices[2 * s + 1];
+    C.sp[s] = p;
+    C.sq[s] = q;
+    C.vseg[q] = s;
+    if (m == 0) {
+      voff[q] = a11(p, q);
+      continue;
+    }
+    const int c0 = V + s * m;
+    for (int i = 0; i < m; ++i) dd[i] = a11(c0 + i, c0 + i);
+    for (int i = 0; i + 1 < m; ++i) ee[i] = a11(c0 + i, c0 + i + 1);
+    piv2[m - 1] = dd[m - 1];
+    for (int i = m - 2; i >= 0; --i) piv2[i] = dd[i] - ee[i] * ee[i] / piv2[i + 1];
+    for (int i = 0; i < m; ++i) {
+      if (!(piv2[i] > 0.0)) return "1D block is not positive definite (check R, beta and k_lambda)";
+      C.pinv[(size_t)i * S + s] = 1.0 / piv2[i];
+    }
+    for (int i = 0; i + 1 < m; ++i) {
+      C.fmul[(size_t)i * S + s] = ee[i] / piv2[i + 1];
+      C.eup[(size_t)i * S + s] = ee[i];
+    }
+    C.ap[s] = a11(p, c0);
+    C.aq[s] = a11(q, c0 + m - 1);
+    std::fill(w.begin(), w.end(), 0.0);
+    w[0] = C.ap[s];
+    chain_solve(s, w);
+    for (int i = 0; i < m; ++i) C.gp[(size_t)i * S + s] = w[i];
+    const double gp0 = w[0];
+    std::fill(w.begin(), w.end(), 0.0);
+    w[m - 1] = C.aq[s];
+    chain_solve(s, w);
+    for (int i = 0; i < m; ++i) C.gq[(size_t)i * S + s] = w[i];
+    vdiag[p] -= C.ap[s] * gp0;
+    vdiag[q] -= C.aq[s] * w[m - 1];
+    voff[q] = -C.ap[s] * w[0];
+  }
+  // vertex tree (parent of q = p of its segment), leaves-first LDL^T by BFS from vertex 0
+  C.vparent.assign(V, -1);
+  for (int s = 0; s < S; ++s) C.vparent[C.sq[s]] = C.sp[s];
+  std::vector<std::vector<int32_t>> vkids(V);
+  for (int v = 0; v < V; ++v)
+    if (C.vparent[v] >= 0) vkids[C.vparent[v]].push_back(v);
+  std::vector<int32_t> vbfs;
+  vbfs.reserve(V);
+  vbfs.push_back(0);
+  for (size_t k = 0; k < vbfs.size(); ++k)
+    for (int c : vkids[vbfs[k]]) vbfs.push_back(c);
+  if ((int)vbfs.size() != V) return "internal error: vertex graph is not a tree";
+  std::vector<double> vpiv(V);
+  std::vector<int32_t> vlevel(V, 0);
+  C.vlval.assign(V, 0.0);
+  C.vdinv.assign(V, 0.0);
+  for (int k = V - 1; k >= 0; --k) {
+    const int v = vbfs[k];
+    double dv = vdiag[v];
+    int lv = 0;
+    for (int u : vkids[v]) {
+      dv -= voff[u] * voff[u] / vpiv[u];
+      lv = std::max(lv, vlevel[u] + 1);
+    }
+    if (!(dv > 0.0)) return "1D block is not positive definite (check R, beta and k_lambda)";
+    vpiv[v] = dv;
+    vlevel[v] = lv;
+    C.vdinv[v] = 1.0 / dv;
+    if (C.vparent[v] >= 0) C.vlval[v] = voff[v] / dv;
+  }
+  C.vchild_ptr.assign(V + 1, 0);
+  for (int v = 0; v < V; ++v) C.vchild_ptr[v + 1] = C.vchild_ptr[v] + (int32_t)vkids[v].size();
+  C.vchild_idx.clear();
+  for (int v = 0; v < V; ++v) for (int u : vkids[v]) C.vchild_idx.push_back(u);
+  int vnlev = 0;
+  for (int v = 0; v < V; ++v) vnlev = std::max(vnlev, vlevel[v] + 1);
+  C.vlvl_ptr.assign(vnlev + 1, 0);
+  for (int v = 0; v < V; ++v) ++C.vlvl_ptr[vlevel[v] + 1];
+  for (int l = 0; l < vnlev; ++l) C.vlvl_ptr[l + 1] += C.vlvl_ptr[l];
+  C.vlvl_nodes.assign(V, 0);
+  {
+    std::vector<int32_t> fill(C.vlvl_ptr.begin(), C.vlvl_ptr.end() - 1);
+    for (int v = 0; v < V; ++v) C.vlvl_nodes[fill[vlevel[v]]++] = v;
+  }
   return std::string();
 }
 

@@ -21,6 +21,25 @@ struct TreeFactor {
   std::vector<int32_t> lvl_nodes;
 };
 
+struct ChainFactor {
+  // Chain-compressed solve of A11: the m = E - 1 interior nodes of every
+  // segment form a tridiagonal block T_s between the segment's parent-side
+  // vertex p and child vertex q.  Per segment: y = T_s^-1 v_c; the vertices
+  // solve the Schur complement (a tree over the vertices, edges = segments)
+  // with right-hand side v_v - (couplings) y; then z_c = y - g_p z_p - g_q z_q.
+  // Per-step arrays are laid out [step][segment].
+  int m = 0;                        // interior nodes per segment
+  std::vector<double> fmul;         // [m - 1][S]: w_i = v_i - fmul_i w_{i+1}
+  std::vector<double> pinv;         // [m][S]: 1 / pivot_i (elimination from the q end)
+  std::vector<double> eup;          // [m - 1][S]: T[i, i + 1] (back substitution towards q)
+  std::vector<double> gp, gq;       // [m][S]: T^-1 (a_p e_0), T^-1 (a_q e_{m-1})
+  std::vector<double> ap, aq;       // [S]: A[p, c_0], A[q, c_{m-1}]
+  std::vector<int32_t> sp, sq;      // [S]: parent-side and child vertex
+  // leaves-first LDL^T of the vertex Schur complement
+  std::vector<int32_t> vparent, vseg, vchild_ptr, vchild_idx, vlvl_ptr, vlvl_nodes;
+  std::vector<double> vlval, vdinv;
+};
+
 struct HostInstance {
   int n_cells = 0, n = 0, n3d = 0, n1d = 0;
   std::vector<int32_t> row_ptr, col;   // CSR of A, local indices, sorted columns
@@ -38,6 +57,7 @@ struct HostInstance {
   std::vector<double> diag;            // diag(A)
   double alpha = 0.0;                  // RMS of diag(A00) over the free 3D nodes
   TreeFactor tree;
+  ChainFactor chain;
 };
 
 // Validates and assembles; returns an empty string on success or an error message.

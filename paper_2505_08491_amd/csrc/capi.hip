@@ -124,6 +124,12 @@ void free_sys(mdnp_sys* s) {
                   s->d_alpha, s->d_t_off, s->d_t_lvloff, s->d_t_lvlptr, s->d_t_lvlnodes, s->d_t_parent,
                   s->d_t_childptr, s->d_t_childidx, s->d_t_lval, s->d_t_dinv};
   for (void* p : ptrs) dfree(p);
+  {
+    auto& c = s->chain;
+    void* cp[] = {c.meta, c.soff, c.fmul, c.eup, c.pinv, c.gp, c.gq, c.ap, c.aq, c.sp, c.sq, c.vparent, c.vseg,
+                  c.vchild_ptr, c.vchild_idx, c.vlvl_ptr, c.vlvl_nodes, c.vlval, c.vdinv};
+    for (void* p : cp) dfree(p);
+  }
   free_blocks(s->blk);
   free_blocks(s->blk3);
   free_blocks(s->mblk);
@@ -261,8 +267,54 @@ extern "C" mdnp_status mdnp_host_export(const mdnp_host_sys* hs, int32_t* row_pt
   return MDNP_OK;
 }
 
+// Host form of the chain-compressed 1D solve (the steps of k_chain_solve).
+static void host_chain_solve(const ChainFactor& C, const double* v1, double* z1) {
+  const int m = C.m, S = (int)C.sp.size(), V = (int)C.vparent.size();
+  std::vector<double> t0(S, 0.0), t1(S, 0.0), w(std::max(m, 1)), rv(V);
+  auto seg_solve = [&](int s) {
+    const double* vc = v1 + V + (size_t)s * m;
+    for (int k = m - 1; k >= 0; --k) w[k] = vc[k] - (k + 1 < m ? C.fmul[(size_t)k * S + s] * w[k + 1] : 0.0);
+    for (int k = 0; k < m; ++k)
+      w[k] = (k == 0 ? w[0] : w[k] - C.eup[(size_t)(k - 1) * S + s] * w[k - 1]) * C.pinv[(size_t)k * S + s];
+  };
+  for (int s = 0; s < S && m > 0; ++s) {
+    seg_solve(s);
+    t0[s] = C.ap[s] * w[0];
+    t1[s] = C.aq[s] * w[m - 1];
+  }
+  for (int u = 0; u < V; ++u) {
+    double r = v1[u];
+    if (C.vseg[u] >= 0) r -= t1[C.vseg[u]];
+    for (int q = C.vchild_ptr[u]; q < C.vchild_ptr[u + 1]; ++q) r -= t0[C.vseg[C.vchild_idx[q]]];
+    rv[u] = r;
+  }
+  const int nlev = (int)C.vlvl_ptr.size() - 1;
+  for (int L = 0; L < nlev; ++L)
+    for (int k = C.vlvl_ptr[L]; k < C.vlvl_ptr[L + 1]; ++k) {
+      const int u = C.vlvl_nodes[k];
+      for (int q = C.vchild_ptr[u]; q < C.vchild_ptr[u + 1]; ++q) rv[u] -= C.vlval[C.vchild_idx[q]] * rv[C.vchild_idx[q]];
+    }
+  for (int u = 0; u < V; ++u) rv[u] *= C.vdinv[u];
+  for (int L = nlev - 1; L >= 0; --L)
+    for (int k = C.vlvl_ptr[L]; k < C.vlvl_ptr[L + 1]; ++k) {
+      const int u = C.vlvl_nodes[k];
+      if (C.vparent[u] >= 0) rv[u] -= C.vlval[u] * rv[C.vparent[u]];
+    }
+  for (int u = 0; u < V; ++u) z1[u] = rv[u];
+  for (int s = 0; s < S && m > 0; ++s) {
+    seg_solve(s);
+    for (int k = 0; k < m; ++k)
+      z1[V + (size_t)s * m + k] =
+          w[k] - C.gp[(size_t)k * S + s] * rv[C.sp[s]] - C.gq[(size_t)k * S + s] * rv[C.sq[s]];
+  }
+}
+
 extern "C" mdnp_status mdnp_host_tree_solve(const mdnp_host_sys* hs, const double* v1, double* z1) {
   if (!hs || !v1 || !z1) return MDNP_E_ARG;
+  if (hs->h.chain.m <= kChainMaxM) {
+    host_chain_solve(hs->h.chain, v1, z1);
+    return MDNP_OK;
+  }
   const TreeFactor& T = hs->h.tree;
   const int n1d = hs->h.n1d;
   std::vector<double> y(v1, v1 + n1d);
@@ -419,6 +471,76 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
     s->d_t_lval = dupload(lval, stream);
     s->d_t_dinv = dupload(tdinv, stream);
     tree_solve_setup(sizeof(double) * (size_t)s->max_n1d);
+    // chain-compressed tree solve
+    {
+      auto& cd = s->chain;
+      std::vector<int32_t> meta, sp, sq, vparent, vseg, vcp, vci, vlp, vln;
+      std::vector<int64_t> soff;
+      std::vector<double> fmul, eup, pinv, gp, gq, ap, aq, vlval, vdinv;
+      bool ok = true;
+      for (int i = 0; i < n_inst; ++i) {
+        const ChainFactor& C = s->host[i].chain;
+        const int S = (int)C.sp.size(), V = (int)C.vparent.size();
+        ok = ok && C.m <= kChainMaxM;
+        cd.max_v = std::max(cd.max_v, V);
+        cd.max_s = std::max(cd.max_s, S);
+        const int32_t m8[8] = {C.m, S, V, (int32_t)C.vlvl_ptr.size() - 1, (int32_t)sp.size(), (int32_t)vparent.size(),
+                               (int32_t)vlp.size(), (int32_t)vci.size()};
+        meta.insert(meta.end(), m8, m8 + 8);
+        soff.push_back((int64_t)fmul.size());
+        soff.push_back((int64_t)pinv.size());
+        fmul.insert(fmul.end(), C.fmul.begin(), C.fmul.end());
+        eup.insert(eup.end(), C.eup.begin(), C.eup.end());
+        pinv.insert(pinv.end(), C.pinv.begin(), C.pinv.end());
+        gp.insert(gp.end(), C.gp.begin(), C.gp.end());
+        gq.insert(gq.end(), C.gq.begin(), C.gq.end());
+        ap.insert(ap.end(), C.ap.begin(), C.ap.end());
+        aq.insert(aq.end(), C.aq.begin(), C.aq.end());
+        sp.insert(sp.end(), C.sp.begin(), C.sp.end());
+        sq.insert(sq.end(), C.sq.begin(), C.sq.end());
+        vparent.insert(vparent.end(), C.vparent.begin(), C.vparent.end());
+        vseg.insert(vseg.end(), C.vseg.begin(), C.vseg.end());
+        vcp.insert(vcp.end(), C.vchild_ptr.begin(), C.vchild_ptr.end());
+        vci.insert(vci.end(), C.vchild_idx.begin(), C.vchild_idx.end());
+        vlp.insert(vlp.end(), C.vlvl_ptr.begin(), C.vlvl_ptr.end());
+        vln.insert(vln.end(), C.vlvl_nodes.begin(), C.vlvl_nodes.end());
+        vlval.insert(vlval.end(), C.vlval.begin(), C.vlval.end());
+        vdinv.insert(vdinv.end(), C.vdinv.begin(), C.vdinv.end());
+      }
+      // vertex values, two coupling terms per segment and the vertex tree in LDS
+      for (int i = 0; i < n_inst; ++i) {
+        const ChainFactor& C = s->host[i].chain;
+        cd.lds_bytes = std::max(cd.lds_bytes, chain_lds_bytes((int)C.vparent.size(), (int)C.sp.size(),
+                                                             (int)C.vlvl_ptr.size() - 1));
+      }
+      ok = ok && cd.lds_bytes <= 160 * 1024;
+      cd.enabled = ok ? 1 : 0;
+      if (ok) {
+        // keep every array non-empty so that each pointer is valid
+        for (auto* v : {&fmul, &eup, &pinv, &gp, &gq}) if (v->empty()) v->push_back(0.0);
+        if (vci.empty()) vci.push_back(0);
+        cd.meta = dupload(meta, stream);
+        cd.soff = dupload(soff, stream);
+        cd.fmul = dupload(fmul, stream);
+        cd.eup = dupload(eup, stream);
+        cd.pinv = dupload(pinv, stream);
+        cd.gp = dupload(gp, stream);
+        cd.gq = dupload(gq, stream);
+        cd.ap = dupload(ap, stream);
+        cd.aq = dupload(aq, stream);
+        cd.sp = dupload(sp, stream);
+        cd.sq = dupload(sq, stream);
+        cd.vparent = dupload(vparent, stream);
+        cd.vseg = dupload(vseg, stream);
+        cd.vchild_ptr = dupload(vcp, stream);
+        cd.vchild_idx = dupload(vci, stream);
+        cd.vlvl_ptr = dupload(vlp, stream);
+        cd.vlvl_nodes = dupload(vln, stream);
+        cd.vlval = dupload(vlval, stream);
+        cd.vdinv = dupload(vdinv, stream);
+        chain_solve_setup(cd.lds_bytes);
+      }
+    }
     // reduction tilings
     std::vector<int64_t> st_all(n_inst), len_all(n_inst), st3(n_inst), len3(n_inst);
     for (int i = 0; i < n_inst; ++i) {
@@ -438,6 +560,7 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
       std::vector<double>().swap(h.m_val);
       std::vector<int32_t>().swap(h.m_a01);
       h.tree = TreeFactor();
+      h.chain = ChainFactor();
     }
     ctx->systems.push_back(s);
     *out = s;

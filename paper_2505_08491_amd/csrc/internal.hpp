@@ -132,6 +132,31 @@ struct mdnp_sys {
   int32_t* d_t_childidx = nullptr; // local node ids
   double* d_t_lval = nullptr;
   double* d_t_dinv = nullptr;
+  // chain-compressed tree solve (per instance offsets into concatenated arrays)
+  struct ChainDev {
+    int enabled = 0;                 // all instances fit the on-chip form
+    int max_v = 0, max_s = 0;        // largest vertex / segment count
+    size_t lds_bytes = 0;            // dynamic LDS of the solve kernel
+    int32_t* meta = nullptr;         // [n_inst][8]: m, S, V, vlvl count, seg off, vtx off, vlvl off, vchild off
+    int64_t* soff = nullptr;         // [n_inst][2]: offsets of the [m-1][S] and [m][S] step arrays
+    double* fmul = nullptr;
+    double* eup = nullptr;
+    double* pinv = nullptr;
+    double* gp = nullptr;
+    double* gq = nullptr;
+    double* ap = nullptr;
+    double* aq = nullptr;
+    int32_t* sp = nullptr;           // local vertex ids
+    int32_t* sq = nullptr;
+    int32_t* vparent = nullptr;      // local vertex ids
+    int32_t* vseg = nullptr;         // local segment ids
+    int32_t* vchild_ptr = nullptr;   // [V + 1] per instance, local offsets into the instance's vchild_idx
+    int32_t* vchild_idx = nullptr;
+    int32_t* vlvl_ptr = nullptr;     // [levels + 1] per instance, local
+    int32_t* vlvl_nodes = nullptr;
+    double* vlval = nullptr;
+    double* vdinv = nullptr;
+  } chain;
   mdnp::Blocks blk;                // whole vectors
   mdnp::Blocks blk3;               // 3D parts only
   mdnp::Blocks mblk;               // coupling-row lists

@@ -5,6 +5,7 @@
 // per contiguous chunk ("block") inside one instance, each block writing one
 // FP64 partial sum; every consumer sums the partials of its instance in a
 // fixed order, so results are bitwise reproducible run to run.
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -87,6 +88,103 @@ __device__ __forceinline__ Tacc stencil_row(const Tv* __restrict__ x, int64_t ba
   return (Tacc)st4[0] * grp[0] + (Tacc)st4[1] * grp[1] + (Tacc)st4[2] * grp[2] + (Tacc)st4[3] * grp[3];
 }
 
+// y = S x on the 3D rows, sweeping z.  A block owns rows y0 .. y0 + SW_TY - 1
+// of planes z0 .. z0 + zc - 1 of one instance.  Each input plane z' is staged
+// in LDS over rows y0 - 1 .. y0 + SW_TY with Dirichlet nodes and the outside
+// set to zero (their columns are eliminated), and reduced once to its 2D
+// partials per node: centre, the 4 in-plane face neighbours and the 4
+// in-plane corners.  Output plane z gathers them from z' = z (offsets 0, 1, 2
+// differing coordinates) and z' = z +- 1 (1, 2, 3), so two accumulators ride
+// along the sweep.  Dirichlet rows copy x.  The next plane's values are
+// loaded into registers while the current one is reduced.
+constexpr int SW_TY = 4;          // output rows per block
+constexpr int SW_NX = 2;          // x positions per thread: n <= 128
+
+template <typename Tv, typename Tacc>
+__global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict__ stencil, const Tv* __restrict__ x,
+                                                       Tv* __restrict__ y, const int64_t* __restrict__ off, int n,
+                                                       int ytiles, int zc, const InstState* st, int mask) {
+  __shared__ Tacc pl[2][SW_TY + 2][130];
+  const int i = blockIdx.z;
+  if (mask && !st[i].active) return;
+  const int y0 = (blockIdx.x % ytiles) * SW_TY;
+  const int z0 = (blockIdx.x / ytiles) * zc;
+  const int zend = min(n, z0 + zc);
+  const int64_t nn = (int64_t)n * n;
+  const Tv* X = x + off[i];
+  Tv* Y = y + off[i];
+  const Tacc w0 = (Tacc)stencil[4 * i], w1 = (Tacc)stencil[4 * i + 1], w2 = (Tacc)stencil[4 * i + 2],
+             w3 = (Tacc)stencil[4 * i + 3];
+  const int t = threadIdx.x;
+  const int row = t >> 6, lx = t & 63;      // output row of the tile, first x
+  // plane staging: item q = r * n + xx over rows y0 - 1 .. y0 + SW_TY
+  const int items = (SW_TY + 2) * n;
+  constexpr int NLD = ((SW_TY + 2) * 128 + 255) / 256;
+  auto load = [&](int zp, Tacc (&v)[NLD]) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int q = t + k * 256;
+      Tacc a = 0;
+      if (q < items && zp > 0 && zp < n - 1) {
+        const int r = q / n, xx = q - r * n, gy = y0 + r - 1;
+        if (gy > 0 && gy < n - 1 && xx > 0 && xx < n - 1) a = (Tacc)X[zp * nn + (int64_t)gy * n + xx];
+      }
+      v[k] = a;
+    }
+  };
+  auto store = [&](int buf, const Tacc (&v)[NLD]) {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int q = t + k * 256;
+      if (q < items) {
+        const int r = q / n, xx = q - r * n;
+        pl[buf][r][xx + 1] = v[k];
+      }
+    }
+    if (t < SW_TY + 2) {  // x halo columns
+      pl[buf][t][0] = 0;
+      pl[buf][t][n + 1] = 0;
+    }
+  };
+  Tacc accp[SW_NX], accc[SW_NX];  // partial outputs of planes zp - 1 and zp on entry to step zp
+#pragma unroll
+  for (int k = 0; k < SW_NX; ++k) accp[k] = accc[k] = 0;
+  // registers hold the next two planes: va = zp, vb = zp + 1 on entry to step zp
+  Tacc va[NLD], vb[NLD];
+  load(z0 - 1, va);
+  load(z0, vb);
+  const int gyo = y0 + row;
+  for (int zp = z0 - 1; zp <= zend; ++zp) {
+    const int buf = (zp - z0 + 1) & 1;
+    store(buf, va);
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) va[k] = vb[k];
+    __syncthreads();
+    if (zp + 1 < zend) load(zp + 2, vb);
+#pragma unroll
+    for (int k = 0; k < SW_NX; ++k) {
+      const int xx = lx + 64 * k;
+      if (xx >= n) continue;
+      // 2D partials of plane zp at (gyo, xx)
+      const Tacc c = pl[buf][row + 1][xx + 1];
+      const Tacc f = pl[buf][row][xx + 1] + pl[buf][row + 2][xx + 1] + pl[buf][row + 1][xx] + pl[buf][row + 1][xx + 2];
+      const Tacc e = pl[buf][row][xx] + pl[buf][row][xx + 2] + pl[buf][row + 2][xx] + pl[buf][row + 2][xx + 2];
+      const Tacc up = w1 * c + w2 * f + w3 * e;   // contribution to the planes zp - 1 and zp + 1
+      const Tacc mid = w0 * c + w1 * f + w2 * e;  // contribution to plane zp
+      // output plane zp - 1 is complete
+      const int zo = zp - 1;
+      if (zo >= z0 && gyo < n) {
+        const int64_t v_ = zo * nn + (int64_t)gyo * n + xx;
+        const bool bnd = zo == 0 || zo == n - 1 || gyo == 0 || gyo == n - 1 || xx == 0 || xx == n - 1;
+        Y[v_] = bnd ? X[v_] : (Tv)(accp[k] + up);
+      }
+      accp[k] = accc[k] + mid;  // output plane zp: planes zp - 1 and zp so far
+      accc[k] = up;             // output plane zp + 1: plane zp so far
+    }
+    __syncthreads();
+  }
+}
+
 // y = S x over whole concatenated vectors (one thread per row; 1D rows get 0).
 // RES = 1: r = b - S x, with partial sums of r^2 over the rows that have no
 // coupling entries (the coupling-row kernel completes and sums the others).
@@ -125,20 +223,21 @@ __global__ void __launch_bounds__(BS) k_stencil(const double* __restrict__ stenc
 }
 
 // Coupling rows (3D rows touched by the averaging operator and all 1D rows),
-// G lanes per row: y[row] += (M x)[row] (RES = 0) or r[row] -= (M x)[row] with
-// partial sums of r^2 (RES = 1).
+// G lanes per row: y[row] += (M x)[row] (RES = 0), the same with the 1D rows
+// overwritten instead (RES = 2: y holds only the 3D stencil part), or
+// r[row] -= (M x)[row] with partial sums of r^2 (RES = 1).
 template <typename Tv, typename Tm, typename Tacc, int G, int RES>
 __global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows, const int32_t* __restrict__ mptr,
                                               const int32_t* __restrict__ mcol, const Tm* __restrict__ mval,
                                               const Tv* __restrict__ x, Tv* __restrict__ y, const int32_t* binst,
                                               const int64_t* bstart, const int64_t* bend, const InstState* st,
-                                              int mask, double* part) {
+                                              int mask, double* part, const int64_t* off = nullptr, int n3d = 0) {
   __shared__ double sh[BS / 64];
   const int b = blockIdx.x;
   const int i = binst[b];
   if (mask == 1 && !st[i].active) return;
   if (mask == 2 && st[i].done) {
-    if (RES && threadIdx.x == 0) part[b] = 0.0;
+    if (RES == 1 && threadIdx.x == 0) part[b] = 0.0;
     return;
   }
   const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = BS / G;
@@ -151,16 +250,18 @@ __global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows,
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
     if (lane == 0) {
-      if (RES) {
+      if (RES == 1) {
         const double rv = (double)y[row] - (double)acc;
         y[row] = (Tv)rv;
         loc += rv * rv;
+      } else if (RES == 2 && row - off[i] >= n3d) {
+        y[row] = (Tv)acc;  // 1D row: no stencil part
       } else {
         y[row] = (Tv)((Tacc)y[row] + acc);
       }
     }
   }
-  if (RES) {
+  if (RES == 1) {
     const double t = block_sum(loc, sh);
     if (threadIdx.x == 0) part[b] = t;
   }
@@ -336,6 +437,137 @@ __global__ void __launch_bounds__(BS) k_tree_solve(const T* __restrict__ v, T* _
     __syncthreads();
   }
   for (int c = threadIdx.x; c < n1d; c += blockDim.x) z[g0 + c] = from_d<T>(ys[c]);
+}
+
+// Chain-compressed solve z1 = A11^-1 v1 (same matrix as the leaves-first
+// LDL^T above, elimination grouped by segment), one block per instance:
+//  (a) every segment solves its tridiagonal block y = T^-1 v_c (one thread per
+//      segment, FP64 in registers) and leaves its couplings a_p y_0, a_q y_{m-1};
+//  (b) the vertices form the right-hand side of the Schur complement, a tree
+//      over the vertices, and solve it level by level in LDS;
+//  (c) every segment recomputes y and writes z_c = y - g_p z_p - g_q z_q.
+struct ChainArgs {
+  const int32_t* meta;
+  const int64_t* soff;
+  const double *fmul, *eup, *pinv, *gp, *gq, *ap, *aq;
+  const int32_t *sp, *sq, *vparent, *vseg, *vchild_ptr, *vchild_idx, *vlvl_ptr, *vlvl_nodes;
+  const double *vlval, *vdinv;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_chain_solve(const T* __restrict__ v, T* __restrict__ z, const int64_t* off,
+                                                     int n3d, ChainArgs c, const InstState* st, int want_mode) {
+  // LDS: vertex values, a_p y_0 and a_q y_{m-1} per segment, then the vertex
+  // tree (multipliers, inverse pivots, parents, parent segments, children,
+  // level lists) so that the level sweeps touch no global memory
+  extern __shared__ double cs[];
+  const int i = blockIdx.x;
+  if (st && !mode_ok(st[i], want_mode)) return;
+  const int32_t* mt = c.meta + 8 * i;
+  const int m = mt[0], S = mt[1], V = mt[2], nlev = mt[3];
+  const int so = mt[4], vo = mt[5], lo = mt[6], co = mt[7];
+  const int64_t o1 = c.soff[2 * i], o2 = c.soff[2 * i + 1];
+  const double* fmul = c.fmul + o1;
+  const double* eup = c.eup + o1;
+  const double* pinv = c.pinv + o2;
+  double* rv = cs;
+  double* t0 = rv + V;
+  double* t1 = t0 + S;
+  double* vl = t1 + S;
+  double* vd = vl + V;
+  int32_t* vp = (int32_t*)(vd + V);
+  int32_t* vsg = vp + V;
+  int32_t* vcp = vsg + V;        // V + 1
+  int32_t* vci = vcp + V + 1;    // V - 1 (one parent per non-root vertex)
+  int32_t* ln = vci + (V - 1);   // V
+  int32_t* lp = ln + V;          // nlev + 1
+  for (int u = threadIdx.x; u < V; u += blockDim.x) {
+    vl[u] = c.vlval[vo + u];
+    vd[u] = c.vdinv[vo + u];
+    vp[u] = c.vparent[vo + u];
+    vsg[u] = c.vseg[vo + u];
+    ln[u] = c.vlvl_nodes[vo + u];
+    if (u < V - 1) vci[u] = c.vchild_idx[co + u];
+  }
+  for (int u = threadIdx.x; u <= V; u += blockDim.x) vcp[u] = c.vchild_ptr[vo + i + u];
+  for (int u = threadIdx.x; u <= nlev; u += blockDim.x) lp[u] = c.vlvl_ptr[lo + u];
+  const int64_t g0 = off[i] + n3d;  // first 1D unknown
+  const T* vv = v + g0;
+  T* zz = z + g0;
+  // tridiagonal solve of segment s: w from the q end, then y from the p end
+  auto seg_solve = [&](int s, double (&w)[kChainMaxM]) {
+    const T* vc = vv + V + (int64_t)s * m;
+#pragma unroll
+    for (int k = kChainMaxM - 1; k >= 0; --k) {
+      if (k < m) w[k] = to_d(vc[k]) - (k + 1 < m ? fmul[(int64_t)k * S + s] * w[k + 1] : 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < kChainMaxM; ++k) {
+      if (k < m) w[k] = (k == 0 ? w[0] : w[k] - eup[(int64_t)(k - 1) * S + s] * w[k - 1]) * pinv[(int64_t)k * S + s];
+    }
+  };
+  for (int s = threadIdx.x; s < S; s += blockDim.x) {
+    double w[kChainMaxM];
+    if (m > 0) {
+      seg_solve(s, w);
+      t0[s] = c.ap[so + s] * w[0];
+      double last = 0.0;
+#pragma unroll
+      for (int k = 0; k < kChainMaxM; ++k)
+        if (k == m - 1) last = w[k];
+      t1[s] = c.aq[so + s] * last;
+    } else {
+      t0[s] = 0.0;
+      t1[s] = 0.0;
+    }
+  }
+  __syncthreads();
+  // right-hand side of the vertex system
+  for (int u = threadIdx.x; u < V; u += blockDim.x) {
+    double r = to_d(vv[u]);
+    const int ps = vsg[u];
+    if (ps >= 0) r -= t1[ps];
+    for (int q = vcp[u]; q < vcp[u + 1]; ++q) r -= t0[vsg[vci[q]]];
+    rv[u] = r;
+  }
+  __syncthreads();
+  // leaves-first LDL^T of the vertex tree
+  for (int L = 0; L < nlev; ++L) {
+    for (int k = lp[L] + threadIdx.x; k < lp[L + 1]; k += blockDim.x) {
+      const int u = ln[k];
+      double acc = rv[u];
+      for (int q = vcp[u]; q < vcp[u + 1]; ++q) {
+        const int kid = vci[q];
+        acc -= vl[kid] * rv[kid];
+      }
+      rv[u] = acc;
+    }
+    __syncthreads();
+  }
+  for (int u = threadIdx.x; u < V; u += blockDim.x) rv[u] *= vd[u];
+  __syncthreads();
+  for (int L = nlev - 1; L >= 0; --L) {
+    for (int k = lp[L] + threadIdx.x; k < lp[L + 1]; k += blockDim.x) {
+      const int u = ln[k];
+      const int pu = vp[u];
+      if (pu >= 0) rv[u] -= vl[u] * rv[pu];
+    }
+    __syncthreads();
+  }
+  for (int u = threadIdx.x; u < V; u += blockDim.x) zz[u] = from_d<T>(rv[u]);
+  // chain interiors
+  const double* gp = c.gp + o2;
+  const double* gq = c.gq + o2;
+  for (int s = threadIdx.x; s < S; s += blockDim.x) {
+    if (m == 0) continue;
+    double w[kChainMaxM];
+    seg_solve(s, w);
+    const double zp = rv[c.sp[so + s]], zq = rv[c.sq[so + s]];
+    T* zc = zz + V + (int64_t)s * m;
+#pragma unroll
+    for (int k = 0; k < kChainMaxM; ++k)
+      if (k < m) zc[k] = from_d<T>(w[k] - gp[(int64_t)k * S + s] * zp - gq[(int64_t)k * S + s] * zq);
+  }
 }
 
 // Extension b0 = v0 - A01 z1 (z1 already in z), in two passes: every 3D row
@@ -571,16 +803,38 @@ __global__ void __launch_bounds__(BS) k_update_x(const T* __restrict__ Z, int64_
 template <typename T>
 void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, hipStream_t stream) {
   const int mk = mask ? 1 : 0;
+  const int n = s->n;
+  if (n > 64 * SW_NX) {  // one thread per row
+    if (sizeof(T) == 8) {
+      hipLaunchKernelGGL((k_stencil<T, double, 0>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr,
+                         x, (const double*)nullptr, y, s->d_off, s->n, s->n3d, BLK(s), st, mk, (double*)nullptr);
+      hipLaunchKernelGGL((k_mrows<T, double, double, 8, 0>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
+                         s->d_mptr, s->d_mcol, s->d_mval64, x, y, MBLK(s), st, mk, (double*)nullptr);
+    } else {
+      hipLaunchKernelGGL((k_stencil<T, float, 0>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr,
+                         x, (const double*)nullptr, y, s->d_off, s->n, s->n3d, BLK(s), st, mk, (double*)nullptr);
+      hipLaunchKernelGGL((k_mrows<T, float, float, 8, 0>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
+                         s->d_mptr, s->d_mcol, s->d_mval32, x, y, MBLK(s), st, mk, (double*)nullptr);
+    }
+    return;
+  }
+  const int ytiles = (n + SW_TY - 1) / SW_TY;
+  // about eight blocks per compute unit over the batch
+  int nz = (2048 + ytiles * s->n_inst - 1) / (ytiles * s->n_inst);
+  nz = std::max(1, std::min(nz, n));
+  const int zc = (n + nz - 1) / nz;
+  nz = (n + zc - 1) / zc;
+  const dim3 grid((unsigned)(ytiles * nz), 1, (unsigned)s->n_inst);
   if (sizeof(T) == 8) {
-    hipLaunchKernelGGL((k_stencil<T, double, 0>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr, x,
-                       (const double*)nullptr, y, s->d_off, s->n, s->n3d, BLK(s), st, mk, (double*)nullptr);
-    hipLaunchKernelGGL((k_mrows<T, double, double, 8, 0>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
-                       s->d_mptr, s->d_mcol, s->d_mval64, x, y, MBLK(s), st, mk, (double*)nullptr);
+    hipLaunchKernelGGL((k_stencil_sweep<T, double>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
+                       ytiles, zc, st, mk);
+    hipLaunchKernelGGL((k_mrows<T, double, double, 8, 2>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
+                       s->d_mptr, s->d_mcol, s->d_mval64, x, y, MBLK(s), st, mk, (double*)nullptr, s->d_off, s->n3d);
   } else {
-    hipLaunchKernelGGL((k_stencil<T, float, 0>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr, x,
-                       (const double*)nullptr, y, s->d_off, s->n, s->n3d, BLK(s), st, mk, (double*)nullptr);
-    hipLaunchKernelGGL((k_mrows<T, float, float, 8, 0>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
-                       s->d_mptr, s->d_mcol, s->d_mval32, x, y, MBLK(s), st, mk, (double*)nullptr);
+    hipLaunchKernelGGL((k_stencil_sweep<T, float>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
+                       ytiles, zc, st, mk);
+    hipLaunchKernelGGL((k_mrows<T, float, float, 8, 2>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
+                       s->d_mptr, s->d_mcol, s->d_mval32, x, y, MBLK(s), st, mk, (double*)nullptr, s->d_off, s->n3d);
   }
 }
 template void launch_spmv<float>(mdnp_sys*, const float*, float*, const InstState*, bool, hipStream_t);
@@ -660,8 +914,26 @@ void tree_solve_setup(size_t shm_bytes) {
   }
 }
 
+void chain_solve_setup(size_t shm_bytes) {
+  if (shm_bytes > 65536) {
+    hipFuncSetAttribute((const void*)k_chain_solve<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_bytes);
+    hipFuncSetAttribute((const void*)k_chain_solve<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_bytes);
+  }
+}
+
 template <typename T>
 void launch_tree_solve(mdnp_sys* s, const T* v, T* z, const InstState* st, int want_mode, hipStream_t stream) {
+  const auto& cd = s->chain;
+  if (cd.enabled) {
+    const ChainArgs a{cd.meta, cd.soff, cd.fmul, cd.eup, cd.pinv, cd.gp, cd.gq, cd.ap, cd.aq, cd.sp, cd.sq,
+                      cd.vparent, cd.vseg, cd.vchild_ptr, cd.vchild_idx, cd.vlvl_ptr, cd.vlvl_nodes, cd.vlval,
+                      cd.vdinv};
+    const size_t shm = cd.lds_bytes;
+    const int threads = std::min(512, std::max(64, (std::max(cd.max_s, cd.max_v) + 63) / 64 * 64));
+    hipLaunchKernelGGL((k_chain_solve<T>), dim3(s->n_inst), dim3(threads), shm, stream, v, z, s->d_off, s->n3d, a, st,
+                       want_mode);
+    return;
+  }
   const size_t shm = sizeof(double) * (size_t)s->max_n1d;
   hipLaunchKernelGGL((k_tree_solve<T>), dim3(s->n_inst), dim3(BS), shm, stream, v, z, s->d_off, s->n3d,
                      s->d_t_off, s->d_t_lvloff, s->d_t_lvlptr, s->d_t_lvlnodes, s->d_t_parent, s->d_t_childptr,

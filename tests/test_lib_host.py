@@ -66,6 +66,20 @@ def test_tree_factorisation_solves_a11():
         assert np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref) < 1e-12
 
 
+@pytest.mark.parametrize("elems", [1, 2, 40])
+def test_tree_solve_segment_lengths(elems):
+    """Chain-compressed 1D solve with no interior node, one interior node, and
+    more interior nodes than the chain form holds (leaves-first fallback)."""
+    inst = synth.make_instance(77, 8, n_segments=6, elems_per_segment=elems, radius=0.01, beta=1.0)
+    P = _lib()
+    h = P.host_assemble(inst)
+    s = fem.assemble(inst)
+    Q = krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s))
+    v = synth.fast_normal(5, s.n1d)
+    z_ref = Q.solve_1d(v)
+    assert np.linalg.norm(h.tree_solve(v) - z_ref) / np.linalg.norm(z_ref) < 1e-12
+
+
 def test_geometry_errors():
     P = _lib()
     inst = synth.make_instance(1, 8, n_segments=3, elems_per_segment=2, radius=0.01)
