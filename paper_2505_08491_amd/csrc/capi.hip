@@ -82,10 +82,10 @@ void dfree(void* p) {
 hipStream_t pick(mdnp_ctx* ctx, void* s) { return s ? (hipStream_t)s : ctx->stream; }
 
 void build_blocks(Blocks& B, const std::vector<int64_t>& start_i, const std::vector<int64_t>& len_i,
-                  int64_t total_len, hipStream_t s) {
+                  int64_t total_len, hipStream_t s, int min_chunk = 256, int64_t target_blocks = 2048) {
   const int n_inst = (int)start_i.size();
-  int chunk = 256;
-  while (chunk < 8192 && total_len / chunk > 2048) chunk *= 2;
+  int chunk = min_chunk;
+  while (chunk < 8192 && total_len / chunk > target_blocks) chunk *= 2;
   B.chunk = chunk;
   std::vector<int32_t> bi;
   std::vector<int64_t> bs, be;
@@ -119,7 +119,7 @@ void free_work(SolveWork& w) {
 }
 
 void free_sys(mdnp_sys* s) {
-  void* ptrs[] = {s->d_off, s->d_stencil, s->d_mptr, s->d_mcol, s->d_mval64, s->d_mval32, s->d_ma01, s->d_mrows,
+  void* ptrs[] = {s->d_off, s->d_stencil, s->d_mptr, s->d_mcol, s->d_mval64, s->d_mval32, s->d_ma01, s->d_mrows, s->d_mlp,
                   s->d_dinv, s->d_dist,
                   s->d_alpha, s->d_t_off, s->d_t_lvloff, s->d_t_lvlptr, s->d_t_lvlnodes, s->d_t_parent,
                   s->d_t_childptr, s->d_t_childidx, s->d_t_lval, s->d_t_dinv};
@@ -442,8 +442,19 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
       s->m_nnz.push_back((int64_t)h.m_col.size());
     }
     s->d_mrows = dupload(mrows, stream);
-    build_blocks(s->mblk, ms, ml, (int64_t)mrows.size(), stream);
-    build_blocks(s->mblk3, ms, ml3, (int64_t)mrows.size(), stream);
+    {
+      // entries of listed row q are [mlp[q], mlp[q + 1]): rows left out of the
+      // list have no M entries, so consecutive listed rows are contiguous in M
+      std::vector<int32_t> mlp(mrows.size() + 1);
+      for (size_t q = 0; q < mrows.size(); ++q) mlp[q] = mp[mrows[q]];
+      mlp[mrows.size()] = mrows.empty() ? 0 : mp[mrows.back() + 1];
+      for (size_t q = 0; q < mrows.size(); ++q)
+        if (mp[mrows[q] + 1] != mlp[q + 1]) fail(MDNP_E_ARG, "internal error: coupling rows are not contiguous");
+      s->d_mlp = dupload(mlp, stream);
+    }
+    // coupling rows: short chunks (a few rows per lane group) for latency hiding
+    build_blocks(s->mblk, ms, ml, (int64_t)mrows.size(), stream, 64, 8192);
+    build_blocks(s->mblk3, ms, ml3, (int64_t)mrows.size(), stream, 64, 8192);
     // tree factorisation
     std::vector<int32_t> toff(n_inst + 1, 0), lvloff(n_inst + 1, 0), lvlptr, lvlnodes, parent, childptr, childidx;
     std::vector<double> lval, tdinv;

@@ -1092,7 +1092,7 @@ void launch_s1(const MfmaArgs& a, int batch, hipStream_t stream) {
   else if (wl) launch_s1_tiled<CA, CB, COUT, 2, IN, EPI, Tv, WSMALL ? 1 : 0>(a, batch, lds, w2, stream);
   else launch_s1_tiled<CA, CB, COUT, 2, IN, EPI, Tv, 0>(a, batch, lds, w2, stream);
   // the x = n - 1 column
-  constexpr int MBE = 4;
+  constexpr int MBE = 1;
   const int64_t nmb = ((int64_t)n * n + 15) / 16;
   const dim3 grid((unsigned)((nmb + WAVES * MBE - 1) / (WAVES * MBE)), 1, batch);
   hipLaunchKernelGGL((k_conv_mfma<IN ? 8 : CA, CB, COUT, 1, MBE, IN, EPI, Tv, 1>), grid, dim3(WAVES * 64), 0, stream,
@@ -1139,7 +1139,7 @@ void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream) {
     else launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF1>(a, q, batch, lds, xb, stream);
   }
   if (!EPI) {
-    constexpr int MBE = 4;
+    constexpr int MBE = 1;
     const int64_t nmb = ((int64_t)n * n + 15) / 16;
     const dim3 grid((unsigned)((nmb + WAVES * MBE - 1) / (WAVES * MBE)), 1, batch);
     hipLaunchKernelGGL((k_conv_mfma<IN ? 8 : CA, CB, 16, 1, MBE, IN, EPI, Tv, 1>), grid, dim3(WAVES * 64), 0, stream,
@@ -1178,7 +1178,7 @@ void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream) {
   if (lds > 65536) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(kern, dim3((unsigned)(q.ytiles * nz), 1, batch), dim3(2 * xb * 64), lds, stream, a, q);
   if (!EPI) {
-    constexpr int MBE = 4;
+    constexpr int MBE = 1;
     const int64_t nmb = ((int64_t)n * n + 15) / 16;
     const dim3 grid((unsigned)((nmb + WAVES * MBE - 1) / (WAVES * MBE)), 1, batch);
     hipLaunchKernelGGL((k_conv_mfma<CA, CB, 16, 1, MBE, 0, EPI, Tv, 1>), grid, dim3(WAVES * 64), 0, stream, a);

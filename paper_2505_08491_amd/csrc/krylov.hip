@@ -45,6 +45,14 @@ __device__ double inst_sum(const double* part, const int32_t* first, int i, doub
   return block_sum(t, sh);
 }
 
+// Sum of the partials part[first[i] .. first[i+1]) by one wavefront in a fixed
+// order (lane-strided, then a butterfly), result in every lane.
+__device__ __forceinline__ double wave_inst_sum(const double* part, const int32_t* first, int i) {
+  double t = 0.0;
+  for (int b = first[i] + (int)(threadIdx.x & 63); b < first[i + 1]; b += 64) t += part[b];
+  return wave_sum(t);
+}
+
 __device__ __forceinline__ int find_inst(const int64_t* off, int n_inst, int64_t g) {
   int lo = 0, hi = n_inst;  // off[lo] <= g < off[hi]
   while (hi - lo > 1) {
@@ -58,6 +66,20 @@ __device__ __forceinline__ bool is_boundary(int r, int n) {
   int i = r % n, j = (r / n) % n, k = r / (n * n);
   return i == 0 || j == 0 || k == 0 || i == n - 1 || j == n - 1 || k == n - 1;
 }
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// For a grid of 8 * ceil(nlog / 8) workgroups this returns the logical block
+// of the calling workgroup such that every XCD runs a contiguous range of
+// logical blocks (blocks are ordered by instance, so an XCD's L2 sees about
+// n_inst / 8 instances), or -1 for the padding workgroups.
+__device__ __forceinline__ int xcd_logical_block(int nlog) {
+  const int per = (nlog + 7) / 8;
+  const int p = blockIdx.x;
+  const int b = (p % 8) * per + p / 8;
+  return b < nlog ? b : -1;
+}
+
+inline unsigned xcd_grid(int nlog) { return (unsigned)(8 * ((nlog + 7) / 8)); }
 
 // ---------------------------------------------------------------- operator A = S + M
 
@@ -103,12 +125,16 @@ constexpr int SW_NX = 2;          // x positions per thread: n <= 128
 template <typename Tv, typename Tacc>
 __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict__ stencil, const Tv* __restrict__ x,
                                                        Tv* __restrict__ y, const int64_t* __restrict__ off, int n,
-                                                       int ytiles, int zc, const InstState* st, int mask) {
+                                                       int ytiles, int zc, int n_inst, const InstState* st,
+                                                       int mask) {
   __shared__ Tacc pl[2][SW_TY + 2][130];
-  const int i = blockIdx.z;
+  const int nz = (n + zc - 1) / zc;
+  const int lb = xcd_logical_block(n_inst * ytiles * nz);
+  if (lb < 0) return;
+  const int i = lb / (ytiles * nz), tile = lb - i * (ytiles * nz);
   if (mask && !st[i].active) return;
-  const int y0 = (blockIdx.x % ytiles) * SW_TY;
-  const int z0 = (blockIdx.x / ytiles) * zc;
+  const int y0 = (tile % ytiles) * SW_TY;
+  const int z0 = (tile / ytiles) * zc;
   const int zend = min(n, z0 + zc);
   const int64_t nn = (int64_t)n * n;
   const Tv* X = x + off[i];
@@ -227,13 +253,14 @@ __global__ void __launch_bounds__(BS) k_stencil(const double* __restrict__ stenc
 // overwritten instead (RES = 2: y holds only the 3D stencil part), or
 // r[row] -= (M x)[row] with partial sums of r^2 (RES = 1).
 template <typename Tv, typename Tm, typename Tacc, int G, int RES>
-__global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows, const int32_t* __restrict__ mptr,
+__global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows, const int32_t* __restrict__ mlp,
                                               const int32_t* __restrict__ mcol, const Tm* __restrict__ mval,
                                               const Tv* __restrict__ x, Tv* __restrict__ y, const int32_t* binst,
                                               const int64_t* bstart, const int64_t* bend, const InstState* st,
-                                              int mask, double* part, const int64_t* off = nullptr, int n3d = 0) {
+                                              int mask, double* part, int nblk, const int64_t* off = nullptr, int n3d = 0) {
   __shared__ double sh[BS / 64];
-  const int b = blockIdx.x;
+  const int b = xcd_logical_block(nblk);
+  if (b < 0) return;
   const int i = binst[b];
   if (mask == 1 && !st[i].active) return;
   if (mask == 2 && st[i].done) {
@@ -245,8 +272,22 @@ __global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows,
   for (int64_t q = bstart[b] + grp; q < bend[b]; q += ng) {
     const int row = mrows[q];
     Tacc acc = 0;
-    const int e = mptr[row + 1];
-    for (int k = mptr[row] + lane; k < e; k += G) acc += (Tacc)mval[k] * (Tacc)x[mcol[k]];
+    const int e = mlp[q + 1];
+    // U entries per lane per pass, all loads of a pass in flight together
+    constexpr int U = 4;
+    for (int k0 = mlp[q] + lane; k0 < e; k0 += U * G) {
+      int cidx[U];
+      Tm mv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * G;
+        cidx[u] = k < e ? mcol[k] : -1;
+        mv[u] = k < e ? mval[k] : (Tm)0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (cidx[u] >= 0) acc += (Tacc)mv[u] * (Tacc)x[cidx[u]];
+    }
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
     if (lane == 0) {
@@ -297,12 +338,13 @@ __global__ void __launch_bounds__(BS) k_norm2_part(const double* __restrict__ x,
 
 // ---------------------------------------------------------------- cycle control
 
+// One wavefront per instance (grid = n_inst, 64 threads).
 __global__ void k_init_state(InstState* st, const double* part, const int32_t* first, int n_inst,
                              double tol, int max_iters) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x;
   if (i >= n_inst) return;
-  double s = 0.0;
-  for (int b = first[i]; b < first[i + 1]; ++b) s += part[b];
+  const double s = wave_inst_sum(part, first, i);
+  if (threadIdx.x != 0) return;
   InstState z{};
   z.bnorm = sqrt(s);
   z.tol = tol;
@@ -317,10 +359,13 @@ __global__ void k_init_state(InstState* st, const double* part, const int32_t* f
 }
 
 // Start of a restart cycle: beta = ||r||, convergence and stall tests.
+// One wavefront per instance (grid = n_inst, 64 threads).
 __global__ void k_cycle_start(InstState* st, const double* part, const int32_t* first, const double* part2,
                               const int32_t* first2, int n_inst, double* g, double* hist, int hist_cap, int m) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x;
   if (i >= n_inst) return;
+  const double s = wave_inst_sum(part, first, i) + wave_inst_sum(part2, first2, i);
+  if (threadIdx.x != 0) return;
   InstState z = st[i];
   z.active = 0;
   z.jend = 0;
@@ -328,9 +373,6 @@ __global__ void k_cycle_start(InstState* st, const double* part, const int32_t* 
     st[i] = z;
     return;
   }
-  double s = 0.0;
-  for (int b = first[i]; b < first[i + 1]; ++b) s += part[b];
-  for (int b = first2[i]; b < first2[i + 1]; ++b) s += part2[b];
   const double beta = sqrt(s);
   const double rel = beta / z.bnorm;
   if (z.nhist < hist_cap) hist[(int64_t)i * hist_cap + z.nhist++] = -rel;
@@ -599,13 +641,14 @@ __global__ void __launch_bounds__(BS) k_ext_copy(const T* __restrict__ v, T* __r
 
 template <typename T, typename Tm, int G>
 __global__ void __launch_bounds__(BS) k_ext_rows(const T* __restrict__ v, T* __restrict__ z,
-                                                 const int32_t* __restrict__ mrows, const int32_t* __restrict__ mptr,
+                                                 const int32_t* __restrict__ mrows, const int32_t* __restrict__ mlp,
                                                  const int32_t* __restrict__ mcol, const Tm* __restrict__ mval,
                                                  const int32_t* __restrict__ ma01, const int64_t* off, int n3d,
                                                  const int32_t* binst, const int64_t* bstart, const int64_t* bend,
-                                                 const InstState* st, int want_mode, double* part) {
+                                                 const InstState* st, int want_mode, double* part, int nblk) {
   __shared__ double sh[BS / 64];
-  const int b = blockIdx.x;
+  const int b = xcd_logical_block(nblk);
+  if (b < 0) return;
   const int i = binst[b];
   if (st && !mode_ok(st[i], want_mode)) {
     if (threadIdx.x == 0) part[b] = 0.0;
@@ -618,8 +661,21 @@ __global__ void __launch_bounds__(BS) k_ext_rows(const T* __restrict__ v, T* __r
     const int row = mrows[q];
     const int r = (int)(row - base);
     double acc = 0.0;
-    const int e = mptr[row + 1];
-    for (int k = ma01[(int64_t)i * n3d + r] + lane; k < e; k += G) acc += (double)mval[k] * to_d(z[mcol[k]]);
+    const int e = mlp[q + 1];
+    constexpr int U = 4;
+    for (int k0 = ma01[(int64_t)i * n3d + r] + lane; k0 < e; k0 += U * G) {
+      int cidx[U];
+      Tm mv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * G;
+        cidx[u] = k < e ? mcol[k] : -1;
+        mv[u] = k < e ? mval[k] : (Tm)0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (cidx[u] >= 0) acc += (double)mv[u] * to_d(z[cidx[u]]);
+    }
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
     if (lane == 0) {
@@ -645,14 +701,14 @@ __global__ void __launch_bounds__(BS) k_block_jacobi3d(T* __restrict__ z, const 
     z[base + r] = from_d<T>(to_d(z[base + r]) * dinv[base + r]);
 }
 
+// One wavefront per instance (grid = n_inst, 64 threads).
 __global__ void k_inv_scale(const double* part3, const int32_t* first, const double* part4, const int32_t* first4,
                             int n_inst, double* inv_s, InstState* st, int want_mode) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x;
   if (i >= n_inst) return;
   if (st && !mode_ok(st[i], want_mode)) return;
-  double s = 0.0;
-  for (int b = first[i]; b < first[i + 1]; ++b) s += part3[b];
-  for (int b = first4[i]; b < first4[i + 1]; ++b) s += part4[b];
+  double s = wave_inst_sum(part3, first, i) + wave_inst_sum(part4, first4, i);
+  if (threadIdx.x != 0) return;
   s = sqrt(s);
   inv_s[i] = s > 0.0 ? 1.0 / s : 0.0;
   inv_s[n_inst + i] = s;
@@ -808,13 +864,13 @@ void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, 
     if (sizeof(T) == 8) {
       hipLaunchKernelGGL((k_stencil<T, double, 0>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr,
                          x, (const double*)nullptr, y, s->d_off, s->n, s->n3d, BLK(s), st, mk, (double*)nullptr);
-      hipLaunchKernelGGL((k_mrows<T, double, double, 8, 0>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
-                         s->d_mptr, s->d_mcol, s->d_mval64, x, y, MBLK(s), st, mk, (double*)nullptr);
+      hipLaunchKernelGGL((k_mrows<T, double, double, 8, 0>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
+                         s->d_mlp, s->d_mcol, s->d_mval64, x, y, MBLK(s), st, mk, (double*)nullptr, s->mblk.nblk);
     } else {
       hipLaunchKernelGGL((k_stencil<T, float, 0>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr,
                          x, (const double*)nullptr, y, s->d_off, s->n, s->n3d, BLK(s), st, mk, (double*)nullptr);
-      hipLaunchKernelGGL((k_mrows<T, float, float, 8, 0>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
-                         s->d_mptr, s->d_mcol, s->d_mval32, x, y, MBLK(s), st, mk, (double*)nullptr);
+      hipLaunchKernelGGL((k_mrows<T, float, float, 8, 0>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
+                         s->d_mlp, s->d_mcol, s->d_mval32, x, y, MBLK(s), st, mk, (double*)nullptr, s->mblk.nblk);
     }
     return;
   }
@@ -824,17 +880,17 @@ void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, 
   nz = std::max(1, std::min(nz, n));
   const int zc = (n + nz - 1) / nz;
   nz = (n + zc - 1) / zc;
-  const dim3 grid((unsigned)(ytiles * nz), 1, (unsigned)s->n_inst);
+  const dim3 grid(xcd_grid(ytiles * nz * s->n_inst));
   if (sizeof(T) == 8) {
     hipLaunchKernelGGL((k_stencil_sweep<T, double>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, st, mk);
-    hipLaunchKernelGGL((k_mrows<T, double, double, 8, 2>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
-                       s->d_mptr, s->d_mcol, s->d_mval64, x, y, MBLK(s), st, mk, (double*)nullptr, s->d_off, s->n3d);
+                       ytiles, zc, s->n_inst, st, mk);
+    hipLaunchKernelGGL((k_mrows<T, double, double, 8, 2>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
+                       s->d_mlp, s->d_mcol, s->d_mval64, x, y, MBLK(s), st, mk, (double*)nullptr, s->mblk.nblk, s->d_off, s->n3d);
   } else {
     hipLaunchKernelGGL((k_stencil_sweep<T, float>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, st, mk);
-    hipLaunchKernelGGL((k_mrows<T, float, float, 8, 2>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
-                       s->d_mptr, s->d_mcol, s->d_mval32, x, y, MBLK(s), st, mk, (double*)nullptr, s->d_off, s->n3d);
+                       ytiles, zc, s->n_inst, st, mk);
+    hipLaunchKernelGGL((k_mrows<T, float, float, 8, 2>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
+                       s->d_mlp, s->d_mcol, s->d_mval32, x, y, MBLK(s), st, mk, (double*)nullptr, s->mblk.nblk, s->d_off, s->n3d);
   }
 }
 template void launch_spmv<float>(mdnp_sys*, const float*, float*, const InstState*, bool, hipStream_t);
@@ -865,8 +921,8 @@ void launch_residual(mdnp_sys* s, const double* b, const double* x, double* r, d
   const int mk = st ? 2 : 0;
   hipLaunchKernelGGL((k_stencil<double, double, 1>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr,
                      x, b, r, s->d_off, s->n, s->n3d, BLK(s), st, mk, part);
-  hipLaunchKernelGGL((k_mrows<double, double, double, 8, 1>), dim3(s->mblk.nblk), dim3(BS), 0, stream, s->d_mrows,
-                     s->d_mptr, s->d_mcol, s->d_mval64, x, r, MBLK(s), st, mk, partm);
+  hipLaunchKernelGGL((k_mrows<double, double, double, 8, 1>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
+                     s->d_mlp, s->d_mcol, s->d_mval64, x, r, MBLK(s), st, mk, partm, s->mblk.nblk);
 }
 
 void launch_norm2_partials(mdnp_sys* s, const double* x, double* part, hipStream_t stream) {
@@ -875,13 +931,13 @@ void launch_norm2_partials(mdnp_sys* s, const double* x, double* part, hipStream
 
 void launch_init_state(mdnp_sys* s, InstState* st, const double* part, double tol, int max_iters,
                        hipStream_t stream) {
-  hipLaunchKernelGGL(k_init_state, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, st, part, s->blk.first,
+  hipLaunchKernelGGL(k_init_state, dim3(s->n_inst), dim3(64), 0, stream, st, part, s->blk.first,
                      s->n_inst, tol, max_iters);
 }
 
 void launch_cycle_start(mdnp_sys* s, InstState* st, const double* part, const double* partm, double* g, double* hist,
                         int hist_cap, int m, hipStream_t stream) {
-  hipLaunchKernelGGL(k_cycle_start, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, st, part, s->blk.first, partm,
+  hipLaunchKernelGGL(k_cycle_start, dim3(s->n_inst), dim3(64), 0, stream, st, part, s->blk.first, partm,
                      s->mblk.first, s->n_inst, g, hist, hist_cap, m);
 }
 
@@ -948,11 +1004,13 @@ void launch_extension(mdnp_sys* s, const T* v, T* z, double* part3, double* part
   hipLaunchKernelGGL((k_ext_copy<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, v, z, s->d_mptr, s->d_off, BLK3(s), st,
                      want_mode, part3);
   if (sizeof(T) == 8)
-    hipLaunchKernelGGL((k_ext_rows<T, double, 8>), dim3(s->mblk3.nblk), dim3(BS), 0, stream, v, z, s->d_mrows,
-                       s->d_mptr, s->d_mcol, s->d_mval64, s->d_ma01, s->d_off, s->n3d, MBLK3(s), st, want_mode, part3m);
+    hipLaunchKernelGGL((k_ext_rows<T, double, 8>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream, v, z,
+                       s->d_mrows, s->d_mlp, s->d_mcol, s->d_mval64, s->d_ma01, s->d_off, s->n3d, MBLK3(s), st,
+                       want_mode, part3m, s->mblk3.nblk);
   else
-    hipLaunchKernelGGL((k_ext_rows<T, float, 8>), dim3(s->mblk3.nblk), dim3(BS), 0, stream, v, z, s->d_mrows,
-                       s->d_mptr, s->d_mcol, s->d_mval32, s->d_ma01, s->d_off, s->n3d, MBLK3(s), st, want_mode, part3m);
+    hipLaunchKernelGGL((k_ext_rows<T, float, 8>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream, v, z,
+                       s->d_mrows, s->d_mlp, s->d_mcol, s->d_mval32, s->d_ma01, s->d_off, s->n3d, MBLK3(s), st,
+                       want_mode, part3m, s->mblk3.nblk);
 }
 template void launch_extension<float>(mdnp_sys*, const float*, float*, double*, double*, const InstState*, int,
                                       hipStream_t);
@@ -969,7 +1027,7 @@ template void launch_block_jacobi3d<double>(mdnp_sys*, double*, const InstState*
 
 void launch_inv_scale(mdnp_sys* s, const double* part3, const double* part3m, double* inv_s, InstState* st,
                       int want_mode, hipStream_t stream) {
-  hipLaunchKernelGGL(k_inv_scale, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, part3, s->blk3.first, part3m,
+  hipLaunchKernelGGL(k_inv_scale, dim3(s->n_inst), dim3(64), 0, stream, part3, s->blk3.first, part3m,
                      s->mblk3.first, s->n_inst, inv_s, st, want_mode);
 }
 
