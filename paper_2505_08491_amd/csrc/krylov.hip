@@ -629,11 +629,24 @@ __global__ void __launch_bounds__(BS) k_ext_copy(const T* __restrict__ v, T* __r
   }
   const int64_t base = off[i];
   double loc = 0.0;
-  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += blockDim.x) {
-    const int64_t g = base + r;
-    const T vv = v[g];
-    z[g] = vv;
-    if (mptr[g + 1] == mptr[g]) loc += to_d(vv) * to_d(vv);
+  constexpr int U = 8;
+  const int64_t r1 = bend[b];
+  for (int64_t r0 = bstart[b] + threadIdx.x; r0 < r1; r0 += (int64_t)U * BS) {
+    T vl[U];
+    bool free_row[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t g = base + min(r0 + (int64_t)u * BS, r1 - 1);
+      vl[u] = v[g];
+      free_row[u] = mptr[g + 1] == mptr[g];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + (int64_t)u * BS;
+      if (r >= r1) break;
+      z[base + r] = vl[u];
+      if (free_row[u]) loc += to_d(vl[u]) * to_d(vl[u]);
+    }
   }
   double t = block_sum(loc, sh);
   if (threadIdx.x == 0) part[b] = t;
@@ -741,17 +754,37 @@ __global__ void __launch_bounds__(BS) k_mgs(T* __restrict__ V, int64_t ld, int j
   const T* vp = V + (int64_t)(k - 1) * ld;
   const T* vk = V + (int64_t)k * ld;
   double acc = 0.0, acc0 = 0.0;
-  for (int64_t e = bstart[b] + threadIdx.x; e < bend[b]; e += blockDim.x) {
-    double wv = to_d(w[e]);
-    if (k == 0) acc0 += wv * wv;
-    if (k >= 1) {
-      wv -= h * to_d(vp[e]);
-      const T ws = from_d<T>(wv);
-      w[e] = ws;
-      wv = to_d(ws);
+  // U elements per thread per pass, all loads of a pass issued before use
+  constexpr int U = 8;
+  const int64_t e1 = bend[b];
+  // unconditional loads (index clamped into the block, pointers made valid)
+  // so that the compiler issues all of a pass's loads before the first use
+  const T* vpp = k >= 1 ? vp : w;
+  const T* vkk = k <= j ? vk : w;
+  for (int64_t e0 = bstart[b] + threadIdx.x; e0 < e1; e0 += (int64_t)U * BS) {
+    T wl[U], pl[U], kl[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = min(e0 + (int64_t)u * BS, e1 - 1);
+      wl[u] = w[e];
+      pl[u] = vpp[e];
+      kl[u] = vkk[e];
     }
-    if (k <= j) acc += wv * to_d(vk[e]);
-    else acc += wv * wv;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + (int64_t)u * BS;
+      if (e >= e1) break;
+      double wv = to_d(wl[u]);
+      if (k == 0) acc0 += wv * wv;
+      if (k >= 1) {
+        wv -= h * to_d(pl[u]);
+        const T ws = from_d<T>(wv);
+        w[e] = ws;
+        wv = to_d(ws);
+      }
+      if (k <= j) acc += wv * to_d(kl[u]);
+      else acc += wv * wv;
+    }
   }
   double t = block_sum(acc, sh);
   if (threadIdx.x == 0) part_cur[b] = t;
@@ -781,7 +814,20 @@ __global__ void __launch_bounds__(BS) k_mgs_finish(T* __restrict__ V, int64_t ld
   const double w0 = sqrt(inst_sum(part_w0, first, i, sh));
   T* w = V + (int64_t)(j + 1) * ld;
   const double sc = hn > 0.0 ? 1.0 / hn : 0.0;
-  for (int64_t e = bstart[b] + threadIdx.x; e < bend[b]; e += blockDim.x) w[e] = from_d<T>(to_d(w[e]) * sc);
+  {
+    constexpr int U = 8;
+    const int64_t e1 = bend[b];
+    for (int64_t e0 = bstart[b] + threadIdx.x; e0 < e1; e0 += (int64_t)U * BS) {
+      T wl[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) wl[u] = w[min(e0 + (int64_t)u * BS, e1 - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = e0 + (int64_t)u * BS;
+        if (e < e1) w[e] = from_d<T>(to_d(wl[u]) * sc);
+      }
+    }
+  }
   if (b != first[i] || threadIdx.x != 0) return;
   double* Hc = H + (int64_t)i * (m + 1) * m;  // Hc[row * m + col]
   double* c = cs + (int64_t)i * m;
