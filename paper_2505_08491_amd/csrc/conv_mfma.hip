@@ -235,6 +235,130 @@ __global__ void __launch_bounds__(WAVES * 64) k_conv_mfma(MfmaArgs p) {
   }
 }
 
+// The column x = n - 1 of a stride-1 layer (left out by the sweep kernels):
+// one workgroup of KSW waves per plane z, covering all of that column's
+// blocks of 16 consecutive y (at most YB of them) so that every weight
+// fragment loaded serves YB MFMAs; wave w accumulates the K chunks c = w,
+// w + KSW, ...; the partial sums meet in LDS and the waves finish the
+// (block, output block) fragments in turn (bias, ReLU, BF16 store).  IN = 1
+// builds the first layer's input.
+template <int CA, int CB, int COUT, int IN, typename Tv, int KSW, int YB>
+__global__ void __launch_bounds__(KSW * 64) k_conv_edge(MfmaArgs p) {
+  constexpr int CIN = CA + CB;
+  constexpr int NB = COUT / 16;
+  constexpr int KCH = (27 * CIN + 31) / 32;
+  extern __shared__ __attribute__((aligned(16))) unsigned char edge_lds[];
+  f32x4* red = (f32x4*)edge_lds;  // [KSW][YB][NB][64]
+  const int bt = blockIdx.z;
+  if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
+  const int n = p.n_out;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, r = lane & 15;
+  const int nyb = (n + 15) / 16;
+  const int oz = blockIdx.x, ox = n - 1;
+  const int64_t nn = (int64_t)n * n, nv = nn * n;
+  int64_t base[YB];
+  unsigned msk[YB];
+#pragma unroll
+  for (int m = 0; m < YB; ++m) {
+    const int oy = m * 16 + r;
+    const bool ok = m < nyb && oy < n;
+    base[m] = ((int64_t)oz * n + (ok ? oy : 0)) * n + ox;
+    unsigned mk = 0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (ox + t - 1 >= 0 && ox + t - 1 < n) mk |= 1u << t;
+      if (oy + t - 1 >= 0 && oy + t - 1 < n) mk |= 1u << (3 + t);
+      if (oz + t - 1 >= 0 && oz + t - 1 < n) mk |= 1u << (6 + t);
+    }
+    msk[m] = ok ? mk : 0u;
+  }
+  const bf16* A = IN ? nullptr : p.a + (int64_t)bt * nv * CA;
+  const bf16* B = CB ? p.b + (int64_t)bt * nv * CB : nullptr;
+  const Tv* Z = IN ? (const Tv*)p.z + p.off[bt] : nullptr;
+  const float* D = IN ? p.dist + (int64_t)bt * nv : nullptr;
+  const float sc = IN ? (float)p.inv_s[bt] : 0.0f;
+  f32x4 acc[YB][NB];
+#pragma unroll
+  for (int m = 0; m < YB; ++m)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[m][nb] = {0.f, 0.f, 0.f, 0.f};
+  for (int c = wave; c < KCH; c += KSW) {
+    const int k0 = c * 32 + g * 8;
+    const int tap = k0 / CIN;
+    const int ci = k0 - tap * CIN;
+    const bool tap_ok = tap < 27;
+    const int tz = tap / 9, ty = (tap / 3) % 3, tx = tap % 3;
+    const unsigned need = (1u << tx) | (8u << ty) | (64u << tz);
+    const int64_t toff = (int64_t)(tz - 1) * nn + (int64_t)(ty - 1) * n + (tx - 1);
+    bf16x8 wf[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      wf[nb] = tap_ok ? load8(p.w + ((int64_t)(nb * 16 + r) * 27 + tap) * CIN + ci) : zero8();
+    bf16x8 x[YB];
+#pragma unroll
+    for (int m = 0; m < YB; ++m) {
+      x[m] = zero8();
+      if (tap_ok && (msk[m] & need) == need) {
+        const int64_t vin = base[m] + toff;
+        if (IN) x[m] = pack2((float)Z[vin] * sc, D[vin]);
+        else if (CB == 0 || ci < CA) x[m] = load8(A + vin * CA + ci);
+        else x[m] = load8(B + vin * CB + (ci - CA));
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < YB; ++m)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[nb], x[m], acc[m][nb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int m = 0; m < YB; ++m)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) red[((wave * YB + m) * NB + nb) * 64 + lane] = acc[m][nb];
+  __syncthreads();
+  bf16* Y = p.y + (int64_t)bt * nv * COUT;
+  for (int f = wave; f < nyb * NB; f += KSW) {
+    const int m = f / NB, nb = f - m * NB;
+    f32x4 sum = red[(m * NB + nb) * 64 + lane];
+    for (int w = 1; w < KSW; ++w) {
+      const f32x4 o = red[((w * YB + m) * NB + nb) * 64 + lane];
+      sum += o;
+    }
+    const int oy = m * 16 + r;
+    if (oy >= n) continue;
+    const int co = nb * 16 + g * 4;
+    float y0 = sum[0] + p.bias[co], y1 = sum[1] + p.bias[co + 1];
+    float y2 = sum[2] + p.bias[co + 2], y3 = sum[3] + p.bias[co + 3];
+    if (p.relu) {
+      y0 = fmaxf(y0, 0.f); y1 = fmaxf(y1, 0.f); y2 = fmaxf(y2, 0.f); y3 = fmaxf(y3, 0.f);
+    }
+    uint2 pk;
+    pk.x = (unsigned)f2bf(y0) | ((unsigned)f2bf(y1) << 16);
+    pk.y = (unsigned)f2bf(y2) | ((unsigned)f2bf(y3) << 16);
+    const int64_t v = ((int64_t)oz * n + oy) * n + ox;
+    *(uint2*)(Y + v * COUT + co) = pk;
+  }
+}
+
+template <int CA, int CB, int COUT, int IN, typename Tv>
+void launch_edge(const MfmaArgs& a, int batch, hipStream_t stream) {
+  constexpr int KSW = 8, YB = 5;  // up to 80 rows: n <= 80
+  constexpr size_t lds = (size_t)KSW * YB * (COUT / 16) * 64 * 16;
+  static_assert(lds <= 160 * 1024, "edge partials exceed LDS");
+  const int n = a.n_out;
+  if (n > 16 * YB) {  // the global-load kernel's edge mode
+    constexpr int MBE = 1;
+    const int64_t nmb = ((int64_t)n * n + 15) / 16;
+    const dim3 grid((unsigned)((nmb + WAVES * MBE - 1) / (WAVES * MBE)), 1, batch);
+    hipLaunchKernelGGL((k_conv_mfma<CA, CB, COUT, 1, MBE, IN, 0, Tv, 1>), grid, dim3(WAVES * 64), 0, stream, a);
+    return;
+  }
+  auto kern = k_conv_edge<CA, CB, COUT, IN, Tv, KSW, YB>;
+  if (lds > 65536) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(kern, dim3((unsigned)n, 1, batch), dim3(KSW * 64), lds, stream, a);
+}
+
 // Stride-1 convolution with the input tile staged in LDS.  A workgroup owns the
 // output rows y0..y0+TY-1 of the planes z0..z0+TZ-1 for x in [0, n-1) (the
 // column x = n-1 is left to the EDGE variant of k_conv_mfma, so that every
@@ -950,6 +1074,185 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// Stride-1 convolution with COUT = 32 or 64 (the coarse levels), z-sweep with
+// a three-plane LDS ring over rows y0 - 1 .. y0 + MB (x = -1 .. n - 1, zero
+// outside), the next plane staged in registers while the current one is
+// computed.  XB * KG waves: wave (xq, kg) owns x block xq and the K chunks
+// [kg KPG, (kg + 1) KPG) for all NB = COUT / 16 output blocks, with those
+// weights in registers; as in the 16-channel kernels one input fragment (row
+// j) serves the output rows j - 2 .. j.  The KG partial sums meet in LDS and
+// each wave finishes (sum, bias, ReLU, store) every KG-th output fragment.
+template <int CA, int CB, int COUT, int MB, int KG, int NPF>
+__global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
+  constexpr int CIN = CA + CB;
+  typedef RowsTile<CIN, 0> T;
+  constexpr int CLP = T::CLP;
+  constexpr int CPV = T::CPV;
+  constexpr int NB = COUT / 16;
+  constexpr int KCT = RowsK<CIN, 0>::KCT;
+  constexpr int KPG = (KCT + KG - 1) / KG;   // chunk slots per wave
+  constexpr int YW = MB + 2;
+  constexpr int NF = MB * NB;                // output fragments per x block
+  constexpr int CPA = CA / 8;
+  extern __shared__ __attribute__((aligned(1024))) unsigned short ring[];
+  int bxr, bt;
+  xcd_remap(bxr, bt);
+  if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
+  const int n = p.n_out;
+  const int XW = n + 1;
+  const int y0 = q.ylo + (bxr % q.ytiles) * MB;
+  const int z0 = q.zlo + (bxr / q.ytiles) * q.zc;
+  const int zend = min(q.zhi, z0 + q.zc);
+  const int64_t nv = (int64_t)n * n * n;
+  const int nthr = blockDim.x;
+  const int xbn = (n - 1) / 16;
+  const int plane_elems = (int)(T::plane_bytes(MB, n) / 2);
+  const int plane_items = YW * XW * CPV;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int g = lane >> 4, r = lane & 15;
+  const int xq = wave % xbn, kg = wave / xbn;
+  f32x4* red = (f32x4*)(ring + (size_t)3 * plane_elems);  // [KG][xbn][NF][64]
+  const bf16* A = p.a + (int64_t)bt * nv * CA;
+  const bf16* B = CB ? p.b + (int64_t)bt * nv * CB : nullptr;
+  auto load_plane = [&](int gz, u32x4 (&buf)[NPF]) {
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+      const int it = threadIdx.x + k * nthr;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (it < plane_items) {
+        const int vt = it / CPV, ch = it - vt * CPV;
+        const int row = vt / XW, xx = vt - row * XW;
+        const int gx = xx - 1, gy = y0 + row - 1;
+        if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0) {
+          const int64_t vv = ((int64_t)gz * n + gy) * n + gx;
+          v = (CB == 0 || ch < CPA) ? *(const u32x4*)(A + vv * CA + ch * 8)
+                                    : *(const u32x4*)(B + vv * CB + (ch - CPA) * 8);
+        }
+      }
+      buf[k] = v;
+    }
+  };
+  auto store_plane = [&](int slot, const u32x4 (&buf)[NPF]) {
+    unsigned short* pl = ring + (size_t)slot * plane_elems;
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+      const int it = threadIdx.x + k * nthr;
+      if (it < plane_items) {
+        const int vt = it / CPV, ch = it - vt * CPV;
+        *(u32x4*)(pl + (size_t)vt * CLP + ch * 8) = buf[k];
+      }
+    }
+  };
+  // weights of this wave's chunks, [16 cout][3 ty][KCT * 32] per output block
+  const int cb = kg * KPG;
+  bf16x8 wr[3][KPG][NB];
+  int lofs[KPG], ltz[KPG];
+  bool lok[KPG];
+  {
+    const unsigned short* wsrc = (const unsigned short*)p.wrows;
+#pragma unroll
+    for (int i = 0; i < KPG; ++i) {
+      const int c = cb + i;
+      const bool cin = c < KCT;
+#pragma unroll
+      for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          wr[ty][i][nb] =
+              cin ? __builtin_bit_cast(bf16x8, *(const u32x4*)(wsrc + ((nb * 16 + r) * 3 + ty) * (KCT * 32) + c * 32 + g * 8))
+                  : zero8();
+      const int k = c * 32 + g * 8;
+      const int pp = k / CIN, ci = k - pp * CIN;
+      lok[i] = cin && pp < 9;
+      ltz[i] = lok[i] ? pp / 3 : 0;
+      lofs[i] = (lok[i] ? pp % 3 : 0) * CLP + ci;
+    }
+  }
+  const int nch = min(KPG, KCT - cb);  // chunks of this wave (wave-uniform)
+  const int xl = xq * 16 + r;
+  u32x4 pf[NPF];
+  load_plane(z0 - 1, pf);
+  store_plane(0, pf);
+  load_plane(z0, pf);
+  store_plane(1, pf);
+  load_plane(z0 + 1, pf);
+  for (int z = z0; z < zend; ++z) {
+    const int s0 = (z - z0) % 3;
+    store_plane((s0 + 2) % 3, pf);
+    __syncthreads();
+    if (z + 1 < zend) load_plane(z + 2, pf);
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[m][nb] = {0.f, 0.f, 0.f, 0.f};
+    auto fetch = [&](int i, bf16x8 (&xf)[MB + 2]) {
+      const unsigned short* base = ring + (size_t)((s0 + ltz[i]) % 3) * plane_elems + (size_t)xl * CLP + lofs[i];
+#pragma unroll
+      for (int j = 0; j < MB + 2; ++j)
+        xf[j] = lok[i] ? __builtin_bit_cast(bf16x8, *(const u32x4*)(base + (size_t)j * XW * CLP)) : zero8();
+    };
+    auto mma = [&](int i, const bf16x8 (&xf)[MB + 2]) {
+#pragma unroll
+      for (int j = 0; j < MB + 2; ++j)
+#pragma unroll
+        for (int ty = 0; ty < 3; ++ty) {
+          const int m = j - ty;
+          if (m >= 0 && m < MB) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+              acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[ty][i][nb], xf[j], acc[m][nb], 0, 0, 0);
+          }
+        }
+    };
+    if (nch > 0) {
+      bf16x8 xa[MB + 2], xb[MB + 2];
+      fetch(0, xa);
+#pragma unroll
+      for (int i = 0; i < KPG; i += 2) {
+        if (i + 1 < KPG) fetch(i + 1, xb);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(i, xa);
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + 2 < KPG) fetch(i + 2, xa);
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + 1 < KPG) mma(i + 1, xb);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    // partial sums to LDS: red[kg][xq][f][lane], f = m * NB + nb
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        red[((size_t)(kg * xbn + xq) * NF + m * NB + nb) * 64 + lane] = acc[m][nb];
+    __syncthreads();
+    // this wave finishes fragments f = kg, kg + KG, ... of x block xq
+    bf16* Y = p.y + (int64_t)bt * nv * COUT;
+    for (int f = kg; f < NF; f += KG) {
+      f32x4 sum = red[((size_t)xq * NF + f) * 64 + lane];
+      for (int k2 = 1; k2 < KG; ++k2) {
+        const f32x4 o = red[((size_t)(k2 * xbn + xq) * NF + f) * 64 + lane];
+        sum += o;
+      }
+      const int m = f / NB, nb = f - m * NB;
+      const int y = y0 + m;
+      if (y >= q.yhi) continue;
+      const int co = nb * 16 + g * 4;
+      float y0v = sum[0] + p.bias[co], y1v = sum[1] + p.bias[co + 1];
+      float y2v = sum[2] + p.bias[co + 2], y3v = sum[3] + p.bias[co + 3];
+      if (p.relu) {
+        y0v = fmaxf(y0v, 0.f); y1v = fmaxf(y1v, 0.f); y2v = fmaxf(y2v, 0.f); y3v = fmaxf(y3v, 0.f);
+      }
+      uint2 pk;
+      pk.x = (unsigned)f2bf(y0v) | ((unsigned)f2bf(y1v) << 16);
+      pk.y = (unsigned)f2bf(y2v) | ((unsigned)f2bf(y3v) << 16);
+      const int64_t v = ((int64_t)z * n + y) * n + xl;
+      *(uint2*)(Y + v * COUT + co) = pk;
+    }
+  }
+}
+
 // Stride-2 transposed convolution, one output parity class (px, py, pz) per
 // blockIdx.y.  Output o = 2 q + p along each axis; p = 0 takes tap 1 from input
 // q, p = 1 takes tap 0 from input q + 1 and tap 2 from input q.
@@ -1091,12 +1394,8 @@ void launch_s1(const MfmaArgs& a, int batch, hipStream_t stream) {
   else if (ty == 4) launch_s1_tiled<CA, CB, COUT, 4, IN, EPI, Tv, 0>(a, batch, lds, w4, stream);
   else if (wl) launch_s1_tiled<CA, CB, COUT, 2, IN, EPI, Tv, WSMALL ? 1 : 0>(a, batch, lds, w2, stream);
   else launch_s1_tiled<CA, CB, COUT, 2, IN, EPI, Tv, 0>(a, batch, lds, w2, stream);
-  // the x = n - 1 column
-  constexpr int MBE = 1;
-  const int64_t nmb = ((int64_t)n * n + 15) / 16;
-  const dim3 grid((unsigned)((nmb + WAVES * MBE - 1) / (WAVES * MBE)), 1, batch);
-  hipLaunchKernelGGL((k_conv_mfma<IN ? 8 : CA, CB, COUT, 1, MBE, IN, EPI, Tv, 1>), grid, dim3(WAVES * 64), 0, stream,
-                     a);
+  // the x = n - 1 column (Dirichlet when the head is fused: nothing to write)
+  if (!EPI) launch_edge<IN ? 8 : CA, CB, COUT, IN, Tv>(a, batch, stream);
 }
 
 // Full-resolution 16-channel layers: the row-reuse sweep for x < n - 1 plus the
@@ -1138,13 +1437,7 @@ void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream) {
     if (need <= NPF0) launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF0>(a, q, batch, lds, xb, stream);
     else launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF1>(a, q, batch, lds, xb, stream);
   }
-  if (!EPI) {
-    constexpr int MBE = 1;
-    const int64_t nmb = ((int64_t)n * n + 15) / 16;
-    const dim3 grid((unsigned)((nmb + WAVES * MBE - 1) / (WAVES * MBE)), 1, batch);
-    hipLaunchKernelGGL((k_conv_mfma<IN ? 8 : CA, CB, 16, 1, MBE, IN, EPI, Tv, 1>), grid, dim3(WAVES * 64), 0, stream,
-                       a);
-  }
+  if (!EPI) launch_edge<IN ? 8 : CA, CB, 16, IN, Tv>(a, batch, stream);
 }
 
 // Stored 16-channel layers: the two-waves-per-SIMD sweep for x < n - 1 plus
@@ -1177,12 +1470,36 @@ void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream) {
   auto kern = k_conv16_ks<CA, CB, MB, KS, EPI, Tv, NLW>;
   if (lds > 65536) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(kern, dim3((unsigned)(q.ytiles * nz), 1, batch), dim3(2 * xb * 64), lds, stream, a, q);
-  if (!EPI) {
-    constexpr int MBE = 1;
-    const int64_t nmb = ((int64_t)n * n + 15) / 16;
-    const dim3 grid((unsigned)((nmb + WAVES * MBE - 1) / (WAVES * MBE)), 1, batch);
-    hipLaunchKernelGGL((k_conv_mfma<CA, CB, 16, 1, MBE, 0, EPI, Tv, 1>), grid, dim3(WAVES * 64), 0, stream, a);
+  if (!EPI) launch_edge<CA, CB, 16, 0, Tv>(a, batch, stream);
+}
+
+// Coarse-level stride-1 layers (COUT = 32 or 64): the K-split sweep for
+// x < n - 1 plus the EDGE kernel for x = n - 1; launch_s1 where it does not fit.
+template <int CA, int CB, int COUT, int MB, int KG, int NPF>
+void launch_convw(const MfmaArgs& a, int batch, hipStream_t stream) {
+  typedef RowsTile<CA + CB, 0> T;
+  constexpr int NF = MB * (COUT / 16);
+  const int n = a.n_out;
+  const int xb = (n - 1) / 16;
+  const size_t lds = 3 * T::plane_bytes(MB, n) + (size_t)KG * xb * NF * 1024;
+  const bool fits = (n - 1) % 16 == 0 && xb >= 1 && xb * KG <= 8 && lds <= 160 * 1024 &&
+                    (MB + 2) * (n + 1) * T::CPV <= NPF * xb * KG * 64;
+  if (!fits) {
+    launch_s1<CA, CB, COUT, 0, 0, float>(a, batch, stream);
+    return;
   }
+  RowsGrid q;
+  q.ylo = q.zlo = 0;
+  q.yhi = q.zhi = n;
+  q.ytiles = (n + MB - 1) / MB;
+  int nz = (1024 + q.ytiles * batch - 1) / (q.ytiles * batch);
+  nz = std::max(1, std::min(nz, n));
+  q.zc = (n + nz - 1) / nz;
+  nz = (n + q.zc - 1) / q.zc;
+  auto kern = k_convw<CA, CB, COUT, MB, KG, NPF>;
+  if (lds > 65536) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(q.ytiles * nz), 1, batch), dim3(xb * KG * 64), lds, stream, a, q);
+  launch_edge<CA, CB, COUT, 0, float>(a, batch, stream);
 }
 
 MfmaArgs args_from(const ConvP& p, const bf16* w) {
@@ -1241,14 +1558,14 @@ static int64_t mfma_weight_count() {
   return tot;
 }
 
-// Row-reuse weight layout [16][3 ty][KCT * 32] of a 16-channel stride-1 layer.
+// Row-reuse weight layout [COUT][3 ty][KCT * 32] of a stride-1 layer.
 // IN = 1 (two input channels): k = 8 tz + 2 tx + ch for tz < 3, else zero.
 // Otherwise k = (3 tz + tx) * CIN + ci, zero from 9 CIN on.
-template <int CIN, int IN>
+template <int CIN, int IN, int COUT = 16>
 __global__ void k_w_rows(const float* __restrict__ w, bf16* __restrict__ o) {
   constexpr int KCT = RowsK<CIN, IN>::KCT;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= 16 * 3 * KCT * 32) return;
+  if (k >= COUT * 3 * KCT * 32) return;
   const int kk = k % (KCT * 32), ty = (k / (KCT * 32)) % 3, co = k / (3 * KCT * 32);
   float v = 0.0f;
   if (IN) {
@@ -1266,6 +1583,9 @@ constexpr int64_t kRowsIn0 = 16 * 3 * RowsK<2, 1>::KCT * 32;
 constexpr int64_t kRowsL0b = 16 * 3 * RowsK<16, 0>::KCT * 32;
 constexpr int64_t kRowsD0 = 16 * 3 * RowsK<32, 0>::KCT * 32;
 
+constexpr int64_t kRowsL1b = 32 * 3 * RowsK<32, 0>::KCT * 32;
+constexpr int64_t kRowsL2b = 64 * 3 * RowsK<64, 0>::KCT * 32;
+constexpr int64_t kRowsD1 = 32 * 3 * RowsK<64, 0>::KCT * 32;
 constexpr int64_t kZeroCount = 128;  // 256 zero bytes
 
 struct MfmaWeights {
@@ -1273,18 +1593,29 @@ struct MfmaWeights {
   const bf16* rows_in0;
   const bf16* rows_l0b;
   const bf16* rows_d0;
+  const bf16* rows_l1b;
+  const bf16* rows_l2b;
+  const bf16* rows_d1;
   const bf16* zeros;
 };
 
 static MfmaWeights mfma_extra(const CnnState& c) {
   const bf16* e = c.wmf + mfma_weight_count();
-  const bf16* r0 = e + kIn8Count;
-  return {e, r0, r0 + kRowsIn0, r0 + kRowsIn0 + kRowsL0b, r0 + kRowsIn0 + kRowsL0b + kRowsD0};
+  MfmaWeights x;
+  x.in8 = e;
+  x.rows_in0 = x.in8 + kIn8Count;
+  x.rows_l0b = x.rows_in0 + kRowsIn0;
+  x.rows_d0 = x.rows_l0b + kRowsL0b;
+  x.rows_l1b = x.rows_d0 + kRowsD0;
+  x.rows_l2b = x.rows_l1b + kRowsL1b;
+  x.rows_d1 = x.rows_l2b + kRowsL2b;
+  x.zeros = x.rows_d1 + kRowsD1;
+  return x;
 }
 
 void cnn_prepare_mfma_weights(CnnState& c, const float* d_w, hipStream_t stream) {
   const int64_t tot = mfma_weight_count();
-  const int64_t extra = kIn8Count + kRowsIn0 + kRowsL0b + kRowsD0 + kZeroCount;
+  const int64_t extra = kIn8Count + kRowsIn0 + kRowsL0b + kRowsD0 + kRowsL1b + kRowsL2b + kRowsD1 + kZeroCount;
   if (!c.wmf && hipMalloc(&c.wmf, sizeof(bf16) * (size_t)(tot + extra)) != hipSuccess) {
     c.wmf = nullptr;
     return;
@@ -1299,6 +1630,12 @@ void cnn_prepare_mfma_weights(CnnState& c, const float* d_w, hipStream_t stream)
                      (bf16*)x.rows_l0b);
   hipLaunchKernelGGL((k_w_rows<32, 0>), dim3((kRowsD0 + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[9],
                      (bf16*)x.rows_d0);
+  hipLaunchKernelGGL((k_w_rows<32, 0, 32>), dim3((kRowsL1b + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[3],
+                     (bf16*)x.rows_l1b);
+  hipLaunchKernelGGL((k_w_rows<64, 0, 64>), dim3((kRowsL2b + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[5],
+                     (bf16*)x.rows_l2b);
+  hipLaunchKernelGGL((k_w_rows<64, 0, 32>), dim3((kRowsD1 + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[7],
+                     (bf16*)x.rows_d1);
   for (int l = 0; l < kNumLayers; ++l) {
     const LayerSpec& L = kLayers[l];
     const int64_t nw = (int64_t)L.cout * (L.kind == KIND_PT ? 1 : 27) * L.cin;
@@ -1383,11 +1720,26 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
       break;
     }
     case 2: launch_conv<16, 0, 32, 2, 4>(p, batch, w, stream); break;    // L1a
-    case 3: launch_conv<32, 0, 32, 1, 4>(p, batch, w, stream); break;    // L1b
+    case 3: {                                                             // L1b
+      MfmaArgs a = args_from(p, w);
+      a.wrows = mfma_extra(c).rows_l1b;
+      launch_convw<32, 0, 32, 3, 4, 2>(a, batch, stream);
+      break;
+    }
     case 4: launch_conv<32, 0, 64, 2, 2>(p, batch, w, stream); break;    // L2a
-    case 5: launch_conv<64, 0, 64, 1, 2>(p, batch, w, stream); break;    // L2b
+    case 5: {                                                             // L2b
+      MfmaArgs a = args_from(p, w);
+      a.wrows = mfma_extra(c).rows_l2b;
+      launch_convw<64, 0, 64, 2, 8, 2>(a, batch, stream);
+      break;
+    }
     case 6: launch_tconv<64, 32, 4>(p, batch, w, stream); break;         // U1
-    case 7: launch_conv<32, 32, 32, 1, 4>(p, batch, w, stream); break;   // D1
+    case 7: {                                                             // D1
+      MfmaArgs a = args_from(p, w);
+      a.wrows = mfma_extra(c).rows_d1;
+      launch_convw<32, 32, 32, 3, 4, 3>(a, batch, stream);
+      break;
+    }
     case 8: launch_tconv<32, 16, 4>(p, batch, w, stream); break;         // U0
     case 9: {                                                             // D0
       MfmaArgs a = args_from(p, w);
