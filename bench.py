@@ -57,6 +57,49 @@ def spmv_bytes(S, vec_bytes=4):
     return 2 * S.ntot * vec_bytes + m_nnz * (vec_bytes + 4) + m_rows * 8
 
 
+def unet_flops(n):
+    """Algorithmic FLOPs of one U-net forward at grid side n (n = 2^k + 1):
+    2 * taps * Cin * Cout per output voxel; a strided convolution counts its
+    27 taps (zero padding included), the transposed convolution the taps that
+    reach each output parity (1, 2 or 4 or 8), the head 1 tap."""
+    from paper_2505_08491_amd.weights import LAYERS
+    sizes = [n, (n + 1) // 2, (n + 3) // 4]
+    lvl = {"L0a": 0, "L0b": 0, "L1a": 1, "L1b": 1, "L2a": 2, "L2b": 2, "U1": 1, "D1": 1, "U0": 0, "D0": 0, "H": 0}
+    tot = 0
+    for name, kind, ci, co, _ in LAYERS:
+        m = sizes[lvl[name]]
+        if kind == "t2":
+            ne = (m + 1) // 2
+            taps = (ne + 2 * (m - ne)) ** 3      # output sides: even index 1 tap, odd 2 taps
+            tot += 2 * taps * ci * co
+        else:
+            tot += 2 * (1 if kind == "pt" else 27) * ci * co * m ** 3
+    return tot
+
+
+def spmv_traffic(S):
+    """HBM bytes per batched SpMV launch from the committed rocprofv3 PMC
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel), or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "spmv_64x16_traffic.txt")
+    src = os.path.join(ROOT, "paper_2505_08491_amd", "csrc", "krylov.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("krylov.hip sha256") != digest:
+        return None
+    try:
+        return float(fields["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def time_kernel(ctx, fn, reps):
     """Average duration (ms) of `fn` launches measured with HIP events on the
     library's stream."""
@@ -166,9 +209,21 @@ def main():
     xs = torch.randn(S.ntot, device="cuda")
     ms_spmv = time_kernel(ctx, lambda: S.spmv(xs), 20)
     gbps = spmv_bytes(S) / (ms_spmv * 1e-3) / 1e9
+    # practical copy bandwidth (1 GiB device-to-device) on the same stream
+    cbuf = torch.empty(2, 1 << 28, device="cuda")
+    with torch.cuda.stream(ctx.stream):
+        ms_copy = time_kernel(ctx, lambda: cbuf[1].copy_(cbuf[0]), 10)
+    copy_gbps = 2 * cbuf[0].numel() * 4 / (ms_copy * 1e-3) / 1e9
+    del cbuf
     # preconditioner application (1D solve + extension + U-net + unscale) on the batch
     ms_prec = time_kernel(ctx, lambda: S.precond_apply(xs), 5)
-    cnn_flop = 22.0e9 * (a.n_cells / 64) ** 3 * S.n_inst
+    n = a.n_cells + 1
+    cnn_flop = unet_flops(n) * S.n_inst
+    # the network alone (stored activations, BF16 MFMA) on the same batch
+    wd = torch.from_numpy(np.ascontiguousarray(w, dtype=np.float32)).cuda()
+    xin = torch.randn(S.n_inst, n ** 3, 2, device="cuda")
+    ms_cnn = time_kernel(ctx, lambda: ctx.cnn_forward(wd, xin, n, a.cnn_dtype), 5)
+    del xin
 
     jac = None
     if not a.skip_jacobi:
@@ -193,9 +248,14 @@ def main():
         "neural": {"iters_mean": float(np.mean(neural_iters)), "iters_max": int(max(neural_iters)),
                    "converged_all": conv_all, "used_fallback": int(n_fb), "max_true_rel_res": max(rel_n)},
         "jacobi": jac,
-        "roofline": {"bound": "hbm", "kernel": "k_stencil + k_mrows (batched y = (S + M) x, FP32)", "achieved": gbps,
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
-                     "algorithmic_bytes": spmv_bytes(S), "ms_per_launch": ms_spmv},
+        "roofline": {"bound": "hbm", "kernel": "k_stencil_sweep + k_mrows (batched y = (S + M) x, FP32)",
+                     "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+                     "traffic": spmv_traffic(S), "algorithmic_bytes": spmv_bytes(S), "ms_per_launch": ms_spmv,
+                     "copy_gbps": copy_gbps},
+        "unet": {"bound": "mfma", "dtype": a.cnn_dtype, "gflop_per_forward": cnn_flop / 1e9,
+                 "ms_per_forward": ms_cnn, "achieved": cnn_flop / (ms_cnn * 1e-3) / 1e12,
+                 "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": cnn_flop / (ms_cnn * 1e-3) / 1e12 / BF16_PEAK_TFLOPS},
         "preconditioner": {"ms_per_apply": ms_prec, "cnn_tflops": cnn_flop / (ms_prec * 1e-3) / 1e12},
         "upload_s": t_upload,
     }
