@@ -317,3 +317,77 @@ def test_loss_grad_matches_oracle(ctx):
         g = -2 * (A00 @ e) / s.alpha
         g[s.boundary] = 0
         assert np.linalg.norm(du[k] - g) <= 1e-5 * np.linalg.norm(g)
+
+
+# ---------------------------------------------------------------- bench configuration (64^3 cells, 512 x 16 trees)
+
+@pytest.fixture(scope="module")
+def bench64(ctx):
+    """Two instances of the benchmark workload (the timed launch configuration:
+    65^3 grids, 8193-node trees) with their oracle assemblies."""
+    P = _P()
+    insts = synth.workload_transfer(64, 2)
+    S = P.System(ctx, insts, vec_dtype="f32")
+    systems = [fem.assemble(i) for i in insts]
+    yield S, insts, systems
+    S.free()
+
+
+def test_spmv_bench_config(ctx, bench64):
+    """y = A x at the benchmark size: stencil sweep + coupling rows vs the oracle CSR."""
+    S, _, systems = bench64
+    A, _ = oracle_block(systems)
+    x = synth.fast_normal(11, A.shape[0]).astype(np.float32)
+    y = S.spmv(dev(x, torch.float32)).cpu().double().numpy()
+    ref = A @ x.astype(np.float64)
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) <= 1e-6
+
+
+def test_tree_solve_bench_config(ctx, bench64):
+    """Chain-compressed A11^-1 on 8193-node trees (512 segments x 15 interior nodes)."""
+    S, _, systems = bench64
+    v = synth.fast_normal(12, S.ntot).astype(np.float32)
+    z = S.tree_solve(dev(v, torch.float32)).cpu().double().numpy()
+    for k, s in enumerate(systems):
+        o0 = S.offsets[k] + s.n3d
+        v1 = v[o0:o0 + s.n1d].astype(np.float64)
+        Q = krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s))
+        ref = Q.solve_1d(v1)
+        assert np.linalg.norm(z[o0:o0 + s.n1d] - ref) / np.linalg.norm(ref) <= 1e-6, k
+
+
+def test_cnn_forward_bench_grid(ctx):
+    """The whole network at 65^3 (BF16): every conv kernel in the launch shapes
+    of the benchmark (level grids 65, 33, 17)."""
+    n, batch = 65, 2
+    th = _theta(4)
+    rng = np.random.default_rng(9)
+    X = np.stack([rng.normal(size=(n, n, n)) / n ** 1.5, rng.uniform(0, 0.5, (n, n, n))], axis=-1)
+    X = np.stack([X, X[:, ::-1].copy()])
+    y = ctx.cnn_forward(dev(th, torch.float32), dev(X.reshape(batch, -1, 2), torch.float32), n, "bf16")
+    y = y.cpu().double().numpy()
+    th64 = th.astype(np.float32).astype(np.float64)
+    for k in range(batch):
+        ref = ocnn.forward(th64, X[k].astype(np.float32).astype(np.float64))[0]
+        err = np.linalg.norm(y[k] - ref.ravel()) / np.linalg.norm(ref)
+        assert err <= 4e-2, (k, err)
+
+
+def test_neural_precond_bench_config(ctx, bench64):
+    """Q(v) at the benchmark size with the trained weights: first-layer input
+    built from the Krylov vector, fused D0 + head + unscaling, 1D solve and
+    extension, against the FP64 oracle."""
+    from paper_2505_08491_amd import weights as W
+    S, _, systems = bench64
+    wpath = W.default_path()
+    th = W.load(wpath)[0] if __import__("os").path.exists(wpath + ".bin") else _theta(5).astype(np.float32)
+    S.set_preconditioner("neural", weights=th, cnn_dtype="bf16")
+    th64 = np.asarray(th, dtype=np.float32).astype(np.float64)
+    net = lambda X: ocnn.forward(th64, X)[0]
+    v = synth.fast_normal(13, S.ntot).astype(np.float32)
+    z = S.precond_apply(dev(v, torch.float32)).cpu().double().numpy()
+    for k, s in enumerate(systems):
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(v[o0:o1].astype(np.float64))
+        err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
+        assert err <= 5e-2, (k, err)
