@@ -127,7 +127,7 @@ void free_sys(mdnp_sys* s) {
   {
     auto& c = s->chain;
     void* cp[] = {c.meta, c.soff, c.fmul, c.eup, c.pinv, c.gp, c.gq, c.ap, c.aq, c.sp, c.sq, c.vparent, c.vseg,
-                  c.vchild_ptr, c.vchild_idx, c.vlvl_ptr, c.vlvl_nodes, c.vlval, c.vdinv};
+                  c.vchild_ptr, c.vchild_idx, c.vlvl_ptr, c.vlvl_nodes, c.vlval, c.vdinv, c.t01, c.zv};
     for (void* p : cp) dfree(p);
   }
   free_blocks(s->blk);
@@ -495,6 +495,7 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
         ok = ok && C.m <= kChainMaxM;
         cd.max_v = std::max(cd.max_v, V);
         cd.max_s = std::max(cd.max_s, S);
+        cd.max_m = std::max(cd.max_m, C.m);
         const int32_t m8[8] = {C.m, S, V, (int32_t)C.vlvl_ptr.size() - 1, (int32_t)sp.size(), (int32_t)vparent.size(),
                                (int32_t)vlp.size(), (int32_t)vci.size()};
         meta.insert(meta.end(), m8, m8 + 8);
@@ -549,6 +550,8 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
         cd.vlvl_nodes = dupload(vln, stream);
         cd.vlval = dupload(vlval, stream);
         cd.vdinv = dupload(vdinv, stream);
+        cd.t01 = dalloc<double>(2 * sp.size());
+        cd.zv = dalloc<double>(vparent.size());
         chain_solve_setup(cd.lds_bytes);
       }
     }

@@ -137,6 +137,7 @@ struct mdnp_sys {
   struct ChainDev {
     int enabled = 0;                 // all instances fit the on-chip form
     int max_v = 0, max_s = 0;        // largest vertex / segment count
+    int max_m = 0;                   // most interior nodes per segment
     size_t lds_bytes = 0;            // dynamic LDS of the solve kernel
     int32_t* meta = nullptr;         // [n_inst][8]: m, S, V, vlvl count, seg off, vtx off, vlvl off, vchild off
     int64_t* soff = nullptr;         // [n_inst][2]: offsets of the [m-1][S] and [m][S] step arrays
@@ -157,6 +158,8 @@ struct mdnp_sys {
     int32_t* vlvl_nodes = nullptr;
     double* vlval = nullptr;
     double* vdinv = nullptr;
+    double* t01 = nullptr;           // [segments][2] scratch: segment couplings
+    double* zv = nullptr;            // [vertices] scratch: FP64 vertex values
   } chain;
   mdnp::Blocks blk;                // whole vectors
   mdnp::Blocks blk3;               // 3D parts only

@@ -38,9 +38,10 @@ void tree_solve_setup(size_t shm_bytes);
 // chain-compressed tree solve: largest supported number of interior nodes per segment
 constexpr int kChainMaxM = 32;
 void chain_solve_setup(size_t shm_bytes);
-// LDS bytes of the chain-compressed solve for V vertices, S segments and nlev vertex levels
+// LDS bytes of the chain-compressed solve's vertex kernel for V vertices and nlev levels
 inline size_t chain_lds_bytes(int V, int S, int nlev) {
-  return sizeof(double) * (3 * (size_t)V + 2 * (size_t)S) + sizeof(int32_t) * (5 * (size_t)V + 2 + (size_t)nlev);
+  (void)S;
+  return sizeof(double) * 3 * (size_t)V + sizeof(int32_t) * (5 * (size_t)V + 2 + (size_t)nlev);
 }
 template <typename T>
 void launch_tree_solve(mdnp_sys* s, const T* v, T* z, const InstState* st, int want_mode,

@@ -38,6 +38,23 @@ __device__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// block_sum with barriers that wait for LDS traffic only (global loads issued
+// before it stay in flight); same order, same result.
+__device__ double block_sum_lds(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+  double t = 0.0;
+  for (int k = 0; k < nw; ++k) t += sh[k];
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+  return t;
+}
+
 // Sum of the partials of instance i (fixed order), result in every thread.
 __device__ double inst_sum(const double* part, const int32_t* first, int i, double* sh) {
   double t = 0.0;
@@ -482,40 +499,93 @@ __global__ void __launch_bounds__(BS) k_tree_solve(const T* __restrict__ v, T* _
 }
 
 // Chain-compressed solve z1 = A11^-1 v1 (same matrix as the leaves-first
-// LDL^T above, elimination grouped by segment), one block per instance:
-//  (a) every segment solves its tridiagonal block y = T^-1 v_c (one thread per
-//      segment, FP64 in registers) and leaves its couplings a_p y_0, a_q y_{m-1};
-//  (b) the vertices form the right-hand side of the Schur complement, a tree
-//      over the vertices, and solve it level by level in LDS;
-//  (c) every segment recomputes y and writes z_c = y - g_p z_p - g_q z_q.
+// LDL^T above, elimination grouped by segment), three launches:
+//  (a) k_chain_fwd, one thread per segment: y = T^-1 v_c for its tridiagonal
+//      block (FP64 in registers), leaving the couplings a_p y_0, a_q y_{m-1};
+//  (b) k_chain_vertex, one block per instance: the right-hand side of the
+//      Schur complement on the vertices (a tree over the segments), solved
+//      level by level with the vertex tree staged in LDS;
+//  (c) k_chain_back, one thread per segment: recompute y, write
+//      z_c = y - g_p z_p - g_q z_q.
 struct ChainArgs {
   const int32_t* meta;
   const int64_t* soff;
   const double *fmul, *eup, *pinv, *gp, *gq, *ap, *aq;
   const int32_t *sp, *sq, *vparent, *vseg, *vchild_ptr, *vchild_idx, *vlvl_ptr, *vlvl_nodes;
   const double *vlval, *vdinv;
+  double* t01;  // [segments][2]: a_p y_0, a_q y_{m-1}
+  double* zv;   // [vertices]: FP64 vertex values
 };
 
+// y = T_s^-1 v_c in w (w from the q end, then y from the p end).
+// All loads of a segment (indices clamped into range) are issued before the
+// two recurrences, which then run from registers; steps beyond m are masked
+// by selects.  MM >= m >= 1.
+template <typename T, int MM>
+__device__ __forceinline__ void chain_seg_solve(const T* __restrict__ vc, const double* fmul, const double* eup,
+                                                const double* pinv, int m, int S, int s, double (&w)[MM]) {
+  const int mm1 = m > 1 ? m - 2 : 0;  // last index of the [m - 1][S] arrays (clamped)
+  double vr[MM], fm[MM], eu[MM], pv[MM];
+#pragma unroll
+  for (int k = 0; k < MM; ++k) {
+    vr[k] = to_d(vc[min(k, m - 1)]);
+    fm[k] = fmul[(int64_t)min(k, mm1) * S + s];
+    eu[k] = eup[(int64_t)min(k > 0 ? k - 1 : 0, mm1) * S + s];
+    pv[k] = pinv[(int64_t)min(k, m - 1) * S + s];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  double wn = 0.0;
+#pragma unroll
+  for (int k = MM - 1; k >= 0; --k) {
+    const double wk = vr[k] - (k + 1 < m ? fm[k] * wn : 0.0);
+    w[k] = k < m ? wk : 0.0;
+    wn = k < m ? wk : wn;
+  }
+  double yp = 0.0;
+#pragma unroll
+  for (int k = 0; k < MM; ++k) {
+    const double yk = (k == 0 ? w[0] : w[k] - eu[k] * yp) * pv[k];
+    w[k] = k < m ? yk : w[k];
+    yp = yk;
+  }
+}
+
+template <typename T, int MM>
+__global__ void __launch_bounds__(64) k_chain_fwd(const T* __restrict__ v, const int64_t* off, int n3d, ChainArgs c,
+                                                  const InstState* st, int want_mode) {
+  const int i = blockIdx.y;
+  if (st && !mode_ok(st[i], want_mode)) return;
+  const int32_t* mt = c.meta + 8 * i;
+  const int m = mt[0], S = mt[1], V = mt[2], so = mt[4];
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= S) return;
+  double t0 = 0.0, t1 = 0.0;
+  if (m > 0) {
+    const int64_t o1 = c.soff[2 * i], o2 = c.soff[2 * i + 1];
+    double w[MM];
+    chain_seg_solve<T, MM>(v + off[i] + n3d + V + (int64_t)s * m, c.fmul + o1, c.eup + o1, c.pinv + o2, m, S, s, w);
+    double last = 0.0;
+#pragma unroll
+    for (int k = 0; k < MM; ++k)
+      if (k == m - 1) last = w[k];
+    t0 = c.ap[so + s] * w[0];
+    t1 = c.aq[so + s] * last;
+  }
+  c.t01[2 * (int64_t)(so + s)] = t0;
+  c.t01[2 * (int64_t)(so + s) + 1] = t1;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(512) k_chain_solve(const T* __restrict__ v, T* __restrict__ z, const int64_t* off,
-                                                     int n3d, ChainArgs c, const InstState* st, int want_mode) {
-  // LDS: vertex values, a_p y_0 and a_q y_{m-1} per segment, then the vertex
-  // tree (multipliers, inverse pivots, parents, parent segments, children,
-  // level lists) so that the level sweeps touch no global memory
+__global__ void __launch_bounds__(512) k_chain_vertex(const T* __restrict__ v, T* __restrict__ z, const int64_t* off,
+                                                      int n3d, ChainArgs c, const InstState* st, int want_mode) {
   extern __shared__ double cs[];
   const int i = blockIdx.x;
   if (st && !mode_ok(st[i], want_mode)) return;
   const int32_t* mt = c.meta + 8 * i;
-  const int m = mt[0], S = mt[1], V = mt[2], nlev = mt[3];
+  const int V = mt[2], nlev = mt[3];
   const int so = mt[4], vo = mt[5], lo = mt[6], co = mt[7];
-  const int64_t o1 = c.soff[2 * i], o2 = c.soff[2 * i + 1];
-  const double* fmul = c.fmul + o1;
-  const double* eup = c.eup + o1;
-  const double* pinv = c.pinv + o2;
   double* rv = cs;
-  double* t0 = rv + V;
-  double* t1 = t0 + S;
-  double* vl = t1 + S;
+  double* vl = rv + V;
   double* vd = vl + V;
   int32_t* vp = (int32_t*)(vd + V);
   int32_t* vsg = vp + V;
@@ -533,47 +603,17 @@ __global__ void __launch_bounds__(512) k_chain_solve(const T* __restrict__ v, T*
   }
   for (int u = threadIdx.x; u <= V; u += blockDim.x) vcp[u] = c.vchild_ptr[vo + i + u];
   for (int u = threadIdx.x; u <= nlev; u += blockDim.x) lp[u] = c.vlvl_ptr[lo + u];
-  const int64_t g0 = off[i] + n3d;  // first 1D unknown
-  const T* vv = v + g0;
-  T* zz = z + g0;
-  // tridiagonal solve of segment s: w from the q end, then y from the p end
-  auto seg_solve = [&](int s, double (&w)[kChainMaxM]) {
-    const T* vc = vv + V + (int64_t)s * m;
-#pragma unroll
-    for (int k = kChainMaxM - 1; k >= 0; --k) {
-      if (k < m) w[k] = to_d(vc[k]) - (k + 1 < m ? fmul[(int64_t)k * S + s] * w[k + 1] : 0.0);
-    }
-#pragma unroll
-    for (int k = 0; k < kChainMaxM; ++k) {
-      if (k < m) w[k] = (k == 0 ? w[0] : w[k] - eup[(int64_t)(k - 1) * S + s] * w[k - 1]) * pinv[(int64_t)k * S + s];
-    }
-  };
-  for (int s = threadIdx.x; s < S; s += blockDim.x) {
-    double w[kChainMaxM];
-    if (m > 0) {
-      seg_solve(s, w);
-      t0[s] = c.ap[so + s] * w[0];
-      double last = 0.0;
-#pragma unroll
-      for (int k = 0; k < kChainMaxM; ++k)
-        if (k == m - 1) last = w[k];
-      t1[s] = c.aq[so + s] * last;
-    } else {
-      t0[s] = 0.0;
-      t1[s] = 0.0;
-    }
-  }
   __syncthreads();
-  // right-hand side of the vertex system
+  const T* vv = v + off[i] + n3d;
+  const double* t01 = c.t01 + 2 * (int64_t)so;
   for (int u = threadIdx.x; u < V; u += blockDim.x) {
     double r = to_d(vv[u]);
     const int ps = vsg[u];
-    if (ps >= 0) r -= t1[ps];
-    for (int q = vcp[u]; q < vcp[u + 1]; ++q) r -= t0[vsg[vci[q]]];
+    if (ps >= 0) r -= t01[2 * ps + 1];
+    for (int q = vcp[u]; q < vcp[u + 1]; ++q) r -= t01[2 * vsg[vci[q]]];
     rv[u] = r;
   }
   __syncthreads();
-  // leaves-first LDL^T of the vertex tree
   for (int L = 0; L < nlev; ++L) {
     for (int k = lp[L] + threadIdx.x; k < lp[L + 1]; k += blockDim.x) {
       const int u = ln[k];
@@ -596,20 +636,39 @@ __global__ void __launch_bounds__(512) k_chain_solve(const T* __restrict__ v, T*
     }
     __syncthreads();
   }
-  for (int u = threadIdx.x; u < V; u += blockDim.x) zz[u] = from_d<T>(rv[u]);
-  // chain interiors
+  T* zz = z + off[i] + n3d;
+  for (int u = threadIdx.x; u < V; u += blockDim.x) {
+    zz[u] = from_d<T>(rv[u]);
+    c.zv[vo + u] = rv[u];
+  }
+}
+
+template <typename T, int MM>
+__global__ void __launch_bounds__(64) k_chain_back(const T* __restrict__ v, T* __restrict__ z, const int64_t* off,
+                                                   int n3d, ChainArgs c, const InstState* st, int want_mode) {
+  const int i = blockIdx.y;
+  if (st && !mode_ok(st[i], want_mode)) return;
+  const int32_t* mt = c.meta + 8 * i;
+  const int m = mt[0], S = mt[1], V = mt[2], so = mt[4], vo = mt[5];
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= S || m == 0) return;
+  const int64_t o1 = c.soff[2 * i], o2 = c.soff[2 * i + 1];
+  const int64_t g0 = off[i] + n3d + V + (int64_t)s * m;
+  double w[MM];
+  chain_seg_solve<T, MM>(v + g0, c.fmul + o1, c.eup + o1, c.pinv + o2, m, S, s, w);
+  const double zp = c.zv[vo + c.sp[so + s]], zq = c.zv[vo + c.sq[so + s]];
   const double* gp = c.gp + o2;
   const double* gq = c.gq + o2;
-  for (int s = threadIdx.x; s < S; s += blockDim.x) {
-    if (m == 0) continue;
-    double w[kChainMaxM];
-    seg_solve(s, w);
-    const double zp = rv[c.sp[so + s]], zq = rv[c.sq[so + s]];
-    T* zc = zz + V + (int64_t)s * m;
+  double gpr[MM], gqr[MM];
 #pragma unroll
-    for (int k = 0; k < kChainMaxM; ++k)
-      if (k < m) zc[k] = from_d<T>(w[k] - gp[(int64_t)k * S + s] * zp - gq[(int64_t)k * S + s] * zq);
+  for (int k = 0; k < MM; ++k) {
+    gpr[k] = gp[(int64_t)min(k, m - 1) * S + s];
+    gqr[k] = gq[(int64_t)min(k, m - 1) * S + s];
   }
+  T* zc = z + g0;
+#pragma unroll
+  for (int k = 0; k < MM; ++k)
+    if (k < m) zc[k] = from_d<T>(w[k] - gpr[k] * zp - gqr[k] * zq);
 }
 
 // Extension b0 = v0 - A01 z1 (z1 already in z), in two passes: every 3D row
@@ -746,30 +805,54 @@ __global__ void __launch_bounds__(BS) k_mgs(T* __restrict__ V, int64_t ld, int j
   const int i = binst[b];
   if (!st[i].active) return;
   T* w = V + (int64_t)(j + 1) * ld;
-  double h = 0.0;
-  if (k >= 1) {
-    h = inst_sum(part_prev, first, i, sh);
-    if (b == first[i] && threadIdx.x == 0) H[((int64_t)i * (m + 1) + (k - 1)) * m + j] = h;
-  }
   const T* vp = V + (int64_t)(k - 1) * ld;
   const T* vk = V + (int64_t)k * ld;
   double acc = 0.0, acc0 = 0.0;
-  // U elements per thread per pass, all loads of a pass issued before use
+  // U elements per thread per pass; unconditional loads (index clamped into
+  // the block, pointers made valid) so that a pass's loads are all issued
+  // before their first use, and the next pass's loads (the first one: before
+  // h is formed from the previous step's partials) overlap the current work
   constexpr int U = 8;
   const int64_t e1 = bend[b];
-  // unconditional loads (index clamped into the block, pointers made valid)
-  // so that the compiler issues all of a pass's loads before the first use
   const T* vpp = k >= 1 ? vp : w;
   const T* vkk = k <= j ? vk : w;
-  for (int64_t e0 = bstart[b] + threadIdx.x; e0 < e1; e0 += (int64_t)U * BS) {
-    T wl[U], pl[U], kl[U];
+  T wl[U], pl[U], kl[U], wn[U], pn[U], kn[U];
+  auto load_pass = [&](int64_t e0, T (&wa)[U], T (&pa)[U], T (&ka)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = min(e0 + (int64_t)u * BS, e1 - 1);
-      wl[u] = w[e];
-      pl[u] = vpp[e];
-      kl[u] = vkk[e];
+      wa[u] = w[e];
+      pa[u] = vpp[e];
+      ka[u] = vkk[e];
     }
+  };
+  // the previous step's partials are read first, so that waiting for them
+  // does not wait for the element loads issued after them
+  const int f0 = first[i], f1 = first[i + 1];
+  constexpr int NP = 4;  // partials per thread read ahead (instances of up to 4 BS blocks)
+  double hq[NP];
+  double hp = 0.0;
+  if (k >= 1) {
+    for (int q = f0 + (int)threadIdx.x + NP * BS; q < f1; q += BS) hp += part_prev[q];  // larger instances
+#pragma unroll
+    for (int u = 0; u < NP; ++u) hq[u] = part_prev[min(f0 + (int)threadIdx.x + u * BS, f1 - 1)];
+  }
+  int64_t e0 = bstart[b] + threadIdx.x;
+  // keep the element loads ahead of any use of the partials
+  __builtin_amdgcn_sched_barrier(0);
+  if (e0 < e1) load_pass(e0, wl, pl, kl);
+  __builtin_amdgcn_sched_barrier(0);
+  double h = 0.0;
+  if (k >= 1) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+      if (f0 + (int)threadIdx.x + u * BS < f1) hp += hq[u];
+    h = block_sum_lds(hp, sh);
+    if (b == f0 && threadIdx.x == 0) H[((int64_t)i * (m + 1) + (k - 1)) * m + j] = h;
+  }
+  for (; e0 < e1; e0 += (int64_t)U * BS) {
+    const bool more = e0 + (int64_t)U * BS < e1;
+    if (more) load_pass(e0 + (int64_t)U * BS, wn, pn, kn);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = e0 + (int64_t)u * BS;
@@ -784,6 +867,14 @@ __global__ void __launch_bounds__(BS) k_mgs(T* __restrict__ V, int64_t ld, int j
       }
       if (k <= j) acc += wv * to_d(kl[u]);
       else acc += wv * wv;
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        wl[u] = wn[u];
+        pl[u] = pn[u];
+        kl[u] = kn[u];
+      }
     }
   }
   double t = block_sum(acc, sh);
@@ -810,36 +901,90 @@ __global__ void __launch_bounds__(BS) k_mgs_finish(T* __restrict__ V, int64_t ld
   const int b = blockIdx.x;
   const int i = binst[b];
   if (!st[i].active) return;
-  const double hn = sqrt(inst_sum(part_last, first, i, sh));
-  const double w0 = sqrt(inst_sum(part_w0, first, i, sh));
   T* w = V + (int64_t)(j + 1) * ld;
+  // partials of both norms and the first pass of w are all in flight before
+  // the block reductions
+  constexpr int U = 8, NP = 4;
+  const int f0 = first[i], f1 = first[i + 1];
+  double pa = 0.0, pb = 0.0;
+  for (int q = f0 + (int)threadIdx.x + NP * BS; q < f1; q += BS) {  // instances of more than NP BS blocks
+    pa += part_last[q];
+    pb += part_w0[q];
+  }
+  double qa[NP], qb[NP];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    const int q = min(f0 + (int)threadIdx.x + u * BS, f1 - 1);
+    qa[u] = part_last[q];
+    qb[u] = part_w0[q];
+  }
+  const int64_t e1 = bend[b];
+  int64_t e0 = bstart[b] + threadIdx.x;
+  T wl[U];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < U; ++u) wl[u] = w[min(e0 + (int64_t)u * BS, e1 - 1)];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < NP; ++u)
+    if (f0 + (int)threadIdx.x + u * BS < f1) {
+      pa += qa[u];
+      pb += qb[u];
+    }
+  const double hn = sqrt(block_sum_lds(pa, sh));
+  const double w0 = sqrt(block_sum_lds(pb, sh));
   const double sc = hn > 0.0 ? 1.0 / hn : 0.0;
-  {
-    constexpr int U = 8;
-    const int64_t e1 = bend[b];
-    for (int64_t e0 = bstart[b] + threadIdx.x; e0 < e1; e0 += (int64_t)U * BS) {
-      T wl[U];
+  for (; e0 < e1; e0 += (int64_t)U * BS) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) wl[u] = w[min(e0 + (int64_t)u * BS, e1 - 1)];
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + (int64_t)u * BS;
+      if (e < e1) w[e] = from_d<T>(to_d(wl[u]) * sc);
+    }
+    const int64_t en = e0 + (int64_t)U * BS;
+    if (en < e1) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t e = e0 + (int64_t)u * BS;
-        if (e < e1) w[e] = from_d<T>(to_d(wl[u]) * sc);
-      }
+      for (int u = 0; u < U; ++u) wl[u] = w[min(en + (int64_t)u * BS, e1 - 1)];
     }
   }
-  if (b != first[i] || threadIdx.x != 0) return;
+  if (b != first[i]) return;
   double* Hc = H + (int64_t)i * (m + 1) * m;  // Hc[row * m + col]
   double* c = cs + (int64_t)i * m;
   double* s = sn + (int64_t)i * m;
   double* gi = g + (int64_t)i * (m + 1);
-  Hc[(j + 1) * m + j] = hn;
-  for (int q = 0; q < j; ++q) {
-    const double a = Hc[q * m + j], bb = Hc[(q + 1) * m + j];
-    Hc[q * m + j] = c[q] * a + s[q] * bb;
-    Hc[(q + 1) * m + j] = -s[q] * a + c[q] * bb;
+  // column j and the previous rotations staged in LDS by the whole block, so
+  // that the sequential rotation sweep below reads no global memory
+  constexpr int MR = 128;
+  __shared__ double hcol[MR + 1], csh[MR], snh[MR];
+  const bool staged = j < MR;
+  if (staged) {
+    for (int q = threadIdx.x; q <= j; q += blockDim.x) {
+      hcol[q] = Hc[q * m + j];
+      if (q < j) {
+        csh[q] = c[q];
+        snh[q] = s[q];
+      }
+    }
+    __syncthreads();
   }
-  const double a = Hc[j * m + j], bb = hn;
+  if (threadIdx.x != 0) return;
+  double a;
+  if (staged) {
+    double carry = hcol[0];  // rotated entry q of the column
+    for (int q = 0; q < j; ++q) {
+      const double x0 = carry, x1 = hcol[q + 1];
+      Hc[q * m + j] = csh[q] * x0 + snh[q] * x1;
+      carry = -snh[q] * x0 + csh[q] * x1;
+    }
+    a = carry;
+  } else {
+    for (int q = 0; q < j; ++q) {
+      const double x0 = Hc[q * m + j], x1 = Hc[(q + 1) * m + j];
+      Hc[q * m + j] = c[q] * x0 + s[q] * x1;
+      Hc[(q + 1) * m + j] = -s[q] * x0 + c[q] * x1;
+    }
+    a = Hc[j * m + j];
+  }
+  const double bb = hn;
   const double den = hypot(a, bb);
   const double cj = den == 0.0 ? 1.0 : a / den, sj = den == 0.0 ? 0.0 : bb / den;
   c[j] = cj;
@@ -885,9 +1030,18 @@ __global__ void __launch_bounds__(BS) k_update_x(const T* __restrict__ Z, int64_
   const int je = st[i].jend;
   if (je == 0) return;
   const double* yi = y + (int64_t)i * m;
+  // four basis vectors per pass, loads issued before use (same summation order)
+  constexpr int QU = 4;
   for (int64_t e = bstart[b] + threadIdx.x; e < bend[b]; e += blockDim.x) {
     double acc = x[e];
-    for (int q = 0; q < je; ++q) acc += yi[q] * to_d(Z[(int64_t)q * ld + e]);
+    for (int q0 = 0; q0 < je; q0 += QU) {
+      T zl[QU];
+#pragma unroll
+      for (int u = 0; u < QU; ++u) zl[u] = Z[(int64_t)min(q0 + u, je - 1) * ld + e];
+#pragma unroll
+      for (int u = 0; u < QU; ++u)
+        if (q0 + u < je) acc += yi[q0 + u] * to_d(zl[u]);
+    }
     x[e] = acc;
   }
 }
@@ -1018,8 +1172,8 @@ void tree_solve_setup(size_t shm_bytes) {
 
 void chain_solve_setup(size_t shm_bytes) {
   if (shm_bytes > 65536) {
-    hipFuncSetAttribute((const void*)k_chain_solve<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_bytes);
-    hipFuncSetAttribute((const void*)k_chain_solve<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_bytes);
+    hipFuncSetAttribute((const void*)k_chain_vertex<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_bytes);
+    hipFuncSetAttribute((const void*)k_chain_vertex<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_bytes);
   }
 }
 
@@ -1029,11 +1183,19 @@ void launch_tree_solve(mdnp_sys* s, const T* v, T* z, const InstState* st, int w
   if (cd.enabled) {
     const ChainArgs a{cd.meta, cd.soff, cd.fmul, cd.eup, cd.pinv, cd.gp, cd.gq, cd.ap, cd.aq, cd.sp, cd.sq,
                       cd.vparent, cd.vseg, cd.vchild_ptr, cd.vchild_idx, cd.vlvl_ptr, cd.vlvl_nodes, cd.vlval,
-                      cd.vdinv};
-    const size_t shm = cd.lds_bytes;
-    const int threads = std::min(512, std::max(64, (std::max(cd.max_s, cd.max_v) + 63) / 64 * 64));
-    hipLaunchKernelGGL((k_chain_solve<T>), dim3(s->n_inst), dim3(threads), shm, stream, v, z, s->d_off, s->n3d, a, st,
-                       want_mode);
+                      cd.vdinv, cd.t01, cd.zv};
+    const dim3 sgrid((unsigned)((cd.max_s + 63) / 64), (unsigned)s->n_inst);
+    const bool m16 = cd.max_m <= 16;
+    if (m16) hipLaunchKernelGGL((k_chain_fwd<T, 16>), sgrid, dim3(64), 0, stream, v, s->d_off, s->n3d, a, st, want_mode);
+    else hipLaunchKernelGGL((k_chain_fwd<T, kChainMaxM>), sgrid, dim3(64), 0, stream, v, s->d_off, s->n3d, a, st,
+                            want_mode);
+    const int threads = std::min(512, std::max(64, (cd.max_v + 63) / 64 * 64));
+    hipLaunchKernelGGL((k_chain_vertex<T>), dim3(s->n_inst), dim3(threads), cd.lds_bytes, stream, v, z, s->d_off,
+                       s->n3d, a, st, want_mode);
+    if (m16) hipLaunchKernelGGL((k_chain_back<T, 16>), sgrid, dim3(64), 0, stream, v, z, s->d_off, s->n3d, a, st,
+                                want_mode);
+    else hipLaunchKernelGGL((k_chain_back<T, kChainMaxM>), sgrid, dim3(64), 0, stream, v, z, s->d_off, s->n3d, a, st,
+                            want_mode);
     return;
   }
   const size_t shm = sizeof(double) * (size_t)s->max_n1d;
