@@ -1253,20 +1253,24 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
   }
 }
 
-// Stride-2 transposed convolution, one output parity class (px, py, pz) per
-// blockIdx.y.  Output o = 2 q + p along each axis; p = 0 takes tap 1 from input
-// q, p = 1 takes tap 0 from input q + 1 and tap 2 from input q.
+// Transposed stride-2 convolution.  Output o = 2 q + p along each axis; p = 0
+// takes tap 1 from input q, p = 1 takes tap 0 from input q + 1 and tap 2 from
+// input q.  One (y, z) parity class per blockIdx.y, both x parities per wave:
+// the 16 coarse voxels q of an M block give the output voxels 2q
+// (tap tx = 1 from q) and 2q + 1 (taps tx = 2 from q and tx = 0 from q + 1),
+// so the input fragments of q and q + 1 serve both and every wave writes the
+// 32 contiguous output voxels 2q, 2q + 1 of its block (whole cache lines).
 template <int CIN, int COUT, int MB>
-__global__ void __launch_bounds__(WAVES * 64) k_tconv_mfma(const bf16* __restrict__ src, const bf16* __restrict__ W,
+__global__ void __launch_bounds__(WAVES * 64) k_tconv_pair(const bf16* __restrict__ src, const bf16* __restrict__ W,
                                                           const float* __restrict__ bias, bf16* __restrict__ dst,
                                                           int n_in, const InstState* st, int want_mode) {
   constexpr int NB = COUT / 16;
   constexpr int CPT = CIN / 32;  // K chunks per tap
   const int bt = blockIdx.z;
   if (st && !(st[bt].active && st[bt].mode == want_mode)) return;
-  const int cls = blockIdx.y;
-  const int px = cls & 1, py = (cls >> 1) & 1, pz = (cls >> 2) & 1;
-  const int cx = n_in - px, cy = n_in - py, cz = n_in - pz;
+  const int cls = blockIdx.y;  // (py, pz)
+  const int py = cls & 1, pz = (cls >> 1) & 1;
+  const int cx = n_in, cy = n_in - py, cz = n_in - pz;
   const int64_t ncls = (int64_t)cx * cy * cz;
   const int n_out = 2 * n_in - 1;
   const int64_t nvo = (int64_t)n_out * n_out * n_out;
@@ -1276,7 +1280,7 @@ __global__ void __launch_bounds__(WAVES * 64) k_tconv_mfma(const bf16* __restric
   const int64_t mb0 = ((int64_t)blockIdx.x * WAVES + wave) * MB;
   if (mb0 * 16 >= ncls) return;
   int64_t vout[MB], ibase[MB];
-  bool ok[MB];
+  bool ok[MB], ok1[MB];
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
     const int64_t v = (mb0 + m) * 16 + r;
@@ -1287,36 +1291,44 @@ __global__ void __launch_bounds__(WAVES * 64) k_tconv_mfma(const bf16* __restric
       qy = (int)((v / cx) % cy);
       qz = (int)(v / ((int64_t)cx * cy));
     }
-    vout[m] = ((int64_t)(2 * qz + pz) * n_out + (2 * qy + py)) * n_out + (2 * qx + px);
+    ok1[m] = ok[m] && qx + 1 < n_in;  // the odd output 2q + 1 exists
+    vout[m] = ((int64_t)(2 * qz + pz) * n_out + (2 * qy + py)) * n_out + 2 * qx;
     ibase[m] = ((int64_t)qz * n_in + qy) * n_in + qx;
   }
   const bf16* X = src + (int64_t)bt * nvi * CIN;
-  f32x4 acc[MB][NB];
+  f32x4 acc0[MB][NB], acc1[MB][NB];  // even / odd output x
 #pragma unroll
   for (int m = 0; m < MB; ++m)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[m][nb] = {0.f, 0.f, 0.f, 0.f};
-  const int ntap = 1 << (px + py + pz);
+    for (int nb = 0; nb < NB; ++nb) acc0[m][nb] = acc1[m][nb] = {0.f, 0.f, 0.f, 0.f};
+  const int ntap = 1 << (py + pz);  // (y, z) tap combinations of the class
   for (int j = 0; j < ntap; ++j) {
-    // decode class tap j: one bit per odd axis (x first)
     int b = 0;
-    int tx = 1, ty = 1, tz = 1, ox = 0, oy = 0, oz = 0;
-    if (px) { const int s = (j >> b++) & 1; tx = s ? 2 : 0; ox = s ? 0 : 1; }
-    if (py) { const int s = (j >> b++) & 1; ty = s ? 2 : 0; oy = s ? 0 : 1; }
-    if (pz) { const int s = (j >> b++) & 1; tz = s ? 2 : 0; oz = s ? 0 : 1; }
-    const int tap = tz * 9 + ty * 3 + tx;
-    const int64_t toff = ((int64_t)oz * n_in + oy) * n_in + ox;
+    int ty = 1, tz = 1, oy = 0, oz = 0;
+    if (py) { const int sgn = (j >> b++) & 1; ty = sgn ? 2 : 0; oy = sgn ? 0 : 1; }
+    if (pz) { const int sgn = (j >> b++) & 1; tz = sgn ? 2 : 0; oz = sgn ? 0 : 1; }
+    const int64_t toff = ((int64_t)oz * n_in + oy) * n_in;
+    const int tap_c = tz * 9 + ty * 3 + 1, tap_l = tz * 9 + ty * 3 + 2, tap_r = tz * 9 + ty * 3 + 0;
     for (int cc = 0; cc < CPT; ++cc) {
       const int ci = cc * 32 + g * 8;
-      bf16x8 wf[NB];
+      bf16x8 wc[NB], wl[NB], wr[NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) wf[nb] = load8(W + ((int64_t)(nb * 16 + r) * 27 + tap) * CIN + ci);
+      for (int nb = 0; nb < NB; ++nb) {
+        const bf16* wb = W + (int64_t)(nb * 16 + r) * 27 * CIN + ci;
+        wc[nb] = load8(wb + (int64_t)tap_c * CIN);
+        wl[nb] = load8(wb + (int64_t)tap_l * CIN);
+        wr[nb] = load8(wb + (int64_t)tap_r * CIN);
+      }
 #pragma unroll
       for (int m = 0; m < MB; ++m) {
-        const bf16x8 xf = ok[m] ? load8(X + (ibase[m] + toff) * CIN + ci) : zero8();
+        const bf16x8 x0 = ok[m] ? load8(X + (ibase[m] + toff) * CIN + ci) : zero8();
+        const bf16x8 x1 = ok1[m] ? load8(X + (ibase[m] + toff + 1) * CIN + ci) : zero8();
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[nb], xf, acc[m][nb], 0, 0, 0);
+        for (int nb = 0; nb < NB; ++nb) {
+          acc0[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wc[nb], x0, acc0[m][nb], 0, 0, 0);
+          acc1[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl[nb], x0, acc1[m][nb], 0, 0, 0);
+          acc1[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[nb], x1, acc1[m][nb], 0, 0, 0);
+        }
       }
     }
   }
@@ -1327,12 +1339,16 @@ __global__ void __launch_bounds__(WAVES * 64) k_tconv_mfma(const bf16* __restric
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int co = nb * 16 + g * 4;
-      const float y0 = acc[m][nb][0] + bias[co], y1 = acc[m][nb][1] + bias[co + 1];
-      const float y2 = acc[m][nb][2] + bias[co + 2], y3 = acc[m][nb][3] + bias[co + 3];
+      const float b0 = bias[co], b1 = bias[co + 1], b2 = bias[co + 2], b3 = bias[co + 3];
       uint2 pk;
-      pk.x = (unsigned)f2bf(y0) | ((unsigned)f2bf(y1) << 16);
-      pk.y = (unsigned)f2bf(y2) | ((unsigned)f2bf(y3) << 16);
+      pk.x = (unsigned)f2bf(acc0[m][nb][0] + b0) | ((unsigned)f2bf(acc0[m][nb][1] + b1) << 16);
+      pk.y = (unsigned)f2bf(acc0[m][nb][2] + b2) | ((unsigned)f2bf(acc0[m][nb][3] + b3) << 16);
       *(uint2*)(Y + vout[m] * COUT + co) = pk;
+      if (ok1[m]) {
+        pk.x = (unsigned)f2bf(acc1[m][nb][0] + b0) | ((unsigned)f2bf(acc1[m][nb][1] + b1) << 16);
+        pk.y = (unsigned)f2bf(acc1[m][nb][2] + b2) | ((unsigned)f2bf(acc1[m][nb][3] + b3) << 16);
+        *(uint2*)(Y + (vout[m] + 1) * COUT + co) = pk;
+      }
     }
   }
 }
@@ -1532,10 +1548,10 @@ void launch_conv(const ConvP& p, int batch, const bf16* w, hipStream_t stream) {
 
 template <int CIN, int COUT, int MB>
 void launch_tconv(const ConvP& p, int batch, const bf16* w, hipStream_t stream) {
-  const int64_t ncls = (int64_t)p.n_in * p.n_in * p.n_in;  // largest class
+  const int64_t ncls = (int64_t)p.n_in * p.n_in * p.n_in;  // largest (y, z) class
   const int64_t nmb = (ncls + 15) / 16;
-  const dim3 grid((unsigned)((nmb + WAVES * MB - 1) / (WAVES * MB)), 8, batch);
-  hipLaunchKernelGGL((k_tconv_mfma<CIN, COUT, MB>), grid, dim3(WAVES * 64), 0, stream, (const bf16*)p.a, w, p.bias,
+  const dim3 grid((unsigned)((nmb + WAVES * MB - 1) / (WAVES * MB)), 4, batch);
+  hipLaunchKernelGGL((k_tconv_pair<CIN, COUT, MB>), grid, dim3(WAVES * 64), 0, stream, (const bf16*)p.a, w, p.bias,
                      (bf16*)p.y, p.n_in, p.st, p.want_mode);
 }
 
