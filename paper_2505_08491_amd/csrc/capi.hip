@@ -147,15 +147,18 @@ struct Parts {
   double *pA, *pB, *pW, *p3, *pM, *pM3;
 };
 
+// pA, pB: ping-pong partials of the Gram-Schmidt passes (kMgsVals values per
+// block; the other vector reductions use their first blk.nblk entries)
 size_t parts_size(const mdnp_sys* s) {
-  return 3 * (size_t)s->blk.nblk + (size_t)s->blk3.nblk + (size_t)s->mblk.nblk + (size_t)s->mblk3.nblk;
+  return (2 * (size_t)kMgsVals + 1) * (size_t)s->blk.nblk + (size_t)s->blk3.nblk + (size_t)s->mblk.nblk +
+         (size_t)s->mblk3.nblk;
 }
 
 Parts parts(const mdnp_sys* s, double* base) {
   Parts p;
   p.pA = base;
-  p.pB = p.pA + s->blk.nblk;
-  p.pW = p.pB + s->blk.nblk;
+  p.pB = p.pA + (size_t)kMgsVals * s->blk.nblk;
+  p.pW = p.pB + (size_t)kMgsVals * s->blk.nblk;
   p.p3 = p.pW + s->blk.nblk;
   p.pM = p.p3 + s->blk3.nblk;
   p.pM3 = p.pM + s->mblk.nblk;
@@ -736,18 +739,20 @@ void arnoldi_cycle(mdnp_sys* s, int m, bool any_fb, double* x, hipStream_t strea
   T* V = (T*)w.V;
   T* Z = (T*)w.Z;
   const int64_t nt = s->ntot;
-  double* pA = w.part;
-  double* pB = w.part + s->blk.nblk;
-  double* pW = w.part + 2 * (size_t)s->blk.nblk;
+  const Parts P = parts(s, w.part);
+  double* pA = P.pA;
+  double* pB = P.pB;
+  double* pW = P.pW;
   for (int j = 0; j < m; ++j) {
     apply_prec<T>(s, V + j * nt, Z + j * nt, w.st, any_fb, stream);
     launch_spmv<T>(s, Z + j * nt, V + (j + 1) * nt, w.st, true, stream);
-    for (int k = 0; k <= j + 1; ++k) {
-      double* cur = (k % 2 == 0) ? pA : pB;
-      double* prev = (k % 2 == 0) ? pB : pA;
-      launch_mgs<T>(s, V, j, k, prev, cur, pW, w.H, w.m, w.st, stream);
+    const int np = mgs_passes(j);
+    for (int g = 0; g < np; ++g) {
+      double* cur = (g % 2 == 0) ? pA : pB;
+      double* prev = (g % 2 == 0) ? pB : pA;
+      launch_mgs<T>(s, V, j, g, prev, cur, pW, w.H, w.m, w.st, stream);
     }
-    double* last = ((j + 1) % 2 == 0) ? pA : pB;
+    double* last = ((np - 1) % 2 == 0) ? pA : pB;
     launch_mgs_finish<T>(s, V, j, last, pW, w.H, w.cs, w.sn, w.g, w.hist, w.hist_cap, w.m, w.st, stream);
   }
   launch_solve_y(s, w.H, w.g, w.y, w.m, w.st, stream);

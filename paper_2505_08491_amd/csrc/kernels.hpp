@@ -54,9 +54,14 @@ void launch_block_jacobi3d(mdnp_sys* s, T* z, const InstState* st, int want_mode
 void launch_inv_scale(mdnp_sys* s, const double* part3, const double* part3m, double* inv_s, InstState* st,
                       int want_mode, hipStream_t stream);
 
-// Arnoldi
+// Arnoldi: modified Gram-Schmidt of V[j+1] in passes g = 0 .. mgs_passes(j) - 1,
+// kMgsGroup basis vectors per pass; each pass keeps kMgsVals partial sums per
+// block (ping-pong buffers of kMgsVals * blk.nblk doubles).
+constexpr int kMgsGroup = 4;
+constexpr int kMgsVals = kMgsGroup + kMgsGroup * (kMgsGroup - 1) / 2;
+inline int mgs_passes(int j) { return (j + kMgsGroup) / kMgsGroup + 1; }
 template <typename T>
-void launch_mgs(mdnp_sys* s, T* V, int j, int k, const double* part_prev, double* part_cur,
+void launch_mgs(mdnp_sys* s, T* V, int j, int g, const double* part_prev, double* part_cur,
                 double* part_w0, double* H, int m, const InstState* st, hipStream_t stream);
 template <typename T>
 void launch_mgs_finish(mdnp_sys* s, T* V, int j, const double* part_last, const double* part_w0,

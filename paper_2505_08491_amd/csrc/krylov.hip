@@ -55,6 +55,30 @@ __device__ double block_sum_lds(double v, double* sh) {
   return t;
 }
 
+// block_sum_lds of NV values at once (one pair of barriers); sh holds
+// NV * (BS / 64) doubles.  Result valid in every thread.
+template <int NV>
+__device__ void block_sums_lds(double (&v)[NV], double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    v[q] = wave_sum(v[q]);
+    if (lane == 0) sh[q * (BS / 64) + wid] = v[q];
+  }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double t = 0.0;
+    for (int k = 0; k < nw; ++k) t += sh[q * (BS / 64) + k];
+    v[q] = t;
+  }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Sum of the partials of instance i (fixed order), result in every thread.
 __device__ double inst_sum(const double* part, const int32_t* first, int i, double* sh) {
   double t = 0.0;
@@ -789,99 +813,164 @@ __global__ void k_inv_scale(const double* part3, const int32_t* first, const dou
 
 // ---------------------------------------------------------------- Arnoldi (modified Gram-Schmidt)
 
-// Step k of the MGS sweep for the new vector w = V[j+1] (k = 0..j+1):
-//   k >= 1: h_{k-1,j} = <w, v_{k-1}> from the partials of step k-1; w -= h v_{k-1};
-//   k <= j: partials of <w, v_k>;   k = j+1: partials of <w, w>;
-//   k == 0: also partials of <w, w> before orthogonalisation (breakdown test).
-// Arithmetic in FP64; w is stored back in the vector type.
-template <typename T>
-__global__ void __launch_bounds__(BS) k_mgs(T* __restrict__ V, int64_t ld, int j, int k,
+// Modified Gram-Schmidt for the new vector w = V[j+1], taken kMgsGroup basis
+// vectors per pass.  Within a group the sequential MGS coefficients follow from
+// inner products taken with the group's input w:
+//   h_b = <w - sum_{a<b} h_a v_a, v_b> = <w, v_b> - sum_{a<b} h_a <v_a, v_b>,
+// an identity of exact arithmetic (the <v_a, v_b> are kept, not assumed zero),
+// so one pass over w serves a whole group.  A pass
+//   - forms the coefficients of the previous group (NPD vectors from p0) from
+//     that pass's partial sums and subtracts them from w, which is stored back
+//     rounded once to the vector type;
+//   - takes the partials of <w, v_c> and <v_a, v_b> for the NCU vectors of the
+//     current group (from c0), or of <w, w> when the group is empty (last pass);
+//   - on the first pass, also those of <w, w> before orthogonalisation.
+// Partial q of block b sits at part[q * nblk + b]; dots first, then the pairs
+// a < b at NCU + b (b - 1) / 2 + a.  FP64 arithmetic throughout.
+template <typename T, int NPD, int NCU>
+__global__ void __launch_bounds__(BS) k_mgs(T* __restrict__ V, int64_t ld, int j, int p0, int c0,
                                             const double* __restrict__ part_prev, double* __restrict__ part_cur,
                                             double* __restrict__ part_w0, double* __restrict__ H, int m,
                                             const int32_t* binst, const int64_t* bstart, const int64_t* bend,
-                                            const int32_t* first, const InstState* st) {
-  __shared__ double sh[BS / 64];
+                                            const int32_t* first, const InstState* st, int nblk) {
+  constexpr int NPV = NPD + NPD * (NPD - 1) / 2;              // partial sums read
+  constexpr int NCV = NCU > 0 ? NCU + NCU * (NCU - 1) / 2 : 1;  // partial sums written
+  constexpr int NSH = (NPV > NCV ? NPV : NCV) + 1;
+  constexpr int NVEC = 1 + NPD + NCU;
+  constexpr int U = NVEC <= 3 ? 8 : 4;  // elements per thread per pass
+  __shared__ double sh[NSH * (BS / 64)];
   const int b = blockIdx.x;
   const int i = binst[b];
   if (!st[i].active) return;
   T* w = V + (int64_t)(j + 1) * ld;
-  const T* vp = V + (int64_t)(k - 1) * ld;
-  const T* vk = V + (int64_t)k * ld;
-  double acc = 0.0, acc0 = 0.0;
-  // U elements per thread per pass; unconditional loads (index clamped into
-  // the block, pointers made valid) so that a pass's loads are all issued
-  // before their first use, and the next pass's loads (the first one: before
-  // h is formed from the previous step's partials) overlap the current work
-  constexpr int U = 8;
-  const int64_t e1 = bend[b];
-  const T* vpp = k >= 1 ? vp : w;
-  const T* vkk = k <= j ? vk : w;
-  T wl[U], pl[U], kl[U], wn[U], pn[U], kn[U];
-  auto load_pass = [&](int64_t e0, T (&wa)[U], T (&pa)[U], T (&ka)[U]) {
+  const int f0 = first[i], f1 = first[i + 1];
+  const int t = (int)threadIdx.x;
+  // previous pass's partials: the first BS blocks of the instance in flight
+  // before the element loads, the rest (large instances) summed up front
+  double hp[NPV > 0 ? NPV : 1];
+  double hq[NPV > 0 ? NPV : 1];
+#pragma unroll
+  for (int q = 0; q < NPV; ++q) hp[q] = 0.0;
+  for (int r = f0 + t + BS; r < f1; r += BS) {
+#pragma unroll
+    for (int q = 0; q < NPV; ++q) hp[q] += part_prev[(int64_t)q * nblk + r];
+  }
+#pragma unroll
+  for (int q = 0; q < NPV; ++q) hq[q] = part_prev[(int64_t)q * nblk + min(f0 + t, f1 - 1)];
+  // uniform base pointers at the block's first element and 32-bit byte
+  // offsets shared by all vectors (SGPR base + VGPR offset addressing)
+  const int64_t es = bstart[b];
+  const int len = (int)(bend[b] - es);
+  T* wb = w + es;
+  const char* pbase[NPD > 0 ? NPD : 1];
+  const char* cbase[NCU > 0 ? NCU : 1];
+#pragma unroll
+  for (int a = 0; a < NPD; ++a) pbase[a] = (const char*)(V + (int64_t)(p0 + a) * ld + es);
+#pragma unroll
+  for (int c = 0; c < NCU; ++c) cbase[c] = (const char*)(V + (int64_t)(c0 + c) * ld + es);
+  int e0 = t;
+  T wl[U], pl[NPD > 0 ? NPD : 1][U], cl[NCU > 0 ? NCU : 1][U];
+  auto load_pass = [&](int ea, T (&wa)[U], T (&pa)[NPD > 0 ? NPD : 1][U], T (&ca)[NCU > 0 ? NCU : 1][U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t e = min(e0 + (int64_t)u * BS, e1 - 1);
-      wa[u] = w[e];
-      pa[u] = vpp[e];
-      ka[u] = vkk[e];
+      const uint32_t off = (uint32_t)min(ea + u * BS, len - 1) * (uint32_t)sizeof(T);
+      wa[u] = *(const T*)((const char*)wb + off);
+#pragma unroll
+      for (int a = 0; a < NPD; ++a) pa[a][u] = *(const T*)(pbase[a] + off);
+#pragma unroll
+      for (int c = 0; c < NCU; ++c) ca[c][u] = *(const T*)(cbase[c] + off);
     }
   };
-  // the previous step's partials are read first, so that waiting for them
-  // does not wait for the element loads issued after them
-  const int f0 = first[i], f1 = first[i + 1];
-  constexpr int NP = 4;  // partials per thread read ahead (instances of up to 4 BS blocks)
-  double hq[NP];
-  double hp = 0.0;
-  if (k >= 1) {
-    for (int q = f0 + (int)threadIdx.x + NP * BS; q < f1; q += BS) hp += part_prev[q];  // larger instances
-#pragma unroll
-    for (int u = 0; u < NP; ++u) hq[u] = part_prev[min(f0 + (int)threadIdx.x + u * BS, f1 - 1)];
-  }
-  int64_t e0 = bstart[b] + threadIdx.x;
-  // keep the element loads ahead of any use of the partials
   __builtin_amdgcn_sched_barrier(0);
-  if (e0 < e1) load_pass(e0, wl, pl, kl);
+  if (e0 < len) load_pass(e0, wl, pl, cl);
   __builtin_amdgcn_sched_barrier(0);
-  double h = 0.0;
-  if (k >= 1) {
+  double h[NPD > 0 ? NPD : 1];
+  if constexpr (NPD > 0) {
 #pragma unroll
-    for (int u = 0; u < NP; ++u)
-      if (f0 + (int)threadIdx.x + u * BS < f1) hp += hq[u];
-    h = block_sum_lds(hp, sh);
-    if (b == f0 && threadIdx.x == 0) H[((int64_t)i * (m + 1) + (k - 1)) * m + j] = h;
+    for (int q = 0; q < NPV; ++q)
+      if (f0 + t < f1) hp[q] += hq[q];
+    block_sums_lds<NPV>(hp, sh);
+    // sequential MGS coefficients of the previous group
+#pragma unroll
+    for (int bb = 0; bb < NPD; ++bb) {
+      double v = hp[bb];
+#pragma unroll
+      for (int a = 0; a < bb; ++a) v -= h[a] * hp[NPD + bb * (bb - 1) / 2 + a];
+      h[bb] = v;
+    }
+    if (b == f0 && t < NPD) {
+      double ht = h[0];
+#pragma unroll
+      for (int a = 1; a < NPD; ++a)
+        if (t == a) ht = h[a];
+      H[((int64_t)i * (m + 1) + (p0 + t)) * m + j] = ht;
+    }
   }
-  for (; e0 < e1; e0 += (int64_t)U * BS) {
-    const bool more = e0 + (int64_t)U * BS < e1;
-    if (more) load_pass(e0 + (int64_t)U * BS, wn, pn, kn);
+  double acc[NCV], acc0 = 0.0;
+#pragma unroll
+  for (int q = 0; q < NCV; ++q) acc[q] = 0.0;
+  T wn[U], pn[NPD > 0 ? NPD : 1][U], cn[NCU > 0 ? NCU : 1][U];
+  for (; e0 < len; e0 += U * BS) {
+    const bool more = e0 + U * BS < len;
+    if (more) load_pass(e0 + U * BS, wn, pn, cn);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t e = e0 + (int64_t)u * BS;
-      if (e >= e1) break;
+      const int e = e0 + u * BS;
+      if (e >= len) break;
       double wv = to_d(wl[u]);
-      if (k == 0) acc0 += wv * wv;
-      if (k >= 1) {
-        wv -= h * to_d(pl[u]);
+      if constexpr (NPD == 0) acc0 += wv * wv;
+      if constexpr (NPD > 0) {
+#pragma unroll
+        for (int a = 0; a < NPD; ++a) wv -= h[a] * to_d(pl[a][u]);
         const T ws = from_d<T>(wv);
-        w[e] = ws;
+        wb[e] = ws;
         wv = to_d(ws);
       }
-      if (k <= j) acc += wv * to_d(kl[u]);
-      else acc += wv * wv;
+      if constexpr (NCU > 0) {
+#pragma unroll
+        for (int c = 0; c < NCU; ++c) acc[c] += wv * to_d(cl[c][u]);
+#pragma unroll
+        for (int bb = 1; bb < NCU; ++bb)
+#pragma unroll
+          for (int a = 0; a < bb; ++a) acc[NCU + bb * (bb - 1) / 2 + a] += to_d(cl[a][u]) * to_d(cl[bb][u]);
+      } else {
+        acc[0] += wv * wv;
+      }
     }
     if (more) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         wl[u] = wn[u];
-        pl[u] = pn[u];
-        kl[u] = kn[u];
+#pragma unroll
+        for (int a = 0; a < NPD; ++a) pl[a][u] = pn[a][u];
+#pragma unroll
+        for (int c = 0; c < NCU; ++c) cl[c][u] = cn[c][u];
       }
     }
   }
-  double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) part_cur[b] = t;
-  if (k == 0) {
-    double t0 = block_sum(acc0, sh);
-    if (threadIdx.x == 0) part_w0[b] = t0;
+  if constexpr (NPD == 0) {
+    double all[NCV + 1];
+#pragma unroll
+    for (int q = 0; q < NCV; ++q) all[q] = acc[q];
+    all[NCV] = acc0;
+    block_sums_lds<NCV + 1>(all, sh);
+    if (t < NCV) {
+      double o = all[0];
+#pragma unroll
+      for (int q = 1; q < NCV; ++q)
+        if (t == q) o = all[q];
+      part_cur[(int64_t)t * nblk + b] = o;
+    }
+    if (t == 0) part_w0[b] = all[NCV];
+  } else {
+    block_sums_lds<NCV>(acc, sh);
+    if (t < NCV) {
+      double o = acc[0];
+#pragma unroll
+      for (int q = 1; q < NCV; ++q)
+        if (t == q) o = acc[q];
+      part_cur[(int64_t)t * nblk + b] = o;
+    }
   }
 }
 
@@ -1239,11 +1328,38 @@ void launch_inv_scale(mdnp_sys* s, const double* part3, const double* part3m, do
                      s->mblk3.first, s->n_inst, inv_s, st, want_mode);
 }
 
+template <typename T, int NPD, int NCU>
+void launch_mgs_pass(mdnp_sys* s, T* V, int j, int p0, int c0, const double* part_prev, double* part_cur,
+                     double* part_w0, double* H, int m, const InstState* st, hipStream_t stream) {
+  hipLaunchKernelGGL((k_mgs<T, NPD, NCU>), dim3(s->blk.nblk), dim3(BS), 0, stream, V, (int64_t)s->ntot, j, p0, c0,
+                     part_prev, part_cur, part_w0, H, m, BLK(s), s->blk.first, st, s->blk.nblk);
+}
+
 template <typename T>
-void launch_mgs(mdnp_sys* s, T* V, int j, int k, const double* part_prev, double* part_cur, double* part_w0,
+void launch_mgs(mdnp_sys* s, T* V, int j, int g, const double* part_prev, double* part_cur, double* part_w0,
                 double* H, int m, const InstState* st, hipStream_t stream) {
-  hipLaunchKernelGGL((k_mgs<T>), dim3(s->blk.nblk), dim3(BS), 0, stream, V, (int64_t)s->ntot, j, k, part_prev,
-                     part_cur, part_w0, H, m, BLK(s), s->blk.first, st);
+  static_assert(kMgsGroup == 4, "pass dispatch below is written for groups of 4");
+  const int nvec = j + 1;
+  const int npd = g >= 1 ? std::min(kMgsGroup, nvec - (g - 1) * kMgsGroup) : 0;
+  const int ncu = std::max(0, std::min(kMgsGroup, nvec - g * kMgsGroup));
+  const int p0 = (g - 1) * kMgsGroup, c0 = g * kMgsGroup;
+#define MGS_PASS(A, B) launch_mgs_pass<T, A, B>(s, V, j, p0, c0, part_prev, part_cur, part_w0, H, m, st, stream)
+  switch (npd * 8 + ncu) {
+    case 0 * 8 + 1: MGS_PASS(0, 1); break;
+    case 0 * 8 + 2: MGS_PASS(0, 2); break;
+    case 0 * 8 + 3: MGS_PASS(0, 3); break;
+    case 0 * 8 + 4: MGS_PASS(0, 4); break;
+    case 4 * 8 + 1: MGS_PASS(4, 1); break;
+    case 4 * 8 + 2: MGS_PASS(4, 2); break;
+    case 4 * 8 + 3: MGS_PASS(4, 3); break;
+    case 4 * 8 + 4: MGS_PASS(4, 4); break;
+    case 1 * 8 + 0: MGS_PASS(1, 0); break;
+    case 2 * 8 + 0: MGS_PASS(2, 0); break;
+    case 3 * 8 + 0: MGS_PASS(3, 0); break;
+    case 4 * 8 + 0: MGS_PASS(4, 0); break;
+    default: break;  // not reached: j >= 0, 0 <= g <= mgs_passes(j) - 1
+  }
+#undef MGS_PASS
 }
 template void launch_mgs<float>(mdnp_sys*, float*, int, int, const double*, double*, double*, double*, int,
                                 const InstState*, hipStream_t);
