@@ -120,7 +120,7 @@ void free_work(SolveWork& w) {
 
 void free_sys(mdnp_sys* s) {
   void* ptrs[] = {s->d_off, s->d_stencil, s->d_mptr, s->d_mcol, s->d_mval64, s->d_mval32, s->d_ma01, s->d_mrows, s->d_mlp,
-                  s->d_dinv, s->d_dist,
+                  s->d_a01p, s->d_a01c, s->d_a01v64, s->d_a01v32, s->d_dinv, s->d_dist,
                   s->d_alpha, s->d_t_off, s->d_t_lvloff, s->d_t_lvlptr, s->d_t_lvlnodes, s->d_t_parent,
                   s->d_t_childptr, s->d_t_childidx, s->d_t_lval, s->d_t_dinv};
   for (void* p : ptrs) dfree(p);
@@ -454,6 +454,30 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
       for (size_t q = 0; q < mrows.size(); ++q)
         if (mp[mrows[q] + 1] != mlp[q + 1]) fail(MDNP_E_ARG, "internal error: coupling rows are not contiguous");
       s->d_mlp = dupload(mlp, stream);
+    }
+    {
+      // A01 (3D rows x 1D columns) as a compact CSR over the listed rows
+      // (empty for the 1D rows): the extension reads only these entries
+      std::vector<int32_t> ap(mrows.size() + 1, 0), ac;
+      std::vector<double> av64;
+      std::vector<float> av32;
+      for (int i = 0; i < n_inst; ++i)
+        for (int64_t q = ms[i]; q < ms[i] + ml[i]; ++q) {
+          ap[q] = (int32_t)ac.size();
+          if (q >= ms[i] + ml3[i]) continue;
+          const int32_t row = mrows[q];
+          const int64_t r = row - s->off[i];
+          for (int32_t k = ma01[(size_t)i * s->n3d + r]; k < mp[row + 1]; ++k) {
+            ac.push_back(mc[k]);
+            av64.push_back(mv64[k]);
+            av32.push_back(mv32[k]);
+          }
+        }
+      ap[mrows.size()] = (int32_t)ac.size();
+      s->d_a01p = dupload(ap, stream);
+      s->d_a01c = dupload(ac, stream);
+      s->d_a01v64 = dupload(av64, stream);
+      s->d_a01v32 = dupload(av32, stream);
     }
     // coupling rows: short chunks (a few rows per lane group) for latency hiding
     build_blocks(s->mblk, ms, ml, (int64_t)mrows.size(), stream, 64, 8192);

@@ -235,32 +235,31 @@ __global__ void __launch_bounds__(WAVES * 64) k_conv_mfma(MfmaArgs p) {
   }
 }
 
-// The column x = n - 1 of a stride-1 layer (left out by the sweep kernels):
-// one workgroup of KSW waves per plane z, covering all of that column's
-// blocks of 16 consecutive y (at most YB of them) so that every weight
-// fragment loaded serves YB MFMAs; wave w accumulates the K chunks c = w,
-// w + KSW, ...; the partial sums meet in LDS and the waves finish the
-// (block, output block) fragments in turn (bias, ReLU, BF16 store).  IN = 1
-// builds the first layer's input.
-template <int CA, int CB, int COUT, int IN, typename Tv, int KSW, int YB>
-__global__ void __launch_bounds__(KSW * 64) k_conv_edge(MfmaArgs p) {
+// The column x = n - 1 of a stride-1 layer (left out by the sweep kernels),
+// plane oz of instance bt, by the nw = blockDim.x / 64 waves of one workgroup:
+// all of that column's blocks of 16 consecutive y (at most YBM of them) are
+// covered, so that every weight fragment loaded serves up to YBM MFMAs; wave w
+// accumulates the K chunks c = w, w + nw, ...; the partial sums meet in LDS
+// (red: nw * nyb * COUT / 16 * 1 KiB) and the waves finish the (block, output
+// block) fragments in turn (bias, ReLU, BF16 store).  IN = 1 builds the first
+// layer's input.  Called by the sweep kernels' extra workgroups and by
+// k_conv_edge.
+template <int CA, int CB, int COUT, int IN, typename Tv, int YBM>
+__device__ __forceinline__ void edge_plane(const MfmaArgs& p, int oz, int bt, f32x4* red) {
   constexpr int CIN = CA + CB;
   constexpr int NB = COUT / 16;
   constexpr int KCH = (27 * CIN + 31) / 32;
-  extern __shared__ __attribute__((aligned(16))) unsigned char edge_lds[];
-  f32x4* red = (f32x4*)edge_lds;  // [KSW][YB][NB][64]
-  const int bt = blockIdx.z;
-  if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
   const int n = p.n_out;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int g = lane >> 4, r = lane & 15;
   const int nyb = (n + 15) / 16;
-  const int oz = blockIdx.x, ox = n - 1;
+  const int ox = n - 1;
   const int64_t nn = (int64_t)n * n, nv = nn * n;
-  int64_t base[YB];
-  unsigned msk[YB];
+  int64_t base[YBM];
+  unsigned msk[YBM];
 #pragma unroll
-  for (int m = 0; m < YB; ++m) {
+  for (int m = 0; m < YBM; ++m) {
     const int oy = m * 16 + r;
     const bool ok = m < nyb && oy < n;
     base[m] = ((int64_t)oz * n + (ok ? oy : 0)) * n + ox;
@@ -278,12 +277,12 @@ __global__ void __launch_bounds__(KSW * 64) k_conv_edge(MfmaArgs p) {
   const Tv* Z = IN ? (const Tv*)p.z + p.off[bt] : nullptr;
   const float* D = IN ? p.dist + (int64_t)bt * nv : nullptr;
   const float sc = IN ? (float)p.inv_s[bt] : 0.0f;
-  f32x4 acc[YB][NB];
+  f32x4 acc[YBM][NB];
 #pragma unroll
-  for (int m = 0; m < YB; ++m)
+  for (int m = 0; m < YBM; ++m)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[m][nb] = {0.f, 0.f, 0.f, 0.f};
-  for (int c = wave; c < KCH; c += KSW) {
+  for (int c = wave; c < KCH; c += nw) {
     const int k0 = c * 32 + g * 8;
     const int tap = k0 / CIN;
     const int ci = k0 - tap * CIN;
@@ -295,9 +294,9 @@ __global__ void __launch_bounds__(KSW * 64) k_conv_edge(MfmaArgs p) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
       wf[nb] = tap_ok ? load8(p.w + ((int64_t)(nb * 16 + r) * 27 + tap) * CIN + ci) : zero8();
-    bf16x8 x[YB];
+    bf16x8 x[YBM];
 #pragma unroll
-    for (int m = 0; m < YB; ++m) {
+    for (int m = 0; m < YBM; ++m) {
       x[m] = zero8();
       if (tap_ok && (msk[m] & need) == need) {
         const int64_t vin = base[m] + toff;
@@ -307,22 +306,26 @@ __global__ void __launch_bounds__(KSW * 64) k_conv_edge(MfmaArgs p) {
       }
     }
 #pragma unroll
-    for (int m = 0; m < YB; ++m)
+    for (int m = 0; m < YBM; ++m)
+      if (m < nyb) {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[nb], x[m], acc[m][nb], 0, 0, 0);
+        for (int nb = 0; nb < NB; ++nb)
+          acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[nb], x[m], acc[m][nb], 0, 0, 0);
+      }
   }
 #pragma unroll
-  for (int m = 0; m < YB; ++m)
+  for (int m = 0; m < YBM; ++m)
+    if (m < nyb) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) red[((wave * YB + m) * NB + nb) * 64 + lane] = acc[m][nb];
+      for (int nb = 0; nb < NB; ++nb) red[((wave * nyb + m) * NB + nb) * 64 + lane] = acc[m][nb];
+    }
   __syncthreads();
   bf16* Y = p.y + (int64_t)bt * nv * COUT;
-  for (int f = wave; f < nyb * NB; f += KSW) {
+  for (int f = wave; f < nyb * NB; f += nw) {
     const int m = f / NB, nb = f - m * NB;
     f32x4 sum = red[(m * NB + nb) * 64 + lane];
-    for (int w = 1; w < KSW; ++w) {
-      const f32x4 o = red[((w * YB + m) * NB + nb) * 64 + lane];
+    for (int w = 1; w < nw; ++w) {
+      const f32x4 o = red[((w * nyb + m) * NB + nb) * 64 + lane];
       sum += o;
     }
     const int oy = m * 16 + r;
@@ -339,6 +342,23 @@ __global__ void __launch_bounds__(KSW * 64) k_conv_edge(MfmaArgs p) {
     const int64_t v = ((int64_t)oz * n + oy) * n + ox;
     *(uint2*)(Y + v * COUT + co) = pk;
   }
+}
+
+// Edge column of a stride-1 layer as a kernel of its own: one workgroup of
+// KSW waves per plane (grid x = planes, z = instances).
+template <int CA, int CB, int COUT, int IN, typename Tv, int KSW, int YB>
+__global__ void __launch_bounds__(KSW * 64) k_conv_edge(MfmaArgs p) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char edge_lds[];
+  const int bt = blockIdx.z;
+  if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
+  edge_plane<CA, CB, COUT, IN, Tv, YB>(p, blockIdx.x, bt, (f32x4*)edge_lds);
+}
+
+// Largest n whose edge column the sweep kernels take in extra workgroups, and
+// the LDS those workgroups need.
+constexpr int kEdgeYB = 5;
+inline size_t edge_lds_bytes(int nwaves, int n, int cout) {
+  return (size_t)nwaves * ((n + 15) / 16) * (cout / 16) * 64 * 16;
 }
 
 template <int CA, int CB, int COUT, int IN, typename Tv>
@@ -601,6 +621,7 @@ struct RowsTile {
 struct RowsGrid {
   int ylo = 0, yhi = 0, zlo = 0, zhi = 0;  // output rows / planes computed
   int zc = 0, ytiles = 0;
+  int nedge = 0;  // leading workgroups per instance that compute the x = n - 1 column, one plane each
 };
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -619,6 +640,11 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
   int bxr, bt;
   xcd_remap(bxr, bt);
   if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
+  if (bxr < q.nedge) {
+    edge_plane<IN ? 8 : CA, CB, 16, IN, Tv, kEdgeYB>(p, bxr, bt, (f32x4*)ring);
+    return;
+  }
+  bxr -= q.nedge;
   const int n = p.n_out;
   const int XW = n + 1;
   const int y0 = q.ylo + (bxr % q.ytiles) * MB;
@@ -860,6 +886,11 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
   int bxr, bt;
   xcd_remap(bxr, bt);
   if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
+  if (!EPI && bxr < q.nedge) {
+    edge_plane<CA, CB, 16, 0, Tv, kEdgeYB>(p, bxr, bt, (f32x4*)ring);
+    return;
+  }
+  bxr -= q.nedge;
   const int n = p.n_out;
   const int XW = n + 1;
   const int y0 = q.ylo + (bxr % q.ytiles) * TYR;
@@ -1098,6 +1129,11 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
   int bxr, bt;
   xcd_remap(bxr, bt);
   if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
+  if (bxr < q.nedge) {
+    edge_plane<CA, CB, COUT, 0, float, kEdgeYB>(p, bxr, bt, (f32x4*)ring);
+    return;
+  }
+  bxr -= q.nedge;
   const int n = p.n_out;
   const int XW = n + 1;
   const int y0 = q.ylo + (bxr % q.ytiles) * MB;
@@ -1422,7 +1458,7 @@ void launch_rows16_npf(const MfmaArgs& a, const RowsGrid& q, int batch, size_t l
   auto kern = k_conv16_rows<CA, CB, MB, IN, EPI, Tv, NPF>;
   if (lds > 65536) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const int nz = (q.zhi - q.zlo + q.zc - 1) / q.zc;
-  hipLaunchKernelGGL(kern, dim3((unsigned)(q.ytiles * nz), 1, batch), dim3(xb * 64), lds, stream, a, q);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(q.nedge + q.ytiles * nz), 1, batch), dim3(xb * 64), lds, stream, a, q);
 }
 
 template <int CA, int CB, int MB, int IN, int EPI, typename Tv, int NPF0, int NPF1>
@@ -1447,13 +1483,16 @@ void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream) {
   int nz = (1024 + q.ytiles * batch - 1) / (q.ytiles * batch);
   nz = std::max(1, std::min(nz, planes));
   q.zc = (planes + nz - 1) / nz;
+  // the x = n - 1 column in extra workgroups (not needed with the head: Dirichlet)
+  q.nedge = (!EPI && n <= 16 * kEdgeYB) ? n : 0;
+  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(xb, n, 16) : (size_t)0);
   if constexpr (!IN) {
-    launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, 1>(a, q, batch, lds, xb, stream);
+    launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, 1>(a, q, batch, lds_all, xb, stream);
   } else {
-    if (need <= NPF0) launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF0>(a, q, batch, lds, xb, stream);
-    else launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF1>(a, q, batch, lds, xb, stream);
+    if (need <= NPF0) launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF0>(a, q, batch, lds_all, xb, stream);
+    else launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF1>(a, q, batch, lds_all, xb, stream);
   }
-  if (!EPI) launch_edge<IN ? 8 : CA, CB, 16, IN, Tv>(a, batch, stream);
+  if (!EPI && !q.nedge) launch_edge<IN ? 8 : CA, CB, 16, IN, Tv>(a, batch, stream);
 }
 
 // Stored 16-channel layers: the two-waves-per-SIMD sweep for x < n - 1 plus
@@ -1483,10 +1522,14 @@ void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream) {
   nz = std::max(1, std::min(nz, planes));
   q.zc = (planes + nz - 1) / nz;
   nz = (planes + q.zc - 1) / q.zc;
+  q.nedge = (!EPI && n <= 16 * kEdgeYB) ? n : 0;
+  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(2 * xb, n, 16) : (size_t)0);
   auto kern = k_conv16_ks<CA, CB, MB, KS, EPI, Tv, NLW>;
-  if (lds > 65536) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(kern, dim3((unsigned)(q.ytiles * nz), 1, batch), dim3(2 * xb * 64), lds, stream, a, q);
-  if (!EPI) launch_edge<CA, CB, 16, 0, Tv>(a, batch, stream);
+  if (lds_all > 65536)
+    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_all);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(q.nedge + q.ytiles * nz), 1, batch), dim3(2 * xb * 64), lds_all, stream,
+                     a, q);
+  if (!EPI && !q.nedge) launch_edge<CA, CB, 16, 0, Tv>(a, batch, stream);
 }
 
 // Coarse-level stride-1 layers (COUT = 32 or 64): the K-split sweep for
@@ -1512,10 +1555,14 @@ void launch_convw(const MfmaArgs& a, int batch, hipStream_t stream) {
   nz = std::max(1, std::min(nz, n));
   q.zc = (n + nz - 1) / nz;
   nz = (n + q.zc - 1) / q.zc;
+  q.nedge = n <= 16 * kEdgeYB ? n : 0;
+  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(xb * KG, n, COUT) : (size_t)0);
   auto kern = k_convw<CA, CB, COUT, MB, KG, NPF>;
-  if (lds > 65536) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(kern, dim3((unsigned)(q.ytiles * nz), 1, batch), dim3(xb * KG * 64), lds, stream, a, q);
-  launch_edge<CA, CB, COUT, 0, float>(a, batch, stream);
+  if (lds_all > 65536)
+    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_all);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(q.nedge + q.ytiles * nz), 1, batch), dim3(xb * KG * 64), lds_all, stream,
+                     a, q);
+  if (!q.nedge) launch_edge<CA, CB, COUT, 0, float>(a, batch, stream);
 }
 
 MfmaArgs args_from(const ConvP& p, const bf16* w) {

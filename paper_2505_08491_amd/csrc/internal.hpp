@@ -120,6 +120,10 @@ struct mdnp_sys {
   int32_t* d_ma01 = nullptr;       // [n_inst * n3d] first M entry of each 3D row with a 1D column
   int32_t* d_mrows = nullptr;      // global ids of the rows with M entries (per instance: 3D rows, then 1D rows)
   int32_t* d_mlp = nullptr;        // [rows listed + 1] M entry range of each listed row
+  int32_t* d_a01p = nullptr;       // [rows listed + 1] A01 entry range of each listed row (empty for 1D rows)
+  int32_t* d_a01c = nullptr;       // A01 global column indices (1D nodes)
+  double* d_a01v64 = nullptr;
+  float* d_a01v32 = nullptr;
   double* d_dinv = nullptr;        // [ntot] 1 / diag(A)
   float* d_dist = nullptr;         // [n_inst * n3d]
   double* d_alpha = nullptr;       // [n_inst]

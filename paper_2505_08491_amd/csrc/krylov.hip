@@ -315,19 +315,23 @@ __global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows,
     Tacc acc = 0;
     const int e = mlp[q + 1];
     // U entries per lane per pass, all loads of a pass in flight together
-    constexpr int U = 4;
+    // (indices clamped into the row: every listed row has entries)
+    constexpr int U = 32 / G;
     for (int k0 = mlp[q] + lane; k0 < e; k0 += U * G) {
       int cidx[U];
       Tm mv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int k = k0 + u * G;
-        cidx[u] = k < e ? mcol[k] : -1;
-        mv[u] = k < e ? mval[k] : (Tm)0;
+        const int k = min(k0 + u * G, e - 1);
+        cidx[u] = mcol[k];
+        mv[u] = mval[k];
       }
+      Tv xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) xv[u] = x[cidx[u]];
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (cidx[u] >= 0) acc += (Tacc)mv[u] * (Tacc)x[cidx[u]];
+        if (k0 + u * G < e) acc += (Tacc)mv[u] * (Tacc)xv[u];
     }
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
@@ -695,93 +699,94 @@ __global__ void __launch_bounds__(64) k_chain_back(const T* __restrict__ v, T* _
     if (k < m) zc[k] = from_d<T>(w[k] - gpr[k] * zp - gqr[k] * zq);
 }
 
-// Extension b0 = v0 - A01 z1 (z1 already in z), in two passes: every 3D row
-// copies v0 (partial sums of b0^2 over rows without coupling), then the
-// coupling rows subtract their A01 z1 part (partial sums over those rows).
-template <typename T>
-__global__ void __launch_bounds__(BS) k_ext_copy(const T* __restrict__ v, T* __restrict__ z,
-                                                 const int32_t* __restrict__ mptr, const int64_t* off,
-                                                 const int32_t* binst, const int64_t* bstart, const int64_t* bend,
-                                                 const InstState* st, int want_mode, double* part) {
-  __shared__ double sh[BS / 64];
-  const int b = blockIdx.x;
-  const int i = binst[b];
-  if (st && !mode_ok(st[i], want_mode)) {
-    if (threadIdx.x == 0) part[b] = 0.0;
-    return;
-  }
-  const int64_t base = off[i];
-  double loc = 0.0;
-  constexpr int U = 8;
-  const int64_t r1 = bend[b];
-  for (int64_t r0 = bstart[b] + threadIdx.x; r0 < r1; r0 += (int64_t)U * BS) {
-    T vl[U];
-    bool free_row[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t g = base + min(r0 + (int64_t)u * BS, r1 - 1);
-      vl[u] = v[g];
-      free_row[u] = mptr[g + 1] == mptr[g];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t r = r0 + (int64_t)u * BS;
-      if (r >= r1) break;
-      z[base + r] = vl[u];
-      if (free_row[u]) loc += to_d(vl[u]) * to_d(vl[u]);
-    }
-  }
-  double t = block_sum(loc, sh);
-  if (threadIdx.x == 0) part[b] = t;
-}
-
+// Extension b0 = v0 - A01 z1 (z1 already in z), one launch with two kinds of
+// blocks.  Blocks [0, ncopy) take chunks of 3D rows: the rows without
+// coupling copy v0 and add to the partial sums of b0^2 (part3).  The other
+// blocks take chunks of coupling rows, G lanes per row: b0 = v0 - A01 z1 with
+// A01 in a compact CSR of its own, partial sums in part3m.  Each 3D row is
+// written by exactly one block.
 template <typename T, typename Tm, int G>
-__global__ void __launch_bounds__(BS) k_ext_rows(const T* __restrict__ v, T* __restrict__ z,
-                                                 const int32_t* __restrict__ mrows, const int32_t* __restrict__ mlp,
-                                                 const int32_t* __restrict__ mcol, const Tm* __restrict__ mval,
-                                                 const int32_t* __restrict__ ma01, const int64_t* off, int n3d,
-                                                 const int32_t* binst, const int64_t* bstart, const int64_t* bend,
-                                                 const InstState* st, int want_mode, double* part, int nblk) {
+__global__ void __launch_bounds__(BS) k_ext(const T* __restrict__ v, T* __restrict__ z,
+                                            const int32_t* __restrict__ mptr, const int64_t* off,
+                                            const int32_t* cinst, const int64_t* cstart, const int64_t* cend, int ncopy,
+                                            const int32_t* __restrict__ mrows, const int32_t* __restrict__ ap,
+                                            const int32_t* __restrict__ ac, const Tm* __restrict__ av,
+                                            const int32_t* rinst, const int64_t* rstart, const int64_t* rend,
+                                            const InstState* st, int want_mode, double* part3, double* part3m) {
   __shared__ double sh[BS / 64];
-  const int b = xcd_logical_block(nblk);
-  if (b < 0) return;
-  const int i = binst[b];
-  if (st && !mode_ok(st[i], want_mode)) {
-    if (threadIdx.x == 0) part[b] = 0.0;
+  double loc = 0.0;
+  if ((int)blockIdx.x < ncopy) {
+    const int b = blockIdx.x;
+    const int i = cinst[b];
+    if (st && !mode_ok(st[i], want_mode)) {
+      if (threadIdx.x == 0) part3[b] = 0.0;
+      return;
+    }
+    const int64_t base = off[i];
+    constexpr int U = 8;
+    const int64_t r1 = cend[b];
+    for (int64_t r0 = cstart[b] + threadIdx.x; r0 < r1; r0 += (int64_t)U * BS) {
+      T vl[U];
+      bool free_row[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t g = base + min(r0 + (int64_t)u * BS, r1 - 1);
+        vl[u] = v[g];
+        free_row[u] = mptr[g + 1] == mptr[g];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = r0 + (int64_t)u * BS;
+        if (r >= r1) break;
+        if (free_row[u]) {
+          z[base + r] = vl[u];
+          loc += to_d(vl[u]) * to_d(vl[u]);
+        }
+      }
+    }
+    const double t = block_sum(loc, sh);
+    if (threadIdx.x == 0) part3[b] = t;
     return;
   }
-  const int64_t base = off[i];
-  const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = BS / G;
-  double loc = 0.0;
-  for (int64_t q = bstart[b] + grp; q < bend[b]; q += ng) {
+  const int b = blockIdx.x - ncopy;
+  const int i = rinst[b];
+  if (st && !mode_ok(st[i], want_mode)) {
+    if (threadIdx.x == 0) part3m[b] = 0.0;
+    return;
+  }
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+  constexpr int NG = BS / G, U = 2;
+  for (int64_t q = rstart[b] + grp; q < rend[b]; q += NG) {
     const int row = mrows[q];
-    const int r = (int)(row - base);
+    const int e0 = ap[q], e1 = ap[q + 1];
+    const T vr = v[row];
     double acc = 0.0;
-    const int e = mlp[q + 1];
-    constexpr int U = 4;
-    for (int k0 = ma01[(int64_t)i * n3d + r] + lane; k0 < e; k0 += U * G) {
+    for (int k0 = e0 + lane; k0 < e1; k0 += U * G) {
       int cidx[U];
       Tm mv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int k = k0 + u * G;
-        cidx[u] = k < e ? mcol[k] : -1;
-        mv[u] = k < e ? mval[k] : (Tm)0;
+        const int k = min(k0 + u * G, e1 - 1);
+        cidx[u] = ac[k];
+        mv[u] = av[k];
       }
+      T zv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) zv[u] = z[cidx[u]];
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (cidx[u] >= 0) acc += (double)mv[u] * to_d(z[cidx[u]]);
+        if (k0 + u * G < e1) acc += (double)mv[u] * to_d(zv[u]);
     }
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
     if (lane == 0) {
-      const T stored = from_d<T>(to_d(v[row]) - acc);
+      const T stored = from_d<T>(to_d(vr) - acc);
       z[row] = stored;
       loc += to_d(stored) * to_d(stored);
     }
   }
-  double t = block_sum(loc, sh);
-  if (threadIdx.x == 0) part[b] = t;
+  const double t = block_sum(loc, sh);
+  if (threadIdx.x == 0) part3m[b] = t;
 }
 
 template <typename T>
@@ -1173,12 +1178,12 @@ void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, 
   if (sizeof(T) == 8) {
     hipLaunchKernelGGL((k_stencil_sweep<T, double>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
                        ytiles, zc, s->n_inst, st, mk);
-    hipLaunchKernelGGL((k_mrows<T, double, double, 8, 2>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
+    hipLaunchKernelGGL((k_mrows<T, double, double, 4, 2>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
                        s->d_mlp, s->d_mcol, s->d_mval64, x, y, MBLK(s), st, mk, (double*)nullptr, s->mblk.nblk, s->d_off, s->n3d);
   } else {
     hipLaunchKernelGGL((k_stencil_sweep<T, float>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
                        ytiles, zc, s->n_inst, st, mk);
-    hipLaunchKernelGGL((k_mrows<T, float, float, 8, 2>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
+    hipLaunchKernelGGL((k_mrows<T, float, float, 4, 2>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
                        s->d_mlp, s->d_mcol, s->d_mval32, x, y, MBLK(s), st, mk, (double*)nullptr, s->mblk.nblk, s->d_off, s->n3d);
   }
 }
@@ -1298,16 +1303,15 @@ template void launch_tree_solve<double>(mdnp_sys*, const double*, double*, const
 template <typename T>
 void launch_extension(mdnp_sys* s, const T* v, T* z, double* part3, double* part3m, const InstState* st,
                       int want_mode, hipStream_t stream) {
-  hipLaunchKernelGGL((k_ext_copy<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, v, z, s->d_mptr, s->d_off, BLK3(s), st,
-                     want_mode, part3);
+  const int nb = s->blk3.nblk + s->mblk3.nblk;
   if (sizeof(T) == 8)
-    hipLaunchKernelGGL((k_ext_rows<T, double, 8>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream, v, z,
-                       s->d_mrows, s->d_mlp, s->d_mcol, s->d_mval64, s->d_ma01, s->d_off, s->n3d, MBLK3(s), st,
-                       want_mode, part3m, s->mblk3.nblk);
+    hipLaunchKernelGGL((k_ext<T, double, 4>), dim3(nb), dim3(BS), 0, stream, v, z, s->d_mptr, s->d_off, BLK3(s),
+                       s->blk3.nblk, s->d_mrows, s->d_a01p, s->d_a01c, s->d_a01v64, MBLK3(s), st, want_mode, part3,
+                       part3m);
   else
-    hipLaunchKernelGGL((k_ext_rows<T, float, 8>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream, v, z,
-                       s->d_mrows, s->d_mlp, s->d_mcol, s->d_mval32, s->d_ma01, s->d_off, s->n3d, MBLK3(s), st,
-                       want_mode, part3m, s->mblk3.nblk);
+    hipLaunchKernelGGL((k_ext<T, float, 4>), dim3(nb), dim3(BS), 0, stream, v, z, s->d_mptr, s->d_off, BLK3(s),
+                       s->blk3.nblk, s->d_mrows, s->d_a01p, s->d_a01c, s->d_a01v32, MBLK3(s), st, want_mode, part3,
+                       part3m);
 }
 template void launch_extension<float>(mdnp_sys*, const float*, float*, double*, double*, const InstState*, int,
                                       hipStream_t);
