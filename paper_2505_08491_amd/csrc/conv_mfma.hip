@@ -621,7 +621,7 @@ struct RowsTile {
 struct RowsGrid {
   int ylo = 0, yhi = 0, zlo = 0, zhi = 0;  // output rows / planes computed
   int zc = 0, ytiles = 0;
-  int nedge = 0;  // leading workgroups per instance that compute the x = n - 1 column, one plane each
+  int nedge = 0;  // trailing workgroups per instance that compute the x = n - 1 column, one plane each
 };
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -640,11 +640,10 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
   int bxr, bt;
   xcd_remap(bxr, bt);
   if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
-  if (bxr < q.nedge) {
-    edge_plane<IN ? 8 : CA, CB, 16, IN, Tv, kEdgeYB>(p, bxr, bt, (f32x4*)ring);
+  if (bxr >= (int)gridDim.x - q.nedge) {
+    edge_plane<IN ? 8 : CA, CB, 16, IN, Tv, kEdgeYB>(p, bxr - ((int)gridDim.x - q.nedge), bt, (f32x4*)ring);
     return;
   }
-  bxr -= q.nedge;
   const int n = p.n_out;
   const int XW = n + 1;
   const int y0 = q.ylo + (bxr % q.ytiles) * MB;
@@ -886,11 +885,10 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
   int bxr, bt;
   xcd_remap(bxr, bt);
   if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
-  if (!EPI && bxr < q.nedge) {
-    edge_plane<CA, CB, 16, 0, Tv, kEdgeYB>(p, bxr, bt, (f32x4*)ring);
+  if (!EPI && bxr >= (int)gridDim.x - q.nedge) {
+    edge_plane<CA, CB, 16, 0, Tv, kEdgeYB>(p, bxr - ((int)gridDim.x - q.nedge), bt, (f32x4*)ring);
     return;
   }
-  bxr -= q.nedge;
   const int n = p.n_out;
   const int XW = n + 1;
   const int y0 = q.ylo + (bxr % q.ytiles) * TYR;
@@ -1129,11 +1127,10 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
   int bxr, bt;
   xcd_remap(bxr, bt);
   if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
-  if (bxr < q.nedge) {
-    edge_plane<CA, CB, COUT, 0, float, kEdgeYB>(p, bxr, bt, (f32x4*)ring);
+  if (bxr >= (int)gridDim.x - q.nedge) {
+    edge_plane<CA, CB, COUT, 0, float, kEdgeYB>(p, bxr - ((int)gridDim.x - q.nedge), bt, (f32x4*)ring);
     return;
   }
-  bxr -= q.nedge;
   const int n = p.n_out;
   const int XW = n + 1;
   const int y0 = q.ylo + (bxr % q.ytiles) * MB;
@@ -1289,102 +1286,89 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
   }
 }
 
-// Transposed stride-2 convolution.  Output o = 2 q + p along each axis; p = 0
-// takes tap 1 from input q, p = 1 takes tap 0 from input q + 1 and tap 2 from
-// input q.  One (y, z) parity class per blockIdx.y, both x parities per wave:
-// the 16 coarse voxels q of an M block give the output voxels 2q
-// (tap tx = 1 from q) and 2q + 1 (taps tx = 2 from q and tx = 0 from q + 1),
-// so the input fragments of q and q + 1 serve both and every wave writes the
-// 32 contiguous output voxels 2q, 2q + 1 of its block (whole cache lines).
+// Transposed stride-2 convolution, all eight output parities per wave.  Along
+// each axis the output o = 2 q + p takes tap 1 from input q when p = 0, and
+// taps 2 from q and 0 from q + 1 when p = 1.  A wave owns MB blocks of 16
+// consecutive coarse voxels q: it loads the input fragments of q + (ox, oy, oz)
+// for the 8 offsets once, then for each parity p accumulates the taps of the
+// offsets o contained in p (27 (o, p) pairs in all) and stores the 16 output
+// voxels 2 q + p.  grid y = output channel block of 16.  Weights come as MFMA
+// fragments [27 tap][CIN / 32][COUT / 16][64 lanes][8] (one coalesced 1 KiB
+// load per fragment).
 template <int CIN, int COUT, int MB>
-__global__ void __launch_bounds__(WAVES * 64) k_tconv_pair(const bf16* __restrict__ src, const bf16* __restrict__ W,
-                                                          const float* __restrict__ bias, bf16* __restrict__ dst,
-                                                          int n_in, const InstState* st, int want_mode) {
+__global__ void __launch_bounds__(WAVES * 64) k_tconv_all(const bf16* __restrict__ src, const bf16* __restrict__ WF,
+                                                         const float* __restrict__ bias, bf16* __restrict__ dst,
+                                                         int n_in, const InstState* st, int want_mode) {
   constexpr int NB = COUT / 16;
-  constexpr int CPT = CIN / 32;  // K chunks per tap
+  constexpr int CPT = CIN / 32;
   const int bt = blockIdx.z;
   if (st && !(st[bt].active && st[bt].mode == want_mode)) return;
-  const int cls = blockIdx.y;  // (py, pz)
-  const int py = cls & 1, pz = (cls >> 1) & 1;
-  const int cx = n_in, cy = n_in - py, cz = n_in - pz;
-  const int64_t ncls = (int64_t)cx * cy * cz;
+  const int nb = blockIdx.y;
   const int n_out = 2 * n_in - 1;
+  const int64_t nn_in = (int64_t)n_in * n_in, nvi = nn_in * n_in;
   const int64_t nvo = (int64_t)n_out * n_out * n_out;
-  const int64_t nvi = (int64_t)n_in * n_in * n_in;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, r = lane & 15;
   const int64_t mb0 = ((int64_t)blockIdx.x * WAVES + wave) * MB;
-  if (mb0 * 16 >= ncls) return;
-  int64_t vout[MB], ibase[MB];
-  bool ok[MB], ok1[MB];
+  if (mb0 * 16 >= nvi) return;
+  int64_t vin[MB], vout[MB];
+  unsigned okm[MB];  // bit 0: voxel exists; bits 1-3: q + 1 inside along x, y, z
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
     const int64_t v = (mb0 + m) * 16 + r;
-    ok[m] = v < ncls;
-    int qx = 0, qy = 0, qz = 0;
-    if (ok[m]) {
-      qx = (int)(v % cx);
-      qy = (int)((v / cx) % cy);
-      qz = (int)(v / ((int64_t)cx * cy));
-    }
-    ok1[m] = ok[m] && qx + 1 < n_in;  // the odd output 2q + 1 exists
-    vout[m] = ((int64_t)(2 * qz + pz) * n_out + (2 * qy + py)) * n_out + 2 * qx;
-    ibase[m] = ((int64_t)qz * n_in + qy) * n_in + qx;
+    const bool ok = v < nvi;
+    const int64_t vc = ok ? v : 0;
+    const int qx = (int)(vc % n_in), qy = (int)((vc / n_in) % n_in), qz = (int)(vc / nn_in);
+    okm[m] = ok ? (1u | (qx + 1 < n_in ? 2u : 0u) | (qy + 1 < n_in ? 4u : 0u) | (qz + 1 < n_in ? 8u : 0u)) : 0u;
+    vin[m] = vc;
+    vout[m] = ((int64_t)(2 * qz) * n_out + 2 * qy) * n_out + 2 * qx;
   }
   const bf16* X = src + (int64_t)bt * nvi * CIN;
-  f32x4 acc0[MB][NB], acc1[MB][NB];  // even / odd output x
+  bf16x8 xin[MB][8][CPT];
 #pragma unroll
   for (int m = 0; m < MB; ++m)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc0[m][nb] = acc1[m][nb] = {0.f, 0.f, 0.f, 0.f};
-  const int ntap = 1 << (py + pz);  // (y, z) tap combinations of the class
-  for (int j = 0; j < ntap; ++j) {
-    int b = 0;
-    int ty = 1, tz = 1, oy = 0, oz = 0;
-    if (py) { const int sgn = (j >> b++) & 1; ty = sgn ? 2 : 0; oy = sgn ? 0 : 1; }
-    if (pz) { const int sgn = (j >> b++) & 1; tz = sgn ? 2 : 0; oz = sgn ? 0 : 1; }
-    const int64_t toff = ((int64_t)oz * n_in + oy) * n_in;
-    const int tap_c = tz * 9 + ty * 3 + 1, tap_l = tz * 9 + ty * 3 + 2, tap_r = tz * 9 + ty * 3 + 0;
-    for (int cc = 0; cc < CPT; ++cc) {
-      const int ci = cc * 32 + g * 8;
-      bf16x8 wc[NB], wl[NB], wr[NB];
+    for (int o = 0; o < 8; ++o) {
+      const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+      const unsigned need = 1u | (ox ? 2u : 0u) | (oy ? 4u : 0u) | (oz ? 8u : 0u);
+      const bool valid = (okm[m] & need) == need;
+      const int64_t vi = vin[m] + ox + oy * (int64_t)n_in + oz * nn_in;
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const bf16* wb = W + (int64_t)(nb * 16 + r) * 27 * CIN + ci;
-        wc[nb] = load8(wb + (int64_t)tap_c * CIN);
-        wl[nb] = load8(wb + (int64_t)tap_l * CIN);
-        wr[nb] = load8(wb + (int64_t)tap_r * CIN);
-      }
+      for (int cc = 0; cc < CPT; ++cc)
+        xin[m][o][cc] = valid ? load8(X + vi * CIN + cc * 32 + g * 8) : zero8();
+    }
+  const u32x4* wf = (const u32x4*)WF + lane;
+  bf16* Y = dst + (int64_t)bt * nvo * COUT;
+  const int co = nb * 16 + g * 4;
+  const float b0 = bias[co], b1 = bias[co + 1], b2 = bias[co + 2], b3 = bias[co + 3];
 #pragma unroll
-      for (int m = 0; m < MB; ++m) {
-        const bf16x8 x0 = ok[m] ? load8(X + (ibase[m] + toff) * CIN + ci) : zero8();
-        const bf16x8 x1 = ok1[m] ? load8(X + (ibase[m] + toff + 1) * CIN + ci) : zero8();
+  for (int p = 0; p < 8; ++p) {
+    const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
+    f32x4 acc[MB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          acc0[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wc[nb], x0, acc0[m][nb], 0, 0, 0);
-          acc1[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl[nb], x0, acc1[m][nb], 0, 0, 0);
-          acc1[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[nb], x1, acc1[m][nb], 0, 0, 0);
-        }
+    for (int m = 0; m < MB; ++m) acc[m] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      if (o & ~p) continue;
+      const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+      const int tx = px ? (ox ? 0 : 2) : 1, ty = py ? (oy ? 0 : 2) : 1, tz = pz ? (oz ? 0 : 2) : 1;
+      const int tap = tz * 9 + ty * 3 + tx;
+#pragma unroll
+      for (int cc = 0; cc < CPT; ++cc) {
+        const bf16x8 w = __builtin_bit_cast(bf16x8, wf[((tap * CPT + cc) * NB + nb) * 64]);
+#pragma unroll
+        for (int m = 0; m < MB; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xin[m][o][cc], acc[m], 0, 0, 0);
       }
     }
-  }
-  bf16* Y = dst + (int64_t)bt * nvo * COUT;
+    const unsigned need = 1u | (px ? 2u : 0u) | (py ? 4u : 0u) | (pz ? 8u : 0u);
 #pragma unroll
-  for (int m = 0; m < MB; ++m) {
-    if (!ok[m]) continue;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int co = nb * 16 + g * 4;
-      const float b0 = bias[co], b1 = bias[co + 1], b2 = bias[co + 2], b3 = bias[co + 3];
+    for (int m = 0; m < MB; ++m) {
+      if ((okm[m] & need) != need) continue;
+      const int64_t vo = vout[m] + ((int64_t)pz * n_out + py) * n_out + px;
       uint2 pk;
-      pk.x = (unsigned)f2bf(acc0[m][nb][0] + b0) | ((unsigned)f2bf(acc0[m][nb][1] + b1) << 16);
-      pk.y = (unsigned)f2bf(acc0[m][nb][2] + b2) | ((unsigned)f2bf(acc0[m][nb][3] + b3) << 16);
-      *(uint2*)(Y + vout[m] * COUT + co) = pk;
-      if (ok1[m]) {
-        pk.x = (unsigned)f2bf(acc1[m][nb][0] + b0) | ((unsigned)f2bf(acc1[m][nb][1] + b1) << 16);
-        pk.y = (unsigned)f2bf(acc1[m][nb][2] + b2) | ((unsigned)f2bf(acc1[m][nb][3] + b3) << 16);
-        *(uint2*)(Y + (vout[m] + 1) * COUT + co) = pk;
-      }
+      pk.x = (unsigned)f2bf(acc[m][0] + b0) | ((unsigned)f2bf(acc[m][1] + b1) << 16);
+      pk.y = (unsigned)f2bf(acc[m][2] + b2) | ((unsigned)f2bf(acc[m][3] + b3) << 16);
+      *(uint2*)(Y + vo * COUT + co) = pk;
     }
   }
 }
@@ -1594,13 +1578,13 @@ void launch_conv(const ConvP& p, int batch, const bf16* w, hipStream_t stream) {
 }
 
 template <int CIN, int COUT, int MB>
-void launch_tconv(const ConvP& p, int batch, const bf16* w, hipStream_t stream) {
-  const int64_t ncls = (int64_t)p.n_in * p.n_in * p.n_in;  // largest (y, z) class
-  const int64_t nmb = (ncls + 15) / 16;
-  const dim3 grid((unsigned)((nmb + WAVES * MB - 1) / (WAVES * MB)), 4, batch);
-  hipLaunchKernelGGL((k_tconv_pair<CIN, COUT, MB>), grid, dim3(WAVES * 64), 0, stream, (const bf16*)p.a, w, p.bias,
+void launch_tconv_all(const ConvP& p, int batch, const bf16* wfrag, hipStream_t stream) {
+  const int64_t nmb = ((int64_t)p.n_in * p.n_in * p.n_in + 15) / 16;
+  const dim3 grid((unsigned)((nmb + WAVES * MB - 1) / (WAVES * MB)), COUT / 16, batch);
+  hipLaunchKernelGGL((k_tconv_all<CIN, COUT, MB>), grid, dim3(WAVES * 64), 0, stream, (const bf16*)p.a, wfrag, p.bias,
                      (bf16*)p.y, p.n_in, p.st, p.want_mode);
 }
+
 
 }  // namespace
 
@@ -1641,6 +1625,19 @@ __global__ void k_w_rows(const float* __restrict__ w, bf16* __restrict__ o) {
   o[k] = __float2bfloat16(v);
 }
 
+// Transposed-convolution weights as MFMA A fragments: element e of lane
+// (g, r) of fragment (tap, cc, nb) is w[nb * 16 + r][tap][cc * 32 + g * 8 + e].
+template <int CIN, int COUT>
+__global__ void k_w_tfrag(const float* __restrict__ w, bf16* __restrict__ o) {
+  constexpr int CPT = CIN / 32, NB = COUT / 16;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 27 * CPT * NB * 512) return;
+  const int e = k % 8, lane = (k / 8) % 64, f = k / 512;
+  const int nb = f % NB, cc = (f / NB) % CPT, tap = f / (NB * CPT);
+  const int g = lane >> 4, r = lane & 15;
+  o[k] = __float2bfloat16(w[((int64_t)(nb * 16 + r) * 27 + tap) * CIN + cc * 32 + g * 8 + e]);
+}
+
 constexpr int64_t kIn8Count = 16 * 27 * 8;
 constexpr int64_t kRowsIn0 = 16 * 3 * RowsK<2, 1>::KCT * 32;
 constexpr int64_t kRowsL0b = 16 * 3 * RowsK<16, 0>::KCT * 32;
@@ -1649,6 +1646,8 @@ constexpr int64_t kRowsD0 = 16 * 3 * RowsK<32, 0>::KCT * 32;
 constexpr int64_t kRowsL1b = 32 * 3 * RowsK<32, 0>::KCT * 32;
 constexpr int64_t kRowsL2b = 64 * 3 * RowsK<64, 0>::KCT * 32;
 constexpr int64_t kRowsD1 = 32 * 3 * RowsK<64, 0>::KCT * 32;
+constexpr int64_t kTfU1 = 27 * (64 / 32) * (32 / 16) * 512;
+constexpr int64_t kTfU0 = 27 * (32 / 32) * (16 / 16) * 512;
 constexpr int64_t kZeroCount = 128;  // 256 zero bytes
 
 struct MfmaWeights {
@@ -1659,6 +1658,8 @@ struct MfmaWeights {
   const bf16* rows_l1b;
   const bf16* rows_l2b;
   const bf16* rows_d1;
+  const bf16* tf_u1;
+  const bf16* tf_u0;
   const bf16* zeros;
 };
 
@@ -1672,13 +1673,16 @@ static MfmaWeights mfma_extra(const CnnState& c) {
   x.rows_l1b = x.rows_d0 + kRowsD0;
   x.rows_l2b = x.rows_l1b + kRowsL1b;
   x.rows_d1 = x.rows_l2b + kRowsL2b;
-  x.zeros = x.rows_d1 + kRowsD1;
+  x.tf_u1 = x.rows_d1 + kRowsD1;
+  x.tf_u0 = x.tf_u1 + kTfU1;
+  x.zeros = x.tf_u0 + kTfU0;
   return x;
 }
 
 void cnn_prepare_mfma_weights(CnnState& c, const float* d_w, hipStream_t stream) {
   const int64_t tot = mfma_weight_count();
-  const int64_t extra = kIn8Count + kRowsIn0 + kRowsL0b + kRowsD0 + kRowsL1b + kRowsL2b + kRowsD1 + kZeroCount;
+  const int64_t extra =
+      kIn8Count + kRowsIn0 + kRowsL0b + kRowsD0 + kRowsL1b + kRowsL2b + kRowsD1 + kTfU1 + kTfU0 + kZeroCount;
   if (!c.wmf && hipMalloc(&c.wmf, sizeof(bf16) * (size_t)(tot + extra)) != hipSuccess) {
     c.wmf = nullptr;
     return;
@@ -1699,6 +1703,10 @@ void cnn_prepare_mfma_weights(CnnState& c, const float* d_w, hipStream_t stream)
                      (bf16*)x.rows_l2b);
   hipLaunchKernelGGL((k_w_rows<64, 0, 32>), dim3((kRowsD1 + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[7],
                      (bf16*)x.rows_d1);
+  hipLaunchKernelGGL((k_w_tfrag<64, 32>), dim3((kTfU1 + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[6],
+                     (bf16*)x.tf_u1);
+  hipLaunchKernelGGL((k_w_tfrag<32, 16>), dim3((kTfU0 + 255) / 256), dim3(256), 0, stream, d_w + c.w_off[8],
+                     (bf16*)x.tf_u0);
   for (int l = 0; l < kNumLayers; ++l) {
     const LayerSpec& L = kLayers[l];
     const int64_t nw = (int64_t)L.cout * (L.kind == KIND_PT ? 1 : 27) * L.cin;
@@ -1796,14 +1804,14 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
       launch_convw<64, 0, 64, 2, 8, 2>(a, batch, stream);
       break;
     }
-    case 6: launch_tconv<64, 32, 4>(p, batch, w, stream); break;         // U1
+    case 6: launch_tconv_all<64, 32, 1>(p, batch, mfma_extra(c).tf_u1, stream); break;  // U1
     case 7: {                                                             // D1
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_d1;
       launch_convw<32, 32, 32, 3, 4, 3>(a, batch, stream);
       break;
     }
-    case 8: launch_tconv<32, 16, 4>(p, batch, w, stream); break;         // U0
+    case 8: launch_tconv_all<32, 16, 2>(p, batch, mfma_extra(c).tf_u0, stream); break;  // U0
     case 9: {                                                             // D0
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_d0;
