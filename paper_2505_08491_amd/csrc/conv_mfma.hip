@@ -618,6 +618,11 @@ struct RowsTile {
   }
 };
 
+// Workgroups aimed at by the z split of the sweep launches (over the batch):
+// longer sweeps for the fused last layer and the 64-channel level.
+constexpr int kSweepBlocksD0 = 256;
+constexpr int kSweepBlocksL2b = 384;
+
 struct RowsGrid {
   int ylo = 0, yhi = 0, zlo = 0, zhi = 0;  // output rows / planes computed
   int zc = 0, ytiles = 0;
@@ -1483,7 +1488,7 @@ void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream) {
 // the EDGE kernel for x = n - 1 (not needed with the head: that column is
 // Dirichlet).
 template <int CA, int CB, int MB, int KS, int EPI, typename Tv>
-void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream) {
+void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream, int target = 1024) {
   constexpr int NLW = 4;
   constexpr int TYR = KS ? MB : 2 * MB;
   typedef RowsTile<CA + CB, 0> T;
@@ -1502,7 +1507,7 @@ void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream) {
   q.yhi = q.zhi = EPI ? n - 1 : n;
   q.ytiles = (q.yhi - q.ylo + TYR - 1) / TYR;
   const int planes = q.zhi - q.zlo;
-  int nz = (1024 + q.ytiles * batch - 1) / (q.ytiles * batch);
+  int nz = (target + q.ytiles * batch - 1) / (q.ytiles * batch);
   nz = std::max(1, std::min(nz, planes));
   q.zc = (planes + nz - 1) / nz;
   nz = (planes + q.zc - 1) / q.zc;
@@ -1519,7 +1524,7 @@ void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream) {
 // Coarse-level stride-1 layers (COUT = 32 or 64): the K-split sweep for
 // x < n - 1 plus the EDGE kernel for x = n - 1; launch_s1 where it does not fit.
 template <int CA, int CB, int COUT, int MB, int KG, int NPF>
-void launch_convw(const MfmaArgs& a, int batch, hipStream_t stream) {
+void launch_convw(const MfmaArgs& a, int batch, hipStream_t stream, int target = 1024) {
   typedef RowsTile<CA + CB, 0> T;
   constexpr int NF = MB * (COUT / 16);
   const int n = a.n_out;
@@ -1535,7 +1540,7 @@ void launch_convw(const MfmaArgs& a, int batch, hipStream_t stream) {
   q.ylo = q.zlo = 0;
   q.yhi = q.zhi = n;
   q.ytiles = (n + MB - 1) / MB;
-  int nz = (1024 + q.ytiles * batch - 1) / (q.ytiles * batch);
+  int nz = (target + q.ytiles * batch - 1) / (q.ytiles * batch);
   nz = std::max(1, std::min(nz, n));
   q.zc = (n + nz - 1) / nz;
   nz = (n + q.zc - 1) / q.zc;
@@ -1770,7 +1775,7 @@ void conv_mfma_d0_head(const CnnState& c, const bf16* u0, const bf16* s0, int n,
   a.alpha_override = alpha_override;
   a.scale = scale;
   (void)nmb;
-  launch_ks16<16, 16, 4, 1, 1, Tv>(a, batch, stream);
+  launch_ks16<16, 16, 4, 1, 1, Tv>(a, batch, stream, kSweepBlocksD0);
 }
 template void conv_mfma_d0_head<float>(const CnnState&, const bf16*, const bf16*, int, int, float*, const int64_t*,
                                        const double*, double, const double*, const InstState*, hipStream_t);
@@ -1801,7 +1806,7 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
     case 5: {                                                             // L2b
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_l2b;
-      launch_convw<64, 0, 64, 2, 8, 2>(a, batch, stream);
+      launch_convw<64, 0, 64, 2, 8, 2>(a, batch, stream, kSweepBlocksL2b);
       break;
     }
     case 6: launch_tconv_all<64, 32, 1>(p, batch, mfma_extra(c).tf_u1, stream); break;  // U1
