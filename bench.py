@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--jacobi-steps", type=int, default=1)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-jacobi", action="store_true")
+    ap.add_argument("--smooth-sweeps", type=int, default=1,
+                    help="Jacobi pre/post-smoothing steps of the extra smoothed solve (0: skip it)")
+    ap.add_argument("--smooth-omega", type=float, default=0.8)
     ap.add_argument("--cpu-neural-iters", type=int, default=3)
     ap.add_argument("--cpu-jacobi-iters", type=int, default=50)
     return ap.parse_args()
@@ -225,6 +228,22 @@ def main():
     ms_cnn = time_kernel(ctx, lambda: ctx.cnn_forward(wd, xin, n, a.cnn_dtype), 5)
     del xin
 
+    # the same solve with Jacobi pre/post-smoothing of the network's 3D solve
+    smoothed = None
+    if a.smooth_sweeps > 0:
+        S.set_preconditioner("neural", weights=w, cnn_dtype=a.cnn_dtype)
+        S.set_smoothing(a.smooth_sweeps, a.smooth_omega)
+        Ts, sts = run(neural_opts, a.steps, 1)
+        rel_s = true_rel()
+        ms_prec_s = time_kernel(ctx, lambda: S.precond_apply(xs), 5)
+        S.set_smoothing(0)
+        smoothed = {"sweeps": a.smooth_sweeps, "omega": a.smooth_omega,
+                    "solves_per_s": S.n_inst * a.steps / Ts, "ms_per_solve": Ts / a.steps * 1e3,
+                    "iters_mean": float(np.mean([q["iters"] + q["fallback_iters"] for q in sts])),
+                    "converged_all": all(q["converged"] for q in sts),
+                    "used_fallback": int(sum(q["used_fallback"] for q in sts)), "max_true_rel_res": max(rel_s),
+                    "ms_per_apply": ms_prec_s}
+
     jac = None
     if not a.skip_jacobi:
         S.set_preconditioner("jacobi")
@@ -247,6 +266,7 @@ def main():
                    "weights": os.path.relpath(wpath, ROOT) if trained else "untrained (Kaiming init)"},
         "neural": {"iters_mean": float(np.mean(neural_iters)), "iters_max": int(max(neural_iters)),
                    "converged_all": conv_all, "used_fallback": int(n_fb), "max_true_rel_res": max(rel_n)},
+        "neural_smoothed": smoothed,
         "jacobi": jac,
         "roofline": {"bound": "hbm", "kernel": "k_stencil_sweep + k_mrows (batched y = (S + M) x, FP32)",
                      "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,

@@ -159,6 +159,18 @@ mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* sys, mdnp_prec_kind
                                     const float* weights, int64_t n_weights, double alpha,
                                     mdnp_dtype cnn_dtype);
 
+/* Jacobi pre- and post-smoothing of the network's 3D solve (Section 5, "Effect
+ * of pre- and post-smoothing"): with sweeps > 0 the MDNP_PREC_NEURAL
+ * preconditioner computes its 3D part as
+ *   z0 = `sweeps` damped Jacobi steps z <- z + omega D^-1 (b0 - A00 z) from 0,
+ *   z0 += N(b0 - A00 z0)   (the network with its own normalisation),
+ *   z0 = `sweeps` more steps from z0,
+ * D = diag(A00).  sweeps = 0 switches it off (the default).  Takes effect on
+ * the next solve or preconditioner application; allocates three vectors of
+ * the system's length and type, freed with the system or by sweeps = 0.
+ * Errors: MDNP_E_ARG (sweeps outside [0, 16], omega outside (0, 2)). */
+mdnp_status mdnp_set_smoothing(mdnp_ctx* ctx, mdnp_sys* sys, int32_t sweeps, double omega);
+
 /* ---------------------------------------------------------------- solve */
 
 /* Restarted right-preconditioned FGMRES(m) on every instance at once (Section

@@ -12,7 +12,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   "twosteps"): an exact 1D solve with the lower diagonal block, then the 3D
   correction b0 - A01 z1 handed to a 3D solver P3D (eq. "decoupled_3d_problem").
 * P3D choices: Jacobi (diag(A00)^-1), exact (A00^-1, pins only) and the
-  neural operator (module `cnn`).
+  neural operator (module `cnn`), optionally wrapped in damped-Jacobi pre-
+  and post-smoothing (Section 5, "Effect of pre- and post-smoothing").
 """
 from __future__ import annotations
 
@@ -188,6 +189,31 @@ def p3d_neural(system, net_apply):
         z = (s / alpha) * U
         z[bnd] = b[bnd]
         return z
+    return apply
+
+
+def jacobi_sweeps(A, b, z, omega, sweeps):
+    """`sweeps` damped Jacobi steps z <- z + omega D^-1 (b - A z), D = diag(A)
+    (the relaxation S_J of Section 5, "Effect of pre- and post-smoothing")."""
+    dinv = 1.0 / A.diagonal()
+    for _ in range(sweeps):
+        z = z + omega * dinv * (b - A @ z)
+    return z
+
+
+def p3d_smoothed(system, p3d, omega, sweeps):
+    """P3D wrapped in Jacobi pre- and post-smoothing on A00 (Section 5,
+    "Effect of pre- and post-smoothing"): `sweeps` relaxation steps on
+    A00 z = b from z = 0, the correction z += P3D(b - A00 z) on the remaining
+    residual, then `sweeps` relaxation steps from the corrected z.  The paper
+    names the smoother S_J(A, r, x0, maxit) without its damping or step count;
+    omega and sweeps are parameters here."""
+    A00 = system.blocks()[0].tocsr()
+
+    def apply(b):
+        z = jacobi_sweeps(A00, b, np.zeros_like(b), omega, sweeps)
+        z = z + p3d(b - A00 @ z)
+        return jacobi_sweeps(A00, b, z, omega, sweeps)
     return apply
 
 

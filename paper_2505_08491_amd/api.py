@@ -241,6 +241,10 @@ class System:
                                                     w.ctypes.data if w is not None else None, n, alpha,
                                                     DTYPE[cnn_dtype]))
 
+    def set_smoothing(self, sweeps: int, omega: float = 0.8):
+        """Jacobi pre/post-smoothing of the neural 3D solve (0 sweeps: off)."""
+        self.ctx._check(lib.mdnp_set_smoothing(self.ctx.h, self.h, int(sweeps), float(omega)))
+
     @staticmethod
     def opts(restart=30, max_iters=1000, fallback_restart=50, fallback_max_iters=0, tol=1e-8, history=True,
              use_graph=False) -> SolveOpts:

@@ -118,7 +118,13 @@ void free_work(SolveWork& w) {
   w = SolveWork();
 }
 
+void free_smooth(SmoothState& m) {
+  dfree(m.sb); dfree(m.sr); dfree(m.t);
+  m = SmoothState();
+}
+
 void free_sys(mdnp_sys* s) {
+  free_smooth(s->smooth);
   void* ptrs[] = {s->d_off, s->d_stencil, s->d_mptr, s->d_mcol, s->d_mval64, s->d_mval32, s->d_ma01, s->d_mrows, s->d_mlp,
                   s->d_a01p, s->d_a01c, s->d_a01v64, s->d_a01v32, s->d_dinv, s->d_dist,
                   s->d_alpha, s->d_t_off, s->d_t_lvloff, s->d_t_lvlptr, s->d_t_lvlnodes, s->d_t_parent,
@@ -704,6 +710,39 @@ extern "C" mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* s, mdnp_
   });
 }
 
+extern "C" mdnp_status mdnp_set_smoothing(mdnp_ctx* ctx, mdnp_sys* s, int32_t sweeps, double omega) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s) fail(MDNP_E_ARG, "null system");
+    if (sweeps < 0 || sweeps > 16) fail(MDNP_E_ARG, "sweeps must be in [0, 16]");
+    if (sweeps > 0 && !(omega > 0.0 && omega < 2.0)) fail(MDNP_E_ARG, "omega must be in (0, 2)");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (s->work.graph) {
+      (void)hipGraphExecDestroy(s->work.graph);
+      s->work.graph = nullptr;
+      s->work.graph_m = -1;
+    }
+    SmoothState& m = s->smooth;
+    if (sweeps == 0) {
+      free_smooth(m);
+      return;
+    }
+    if (!m.sb) {
+      const size_t bytes = vsize(s->vec_dtype) * (size_t)s->ntot;
+      m.sb = dalloc<char>(bytes);
+      m.sr = dalloc<char>(bytes);
+      m.t = dalloc<char>(bytes);
+      // the 1D parts are never written by the smoothing kernels: keep them finite
+      HIPCHK(hipMemsetAsync(m.sb, 0, bytes, ctx->stream));
+      HIPCHK(hipMemsetAsync(m.sr, 0, bytes, ctx->stream));
+      HIPCHK(hipMemsetAsync(m.t, 0, bytes, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    m.sweeps = sweeps;
+    m.omega = omega;
+  });
+}
+
 // ============================================================================ solve
 
 namespace {
@@ -748,9 +787,15 @@ void apply_prec(mdnp_sys* s, const T* v, T* z, const InstState* st, bool any_fb,
       launch_extension<T>(s, v, z, P.p3, P.pM3, st, 0, stream);
       if (s->kind == MDNP_PREC_BLOCK_JACOBI) {
         launch_block_jacobi3d<T>(s, z, st, 0, stream);
+      } else if (s->smooth.sweeps > 0) {
+        // z0 = S(b0): pre-smoothing, the network on the remaining residual, post-smoothing
+        launch_smooth_pre<T>(s, z, st, P.p3, stream);
+        launch_inv_scale(s, P.p3, nullptr, s->cnn.inv_s, const_cast<InstState*>(st), 0, stream);
+        cnn_apply_in_solver<T>(s, (const T*)s->smooth.sr, z, 1, st, stream);
+        launch_smooth_post<T>(s, z, st, stream);
       } else {
         launch_inv_scale(s, P.p3, P.pM3, s->cnn.inv_s, const_cast<InstState*>(st), 0, stream);
-        cnn_apply_in_solver<T>(s, z, st, stream);
+        cnn_apply_in_solver<T>(s, z, z, 0, st, stream);
       }
       break;
   }

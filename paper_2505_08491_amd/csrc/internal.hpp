@@ -67,6 +67,16 @@ struct CnnState {
   size_t loss_bytes = 0;
 };
 
+// Jacobi pre/post-smoothing of the neural 3D solve (sweeps = 0: off) and its
+// scratch vectors (full length, vector type).
+struct SmoothState {
+  int sweeps = 0;
+  double omega = 0.0;
+  void* sb = nullptr;          // b0
+  void* sr = nullptr;          // network input b0 - A00 z
+  void* t = nullptr;           // A00 z
+};
+
 struct SolveWork {
   int m = 0;                   // restart the buffers were sized for
   int hist_cap = 0;
@@ -174,5 +184,6 @@ struct mdnp_sys {
   bool prec_set = false;
   double alpha_override = 0.0;
   mdnp::CnnState cnn;
+  mdnp::SmoothState smooth;
   mdnp::SolveWork work;
 };

@@ -291,14 +291,16 @@ __global__ void __launch_bounds__(BS) k_stencil(const double* __restrict__ stenc
 
 // Coupling rows (3D rows touched by the averaging operator and all 1D rows),
 // G lanes per row: y[row] += (M x)[row] (RES = 0), the same with the 1D rows
-// overwritten instead (RES = 2: y holds only the 3D stencil part), or
-// r[row] -= (M x)[row] with partial sums of r^2 (RES = 1).
+// overwritten instead (RES = 2: y holds only the 3D stencil part),
+// r[row] -= (M x)[row] with partial sums of r^2 (RES = 1), or, over the 3D
+// rows only, y[row] += (M00 x)[row] leaving out the A01 entries (RES = 3).
 template <typename Tv, typename Tm, typename Tacc, int G, int RES>
 __global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows, const int32_t* __restrict__ mlp,
                                               const int32_t* __restrict__ mcol, const Tm* __restrict__ mval,
                                               const Tv* __restrict__ x, Tv* __restrict__ y, const int32_t* binst,
                                               const int64_t* bstart, const int64_t* bend, const InstState* st,
-                                              int mask, double* part, int nblk, const int64_t* off = nullptr, int n3d = 0) {
+                                              int mask, double* part, int nblk, const int64_t* off = nullptr, int n3d = 0,
+                                              const int32_t* __restrict__ ap = nullptr) {
   __shared__ double sh[BS / 64];
   const int b = xcd_logical_block(nblk);
   if (b < 0) return;
@@ -313,7 +315,8 @@ __global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows,
   for (int64_t q = bstart[b] + grp; q < bend[b]; q += ng) {
     const int row = mrows[q];
     Tacc acc = 0;
-    const int e = mlp[q + 1];
+    // RES = 3 (A00 only): the row's A01 entries, its last ones, are left out
+    const int e = RES == 3 ? mlp[q + 1] - (ap[q + 1] - ap[q]) : mlp[q + 1];
     // U entries per lane per pass, all loads of a pass in flight together
     // (indices clamped into the row: every listed row has entries)
     constexpr int U = 32 / G;
@@ -808,12 +811,80 @@ __global__ void k_inv_scale(const double* part3, const int32_t* first, const dou
   const int i = blockIdx.x;
   if (i >= n_inst) return;
   if (st && !mode_ok(st[i], want_mode)) return;
-  double s = wave_inst_sum(part3, first, i) + wave_inst_sum(part4, first4, i);
+  double s = wave_inst_sum(part3, first, i) + (part4 ? wave_inst_sum(part4, first4, i) : 0.0);
   if (threadIdx.x != 0) return;
   s = sqrt(s);
   inv_s[i] = s > 0.0 ? 1.0 / s : 0.0;
   inv_s[n_inst + i] = s;
   if (st) st[i].scale3d = s;
+}
+
+// ---------------------------------------------------------------- Jacobi smoothing of the 3D solve
+// Damped Jacobi relaxation z <- z + omega D^-1 (b0 - A00 z) around the network
+// (Section 5, pre- and post-smoothing), over the 3D rows of the instances on
+// the configured preconditioner.  D = diag(A00) (unit on Dirichlet rows).
+
+// First relaxation step from z = 0: keeps b0 (from the extension, in z) in sb
+// and sets z = omega D^-1 b0.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_smooth_first(T* __restrict__ z, T* __restrict__ sb,
+                                                     const double* __restrict__ dinv, double omega, const int64_t* off,
+                                                     const int32_t* binst, const int64_t* bstart, const int64_t* bend,
+                                                     const InstState* st) {
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (st && !mode_ok(st[i], 0)) return;
+  const int64_t base = off[i];
+  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += BS) {
+    const int64_t g = base + r;
+    const T b0 = z[g];
+    sb[g] = b0;
+    z[g] = from_d<T>(omega * dinv[g] * to_d(b0));
+  }
+}
+
+// One relaxation step z += omega D^-1 (sb - t), t = A00 z.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_smooth_sweep(T* __restrict__ z, const T* __restrict__ sb,
+                                                     const T* __restrict__ t, const double* __restrict__ dinv,
+                                                     double omega, const int64_t* off, const int32_t* binst,
+                                                     const int64_t* bstart, const int64_t* bend, const InstState* st) {
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (st && !mode_ok(st[i], 0)) return;
+  const int64_t base = off[i];
+  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += BS) {
+    const int64_t g = base + r;
+    z[g] = from_d<T>(to_d(z[g]) + omega * dinv[g] * (to_d(sb[g]) - to_d(t[g])));
+  }
+}
+
+// Residual of the pre-smoothed z: sr = sb - t (t = A00 z), the network input,
+// with per-block partial sums of sr^2 for its normalisation.  On the Dirichlet
+// rows the 3D solver returns its input, so sr is added to z there.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_smooth_res(T* __restrict__ z, const T* __restrict__ sb,
+                                                   const T* __restrict__ t, T* __restrict__ sr, int n,
+                                                   const int64_t* off, const int32_t* binst, const int64_t* bstart,
+                                                   const int64_t* bend, const InstState* st, double* part) {
+  __shared__ double sh[BS / 64];
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (st && !mode_ok(st[i], 0)) {
+    if (threadIdx.x == 0) part[b] = 0.0;
+    return;
+  }
+  const int64_t base = off[i];
+  double loc = 0.0;
+  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += BS) {
+    const int64_t g = base + r;
+    const T rv = from_d<T>(to_d(sb[g]) - to_d(t[g]));
+    sr[g] = rv;
+    loc += to_d(rv) * to_d(rv);
+    if (is_boundary((int)r, n)) z[g] = from_d<T>(to_d(z[g]) + to_d(rv));
+  }
+  const double tt = block_sum(loc, sh);
+  if (threadIdx.x == 0) part[b] = tt;
 }
 
 // ---------------------------------------------------------------- Arnoldi (modified Gram-Schmidt)
@@ -1189,6 +1260,78 @@ void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, 
 }
 template void launch_spmv<float>(mdnp_sys*, const float*, float*, const InstState*, bool, hipStream_t);
 template void launch_spmv<double>(mdnp_sys*, const double*, double*, const InstState*, bool, hipStream_t);
+
+// y = A00 x on the 3D rows of the instances on the configured preconditioner
+// (x, y full-length vectors): the stencil sweep, then the 3D coupling rows
+// without their A01 entries.
+template <typename T>
+void launch_a00(mdnp_sys* s, const T* x, T* y, const InstState* st, hipStream_t stream) {
+  const int n = s->n;
+  if (n > 64 * SW_NX) {  // one thread per row (no masking: y is scratch)
+    launch_spmv_a00_all<T>(s, x, y, stream);
+    return;
+  }
+  const int mk = st ? 1 : 0;
+  const int ytiles = (n + SW_TY - 1) / SW_TY;
+  int nz = (2048 + ytiles * s->n_inst - 1) / (ytiles * s->n_inst);
+  nz = std::max(1, std::min(nz, n));
+  const int zc = (n + nz - 1) / nz;
+  nz = (n + zc - 1) / zc;
+  const dim3 grid(xcd_grid(ytiles * nz * s->n_inst));
+  if (sizeof(T) == 8) {
+    hipLaunchKernelGGL((k_stencil_sweep<T, double>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
+                       ytiles, zc, s->n_inst, st, mk);
+    hipLaunchKernelGGL((k_mrows<T, double, double, 4, 3>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream,
+                       s->d_mrows, s->d_mlp, s->d_mcol, s->d_mval64, x, y, MBLK3(s), st, mk, (double*)nullptr,
+                       s->mblk3.nblk, s->d_off, s->n3d, s->d_a01p);
+  } else {
+    hipLaunchKernelGGL((k_stencil_sweep<T, float>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
+                       ytiles, zc, s->n_inst, st, mk);
+    hipLaunchKernelGGL((k_mrows<T, float, float, 4, 3>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream,
+                       s->d_mrows, s->d_mlp, s->d_mcol, s->d_mval32, x, y, MBLK3(s), st, mk, (double*)nullptr,
+                       s->mblk3.nblk, s->d_off, s->n3d, s->d_a01p);
+  }
+}
+
+template void launch_a00<float>(mdnp_sys*, const float*, float*, const InstState*, hipStream_t);
+template void launch_a00<double>(mdnp_sys*, const double*, double*, const InstState*, hipStream_t);
+
+// The smoothed 3D solve of the neural preconditioner, after the extension has
+// left b0 in z: pre-smoothing, network input sr (its norm partials in part3),
+// and after the network has added its correction, post-smoothing.
+template <typename T>
+void launch_smooth_pre(mdnp_sys* s, T* z, const InstState* st, double* part3, hipStream_t stream) {
+  const SmoothState& m = s->smooth;
+  T* sb = (T*)m.sb;
+  T* sr = (T*)m.sr;
+  T* t = (T*)m.t;
+  hipLaunchKernelGGL((k_smooth_first<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, sb, s->d_dinv, m.omega,
+                     s->d_off, BLK3(s), st);
+  for (int k = 1; k < m.sweeps; ++k) {
+    launch_a00<T>(s, z, t, st, stream);
+    hipLaunchKernelGGL((k_smooth_sweep<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, (const T*)sb, (const T*)t,
+                       s->d_dinv, m.omega, s->d_off, BLK3(s), st);
+  }
+  launch_a00<T>(s, z, t, st, stream);
+  hipLaunchKernelGGL((k_smooth_res<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, (const T*)sb, (const T*)t, sr,
+                     s->n, s->d_off, BLK3(s), st, part3);
+}
+template void launch_smooth_pre<float>(mdnp_sys*, float*, const InstState*, double*, hipStream_t);
+template void launch_smooth_pre<double>(mdnp_sys*, double*, const InstState*, double*, hipStream_t);
+
+template <typename T>
+void launch_smooth_post(mdnp_sys* s, T* z, const InstState* st, hipStream_t stream) {
+  const SmoothState& m = s->smooth;
+  const T* sb = (const T*)m.sb;
+  T* t = (T*)m.t;
+  for (int k = 0; k < m.sweeps; ++k) {
+    launch_a00<T>(s, z, t, st, stream);
+    hipLaunchKernelGGL((k_smooth_sweep<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, sb, (const T*)t, s->d_dinv,
+                       m.omega, s->d_off, BLK3(s), st);
+  }
+}
+template void launch_smooth_post<float>(mdnp_sys*, float*, const InstState*, hipStream_t);
+template void launch_smooth_post<double>(mdnp_sys*, double*, const InstState*, hipStream_t);
 
 void launch_spmv_a00_slots(mdnp_sys* s, const int32_t* inst, int n_slots, const float* x, float* y,
                            hipStream_t stream) {

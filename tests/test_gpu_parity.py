@@ -202,6 +202,51 @@ def test_neural_block_preconditioner(ctx, vec, cnn_dtype, tol):
         assert err <= tol, (k, err)
 
 
+@pytest.mark.parametrize("vec,cnn_dtype,tol", [("f64", "f32", 2e-5), ("f32", "f32", 2e-5), ("f32", "bf16", 5e-2)])
+@pytest.mark.parametrize("sweeps,omega", [(1, 0.8), (2, 0.6)])
+def test_smoothed_neural_block_preconditioner(ctx, vec, cnn_dtype, tol, sweeps, omega):
+    """Q(v) with the network 3D solve wrapped in Jacobi pre/post-smoothing
+    (Section 5): A00 applications, relaxation steps, network on the remaining
+    residual and its Dirichlet rows, against the oracle's composition."""
+    P = _P()
+    insts = [synth.make_instance(910 + i, 16, n_segments=s, elems_per_segment=3, radius=0.01, beta=1.0)
+             for i, s in enumerate((6, 10))]
+    S = P.System(ctx, insts, vec_dtype=vec)
+    th = _theta(4)
+    S.set_preconditioner("neural", weights=th.astype(np.float32), cnn_dtype=cnn_dtype)
+    S.set_smoothing(sweeps, omega)
+    th64 = th.astype(np.float32).astype(np.float64)
+    net = lambda X: ocnn.forward(th64, X)[0]
+    v = synth.fast_normal(7, S.ntot)
+    td = torch.float64 if vec == "f64" else torch.float32
+    z = S.precond_apply(dev(v, td)).cpu().double().numpy()
+    for k, inst in enumerate(insts):
+        s = fem.assemble(inst)
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        vk = v[o0:o1] if vec == "f64" else v[o0:o1].astype(np.float32).astype(np.float64)
+        p3 = krylov.p3d_smoothed(s, krylov.p3d_neural(s, net), omega, sweeps)
+        ref = krylov.BlockPreconditioner(s, p3)(vk)
+        err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
+        assert err <= tol, (k, err)
+    # switching it off restores the plain preconditioner
+    S.set_smoothing(0)
+    z0 = S.precond_apply(dev(v, td)).cpu().double().numpy()
+    s = fem.assemble(insts[0])
+    vk = v[:S.offsets[1]] if vec == "f64" else v[:S.offsets[1]].astype(np.float32).astype(np.float64)
+    ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(vk)
+    assert np.linalg.norm(z0[:S.offsets[1]] - ref) / np.linalg.norm(ref) <= tol
+    S.free()
+
+
+def test_smoothing_rejects_bad_arguments(ctx):
+    P = _P()
+    S = P.System(ctx, [synth.make_instance(920, 8, n_segments=3, elems_per_segment=3, radius=0.02, beta=1.0)])
+    for sweeps, omega in [(-1, 0.8), (17, 0.8), (1, 0.0), (1, 2.0)]:
+        with pytest.raises(Exception):
+            S.set_smoothing(sweeps, omega)
+    S.free()
+
+
 # ---------------------------------------------------------------- solves (rows a1, a6-a9, a11)
 
 def test_jacobi_gmres_fp64_matches_oracle(ctx):
@@ -391,3 +436,25 @@ def test_neural_precond_bench_config(ctx, bench64):
         ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(v[o0:o1].astype(np.float64))
         err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
         assert err <= 5e-2, (k, err)
+
+
+def test_smoothed_precond_bench_config(ctx, bench64):
+    """The smoothed neural preconditioner (one damped Jacobi step on each side,
+    omega = 0.8) at the benchmark size, instance 0, against the FP64 oracle."""
+    from paper_2505_08491_amd import weights as W
+    S, _, systems = bench64
+    wpath = W.default_path()
+    th = W.load(wpath)[0] if __import__("os").path.exists(wpath + ".bin") else _theta(5).astype(np.float32)
+    S.set_preconditioner("neural", weights=th, cnn_dtype="bf16")
+    S.set_smoothing(1, 0.8)
+    th64 = np.asarray(th, dtype=np.float32).astype(np.float64)
+    net = lambda X: ocnn.forward(th64, X)[0]
+    v = synth.fast_normal(14, S.ntot).astype(np.float32)
+    z = S.precond_apply(dev(v, torch.float32)).cpu().double().numpy()
+    S.set_smoothing(0)
+    s = systems[0]
+    o0, o1 = S.offsets[0], S.offsets[1]
+    p3 = krylov.p3d_smoothed(s, krylov.p3d_neural(s, net), 0.8, 1)
+    ref = krylov.BlockPreconditioner(s, p3)(v[o0:o1].astype(np.float64))
+    err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
+    assert err <= 5e-2, err

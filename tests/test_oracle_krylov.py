@@ -123,3 +123,60 @@ def test_tree_solve_block_is_exact():
     z = Q.solve_1d(v1)
     zd = np.linalg.solve(A11.toarray(), v1)
     assert np.linalg.norm(z - zd) / np.linalg.norm(zd) < 1e-13
+
+
+def _smoothing_case():
+    inst = synth.make_instance(5, 8, n_segments=3, elems_per_segment=3, radius=0.02, beta=1.0)
+    s = fem.assemble(inst)
+    A00 = s.blocks()[0].toarray()
+    b = np.random.default_rng(11).normal(size=s.n3d)
+    return s, A00, b
+
+
+def test_smoothed_exact_inner_solve_stays_exact():
+    """With P3D = A00^-1 the pre-smoothing error is removed exactly by the
+    correction and post-smoothing leaves the exact solution in place."""
+    s, A00, b = _smoothing_case()
+    for omega, sweeps in [(0.8, 1), (0.6, 2), (1.0, 3)]:
+        z = krylov.p3d_smoothed(s, krylov.p3d_exact(s), omega, sweeps)(b)
+        zx = np.linalg.solve(A00, b)
+        assert np.linalg.norm(z - zx) / np.linalg.norm(zx) < 1e-12
+
+
+def test_smoothed_error_propagation():
+    """For a linear inner preconditioner B the smoothed preconditioner P has
+    error propagation I - P A00 = S^k (I - B A00) S^k with the relaxation
+    matrix S = I - omega D^-1 A00 (k sweeps on each side); with B = 0 that is
+    2 k plain relaxation steps from zero."""
+    s, A00, b = _smoothing_case()
+    n = A00.shape[0]
+    I = np.eye(n)
+    Dinv = np.diag(1.0 / np.diag(A00))
+    Bj = Dinv.copy()
+    for omega, k in [(0.8, 1), (0.6, 2)]:
+        S = I - omega * Dinv @ A00
+        Sk = np.linalg.matrix_power(S, k)
+        for B, p3 in [(Bj, krylov.p3d_jacobi(s)), (np.zeros((n, n)), lambda r: np.zeros_like(r))]:
+            E = Sk @ (I - B @ A00) @ Sk
+            expect = (I - E) @ np.linalg.solve(A00, b)
+            z = krylov.p3d_smoothed(s, p3, omega, k)(b)
+            assert np.linalg.norm(z - expect) / np.linalg.norm(expect) < 1e-10
+
+
+def test_smoothing_lowers_neural_iterations():
+    """Jacobi smoothing around the trained network lowers the FGMRES step count
+    on a 16^3 instance (the effect Section 5 reports)."""
+    from paper_2505_08491_amd import weights as W
+    import os
+    if not os.path.exists(W.default_path() + ".bin"):
+        pytest.skip("trained weights not present")
+    theta = W.load(W.default_path())[0].astype(np.float64)
+    inst = synth.make_instance(21, 16, n_segments=12, elems_per_segment=4, radius=0.008, beta=1.0)
+    s = fem.assemble(inst)
+    net = lambda X: cnn.forward(theta, X)[0]
+    plain = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))
+    smooth = krylov.BlockPreconditioner(s, krylov.p3d_smoothed(s, krylov.p3d_neural(s, net), 0.8, 1))
+    r0 = krylov.fgmres(s.A, s.F, precond=plain, restart=30, tol=1e-8, max_iters=300)
+    r1 = krylov.fgmres(s.A, s.F, precond=smooth, restart=30, tol=1e-8, max_iters=300)
+    assert r0.converged and r1.converged
+    assert r1.iters < r0.iters
