@@ -126,7 +126,7 @@ void free_smooth(SmoothState& m) {
 void free_sys(mdnp_sys* s) {
   free_smooth(s->smooth);
   void* ptrs[] = {s->d_off, s->d_stencil, s->d_mptr, s->d_mcol, s->d_mval64, s->d_mval32, s->d_ma01, s->d_mrows, s->d_mlp,
-                  s->d_a01p, s->d_a01c, s->d_a01v64, s->d_a01v32, s->d_dinv, s->d_dist,
+                  s->d_a01p, s->d_a01c, s->d_a01v64, s->d_a01v32, s->d_m3e, s->d_dinv, s->d_dinv32, s->d_dist,
                   s->d_alpha, s->d_t_off, s->d_t_lvloff, s->d_t_lvlptr, s->d_t_lvlnodes, s->d_t_parent,
                   s->d_t_childptr, s->d_t_childidx, s->d_t_lval, s->d_t_dinv};
   for (void* p : ptrs) dfree(p);
@@ -434,6 +434,10 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
     s->d_mval32 = dupload(mv32, stream);
     s->d_ma01 = dupload(ma01, stream);
     s->d_dinv = dupload(dinv, stream);
+    {
+      std::vector<float> dinv32(dinv.begin(), dinv.end());
+      s->d_dinv32 = dupload(dinv32, stream);
+    }
     s->d_dist = dupload(dist, stream);
     s->d_alpha = dupload(alpha, stream);
     // coupling-row lists: 3D rows with M entries, then all 1D rows
@@ -481,6 +485,10 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
         }
       ap[mrows.size()] = (int32_t)ac.size();
       s->d_a01p = dupload(ap, stream);
+      // end of the 3D-column entries of each listed row (its A01 entries come last)
+      std::vector<int32_t> m3e(mrows.size());
+      for (size_t q = 0; q < mrows.size(); ++q) m3e[q] = mp[mrows[q] + 1] - (ap[q + 1] - ap[q]);
+      s->d_m3e = dupload(m3e, stream);
       s->d_a01c = dupload(ac, stream);
       s->d_a01v64 = dupload(av64, stream);
       s->d_a01v32 = dupload(av32, stream);
@@ -783,20 +791,26 @@ void apply_prec(mdnp_sys* s, const T* v, T* z, const InstState* st, bool any_fb,
       break;
     case MDNP_PREC_BLOCK_JACOBI:
     case MDNP_PREC_NEURAL:
+    {
+      const bool smooth = s->kind == MDNP_PREC_NEURAL && s->smooth.sweeps > 0;
       launch_tree_solve<T>(s, v, z, st, 0, stream);
-      launch_extension<T>(s, v, z, P.p3, P.pM3, st, 0, stream);
+      launch_extension<T>(s, v, z, P.p3, P.pM3, st, 0, stream, smooth);
       if (s->kind == MDNP_PREC_BLOCK_JACOBI) {
         launch_block_jacobi3d<T>(s, z, st, 0, stream);
-      } else if (s->smooth.sweeps > 0) {
-        // z0 = S(b0): pre-smoothing, the network on the remaining residual, post-smoothing
+      } else if (smooth) {
+        // z0 = smoothed 3D solve of b0: relaxation from zero (the first step in
+        // the extension), the network on the remaining residual (its correction
+        // replaces that residual in sr), relaxation from the corrected z0
+        T* sr = (T*)s->smooth.sr;
         launch_smooth_pre<T>(s, z, st, P.p3, stream);
         launch_inv_scale(s, P.p3, nullptr, s->cnn.inv_s, const_cast<InstState*>(st), 0, stream);
-        cnn_apply_in_solver<T>(s, (const T*)s->smooth.sr, z, 1, st, stream);
+        cnn_apply_in_solver<T>(s, sr, sr, st, stream);
         launch_smooth_post<T>(s, z, st, stream);
       } else {
         launch_inv_scale(s, P.p3, P.pM3, s->cnn.inv_s, const_cast<InstState*>(st), 0, stream);
-        cnn_apply_in_solver<T>(s, z, z, 0, st, stream);
+        cnn_apply_in_solver<T>(s, z, z, st, stream);
       }
+    }
       break;
   }
   if (any_fb) launch_prec_jacobi<T>(s, v, z, st, 1, stream);

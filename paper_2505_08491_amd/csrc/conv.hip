@@ -136,12 +136,12 @@ __global__ void __launch_bounds__(BS) k_conv_in0(const Tv* __restrict__ z, const
 }
 
 // Last layer inside the solver: 1x1 16 -> 1, then z0 = s / alpha * U on the free
-// nodes, stored (acc = 0) or added to z0 (acc = 1); Dirichlet nodes are left alone.
+// nodes (Dirichlet nodes are left alone).
 template <typename Tv, typename Tin>
 __global__ void __launch_bounds__(BS) k_head_out(const Tin* __restrict__ d0, const float* __restrict__ wt,
                                                  const float* __restrict__ bias, int n, Tv* __restrict__ z,
                                                  const int64_t* off, const double* alpha, double alpha_override,
-                                                 const double* scale, int acc, const InstState* st) {
+                                                 const double* scale, const InstState* st) {
   const int64_t nvox = (int64_t)n * n * n;
   const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
   const int i = blockIdx.z;
@@ -154,8 +154,7 @@ __global__ void __launch_bounds__(BS) k_head_out(const Tin* __restrict__ d0, con
   for (int c = 0; c < 16; ++c) out = fmaf(wt[c], ld(x + c), out);
   const double a = alpha_override > 0.0 ? alpha_override : alpha[i];
   const double s = scale[i];
-  Tv* zp = z + off[i] + v;
-  *zp = (Tv)((s / a) * (double)out + (acc ? (double)*zp : 0.0));
+  z[off[i] + v] = (Tv)((s / a) * (double)out);
 }
 
 // Weight copies: forward [taps][cin][cout]; adjoint [taps][cout][cin] with the
@@ -568,7 +567,7 @@ void cnn_forward_batch(CnnState& c, const float* in, float* out, void* saved, in
 }
 
 template <typename Tv>
-void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, int acc, const InstState* st, hipStream_t stream) {
+void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, const InstState* st, hipStream_t stream) {
   CnnState& c = s->cnn;
   const int n = s->n, batch = s->n_inst;
   if (!ensure_scratch(c, (size_t)cnn_saved_bytes(batch, n, c.dtype))) return;
@@ -583,17 +582,17 @@ void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, int acc, const InstS
     conv_mfma_in0<Tv>(c, zin, s->d_off, c.inv_s, s->d_dist, n, batch, (bf16*)act[1], st, stream);
     unet_middle<bf16>(c, c.w, act, batch, n, c.dtype, st, stream, 8);
     conv_mfma_d0_head<Tv>(c, (const bf16*)act[9], (const bf16*)act[2], n, batch, z, s->d_off, s->d_alpha,
-                          s->alpha_override, c.inv_s + s->n_inst, acc, st, stream);
+                          s->alpha_override, c.inv_s + s->n_inst, st, stream);
   } else {
     hipLaunchKernelGGL((k_conv_in0<Tv, float>), grid, dim3(BS), 0, stream, zin, s->d_off, c.inv_s, s->d_dist,
                        c.wt + c.wt_off[0], c.w + c.b_off[0], n, (float*)act[1], st);
     unet_middle<float>(c, c.w, act, batch, n, c.dtype, st, stream);
     hipLaunchKernelGGL((k_head_out<Tv, float>), grid, dim3(BS), 0, stream, (const float*)act[10],
-                       c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override, c.inv_s + s->n_inst, acc, st);
+                       c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override, c.inv_s + s->n_inst, st);
   }
 }
-template void cnn_apply_in_solver<float>(mdnp_sys*, const float*, float*, int, const InstState*, hipStream_t);
-template void cnn_apply_in_solver<double>(mdnp_sys*, const double*, double*, int, const InstState*, hipStream_t);
+template void cnn_apply_in_solver<float>(mdnp_sys*, const float*, float*, const InstState*, hipStream_t);
+template void cnn_apply_in_solver<double>(mdnp_sys*, const double*, double*, const InstState*, hipStream_t);
 
 // ---------------------------------------------------------------- backward
 

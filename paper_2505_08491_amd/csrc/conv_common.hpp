@@ -47,6 +47,6 @@ void conv_mfma_in0(const CnnState& c, const Tv* z, const int64_t* off, const dou
 template <typename Tv>
 void conv_mfma_d0_head(const CnnState& c, const bf16* u0, const bf16* s0, int n, int batch, Tv* z,
                        const int64_t* off, const double* alpha, double alpha_override, const double* scale,
-                       int acc, const InstState* st, hipStream_t stream);
+                       const InstState* st, hipStream_t stream);
 
 }  // namespace mdnp

@@ -81,7 +81,6 @@ struct MfmaArgs {
   const double* alpha = nullptr;
   double alpha_override = 0.0;
   const double* scale = nullptr;
-  int zacc = 0;                 // add the unscaled head output to z instead of storing it
 };
 
 __device__ __forceinline__ bf16x8 pack2(float x0, float x1) {
@@ -230,7 +229,7 @@ __global__ void __launch_bounds__(WAVES * 64) k_conv_mfma(MfmaArgs p) {
       if (g == 0 && vok[m]) {
         const int ox = (int)(v % n_out), oy = (int)((v / n_out) % n_out), oz = (int)(v / ((int64_t)n_out * n_out));
         const bool bnd = ox == 0 || oy == 0 || oz == 0 || ox == n_out - 1 || oy == n_out - 1 || oz == n_out - 1;
-        if (!bnd) zo[v] = (Tv)((double)(f * (h + p.bh[0])) + (p.zacc ? (double)zo[v] : 0.0));
+        if (!bnd) zo[v] = (Tv)(f * (h + p.bh[0]));
       }
     }
   }
@@ -575,7 +574,7 @@ __global__ void __launch_bounds__(512) k_conv_lds(MfmaArgs p) {
         const int64_t v = vout[m];
         const int ox = (int)(v % n), oy = (int)((v / n) % n), oz = (int)(v / ((int64_t)n * n));
         const bool bnd = ox == 0 || oy == 0 || oz == 0 || ox == n - 1 || oy == n - 1 || oz == n - 1;
-        if (!bnd) zo[v] = (Tv)((double)(f * (h + p.bh[0])) + (p.zacc ? (double)zo[v] : 0.0));
+        if (!bnd) zo[v] = (Tv)(f * (h + p.bh[0]));
       }
     }
   }
@@ -847,10 +846,7 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
         const int y = y0 + m;
         // Dirichlet nodes keep the value set before the network runs
         if (g == 0 && y < q.yhi && y > 0 && y < n - 1 && xl > 0 && z > 0 && z < n - 1)
-        {
-          Tv* zp = zo + ((int64_t)z * n + y) * n + xl;
-          *zp = (Tv)((double)(f * (h + p.bh[0])) + (p.zacc ? (double)*zp : 0.0));
-        }
+          zo[((int64_t)z * n + y) * n + xl] = (Tv)(f * (h + p.bh[0]));
       }
     }
     if (!IN) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -1009,7 +1005,6 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
   bf16* Y = EPI ? nullptr : p.y + (int64_t)bt * nv * 16;
   Tv* zo = EPI ? (Tv*)p.zout + p.off[bt] : nullptr;
   const int relu = p.relu;
-  const int zacc = p.zacc;
   dma_plane(z0 - 1, 0);
   dma_plane(z0, 1);
   dma_plane(z0 + 1, 2);
@@ -1104,10 +1099,7 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
           const int y = y0 + rb0 + m;
           // Dirichlet nodes keep the value set before the network runs
           if (g == 0 && y < q.yhi && y > 0 && y < n - 1 && xl > 0 && z > 0 && z < n - 1)
-          {
-            Tv* zp = zo + ((int64_t)z * n + y) * n + xl;
-            *zp = (Tv)((double)(fsc * (h + bhv)) + (zacc ? (double)*zp : 0.0));
-          }
+            zo[((int64_t)z * n + y) * n + xl] = (Tv)(fsc * (h + bhv));
         }
       }
     }
@@ -1760,7 +1752,7 @@ template void conv_mfma_in0<double>(const CnnState&, const double*, const int64_
 template <typename Tv>
 void conv_mfma_d0_head(const CnnState& c, const bf16* u0, const bf16* s0, int n, int batch, Tv* z,
                        const int64_t* off, const double* alpha, double alpha_override, const double* scale,
-                       int acc, const InstState* st, hipStream_t stream) {
+                       const InstState* st, hipStream_t stream) {
   constexpr int MB = 4;
   const int64_t nvo = (int64_t)n * n * n;
   const int64_t nmb = (nvo + 15) / 16;
@@ -1782,15 +1774,14 @@ void conv_mfma_d0_head(const CnnState& c, const bf16* u0, const bf16* s0, int n,
   a.alpha = alpha;
   a.alpha_override = alpha_override;
   a.scale = scale;
-  a.zacc = acc;
   (void)nmb;
   launch_ks16<16, 16, 4, 1, 1, Tv>(a, batch, stream, kSweepBlocksD0);
 }
 template void conv_mfma_d0_head<float>(const CnnState&, const bf16*, const bf16*, int, int, float*, const int64_t*,
-                                       const double*, double, const double*, int, const InstState*, hipStream_t);
+                                       const double*, double, const double*, const InstState*, hipStream_t);
 template void conv_mfma_d0_head<double>(const CnnState&, const bf16*, const bf16*, int, int, double*,
-                                        const int64_t*, const double*, double, const double*, int,
-                                        const InstState*, hipStream_t);
+                                        const int64_t*, const double*, double, const double*, const InstState*,
+                                        hipStream_t);
 
 // Layers L0b .. D0 (indices 1 .. 9) with their fixed channel counts.
 void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c, hipStream_t stream) {

@@ -134,7 +134,9 @@ struct mdnp_sys {
   int32_t* d_a01c = nullptr;       // A01 global column indices (1D nodes)
   double* d_a01v64 = nullptr;
   float* d_a01v32 = nullptr;
+  int32_t* d_m3e = nullptr;        // [rows listed] end of each listed row's 3D-column M entries
   double* d_dinv = nullptr;        // [ntot] 1 / diag(A)
+  float* d_dinv32 = nullptr;       // the same in FP32 (relaxation steps of the smoothing)
   float* d_dist = nullptr;         // [n_inst * n3d]
   double* d_alpha = nullptr;       // [n_inst]
   // tree factorisation

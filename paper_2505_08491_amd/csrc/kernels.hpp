@@ -48,14 +48,14 @@ void launch_tree_solve(mdnp_sys* s, const T* v, T* z, const InstState* st, int w
                        hipStream_t stream);
 template <typename T>
 void launch_extension(mdnp_sys* s, const T* v, T* z, double* part3, double* part3m, const InstState* st,
-                      int want_mode, hipStream_t stream);
+                      int want_mode, hipStream_t stream, bool smooth_first = false);
 template <typename T>
 void launch_block_jacobi3d(mdnp_sys* s, T* z, const InstState* st, int want_mode, hipStream_t stream);
 void launch_inv_scale(mdnp_sys* s, const double* part3, const double* part3m, double* inv_s, InstState* st,
                       int want_mode, hipStream_t stream);
 // Jacobi smoothing around the network (part3m of launch_inv_scale may be null)
 template <typename T>
-void launch_a00(mdnp_sys* s, const T* x, T* y, const InstState* st, hipStream_t stream);
+void launch_a00(mdnp_sys* s, const T* x, T* y, const InstState* st, hipStream_t stream, const T* x2 = nullptr);
 template <typename T>
 void launch_smooth_pre(mdnp_sys* s, T* z, const InstState* st, double* part3, hipStream_t stream);
 template <typename T>
@@ -94,10 +94,10 @@ bool cnn_reserve(CnnState& c, int batch, int n, mdnp_dtype dtype);
 void cnn_backward_batch(CnnState& c, const void* saved, const float* dy, float* dx, float* dw,
                         int batch, int n, mdnp_dtype dtype, hipStream_t stream);
 // In-solver application on the 3D parts of the vectors (type T): reads
-// zin0 * inv_s and the distance field, then stores (acc = 0) or adds (acc = 1)
-// z0 = s / alpha * U on the free nodes of z.
+// zin0 * inv_s and the distance field, writes z0 = s / alpha * U on the free
+// nodes of z (zin and z may be the same vector).
 template <typename T>
-void cnn_apply_in_solver(mdnp_sys* s, const T* zin, T* z, int acc, const InstState* st, hipStream_t stream);
+void cnn_apply_in_solver(mdnp_sys* s, const T* zin, T* z, const InstState* st, hipStream_t stream);
 void cnn_release(CnnState& c);
 void launch_loss_grad(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u,
                       float* du, double* loss, hipStream_t stream);

@@ -7,6 +7,7 @@
 // fixed order, so results are bitwise reproducible run to run.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -163,11 +164,11 @@ __device__ __forceinline__ Tacc stencil_row(const Tv* __restrict__ x, int64_t ba
 constexpr int SW_TY = 4;          // output rows per block
 constexpr int SW_NX = 2;          // x positions per thread: n <= 128
 
-template <typename Tv, typename Tacc>
+template <typename Tv, typename Tacc, int SUM = 0>
 __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict__ stencil, const Tv* __restrict__ x,
                                                        Tv* __restrict__ y, const int64_t* __restrict__ off, int n,
                                                        int ytiles, int zc, int n_inst, const InstState* st,
-                                                       int mask) {
+                                                       int mask, const Tv* __restrict__ x2 = nullptr) {
   __shared__ Tacc pl[2][SW_TY + 2][130];
   const int nz = (n + zc - 1) / zc;
   const int lb = xcd_logical_block(n_inst * ytiles * nz);
@@ -179,6 +180,7 @@ __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict_
   const int zend = min(n, z0 + zc);
   const int64_t nn = (int64_t)n * n;
   const Tv* X = x + off[i];
+  const Tv* X2 = SUM ? x2 + off[i] : nullptr;  // SUM = 1: S (x + x2)
   Tv* Y = y + off[i];
   const Tacc w0 = (Tacc)stencil[4 * i], w1 = (Tacc)stencil[4 * i + 1], w2 = (Tacc)stencil[4 * i + 2],
              w3 = (Tacc)stencil[4 * i + 3];
@@ -194,7 +196,10 @@ __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict_
       Tacc a = 0;
       if (q < items && zp > 0 && zp < n - 1) {
         const int r = q / n, xx = q - r * n, gy = y0 + r - 1;
-        if (gy > 0 && gy < n - 1 && xx > 0 && xx < n - 1) a = (Tacc)X[zp * nn + (int64_t)gy * n + xx];
+        if (gy > 0 && gy < n - 1 && xx > 0 && xx < n - 1) {
+          const int64_t vq = zp * nn + (int64_t)gy * n + xx;
+          a = SUM ? (Tacc)X[vq] + (Tacc)X2[vq] : (Tacc)X[vq];
+        }
       }
       v[k] = a;
     }
@@ -243,7 +248,8 @@ __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict_
       if (zo >= z0 && gyo < n) {
         const int64_t v_ = zo * nn + (int64_t)gyo * n + xx;
         const bool bnd = zo == 0 || zo == n - 1 || gyo == 0 || gyo == n - 1 || xx == 0 || xx == n - 1;
-        Y[v_] = bnd ? X[v_] : (Tv)(accp[k] + up);
+        if (bnd) Y[v_] = SUM ? (Tv)((Tacc)X[v_] + (Tacc)X2[v_]) : X[v_];
+        else Y[v_] = (Tv)(accp[k] + up);
       }
       accp[k] = accc[k] + mid;  // output plane zp: planes zp - 1 and zp so far
       accc[k] = up;             // output plane zp + 1: plane zp so far
@@ -293,14 +299,16 @@ __global__ void __launch_bounds__(BS) k_stencil(const double* __restrict__ stenc
 // G lanes per row: y[row] += (M x)[row] (RES = 0), the same with the 1D rows
 // overwritten instead (RES = 2: y holds only the 3D stencil part),
 // r[row] -= (M x)[row] with partial sums of r^2 (RES = 1), or, over the 3D
-// rows only, y[row] += (M00 x)[row] leaving out the A01 entries (RES = 3).
+// rows only, y[row] += (M00 x)[row] leaving out the A01 entries (RES = 3;
+// with x2, M00 (x + x2)).
 template <typename Tv, typename Tm, typename Tacc, int G, int RES>
 __global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows, const int32_t* __restrict__ mlp,
                                               const int32_t* __restrict__ mcol, const Tm* __restrict__ mval,
                                               const Tv* __restrict__ x, Tv* __restrict__ y, const int32_t* binst,
                                               const int64_t* bstart, const int64_t* bend, const InstState* st,
                                               int mask, double* part, int nblk, const int64_t* off = nullptr, int n3d = 0,
-                                              const int32_t* __restrict__ ap = nullptr) {
+                                              const int32_t* __restrict__ ap = nullptr,
+                                              const Tv* __restrict__ x2 = nullptr) {
   __shared__ double sh[BS / 64];
   const int b = xcd_logical_block(nblk);
   if (b < 0) return;
@@ -315,8 +323,8 @@ __global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows,
   for (int64_t q = bstart[b] + grp; q < bend[b]; q += ng) {
     const int row = mrows[q];
     Tacc acc = 0;
-    // RES = 3 (A00 only): the row's A01 entries, its last ones, are left out
-    const int e = RES == 3 ? mlp[q + 1] - (ap[q + 1] - ap[q]) : mlp[q + 1];
+    // RES = 3 (A00 only): the row's entries end before its A01 entries (ap)
+    const int e = RES == 3 ? ap[q] : mlp[q + 1];
     // U entries per lane per pass, all loads of a pass in flight together
     // (indices clamped into the row: every listed row has entries)
     constexpr int U = 32 / G;
@@ -329,9 +337,13 @@ __global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows,
         cidx[u] = mcol[k];
         mv[u] = mval[k];
       }
-      Tv xv[U];
+      Tacc xv[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) xv[u] = x[cidx[u]];
+      for (int u = 0; u < U; ++u) xv[u] = (Tacc)x[cidx[u]];
+      if (RES == 3 && x2) {  // M00 (x + x2)
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] += (Tacc)x2[cidx[u]];
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (k0 + u * G < e) acc += (Tacc)mv[u] * (Tacc)xv[u];
@@ -703,7 +715,7 @@ __global__ void __launch_bounds__(64) k_chain_back(const T* __restrict__ v, T* _
 }
 
 // Extension b0 = v0 - A01 z1 (z1 already in z), one launch with two kinds of
-// blocks.  Blocks [0, ncopy) take chunks of 3D rows: the rows without
+// blocks (with sb: the first smoothing step, b0 into sb and z = omega D^-1 b0).  Blocks [0, ncopy) take chunks of 3D rows: the rows without
 // coupling copy v0 and add to the partial sums of b0^2 (part3).  The other
 // blocks take chunks of coupling rows, G lanes per row: b0 = v0 - A01 z1 with
 // A01 in a compact CSR of its own, partial sums in part3m.  Each 3D row is
@@ -715,7 +727,8 @@ __global__ void __launch_bounds__(BS) k_ext(const T* __restrict__ v, T* __restri
                                             const int32_t* __restrict__ mrows, const int32_t* __restrict__ ap,
                                             const int32_t* __restrict__ ac, const Tm* __restrict__ av,
                                             const int32_t* rinst, const int64_t* rstart, const int64_t* rend,
-                                            const InstState* st, int want_mode, double* part3, double* part3m) {
+                                            const InstState* st, int want_mode, double* part3, double* part3m,
+                                            T* __restrict__ sb, const float* __restrict__ dinv, double omega) {
   __shared__ double sh[BS / 64];
   double loc = 0.0;
   if ((int)blockIdx.x < ncopy) {
@@ -742,7 +755,12 @@ __global__ void __launch_bounds__(BS) k_ext(const T* __restrict__ v, T* __restri
         const int64_t r = r0 + (int64_t)u * BS;
         if (r >= r1) break;
         if (free_row[u]) {
-          z[base + r] = vl[u];
+          if (sb) {  // first smoothing step from zero
+            sb[base + r] = vl[u];
+            z[base + r] = from_d<T>(omega * (double)dinv[base + r] * to_d(vl[u]));
+          } else {
+            z[base + r] = vl[u];
+          }
           loc += to_d(vl[u]) * to_d(vl[u]);
         }
       }
@@ -784,7 +802,12 @@ __global__ void __launch_bounds__(BS) k_ext(const T* __restrict__ v, T* __restri
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
     if (lane == 0) {
       const T stored = from_d<T>(to_d(vr) - acc);
-      z[row] = stored;
+      if (sb) {
+        sb[row] = stored;
+        z[row] = from_d<T>(omega * (double)dinv[row] * to_d(stored));
+      } else {
+        z[row] = stored;
+      }
       loc += to_d(stored) * to_d(stored);
     }
   }
@@ -822,51 +845,67 @@ __global__ void k_inv_scale(const double* part3, const int32_t* first, const dou
 // ---------------------------------------------------------------- Jacobi smoothing of the 3D solve
 // Damped Jacobi relaxation z <- z + omega D^-1 (b0 - A00 z) around the network
 // (Section 5, pre- and post-smoothing), over the 3D rows of the instances on
-// the configured preconditioner.  D = diag(A00) (unit on Dirichlet rows).
+// the configured preconditioner.  D = diag(A00) (unit on Dirichlet rows).  The
+// first step from z = 0 (z = omega D^-1 b0, b0 kept in sb) is taken by the
+// extension kernel.
 
-// First relaxation step from z = 0: keeps b0 (from the extension, in z) in sb
-// and sets z = omega D^-1 b0.
+// z += x over the 3D rows.
 template <typename T>
-__global__ void __launch_bounds__(BS) k_smooth_first(T* __restrict__ z, T* __restrict__ sb,
-                                                     const double* __restrict__ dinv, double omega, const int64_t* off,
+__global__ void __launch_bounds__(BS) k_vec_add3d(T* __restrict__ z, const T* __restrict__ x, const int64_t* off,
+                                                  const int32_t* binst, const int64_t* bstart, const int64_t* bend,
+                                                  const InstState* st) {
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (st && !mode_ok(st[i], 0)) return;
+  const int64_t base = off[i];
+  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += BS)
+    z[base + r] = from_d<T>(to_d(z[base + r]) + to_d(x[base + r]));
+}
+
+// One relaxation step z <- (z + x2) + omega D^-1 (sb - t) with t = A00 (z + x2)
+// (x2 = the network's correction, or null).
+template <typename T>
+__global__ void __launch_bounds__(BS) k_smooth_sweep(T* __restrict__ z, const T* __restrict__ x2,
+                                                     const T* __restrict__ sb, const T* __restrict__ t,
+                                                     const float* __restrict__ dinv, double omega, const int64_t* off,
                                                      const int32_t* binst, const int64_t* bstart, const int64_t* bend,
                                                      const InstState* st) {
   const int b = blockIdx.x;
   const int i = binst[b];
   if (st && !mode_ok(st[i], 0)) return;
   const int64_t base = off[i];
-  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += BS) {
-    const int64_t g = base + r;
-    const T b0 = z[g];
-    sb[g] = b0;
-    z[g] = from_d<T>(omega * dinv[g] * to_d(b0));
-  }
-}
-
-// One relaxation step z += omega D^-1 (sb - t), t = A00 z.
-template <typename T>
-__global__ void __launch_bounds__(BS) k_smooth_sweep(T* __restrict__ z, const T* __restrict__ sb,
-                                                     const T* __restrict__ t, const double* __restrict__ dinv,
-                                                     double omega, const int64_t* off, const int32_t* binst,
-                                                     const int64_t* bstart, const int64_t* bend, const InstState* st) {
-  const int b = blockIdx.x;
-  const int i = binst[b];
-  if (st && !mode_ok(st[i], 0)) return;
-  const int64_t base = off[i];
-  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += BS) {
-    const int64_t g = base + r;
-    z[g] = from_d<T>(to_d(z[g]) + omega * dinv[g] * (to_d(sb[g]) - to_d(t[g])));
+  constexpr int U = 4;
+  const int64_t r1 = bend[b];
+  for (int64_t r0 = bstart[b] + threadIdx.x; r0 < r1; r0 += (int64_t)U * BS) {
+    T zl[U], xl[U], bl[U], tl[U];
+    float dl[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t g = base + min(r0 + (int64_t)u * BS, r1 - 1);
+      zl[u] = z[g];
+      xl[u] = x2 ? x2[g] : (T)0;
+      bl[u] = sb[g];
+      tl[u] = t[g];
+      dl[u] = dinv[g];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + (int64_t)u * BS;
+      if (r >= r1) break;
+      z[base + r] = from_d<T>(to_d(zl[u]) + to_d(xl[u]) + omega * (double)dl[u] * (to_d(bl[u]) - to_d(tl[u])));
+    }
   }
 }
 
 // Residual of the pre-smoothed z: sr = sb - t (t = A00 z), the network input,
-// with per-block partial sums of sr^2 for its normalisation.  On the Dirichlet
-// rows the 3D solver returns its input, so sr is added to z there.
+// with per-block partial sums of sr^2 for its normalisation.  The network
+// overwrites sr on the free nodes with its correction; on the Dirichlet rows
+// the 3D solver returns its input, so sr is already the correction there.
 template <typename T>
-__global__ void __launch_bounds__(BS) k_smooth_res(T* __restrict__ z, const T* __restrict__ sb,
-                                                   const T* __restrict__ t, T* __restrict__ sr, int n,
-                                                   const int64_t* off, const int32_t* binst, const int64_t* bstart,
-                                                   const int64_t* bend, const InstState* st, double* part) {
+__global__ void __launch_bounds__(BS) k_smooth_res(const T* __restrict__ sb, const T* __restrict__ t,
+                                                   T* __restrict__ sr, const int64_t* off, const int32_t* binst,
+                                                   const int64_t* bstart, const int64_t* bend, const InstState* st,
+                                                   double* part) {
   __shared__ double sh[BS / 64];
   const int b = blockIdx.x;
   const int i = binst[b];
@@ -876,12 +915,24 @@ __global__ void __launch_bounds__(BS) k_smooth_res(T* __restrict__ z, const T* _
   }
   const int64_t base = off[i];
   double loc = 0.0;
-  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += BS) {
-    const int64_t g = base + r;
-    const T rv = from_d<T>(to_d(sb[g]) - to_d(t[g]));
-    sr[g] = rv;
-    loc += to_d(rv) * to_d(rv);
-    if (is_boundary((int)r, n)) z[g] = from_d<T>(to_d(z[g]) + to_d(rv));
+  constexpr int U = 4;
+  const int64_t r1 = bend[b];
+  for (int64_t r0 = bstart[b] + threadIdx.x; r0 < r1; r0 += (int64_t)U * BS) {
+    T bl[U], tl[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t g = base + min(r0 + (int64_t)u * BS, r1 - 1);
+      bl[u] = sb[g];
+      tl[u] = t[g];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + (int64_t)u * BS;
+      if (r >= r1) break;
+      const T rv = from_d<T>(to_d(bl[u]) - to_d(tl[u]));
+      sr[base + r] = rv;
+      loc += to_d(rv) * to_d(rv);
+    }
   }
   const double tt = block_sum(loc, sh);
   if (threadIdx.x == 0) part[b] = tt;
@@ -1261,13 +1312,13 @@ void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, 
 template void launch_spmv<float>(mdnp_sys*, const float*, float*, const InstState*, bool, hipStream_t);
 template void launch_spmv<double>(mdnp_sys*, const double*, double*, const InstState*, bool, hipStream_t);
 
-// y = A00 x on the 3D rows of the instances on the configured preconditioner
-// (x, y full-length vectors): the stencil sweep, then the 3D coupling rows
-// without their A01 entries.
+// y = A00 x (or A00 (x + x2)) on the 3D rows of the instances on the configured
+// preconditioner (full-length vectors): the stencil sweep, then the 3D coupling
+// rows without their A01 entries.  x2 only where the sweep applies (n <= 128).
 template <typename T>
-void launch_a00(mdnp_sys* s, const T* x, T* y, const InstState* st, hipStream_t stream) {
+void launch_a00(mdnp_sys* s, const T* x, T* y, const InstState* st, hipStream_t stream, const T* x2) {
   const int n = s->n;
-  if (n > 64 * SW_NX) {  // one thread per row (no masking: y is scratch)
+  if (n > 64 * SW_NX) {  // one thread per row (no masking: y is scratch); x2 not taken here
     launch_spmv_a00_all<T>(s, x, y, stream);
     return;
   }
@@ -1278,56 +1329,63 @@ void launch_a00(mdnp_sys* s, const T* x, T* y, const InstState* st, hipStream_t 
   const int zc = (n + nz - 1) / nz;
   nz = (n + zc - 1) / zc;
   const dim3 grid(xcd_grid(ytiles * nz * s->n_inst));
-  if (sizeof(T) == 8) {
-    hipLaunchKernelGGL((k_stencil_sweep<T, double>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, s->n_inst, st, mk);
-    hipLaunchKernelGGL((k_mrows<T, double, double, 4, 3>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream,
-                       s->d_mrows, s->d_mlp, s->d_mcol, s->d_mval64, x, y, MBLK3(s), st, mk, (double*)nullptr,
-                       s->mblk3.nblk, s->d_off, s->n3d, s->d_a01p);
-  } else {
-    hipLaunchKernelGGL((k_stencil_sweep<T, float>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, s->n_inst, st, mk);
-    hipLaunchKernelGGL((k_mrows<T, float, float, 4, 3>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream,
-                       s->d_mrows, s->d_mlp, s->d_mcol, s->d_mval32, x, y, MBLK3(s), st, mk, (double*)nullptr,
-                       s->mblk3.nblk, s->d_off, s->n3d, s->d_a01p);
-  }
+  typedef typename std::conditional<sizeof(T) == 8, double, float>::type Tm;
+  const Tm* mv = sizeof(T) == 8 ? (const Tm*)s->d_mval64 : (const Tm*)s->d_mval32;
+  if (x2)
+    hipLaunchKernelGGL((k_stencil_sweep<T, Tm, 1>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
+                       ytiles, zc, s->n_inst, st, mk, x2);
+  else
+    hipLaunchKernelGGL((k_stencil_sweep<T, Tm>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
+                       ytiles, zc, s->n_inst, st, mk, (const T*)nullptr);
+  hipLaunchKernelGGL((k_mrows<T, Tm, Tm, 4, 3>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream, s->d_mrows,
+                     s->d_mlp, s->d_mcol, mv, x, y, MBLK3(s), st, mk, (double*)nullptr, s->mblk3.nblk, s->d_off,
+                     s->n3d, s->d_m3e, x2);
 }
 
-template void launch_a00<float>(mdnp_sys*, const float*, float*, const InstState*, hipStream_t);
-template void launch_a00<double>(mdnp_sys*, const double*, double*, const InstState*, hipStream_t);
+template void launch_a00<float>(mdnp_sys*, const float*, float*, const InstState*, hipStream_t, const float*);
+template void launch_a00<double>(mdnp_sys*, const double*, double*, const InstState*, hipStream_t, const double*);
 
-// The smoothed 3D solve of the neural preconditioner, after the extension has
-// left b0 in z: pre-smoothing, network input sr (its norm partials in part3),
-// and after the network has added its correction, post-smoothing.
+// The smoothed 3D solve of the neural preconditioner.  After the extension
+// (which took the first relaxation step): the remaining pre-smoothing steps,
+// then the network input sr = b0 - A00 z (its norm partials in part3).
 template <typename T>
 void launch_smooth_pre(mdnp_sys* s, T* z, const InstState* st, double* part3, hipStream_t stream) {
   const SmoothState& m = s->smooth;
-  T* sb = (T*)m.sb;
+  const T* sb = (const T*)m.sb;
   T* sr = (T*)m.sr;
   T* t = (T*)m.t;
-  hipLaunchKernelGGL((k_smooth_first<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, sb, s->d_dinv, m.omega,
-                     s->d_off, BLK3(s), st);
   for (int k = 1; k < m.sweeps; ++k) {
     launch_a00<T>(s, z, t, st, stream);
-    hipLaunchKernelGGL((k_smooth_sweep<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, (const T*)sb, (const T*)t,
-                       s->d_dinv, m.omega, s->d_off, BLK3(s), st);
+    hipLaunchKernelGGL((k_smooth_sweep<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, (const T*)nullptr, sb,
+                       (const T*)t, s->d_dinv32, m.omega, s->d_off, BLK3(s), st);
   }
   launch_a00<T>(s, z, t, st, stream);
-  hipLaunchKernelGGL((k_smooth_res<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, (const T*)sb, (const T*)t, sr,
-                     s->n, s->d_off, BLK3(s), st, part3);
+  hipLaunchKernelGGL((k_smooth_res<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, sb, (const T*)t, sr, s->d_off,
+                     BLK3(s), st, part3);
 }
 template void launch_smooth_pre<float>(mdnp_sys*, float*, const InstState*, double*, hipStream_t);
 template void launch_smooth_pre<double>(mdnp_sys*, double*, const InstState*, double*, hipStream_t);
 
+// After the network has left its correction in sr: z += sr folded into the
+// first post-smoothing step (t = A00 (z + sr), z = z + sr + omega D^-1 (b0 - t)),
+// then the remaining steps.
 template <typename T>
 void launch_smooth_post(mdnp_sys* s, T* z, const InstState* st, hipStream_t stream) {
   const SmoothState& m = s->smooth;
   const T* sb = (const T*)m.sb;
+  const T* sr = (const T*)m.sr;
   T* t = (T*)m.t;
-  for (int k = 0; k < m.sweeps; ++k) {
+  if (s->n > 64 * SW_NX) {  // without the sweep: z += sr first
+    hipLaunchKernelGGL((k_vec_add3d<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, sr, s->d_off, BLK3(s), st);
+    sr = nullptr;
+  }
+  launch_a00<T>(s, z, t, st, stream, sr);
+  hipLaunchKernelGGL((k_smooth_sweep<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, sr, sb, (const T*)t,
+                     s->d_dinv32, m.omega, s->d_off, BLK3(s), st);
+  for (int k = 1; k < m.sweeps; ++k) {
     launch_a00<T>(s, z, t, st, stream);
-    hipLaunchKernelGGL((k_smooth_sweep<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, sb, (const T*)t, s->d_dinv,
-                       m.omega, s->d_off, BLK3(s), st);
+    hipLaunchKernelGGL((k_smooth_sweep<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, (const T*)nullptr, sb,
+                       (const T*)t, s->d_dinv32, m.omega, s->d_off, BLK3(s), st);
   }
 }
 template void launch_smooth_post<float>(mdnp_sys*, float*, const InstState*, hipStream_t);
@@ -1445,21 +1503,23 @@ template void launch_tree_solve<double>(mdnp_sys*, const double*, double*, const
 
 template <typename T>
 void launch_extension(mdnp_sys* s, const T* v, T* z, double* part3, double* part3m, const InstState* st,
-                      int want_mode, hipStream_t stream) {
+                      int want_mode, hipStream_t stream, bool smooth_first) {
   const int nb = s->blk3.nblk + s->mblk3.nblk;
+  T* sb = smooth_first ? (T*)s->smooth.sb : nullptr;
+  const double om = s->smooth.omega;
   if (sizeof(T) == 8)
     hipLaunchKernelGGL((k_ext<T, double, 4>), dim3(nb), dim3(BS), 0, stream, v, z, s->d_mptr, s->d_off, BLK3(s),
                        s->blk3.nblk, s->d_mrows, s->d_a01p, s->d_a01c, s->d_a01v64, MBLK3(s), st, want_mode, part3,
-                       part3m);
+                       part3m, sb, s->d_dinv32, om);
   else
     hipLaunchKernelGGL((k_ext<T, float, 4>), dim3(nb), dim3(BS), 0, stream, v, z, s->d_mptr, s->d_off, BLK3(s),
                        s->blk3.nblk, s->d_mrows, s->d_a01p, s->d_a01c, s->d_a01v32, MBLK3(s), st, want_mode, part3,
-                       part3m);
+                       part3m, sb, s->d_dinv32, om);
 }
 template void launch_extension<float>(mdnp_sys*, const float*, float*, double*, double*, const InstState*, int,
-                                      hipStream_t);
+                                      hipStream_t, bool);
 template void launch_extension<double>(mdnp_sys*, const double*, double*, double*, double*, const InstState*, int,
-                                       hipStream_t);
+                                       hipStream_t, bool);
 
 template <typename T>
 void launch_block_jacobi3d(mdnp_sys* s, T* z, const InstState* st, int want_mode, hipStream_t stream) {
