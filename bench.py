@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--smooth-sweeps", type=int, default=1,
                     help="Jacobi pre/post-smoothing steps of the extra smoothed solve (0: skip it)")
     ap.add_argument("--smooth-omega", type=float, default=0.8)
+    ap.add_argument("--inner-steps", type=int, default=3,
+                    help="inner FGMRES steps of the extra inner-solve run (0: skip it)")
     ap.add_argument("--cpu-neural-iters", type=int, default=3)
     ap.add_argument("--cpu-jacobi-iters", type=int, default=50)
     return ap.parse_args()
@@ -244,6 +246,21 @@ def main():
                     "used_fallback": int(sum(q["used_fallback"] for q in sts)), "max_true_rel_res": max(rel_s),
                     "ms_per_apply": ms_prec_s}
 
+    # the 3D block solved by inner FGMRES steps with the network as preconditioner
+    inner = None
+    if a.inner_steps > 0:
+        S.set_preconditioner("neural", weights=w, cnn_dtype=a.cnn_dtype)
+        S.set_inner_steps(a.inner_steps)
+        Ti, sti = run(neural_opts, a.steps, 1)
+        rel_i = true_rel()
+        ms_prec_i = time_kernel(ctx, lambda: S.precond_apply(xs), 5)
+        S.set_inner_steps(0)
+        inner = {"steps": a.inner_steps, "solves_per_s": S.n_inst * a.steps / Ti, "ms_per_solve": Ti / a.steps * 1e3,
+                 "iters_mean": float(np.mean([q["iters"] + q["fallback_iters"] for q in sti])),
+                 "converged_all": all(q["converged"] for q in sti),
+                 "used_fallback": int(sum(q["used_fallback"] for q in sti)), "max_true_rel_res": max(rel_i),
+                 "ms_per_apply": ms_prec_i}
+
     jac = None
     if not a.skip_jacobi:
         S.set_preconditioner("jacobi")
@@ -267,6 +284,7 @@ def main():
         "neural": {"iters_mean": float(np.mean(neural_iters)), "iters_max": int(max(neural_iters)),
                    "converged_all": conv_all, "used_fallback": int(n_fb), "max_true_rel_res": max(rel_n)},
         "neural_smoothed": smoothed,
+        "neural_inner_fgmres": inner,
         "jacobi": jac,
         "roofline": {"bound": "hbm", "kernel": "k_stencil_sweep + k_mrows (batched y = (S + M) x, FP32)",
                      "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,

@@ -168,8 +168,19 @@ mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* sys, mdnp_prec_kind
  * D = diag(A00).  sweeps = 0 switches it off (the default).  Takes effect on
  * the next solve or preconditioner application; allocates three vectors of
  * the system's length and type, freed with the system or by sweeps = 0.
- * Errors: MDNP_E_ARG (sweeps outside [0, 16], omega outside (0, 2)). */
+ * Errors: MDNP_E_ARG (sweeps outside [0, 16], omega outside (0, 2)),
+ * MDNP_E_STATE (inner FGMRES steps are on). */
 mdnp_status mdnp_set_smoothing(mdnp_ctx* ctx, mdnp_sys* sys, int32_t sweeps, double omega);
+
+/* Inner Krylov 3D solve (Section 6): with steps > 0 the MDNP_PREC_NEURAL
+ * preconditioner computes its 3D part z0 by `steps` FGMRES steps on
+ * A00 z0 = b0 from z0 = 0, right-preconditioned by the network (Arnoldi by
+ * modified Gram-Schmidt in FP64 dot products, stopped early on breakdown), in
+ * place of one network application.  steps = 0 switches it off (the
+ * default).  Allocates 2 steps + 1 vectors of the system's length and type,
+ * freed with the system or by steps = 0.  Errors: MDNP_E_ARG (steps outside
+ * [0, 8]), MDNP_E_STATE (smoothing is on). */
+mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* sys, int32_t steps);
 
 /* ---------------------------------------------------------------- solve */
 

@@ -13,7 +13,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   correction b0 - A01 z1 handed to a 3D solver P3D (eq. "decoupled_3d_problem").
 * P3D choices: Jacobi (diag(A00)^-1), exact (A00^-1, pins only) and the
   neural operator (module `cnn`), optionally wrapped in damped-Jacobi pre-
-  and post-smoothing (Section 5, "Effect of pre- and post-smoothing").
+  and post-smoothing (Section 5, "Effect of pre- and post-smoothing") or
+  used as the preconditioner of a few inner FGMRES steps on A00 (Section 6).
 """
 from __future__ import annotations
 
@@ -214,6 +215,19 @@ def p3d_smoothed(system, p3d, omega, sweeps):
         z = jacobi_sweeps(A00, b, np.zeros_like(b), omega, sweeps)
         z = z + p3d(b - A00 @ z)
         return jacobi_sweeps(A00, b, z, omega, sweeps)
+    return apply
+
+
+def p3d_inner_fgmres(system, p3d, steps):
+    """The 3D solve of Section 6: `steps` FGMRES steps on A00 z = b from z = 0,
+    right-preconditioned by P3D (the paper's P-FGMRES with the network as P).
+    A zero b maps to zero."""
+    A00 = system.blocks()[0].tocsr()
+
+    def apply(b):
+        if not np.any(b):
+            return np.zeros_like(b)
+        return fgmres(A00, b, precond=p3d, restart=steps, tol=0.0, max_iters=steps).x
     return apply
 
 

@@ -241,6 +241,10 @@ class System:
                                                     w.ctypes.data if w is not None else None, n, alpha,
                                                     DTYPE[cnn_dtype]))
 
+    def set_inner_steps(self, steps: int):
+        """Inner FGMRES(steps) 3D solve with the network as preconditioner (0: off)."""
+        self.ctx._check(lib.mdnp_set_inner_steps(self.ctx.h, self.h, int(steps)))
+
     def set_smoothing(self, sweeps: int, omega: float = 0.8):
         """Jacobi pre/post-smoothing of the neural 3D solve (0 sweeps: off)."""
         self.ctx._check(lib.mdnp_set_smoothing(self.ctx.h, self.h, int(sweeps), float(omega)))

@@ -123,8 +123,14 @@ void free_smooth(SmoothState& m) {
   m = SmoothState();
 }
 
+void free_inner(InnerState& q) {
+  dfree(q.IV); dfree(q.IZ); dfree(q.IH); dfree(q.IH0); dfree(q.y); dfree(q.jend); dfree(q.ones);
+  q = InnerState();
+}
+
 void free_sys(mdnp_sys* s) {
   free_smooth(s->smooth);
+  free_inner(s->inner);
   void* ptrs[] = {s->d_off, s->d_stencil, s->d_mptr, s->d_mcol, s->d_mval64, s->d_mval32, s->d_ma01, s->d_mrows, s->d_mlp,
                   s->d_a01p, s->d_a01c, s->d_a01v64, s->d_a01v32, s->d_m3e, s->d_dinv, s->d_dinv32, s->d_dist,
                   s->d_alpha, s->d_t_off, s->d_t_lvloff, s->d_t_lvlptr, s->d_t_lvlnodes, s->d_t_parent,
@@ -718,12 +724,48 @@ extern "C" mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* s, mdnp_
   });
 }
 
+extern "C" mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* s, int32_t steps) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s) fail(MDNP_E_ARG, "null system");
+    if (steps < 0 || steps > 8) fail(MDNP_E_ARG, "steps must be in [0, 8]");
+    if (steps > 0 && s->smooth.sweeps > 0) fail(MDNP_E_STATE, "switch the smoothing off first");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (s->work.graph) {
+      (void)hipGraphExecDestroy(s->work.graph);
+      s->work.graph = nullptr;
+      s->work.graph_m = -1;
+    }
+    free_inner(s->inner);
+    if (steps == 0) return;
+    InnerState& q = s->inner;
+    const size_t vb = vsize(s->vec_dtype) * (size_t)s->ntot;
+    const size_t ni = (size_t)s->n_inst;
+    q.IV = dalloc<char>(vb * (steps + 1));
+    q.IZ = dalloc<char>(vb * steps);
+    q.IH = dalloc<double>(ni * (steps + 1) * steps);
+    q.IH0 = dalloc<double>(ni * steps);
+    q.y = dalloc<double>(ni * steps);
+    q.jend = dalloc<int>(ni);
+    // 1D parts of the basis and directions stay zero; the Hessenberg rows
+    // below the diagonal band are never written
+    HIPCHK(hipMemsetAsync(q.IV, 0, vb * (steps + 1), ctx->stream));
+    HIPCHK(hipMemsetAsync(q.IZ, 0, vb * steps, ctx->stream));
+    HIPCHK(hipMemsetAsync(q.IH, 0, sizeof(double) * ni * (steps + 1) * steps, ctx->stream));
+    std::vector<double> ones(2 * ni, 1.0);
+    q.ones = dupload(ones, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    q.steps = steps;
+  });
+}
+
 extern "C" mdnp_status mdnp_set_smoothing(mdnp_ctx* ctx, mdnp_sys* s, int32_t sweeps, double omega) {
   if (!ctx) return MDNP_E_ARG;
   return guarded(ctx, [&] {
     if (!s) fail(MDNP_E_ARG, "null system");
     if (sweeps < 0 || sweeps > 16) fail(MDNP_E_ARG, "sweeps must be in [0, 16]");
     if (sweeps > 0 && !(omega > 0.0 && omega < 2.0)) fail(MDNP_E_ARG, "omega must be in (0, 2)");
+    if (sweeps > 0 && s->inner.steps > 0) fail(MDNP_E_STATE, "switch the inner FGMRES steps off first");
     HIPCHK(hipSetDevice(ctx->device));
     if (s->work.graph) {
       (void)hipGraphExecDestroy(s->work.graph);
@@ -792,11 +834,16 @@ void apply_prec(mdnp_sys* s, const T* v, T* z, const InstState* st, bool any_fb,
     case MDNP_PREC_BLOCK_JACOBI:
     case MDNP_PREC_NEURAL:
     {
-      const bool smooth = s->kind == MDNP_PREC_NEURAL && s->smooth.sweeps > 0;
+      const bool inner = s->kind == MDNP_PREC_NEURAL && s->inner.steps > 0;
+      const bool smooth = s->kind == MDNP_PREC_NEURAL && !inner && s->smooth.sweeps > 0;
       launch_tree_solve<T>(s, v, z, st, 0, stream);
       launch_extension<T>(s, v, z, P.p3, P.pM3, st, 0, stream, smooth);
       if (s->kind == MDNP_PREC_BLOCK_JACOBI) {
         launch_block_jacobi3d<T>(s, z, st, 0, stream);
+      } else if (inner) {
+        // z0 = inner FGMRES(K) on A00 z0 = b0 with the network as preconditioner
+        launch_inv_scale(s, P.p3, P.pM3, s->cnn.inv_s, const_cast<InstState*>(st), 0, stream);
+        launch_inner_fgmres<T>(s, z, st, P.pA, P.pB, P.pW, stream);
       } else if (smooth) {
         // z0 = smoothed 3D solve of b0: relaxation from zero (the first step in
         // the extension), the network on the remaining residual (its correction

@@ -567,8 +567,10 @@ void cnn_forward_batch(CnnState& c, const float* in, float* out, void* saved, in
 }
 
 template <typename Tv>
-void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, const InstState* st, hipStream_t stream) {
+void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, const InstState* st, hipStream_t stream,
+                         const double* scales) {
   CnnState& c = s->cnn;
+  const double* isc = scales ? scales : c.inv_s;
   const int n = s->n, batch = s->n_inst;
   if (!ensure_scratch(c, (size_t)cnn_saved_bytes(batch, n, c.dtype))) return;
   int64_t offs[13];
@@ -579,20 +581,22 @@ void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, const InstState* st,
   if (c.dtype == MDNP_BF16) {
     // first layer reads the Krylov vector directly; D0, ReLU, the 1x1 head and the
     // unscaling are one kernel writing z0
-    conv_mfma_in0<Tv>(c, zin, s->d_off, c.inv_s, s->d_dist, n, batch, (bf16*)act[1], st, stream);
+    conv_mfma_in0<Tv>(c, zin, s->d_off, isc, s->d_dist, n, batch, (bf16*)act[1], st, stream);
     unet_middle<bf16>(c, c.w, act, batch, n, c.dtype, st, stream, 8);
     conv_mfma_d0_head<Tv>(c, (const bf16*)act[9], (const bf16*)act[2], n, batch, z, s->d_off, s->d_alpha,
-                          s->alpha_override, c.inv_s + s->n_inst, st, stream);
+                          s->alpha_override, isc + s->n_inst, st, stream);
   } else {
-    hipLaunchKernelGGL((k_conv_in0<Tv, float>), grid, dim3(BS), 0, stream, zin, s->d_off, c.inv_s, s->d_dist,
+    hipLaunchKernelGGL((k_conv_in0<Tv, float>), grid, dim3(BS), 0, stream, zin, s->d_off, isc, s->d_dist,
                        c.wt + c.wt_off[0], c.w + c.b_off[0], n, (float*)act[1], st);
     unet_middle<float>(c, c.w, act, batch, n, c.dtype, st, stream);
     hipLaunchKernelGGL((k_head_out<Tv, float>), grid, dim3(BS), 0, stream, (const float*)act[10],
-                       c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override, c.inv_s + s->n_inst, st);
+                       c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override, isc + s->n_inst, st);
   }
 }
-template void cnn_apply_in_solver<float>(mdnp_sys*, const float*, float*, const InstState*, hipStream_t);
-template void cnn_apply_in_solver<double>(mdnp_sys*, const double*, double*, const InstState*, hipStream_t);
+template void cnn_apply_in_solver<float>(mdnp_sys*, const float*, float*, const InstState*, hipStream_t,
+                                         const double*);
+template void cnn_apply_in_solver<double>(mdnp_sys*, const double*, double*, const InstState*, hipStream_t,
+                                          const double*);
 
 // ---------------------------------------------------------------- backward
 

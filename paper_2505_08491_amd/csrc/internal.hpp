@@ -77,6 +77,19 @@ struct SmoothState {
   void* t = nullptr;           // A00 z
 };
 
+// Inner FGMRES(steps) with the network as preconditioner for the 3D block
+// (steps = 0: one network application).
+struct InnerState {
+  int steps = 0;
+  void* IV = nullptr;          // (steps + 1) x ntot basis vectors (1D parts zero)
+  void* IZ = nullptr;          // steps x ntot preconditioned directions
+  double* IH = nullptr;        // n_inst x (steps + 1) x steps
+  double* IH0 = nullptr;       // n_inst x steps: ||A00 z_j|| before orthogonalisation
+  double* y = nullptr;         // n_inst x steps
+  int* jend = nullptr;         // n_inst
+  double* ones = nullptr;      // 2 n_inst ones: unit scaling of the network input/output
+};
+
 struct SolveWork {
   int m = 0;                   // restart the buffers were sized for
   int hist_cap = 0;
@@ -187,5 +200,6 @@ struct mdnp_sys {
   double alpha_override = 0.0;
   mdnp::CnnState cnn;
   mdnp::SmoothState smooth;
+  mdnp::InnerState inner;
   mdnp::SolveWork work;
 };

@@ -60,6 +60,10 @@ template <typename T>
 void launch_smooth_pre(mdnp_sys* s, T* z, const InstState* st, double* part3, hipStream_t stream);
 template <typename T>
 void launch_smooth_post(mdnp_sys* s, T* z, const InstState* st, hipStream_t stream);
+// Inner FGMRES(K) with the network as preconditioner for the 3D block
+template <typename T>
+void launch_inner_fgmres(mdnp_sys* s, T* z, const InstState* st, double* pA, double* pB, double* pW,
+                         hipStream_t stream);
 
 // Arnoldi: modified Gram-Schmidt of V[j+1] in passes g = 0 .. mgs_passes(j) - 1,
 // kMgsGroup basis vectors per pass; each pass keeps kMgsVals partial sums per
@@ -95,9 +99,11 @@ void cnn_backward_batch(CnnState& c, const void* saved, const float* dy, float* 
                         int batch, int n, mdnp_dtype dtype, hipStream_t stream);
 // In-solver application on the 3D parts of the vectors (type T): reads
 // zin0 * inv_s and the distance field, writes z0 = s / alpha * U on the free
-// nodes of z (zin and z may be the same vector).
+// nodes of z (zin and z may be the same vector).  scales = [inv_s; s] per
+// instance (null: the context's, set by launch_inv_scale).
 template <typename T>
-void cnn_apply_in_solver(mdnp_sys* s, const T* zin, T* z, const InstState* st, hipStream_t stream);
+void cnn_apply_in_solver(mdnp_sys* s, const T* zin, T* z, const InstState* st, hipStream_t stream,
+                         const double* scales = nullptr);
 void cnn_release(CnnState& c);
 void launch_loss_grad(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u,
                       float* du, double* loss, hipStream_t stream);

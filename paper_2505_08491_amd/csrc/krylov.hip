@@ -938,6 +938,124 @@ __global__ void __launch_bounds__(BS) k_smooth_res(const T* __restrict__ sb, con
   if (threadIdx.x == 0) part[b] = tt;
 }
 
+// ---------------------------------------------------------------- inner FGMRES on the 3D block
+// The 3D solve of Section 6: K FGMRES steps on A00 z0 = b0 from z0 = 0 with
+// the network as right preconditioner.  Basis vectors IV[0..K] and directions
+// IZ[0..K-1] are full-length vectors whose 1D parts stay zero.
+
+// IV[0] = b0 / ||b0|| (b0 in z, inv_s from its partials).
+template <typename T>
+__global__ void __launch_bounds__(BS) k_inner_start(const T* __restrict__ z, T* __restrict__ v0,
+                                                    const double* __restrict__ inv_s, const int64_t* off,
+                                                    const int32_t* binst, const int64_t* bstart, const int64_t* bend,
+                                                    const InstState* st) {
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (st && !mode_ok(st[i], 0)) return;
+  const int64_t base = off[i];
+  const double sc = inv_s[i];
+  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += BS)
+    v0[base + r] = from_d<T>(to_d(z[base + r]) * sc);
+}
+
+// dst = src over the 3D rows (the network's value on the Dirichlet rows is its input).
+template <typename T>
+__global__ void __launch_bounds__(BS) k_copy3d(const T* __restrict__ src, T* __restrict__ dst, const int64_t* off,
+                                               const int32_t* binst, const int64_t* bstart, const int64_t* bend,
+                                               const InstState* st) {
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (st && !mode_ok(st[i], 0)) return;
+  const int64_t base = off[i];
+  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += BS) dst[base + r] = src[base + r];
+}
+
+// End of inner step j: h = ||w|| from the last Gram-Schmidt pass, stored with
+// ||w|| before orthogonalisation (breakdown test); w /= h unless this is the
+// last step (h = 0 leaves a zero vector).
+template <typename T>
+__global__ void __launch_bounds__(BS) k_inner_finish(T* __restrict__ w, const double* __restrict__ part_last,
+                                                     const double* __restrict__ part_w0, double* __restrict__ IH,
+                                                     double* __restrict__ IH0, int j, int K, int scale,
+                                                     const int32_t* binst, const int64_t* bstart,
+                                                     const int64_t* bend, const int32_t* first,
+                                                     const InstState* st) {
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (st && !mode_ok(st[i], 0)) return;
+  const double hn = sqrt(wave_inst_sum(part_last, first, i));
+  if (b == first[i] && threadIdx.x == 0) {
+    IH[((int64_t)i * (K + 1) + (j + 1)) * K + j] = hn;
+    IH0[(int64_t)i * K + j] = sqrt(wave_inst_sum(part_w0, first, i));
+  }
+  if (!scale) return;
+  const double sc = hn > 0.0 ? 1.0 / hn : 0.0;
+  for (int64_t e = bstart[b] + threadIdx.x; e < bend[b]; e += BS) w[e] = from_d<T>(to_d(w[e]) * sc);
+}
+
+// Least squares of the inner solve, one thread per instance: Givens rotations
+// on the (K+1) x K Hessenberg matrix with g = ||b0|| e1, steps up to the first
+// breakdown (h_{j+1,j} <= 1e-14 ||A00 z_j||), back substitution into y.
+__global__ void k_inner_lsq(const double* __restrict__ IH, const double* __restrict__ IH0,
+                            const double* __restrict__ inv_s, double* __restrict__ y, int* __restrict__ jend_out,
+                            int K, int n_inst, const InstState* st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  if (st && !mode_ok(st[i], 0)) return;
+  constexpr int KM = 8;
+  double H[KM + 1][KM], g[KM + 1], c[KM], s[KM];
+  const double* Hi = IH + (int64_t)i * (K + 1) * K;
+  for (int r = 0; r <= K; ++r)
+    for (int q = 0; q < K; ++q) H[r][q] = Hi[r * K + q];
+  for (int r = 0; r <= K; ++r) g[r] = 0.0;
+  g[0] = inv_s[n_inst + i];  // ||b0||
+  int jend = 0;
+  for (int j = 0; j < K; ++j) {
+    for (int q = 0; q < j; ++q) {
+      const double t = c[q] * H[q][j] + s[q] * H[q + 1][j];
+      H[q + 1][j] = -s[q] * H[q][j] + c[q] * H[q + 1][j];
+      H[q][j] = t;
+    }
+    const double a = H[j][j], bb = H[j + 1][j];
+    const double den = hypot(a, bb);
+    c[j] = den == 0.0 ? 1.0 : a / den;
+    s[j] = den == 0.0 ? 0.0 : bb / den;
+    H[j][j] = c[j] * a + s[j] * bb;
+    g[j + 1] = -s[j] * g[j];
+    g[j] = c[j] * g[j];
+    jend = j + 1;
+    if (bb <= 1e-14 * IH0[(int64_t)i * K + j]) break;
+  }
+  double* yi = y + (int64_t)i * K;
+  for (int q = 0; q < K; ++q) yi[q] = 0.0;
+  for (int q = jend - 1; q >= 0; --q) {
+    double acc = g[q];
+    for (int p = q + 1; p < jend; ++p) acc -= H[q][p] * yi[p];
+    yi[q] = H[q][q] != 0.0 ? acc / H[q][q] : 0.0;
+  }
+  jend_out[i] = jend;
+}
+
+// z0 = sum_j y_j IZ[j] over the 3D rows.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_inner_combine(T* __restrict__ z, const T* __restrict__ IZ, int64_t ld,
+                                                      const double* __restrict__ y, const int* __restrict__ jend,
+                                                      int K, const int64_t* off, const int32_t* binst,
+                                                      const int64_t* bstart, const int64_t* bend,
+                                                      const InstState* st) {
+  const int b = blockIdx.x;
+  const int i = binst[b];
+  if (st && !mode_ok(st[i], 0)) return;
+  const int64_t base = off[i];
+  const int je = jend[i];
+  const double* yi = y + (int64_t)i * K;
+  for (int64_t r = bstart[b] + threadIdx.x; r < bend[b]; r += BS) {
+    double acc = 0.0;
+    for (int q = 0; q < je; ++q) acc += yi[q] * to_d(IZ[(int64_t)q * ld + base + r]);
+    z[base + r] = from_d<T>(acc);
+  }
+}
+
 // ---------------------------------------------------------------- Arnoldi (modified Gram-Schmidt)
 
 // Modified Gram-Schmidt for the new vector w = V[j+1], taken kMgsGroup basis
@@ -968,7 +1086,7 @@ __global__ void __launch_bounds__(BS) k_mgs(T* __restrict__ V, int64_t ld, int j
   __shared__ double sh[NSH * (BS / 64)];
   const int b = blockIdx.x;
   const int i = binst[b];
-  if (!st[i].active) return;
+  if (st && !st[i].active) return;
   T* w = V + (int64_t)(j + 1) * ld;
   const int f0 = first[i], f1 = first[i + 1];
   const int t = (int)threadIdx.x;
@@ -1390,6 +1508,47 @@ void launch_smooth_post(mdnp_sys* s, T* z, const InstState* st, hipStream_t stre
 }
 template void launch_smooth_post<float>(mdnp_sys*, float*, const InstState*, hipStream_t);
 template void launch_smooth_post<double>(mdnp_sys*, double*, const InstState*, hipStream_t);
+
+// The inner FGMRES 3D solve (Section 6) after the extension left b0 in z and
+// launch_inv_scale its norm: K steps, each a network application with unit
+// scaling (the basis vectors are unit vectors), an A00 application and
+// Gram-Schmidt against the previous basis vectors (partials in pA / pB / pW),
+// then the small least-squares problem and z0 = sum_j y_j IZ[j].
+template <typename T>
+void launch_inner_fgmres(mdnp_sys* s, T* z, const InstState* st, double* pA, double* pB, double* pW,
+                         hipStream_t stream) {
+  InnerState& q = s->inner;
+  const int K = q.steps;
+  const int64_t ld = s->ntot;
+  T* IV = (T*)q.IV;
+  T* IZ = (T*)q.IZ;
+  hipLaunchKernelGGL((k_inner_start<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, (const T*)z, IV, s->cnn.inv_s,
+                     s->d_off, BLK3(s), st);
+  for (int j = 0; j < K; ++j) {
+    T* vj = IV + (int64_t)j * ld;
+    T* zj = IZ + (int64_t)j * ld;
+    hipLaunchKernelGGL((k_copy3d<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, (const T*)vj, zj, s->d_off, BLK3(s),
+                       st);
+    cnn_apply_in_solver<T>(s, vj, zj, st, stream, q.ones);
+    launch_a00<T>(s, zj, IV + (int64_t)(j + 1) * ld, st, stream);
+    const int np = mgs_passes(j);
+    for (int g = 0; g < np; ++g) {
+      double* cur = (g % 2 == 0) ? pA : pB;
+      double* prev = (g % 2 == 0) ? pB : pA;
+      launch_mgs<T>(s, IV, j, g, prev, cur, pW, q.IH, K, st, stream);
+    }
+    const double* last = ((np - 1) % 2 == 0) ? pA : pB;
+    hipLaunchKernelGGL((k_inner_finish<T>), dim3(s->blk.nblk), dim3(BS), 0, stream, IV + (int64_t)(j + 1) * ld, last,
+                       (const double*)pW, q.IH, q.IH0, j, K, j + 1 < K ? 1 : 0, BLK(s), s->blk.first, st);
+  }
+  hipLaunchKernelGGL(k_inner_lsq, dim3((s->n_inst + 63) / 64), dim3(64), 0, stream, (const double*)q.IH,
+                     (const double*)q.IH0, (const double*)s->cnn.inv_s, q.y, q.jend, K, s->n_inst, st);
+  hipLaunchKernelGGL((k_inner_combine<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, (const T*)IZ, ld,
+                     (const double*)q.y, (const int*)q.jend, K, s->d_off, BLK3(s), st);
+}
+template void launch_inner_fgmres<float>(mdnp_sys*, float*, const InstState*, double*, double*, double*, hipStream_t);
+template void launch_inner_fgmres<double>(mdnp_sys*, double*, const InstState*, double*, double*, double*,
+                                          hipStream_t);
 
 void launch_spmv_a00_slots(mdnp_sys* s, const int32_t* inst, int n_slots, const float* x, float* y,
                            hipStream_t stream) {

@@ -238,12 +238,46 @@ def test_smoothed_neural_block_preconditioner(ctx, vec, cnn_dtype, tol, sweeps, 
     S.free()
 
 
+@pytest.mark.parametrize("vec,cnn_dtype,tol", [("f64", "f32", 2e-5), ("f32", "f32", 1e-4), ("f32", "bf16", 5e-2)])
+@pytest.mark.parametrize("steps", [1, 3])
+def test_inner_fgmres_block_preconditioner(ctx, vec, cnn_dtype, tol, steps):
+    """Q(v) with the 3D block solved by `steps` inner FGMRES steps on A00 with
+    the network as preconditioner (Section 6), against the oracle's P-FGMRES."""
+    P = _P()
+    insts = [synth.make_instance(930 + i, 16, n_segments=s, elems_per_segment=3, radius=0.01, beta=1.0)
+             for i, s in enumerate((7, 4))]
+    S = P.System(ctx, insts, vec_dtype=vec)
+    th = _theta(6)
+    S.set_preconditioner("neural", weights=th.astype(np.float32), cnn_dtype=cnn_dtype)
+    S.set_inner_steps(steps)
+    th64 = th.astype(np.float32).astype(np.float64)
+    net = lambda X: ocnn.forward(th64, X)[0]
+    v = synth.fast_normal(8, S.ntot)
+    td = torch.float64 if vec == "f64" else torch.float32
+    z = S.precond_apply(dev(v, td)).cpu().double().numpy()
+    for k, inst in enumerate(insts):
+        s = fem.assemble(inst)
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        vk = v[o0:o1] if vec == "f64" else v[o0:o1].astype(np.float32).astype(np.float64)
+        p3 = krylov.p3d_inner_fgmres(s, krylov.p3d_neural(s, net), steps)
+        ref = krylov.BlockPreconditioner(s, p3)(vk)
+        err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
+        assert err <= tol, (k, err)
+    with pytest.raises(Exception):
+        S.set_smoothing(1, 0.8)  # one 3D-solve variant at a time
+    S.set_inner_steps(0)
+    S.free()
+
+
 def test_smoothing_rejects_bad_arguments(ctx):
     P = _P()
     S = P.System(ctx, [synth.make_instance(920, 8, n_segments=3, elems_per_segment=3, radius=0.02, beta=1.0)])
     for sweeps, omega in [(-1, 0.8), (17, 0.8), (1, 0.0), (1, 2.0)]:
         with pytest.raises(Exception):
             S.set_smoothing(sweeps, omega)
+    for steps in (-1, 9):
+        with pytest.raises(Exception):
+            S.set_inner_steps(steps)
     S.free()
 
 
@@ -436,6 +470,28 @@ def test_neural_precond_bench_config(ctx, bench64):
         ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(v[o0:o1].astype(np.float64))
         err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
         assert err <= 5e-2, (k, err)
+
+
+def test_inner_fgmres_precond_bench_config(ctx, bench64):
+    """Three inner FGMRES steps with the trained network at the benchmark size,
+    instance 0, against the FP64 oracle."""
+    from paper_2505_08491_amd import weights as W
+    S, _, systems = bench64
+    wpath = W.default_path()
+    th = W.load(wpath)[0] if __import__("os").path.exists(wpath + ".bin") else _theta(5).astype(np.float32)
+    S.set_preconditioner("neural", weights=th, cnn_dtype="bf16")
+    S.set_inner_steps(3)
+    th64 = np.asarray(th, dtype=np.float32).astype(np.float64)
+    net = lambda X: ocnn.forward(th64, X)[0]
+    v = synth.fast_normal(15, S.ntot).astype(np.float32)
+    z = S.precond_apply(dev(v, torch.float32)).cpu().double().numpy()
+    S.set_inner_steps(0)
+    s = systems[0]
+    o0, o1 = S.offsets[0], S.offsets[1]
+    p3 = krylov.p3d_inner_fgmres(s, krylov.p3d_neural(s, net), 3)
+    ref = krylov.BlockPreconditioner(s, p3)(v[o0:o1].astype(np.float64))
+    err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
+    assert err <= 5e-2, err
 
 
 def test_smoothed_precond_bench_config(ctx, bench64):

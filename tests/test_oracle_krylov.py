@@ -180,3 +180,35 @@ def test_smoothing_lowers_neural_iterations():
     r1 = krylov.fgmres(s.A, s.F, precond=smooth, restart=30, tol=1e-8, max_iters=300)
     assert r0.converged and r1.converged
     assert r1.iters < r0.iters
+
+
+def test_inner_fgmres_with_exact_preconditioner_is_exact():
+    """P-FGMRES with P = A00^-1 solves A00 z = b in its first step."""
+    s, A00, b = _smoothing_case()
+    z = krylov.p3d_inner_fgmres(s, krylov.p3d_exact(s), 3)(b)
+    zx = np.linalg.solve(A00, b)
+    assert np.linalg.norm(z - zx) / np.linalg.norm(zx) < 1e-11
+
+
+def test_inner_fgmres_minimises_residual_over_its_directions():
+    """After k steps from zero, z minimises ||b - A00 z|| over span{P(v_1) .. P(v_k)}
+    (the directions the preconditioner returned), checked by a dense
+    least-squares solve; with a nonlinear (random-network) P."""
+    s, A00, b = _smoothing_case()
+    theta = cnn.init_params(2)
+    base = krylov.p3d_neural(s, lambda X: cnn.forward(theta, X)[0])
+    Z = []
+
+    def rec(v):
+        z = base(v)
+        Z.append(z)
+        return z
+    for k in (1, 3):
+        Z.clear()
+        z = krylov.p3d_inner_fgmres(s, rec, k)(b)
+        Zm = np.stack(Z, axis=1)
+        c, *_ = np.linalg.lstsq(A00 @ Zm, b, rcond=None)
+        zs = Zm @ c
+        assert len(Z) == k
+        assert np.linalg.norm(z - zs) / np.linalg.norm(zs) < 1e-9
+        assert np.linalg.norm(b - A00 @ z) <= np.linalg.norm(b) * (1 + 1e-12)
