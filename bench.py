@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--smooth-sweeps", type=int, default=1,
                     help="Jacobi pre/post-smoothing steps of the extra smoothed solve (0: skip it)")
     ap.add_argument("--smooth-omega", type=float, default=0.8)
+    ap.add_argument("--no-distance-run", type=int, default=1,
+                    help="also time the network trained without the distance input (0: skip)")
     ap.add_argument("--inner-steps", type=int, default=3,
                     help="inner FGMRES steps of the extra inner-solve run (0: skip it)")
     ap.add_argument("--cpu-neural-iters", type=int, default=3)
@@ -261,6 +263,20 @@ def main():
                  "used_fallback": int(sum(q["used_fallback"] for q in sti)), "max_true_rel_res": max(rel_i),
                  "ms_per_apply": ms_prec_i}
 
+    # the network trained with its distance-channel weights held at zero (ablation)
+    nodist = None
+    npath = os.path.join(os.path.dirname(W.default_path()), "unet32_nodist")
+    if a.no_distance_run and os.path.exists(npath + ".bin"):
+        wnd = W.load(npath)[0]
+        S.set_preconditioner("neural", weights=wnd, cnn_dtype=a.cnn_dtype)
+        Tn, stn = run(neural_opts, a.steps, 1)
+        rel_nd = true_rel()
+        nodist = {"weights": os.path.relpath(npath, ROOT), "solves_per_s": S.n_inst * a.steps / Tn,
+                  "ms_per_solve": Tn / a.steps * 1e3,
+                  "iters_mean": float(np.mean([q["iters"] + q["fallback_iters"] for q in stn])),
+                  "converged_all": all(q["converged"] for q in stn),
+                  "used_fallback": int(sum(q["used_fallback"] for q in stn)), "max_true_rel_res": max(rel_nd)}
+
     jac = None
     if not a.skip_jacobi:
         S.set_preconditioner("jacobi")
@@ -285,6 +301,7 @@ def main():
                    "converged_all": conv_all, "used_fallback": int(n_fb), "max_true_rel_res": max(rel_n)},
         "neural_smoothed": smoothed,
         "neural_inner_fgmres": inner,
+        "neural_no_distance": nodist,
         "jacobi": jac,
         "roofline": {"bound": "hbm", "kernel": "k_stencil_sweep + k_mrows (batched y = (S + M) x, FP32)",
                      "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,

@@ -67,8 +67,16 @@ def build_bank(ctx: Context, S: System, krylov_ids=(5, 6, 7, 8)) -> torch.Tensor
     return bank
 
 
+def dist_weight_mask() -> np.ndarray:
+    """Indices of the first layer's weights on the distance channel (input
+    channel 1 of L0a, laid out [16][27][2] at the start of the flat vector)."""
+    return np.arange(16 * 27) * 2 + 1
+
+
 def train(steps=2000, batch=32, graphs=128, n_cells=32, lr=1e-3, lr_min=1e-5, dtype="bf16", seed=0,
-          p_random=0.5, p_rhs=0.25, out=None, log_every=50, val_graphs=16, resume=None):
+          p_random=0.5, p_rhs=0.25, out=None, log_every=50, val_graphs=16, resume=None, no_dist=False):
+    """no_dist: the first layer's distance-channel weights are held at zero, so
+    the network never sees the distance field (parameterisation ablation)."""
     torch.manual_seed(seed)
     ctx = Context(0)
     t0 = time.time()
@@ -96,6 +104,9 @@ def train(steps=2000, batch=32, graphs=128, n_cells=32, lr=1e-3, lr_min=1e-5, dt
             m = torch.from_numpy(ad[:W.N_PARAMS].copy()).cuda()
             v = torch.from_numpy(ad[W.N_PARAMS:].copy()).cuda()
         step0 = int(meta.get("step", 0))
+    dmask = torch.from_numpy(dist_weight_mask()).cuda() if no_dist else None
+    if dmask is not None:
+        w[dmask] = 0.0
     saved = torch.empty(ctx.saved_bytes(batch, n, dtype), dtype=torch.uint8, device="cuda")
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed + 1)
@@ -131,6 +142,8 @@ def train(steps=2000, batch=32, graphs=128, n_cells=32, lr=1e-3, lr_min=1e-5, dt
         frac = (step - 1) / max(1, steps - 1)
         lr_t = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * frac))
         ctx.adam_step(w, dw, m, v, lr_t, step)
+        if dmask is not None:
+            w[dmask] = 0.0
         if step % log_every == 0 or step == step0 + 1 or step == steps:
             lv = float(loss.mean())
             vl = evaluate(w)
@@ -144,7 +157,7 @@ def train(steps=2000, batch=32, graphs=128, n_cells=32, lr=1e-3, lr_min=1e-5, dt
     wn = w.cpu().numpy()
     meta = {"step": steps, "batch": batch, "graphs": graphs, "n_cells": n_cells, "lr": lr, "lr_min": lr_min,
             "schedule": "cosine", "dtype": dtype, "seed": seed, "p_random": p_random, "p_rhs": p_rhs,
-            "train_seconds": elapsed, "history": history}
+            "no_dist": bool(no_dist), "train_seconds": elapsed, "history": history}
     if out:
         os.makedirs(os.path.dirname(out), exist_ok=True)
         W.save(out, wn, meta, adam=(m.cpu().numpy(), v.cpu().numpy()))
@@ -166,11 +179,15 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--resume", default=None)
     ap.add_argument("--log-every", type=int, default=50)
+    ap.add_argument("--p-random", type=float, default=0.5, help="share of random unit samples")
+    ap.add_argument("--p-rhs", type=float, default=0.25, help="share of b/||b|| samples (the rest: Arnoldi vectors)")
+    ap.add_argument("--no-dist", action="store_true", help="keep the distance-channel weights at zero")
     a = ap.parse_args(argv)
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
     train(steps=a.steps, batch=a.batch, graphs=a.graphs, n_cells=a.n_cells, lr=a.lr, dtype=a.dtype, seed=a.seed,
-          out=a.out, log_every=a.log_every, resume=a.resume)
+          p_random=a.p_random, p_rhs=a.p_rhs, out=a.out, log_every=a.log_every, resume=a.resume,
+          no_dist=a.no_dist)
 
 
 if __name__ == "__main__":

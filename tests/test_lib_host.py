@@ -99,3 +99,18 @@ def test_geometry_errors():
     with pytest.raises(P.MdnpError):
         P.host_assemble(bad3)
     P.host_assemble(inst)
+
+
+def test_distance_weight_mask_selects_first_layer_distance_channel():
+    """The no-distance ablation zeroes exactly the first layer's weights on input
+    channel 1 (the distance field) in the flat parameter layout."""
+    import numpy as np
+    from oracle import cnn as ocnn
+    from paper_2505_08491_amd import weights as W
+    from paper_2505_08491_amd.train import dist_weight_mask
+    theta = np.zeros(W.N_PARAMS)
+    theta[dist_weight_mask()] = 1.0
+    layers = ocnn.unflatten(theta)
+    w0 = np.asarray(layers[0][0])
+    assert w0[..., 1].min() == 1.0 and w0[..., 0].max() == 0.0
+    assert sum(float(np.abs(np.asarray(a)).sum()) for l in layers for a in l) == w0[..., 1].size
