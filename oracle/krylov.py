@@ -169,8 +169,17 @@ def p3d_exact(system):
     return lambda b: lu.solve(b)
 
 
+def distance_input(system):
+    """The network's parameter channel: the distance field of the tree (Section
+    2.1) scaled to unit Euclidean norm over the grid, the scale of the unit
+    residual channel it is stacked with (the paper does not fix its scale)."""
+    d = np.asarray(system.dist, dtype=np.float64)
+    nd = float(np.linalg.norm(d))
+    return d / nd if nd > 0.0 else d
+
+
 def p3d_neural(system, net_apply):
-    """P3D(b) = ||b|| alpha^-1 U([b / ||b||, d]) with Dirichlet rows z = b.
+    """P3D(b) = ||b|| alpha^-1 U([b / ||b||, d / ||d||]) with Dirichlet rows z = b.
 
     `net_apply(x2)` evaluates the U-net on a [n, n, n, 2] input and returns
     [n, n, n] (module `cnn`).  alpha is the RMS of diag(A00) over the free
@@ -178,7 +187,7 @@ def p3d_neural(system, net_apply):
     """
     n = system.n_cells + 1
     bnd = system.boundary
-    d = system.dist.reshape(n, n, n)
+    d = distance_input(system).reshape(n, n, n)
     alpha = system.alpha
 
     def apply(b):

@@ -65,6 +65,10 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--variants", default=",".join(VARIANTS))
     ap.add_argument("--reuse-shipped", action="store_true", help="take the shipped weights for `all`")
+    ap.add_argument("--reuse-nodist", action="store_true",
+                    help="take the shipped no-distance weights for `all-nod` (their distance weights are zero, "
+                         "so the distance scaling does not change them)")
+    ap.add_argument("--save-dir", default=None, help="save every trained network as <dir>/unet32_<variant>")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     if ROOT not in sys.path:
@@ -73,11 +77,15 @@ def main(argv=None):
     nets = {}
     meta = {}
     for name in a.variants.split(","):
+        nodist_path = os.path.join(os.path.dirname(W.default_path()), "unet32_nodist")
         if name == "all" and a.reuse_shipped and os.path.exists(W.default_path() + ".bin"):
             nets[name], m = W.load(W.default_path())
+        elif name == "all-nod" and a.reuse_nodist and os.path.exists(nodist_path + ".bin"):
+            nets[name], m = W.load(nodist_path)
         else:
             print(f"training {name}", flush=True)
-            nets[name], m = T.train(steps=a.steps, **VARIANTS[name])
+            out = os.path.join(a.save_dir, "unet32_" + name) if a.save_dir else None
+            nets[name], m = T.train(steps=a.steps, out=out, **VARIANTS[name])
         meta[name] = {k: m.get(k) for k in ("p_random", "p_rhs", "no_dist", "train_seconds")}
         meta[name]["final_val_loss"] = m["history"][-1]["val_loss"] if m.get("history") else None
     ctx = Context(0)

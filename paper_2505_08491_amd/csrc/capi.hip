@@ -428,7 +428,14 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
       for (int r = 0; r < h.n3d; ++r) ma01[(size_t)i * s->n3d + r] = (int32_t)(mo + h.m_a01[r]);
       mo += (int64_t)h.m_col.size();
       for (int r = 0; r < nr; ++r) dinv[o + r] = 1.0 / h.diag[r];
-      std::memcpy(&dist[(size_t)i * s->n3d], h.dist.data(), sizeof(float) * h.n3d);
+      {
+        // the network's distance channel is the distance field scaled to unit
+        // norm, like the residual channel it is stacked with
+        double nd = 0.0;
+        for (int r = 0; r < h.n3d; ++r) nd += (double)h.dist[r] * (double)h.dist[r];
+        const double sc = nd > 0.0 ? 1.0 / std::sqrt(nd) : 0.0;
+        for (int r = 0; r < h.n3d; ++r) dist[(size_t)i * s->n3d + r] = (float)((double)h.dist[r] * sc);
+      }
       alpha[i] = h.alpha;
       for (int q = 0; q < 4; ++q) stn[(size_t)i * 4 + q] = h.stencil[q];
     }

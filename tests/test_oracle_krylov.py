@@ -212,3 +212,11 @@ def test_inner_fgmres_minimises_residual_over_its_directions():
         assert len(Z) == k
         assert np.linalg.norm(z - zs) / np.linalg.norm(zs) < 1e-9
         assert np.linalg.norm(b - A00 @ z) <= np.linalg.norm(b) * (1 + 1e-12)
+
+
+def test_distance_input_is_the_unit_norm_distance_field():
+    s = _c1()
+    d = krylov.distance_input(s)
+    assert abs(np.linalg.norm(d) - 1.0) < 1e-12
+    k = np.argmax(s.dist)
+    assert np.allclose(d * (s.dist[k] / d[k]), s.dist, rtol=1e-12, atol=0)
