@@ -221,6 +221,12 @@ mdnp_status mdnp_export_basis(mdnp_ctx* ctx, const mdnp_sys* sys, int32_t k, voi
 mdnp_status mdnp_spmv(mdnp_ctx* ctx, mdnp_sys* sys, int32_t block, const void* d_x, void* d_y,
                       mdnp_dtype dtype, void* hip_stream);
 
+/* The same y = A x (block 0) launched `reps` times back to back on the stream,
+ * for timing the kernels without per-call host overhead between launches.
+ * Errors: MDNP_E_ARG (reps < 1, null vectors, dtype not F32/F64). */
+mdnp_status mdnp_spmv_repeat(mdnp_ctx* ctx, mdnp_sys* sys, const void* d_x, void* d_y, mdnp_dtype dtype,
+                             int32_t reps, void* hip_stream);
+
 /* z1 = A11^-1 v1 for every instance: the exact 1D solve of eq. "twosteps" by a
  * leaves-first LDL^T factorisation of the tree matrix (no fill).  d_v and d_z
  * are full concatenated vectors of the system's vec_dtype; only the 1D parts

@@ -61,6 +61,7 @@ SIGNATURES = [
     ("mdnp_history", C.c_int, [VP, C.c_int32, VP, C.c_int32, P(C.c_int32)]),
     ("mdnp_export_basis", C.c_int, [VP, VP, C.c_int32, VP, VP]),
     ("mdnp_spmv", C.c_int, [VP, VP, C.c_int32, VP, VP, C.c_int, VP]),
+    ("mdnp_spmv_repeat", C.c_int, [VP, VP, VP, VP, C.c_int, C.c_int32, VP]),
     ("mdnp_tree_solve", C.c_int, [VP, VP, VP, VP, VP]),
     ("mdnp_precond_apply", C.c_int, [VP, VP, VP, VP, VP]),
     ("mdnp_cnn_forward", C.c_int, [VP, VP, VP, VP, VP, C.c_int32, C.c_int32, C.c_int, VP]),

@@ -298,6 +298,12 @@ class System:
         self.ctx.run(lib.mdnp_spmv, self.ctx.h, self.h, block, _ptr(x), _ptr(y), DTYPE[dt], _stream(self.ctx.stream))
         return y
 
+    def spmv_repeat(self, x: torch.Tensor, y: torch.Tensor, reps: int):
+        """y = A x launched `reps` times back to back (kernel timing)."""
+        dt = "f64" if x.dtype == torch.float64 else "f32"
+        self.ctx.run(lib.mdnp_spmv_repeat, self.ctx.h, self.h, _ptr(x), _ptr(y), DTYPE[dt], int(reps),
+                     _stream(self.ctx.stream))
+
     def tree_solve(self, v: torch.Tensor, z: torch.Tensor | None = None) -> torch.Tensor:
         z = torch.zeros_like(v) if z is None else z
         self.ctx.run(lib.mdnp_tree_solve, self.ctx.h, self.h, _ptr(v), _ptr(z), _stream(self.ctx.stream))

@@ -1093,6 +1093,23 @@ extern "C" mdnp_status mdnp_spmv(mdnp_ctx* ctx, mdnp_sys* s, int32_t block, cons
   });
 }
 
+extern "C" mdnp_status mdnp_spmv_repeat(mdnp_ctx* ctx, mdnp_sys* s, const void* d_x, void* d_y, mdnp_dtype dtype,
+                                        int32_t reps, void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !d_x || !d_y) fail(MDNP_E_ARG, "null argument");
+    if (dtype != MDNP_F32 && dtype != MDNP_F64) fail(MDNP_E_ARG, "dtype must be MDNP_F32 or MDNP_F64");
+    if (reps < 1) fail(MDNP_E_ARG, "reps must be positive");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t stream = pick(ctx, hip_stream);
+    for (int k = 0; k < reps; ++k) {
+      if (dtype == MDNP_F64) launch_spmv<double>(s, (const double*)d_x, (double*)d_y, nullptr, false, stream);
+      else launch_spmv<float>(s, (const float*)d_x, (float*)d_y, nullptr, false, stream);
+    }
+    HIPCHK(hipGetLastError());
+  });
+}
+
 extern "C" mdnp_status mdnp_tree_solve(mdnp_ctx* ctx, mdnp_sys* s, const void* d_v, void* d_z, void* hip_stream) {
   if (!ctx) return MDNP_E_ARG;
   return guarded(ctx, [&] {

@@ -422,6 +422,15 @@ def test_spmv_bench_config(ctx, bench64):
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) <= 1e-6
 
 
+def test_spmv_repeat_equals_spmv(ctx, bench64):
+    """The back-to-back timing entry point computes the same y = A x."""
+    S, _, _ = bench64
+    x = dev(synth.fast_normal(16, S.ntot).astype(np.float32), torch.float32)
+    y = torch.empty_like(x)
+    S.spmv_repeat(x, y, 3)
+    assert torch.equal(y, S.spmv(x))
+
+
 def test_tree_solve_bench_config(ctx, bench64):
     """Chain-compressed A11^-1 on 8193-node trees (512 segments x 15 interior nodes)."""
     S, _, systems = bench64
