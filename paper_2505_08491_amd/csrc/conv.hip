@@ -511,6 +511,52 @@ static void unet_middle(CnnState& c, const float* d_w, void* const* act, int bat
   }
 }
 
+// Channels of the packed network input [v][2] into two arrays.
+__global__ void k_split_input(const float* __restrict__ x, float* __restrict__ c0, float* __restrict__ c1,
+                              int64_t nvox) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= nvox) return;
+  const float2 a = ((const float2*)x)[v];
+  c0[v] = a.x;
+  c1[v] = a.y;
+}
+
+// The 1x1 head 16 -> 1 over all voxels: y = b + sum_c w_c x_c, channels in order.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_head16(const T* __restrict__ x, const float* __restrict__ w,
+                                               const float* __restrict__ b, float* __restrict__ y, int64_t nvox) {
+  const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (v >= nvox) return;
+  const T* xv = x + v * 16;
+  float acc = b[0];
+#pragma unroll
+  for (int ch = 0; ch < 16; ++ch) acc = fmaf(w[ch], ld(xv + ch), acc);
+  y[v] = acc;
+}
+
+static bool ensure_split(CnnState& c, int batch, int n, hipStream_t stream) {
+  const size_t nv = (size_t)batch * cube(n);
+  if (c.split && c.split_n >= nv && c.std_batch == batch && c.std_n == n) return true;
+  if (c.split) (void)hipFree(c.split);
+  if (c.std_off) (void)hipFree(c.std_off);
+  if (c.std_ones) (void)hipFree(c.std_ones);
+  c.split = nullptr; c.std_off = nullptr; c.std_ones = nullptr;
+  c.split_n = 0;
+  if (hipMalloc(&c.split, sizeof(float) * 2 * nv) != hipSuccess) { c.split = nullptr; return false; }
+  if (hipMalloc(&c.std_off, sizeof(int64_t) * batch) != hipSuccess) return false;
+  if (hipMalloc(&c.std_ones, sizeof(double) * batch) != hipSuccess) return false;
+  std::vector<int64_t> off(batch);
+  std::vector<double> ones(batch, 1.0);
+  for (int k = 0; k < batch; ++k) off[k] = (int64_t)k * cube(n);
+  (void)hipMemcpyAsync(c.std_off, off.data(), sizeof(int64_t) * batch, hipMemcpyHostToDevice, stream);
+  (void)hipMemcpyAsync(c.std_ones, ones.data(), sizeof(double) * batch, hipMemcpyHostToDevice, stream);
+  (void)hipStreamSynchronize(stream);
+  c.split_n = nv;
+  c.std_batch = batch;
+  c.std_n = n;
+  return true;
+}
+
 template <typename T>
 static void forward_t(CnnState& c, const float* in, float* out, void* saved, int batch, int n, mdnp_dtype dtype,
                       hipStream_t stream) {
@@ -521,7 +567,13 @@ static void forward_t(CnnState& c, const float* in, float* out, void* saved, int
   for (int k = 0; k < 12; ++k) act[k] = base + offs[k];
   hipMemcpyAsync(act[0], in, sizeof(float) * 2 * batch * cube(n), hipMemcpyDeviceToDevice, stream);
   const float* d_w = c.w;
-  {  // L0a: FP32 input
+  if (dtype == MDNP_BF16 && ensure_split(c, batch, n, stream)) {
+    // L0a on MFMA: the first-layer kernel of the solver reading the two channels
+    const int64_t nv = (int64_t)batch * cube(n);
+    hipLaunchKernelGGL(k_split_input, dim3((unsigned)((nv + BS - 1) / BS)), dim3(BS), 0, stream,
+                       (const float*)act[0], c.split, c.split + nv, nv);
+    conv_mfma_in0<float>(c, c.split, c.std_off, c.std_ones, c.split + nv, n, batch, (bf16*)act[1], nullptr, stream);
+  } else {  // L0a: FP32 input, direct
     const LayerSpec& L = kLayers[0];
     ConvP p{};
     p.a = act[0]; p.ca = 2; p.lda = 2; p.a_bs = cube(n) * 2;
@@ -532,12 +584,9 @@ static void forward_t(CnnState& c, const float* in, float* out, void* saved, int
   }
   unet_middle<T>(c, d_w, act, batch, n, dtype, nullptr, stream);
   {  // H: 16 -> 1, FP32 output
-    ConvP p{};
-    p.a = act[10]; p.ca = 16; p.lda = 16; p.a_bs = cube(n) * 16;
-    p.n_in = n; p.n_out = n;
-    p.wt = c.wt + c.wt_off[10]; p.bias = d_w + c.b_off[10]; p.cout = 1;
-    p.y = act[11]; p.ldy = 1; p.y_bs = cube(n); p.relu = 0;
-    conv_direct<T, float>(p, KIND_PT, batch, stream);
+    const int64_t nv = (int64_t)batch * cube(n);
+    hipLaunchKernelGGL((k_head16<T>), dim3((unsigned)((nv + BS - 1) / BS)), dim3(BS), 0, stream, (const T*)act[10],
+                       d_w + c.w_off[10], d_w + c.b_off[10], (float*)act[11], nv);
   }
   if (out) hipMemcpyAsync(out, act[11], sizeof(float) * batch * cube(n), hipMemcpyDeviceToDevice, stream);
 }
@@ -772,6 +821,9 @@ void cnn_release(CnnState& c) {
   if (c.wmf) hipFree(c.wmf);
   if (c.act[0]) hipFree(c.act[0]);
   if (c.inv_s) hipFree(c.inv_s);
+  if (c.split) hipFree(c.split);
+  if (c.std_off) hipFree(c.std_off);
+  if (c.std_ones) hipFree(c.std_ones);
   c = CnnState();
 }
 

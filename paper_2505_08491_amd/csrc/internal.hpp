@@ -65,6 +65,13 @@ struct CnnState {
   size_t bwd_bytes = 0;
   void* loss = nullptr;        // loss scratch
   size_t loss_bytes = 0;
+  // stand-alone BF16 forward: the packed input split into its two channels for
+  // the MFMA first layer, with per-sample offsets and unit scales
+  float* split = nullptr;      // [2][batch * n^3]
+  size_t split_n = 0;
+  int64_t* std_off = nullptr;  // [batch] b * n^3
+  double* std_ones = nullptr;  // [batch] 1
+  int std_batch = 0, std_n = 0;
 };
 
 // Jacobi pre/post-smoothing of the neural 3D solve (sweeps = 0: off) and its
