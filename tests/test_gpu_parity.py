@@ -523,3 +523,60 @@ def test_smoothed_precond_bench_config(ctx, bench64):
     ref = krylov.BlockPreconditioner(s, p3)(v[o0:o1].astype(np.float64))
     err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
     assert err <= 5e-2, err
+
+
+# ---------------------------------------------------------------- 128^3 (resolution transfer, 2.15M 3D unknowns)
+
+@pytest.fixture(scope="module")
+def bench128(ctx):
+    """One instance of the 128^3 transfer workload (129^3 grid: the stencil and
+    the 16-channel layers take their general-size kernels)."""
+    P = _P()
+    S = P.System(ctx, synth.workload_transfer(128, 2)[:1], vec_dtype="f32")
+    yield S
+    S.free()
+
+
+def test_spmv_128(ctx, bench128):
+    """y = A x at 129^3 against the host assembly's CSR (itself checked against
+    the oracle at smaller sizes), FP64 on the CPU."""
+    S = bench128
+    rp, col, val = S.export_csr(0)
+    n = rp.size - 1
+    A = sp.csr_matrix((val, col, rp), shape=(n, n))
+    x = synth.fast_normal(17, n).astype(np.float32)
+    y = S.spmv(dev(x, torch.float32)).cpu().double().numpy()
+    ref = A @ x.astype(np.float64)
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) <= 1e-6
+
+
+def test_cnn_forward_129(ctx):
+    """The whole network at 129^3 (BF16): the general-size LDS-tiled stride-1
+    kernels and the global-load edge columns, against the FP64 oracle."""
+    n = 129
+    th = _theta(8)
+    rng = np.random.default_rng(10)
+    X = np.stack([rng.normal(size=(n, n, n)) / n ** 1.5, rng.uniform(0, 0.5, (n, n, n))], axis=-1)
+    y = ctx.cnn_forward(dev(th, torch.float32), dev(X.reshape(1, -1, 2), torch.float32), n, "bf16")
+    y = y.cpu().double().numpy()
+    ref = ocnn.forward(th.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64))[0]
+    err = np.linalg.norm(y[0] - ref.ravel()) / np.linalg.norm(ref)
+    assert err <= 4e-2, err
+
+
+def test_neural_solve_128(ctx, bench128):
+    """The network trained at 32^3 applied unchanged at 129^3: FGMRES(30)
+    reaches the FP64 true relative residual 1e-8 without the fallback."""
+    from paper_2505_08491_amd import weights as W
+    S = bench128
+    wpath = W.default_path()
+    if not __import__("os").path.exists(wpath + ".bin"):
+        pytest.skip("trained weights not present")
+    S.set_preconditioner("neural", weights=W.load(wpath)[0], cnn_dtype="bf16")
+    b = dev(S.rhs(), torch.float64)
+    x = torch.zeros_like(b)
+    st = S.solve_device(b, x, restart=30, max_iters=2000, fallback_max_iters=20000, tol=1e-8, use_graph=True)
+    r = b - S.spmv(x.clone())
+    rel = float(r.norm() / b.norm())
+    print("128^3 neural iterations", st[0]["iters"], "rel", rel)
+    assert st[0]["converged"] and not st[0]["used_fallback"] and rel <= 1e-8
