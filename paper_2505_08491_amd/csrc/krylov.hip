@@ -1431,24 +1431,29 @@ template void launch_spmv<float>(mdnp_sys*, const float*, float*, const InstStat
 template void launch_spmv<double>(mdnp_sys*, const double*, double*, const InstState*, bool, hipStream_t);
 
 // y = A00 x (or A00 (x + x2)) on the 3D rows of the instances on the configured
-// preconditioner (full-length vectors): the stencil sweep, then the 3D coupling
-// rows without their A01 entries.  x2 only where the sweep applies (n <= 128).
+// preconditioner (full-length vectors, 1D parts of y left at zero or
+// untouched): the stencil, then the 3D coupling rows without their A01
+// entries.  x2 only where the stencil sweep applies (n <= 128).
 template <typename T>
 void launch_a00(mdnp_sys* s, const T* x, T* y, const InstState* st, hipStream_t stream, const T* x2) {
   const int n = s->n;
-  if (n > 64 * SW_NX) {  // one thread per row (no masking: y is scratch); x2 not taken here
-    launch_spmv_a00_all<T>(s, x, y, stream);
+  const int mk = st ? 1 : 0;
+  typedef typename std::conditional<sizeof(T) == 8, double, float>::type Tm;
+  const Tm* mv = sizeof(T) == 8 ? (const Tm*)s->d_mval64 : (const Tm*)s->d_mval32;
+  if (n > 64 * SW_NX) {  // one thread per row (1D rows of y get 0); x2 not taken here
+    hipLaunchKernelGGL((k_stencil<T, Tm, 0>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr, x,
+                       (const double*)nullptr, y, s->d_off, s->n, s->n3d, BLK(s), st, mk, (double*)nullptr);
+    hipLaunchKernelGGL((k_mrows<T, Tm, Tm, 4, 3>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream, s->d_mrows,
+                       s->d_mlp, s->d_mcol, mv, x, y, MBLK3(s), st, mk, (double*)nullptr, s->mblk3.nblk, s->d_off,
+                       s->n3d, s->d_m3e, (const T*)nullptr);
     return;
   }
-  const int mk = st ? 1 : 0;
   const int ytiles = (n + SW_TY - 1) / SW_TY;
   int nz = (2048 + ytiles * s->n_inst - 1) / (ytiles * s->n_inst);
   nz = std::max(1, std::min(nz, n));
   const int zc = (n + nz - 1) / nz;
   nz = (n + zc - 1) / zc;
   const dim3 grid(xcd_grid(ytiles * nz * s->n_inst));
-  typedef typename std::conditional<sizeof(T) == 8, double, float>::type Tm;
-  const Tm* mv = sizeof(T) == 8 ? (const Tm*)s->d_mval64 : (const Tm*)s->d_mval32;
   if (x2)
     hipLaunchKernelGGL((k_stencil_sweep<T, Tm, 1>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
                        ytiles, zc, s->n_inst, st, mk, x2);

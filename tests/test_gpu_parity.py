@@ -580,3 +580,28 @@ def test_neural_solve_128(ctx, bench128):
     rel = float(r.norm() / b.norm())
     print("128^3 neural iterations", st[0]["iters"], "rel", rel)
     assert st[0]["converged"] and not st[0]["used_fallback"] and rel <= 1e-8
+
+
+@pytest.mark.parametrize("variant", ["smooth", "inner"])
+def test_3d_solve_variants_batched_129(ctx, variant):
+    """At 129^3 (general-size A00 kernels) the smoothed and the inner-FGMRES
+    preconditioners of instance 1 of a batch of two equal those of the same
+    instance uploaded alone (the concatenated layout, per-instance offsets)."""
+    P = _P()
+    insts = synth.workload_transfer(128, 2)
+    S2 = P.System(ctx, insts, vec_dtype="f32")
+    S1 = P.System(ctx, insts[1:], vec_dtype="f32")
+    th = _theta(9).astype(np.float32)
+    for S in (S2, S1):
+        S.set_preconditioner("neural", weights=th, cnn_dtype="bf16")
+        if variant == "smooth":
+            S.set_smoothing(1, 0.8)
+        else:
+            S.set_inner_steps(2)
+    v = synth.fast_normal(18, S2.ntot).astype(np.float32)
+    o0, o1 = S2.offsets[1], S2.offsets[2]
+    z2 = S2.precond_apply(dev(v, torch.float32)).cpu().double().numpy()[o0:o1]
+    z1 = S1.precond_apply(dev(v[o0:o1].copy(), torch.float32)).cpu().double().numpy()
+    S2.free()
+    S1.free()
+    assert np.linalg.norm(z2 - z1) <= 1e-6 * np.linalg.norm(z1)
