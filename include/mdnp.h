@@ -182,6 +182,19 @@ mdnp_status mdnp_set_smoothing(mdnp_ctx* ctx, mdnp_sys* sys, int32_t sweeps, dou
  * [0, 8]), MDNP_E_STATE (smoothing is on). */
 mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* sys, int32_t steps);
 
+/* Autotuner of the BF16 network's sweep convolutions: for each sweep layer
+ * (L0a, L0b, L1b, L2b, D1, D0) picks the workgroup count of its z split from
+ * {256 .. 2048} by timing whole network applications on this system's batch
+ * and grid with HIP events (coordinate descent, best of 5).  The choice only
+ * moves output planes between workgroups: results are unchanged.  Kept with
+ * the system; `chosen` (nullable, [11], by layer L0a = 0 .. H = 10; 0 = the
+ * built-in default) receives it.  The library allocates two vectors of the
+ * system's size for the timing and frees them before returning.  Errors:
+ * MDNP_E_STATE without a neural preconditioner, MDNP_E_OOM if those buffers
+ * cannot be allocated (the defaults are kept).  No effect for an FP32
+ * network. */
+mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* sys, int32_t* chosen);
+
 /* ---------------------------------------------------------------- solve */
 
 /* Restarted right-preconditioned FGMRES(m) on every instance at once (Section

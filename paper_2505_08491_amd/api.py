@@ -241,6 +241,12 @@ class System:
                                                     w.ctypes.data if w is not None else None, n, alpha,
                                                     DTYPE[cnn_dtype]))
 
+    def autotune(self):
+        """Time and fix the z split of each BF16 sweep layer; returns the choice by layer."""
+        out = (C.c_int32 * 11)()
+        self.ctx._check(lib.mdnp_autotune(self.ctx.h, self.h, out))
+        return list(out)
+
     def set_inner_steps(self, steps: int):
         """Inner FGMRES(steps) 3D solve with the network as preconditioner (0: off)."""
         self.ctx._check(lib.mdnp_set_inner_steps(self.ctx.h, self.h, int(steps)))

@@ -647,6 +647,73 @@ template void cnn_apply_in_solver<float>(mdnp_sys*, const float*, float*, const 
 template void cnn_apply_in_solver<double>(mdnp_sys*, const double*, double*, const InstState*, hipStream_t,
                                           const double*);
 
+// ---------------------------------------------------------------- autotuning
+
+// Chooses the z split of each BF16 sweep layer (the workgroup target of its
+// launch) on the system's own batch and grid: coordinate descent over the
+// layers, each candidate timed as the best of `reps` whole in-solver network
+// applications with HIP events.  The split only decides which workgroup
+// computes which output planes, so results are the same for every choice.
+static const int kTuneLayers[] = {0, 1, 3, 5, 7, 9};
+static const int kTuneTargets[] = {256, 384, 512, 768, 1024, 1536, 2048};
+
+template <typename Tv>
+static bool autotune_t(mdnp_sys* s, hipStream_t stream, int reps) {
+  CnnState& c = s->cnn;
+  Tv* tmp = nullptr;  // [2][ntot]: fixed input, output
+  double* ones = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const size_t nt = (size_t)s->ntot;
+  bool ok = hipMalloc(&tmp, sizeof(Tv) * 2 * nt) == hipSuccess &&
+            hipMalloc(&ones, sizeof(double) * 2 * s->n_inst) == hipSuccess &&
+            hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  if (ok) {
+    std::vector<Tv> h(nt, (Tv)1e-3);
+    std::vector<double> o(2 * (size_t)s->n_inst, 1.0);
+    ok = hipMemcpyAsync(tmp, h.data(), sizeof(Tv) * nt, hipMemcpyHostToDevice, stream) == hipSuccess &&
+         hipMemcpyAsync(ones, o.data(), sizeof(double) * o.size(), hipMemcpyHostToDevice, stream) == hipSuccess &&
+         hipStreamSynchronize(stream) == hipSuccess;
+  }
+  auto time_once = [&]() {
+    float best = 1e30f;
+    for (int r = 0; r < reps; ++r) {
+      (void)hipEventRecord(e0, stream);
+      cnn_apply_in_solver<Tv>(s, tmp, tmp + nt, nullptr, stream, ones);
+      (void)hipEventRecord(e1, stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      best = std::min(best, ms);
+    }
+    return best;
+  };
+  if (ok) {
+    time_once();  // warm-up
+    for (int layer : kTuneLayers) {
+      int best_t = c.sweep_blocks[layer];
+      float best = 1e30f;
+      for (int t : kTuneTargets) {
+        c.sweep_blocks[layer] = t;
+        const float ms = time_once();
+        if (ms < best) {
+          best = ms;
+          best_t = t;
+        }
+      }
+      c.sweep_blocks[layer] = best_t;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (tmp) (void)hipFree(tmp);
+  if (ones) (void)hipFree(ones);
+  return ok;
+}
+
+bool cnn_autotune(mdnp_sys* s, hipStream_t stream, int reps) {
+  return s->vec_dtype == MDNP_F64 ? autotune_t<double>(s, stream, reps) : autotune_t<float>(s, stream, reps);
+}
+
 // ---------------------------------------------------------------- backward
 
 namespace {

@@ -623,6 +623,11 @@ struct RowsTile {
 constexpr int kSweepBlocksD0 = 256;
 constexpr int kSweepBlocksL2b = 384;
 
+// The autotuned target of `layer` if set, else the default.
+inline int sweep_target(const CnnState& c, int layer, int dflt) {
+  return c.sweep_blocks[layer] > 0 ? c.sweep_blocks[layer] : dflt;
+}
+
 struct RowsGrid {
   int ylo = 0, yhi = 0, zlo = 0, zhi = 0;  // output rows / planes computed
   int zc = 0, ytiles = 0;
@@ -1451,7 +1456,7 @@ void launch_rows16_npf(const MfmaArgs& a, const RowsGrid& q, int batch, size_t l
 }
 
 template <int CA, int CB, int MB, int IN, int EPI, typename Tv, int NPF0, int NPF1>
-void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream) {
+void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream, int target = 1024) {
   constexpr int CL = IN ? 2 : CA + CB;
   typedef RowsTile<CL, IN> T;
   const int n = a.n_out;
@@ -1469,7 +1474,7 @@ void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream) {
   q.ytiles = (q.yhi - q.ylo + MB - 1) / MB;
   const int planes = q.zhi - q.zlo;
   // about four workgroups per compute unit over the batch
-  int nz = (1024 + q.ytiles * batch - 1) / (q.ytiles * batch);
+  int nz = (target + q.ytiles * batch - 1) / (q.ytiles * batch);
   nz = std::max(1, std::min(nz, planes));
   q.zc = (planes + nz - 1) / nz;
   // the x = n - 1 column in extra workgroups (not needed with the head: Dirichlet)
@@ -1742,7 +1747,7 @@ void conv_mfma_in0(const CnnState& c, const Tv* z, const int64_t* off, const dou
   a.inv_s = inv_s;
   a.dist = dist;
   (void)nmb;
-  launch_rows16<0, 0, 5, 1, 0, Tv, 2, 4>(a, batch, stream);
+  launch_rows16<0, 0, 5, 1, 0, Tv, 2, 4>(a, batch, stream, sweep_target(c, 0, 1024));
 }
 template void conv_mfma_in0<float>(const CnnState&, const float*, const int64_t*, const double*, const float*, int,
                                    int, bf16*, const InstState*, hipStream_t);
@@ -1775,7 +1780,7 @@ void conv_mfma_d0_head(const CnnState& c, const bf16* u0, const bf16* s0, int n,
   a.alpha_override = alpha_override;
   a.scale = scale;
   (void)nmb;
-  launch_ks16<16, 16, 4, 1, 1, Tv>(a, batch, stream, kSweepBlocksD0);
+  launch_ks16<16, 16, 4, 1, 1, Tv>(a, batch, stream, sweep_target(c, 9, kSweepBlocksD0));
 }
 template void conv_mfma_d0_head<float>(const CnnState&, const bf16*, const bf16*, int, int, float*, const int64_t*,
                                        const double*, double, const double*, const InstState*, hipStream_t);
@@ -1792,28 +1797,28 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_l0b;
       a.zero16 = mfma_extra(c).zeros;
-      launch_ks16<16, 0, 4, 0, 0, float>(a, batch, stream);
+      launch_ks16<16, 0, 4, 0, 0, float>(a, batch, stream, sweep_target(c, 1, 1024));
       break;
     }
     case 2: launch_conv<16, 0, 32, 2, 4>(p, batch, w, stream); break;    // L1a
     case 3: {                                                             // L1b
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_l1b;
-      launch_convw<32, 0, 32, 3, 4, 2>(a, batch, stream);
+      launch_convw<32, 0, 32, 3, 4, 2>(a, batch, stream, sweep_target(c, 3, 1024));
       break;
     }
     case 4: launch_conv<32, 0, 64, 2, 2>(p, batch, w, stream); break;    // L2a
     case 5: {                                                             // L2b
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_l2b;
-      launch_convw<64, 0, 64, 2, 8, 2>(a, batch, stream, kSweepBlocksL2b);
+      launch_convw<64, 0, 64, 2, 8, 2>(a, batch, stream, sweep_target(c, 5, kSweepBlocksL2b));
       break;
     }
     case 6: launch_tconv_all<64, 32, 1>(p, batch, mfma_extra(c).tf_u1, stream); break;  // U1
     case 7: {                                                             // D1
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_d1;
-      launch_convw<32, 32, 32, 3, 4, 3>(a, batch, stream);
+      launch_convw<32, 32, 32, 3, 4, 3>(a, batch, stream, sweep_target(c, 7, 1024));
       break;
     }
     case 8: launch_tconv_all<32, 16, 2>(p, batch, mfma_extra(c).tf_u0, stream); break;  // U0

@@ -72,6 +72,9 @@ struct CnnState {
   int64_t* std_off = nullptr;  // [batch] b * n^3
   double* std_ones = nullptr;  // [batch] 1
   int std_batch = 0, std_n = 0;
+  // workgroups aimed at by the z split of each sweep layer (0: built-in
+  // default); set by the autotuner, indexed by layer (L0a = 0 .. D0 = 9)
+  int sweep_blocks[11] = {};
 };
 
 // Jacobi pre/post-smoothing of the neural 3D solve (sweeps = 0: off) and its

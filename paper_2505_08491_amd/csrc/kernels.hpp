@@ -104,6 +104,10 @@ void cnn_backward_batch(CnnState& c, const void* saved, const float* dy, float* 
 template <typename T>
 void cnn_apply_in_solver(mdnp_sys* s, const T* zin, T* z, const InstState* st, hipStream_t stream,
                          const double* scales = nullptr);
+// Per-layer z split of the BF16 sweep convolutions chosen by timing on the
+// system's batch and grid (CnnState::sweep_blocks); false if its timing
+// buffers or events could not be created (the defaults are then kept).
+bool cnn_autotune(mdnp_sys* s, hipStream_t stream, int reps);
 void cnn_release(CnnState& c);
 void launch_loss_grad(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u,
                       float* du, double* loss, hipStream_t stream);
