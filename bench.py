@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--inner-steps", type=int, default=3,
                     help="inner FGMRES steps of the extra inner-solve run (0: skip it)")
     ap.add_argument("--autotune", type=int, default=1,
-                    help="time and fix the z split of each BF16 sweep layer before the timed solves (0: defaults)")
+                    help="time and fix the launch shapes (SpMV sweep, BF16 sweep layers) before the timed solves (0: defaults)")
     ap.add_argument("--cpu-neural-iters", type=int, default=3)
     ap.add_argument("--cpu-jacobi-iters", type=int, default=50)
     return ap.parse_args()
@@ -209,7 +209,7 @@ def main():
 
     S.set_preconditioner("neural", weights=w, cnn_dtype=a.cnn_dtype)
     tuned, t_tune = None, 0.0
-    if a.autotune and a.cnn_dtype == "bf16":
+    if a.autotune:
         t0 = time.time()
         tuned = S.autotune()
         t_tune = time.time() - t0
@@ -322,7 +322,7 @@ def main():
                  "frac": cnn_flop / (ms_cnn * 1e-3) / 1e12 / BF16_PEAK_TFLOPS},
         "preconditioner": {"ms_per_apply": ms_prec, "cnn_tflops": cnn_flop / (ms_prec * 1e-3) / 1e12},
         "upload_s": t_upload,
-        "autotune": {"sweep_blocks": tuned, "s": t_tune} if tuned else None,
+        "autotune": {"conv_sweep_blocks": tuned[:11], "spmv_sweep_target": tuned[11], "s": t_tune} if tuned else None,
     }
     if not a.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(insts[0], float(np.mean(neural_iters)),

@@ -182,17 +182,20 @@ mdnp_status mdnp_set_smoothing(mdnp_ctx* ctx, mdnp_sys* sys, int32_t sweeps, dou
  * [0, 8]), MDNP_E_STATE (smoothing is on). */
 mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* sys, int32_t steps);
 
-/* Autotuner of the BF16 network's sweep convolutions: for each sweep layer
- * (L0a, L0b, L1b, L2b, D1, D0) picks the workgroup count of its z split from
- * {256 .. 2048} by timing whole network applications on this system's batch
- * and grid with HIP events (coordinate descent, best of 5).  The choice only
- * moves output planes between workgroups: results are unchanged.  Kept with
- * the system; `chosen` (nullable, [11], by layer L0a = 0 .. H = 10; 0 = the
- * built-in default) receives it.  The library allocates two vectors of the
- * system's size for the timing and frees them before returning.  Errors:
- * MDNP_E_STATE without a neural preconditioner, MDNP_E_OOM if those buffers
- * cannot be allocated (the defaults are kept).  No effect for an FP32
- * network. */
+/* Autotuner of the launch shapes, timed on this system's own batch and grid
+ * with HIP events: the wave count that the stencil sweep of the SpMV splits
+ * its z range for (from {1024 .. 6144}; best of three batches of 20 SpMVs),
+ * and, with a BF16 neural preconditioner set, the workgroup count of the z
+ * split of each sweep convolution (L0a, L0b, L1b, L2b, D1, D0; from
+ * {256 .. 2048}; coordinate descent, best of 5 whole network applications).
+ * The choices only move output planes between waves and workgroups: results
+ * are unchanged.  They are kept with the system; `chosen` (nullable, [12])
+ * receives them: [0 .. 10] the convolution layers L0a = 0 .. H = 10 (0 = the
+ * built-in default), [11] the SpMV sweep target (0 = default; also 0 where
+ * the grid has more than 65 nodes per side and no sweep is used).  The library
+ * allocates two vectors of the system's size for the timing and frees them
+ * before returning.  Errors: MDNP_E_OOM if those buffers cannot be allocated
+ * (the defaults are kept). */
 mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* sys, int32_t* chosen);
 
 /* ---------------------------------------------------------------- solve */

@@ -242,8 +242,9 @@ class System:
                                                     DTYPE[cnn_dtype]))
 
     def autotune(self):
-        """Time and fix the z split of each BF16 sweep layer; returns the choice by layer."""
-        out = (C.c_int32 * 11)()
+        """Time and fix the launch shapes: the z split of each BF16 sweep layer
+        ([0..10], by layer) and of the SpMV stencil sweep ([11])."""
+        out = (C.c_int32 * 12)()
         self.ctx._check(lib.mdnp_autotune(self.ctx.h, self.h, out))
         return list(out)
 

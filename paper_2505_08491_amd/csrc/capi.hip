@@ -735,19 +735,22 @@ extern "C" mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* s, int32_t* chosen
   if (!ctx) return MDNP_E_ARG;
   return guarded(ctx, [&] {
     if (!s) fail(MDNP_E_ARG, "null system");
-    if (s->kind != MDNP_PREC_NEURAL || !s->prec_set) fail(MDNP_E_STATE, "set a neural preconditioner first");
     HIPCHK(hipSetDevice(ctx->device));
-    if (s->work.graph) {
+    if (s->work.graph) {  // captured with the old launch shapes
       (void)hipGraphExecDestroy(s->work.graph);
       s->work.graph = nullptr;
       s->work.graph_m = -1;
     }
-    if (s->cnn.dtype == MDNP_BF16 && !cnn_autotune(s, ctx->stream, 5))
+    if (!spmv_autotune(s, ctx->stream)) fail(MDNP_E_OOM, "autotune: could not allocate its timing buffers");
+    const bool net = s->kind == MDNP_PREC_NEURAL && s->prec_set && s->cnn.dtype == MDNP_BF16;
+    if (net && !cnn_autotune(s, ctx->stream, 5))
       fail(MDNP_E_OOM, "autotune: could not allocate its timing buffers");
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    if (chosen)
+    if (chosen) {
       for (int l = 0; l < 11; ++l) chosen[l] = s->cnn.sweep_blocks[l];
+      chosen[11] = s->sweep_target;
+    }
   });
 }
 

@@ -146,6 +146,7 @@ struct mdnp_sys {
   // operator A = S + M: S the constant 27-point stencil of the free 3D nodes
   // (unit rows on the Dirichlet nodes), M the coupling / 1D part in CSR
   double* d_stencil = nullptr;     // [n_inst * 4] stencil value by differing coordinates
+  int sweep_target = 0;            // workgroups aimed at by the stencil sweep's z split (0: 2048)
   int32_t* d_mptr = nullptr;       // [ntot + 1], global entry offsets
   int32_t* d_mcol = nullptr;       // global column indices
   double* d_mval64 = nullptr;

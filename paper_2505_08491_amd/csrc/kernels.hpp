@@ -108,6 +108,9 @@ void cnn_apply_in_solver(mdnp_sys* s, const T* zin, T* z, const InstState* st, h
 // system's batch and grid (CnnState::sweep_blocks); false if its timing
 // buffers or events could not be created (the defaults are then kept).
 bool cnn_autotune(mdnp_sys* s, hipStream_t stream, int reps);
+// Wave count of the stencil sweep's z split chosen by timing the batched SpMV
+// (mdnp_sys::sweep_target); false if its buffers or events could not be made.
+bool spmv_autotune(mdnp_sys* s, hipStream_t stream);
 void cnn_release(CnnState& c);
 void launch_loss_grad(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u,
                       float* du, double* loss, hipStream_t stream);

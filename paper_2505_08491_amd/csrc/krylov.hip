@@ -152,109 +152,143 @@ __device__ __forceinline__ Tacc stencil_row(const Tv* __restrict__ x, int64_t ba
   return (Tacc)st4[0] * grp[0] + (Tacc)st4[1] * grp[1] + (Tacc)st4[2] * grp[2] + (Tacc)st4[3] * grp[3];
 }
 
-// y = S x on the 3D rows, sweeping z.  A block owns rows y0 .. y0 + SW_TY - 1
-// of planes z0 .. z0 + zc - 1 of one instance.  Each input plane z' is staged
-// in LDS over rows y0 - 1 .. y0 + SW_TY with Dirichlet nodes and the outside
-// set to zero (their columns are eliminated), and reduced once to its 2D
-// partials per node: centre, the 4 in-plane face neighbours and the 4
-// in-plane corners.  Output plane z gathers them from z' = z (offsets 0, 1, 2
-// differing coordinates) and z' = z +- 1 (1, 2, 3), so two accumulators ride
-// along the sweep.  Dirichlet rows copy x.  The next plane's values are
-// loaded into registers while the current one is reduced.
-constexpr int SW_TY = 4;          // output rows per block
-constexpr int SW_NX = 2;          // x positions per thread: n <= 128
+// y = S x on the 3D rows, sweeping z, for n <= SW_NMAX nodes per side.  A
+// wave owns rows y0 .. y0 + SW_TY - 1 of planes z0 .. z0 + zc - 1 of one
+// instance, lane l holding column x = l + 1 (the interior columns and the
+// x = n - 1 boundary column).  For every input plane z' it loads rows
+// y0 - 1 .. y0 + SW_TY, zeroes the nodes on the Dirichlet boundary (their
+// columns are eliminated), takes the x-neighbour sums by lane shifts and forms
+// per output row the 2D partials centre, 4 in-plane faces and 4 in-plane
+// corners.  Output plane z gathers them from z' = z (offsets 0, 1, 2 differing
+// coordinates) and z' = z +- 1 (1, 2, 3), so two accumulators per row ride
+// along the sweep.  Dirichlet rows copy x.  Planes are loaded SW_PD steps ahead
+// into a ring of register sets; the loop is unrolled over the ring, so no set
+// is copied and a step waits only for its own plane.  No LDS, no barriers.
+// The x = 0 boundary column is copied by extra waves of the same launch
+// (the first tile ids, one per instance and SW_FZ planes).
+constexpr int SW_TY = 5;      // output rows per wave
+constexpr int SW_PD = 3;      // planes in flight (register sets)
+constexpr int SW_FZ = 8;      // planes per x = 0 copy wave
+constexpr int SW_NMAX = 65;   // lane l <-> column l + 1
+
+__device__ __forceinline__ float lane_from_left(float v) {  // value of lane l - 1 (0 for lane 0)
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_from_right(float v) {  // value of lane l + 1 (0 for lane 63)
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double lane_from_left(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x138, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_from_right(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x130, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
 
 template <typename Tv, typename Tacc, int SUM = 0>
 __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict__ stencil, const Tv* __restrict__ x,
                                                        Tv* __restrict__ y, const int64_t* __restrict__ off, int n,
-                                                       int ytiles, int zc, int n_inst, const InstState* st,
+                                                       int ytiles, int zc, int nface, int ntile, const InstState* st,
                                                        int mask, const Tv* __restrict__ x2 = nullptr) {
-  __shared__ Tacc pl[2][SW_TY + 2][130];
-  const int nz = (n + zc - 1) / zc;
-  const int lb = xcd_logical_block(n_inst * ytiles * nz);
+  constexpr int NR = SW_TY + 2;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int lb = xcd_logical_block((ntile + 3) >> 2);
   if (lb < 0) return;
-  const int i = lb / (ytiles * nz), tile = lb - i * (ytiles * nz);
-  if (mask && !st[i].active) return;
-  const int y0 = (tile % ytiles) * SW_TY;
-  const int z0 = (tile / ytiles) * zc;
-  const int zend = min(n, z0 + zc);
+  const int tid = lb * 4 + wave;
+  if (tid >= ntile) return;
   const int64_t nn = (int64_t)n * n;
+  if (tid < nface) {  // x = 0 column of planes zf .. zf + SW_FZ - 1
+    const int nzf = (n + SW_FZ - 1) / SW_FZ;
+    const int i = tid / nzf, zf = (tid - i * nzf) * SW_FZ;
+    if (mask && !st[i].active) return;
+    const Tv* X = x + off[i];
+    const Tv* X2 = SUM ? x2 + off[i] : nullptr;
+    Tv* Y = y + off[i];
+    for (int z = zf; z < min(n, zf + SW_FZ); ++z)
+      for (int gy = lane; gy < n; gy += 64) {
+        const int64_t v = z * nn + (int64_t)gy * n;
+        Y[v] = SUM ? (Tv)((Tacc)X[v] + (Tacc)X2[v]) : X[v];
+      }
+    return;
+  }
+  const int nz = (n + zc - 1) / zc;
+  const int t0 = tid - nface;
+  const int i = t0 / (ytiles * nz), rem = t0 - i * (ytiles * nz);
+  if (mask && !st[i].active) return;
+  const int y0 = (rem % ytiles) * SW_TY, z0 = (rem / ytiles) * zc;
+  const int zend = min(n, z0 + zc);
   const Tv* X = x + off[i];
   const Tv* X2 = SUM ? x2 + off[i] : nullptr;  // SUM = 1: S (x + x2)
   Tv* Y = y + off[i];
   const Tacc w0 = (Tacc)stencil[4 * i], w1 = (Tacc)stencil[4 * i + 1], w2 = (Tacc)stencil[4 * i + 2],
              w3 = (Tacc)stencil[4 * i + 3];
-  const int t = threadIdx.x;
-  const int row = t >> 6, lx = t & 63;      // output row of the tile, first x
-  // plane staging: item q = r * n + xx over rows y0 - 1 .. y0 + SW_TY
-  const int items = (SW_TY + 2) * n;
-  constexpr int NLD = ((SW_TY + 2) * 128 + 255) / 256;
-  auto load = [&](int zp, Tacc (&v)[NLD]) {
+  const int xx = lane + 1;
+  const bool xact = xx <= n - 1, xin = xx <= n - 2;
+  // byte offsets of this lane's node in the rows y0 - 1 .. y0 + SW_TY of a
+  // plane (clamped into the grid; 32-bit, so the loads take a scalar base)
+  unsigned roff[NR];
+  bool rin[NR];
 #pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-      const int q = t + k * 256;
-      Tacc a = 0;
-      if (q < items && zp > 0 && zp < n - 1) {
-        const int r = q / n, xx = q - r * n, gy = y0 + r - 1;
-        if (gy > 0 && gy < n - 1 && xx > 0 && xx < n - 1) {
-          const int64_t vq = zp * nn + (int64_t)gy * n + xx;
-          a = SUM ? (Tacc)X[vq] + (Tacc)X2[vq] : (Tacc)X[vq];
+  for (int r = 0; r < NR; ++r) {
+    const int gy = y0 - 1 + r;
+    rin[r] = gy >= 1 && gy <= n - 2;
+    roff[r] = (unsigned)(min(max(gy, 0), n - 1) * n + min(xx, n - 1)) * (unsigned)sizeof(Tv);
+  }
+  Tv v[SW_PD][NR], v2[SUM ? SW_PD : 1][NR];
+  auto load = [&](int zp, int K) {
+    const int64_t zb = (int64_t)min(max(zp, 0), n - 1) * nn;
+    const char* P = (const char*)(X + zb);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[K][r] = *(const Tv*)(P + roff[r]);
+    if (SUM) {
+      const char* P2 = (const char*)(X2 + zb);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) v2[SUM ? K : 0][r] = *(const Tv*)(P2 + roff[r]);
+    }
+  };
+  Tacc accp[SW_TY], accc[SW_TY], prev[SW_TY];  // partial outputs of planes zp - 1, zp; raw plane zp - 1
+#pragma unroll
+  for (int t = 0; t < SW_TY; ++t) accp[t] = accc[t] = prev[t] = 0;
+  const int nsteps = zend - z0 + 2;  // step s reduces input plane zp = z0 - 1 + s
+#pragma unroll
+  for (int K = 0; K < SW_PD; ++K) load(z0 - 1 + K, K);
+  for (int s0 = 0; s0 < nsteps; s0 += SW_PD) {
+#pragma unroll
+    for (int K = 0; K < SW_PD; ++K) {
+      const int s = s0 + K;
+      const int zp = z0 - 1 + s;
+      const bool zin = zp >= 1 && zp <= n - 2;
+      Tacc raw[NR], u[NR], sx[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        raw[r] = (Tacc)v[K][r];
+        if (SUM) raw[r] += (Tacc)v2[SUM ? K : 0][r];
+        u[r] = zin && rin[r] && xin ? raw[r] : (Tacc)0;  // interior nodes only
+        sx[r] = lane_from_left(u[r]) + lane_from_right(u[r]);
+      }
+      const int zo = zp - 1;  // output plane completed in this step
+      const bool st_ok = s < nsteps && zo >= z0;
+      const bool bz = zo == 0 || zo == n - 1;
+#pragma unroll
+      for (int t = 0; t < SW_TY; ++t) {
+        const int r = t + 1;
+        const Tacc c = u[r], f = u[r - 1] + u[r + 1] + sx[r], e = sx[r - 1] + sx[r + 1];
+        const Tacc up = w1 * c + w2 * f + w3 * e;   // contribution to the planes zp - 1 and zp + 1
+        const Tacc mid = w0 * c + w1 * f + w2 * e;  // contribution to plane zp
+        const int gy = y0 + t;
+        if (st_ok && gy < n && xact) {
+          const bool bnd = bz || gy == 0 || gy == n - 1 || !xin;  // Dirichlet row: copy
+          Y[zo * nn + (int64_t)gy * n + xx] = (Tv)(bnd ? prev[t] : accp[t] + up);
         }
+        accp[t] = accc[t] + mid;  // output plane zp: planes zp - 1 and zp so far
+        accc[t] = up;             // output plane zp + 1: plane zp so far
+        prev[t] = raw[r];
       }
-      v[k] = a;
+      load(zp + SW_PD, K);
     }
-  };
-  auto store = [&](int buf, const Tacc (&v)[NLD]) {
-#pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-      const int q = t + k * 256;
-      if (q < items) {
-        const int r = q / n, xx = q - r * n;
-        pl[buf][r][xx + 1] = v[k];
-      }
-    }
-    if (t < SW_TY + 2) {  // x halo columns
-      pl[buf][t][0] = 0;
-      pl[buf][t][n + 1] = 0;
-    }
-  };
-  Tacc accp[SW_NX], accc[SW_NX];  // partial outputs of planes zp - 1 and zp on entry to step zp
-#pragma unroll
-  for (int k = 0; k < SW_NX; ++k) accp[k] = accc[k] = 0;
-  // registers hold the next two planes: va = zp, vb = zp + 1 on entry to step zp
-  Tacc va[NLD], vb[NLD];
-  load(z0 - 1, va);
-  load(z0, vb);
-  const int gyo = y0 + row;
-  for (int zp = z0 - 1; zp <= zend; ++zp) {
-    const int buf = (zp - z0 + 1) & 1;
-    store(buf, va);
-#pragma unroll
-    for (int k = 0; k < NLD; ++k) va[k] = vb[k];
-    __syncthreads();
-    if (zp + 1 < zend) load(zp + 2, vb);
-#pragma unroll
-    for (int k = 0; k < SW_NX; ++k) {
-      const int xx = lx + 64 * k;
-      if (xx >= n) continue;
-      // 2D partials of plane zp at (gyo, xx)
-      const Tacc c = pl[buf][row + 1][xx + 1];
-      const Tacc f = pl[buf][row][xx + 1] + pl[buf][row + 2][xx + 1] + pl[buf][row + 1][xx] + pl[buf][row + 1][xx + 2];
-      const Tacc e = pl[buf][row][xx] + pl[buf][row][xx + 2] + pl[buf][row + 2][xx] + pl[buf][row + 2][xx + 2];
-      const Tacc up = w1 * c + w2 * f + w3 * e;   // contribution to the planes zp - 1 and zp + 1
-      const Tacc mid = w0 * c + w1 * f + w2 * e;  // contribution to plane zp
-      // output plane zp - 1 is complete
-      const int zo = zp - 1;
-      if (zo >= z0 && gyo < n) {
-        const int64_t v_ = zo * nn + (int64_t)gyo * n + xx;
-        const bool bnd = zo == 0 || zo == n - 1 || gyo == 0 || gyo == n - 1 || xx == 0 || xx == n - 1;
-        if (bnd) Y[v_] = SUM ? (Tv)((Tacc)X[v_] + (Tacc)X2[v_]) : X[v_];
-        else Y[v_] = (Tv)(accp[k] + up);
-      }
-      accp[k] = accc[k] + mid;  // output plane zp: planes zp - 1 and zp so far
-      accc[k] = up;             // output plane zp + 1: plane zp so far
-    }
-    __syncthreads();
   }
 }
 
@@ -1390,11 +1424,30 @@ __global__ void __launch_bounds__(BS) k_update_x(const T* __restrict__ Z, int64_
 #define MBLK(s) (s)->mblk.inst, (s)->mblk.start, (s)->mblk.end
 #define MBLK3(s) (s)->mblk3.inst, (s)->mblk3.start, (s)->mblk3.end
 
+// The stencil sweep over the batch: waves of SW_TY rows x a z range, the z
+// split aimed at s->sweep_target waves (default 2048), plus the x = 0 copy
+// waves.  Only for n <= SW_NMAX.
+template <typename T, int SUM>
+void launch_sweep(mdnp_sys* s, const T* x, T* y, const T* x2, const InstState* st, int mk, hipStream_t stream) {
+  const int n = s->n;
+  const int ytiles = (n + SW_TY - 1) / SW_TY;
+  const int target = s->sweep_target > 0 ? s->sweep_target : 2048;
+  int nz = (target + ytiles * s->n_inst - 1) / (ytiles * s->n_inst);
+  nz = std::max(1, std::min(nz, n));
+  const int zc = (n + nz - 1) / nz;
+  nz = (n + zc - 1) / zc;
+  const int nface = s->n_inst * ((n + SW_FZ - 1) / SW_FZ);
+  const int ntile = nface + ytiles * nz * s->n_inst;
+  const dim3 grid(xcd_grid((ntile + 3) / 4));
+  hipLaunchKernelGGL((k_stencil_sweep<T, T, SUM>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
+                     ytiles, zc, nface, ntile, st, mk, x2);
+}
+
 template <typename T>
 void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, hipStream_t stream) {
   const int mk = mask ? 1 : 0;
   const int n = s->n;
-  if (n > 64 * SW_NX) {  // one thread per row
+  if (n > SW_NMAX) {  // one thread per row
     if (sizeof(T) == 8) {
       hipLaunchKernelGGL((k_stencil<T, double, 0>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr,
                          x, (const double*)nullptr, y, s->d_off, s->n, s->n3d, BLK(s), st, mk, (double*)nullptr);
@@ -1408,21 +1461,12 @@ void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, 
     }
     return;
   }
-  const int ytiles = (n + SW_TY - 1) / SW_TY;
-  // about eight blocks per compute unit over the batch
-  int nz = (2048 + ytiles * s->n_inst - 1) / (ytiles * s->n_inst);
-  nz = std::max(1, std::min(nz, n));
-  const int zc = (n + nz - 1) / nz;
-  nz = (n + zc - 1) / zc;
-  const dim3 grid(xcd_grid(ytiles * nz * s->n_inst));
   if (sizeof(T) == 8) {
-    hipLaunchKernelGGL((k_stencil_sweep<T, double>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, s->n_inst, st, mk);
+    launch_sweep<T, 0>(s, x, y, (const T*)nullptr, st, mk, stream);
     hipLaunchKernelGGL((k_mrows<T, double, double, 4, 2>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
                        s->d_mlp, s->d_mcol, s->d_mval64, x, y, MBLK(s), st, mk, (double*)nullptr, s->mblk.nblk, s->d_off, s->n3d);
   } else {
-    hipLaunchKernelGGL((k_stencil_sweep<T, float>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, s->n_inst, st, mk);
+    launch_sweep<T, 0>(s, x, y, (const T*)nullptr, st, mk, stream);
     hipLaunchKernelGGL((k_mrows<T, float, float, 4, 2>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
                        s->d_mlp, s->d_mcol, s->d_mval32, x, y, MBLK(s), st, mk, (double*)nullptr, s->mblk.nblk, s->d_off, s->n3d);
   }
@@ -1430,17 +1474,62 @@ void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, 
 template void launch_spmv<float>(mdnp_sys*, const float*, float*, const InstState*, bool, hipStream_t);
 template void launch_spmv<double>(mdnp_sys*, const double*, double*, const InstState*, bool, hipStream_t);
 
+// Chooses s->sweep_target (the wave count the stencil sweep's z split aims at)
+// by timing batches of back-to-back SpMV launches on the system itself with
+// HIP events (best of three batches of 20 per candidate).  The split only
+// moves output planes between waves: y is the same for every choice.
+template <typename T>
+static bool spmv_autotune_t(mdnp_sys* s, hipStream_t stream) {
+  static const int kTargets[] = {1024, 1536, 2048, 3072, 4096, 6144};
+  T* buf = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const size_t nt = (size_t)s->ntot;
+  bool ok = hipMalloc(&buf, sizeof(T) * 2 * nt) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+            hipEventCreate(&e1) == hipSuccess &&
+            hipMemsetAsync(buf, 0, sizeof(T) * 2 * nt, stream) == hipSuccess;
+  if (ok) {
+    int best_t = s->sweep_target;
+    float best = 1e30f;
+    for (int target : kTargets) {
+      s->sweep_target = target;
+      launch_spmv<T>(s, buf, buf + nt, nullptr, false, stream);  // warm-up
+      for (int rep = 0; rep < 3; ++rep) {
+        (void)hipEventRecord(e0, stream);
+        for (int k = 0; k < 20; ++k) launch_spmv<T>(s, buf, buf + nt, nullptr, false, stream);
+        (void)hipEventRecord(e1, stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          best_t = target;
+        }
+      }
+    }
+    s->sweep_target = best_t;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (buf) (void)hipFree(buf);
+  return ok;
+}
+
+bool spmv_autotune(mdnp_sys* s, hipStream_t stream) {
+  if (s->n > SW_NMAX) return true;  // no sweep at this size
+  return s->vec_dtype == MDNP_F64 ? spmv_autotune_t<double>(s, stream) : spmv_autotune_t<float>(s, stream);
+}
+
 // y = A00 x (or A00 (x + x2)) on the 3D rows of the instances on the configured
 // preconditioner (full-length vectors, 1D parts of y left at zero or
 // untouched): the stencil, then the 3D coupling rows without their A01
-// entries.  x2 only where the stencil sweep applies (n <= 128).
+// entries.  x2 only where the stencil sweep applies (n <= SW_NMAX).
 template <typename T>
 void launch_a00(mdnp_sys* s, const T* x, T* y, const InstState* st, hipStream_t stream, const T* x2) {
   const int n = s->n;
   const int mk = st ? 1 : 0;
   typedef typename std::conditional<sizeof(T) == 8, double, float>::type Tm;
   const Tm* mv = sizeof(T) == 8 ? (const Tm*)s->d_mval64 : (const Tm*)s->d_mval32;
-  if (n > 64 * SW_NX) {  // one thread per row (1D rows of y get 0); x2 not taken here
+  if (n > SW_NMAX) {  // one thread per row (1D rows of y get 0); x2 not taken here
     hipLaunchKernelGGL((k_stencil<T, Tm, 0>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr, x,
                        (const double*)nullptr, y, s->d_off, s->n, s->n3d, BLK(s), st, mk, (double*)nullptr);
     hipLaunchKernelGGL((k_mrows<T, Tm, Tm, 4, 3>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream, s->d_mrows,
@@ -1448,18 +1537,8 @@ void launch_a00(mdnp_sys* s, const T* x, T* y, const InstState* st, hipStream_t 
                        s->n3d, s->d_m3e, (const T*)nullptr);
     return;
   }
-  const int ytiles = (n + SW_TY - 1) / SW_TY;
-  int nz = (2048 + ytiles * s->n_inst - 1) / (ytiles * s->n_inst);
-  nz = std::max(1, std::min(nz, n));
-  const int zc = (n + nz - 1) / nz;
-  nz = (n + zc - 1) / zc;
-  const dim3 grid(xcd_grid(ytiles * nz * s->n_inst));
-  if (x2)
-    hipLaunchKernelGGL((k_stencil_sweep<T, Tm, 1>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, s->n_inst, st, mk, x2);
-  else
-    hipLaunchKernelGGL((k_stencil_sweep<T, Tm>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, s->n_inst, st, mk, (const T*)nullptr);
+  if (x2) launch_sweep<T, 1>(s, x, y, x2, st, mk, stream);
+  else launch_sweep<T, 0>(s, x, y, (const T*)nullptr, st, mk, stream);
   hipLaunchKernelGGL((k_mrows<T, Tm, Tm, 4, 3>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream, s->d_mrows,
                      s->d_mlp, s->d_mcol, mv, x, y, MBLK3(s), st, mk, (double*)nullptr, s->mblk3.nblk, s->d_off,
                      s->n3d, s->d_m3e, x2);
@@ -1498,7 +1577,7 @@ void launch_smooth_post(mdnp_sys* s, T* z, const InstState* st, hipStream_t stre
   const T* sb = (const T*)m.sb;
   const T* sr = (const T*)m.sr;
   T* t = (T*)m.t;
-  if (s->n > 64 * SW_NX) {  // without the sweep: z += sr first
+  if (s->n > SW_NMAX) {  // without the sweep: z += sr first
     hipLaunchKernelGGL((k_vec_add3d<T>), dim3(s->blk3.nblk), dim3(BS), 0, stream, z, sr, s->d_off, BLK3(s), st);
     sr = nullptr;
   }

@@ -278,8 +278,12 @@ def test_smoothing_rejects_bad_arguments(ctx):
     for steps in (-1, 9):
         with pytest.raises(Exception):
             S.set_inner_steps(steps)
-    with pytest.raises(Exception):
-        S.autotune()  # needs the neural preconditioner
+    # without a network only the SpMV sweep is tuned; y does not change
+    x = dev(synth.fast_normal(21, S.ntot), torch.float32)
+    y0 = S.spmv(x).clone()
+    chosen = S.autotune()
+    assert chosen[11] in (1024, 1536, 2048, 3072, 4096, 6144) and not any(chosen[:11]), chosen
+    assert torch.equal(S.spmv(x), y0)
     S.free()
 
 
@@ -528,9 +532,10 @@ def test_smoothed_precond_bench_config(ctx, bench64):
 
 
 def test_autotune_keeps_preconditioner_output(ctx, bench64):
-    """The autotuner only moves output planes between workgroups: Q(v) at the
-    benchmark size is bit-identical before and after tuning, and a solve still
-    runs (its captured graph is rebuilt with the tuned launches)."""
+    """The autotuner only moves output planes between waves and workgroups:
+    Q(v) and A v at the benchmark size are bit-identical before and after
+    tuning, and a solve still runs (its captured graph is rebuilt with the
+    tuned launches)."""
     from paper_2505_08491_amd import weights as W
     S, _, systems = bench64
     wpath = W.default_path()
@@ -538,11 +543,14 @@ def test_autotune_keeps_preconditioner_output(ctx, bench64):
     S.set_preconditioner("neural", weights=th, cnn_dtype="bf16")
     v = dev(synth.fast_normal(16, S.ntot).astype(np.float32), torch.float32)
     z0 = S.precond_apply(v).clone()
+    y0 = S.spmv(v).clone()
     chosen = S.autotune()
     for layer in (0, 1, 3, 5, 7, 9):
         assert chosen[layer] in (256, 384, 512, 768, 1024, 1536, 2048), chosen
+    assert chosen[11] in (1024, 1536, 2048, 3072, 4096, 6144), chosen
     z1 = S.precond_apply(v)
     assert torch.equal(z0, z1)
+    assert torch.equal(S.spmv(v), y0)
     b = np.concatenate([s.F for s in systems])
     _, st = S.solve(b, restart=50, max_iters=300, tol=1e-6)
     assert all(x["converged"] for x in st)
