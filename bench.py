@@ -48,6 +48,8 @@ def parse():
                     help="inner FGMRES steps of the extra inner-solve run (0: skip it)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="time and fix the launch shapes (SpMV sweep, BF16 sweep layers) before the timed solves (0: defaults)")
+    ap.add_argument("--precision-runs", default="fp8,f32",
+                    help="network dtypes also timed on the same workload (comma list of f32/bf16/fp8; empty: none)")
     ap.add_argument("--cpu-neural-iters", type=int, default=3)
     ap.add_argument("--cpu-jacobi-iters", type=int, default=50)
     return ap.parse_args()
@@ -286,6 +288,19 @@ def main():
                   "converged_all": all(q["converged"] for q in stn),
                   "used_fallback": int(sum(q["used_fallback"] for q in stn)), "max_true_rel_res": max(rel_nd)}
 
+    # the same network in other arithmetic: FP32 (direct kernels) and E4M3
+    # weights with per-channel power-of-two scales on the BF16 kernels
+    precision = {}
+    for dt in [d for d in a.precision_runs.split(",") if d and d != a.cnn_dtype]:
+        S.set_preconditioner("neural", weights=w, cnn_dtype=dt)
+        Tp, stp = run(neural_opts, 1, 1)
+        rel_p = true_rel()
+        precision[dt] = {"solves_per_s": S.n_inst / Tp, "ms_per_solve": Tp * 1e3,
+                         "iters_mean": float(np.mean([q["iters"] + q["fallback_iters"] for q in stp])),
+                         "converged_all": all(q["converged"] for q in stp),
+                         "used_fallback": int(sum(q["used_fallback"] for q in stp)), "max_true_rel_res": max(rel_p),
+                         "ms_per_apply": time_kernel(ctx, lambda: S.precond_apply(xs), 3)}
+
     jac = None
     if not a.skip_jacobi:
         S.set_preconditioner("jacobi")
@@ -311,6 +326,7 @@ def main():
         "neural_smoothed": smoothed,
         "neural_inner_fgmres": inner,
         "neural_no_distance": nodist,
+        "neural_precision": precision or None,
         "jacobi": jac,
         "roofline": {"bound": "hbm", "kernel": "k_stencil_sweep + k_mrows (batched y = (S + M) x, FP32)",
                      "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,

@@ -152,7 +152,12 @@ mdnp_status mdnp_export_rhs(const mdnp_sys* sys, int32_t inst, double* F, double
  * (host, FP32, n_weights = 353713) holds the U-net parameters layer by layer,
  * each as [Cout][kz][ky][kx][Cin] then the bias, layers in the order
  * L0a L0b L1a L1b L2a L2b U1 D1 U0 D0 H; cnn_dtype is the arithmetic of the
- * network (MDNP_F32 or MDNP_BF16; FP32 accumulation).  alpha <= 0 keeps each
+ * network (MDNP_F32 or MDNP_BF16; FP32 accumulation).  MDNP_FP8E4M3 rounds
+ * every layer's weights (not the biases) to the OCP 8-bit format E4M3 times
+ * one power-of-two scale per output channel (the smallest 2^k with
+ * max|w| / 2^k <= 448; round to nearest, ties to even) and runs the network
+ * with them on the BF16 kernels, where those values are exact: E4M3 weights,
+ * BF16 activations, FP32 accumulation.  alpha <= 0 keeps each
  * instance's own alpha.  Requires n_cells divisible by 4.  Errors: MDNP_E_ARG,
  * MDNP_E_NONFINITE. */
 mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* sys, mdnp_prec_kind kind,

@@ -712,7 +712,8 @@ extern "C" mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* s, mdnp_
       np += (int64_t)kLayers[l].cout * taps * kLayers[l].cin + kLayers[l].cout;
     }
     if (n_weights != np) fail(MDNP_E_ARG, "expected " + std::to_string(np) + " weights");
-    if (cnn_dtype != MDNP_F32 && cnn_dtype != MDNP_BF16) fail(MDNP_E_ARG, "cnn_dtype must be MDNP_F32 or MDNP_BF16");
+    if (cnn_dtype != MDNP_F32 && cnn_dtype != MDNP_BF16 && cnn_dtype != MDNP_FP8E4M3)
+      fail(MDNP_E_ARG, "cnn_dtype must be MDNP_F32, MDNP_BF16 or MDNP_FP8E4M3");
     if (s->n_cells % 4 != 0 || s->n_cells < 4) fail(MDNP_E_ARG, "the network needs n_cells divisible by 4");
     for (int64_t k = 0; k < n_weights; ++k)
       if (!std::isfinite(weights[k])) fail(MDNP_E_NONFINITE, "non-finite network weight");
@@ -720,6 +721,13 @@ extern "C" mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* s, mdnp_
     if (!c.w_own) c.w_own = dalloc<float>((size_t)np);
     HIPCHK(hipMemcpyAsync(c.w_own, weights, sizeof(float) * np, hipMemcpyHostToDevice, ctx->stream));
     c.w = c.w_own;
+    // FP8: the weights become E4M3 codes x per-channel powers of two, exact in
+    // BF16, and the network runs on the BF16 kernels
+    c.fp8_weights = cnn_dtype == MDNP_FP8E4M3;
+    if (c.fp8_weights) {
+      cnn_quantize_e4m3(c.w_own, ctx->stream);
+      cnn_dtype = MDNP_BF16;
+    }
     c.dtype = cnn_dtype;
     if (!c.inv_s) c.inv_s = dalloc<double>(2 * (size_t)s->n_inst);
     cnn_prepare_weights(c, c.w, ctx->stream);

@@ -389,6 +389,55 @@ int64_t cnn_layer_count() { return kNumLayers; }
 
 static inline int64_t cube(int n) { return (int64_t)n * n * n; }
 
+// ---------------------------------------------------------------- FP8 (E4M3) weights
+
+// Nearest E4M3 value of v (1 sign, 4 exponent bits with bias 7, 3 mantissa
+// bits, subnormals down to 2^-9, largest finite 448), ties to even, saturating
+// at +-448: the quantum of the binade of |v| (at least that of the
+// subnormals, 2^-9) is a power of two, so scaling by it and rounding to an
+// integer in the default round-to-nearest-even mode is exact.
+__device__ __forceinline__ float round_e4m3(float v) {
+  const float a = fabsf(v);
+  if (a >= 448.0f) return copysignf(448.0f, v);
+  int e;
+  (void)frexpf(a, &e);                       // a = f 2^e, f in [0.5, 1): binade 2^(e - 1)
+  const int qe = max(e - 1, -6) - 3;         // quantum 2^qe
+  return copysignf(ldexpf(rintf(ldexpf(a, -qe)), qe), v);
+}
+
+// One workgroup per output channel of one layer (its taps x cin weights,
+// contiguous): the scale is the smallest power of two 2^k with
+// amax / 2^k <= 448 = 0.875 * 2^9, then w = round_e4m3(w / 2^k) * 2^k in place.
+__global__ void __launch_bounds__(256) k_quant_e4m3(float* __restrict__ w, int nper) {
+  __shared__ float red[4];
+  float* row = w + (int64_t)blockIdx.x * nper;
+  float a = 0.0f;
+  for (int k = threadIdx.x; k < nper; k += 256) a = fmaxf(a, fabsf(row[k]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a = fmaxf(a, __shfl_xor(a, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  const float amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  int k = 0;
+  if (amax > 0.0f) {
+    int e;
+    const float f = frexpf(amax, &e);
+    k = f <= 0.875f ? e - 9 : e - 8;
+  }
+  for (int q = threadIdx.x; q < nper; q += 256) row[q] = ldexpf(round_e4m3(ldexpf(row[q], -k)), k);
+}
+
+void cnn_quantize_e4m3(float* d_w, hipStream_t stream) {
+  int64_t off = 0;
+  for (int l = 0; l < kNumLayers; ++l) {
+    const LayerSpec& L = kLayers[l];
+    const int taps = L.kind == KIND_PT ? 1 : 27;
+    const int nper = taps * L.cin;
+    hipLaunchKernelGGL(k_quant_e4m3, dim3((unsigned)L.cout), dim3(256), 0, stream, d_w + off, nper);
+    off += (int64_t)L.cout * nper + L.cout;  // weights [cout][taps][cin], then the biases
+  }
+}
+
 void cnn_prepare_weights(CnnState& c, const float* d_w, hipStream_t stream) {
   int64_t off = 0, toff = 0;
   c.w_off.assign(kNumLayers, 0);

@@ -52,6 +52,7 @@ struct Blocks {
 struct CnnState {
   bool ready = false;
   mdnp_dtype dtype = MDNP_F32;
+  bool fp8_weights = false;    // weights rounded to E4M3 x per-channel power-of-two scales (run as BF16)
   const float* w = nullptr;    // flat weights in use [353713] (owned copy or borrowed)
   float* w_own = nullptr;      // owned copy set by mdnp_set_preconditioner
   float* wt = nullptr;         // per-layer [taps][cin][cout] copies for the direct kernels

@@ -108,6 +108,9 @@ void cnn_apply_in_solver(mdnp_sys* s, const T* zin, T* z, const InstState* st, h
 // system's batch and grid (CnnState::sweep_blocks); false if its timing
 // buffers or events could not be created (the defaults are then kept).
 bool cnn_autotune(mdnp_sys* s, hipStream_t stream, int reps);
+// Rounds the weights of every layer (not the biases) of the flat FP32 vector
+// d_w in place to E4M3 codes times a power-of-two scale per output channel.
+void cnn_quantize_e4m3(float* d_w, hipStream_t stream);
 // Wave count of the stencil sweep's z split chosen by timing the batched SpMV
 // (mdnp_sys::sweep_target); false if its buffers or events could not be made.
 bool spmv_autotune(mdnp_sys* s, hipStream_t stream);

@@ -359,6 +359,35 @@ def test_graph_replay_matches_eager(ctx):
     assert np.array_equal(xa, xb)
 
 
+def test_fp8_weights_match_oracle_quantisation(ctx):
+    """cnn_dtype fp8: the library's E4M3 rounding (per-channel power-of-two
+    scales) gives bit-for-bit the weights of the oracle's quantiser: Q(v) equals
+    the BF16 network run on the oracle-quantised weights exactly, and stays
+    within the BF16 tolerance of the FP64 oracle on those weights."""
+    from oracle import fp8
+    P = _P()
+    insts = [synth.make_instance(930 + i, 16, n_segments=s, elems_per_segment=3, radius=0.01, beta=1.0)
+             for i, s in enumerate((6, 10))]
+    S = P.System(ctx, insts, vec_dtype="f32")
+    th32 = _theta(7).astype(np.float32)
+    thq = fp8.quantize_weights(th32.astype(np.float64))
+    assert np.array_equal(thq.astype(np.float32).astype(np.float64), thq)  # exact in FP32
+    v = synth.fast_normal(8, S.ntot).astype(np.float32)
+    S.set_preconditioner("neural", weights=th32, cnn_dtype="fp8")
+    z8 = S.precond_apply(dev(v, torch.float32)).clone()
+    S.set_preconditioner("neural", weights=thq.astype(np.float32), cnn_dtype="bf16")
+    zq = S.precond_apply(dev(v, torch.float32))
+    assert torch.equal(z8, zq)
+    net = lambda X: ocnn.forward(thq, X)[0]
+    z = z8.cpu().double().numpy()
+    for k, inst in enumerate(insts):
+        s = fem.assemble(inst)
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(v[o0:o1].astype(np.float64))
+        err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
+        assert err <= 5e-2, (k, err)
+
+
 def test_neural_fgmres_solve(ctx):
     P = _P()
     inst = synth.make_instance(42, 16, n_segments=12, elems_per_segment=4, radius=0.008, beta=1.0)
@@ -485,6 +514,33 @@ def test_neural_precond_bench_config(ctx, bench64):
         ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(v[o0:o1].astype(np.float64))
         err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
         assert err <= 5e-2, (k, err)
+
+
+def test_fp8_precond_and_solve_bench_config(ctx, bench64):
+    """The trained network with E4M3 weights at the benchmark size: Q(v) of two
+    instances against the FP64 oracle on the quantised weights, and the batched
+    FGMRES(30) solve reaching rel-res 1e-8 on every instance."""
+    from oracle import fp8
+    from paper_2505_08491_amd import weights as W
+    S, _, systems = bench64
+    wpath = W.default_path()
+    th = W.load(wpath)[0] if __import__("os").path.exists(wpath + ".bin") else _theta(5).astype(np.float32)
+    S.set_preconditioner("neural", weights=th, cnn_dtype="fp8")
+    thq = fp8.quantize_weights(np.asarray(th, dtype=np.float32).astype(np.float64))
+    net = lambda X: ocnn.forward(thq, X)[0]
+    v = synth.fast_normal(17, S.ntot).astype(np.float32)
+    z = S.precond_apply(dev(v, torch.float32)).cpu().double().numpy()
+    for k, s in enumerate(systems[:2]):
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(v[o0:o1].astype(np.float64))
+        err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
+        assert err <= 5e-2, (k, err)
+    b = np.concatenate([s.F for s in systems])
+    x, st = S.solve(b, restart=30, max_iters=600, tol=1e-8)
+    assert all(q["converged"] and not q["used_fallback"] for q in st), st
+    for k, s in enumerate(systems[:2]):
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        assert np.linalg.norm(s.F - s.A @ x[o0:o1]) / np.linalg.norm(s.F) <= 1e-8
 
 
 def test_inner_fgmres_precond_bench_config(ctx, bench64):
