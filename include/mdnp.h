@@ -190,13 +190,16 @@ mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* sys, int32_t steps);
 /* Autotuner of the launch shapes, timed on this system's own batch and grid
  * with HIP events: the wave count that the stencil sweep of the SpMV splits
  * its z range for (from {1024 .. 6144}; best of three batches of 20 SpMVs),
- * and, with a BF16 neural preconditioner set, the workgroup count of the z
- * split of each sweep convolution (L0a, L0b, L1b, L2b, D1, D0; from
- * {256 .. 2048}; coordinate descent, best of 5 whole network applications).
+ * and, with a BF16 (or FP8-weight) neural preconditioner set, the shape of
+ * every convolution launch: the workgroup count of the z split of the sweep
+ * layers (L0a, L0b, L1b, L2b, D1, D0; from {256 .. 2048}) and the 16-voxel
+ * M blocks per wave of the stride-2 and transposed layers (L1a {2, 4, 8}, L2a
+ * {1, 2, 4}, U1 {1, 2}, U0 {1, 2, 4}); coordinate descent, best of 5 whole
+ * network applications.
  * The choices only move output planes between waves and workgroups: results
  * are unchanged.  They are kept with the system; `chosen` (nullable, [12])
  * receives them: [0 .. 10] the convolution layers L0a = 0 .. H = 10 (0 = the
- * built-in default), [11] the SpMV sweep target (0 = default; also 0 where
+ * built-in default, always for H), [11] the SpMV sweep target (0 = default; also 0 where
  * the grid has more than 65 nodes per side and no sweep is used).  The library
  * allocates two vectors of the system's size for the timing and frees them
  * before returning.  Errors: MDNP_E_OOM if those buffers cannot be allocated

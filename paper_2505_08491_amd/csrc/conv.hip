@@ -698,13 +698,29 @@ template void cnn_apply_in_solver<double>(mdnp_sys*, const double*, double*, con
 
 // ---------------------------------------------------------------- autotuning
 
-// Chooses the z split of each BF16 sweep layer (the workgroup target of its
-// launch) on the system's own batch and grid: coordinate descent over the
-// layers, each candidate timed as the best of `reps` whole in-solver network
-// applications with HIP events.  The split only decides which workgroup
-// computes which output planes, so results are the same for every choice.
-static const int kTuneLayers[] = {0, 1, 3, 5, 7, 9};
-static const int kTuneTargets[] = {256, 384, 512, 768, 1024, 1536, 2048};
+// Chooses the launch shape of each BF16 layer on the system's own batch and
+// grid: for the sweep layers the workgroup count their z split aims at, for
+// the stride-2 and transposed layers the 16-voxel M blocks per wave.
+// Coordinate descent over the layers, each candidate timed as the best of
+// `reps` whole in-solver network applications with HIP events.  The shape only
+// decides which wave computes which outputs, in the same order of
+// accumulation, so results are the same for every choice.
+struct TuneLayer {
+  int layer, n;
+  int cand[8];
+};
+static const TuneLayer kTune[] = {
+    {0, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // L0a  z split
+    {1, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // L0b
+    {2, 3, {2, 4, 8}},                               // L1a  M blocks per wave
+    {3, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // L1b
+    {4, 3, {1, 2, 4}},                               // L2a
+    {5, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // L2b
+    {6, 2, {1, 2}},                                  // U1
+    {7, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // D1
+    {8, 3, {1, 2, 4}},                               // U0
+    {9, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // D0 (+ head)
+};
 
 template <typename Tv>
 static bool autotune_t(mdnp_sys* s, hipStream_t stream, int reps) {
@@ -738,10 +754,12 @@ static bool autotune_t(mdnp_sys* s, hipStream_t stream, int reps) {
   };
   if (ok) {
     time_once();  // warm-up
-    for (int layer : kTuneLayers) {
+    for (const TuneLayer& tl : kTune) {
+      const int layer = tl.layer;
       int best_t = c.sweep_blocks[layer];
       float best = 1e30f;
-      for (int t : kTuneTargets) {
+      for (int q = 0; q < tl.n; ++q) {
+        const int t = tl.cand[q];
         c.sweep_blocks[layer] = t;
         const float ms = time_once();
         if (ms < best) {

@@ -1800,28 +1800,43 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
       launch_ks16<16, 0, 4, 0, 0, float>(a, batch, stream, sweep_target(c, 1, 1024));
       break;
     }
-    case 2: launch_conv<16, 0, 32, 2, 4>(p, batch, w, stream); break;    // L1a
+    case 2:  // L1a: M blocks per wave chosen by the autotuner
+      if (c.sweep_blocks[2] == 2) launch_conv<16, 0, 32, 2, 2>(p, batch, w, stream);
+      else if (c.sweep_blocks[2] == 8) launch_conv<16, 0, 32, 2, 8>(p, batch, w, stream);
+      else launch_conv<16, 0, 32, 2, 4>(p, batch, w, stream);
+      break;
     case 3: {                                                             // L1b
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_l1b;
       launch_convw<32, 0, 32, 3, 4, 2>(a, batch, stream, sweep_target(c, 3, 1024));
       break;
     }
-    case 4: launch_conv<32, 0, 64, 2, 2>(p, batch, w, stream); break;    // L2a
+    case 4:  // L2a
+      if (c.sweep_blocks[4] == 1) launch_conv<32, 0, 64, 2, 1>(p, batch, w, stream);
+      else if (c.sweep_blocks[4] == 4) launch_conv<32, 0, 64, 2, 4>(p, batch, w, stream);
+      else launch_conv<32, 0, 64, 2, 2>(p, batch, w, stream);
+      break;
     case 5: {                                                             // L2b
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_l2b;
       launch_convw<64, 0, 64, 2, 8, 2>(a, batch, stream, sweep_target(c, 5, kSweepBlocksL2b));
       break;
     }
-    case 6: launch_tconv_all<64, 32, 1>(p, batch, mfma_extra(c).tf_u1, stream); break;  // U1
+    case 6:  // U1
+      if (c.sweep_blocks[6] == 2) launch_tconv_all<64, 32, 2>(p, batch, mfma_extra(c).tf_u1, stream);
+      else launch_tconv_all<64, 32, 1>(p, batch, mfma_extra(c).tf_u1, stream);
+      break;
     case 7: {                                                             // D1
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_d1;
       launch_convw<32, 32, 32, 3, 4, 3>(a, batch, stream, sweep_target(c, 7, 1024));
       break;
     }
-    case 8: launch_tconv_all<32, 16, 2>(p, batch, mfma_extra(c).tf_u0, stream); break;  // U0
+    case 8:  // U0
+      if (c.sweep_blocks[8] == 1) launch_tconv_all<32, 16, 1>(p, batch, mfma_extra(c).tf_u0, stream);
+      else if (c.sweep_blocks[8] == 4) launch_tconv_all<32, 16, 4>(p, batch, mfma_extra(c).tf_u0, stream);
+      else launch_tconv_all<32, 16, 2>(p, batch, mfma_extra(c).tf_u0, stream);
+      break;
     case 9: {                                                             // D0
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_d0;

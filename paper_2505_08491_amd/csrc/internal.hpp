@@ -73,8 +73,9 @@ struct CnnState {
   int64_t* std_off = nullptr;  // [batch] b * n^3
   double* std_ones = nullptr;  // [batch] 1
   int std_batch = 0, std_n = 0;
-  // workgroups aimed at by the z split of each sweep layer (0: built-in
-  // default); set by the autotuner, indexed by layer (L0a = 0 .. D0 = 9)
+  // launch shape of each BF16 layer set by the autotuner, by layer (L0a = 0 ..
+  // D0 = 9; 0: built-in default): for the sweep layers the workgroups their z
+  // split aims at, for L1a, L2a, U1, U0 the 16-voxel M blocks per wave
   int sweep_blocks[11] = {};
 };
 

@@ -603,6 +603,7 @@ def test_autotune_keeps_preconditioner_output(ctx, bench64):
     chosen = S.autotune()
     for layer in (0, 1, 3, 5, 7, 9):
         assert chosen[layer] in (256, 384, 512, 768, 1024, 1536, 2048), chosen
+    assert chosen[2] in (2, 4, 8) and chosen[4] in (1, 2, 4) and chosen[6] in (1, 2) and chosen[8] in (1, 2, 4)
     assert chosen[11] in (1024, 1536, 2048, 3072, 4096, 6144), chosen
     z1 = S.precond_apply(v)
     assert torch.equal(z0, z1)
