@@ -33,7 +33,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-cells", type=int, default=64)
-    ap.add_argument("--count", type=int, default=16)
+    ap.add_argument("--count", type=int, default=None, help="instances (default 16 at 64^3, 2 at 128^3, 256 batched)")
+    ap.add_argument("--workload", default="transfer", choices=["transfer", "batched32"],
+                    help="transfer: 512-segment trees at --n-cells (the metric at 64^3); batched32: 256 instances "
+                         "at 32^3 with trees of 8-128 segments, R ~ U[0.003, 0.01]")
     ap.add_argument("--weights", default=None)
     ap.add_argument("--cnn-dtype", default="bf16", choices=["bf16", "f32"])
     ap.add_argument("--jacobi-steps", type=int, default=1)
@@ -174,7 +177,16 @@ def main():
     import paper_2505_08491_amd as P
     from paper_2505_08491_amd import weights as W
 
-    insts = synth.workload_transfer(a.n_cells, a.count)
+    if a.workload == "batched32":
+        a.n_cells = 32
+        a.count = a.count or 256
+        insts = synth.workload_batched_32(a.count)
+        wl_desc = (f"{a.count} seeded random trees (8-128 segments x 8 P1 elements, R ~ U[0.003, 0.01]) at "
+                   f"32^3 trilinear cells")
+    else:
+        a.count = a.count or (16 if a.n_cells == 64 else 2)
+        insts = synth.workload_transfer(a.n_cells, a.count)
+        wl_desc = f"{a.count} seeded random trees (512 segments x 16 P1 elements, R=0.002) at {a.n_cells}^3 trilinear cells"
     wpath = a.weights or W.default_path()
     trained = os.path.exists(wpath + ".bin")
     w = W.load(wpath)[0] if trained else W.init(0)
@@ -316,8 +328,7 @@ def main():
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": T / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{a.count} seeded random trees (512 segments x 16 P1 elements, R=0.002) at "
-                               f"{a.n_cells}^3 trilinear cells, FP32 vectors and SpMV, FP64 MGS/Givens/x/true residual, "
+        "config": {"workload": f"{wl_desc}, FP32 vectors and SpMV, FP64 MGS/Givens/x/true residual, "
                                f"{a.cnn_dtype} U-net", "instances": a.count, "n_cells": a.n_cells,
                    "restart": 30, "tol": 1e-8, "cnn_dtype": a.cnn_dtype,
                    "weights": os.path.relpath(wpath, ROOT) if trained else "untrained (Kaiming init)"},
@@ -330,7 +341,8 @@ def main():
         "jacobi": jac,
         "roofline": {"bound": "hbm", "kernel": "k_stencil_sweep + k_mrows (batched y = (S + M) x, FP32)",
                      "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
-                     "traffic": spmv_traffic(S), "algorithmic_bytes": spmv_bytes(S), "ms_per_launch": ms_spmv,
+                     "traffic": spmv_traffic(S) if (a.workload, a.n_cells, a.count) == ("transfer", 64, 16) else None,
+                     "algorithmic_bytes": spmv_bytes(S), "ms_per_launch": ms_spmv,
                      "copy_gbps": copy_gbps},
         "unet": {"bound": "mfma", "dtype": a.cnn_dtype, "gflop_per_forward": cnn_flop / 1e9,
                  "ms_per_forward": ms_cnn, "achieved": cnn_flop / (ms_cnn * 1e-3) / 1e12,

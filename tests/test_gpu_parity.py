@@ -613,6 +613,44 @@ def test_autotune_keeps_preconditioner_output(ctx, bench64):
     assert all(x["converged"] for x in st)
 
 
+# ---------------------------------------------------------------- batched 32^3 x 256 (ragged trees)
+
+def test_batched32_full_config(ctx):
+    """The batched configuration at full size: 256 instances at 32^3 with trees
+    of 8-128 segments, BF16 network, FGMRES(30) to 1e-8 in one batched solve.
+    Every instance converges with true rel-res <= 1e-8 in FP64 on the
+    library's assembled operator (all 256) and on the oracle's own assembly
+    (a sample of 6, from the smallest to the largest tree); the solution of the
+    largest tree is within 1e-6 of the oracle's direct solve."""
+    from paper_2505_08491_amd import weights as W
+    P = _P()
+    insts = synth.workload_batched_32(256)
+    S = P.System(ctx, insts, vec_dtype="f32")
+    wpath = W.default_path()
+    th = W.load(wpath)[0] if __import__("os").path.exists(wpath + ".bin") else _theta(5).astype(np.float32)
+    S.set_preconditioner("neural", weights=th, cnn_dtype="bf16")
+    b = S.rhs()
+    x, st = S.solve(b, restart=30, max_iters=600, tol=1e-8)
+    assert all(q["converged"] and not q["used_fallback"] for q in st), [k for k, q in enumerate(st) if not q["converged"]]
+    for k in range(S.n_inst):
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        rp, ci, va = S.export_csr(k)
+        A = sp.csr_matrix((va, ci, rp), shape=(o1 - o0, o1 - o0))
+        assert np.linalg.norm(b[o0:o1] - A @ x[o0:o1]) <= 1e-8 * np.linalg.norm(b[o0:o1]), k
+    segs = np.array([i.n_segments for i in insts])
+    order = np.argsort(segs, kind="stable")
+    sample = [int(order[q]) for q in np.linspace(0, len(order) - 1, 6).round().astype(int)]
+    for k in sample:
+        s = fem.assemble(insts[k])
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        assert np.linalg.norm(s.F - s.A @ x[o0:o1]) <= 1e-8 * np.linalg.norm(s.F), k
+    k = sample[-1]
+    s = fem.assemble(insts[k])
+    xd = krylov.direct_solve(s)
+    o0, o1 = S.offsets[k], S.offsets[k + 1]
+    assert np.linalg.norm(x[o0:o1] - xd) <= 1e-6 * np.linalg.norm(xd), k
+
+
 # ---------------------------------------------------------------- 128^3 (resolution transfer, 2.15M 3D unknowns)
 
 @pytest.fixture(scope="module")
