@@ -350,7 +350,8 @@ def main():
                  "frac": cnn_flop / (ms_cnn * 1e-3) / 1e12 / BF16_PEAK_TFLOPS},
         "preconditioner": {"ms_per_apply": ms_prec, "cnn_tflops": cnn_flop / (ms_prec * 1e-3) / 1e12},
         "upload_s": t_upload,
-        "autotune": {"conv_sweep_blocks": tuned[:11], "spmv_sweep_target": tuned[11], "s": t_tune} if tuned else None,
+        "autotune": {"conv_sweep_blocks": tuned[:11], "spmv_sweep_target": tuned[11],
+                     "conv_rows_l1b_d1_l0b_d0": tuned[12:16], "s": t_tune} if tuned else None,
     }
     if not a.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(insts[0], float(np.mean(neural_iters)),

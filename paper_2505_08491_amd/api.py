@@ -242,9 +242,10 @@ class System:
                                                     DTYPE[cnn_dtype]))
 
     def autotune(self):
-        """Time and fix the launch shapes: the z split of each BF16 sweep layer
-        ([0..10], by layer) and of the SpMV stencil sweep ([11])."""
-        out = (C.c_int32 * 12)()
+        """Time and fix the launch shapes: the z split / M blocks of each BF16
+        layer ([0..10], by layer), the SpMV stencil sweep's z split ([11]) and
+        the output rows of L1b, D1, L0b, D0 ([12..15])."""
+        out = (C.c_int32 * 16)()
         self.ctx._check(lib.mdnp_autotune(self.ctx.h, self.h, out))
         return list(out)
 

@@ -758,6 +758,10 @@ extern "C" mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* s, int32_t* chosen
     if (chosen) {
       for (int l = 0; l < 11; ++l) chosen[l] = s->cnn.sweep_blocks[l];
       chosen[11] = s->sweep_target;
+      chosen[12] = s->cnn.tile_mb[3];
+      chosen[13] = s->cnn.tile_mb[7];
+      chosen[14] = s->cnn.tile_mb[1];
+      chosen[15] = s->cnn.tile_mb[9];
     }
   });
 }

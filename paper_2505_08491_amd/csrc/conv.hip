@@ -708,8 +708,13 @@ template void cnn_apply_in_solver<double>(mdnp_sys*, const double*, double*, con
 struct TuneLayer {
   int layer, n;
   int cand[8];
+  int rows = 0;  // 1: the candidates are output rows per workgroup (tile_mb), else the launch target
 };
 static const TuneLayer kTune[] = {
+    {1, 4, {3, 4, 5, 6}, 1},                         // L0b  output rows per workgroup (per wave pair)
+    {3, 4, {2, 3, 4, 6}, 1},                         // L1b
+    {7, 2, {2, 3}, 1},                               // D1
+    {9, 3, {3, 4, 5}, 1},                            // D0 (+ head)
     {0, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // L0a  z split
     {1, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // L0b
     {2, 3, {2, 4, 8}},                               // L1a  M blocks per wave
@@ -756,18 +761,19 @@ static bool autotune_t(mdnp_sys* s, hipStream_t stream, int reps) {
     time_once();  // warm-up
     for (const TuneLayer& tl : kTune) {
       const int layer = tl.layer;
-      int best_t = c.sweep_blocks[layer];
+      int* slot = tl.rows ? &c.tile_mb[layer] : &c.sweep_blocks[layer];
+      int best_t = *slot;
       float best = 1e30f;
       for (int q = 0; q < tl.n; ++q) {
         const int t = tl.cand[q];
-        c.sweep_blocks[layer] = t;
+        *slot = t;
         const float ms = time_once();
         if (ms < best) {
           best = ms;
           best_t = t;
         }
       }
-      c.sweep_blocks[layer] = best_t;
+      *slot = best_t;
     }
   }
   if (e0) (void)hipEventDestroy(e0);

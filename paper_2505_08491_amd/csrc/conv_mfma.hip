@@ -1780,7 +1780,10 @@ void conv_mfma_d0_head(const CnnState& c, const bf16* u0, const bf16* s0, int n,
   a.alpha_override = alpha_override;
   a.scale = scale;
   (void)nmb;
-  launch_ks16<16, 16, 4, 1, 1, Tv>(a, batch, stream, sweep_target(c, 9, kSweepBlocksD0));
+  const int t = sweep_target(c, 9, kSweepBlocksD0);
+  if (c.tile_mb[9] == 3) launch_ks16<16, 16, 3, 1, 1, Tv>(a, batch, stream, t);
+  else if (c.tile_mb[9] == 5) launch_ks16<16, 16, 5, 1, 1, Tv>(a, batch, stream, t);
+  else launch_ks16<16, 16, 4, 1, 1, Tv>(a, batch, stream, t);
 }
 template void conv_mfma_d0_head<float>(const CnnState&, const bf16*, const bf16*, int, int, float*, const int64_t*,
                                        const double*, double, const double*, const InstState*, hipStream_t);
@@ -1797,7 +1800,11 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_l0b;
       a.zero16 = mfma_extra(c).zeros;
-      launch_ks16<16, 0, 4, 0, 0, float>(a, batch, stream, sweep_target(c, 1, 1024));
+      const int t = sweep_target(c, 1, 1024);
+      if (c.tile_mb[1] == 3) launch_ks16<16, 0, 3, 0, 0, float>(a, batch, stream, t);
+      else if (c.tile_mb[1] == 5) launch_ks16<16, 0, 5, 0, 0, float>(a, batch, stream, t);
+      else if (c.tile_mb[1] == 6) launch_ks16<16, 0, 6, 0, 0, float>(a, batch, stream, t);
+      else launch_ks16<16, 0, 4, 0, 0, float>(a, batch, stream, t);
       break;
     }
     case 2:  // L1a: M blocks per wave chosen by the autotuner
@@ -1808,7 +1815,11 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
     case 3: {                                                             // L1b
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_l1b;
-      launch_convw<32, 0, 32, 3, 4, 2>(a, batch, stream, sweep_target(c, 3, 1024));
+      const int t = sweep_target(c, 3, 1024);
+      if (c.tile_mb[3] == 2) launch_convw<32, 0, 32, 2, 4, 2>(a, batch, stream, t);
+      else if (c.tile_mb[3] == 4) launch_convw<32, 0, 32, 4, 4, 2>(a, batch, stream, t);
+      else if (c.tile_mb[3] == 6) launch_convw<32, 0, 32, 6, 4, 3>(a, batch, stream, t);
+      else launch_convw<32, 0, 32, 3, 4, 2>(a, batch, stream, t);
       break;
     }
     case 4:  // L2a
@@ -1829,7 +1840,9 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
     case 7: {                                                             // D1
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_d1;
-      launch_convw<32, 32, 32, 3, 4, 3>(a, batch, stream, sweep_target(c, 7, 1024));
+      const int t = sweep_target(c, 7, 1024);
+      if (c.tile_mb[7] == 2) launch_convw<32, 32, 32, 2, 4, 3>(a, batch, stream, t);
+      else launch_convw<32, 32, 32, 3, 4, 3>(a, batch, stream, t);
       break;
     }
     case 8:  // U0

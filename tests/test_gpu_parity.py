@@ -282,7 +282,7 @@ def test_smoothing_rejects_bad_arguments(ctx):
     x = dev(synth.fast_normal(21, S.ntot), torch.float32)
     y0 = S.spmv(x).clone()
     chosen = S.autotune()
-    assert chosen[11] in (1024, 1536, 2048, 3072, 4096, 6144) and not any(chosen[:11]), chosen
+    assert chosen[11] in (1024, 1536, 2048, 3072, 4096, 6144) and not any(chosen[:11] + chosen[12:]), chosen
     assert torch.equal(S.spmv(x), y0)
     S.free()
 
@@ -604,6 +604,8 @@ def test_autotune_keeps_preconditioner_output(ctx, bench64):
     for layer in (0, 1, 3, 5, 7, 9):
         assert chosen[layer] in (256, 384, 512, 768, 1024, 1536, 2048), chosen
     assert chosen[2] in (2, 4, 8) and chosen[4] in (1, 2, 4) and chosen[6] in (1, 2) and chosen[8] in (1, 2, 4)
+    assert chosen[12] in (2, 3, 4, 6) and chosen[13] in (2, 3), chosen
+    assert chosen[14] in (3, 4, 5, 6) and chosen[15] in (3, 4, 5), chosen
     assert chosen[11] in (1024, 1536, 2048, 3072, 4096, 6144), chosen
     z1 = S.precond_apply(v)
     assert torch.equal(z0, z1)
