@@ -154,22 +154,24 @@ __device__ __forceinline__ Tacc stencil_row(const Tv* __restrict__ x, int64_t ba
 
 // y = S x on the 3D rows, sweeping z, for n <= SW_NMAX nodes per side.  A
 // wave owns rows y0 .. y0 + SW_TY - 1 of planes z0 .. z0 + zc - 1 of one
-// instance, lane l holding column x = l + 1 (the interior columns and the
-// x = n - 1 boundary column).  For every input plane z' it loads rows
-// y0 - 1 .. y0 + SW_TY, zeroes the nodes on the Dirichlet boundary (their
-// columns are eliminated), takes the x-neighbour sums by lane shifts and forms
-// per output row the 2D partials centre, 4 in-plane faces and 4 in-plane
-// corners.  Output plane z gathers them from z' = z (offsets 0, 1, 2 differing
-// coordinates) and z' = z +- 1 (1, 2, 3), so two accumulators per row ride
-// along the sweep.  Dirichlet rows copy x.  Planes are loaded SW_PD steps ahead
-// into a ring of register sets; the loop is unrolled over the ring, so no set
-// is copied and a step waits only for its own plane.  No LDS, no barriers.
-// The x = 0 boundary column is copied by extra waves of the same launch
-// (the first tile ids, one per instance and SW_FZ planes).
+// instance, lane l holding columns x = l + 1 + 64 k for k < NX (the interior
+// columns and the x = n - 1 boundary column; NX = 1 up to 65 nodes, 2 up to
+// 129).  For every input plane it loads rows y0 - 1 .. y0 + SW_TY, zeroes the
+// nodes on the Dirichlet boundary (their columns are eliminated), takes the
+// x-neighbour sums by lane shifts (the neighbours across the two column
+// blocks by lane reads) and forms per output row the 2D partials centre,
+// 4 in-plane faces and 4 in-plane corners.  Output plane z gathers them from
+// z' = z (offsets 0, 1, 2 differing coordinates) and z' = z +- 1 (1, 2, 3), so
+// two accumulators per row ride along the sweep.  Dirichlet rows copy x.
+// Planes are loaded SW_PD steps ahead into a ring of register sets; the loop
+// is unrolled over the ring, so no set is copied and a step waits only for its
+// own plane.  No LDS, no barriers.  The x = 0 boundary column is copied by
+// extra waves of the same launch (the first tile ids, one per instance and
+// SW_FZ planes).
 constexpr int SW_TY = 5;      // output rows per wave
 constexpr int SW_PD = 3;      // planes in flight (register sets)
 constexpr int SW_FZ = 8;      // planes per x = 0 copy wave
-constexpr int SW_NMAX = 65;   // lane l <-> column l + 1
+constexpr int SW_NMAX = 129;  // lane l <-> columns l + 1, l + 65
 
 __device__ __forceinline__ float lane_from_left(float v) {  // value of lane l - 1 (0 for lane 0)
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
@@ -187,8 +189,16 @@ __device__ __forceinline__ double lane_from_right(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x130, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float lane_value(float v, int l) {  // v of lane l, in every lane
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane((int)__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane((int)__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
 
-template <typename Tv, typename Tacc, int SUM = 0>
+template <typename Tv, typename Tacc, int SUM = 0, int NX = 1>
 __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict__ stencil, const Tv* __restrict__ x,
                                                        Tv* __restrict__ y, const int64_t* __restrict__ off, int n,
                                                        int ytiles, int zc, int nface, int ntile, const InstState* st,
@@ -225,33 +235,48 @@ __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict_
   Tv* Y = y + off[i];
   const Tacc w0 = (Tacc)stencil[4 * i], w1 = (Tacc)stencil[4 * i + 1], w2 = (Tacc)stencil[4 * i + 2],
              w3 = (Tacc)stencil[4 * i + 3];
-  const int xx = lane + 1;
-  const bool xact = xx <= n - 1, xin = xx <= n - 2;
-  // byte offsets of this lane's node in the rows y0 - 1 .. y0 + SW_TY of a
+  int xx[NX];
+  bool xact[NX], xin[NX];
+#pragma unroll
+  for (int k = 0; k < NX; ++k) {
+    xx[k] = lane + 1 + 64 * k;
+    xact[k] = xx[k] <= n - 1;
+    xin[k] = xx[k] <= n - 2;
+  }
+  // byte offsets of this lane's nodes in the rows y0 - 1 .. y0 + SW_TY of a
   // plane (clamped into the grid; 32-bit, so the loads take a scalar base)
-  unsigned roff[NR];
+  unsigned roff[NX][NR];
   bool rin[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int gy = y0 - 1 + r;
     rin[r] = gy >= 1 && gy <= n - 2;
-    roff[r] = (unsigned)(min(max(gy, 0), n - 1) * n + min(xx, n - 1)) * (unsigned)sizeof(Tv);
+#pragma unroll
+    for (int k = 0; k < NX; ++k)
+      roff[k][r] = (unsigned)(min(max(gy, 0), n - 1) * n + min(xx[k], n - 1)) * (unsigned)sizeof(Tv);
   }
-  Tv v[SW_PD][NR], v2[SUM ? SW_PD : 1][NR];
+  Tv v[SW_PD][NX][NR], v2[SUM ? SW_PD : 1][NX][NR];
   auto load = [&](int zp, int K) {
     const int64_t zb = (int64_t)min(max(zp, 0), n - 1) * nn;
     const char* P = (const char*)(X + zb);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) v[K][r] = *(const Tv*)(P + roff[r]);
+    for (int k = 0; k < NX; ++k)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) v[K][k][r] = *(const Tv*)(P + roff[k][r]);
     if (SUM) {
       const char* P2 = (const char*)(X2 + zb);
 #pragma unroll
-      for (int r = 0; r < NR; ++r) v2[SUM ? K : 0][r] = *(const Tv*)(P2 + roff[r]);
+      for (int k = 0; k < NX; ++k)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v2[SUM ? K : 0][k][r] = *(const Tv*)(P2 + roff[k][r]);
     }
   };
-  Tacc accp[SW_TY], accc[SW_TY], prev[SW_TY];  // partial outputs of planes zp - 1, zp; raw plane zp - 1
+  // partial outputs of planes zp - 1 and zp, raw plane zp - 1 (Dirichlet copies)
+  Tacc accp[NX][SW_TY], accc[NX][SW_TY], prev[NX][SW_TY];
 #pragma unroll
-  for (int t = 0; t < SW_TY; ++t) accp[t] = accc[t] = prev[t] = 0;
+  for (int k = 0; k < NX; ++k)
+#pragma unroll
+    for (int t = 0; t < SW_TY; ++t) accp[k][t] = accc[k][t] = prev[k][t] = 0;
   const int nsteps = zend - z0 + 2;  // step s reduces input plane zp = z0 - 1 + s
 #pragma unroll
   for (int K = 0; K < SW_PD; ++K) load(z0 - 1 + K, K);
@@ -261,32 +286,46 @@ __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict_
       const int s = s0 + K;
       const int zp = z0 - 1 + s;
       const bool zin = zp >= 1 && zp <= n - 2;
-      Tacc raw[NR], u[NR], sx[NR];
+      Tacc raw[NX][NR], u[NX][NR], sx[NX][NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        raw[r] = (Tacc)v[K][r];
-        if (SUM) raw[r] += (Tacc)v2[SUM ? K : 0][r];
-        u[r] = zin && rin[r] && xin ? raw[r] : (Tacc)0;  // interior nodes only
-        sx[r] = lane_from_left(u[r]) + lane_from_right(u[r]);
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+          raw[k][r] = (Tacc)v[K][k][r];
+          if (SUM) raw[k][r] += (Tacc)v2[SUM ? K : 0][k][r];
+          u[k][r] = zin && rin[r] && xin[k] ? raw[k][r] : (Tacc)0;  // interior nodes only
+        }
+        // across the two column blocks (x = 64 <-> x = 65), read in every lane
+        const Tacc x64 = NX == 2 ? lane_value(u[0][r], 63) : (Tacc)0;
+        const Tacc x65 = NX == 2 ? lane_value(u[NX - 1][r], 0) : (Tacc)0;
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+          Tacc lft = lane_from_left(u[k][r]), rgt = lane_from_right(u[k][r]);
+          if (NX == 2 && k == 1) lft = lane == 0 ? x64 : lft;
+          if (NX == 2 && k == 0) rgt = lane == 63 ? x65 : rgt;
+          sx[k][r] = lft + rgt;
+        }
       }
       const int zo = zp - 1;  // output plane completed in this step
       const bool st_ok = s < nsteps && zo >= z0;
       const bool bz = zo == 0 || zo == n - 1;
 #pragma unroll
-      for (int t = 0; t < SW_TY; ++t) {
-        const int r = t + 1;
-        const Tacc c = u[r], f = u[r - 1] + u[r + 1] + sx[r], e = sx[r - 1] + sx[r + 1];
-        const Tacc up = w1 * c + w2 * f + w3 * e;   // contribution to the planes zp - 1 and zp + 1
-        const Tacc mid = w0 * c + w1 * f + w2 * e;  // contribution to plane zp
-        const int gy = y0 + t;
-        if (st_ok && gy < n && xact) {
-          const bool bnd = bz || gy == 0 || gy == n - 1 || !xin;  // Dirichlet row: copy
-          Y[zo * nn + (int64_t)gy * n + xx] = (Tv)(bnd ? prev[t] : accp[t] + up);
+      for (int k = 0; k < NX; ++k)
+#pragma unroll
+        for (int t = 0; t < SW_TY; ++t) {
+          const int r = t + 1;
+          const Tacc c = u[k][r], f = u[k][r - 1] + u[k][r + 1] + sx[k][r], e = sx[k][r - 1] + sx[k][r + 1];
+          const Tacc up = w1 * c + w2 * f + w3 * e;   // contribution to the planes zp - 1 and zp + 1
+          const Tacc mid = w0 * c + w1 * f + w2 * e;  // contribution to plane zp
+          const int gy = y0 + t;
+          if (st_ok && gy < n && xact[k]) {
+            const bool bnd = bz || gy == 0 || gy == n - 1 || !xin[k];  // Dirichlet row: copy
+            Y[zo * nn + (int64_t)gy * n + xx[k]] = (Tv)(bnd ? prev[k][t] : accp[k][t] + up);
+          }
+          accp[k][t] = accc[k][t] + mid;  // output plane zp: planes zp - 1 and zp so far
+          accc[k][t] = up;                // output plane zp + 1: plane zp so far
+          prev[k][t] = raw[k][r];
         }
-        accp[t] = accc[t] + mid;  // output plane zp: planes zp - 1 and zp so far
-        accc[t] = up;             // output plane zp + 1: plane zp so far
-        prev[t] = raw[r];
-      }
       load(zp + SW_PD, K);
     }
   }
@@ -1439,8 +1478,12 @@ void launch_sweep(mdnp_sys* s, const T* x, T* y, const T* x2, const InstState* s
   const int nface = s->n_inst * ((n + SW_FZ - 1) / SW_FZ);
   const int ntile = nface + ytiles * nz * s->n_inst;
   const dim3 grid(xcd_grid((ntile + 3) / 4));
-  hipLaunchKernelGGL((k_stencil_sweep<T, T, SUM>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                     ytiles, zc, nface, ntile, st, mk, x2);
+  if (n <= 65)
+    hipLaunchKernelGGL((k_stencil_sweep<T, T, SUM, 1>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
+                       ytiles, zc, nface, ntile, st, mk, x2);
+  else
+    hipLaunchKernelGGL((k_stencil_sweep<T, T, SUM, 2>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
+                       ytiles, zc, nface, ntile, st, mk, x2);
 }
 
 template <typename T>

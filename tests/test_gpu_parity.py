@@ -64,6 +64,35 @@ def test_spmv_matches_oracle(ctx, vec):
         assert np.array_equal(rp, o.A.indptr) and np.array_equal(col, o.A.indices)
 
 
+@pytest.mark.parametrize("vec", ["f64", "f32"])
+@pytest.mark.parametrize("n_cells", [70, 96])
+def test_spmv_two_column_blocks(ctx, vec, n_cells):
+    """Grids of 66-129 nodes per side, where the stencil sweep gives each lane
+    two columns: A x and A00 x against the host assembly's CSR (itself equal to
+    the oracle's at the sizes above), FP64 on the CPU."""
+    P = _P()
+    insts = [synth.make_instance(950 + i, n_cells, n_segments=s, elems_per_segment=3, radius=0.01, beta=1.0)
+             for i, s in enumerate((5, 9))]
+    S = P.System(ctx, insts, vec_dtype=vec)
+    td = torch.float64 if vec == "f64" else torch.float32
+    x = synth.fast_normal(31, S.ntot)
+    if vec == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+    y = S.spmv(dev(x, td)).cpu().double().numpy()
+    x3 = np.concatenate([x[S.offsets[k]:S.offsets[k] + S.n3d] for k in range(len(insts))])
+    y3 = S.spmv(dev(x3, td), block=1).cpu().double().numpy()
+    tol = 1e-14 if vec == "f64" else 1e-6
+    for k in range(len(insts)):
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        rp, col, val = S.export_csr(k)
+        A = sp.csr_matrix((val, col, rp), shape=(o1 - o0, o1 - o0))
+        ref = A @ x[o0:o1]
+        assert np.linalg.norm(y[o0:o1] - ref) <= tol * np.linalg.norm(ref), k
+        ref3 = A[:S.n3d, :S.n3d] @ x3[k * S.n3d:(k + 1) * S.n3d]
+        got3 = y3[k * S.n3d:(k + 1) * S.n3d]
+        assert np.linalg.norm(got3 - ref3) <= tol * np.linalg.norm(ref3), k
+
+
 def test_spmv_a00_block(ctx):
     P = _P()
     insts = ragged_instances()
