@@ -244,8 +244,9 @@ class System:
     def autotune(self):
         """Time and fix the launch shapes: the z split / M blocks of each BF16
         layer ([0..10], by layer), the SpMV stencil sweep's z split ([11]) and
-        the output rows of L1b, D1, L0b, D0 ([12..15])."""
-        out = (C.c_int32 * 16)()
+        the output rows of L1b, D1, L0b, D0 ([12..15]) and the workgroups of
+        U1, U0 ([16], [17])."""
+        out = (C.c_int32 * 18)()
         self.ctx._check(lib.mdnp_autotune(self.ctx.h, self.h, out))
         return list(out)
 

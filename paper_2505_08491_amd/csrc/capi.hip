@@ -762,6 +762,8 @@ extern "C" mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* s, int32_t* chosen
       chosen[13] = s->cnn.tile_mb[7];
       chosen[14] = s->cnn.tile_mb[1];
       chosen[15] = s->cnn.tile_mb[9];
+      chosen[16] = s->cnn.tile_mb[6];
+      chosen[17] = s->cnn.tile_mb[8];
     }
   });
 }

@@ -699,8 +699,10 @@ template void cnn_apply_in_solver<double>(mdnp_sys*, const double*, double*, con
 // ---------------------------------------------------------------- autotuning
 
 // Chooses the launch shape of each BF16 layer on the system's own batch and
-// grid: for the sweep layers the workgroup count their z split aims at, for
-// the stride-2 and transposed layers the 16-voxel M blocks per wave.
+// grid: for the sweep layers the workgroup count their z split aims at and
+// their output rows per workgroup, for the stride-2 and transposed layers the
+// 16-voxel M blocks per wave, for the transposed layers also the workgroup
+// count (each workgroup stages its weights once and loops over voxel blocks).
 // Coordinate descent over the layers, each candidate timed as the best of
 // `reps` whole in-solver network applications with HIP events.  The shape only
 // decides which wave computes which outputs, in the same order of
@@ -708,13 +710,15 @@ template void cnn_apply_in_solver<double>(mdnp_sys*, const double*, double*, con
 struct TuneLayer {
   int layer, n;
   int cand[8];
-  int rows = 0;  // 1: the candidates are output rows per workgroup (tile_mb), else the launch target
+  int rows = 0;  // 1: the candidates go to tile_mb (output rows, or workgroups of U1 / U0), else to sweep_blocks
 };
 static const TuneLayer kTune[] = {
     {1, 4, {3, 4, 5, 6}, 1},                         // L0b  output rows per workgroup (per wave pair)
     {3, 4, {2, 3, 4, 6}, 1},                         // L1b
     {7, 2, {2, 3}, 1},                               // D1
     {9, 3, {3, 4, 5}, 1},                            // D0 (+ head)
+    {6, 5, {256, 512, 1024, 2048, 4096}, 1},         // U1   workgroups (each loops over voxel blocks)
+    {8, 5, {256, 512, 1024, 2048, 4096}, 1},         // U0
     {0, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // L0a  z split
     {1, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // L0b
     {2, 3, {2, 4, 8}},                               // L1a  M blocks per wave

@@ -1303,14 +1303,18 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
 // for the 8 offsets once, then for each parity p accumulates the taps of the
 // offsets o contained in p (27 (o, p) pairs in all) and stores the 16 output
 // voxels 2 q + p.  grid y = output channel block of 16.  Weights come as MFMA
-// fragments [27 tap][CIN / 32][COUT / 16][64 lanes][8] (one coalesced 1 KiB
-// load per fragment).
+// fragments [27 tap][CIN / 32][COUT / 16][64 lanes][8]; a workgroup copies the
+// fragments of its channel block into LDS once (27 KiB per 32 input channels)
+// and then takes several groups of WAVES x MB voxel blocks in turn, so the
+// weights cross L2 once per workgroup instead of once per wave.
 template <int CIN, int COUT, int MB>
 __global__ void __launch_bounds__(WAVES * 64) k_tconv_all(const bf16* __restrict__ src, const bf16* __restrict__ WF,
                                                          const float* __restrict__ bias, bf16* __restrict__ dst,
                                                          int n_in, const InstState* st, int want_mode) {
   constexpr int NB = COUT / 16;
   constexpr int CPT = CIN / 32;
+  constexpr int NFR = 27 * CPT;  // weight fragments of one output channel block
+  __shared__ u32x4 wl[NFR * 64];
   const int bt = blockIdx.z;
   if (st && !(st[bt].active && st[bt].mode == want_mode)) return;
   const int nb = blockIdx.y;
@@ -1319,66 +1323,74 @@ __global__ void __launch_bounds__(WAVES * 64) k_tconv_all(const bf16* __restrict
   const int64_t nvo = (int64_t)n_out * n_out * n_out;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, r = lane & 15;
-  const int64_t mb0 = ((int64_t)blockIdx.x * WAVES + wave) * MB;
-  if (mb0 * 16 >= nvi) return;
-  int64_t vin[MB], vout[MB];
-  unsigned okm[MB];  // bit 0: voxel exists; bits 1-3: q + 1 inside along x, y, z
-#pragma unroll
-  for (int m = 0; m < MB; ++m) {
-    const int64_t v = (mb0 + m) * 16 + r;
-    const bool ok = v < nvi;
-    const int64_t vc = ok ? v : 0;
-    const int qx = (int)(vc % n_in), qy = (int)((vc / n_in) % n_in), qz = (int)(vc / nn_in);
-    okm[m] = ok ? (1u | (qx + 1 < n_in ? 2u : 0u) | (qy + 1 < n_in ? 4u : 0u) | (qz + 1 < n_in ? 8u : 0u)) : 0u;
-    vin[m] = vc;
-    vout[m] = ((int64_t)(2 * qz) * n_out + 2 * qy) * n_out + 2 * qx;
-  }
+  // this block's weight fragments, once per workgroup, from [tap][cc][nb] to [tap][cc]
+  for (int q = threadIdx.x; q < NFR * 64; q += WAVES * 64)
+    wl[q] = ((const u32x4*)WF)[((q >> 6) * NB + nb) * 64 + (q & 63)];
+  __syncthreads();
   const bf16* X = src + (int64_t)bt * nvi * CIN;
-  bf16x8 xin[MB][8][CPT];
-#pragma unroll
-  for (int m = 0; m < MB; ++m)
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-      const unsigned need = 1u | (ox ? 2u : 0u) | (oy ? 4u : 0u) | (oz ? 8u : 0u);
-      const bool valid = (okm[m] & need) == need;
-      const int64_t vi = vin[m] + ox + oy * (int64_t)n_in + oz * nn_in;
-#pragma unroll
-      for (int cc = 0; cc < CPT; ++cc)
-        xin[m][o][cc] = valid ? load8(X + vi * CIN + cc * 32 + g * 8) : zero8();
-    }
-  const u32x4* wf = (const u32x4*)WF + lane;
   bf16* Y = dst + (int64_t)bt * nvo * COUT;
   const int co = nb * 16 + g * 4;
   const float b0 = bias[co], b1 = bias[co + 1], b2 = bias[co + 2], b3 = bias[co + 3];
-#pragma unroll
-  for (int p = 0; p < 8; ++p) {
-    const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
-    f32x4 acc[MB];
-#pragma unroll
-    for (int m = 0; m < MB; ++m) acc[m] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      if (o & ~p) continue;
-      const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-      const int tx = px ? (ox ? 0 : 2) : 1, ty = py ? (oy ? 0 : 2) : 1, tz = pz ? (oz ? 0 : 2) : 1;
-      const int tap = tz * 9 + ty * 3 + tx;
-#pragma unroll
-      for (int cc = 0; cc < CPT; ++cc) {
-        const bf16x8 w = __builtin_bit_cast(bf16x8, wf[((tap * CPT + cc) * NB + nb) * 64]);
-#pragma unroll
-        for (int m = 0; m < MB; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xin[m][o][cc], acc[m], 0, 0, 0);
-      }
-    }
-    const unsigned need = 1u | (px ? 2u : 0u) | (py ? 4u : 0u) | (pz ? 8u : 0u);
+  const int64_t nmb = (nvi + 15) / 16;
+  // the workgroups of one (nb, instance) take the groups of WAVES * MB blocks in turn
+  for (int64_t grp = blockIdx.x; grp * WAVES * MB < nmb; grp += gridDim.x) {
+    const int64_t mb0 = (grp * WAVES + wave) * MB;
+    if (mb0 >= nmb) continue;
+    int64_t vin[MB], vout[MB];
+    unsigned okm[MB];  // bit 0: voxel exists; bits 1-3: q + 1 inside along x, y, z
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
-      if ((okm[m] & need) != need) continue;
-      const int64_t vo = vout[m] + ((int64_t)pz * n_out + py) * n_out + px;
-      uint2 pk;
-      pk.x = (unsigned)f2bf(acc[m][0] + b0) | ((unsigned)f2bf(acc[m][1] + b1) << 16);
-      pk.y = (unsigned)f2bf(acc[m][2] + b2) | ((unsigned)f2bf(acc[m][3] + b3) << 16);
-      *(uint2*)(Y + vo * COUT + co) = pk;
+      const int64_t v = (mb0 + m) * 16 + r;
+      const bool ok = v < nvi;
+      const int64_t vc = ok ? v : 0;
+      const int qx = (int)(vc % n_in), qy = (int)((vc / n_in) % n_in), qz = (int)(vc / nn_in);
+      okm[m] = ok ? (1u | (qx + 1 < n_in ? 2u : 0u) | (qy + 1 < n_in ? 4u : 0u) | (qz + 1 < n_in ? 8u : 0u)) : 0u;
+      vin[m] = vc;
+      vout[m] = ((int64_t)(2 * qz) * n_out + 2 * qy) * n_out + 2 * qx;
+    }
+    bf16x8 xin[MB][8][CPT];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+        const unsigned need = 1u | (ox ? 2u : 0u) | (oy ? 4u : 0u) | (oz ? 8u : 0u);
+        const bool valid = (okm[m] & need) == need;
+        const int64_t vi = vin[m] + ox + oy * (int64_t)n_in + oz * nn_in;
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc)
+          xin[m][o][cc] = valid ? load8(X + vi * CIN + cc * 32 + g * 8) : zero8();
+      }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
+      f32x4 acc[MB];
+#pragma unroll
+      for (int m = 0; m < MB; ++m) acc[m] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        if (o & ~p) continue;
+        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+        const int tx = px ? (ox ? 0 : 2) : 1, ty = py ? (oy ? 0 : 2) : 1, tz = pz ? (oz ? 0 : 2) : 1;
+        const int tap = tz * 9 + ty * 3 + tx;
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+          const bf16x8 w = __builtin_bit_cast(bf16x8, wl[(tap * CPT + cc) * 64 + lane]);
+#pragma unroll
+          for (int m = 0; m < MB; ++m)
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xin[m][o][cc], acc[m], 0, 0, 0);
+        }
+      }
+      const unsigned need = 1u | (px ? 2u : 0u) | (py ? 4u : 0u) | (pz ? 8u : 0u);
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        if ((okm[m] & need) != need) continue;
+        const int64_t vo = vout[m] + ((int64_t)pz * n_out + py) * n_out + px;
+        uint2 pk;
+        pk.x = (unsigned)f2bf(acc[m][0] + b0) | ((unsigned)f2bf(acc[m][1] + b1) << 16);
+        pk.y = (unsigned)f2bf(acc[m][2] + b2) | ((unsigned)f2bf(acc[m][3] + b3) << 16);
+        *(uint2*)(Y + vo * COUT + co) = pk;
+      }
     }
   }
 }
@@ -1588,9 +1600,14 @@ void launch_conv(const ConvP& p, int batch, const bf16* w, hipStream_t stream) {
 }
 
 template <int CIN, int COUT, int MB>
-void launch_tconv_all(const ConvP& p, int batch, const bf16* wfrag, hipStream_t stream) {
+void launch_tconv_all(const ConvP& p, int batch, const bf16* wfrag, hipStream_t stream, int cap = 0) {
+  // workgroups per (channel block, instance): all groups of WAVES x MB blocks,
+  // or fewer that loop (cap = total workgroups aimed at; 0: 1024)
   const int64_t nmb = ((int64_t)p.n_in * p.n_in * p.n_in + 15) / 16;
-  const dim3 grid((unsigned)((nmb + WAVES * MB - 1) / (WAVES * MB)), COUT / 16, batch);
+  const int64_t groups = (nmb + WAVES * MB - 1) / (WAVES * MB);
+  const int target = cap > 0 ? cap : 1024;
+  const int64_t per = std::max<int64_t>(1, target / ((COUT / 16) * batch));
+  const dim3 grid((unsigned)std::min(groups, per), COUT / 16, batch);
   hipLaunchKernelGGL((k_tconv_all<CIN, COUT, MB>), grid, dim3(WAVES * 64), 0, stream, (const bf16*)p.a, wfrag, p.bias,
                      (bf16*)p.y, p.n_in, p.st, p.want_mode);
 }
@@ -1834,8 +1851,8 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
       break;
     }
     case 6:  // U1
-      if (c.sweep_blocks[6] == 2) launch_tconv_all<64, 32, 2>(p, batch, mfma_extra(c).tf_u1, stream);
-      else launch_tconv_all<64, 32, 1>(p, batch, mfma_extra(c).tf_u1, stream);
+      if (c.sweep_blocks[6] == 2) launch_tconv_all<64, 32, 2>(p, batch, mfma_extra(c).tf_u1, stream, c.tile_mb[6]);
+      else launch_tconv_all<64, 32, 1>(p, batch, mfma_extra(c).tf_u1, stream, c.tile_mb[6]);
       break;
     case 7: {                                                             // D1
       MfmaArgs a = args_from(p, w);
@@ -1846,9 +1863,9 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
       break;
     }
     case 8:  // U0
-      if (c.sweep_blocks[8] == 1) launch_tconv_all<32, 16, 1>(p, batch, mfma_extra(c).tf_u0, stream);
-      else if (c.sweep_blocks[8] == 4) launch_tconv_all<32, 16, 4>(p, batch, mfma_extra(c).tf_u0, stream);
-      else launch_tconv_all<32, 16, 2>(p, batch, mfma_extra(c).tf_u0, stream);
+      if (c.sweep_blocks[8] == 1) launch_tconv_all<32, 16, 1>(p, batch, mfma_extra(c).tf_u0, stream, c.tile_mb[8]);
+      else if (c.sweep_blocks[8] == 4) launch_tconv_all<32, 16, 4>(p, batch, mfma_extra(c).tf_u0, stream, c.tile_mb[8]);
+      else launch_tconv_all<32, 16, 2>(p, batch, mfma_extra(c).tf_u0, stream, c.tile_mb[8]);
       break;
     case 9: {                                                             // D0
       MfmaArgs a = args_from(p, w);

@@ -77,7 +77,8 @@ struct CnnState {
   // D0 = 9; 0: built-in default): for the sweep layers the workgroups their z
   // split aims at, for L1a, L2a, U1, U0 the 16-voxel M blocks per wave
   int sweep_blocks[11] = {};
-  // output rows per wave (pair) of the sweep layers L0b, L1b, D1, D0 (0: default)
+  // output rows per wave (pair) of the sweep layers L0b, L1b, D1, D0, and the
+  // workgroup count of the transposed layers U1, U0 (0: default)
   int tile_mb[11] = {};
 };
 
