@@ -632,6 +632,9 @@ struct RowsGrid {
   int ylo = 0, yhi = 0, zlo = 0, zhi = 0;  // output rows / planes computed
   int zc = 0, ytiles = 0;
   int nedge = 0;  // trailing workgroups per instance that compute the x = n - 1 column, one plane each
+  // k_conv16_ks: x ranges per row (each of xbn 16-column blocks) and the
+  // columns of a ring row (16 xbn + 2: the range and one halo column each side)
+  int nxs = 1, xw = 0;
 };
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -900,13 +903,15 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
     return;
   }
   const int n = p.n_out;
-  const int XW = n + 1;
+  const int XW = q.xw;
   const int y0 = q.ylo + (bxr % q.ytiles) * TYR;
-  const int z0 = q.zlo + (bxr / q.ytiles) * q.zc;
+  const int xh = (bxr / q.ytiles) % q.nxs;
+  const int z0 = q.zlo + (bxr / q.ytiles / q.nxs) * q.zc;
   const int zend = min(q.zhi, z0 + q.zc);
   const int64_t nn = (int64_t)n * n, nv = nn * n;
   const int nwaves = blockDim.x >> 6, xbn = nwaves >> 1;
-  const int plane_elems = (int)(T::plane_bytes(TYR, n) / 2);
+  const int x0 = xh * 16 * xbn;  // first output column of this workgroup
+  const int plane_elems = (int)(T::plane_bytes(TYR, XW - 1) / 2);
   const int plane_items = YW * XW * T::SLOTS;
   const int nload = (plane_items + 63) >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -944,8 +949,8 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
     if (L < nload && it < plane_items) {
       const int vt = it / T::SLOTS, ch = it - vt * T::SLOTS;
       const int row = vt / XW, xx = vt - row * XW;
-      const int gx = xx - 1, gy = y0 + row - 1;
-      if (ch < T::CPV && gy >= 0 && gy < n && gx >= 0) {
+      const int gx = x0 + xx - 1, gy = y0 + row - 1;
+      if (ch < T::CPV && gy >= 0 && gy < n && gx >= 0 && gx < n) {
         const int64_t vv = (int64_t)gy * n + gx;
         if (CB == 0 || ch < CPA) {
           o = (vv * CA + ch * 8) * 2;
@@ -1079,7 +1084,7 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
         for (int m = 0; m < MB; ++m) {
           const int y = y0 + rb0 + m;
           if (y >= q.yhi) continue;
-          const int64_t v = ((int64_t)z * n + y) * n + xl;
+          const int64_t v = ((int64_t)z * n + y) * n + x0 + xl;
           float y0v = acc[m][0] + bia[0], y1v = acc[m][1] + bia[1];
           float y2v = acc[m][2] + bia[2], y3v = acc[m][3] + bia[3];
           if (relu) {
@@ -1103,8 +1108,8 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
           h += __shfl_xor(h, 32, 64);
           const int y = y0 + rb0 + m;
           // Dirichlet nodes keep the value set before the network runs
-          if (g == 0 && y < q.yhi && y > 0 && y < n - 1 && xl > 0 && z > 0 && z < n - 1)
-            zo[((int64_t)z * n + y) * n + xl] = (Tv)(fsc * (h + bhv));
+          if (g == 0 && y < q.yhi && y > 0 && y < n - 1 && x0 + xl > 0 && z > 0 && z < n - 1)
+            zo[((int64_t)z * n + y) * n + x0 + xl] = (Tv)(fsc * (h + bhv));
         }
       }
     }
@@ -1142,14 +1147,16 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
     return;
   }
   const int n = p.n_out;
-  const int XW = n + 1;
+  const int XW = q.xw;
   const int y0 = q.ylo + (bxr % q.ytiles) * MB;
-  const int z0 = q.zlo + (bxr / q.ytiles) * q.zc;
+  const int xh = (bxr / q.ytiles) % q.nxs;
+  const int z0 = q.zlo + (bxr / q.ytiles / q.nxs) * q.zc;
   const int zend = min(q.zhi, z0 + q.zc);
   const int64_t nv = (int64_t)n * n * n;
   const int nthr = blockDim.x;
-  const int xbn = (n - 1) / 16;
-  const int plane_elems = (int)(T::plane_bytes(MB, n) / 2);
+  const int xbn = (XW - 2) / 16;  // x blocks of this workgroup
+  const int x0 = xh * 16 * xbn;   // its first output column
+  const int plane_elems = (int)(T::plane_bytes(MB, XW - 1) / 2);
   const int plane_items = YW * XW * CPV;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int g = lane >> 4, r = lane & 15;
@@ -1165,8 +1172,8 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
       if (it < plane_items) {
         const int vt = it / CPV, ch = it - vt * CPV;
         const int row = vt / XW, xx = vt - row * XW;
-        const int gx = xx - 1, gy = y0 + row - 1;
-        if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0) {
+        const int gx = x0 + xx - 1, gy = y0 + row - 1;
+        if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n) {
           const int64_t vv = ((int64_t)gz * n + gy) * n + gx;
           v = (CB == 0 || ch < CPA) ? *(const u32x4*)(A + vv * CA + ch * 8)
                                     : *(const u32x4*)(B + vv * CB + (ch - CPA) * 8);
@@ -1290,7 +1297,7 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
       uint2 pk;
       pk.x = (unsigned)f2bf(y0v) | ((unsigned)f2bf(y1v) << 16);
       pk.y = (unsigned)f2bf(y2v) | ((unsigned)f2bf(y3v) << 16);
-      const int64_t v = ((int64_t)z * n + y) * n + xl;
+      const int64_t v = ((int64_t)z * n + y) * n + x0 + xl;
       *(uint2*)(Y + v * COUT + co) = pk;
     }
   }
@@ -1511,10 +1518,15 @@ void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream, int target = 
   typedef RowsTile<CA + CB, 0> T;
   const int n = a.n_out;
   const int xb = (n - 1) / 16;
-  const size_t lds = 5 * T::plane_bytes(TYR, n) + (KS ? (size_t)2 * xb * MB * 64 * 16 : 0);
-  const int nload = ((TYR + 2) * (n + 1) * T::SLOTS + 63) / 64;
-  const bool fits = (n - 1) % 16 == 0 && xb >= 1 && xb <= 4 && lds <= 160 * 1024 && a.zero16 &&
-                    nload <= NLW * 2 * xb;
+  // x blocks per workgroup: the largest divisor of xb up to 4 (two waves each);
+  // wider grids take nxs workgroups per row range
+  int xbw = std::min(std::max(xb, 1), 4);
+  while (xb % xbw) --xbw;
+  const int nxs = xb / xbw;
+  const int xw = 16 * xbw + 2;
+  const size_t lds = 5 * T::plane_bytes(TYR, xw - 1) + (KS ? (size_t)2 * xbw * MB * 64 * 16 : 0);
+  const int nload = ((TYR + 2) * xw * T::SLOTS + 63) / 64;
+  const bool fits = (n - 1) % 16 == 0 && xb >= 1 && lds <= 160 * 1024 && a.zero16 && nload <= NLW * 2 * xbw;
   if (!fits) {
     launch_s1<CA, CB, 16, 0, EPI, Tv>(a, batch, stream);
     return;
@@ -1523,18 +1535,20 @@ void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream, int target = 
   q.ylo = q.zlo = EPI ? 1 : 0;
   q.yhi = q.zhi = EPI ? n - 1 : n;
   q.ytiles = (q.yhi - q.ylo + TYR - 1) / TYR;
+  q.nxs = nxs;
+  q.xw = xw;
   const int planes = q.zhi - q.zlo;
-  int nz = (target + q.ytiles * batch - 1) / (q.ytiles * batch);
+  int nz = (target + q.ytiles * nxs * batch - 1) / (q.ytiles * nxs * batch);
   nz = std::max(1, std::min(nz, planes));
   q.zc = (planes + nz - 1) / nz;
   nz = (planes + q.zc - 1) / q.zc;
   q.nedge = (!EPI && n <= 16 * kEdgeYB) ? n : 0;
-  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(2 * xb, n, 16) : (size_t)0);
+  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(2 * xbw, n, 16) : (size_t)0);
   auto kern = k_conv16_ks<CA, CB, MB, KS, EPI, Tv, NLW>;
   if (lds_all > 65536)
     hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_all);
-  hipLaunchKernelGGL(kern, dim3((unsigned)(q.nedge + q.ytiles * nz), 1, batch), dim3(2 * xb * 64), lds_all, stream,
-                     a, q);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(q.nedge + q.ytiles * nxs * nz), 1, batch), dim3(2 * xbw * 64), lds_all,
+                     stream, a, q);
   if (!EPI && !q.nedge) launch_edge<CA, CB, 16, 0, Tv>(a, batch, stream);
 }
 
@@ -1546,9 +1560,15 @@ void launch_convw(const MfmaArgs& a, int batch, hipStream_t stream, int target =
   constexpr int NF = MB * (COUT / 16);
   const int n = a.n_out;
   const int xb = (n - 1) / 16;
-  const size_t lds = 3 * T::plane_bytes(MB, n) + (size_t)KG * xb * NF * 1024;
-  const bool fits = (n - 1) % 16 == 0 && xb >= 1 && xb * KG <= 8 && lds <= 160 * 1024 &&
-                    (MB + 2) * (n + 1) * T::CPV <= NPF * xb * KG * 64;
+  // x blocks per workgroup: the largest divisor of xb with at most 8 waves;
+  // wider grids take nxs workgroups per row range
+  int xbw = std::min(std::max(xb, 1), std::max(1, 8 / KG));
+  while (xb % xbw) --xbw;
+  const int nxs = xb / xbw;
+  const int xw = 16 * xbw + 2;
+  const size_t lds = 3 * T::plane_bytes(MB, xw - 1) + (size_t)KG * xbw * NF * 1024;
+  const bool fits = (n - 1) % 16 == 0 && xb >= 1 && xbw * KG <= 8 && lds <= 160 * 1024 &&
+                    (MB + 2) * xw * T::CPV <= NPF * xbw * KG * 64;
   if (!fits) {
     launch_s1<CA, CB, COUT, 0, 0, float>(a, batch, stream);
     return;
@@ -1557,17 +1577,19 @@ void launch_convw(const MfmaArgs& a, int batch, hipStream_t stream, int target =
   q.ylo = q.zlo = 0;
   q.yhi = q.zhi = n;
   q.ytiles = (n + MB - 1) / MB;
-  int nz = (target + q.ytiles * batch - 1) / (q.ytiles * batch);
+  q.nxs = nxs;
+  q.xw = xw;
+  int nz = (target + q.ytiles * nxs * batch - 1) / (q.ytiles * nxs * batch);
   nz = std::max(1, std::min(nz, n));
   q.zc = (n + nz - 1) / nz;
   nz = (n + q.zc - 1) / q.zc;
   q.nedge = n <= 16 * kEdgeYB ? n : 0;
-  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(xb * KG, n, COUT) : (size_t)0);
+  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(xbw * KG, n, COUT) : (size_t)0);
   auto kern = k_convw<CA, CB, COUT, MB, KG, NPF>;
   if (lds_all > 65536)
     hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_all);
-  hipLaunchKernelGGL(kern, dim3((unsigned)(q.nedge + q.ytiles * nz), 1, batch), dim3(xb * KG * 64), lds_all, stream,
-                     a, q);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(q.nedge + q.ytiles * nxs * nz), 1, batch), dim3(xbw * KG * 64), lds_all,
+                     stream, a, q);
   if (!q.nedge) launch_edge<CA, CB, COUT, 0, float>(a, batch, stream);
 }
 
