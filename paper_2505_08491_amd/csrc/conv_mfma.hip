@@ -658,13 +658,15 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
     return;
   }
   const int n = p.n_out;
-  const int XW = n + 1;
+  const int XW = q.xw;
   const int y0 = q.ylo + (bxr % q.ytiles) * MB;
-  const int z0 = q.zlo + (bxr / q.ytiles) * q.zc;
+  const int xh = (bxr / q.ytiles) % q.nxs;
+  const int z0 = q.zlo + (bxr / q.ytiles / q.nxs) * q.zc;
   const int zend = min(q.zhi, z0 + q.zc);
   const int64_t nv = (int64_t)n * n * n;
   const int nthr = blockDim.x, nwaves = nthr >> 6;
-  const int plane_elems = (int)(T::plane_bytes(MB, n) / 2);
+  const int plane_elems = (int)(T::plane_bytes(MB, XW - 1) / 2);
+  const int x0 = xh * 16 * (int)(blockDim.x >> 6);  // first output column of this workgroup
   const int plane_items = YW * XW * T::SLOTS;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, r = lane & 15;
@@ -683,8 +685,8 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
       if (it < plane_items) {
         const int vt = it / T::SLOTS, ch = it - vt * T::SLOTS;
         const int row = vt / XW, xx = vt - row * XW;
-        const int gx = xx - 1, gy = y0 + row - 1;
-        if (ch < T::CPV && gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0) {
+        const int gx = x0 + xx - 1, gy = y0 + row - 1;
+        if (ch < T::CPV && gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n) {
           const int64_t vv = ((int64_t)gz * n + gy) * n + gx;
           constexpr int CPA = CA / 8;
           src = (CB == 0 || ch < CPA) ? (const void*)(A + vv * CA + ch * 8)
@@ -702,8 +704,8 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
       u32x4 v = {0u, 0u, 0u, 0u};
       if (it < plane_items) {
         const int row = it / XW, xx = it - row * XW;
-        const int gx = xx - 1, gy = y0 + row - 1;
-        if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0) {
+        const int gx = x0 + xx - 1, gy = y0 + row - 1;
+        if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n) {
           const int64_t vv = ((int64_t)gz * n + gy) * n + gx;
           v.x = (unsigned)f2bf((float)Z[vv] * sc) | ((unsigned)f2bf(D[vv]) << 16);
         }
@@ -825,7 +827,7 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
       for (int m = 0; m < MB; ++m) {
         const int y = y0 + m;
         if (y >= q.yhi) continue;
-        const int64_t v = ((int64_t)z * n + y) * n + xl;
+        const int64_t v = ((int64_t)z * n + y) * n + x0 + xl;
         float y0v = acc[m][0] + p.bias[co], y1v = acc[m][1] + p.bias[co + 1];
         float y2v = acc[m][2] + p.bias[co + 2], y3v = acc[m][3] + p.bias[co + 3];
         if (p.relu) {
@@ -853,8 +855,8 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
         h += __shfl_xor(h, 32, 64);
         const int y = y0 + m;
         // Dirichlet nodes keep the value set before the network runs
-        if (g == 0 && y < q.yhi && y > 0 && y < n - 1 && xl > 0 && z > 0 && z < n - 1)
-          zo[((int64_t)z * n + y) * n + xl] = (Tv)(f * (h + p.bh[0]));
+        if (g == 0 && y < q.yhi && y > 0 && y < n - 1 && x0 + xl > 0 && z > 0 && z < n - 1)
+          zo[((int64_t)z * n + y) * n + x0 + xl] = (Tv)(f * (h + p.bh[0]));
       }
     }
     if (!IN) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -1471,7 +1473,8 @@ void launch_rows16_npf(const MfmaArgs& a, const RowsGrid& q, int batch, size_t l
   auto kern = k_conv16_rows<CA, CB, MB, IN, EPI, Tv, NPF>;
   if (lds > 65536) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const int nz = (q.zhi - q.zlo + q.zc - 1) / q.zc;
-  hipLaunchKernelGGL(kern, dim3((unsigned)(q.nedge + q.ytiles * nz), 1, batch), dim3(xb * 64), lds, stream, a, q);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(q.nedge + q.ytiles * q.nxs * nz), 1, batch), dim3(xb * 64), lds, stream,
+                     a, q);
 }
 
 template <int CA, int CB, int MB, int IN, int EPI, typename Tv, int NPF0, int NPF1>
@@ -1480,9 +1483,15 @@ void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream, int target 
   typedef RowsTile<CL, IN> T;
   const int n = a.n_out;
   const int xb = (n - 1) / 16;
-  const size_t lds = (size_t)T::NRING * T::plane_bytes(MB, n);
-  const bool fits = (n - 1) % 16 == 0 && xb >= 1 && xb <= 4 && lds <= 160 * 1024 && (IN || a.zero16);
-  const int need = fits ? ((MB + 2) * (n + 1) * T::SLOTS + xb * 64 - 1) / (xb * 64) : 0;
+  // x blocks (one wave each) per workgroup: the largest divisor of xb up to 4;
+  // wider grids take nxs workgroups per row range
+  int xbw = std::min(std::max(xb, 1), 4);
+  while (xb % xbw) --xbw;
+  const int nxs = xb / xbw;
+  const int xw = 16 * xbw + 2;
+  const size_t lds = (size_t)T::NRING * T::plane_bytes(MB, xw - 1);
+  const bool fits = (n - 1) % 16 == 0 && xb >= 1 && lds <= 160 * 1024 && (IN || a.zero16);
+  const int need = fits ? ((MB + 2) * xw * T::SLOTS + xbw * 64 - 1) / (xbw * 64) : 0;
   if (!fits || (IN && need > NPF1)) {
     launch_s1<IN ? 8 : CA, CB, 16, IN, EPI, Tv>(a, batch, stream);
     return;
@@ -1491,19 +1500,21 @@ void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream, int target 
   q.ylo = q.zlo = EPI ? 1 : 0;
   q.yhi = q.zhi = EPI ? n - 1 : n;
   q.ytiles = (q.yhi - q.ylo + MB - 1) / MB;
+  q.nxs = nxs;
+  q.xw = xw;
   const int planes = q.zhi - q.zlo;
   // about four workgroups per compute unit over the batch
-  int nz = (target + q.ytiles * batch - 1) / (q.ytiles * batch);
+  int nz = (target + q.ytiles * nxs * batch - 1) / (q.ytiles * nxs * batch);
   nz = std::max(1, std::min(nz, planes));
   q.zc = (planes + nz - 1) / nz;
   // the x = n - 1 column in extra workgroups (not needed with the head: Dirichlet)
   q.nedge = (!EPI && n <= 16 * kEdgeYB) ? n : 0;
-  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(xb, n, 16) : (size_t)0);
+  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(xbw, n, 16) : (size_t)0);
   if constexpr (!IN) {
-    launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, 1>(a, q, batch, lds_all, xb, stream);
+    launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, 1>(a, q, batch, lds_all, xbw, stream);
   } else {
-    if (need <= NPF0) launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF0>(a, q, batch, lds_all, xb, stream);
-    else launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF1>(a, q, batch, lds_all, xb, stream);
+    if (need <= NPF0) launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF0>(a, q, batch, lds_all, xbw, stream);
+    else launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, NPF1>(a, q, batch, lds_all, xbw, stream);
   }
   if (!EPI && !q.nedge) launch_edge<IN ? 8 : CA, CB, 16, IN, Tv>(a, batch, stream);
 }
