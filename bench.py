@@ -352,7 +352,8 @@ def main():
         "upload_s": t_upload,
         "autotune": {"conv_sweep_blocks": tuned[:11], "spmv_sweep_target": tuned[11],
                      "conv_rows_l1b_d1_l0b_d0": tuned[12:16],
-                     "tconv_workgroups_u1_u0": tuned[16:18], "s": t_tune} if tuned else None,
+                     "tconv_workgroups_u1_u0": tuned[16:18],
+                     "conv_xblocks_l0a_l0b_l1b_d1_d0": tuned[18:23], "s": t_tune} if tuned else None,
     }
     if not a.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(insts[0], float(np.mean(neural_iters)),

@@ -196,17 +196,19 @@ mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* sys, int32_t steps);
  * M blocks per wave of the stride-2 and transposed layers (L1a {2, 4, 8}, L2a
  * {1, 2, 4}, U1 {1, 2}, U0 {1, 2, 4}) and the output rows of the sweep
  * layers L1b {2, 3, 4, 6}, D1 {2, 3} (per workgroup), L0b {3, 4, 5, 6} and
- * D0 {3, 4, 5} (per wave pair), and the workgroup count of U1 and U0
+ * D0 {3, 4, 5} (per wave pair), the workgroup count of U1 and U0
  * ({256 .. 4096}; each workgroup stages its weights in LDS and loops over
- * voxel blocks);
+ * voxel blocks) and the 16-column x blocks per workgroup of L0a, L0b, D0
+ * {1, 2, 4} and L1b, D1 {1, 2} (rows wider than that split over workgroups);
  * coordinate descent, best of 5 whole network applications.
  * The choices only move output planes between waves and workgroups: results
- * are unchanged.  They are kept with the system; `chosen` (nullable, [18])
+ * are unchanged.  They are kept with the system; `chosen` (nullable, [23])
  * receives them: [0 .. 10] the z split or M blocks of the convolution layers
  * L0a = 0 .. H = 10 (0 = the built-in default, always for H), [11] the SpMV
  * sweep target (0 = default; also 0 where the grid has more than 65 nodes per
  * side and no sweep is used), [12 .. 15] the output rows of L1b, D1, L0b,
- * D0, [16], [17] the workgroups of U1, U0.  The library
+ * D0, [16], [17] the workgroups of U1, U0, [18 .. 22] the x blocks per
+ * workgroup of L0a, L0b, L1b, D1, D0 (0 = as many as fit).  The library
  * allocates two vectors of the system's size for the timing and frees them
  * before returning.  Errors: MDNP_E_OOM if those buffers cannot be allocated
  * (the defaults are kept). */

@@ -244,9 +244,10 @@ class System:
     def autotune(self):
         """Time and fix the launch shapes: the z split / M blocks of each BF16
         layer ([0..10], by layer), the SpMV stencil sweep's z split ([11]) and
-        the output rows of L1b, D1, L0b, D0 ([12..15]) and the workgroups of
-        U1, U0 ([16], [17])."""
-        out = (C.c_int32 * 18)()
+        the output rows of L1b, D1, L0b, D0 ([12..15]), the workgroups of
+        U1, U0 ([16], [17]) and the x blocks per workgroup of L0a, L0b, L1b,
+        D1, D0 ([18..22])."""
+        out = (C.c_int32 * 23)()
         self.ctx._check(lib.mdnp_autotune(self.ctx.h, self.h, out))
         return list(out)
 

@@ -764,6 +764,8 @@ extern "C" mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* s, int32_t* chosen
       chosen[15] = s->cnn.tile_mb[9];
       chosen[16] = s->cnn.tile_mb[6];
       chosen[17] = s->cnn.tile_mb[8];
+      const int xl[5] = {0, 1, 3, 7, 9};
+      for (int k = 0; k < 5; ++k) chosen[18 + k] = s->cnn.tile_xb[xl[k]];
     }
   });
 }

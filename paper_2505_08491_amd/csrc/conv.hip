@@ -710,7 +710,7 @@ template void cnn_apply_in_solver<double>(mdnp_sys*, const double*, double*, con
 struct TuneLayer {
   int layer, n;
   int cand[8];
-  int rows = 0;  // 1: the candidates go to tile_mb (output rows, or workgroups of U1 / U0), else to sweep_blocks
+  int rows = 0;  // 1: the candidates go to tile_mb (output rows, or workgroups of U1 / U0), 2: to tile_xb, else to sweep_blocks
 };
 static const TuneLayer kTune[] = {
     {1, 4, {3, 4, 5, 6}, 1},                         // L0b  output rows per workgroup (per wave pair)
@@ -718,6 +718,11 @@ static const TuneLayer kTune[] = {
     {7, 2, {2, 3}, 1},                               // D1
     {9, 3, {3, 4, 5}, 1},                            // D0 (+ head)
     {6, 5, {256, 512, 1024, 2048, 4096}, 1},         // U1   workgroups (each loops over voxel blocks)
+    {0, 3, {1, 2, 4}, 2},                            // L0a  x blocks per workgroup
+    {1, 3, {1, 2, 4}, 2},                            // L0b
+    {3, 2, {1, 2}, 2},                               // L1b
+    {7, 2, {1, 2}, 2},                               // D1
+    {9, 3, {1, 2, 4}, 2},                            // D0
     {8, 5, {256, 512, 1024, 2048, 4096}, 1},         // U0
     {0, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // L0a  z split
     {1, 7, {256, 384, 512, 768, 1024, 1536, 2048}},  // L0b
@@ -765,7 +770,7 @@ static bool autotune_t(mdnp_sys* s, hipStream_t stream, int reps) {
     time_once();  // warm-up
     for (const TuneLayer& tl : kTune) {
       const int layer = tl.layer;
-      int* slot = tl.rows ? &c.tile_mb[layer] : &c.sweep_blocks[layer];
+      int* slot = tl.rows == 1 ? &c.tile_mb[layer] : tl.rows == 2 ? &c.tile_xb[layer] : &c.sweep_blocks[layer];
       int best_t = *slot;
       float best = 1e30f;
       for (int q = 0; q < tl.n; ++q) {

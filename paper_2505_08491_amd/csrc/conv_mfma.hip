@@ -244,6 +244,8 @@ __global__ void __launch_bounds__(WAVES * 64) k_conv_mfma(MfmaArgs p) {
 // block) fragments in turn (bias, ReLU, BF16 store).  IN = 1 builds the first
 // layer's input.  Called by the sweep kernels' extra workgroups and by
 // k_conv_edge.
+constexpr int kEdgeGroups = 8;  // partial sums of the edge column's K loop
+
 template <int CA, int CB, int COUT, int IN, typename Tv, int YBM>
 __device__ __forceinline__ void edge_plane(const MfmaArgs& p, int oz, int bt, f32x4* red) {
   constexpr int CIN = CA + CB;
@@ -277,54 +279,59 @@ __device__ __forceinline__ void edge_plane(const MfmaArgs& p, int oz, int bt, f3
   const Tv* Z = IN ? (const Tv*)p.z + p.off[bt] : nullptr;
   const float* D = IN ? p.dist + (int64_t)bt * nv : nullptr;
   const float sc = IN ? (float)p.inv_s[bt] : 0.0f;
-  f32x4 acc[YBM][NB];
+  // K chunks c = k mod kEdgeGroups form partial sum k, summed in the order
+  // k = 0, 1, ... whatever the number of waves, so the column does not depend
+  // on the workgroup shape of the launch that computes it
+  for (int kg = wave; kg < kEdgeGroups; kg += nw) {
+    f32x4 acc[YBM][NB];
 #pragma unroll
-  for (int m = 0; m < YBM; ++m)
+    for (int m = 0; m < YBM; ++m)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[m][nb] = {0.f, 0.f, 0.f, 0.f};
-  for (int c = wave; c < KCH; c += nw) {
-    const int k0 = c * 32 + g * 8;
-    const int tap = k0 / CIN;
-    const int ci = k0 - tap * CIN;
-    const bool tap_ok = tap < 27;
-    const int tz = tap / 9, ty = (tap / 3) % 3, tx = tap % 3;
-    const unsigned need = (1u << tx) | (8u << ty) | (64u << tz);
-    const int64_t toff = (int64_t)(tz - 1) * nn + (int64_t)(ty - 1) * n + (tx - 1);
-    bf16x8 wf[NB];
+      for (int nb = 0; nb < NB; ++nb) acc[m][nb] = {0.f, 0.f, 0.f, 0.f};
+    for (int c = kg; c < KCH; c += kEdgeGroups) {
+      const int k0 = c * 32 + g * 8;
+      const int tap = k0 / CIN;
+      const int ci = k0 - tap * CIN;
+      const bool tap_ok = tap < 27;
+      const int tz = tap / 9, ty = (tap / 3) % 3, tx = tap % 3;
+      const unsigned need = (1u << tx) | (8u << ty) | (64u << tz);
+      const int64_t toff = (int64_t)(tz - 1) * nn + (int64_t)(ty - 1) * n + (tx - 1);
+      bf16x8 wf[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-      wf[nb] = tap_ok ? load8(p.w + ((int64_t)(nb * 16 + r) * 27 + tap) * CIN + ci) : zero8();
-    bf16x8 x[YBM];
+      for (int nb = 0; nb < NB; ++nb)
+        wf[nb] = tap_ok ? load8(p.w + ((int64_t)(nb * 16 + r) * 27 + tap) * CIN + ci) : zero8();
+      bf16x8 x[YBM];
 #pragma unroll
-    for (int m = 0; m < YBM; ++m) {
-      x[m] = zero8();
-      if (tap_ok && (msk[m] & need) == need) {
-        const int64_t vin = base[m] + toff;
-        if (IN) x[m] = pack2((float)Z[vin] * sc, D[vin]);
-        else if (CB == 0 || ci < CA) x[m] = load8(A + vin * CA + ci);
-        else x[m] = load8(B + vin * CB + (ci - CA));
+      for (int m = 0; m < YBM; ++m) {
+        x[m] = zero8();
+        if (tap_ok && (msk[m] & need) == need) {
+          const int64_t vin = base[m] + toff;
+          if (IN) x[m] = pack2((float)Z[vin] * sc, D[vin]);
+          else if (CB == 0 || ci < CA) x[m] = load8(A + vin * CA + ci);
+          else x[m] = load8(B + vin * CB + (ci - CA));
+        }
       }
+#pragma unroll
+      for (int m = 0; m < YBM; ++m)
+        if (m < nyb) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[nb], x[m], acc[m][nb], 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int m = 0; m < YBM; ++m)
       if (m < nyb) {
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[nb], x[m], acc[m][nb], 0, 0, 0);
+        for (int nb = 0; nb < NB; ++nb) red[((kg * nyb + m) * NB + nb) * 64 + lane] = acc[m][nb];
       }
   }
-#pragma unroll
-  for (int m = 0; m < YBM; ++m)
-    if (m < nyb) {
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) red[((wave * nyb + m) * NB + nb) * 64 + lane] = acc[m][nb];
-    }
   __syncthreads();
   bf16* Y = p.y + (int64_t)bt * nv * COUT;
   for (int f = wave; f < nyb * NB; f += nw) {
     const int m = f / NB, nb = f - m * NB;
     f32x4 sum = red[(m * NB + nb) * 64 + lane];
-    for (int w = 1; w < nw; ++w) {
+    for (int w = 1; w < kEdgeGroups; ++w) {
       const f32x4 o = red[((w * nyb + m) * NB + nb) * 64 + lane];
       sum += o;
     }
@@ -355,16 +362,16 @@ __global__ void __launch_bounds__(KSW * 64) k_conv_edge(MfmaArgs p) {
 }
 
 // Largest n whose edge column the sweep kernels take in extra workgroups, and
-// the LDS those workgroups need.
+// the LDS those workgroups need (one partial sum per K-chunk group).
 constexpr int kEdgeYB = 5;
-inline size_t edge_lds_bytes(int nwaves, int n, int cout) {
-  return (size_t)nwaves * ((n + 15) / 16) * (cout / 16) * 64 * 16;
+inline size_t edge_lds_bytes(int n, int cout) {
+  return (size_t)kEdgeGroups * ((n + 15) / 16) * (cout / 16) * 64 * 16;
 }
 
 template <int CA, int CB, int COUT, int IN, typename Tv>
 void launch_edge(const MfmaArgs& a, int batch, hipStream_t stream) {
   constexpr int KSW = 8, YB = 5;  // up to 80 rows: n <= 80
-  constexpr size_t lds = (size_t)KSW * YB * (COUT / 16) * 64 * 16;
+  constexpr size_t lds = (size_t)kEdgeGroups * YB * (COUT / 16) * 64 * 16;
   static_assert(lds <= 160 * 1024, "edge partials exceed LDS");
   const int n = a.n_out;
   if (n > 16 * YB) {  // the global-load kernel's edge mode
@@ -1478,14 +1485,14 @@ void launch_rows16_npf(const MfmaArgs& a, const RowsGrid& q, int batch, size_t l
 }
 
 template <int CA, int CB, int MB, int IN, int EPI, typename Tv, int NPF0, int NPF1>
-void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream, int target = 1024) {
+void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream, int target = 1024, int xbmax = 0) {
   constexpr int CL = IN ? 2 : CA + CB;
   typedef RowsTile<CL, IN> T;
   const int n = a.n_out;
   const int xb = (n - 1) / 16;
-  // x blocks (one wave each) per workgroup: the largest divisor of xb up to 4;
-  // wider grids take nxs workgroups per row range
-  int xbw = std::min(std::max(xb, 1), 4);
+  // x blocks (one wave each) per workgroup: the largest divisor of xb up to 4
+  // (or xbmax); wider grids take nxs workgroups per row range
+  int xbw = std::min(std::max(xb, 1), xbmax > 0 ? std::min(xbmax, 4) : 4);
   while (xb % xbw) --xbw;
   const int nxs = xb / xbw;
   const int xw = 16 * xbw + 2;
@@ -1509,7 +1516,7 @@ void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream, int target 
   q.zc = (planes + nz - 1) / nz;
   // the x = n - 1 column in extra workgroups (not needed with the head: Dirichlet)
   q.nedge = (!EPI && n <= 16 * kEdgeYB) ? n : 0;
-  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(xbw, n, 16) : (size_t)0);
+  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(n, 16) : (size_t)0);
   if constexpr (!IN) {
     launch_rows16_npf<CA, CB, MB, IN, EPI, Tv, 1>(a, q, batch, lds_all, xbw, stream);
   } else {
@@ -1523,15 +1530,15 @@ void launch_rows16(const MfmaArgs& a, int batch, hipStream_t stream, int target 
 // the EDGE kernel for x = n - 1 (not needed with the head: that column is
 // Dirichlet).
 template <int CA, int CB, int MB, int KS, int EPI, typename Tv>
-void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream, int target = 1024) {
+void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream, int target = 1024, int xbmax = 0) {
   constexpr int NLW = 4;
   constexpr int TYR = KS ? MB : 2 * MB;
   typedef RowsTile<CA + CB, 0> T;
   const int n = a.n_out;
   const int xb = (n - 1) / 16;
-  // x blocks per workgroup: the largest divisor of xb up to 4 (two waves each);
-  // wider grids take nxs workgroups per row range
-  int xbw = std::min(std::max(xb, 1), 4);
+  // x blocks per workgroup: the largest divisor of xb up to 4 (or xbmax; two
+  // waves each); wider grids take nxs workgroups per row range
+  int xbw = std::min(std::max(xb, 1), xbmax > 0 ? std::min(xbmax, 4) : 4);
   while (xb % xbw) --xbw;
   const int nxs = xb / xbw;
   const int xw = 16 * xbw + 2;
@@ -1554,7 +1561,7 @@ void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream, int target = 
   q.zc = (planes + nz - 1) / nz;
   nz = (planes + q.zc - 1) / q.zc;
   q.nedge = (!EPI && n <= 16 * kEdgeYB) ? n : 0;
-  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(2 * xbw, n, 16) : (size_t)0);
+  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(n, 16) : (size_t)0);
   auto kern = k_conv16_ks<CA, CB, MB, KS, EPI, Tv, NLW>;
   if (lds_all > 65536)
     hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_all);
@@ -1566,14 +1573,14 @@ void launch_ks16(const MfmaArgs& a, int batch, hipStream_t stream, int target = 
 // Coarse-level stride-1 layers (COUT = 32 or 64): the K-split sweep for
 // x < n - 1 plus the EDGE kernel for x = n - 1; launch_s1 where it does not fit.
 template <int CA, int CB, int COUT, int MB, int KG, int NPF>
-void launch_convw(const MfmaArgs& a, int batch, hipStream_t stream, int target = 1024) {
+void launch_convw(const MfmaArgs& a, int batch, hipStream_t stream, int target = 1024, int xbmax = 0) {
   typedef RowsTile<CA + CB, 0> T;
   constexpr int NF = MB * (COUT / 16);
   const int n = a.n_out;
   const int xb = (n - 1) / 16;
-  // x blocks per workgroup: the largest divisor of xb with at most 8 waves;
-  // wider grids take nxs workgroups per row range
-  int xbw = std::min(std::max(xb, 1), std::max(1, 8 / KG));
+  // x blocks per workgroup: the largest divisor of xb with at most 8 waves (or
+  // xbmax blocks); wider grids take nxs workgroups per row range
+  int xbw = std::min(std::max(xb, 1), std::max(1, xbmax > 0 ? std::min(xbmax, 8 / KG) : 8 / KG));
   while (xb % xbw) --xbw;
   const int nxs = xb / xbw;
   const int xw = 16 * xbw + 2;
@@ -1595,7 +1602,7 @@ void launch_convw(const MfmaArgs& a, int batch, hipStream_t stream, int target =
   q.zc = (n + nz - 1) / nz;
   nz = (n + q.zc - 1) / q.zc;
   q.nedge = n <= 16 * kEdgeYB ? n : 0;
-  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(xbw * KG, n, COUT) : (size_t)0);
+  const size_t lds_all = std::max(lds, q.nedge ? edge_lds_bytes(n, COUT) : (size_t)0);
   auto kern = k_convw<CA, CB, COUT, MB, KG, NPF>;
   if (lds_all > 65536)
     hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_all);
@@ -1797,7 +1804,7 @@ void conv_mfma_in0(const CnnState& c, const Tv* z, const int64_t* off, const dou
   a.inv_s = inv_s;
   a.dist = dist;
   (void)nmb;
-  launch_rows16<0, 0, 5, 1, 0, Tv, 2, 4>(a, batch, stream, sweep_target(c, 0, 1024));
+  launch_rows16<0, 0, 5, 1, 0, Tv, 2, 4>(a, batch, stream, sweep_target(c, 0, 1024), c.tile_xb[0]);
 }
 template void conv_mfma_in0<float>(const CnnState&, const float*, const int64_t*, const double*, const float*, int,
                                    int, bf16*, const InstState*, hipStream_t);
@@ -1831,9 +1838,10 @@ void conv_mfma_d0_head(const CnnState& c, const bf16* u0, const bf16* s0, int n,
   a.scale = scale;
   (void)nmb;
   const int t = sweep_target(c, 9, kSweepBlocksD0);
-  if (c.tile_mb[9] == 3) launch_ks16<16, 16, 3, 1, 1, Tv>(a, batch, stream, t);
-  else if (c.tile_mb[9] == 5) launch_ks16<16, 16, 5, 1, 1, Tv>(a, batch, stream, t);
-  else launch_ks16<16, 16, 4, 1, 1, Tv>(a, batch, stream, t);
+  const int xm = c.tile_xb[9];
+  if (c.tile_mb[9] == 3) launch_ks16<16, 16, 3, 1, 1, Tv>(a, batch, stream, t, xm);
+  else if (c.tile_mb[9] == 5) launch_ks16<16, 16, 5, 1, 1, Tv>(a, batch, stream, t, xm);
+  else launch_ks16<16, 16, 4, 1, 1, Tv>(a, batch, stream, t, xm);
 }
 template void conv_mfma_d0_head<float>(const CnnState&, const bf16*, const bf16*, int, int, float*, const int64_t*,
                                        const double*, double, const double*, const InstState*, hipStream_t);
@@ -1851,10 +1859,11 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
       a.wrows = mfma_extra(c).rows_l0b;
       a.zero16 = mfma_extra(c).zeros;
       const int t = sweep_target(c, 1, 1024);
-      if (c.tile_mb[1] == 3) launch_ks16<16, 0, 3, 0, 0, float>(a, batch, stream, t);
-      else if (c.tile_mb[1] == 5) launch_ks16<16, 0, 5, 0, 0, float>(a, batch, stream, t);
-      else if (c.tile_mb[1] == 6) launch_ks16<16, 0, 6, 0, 0, float>(a, batch, stream, t);
-      else launch_ks16<16, 0, 4, 0, 0, float>(a, batch, stream, t);
+      const int xm = c.tile_xb[1];
+      if (c.tile_mb[1] == 3) launch_ks16<16, 0, 3, 0, 0, float>(a, batch, stream, t, xm);
+      else if (c.tile_mb[1] == 5) launch_ks16<16, 0, 5, 0, 0, float>(a, batch, stream, t, xm);
+      else if (c.tile_mb[1] == 6) launch_ks16<16, 0, 6, 0, 0, float>(a, batch, stream, t, xm);
+      else launch_ks16<16, 0, 4, 0, 0, float>(a, batch, stream, t, xm);
       break;
     }
     case 2:  // L1a: M blocks per wave chosen by the autotuner
@@ -1866,10 +1875,11 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_l1b;
       const int t = sweep_target(c, 3, 1024);
-      if (c.tile_mb[3] == 2) launch_convw<32, 0, 32, 2, 4, 2>(a, batch, stream, t);
-      else if (c.tile_mb[3] == 4) launch_convw<32, 0, 32, 4, 4, 2>(a, batch, stream, t);
-      else if (c.tile_mb[3] == 6) launch_convw<32, 0, 32, 6, 4, 3>(a, batch, stream, t);
-      else launch_convw<32, 0, 32, 3, 4, 2>(a, batch, stream, t);
+      const int xm = c.tile_xb[3];
+      if (c.tile_mb[3] == 2) launch_convw<32, 0, 32, 2, 4, 2>(a, batch, stream, t, xm);
+      else if (c.tile_mb[3] == 4) launch_convw<32, 0, 32, 4, 4, 2>(a, batch, stream, t, xm);
+      else if (c.tile_mb[3] == 6) launch_convw<32, 0, 32, 6, 4, 3>(a, batch, stream, t, xm);
+      else launch_convw<32, 0, 32, 3, 4, 2>(a, batch, stream, t, xm);
       break;
     }
     case 4:  // L2a
@@ -1891,8 +1901,8 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_d1;
       const int t = sweep_target(c, 7, 1024);
-      if (c.tile_mb[7] == 2) launch_convw<32, 32, 32, 2, 4, 3>(a, batch, stream, t);
-      else launch_convw<32, 32, 32, 3, 4, 3>(a, batch, stream, t);
+      if (c.tile_mb[7] == 2) launch_convw<32, 32, 32, 2, 4, 3>(a, batch, stream, t, c.tile_xb[7]);
+      else launch_convw<32, 32, 32, 3, 4, 3>(a, batch, stream, t, c.tile_xb[7]);
       break;
     }
     case 8:  // U0

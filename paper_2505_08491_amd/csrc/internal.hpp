@@ -80,6 +80,9 @@ struct CnnState {
   // output rows per wave (pair) of the sweep layers L0b, L1b, D1, D0, and the
   // workgroup count of the transposed layers U1, U0 (0: default)
   int tile_mb[11] = {};
+  // 16-column x blocks per workgroup of the sweep layers L0a, L0b, L1b, D1, D0
+  // (0: as many as fit; fewer splits each row over more workgroups)
+  int tile_xb[11] = {};
 };
 
 // Jacobi pre/post-smoothing of the neural 3D solve (sweeps = 0: off) and its
