@@ -111,10 +111,20 @@ void free_blocks(Blocks& B) {
   B = Blocks();
 }
 
+// Captured graphs hold the launch shapes and buffers of the time they were
+// taken: dropped whenever either changes.
+void drop_graphs(SolveWork& w) {
+  for (hipGraphExec_t g : w.graphs) (void)hipGraphExecDestroy(g);
+  w.graphs.clear();
+  w.graph_m = -1;
+  w.graph_fb = -1;
+}
+
 void free_work(SolveWork& w) {
   dfree(w.V); dfree(w.Z); dfree(w.r); dfree(w.H); dfree(w.cs); dfree(w.sn); dfree(w.g); dfree(w.y);
   dfree(w.part); dfree(w.hist); dfree(w.st);
-  if (w.graph) (void)hipGraphExecDestroy(w.graph);
+  drop_graphs(w);
+  if (w.h_st) (void)hipHostFree(w.h_st);
   w = SolveWork();
 }
 
@@ -698,11 +708,7 @@ extern "C" mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* s, mdnp_
     s->kind = kind;
     s->alpha_override = alpha > 0.0 ? alpha : 0.0;
     s->prec_set = true;
-    if (s->work.graph) {
-      (void)hipGraphExecDestroy(s->work.graph);
-      s->work.graph = nullptr;
-      s->work.graph_m = -1;
-    }
+    drop_graphs(s->work);
     if (kind != MDNP_PREC_NEURAL) return;
     s->prec_set = false;
     if (!weights) fail(MDNP_E_ARG, "neural preconditioner needs weights");
@@ -744,11 +750,7 @@ extern "C" mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* s, int32_t* chosen
   return guarded(ctx, [&] {
     if (!s) fail(MDNP_E_ARG, "null system");
     HIPCHK(hipSetDevice(ctx->device));
-    if (s->work.graph) {  // captured with the old launch shapes
-      (void)hipGraphExecDestroy(s->work.graph);
-      s->work.graph = nullptr;
-      s->work.graph_m = -1;
-    }
+    drop_graphs(s->work);  // captured with the old launch shapes
     if (!spmv_autotune(s, ctx->stream)) fail(MDNP_E_OOM, "autotune: could not allocate its timing buffers");
     const bool net = s->kind == MDNP_PREC_NEURAL && s->prec_set && s->cnn.dtype == MDNP_BF16;
     if (net && !cnn_autotune(s, ctx->stream, 5))
@@ -777,11 +779,7 @@ extern "C" mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* s, int32_t 
     if (steps < 0 || steps > 8) fail(MDNP_E_ARG, "steps must be in [0, 8]");
     if (steps > 0 && s->smooth.sweeps > 0) fail(MDNP_E_STATE, "switch the smoothing off first");
     HIPCHK(hipSetDevice(ctx->device));
-    if (s->work.graph) {
-      (void)hipGraphExecDestroy(s->work.graph);
-      s->work.graph = nullptr;
-      s->work.graph_m = -1;
-    }
+    drop_graphs(s->work);
     free_inner(s->inner);
     if (steps == 0) return;
     InnerState& q = s->inner;
@@ -813,11 +811,7 @@ extern "C" mdnp_status mdnp_set_smoothing(mdnp_ctx* ctx, mdnp_sys* s, int32_t sw
     if (sweeps > 0 && !(omega > 0.0 && omega < 2.0)) fail(MDNP_E_ARG, "omega must be in (0, 2)");
     if (sweeps > 0 && s->inner.steps > 0) fail(MDNP_E_STATE, "switch the inner FGMRES steps off first");
     HIPCHK(hipSetDevice(ctx->device));
-    if (s->work.graph) {
-      (void)hipGraphExecDestroy(s->work.graph);
-      s->work.graph = nullptr;
-      s->work.graph_m = -1;
-    }
+    drop_graphs(s->work);
     SmoothState& m = s->smooth;
     if (sweeps == 0) {
       free_smooth(m);
@@ -843,6 +837,9 @@ extern "C" mdnp_status mdnp_set_smoothing(mdnp_ctx* ctx, mdnp_sys* s, int32_t sw
 
 namespace {
 
+// Arnoldi steps per captured graph of a restart cycle.
+constexpr int kCycleChunk = 5;
+
 void ensure_work(mdnp_sys* s, int m, int hist_cap) {
   SolveWork& w = s->work;
   if (w.m >= m && w.hist_cap >= hist_cap && w.V) return;
@@ -860,6 +857,10 @@ void ensure_work(mdnp_sys* s, int m, int hist_cap) {
   w.part = dalloc<double>(parts_size(s));
   w.hist = dalloc<double>(ni * hist_cap);
   w.st = dalloc<InstState>(ni);
+  if (hipHostMalloc((void**)&w.h_st, sizeof(InstState) * ni, hipHostMallocDefault) != hipSuccess) {
+    w.h_st = nullptr;
+    fail(MDNP_E_OOM, "pinned host copy of the instance states");
+  }
   w.m = m;
   w.hist_cap = hist_cap;
   if (!s->cnn.inv_s) s->cnn.inv_s = dalloc<double>(2 * ni);
@@ -909,8 +910,9 @@ void apply_prec(mdnp_sys* s, const T* v, T* z, const InstState* st, bool any_fb,
   if (any_fb) launch_prec_jacobi<T>(s, v, z, st, 1, stream);
 }
 
+// Arnoldi steps j0 .. j1 - 1 of a restart cycle (all instances, masked).
 template <typename T>
-void arnoldi_cycle(mdnp_sys* s, int m, bool any_fb, double* x, hipStream_t stream) {
+void arnoldi_steps(mdnp_sys* s, int j0, int j1, bool any_fb, hipStream_t stream) {
   SolveWork& w = s->work;
   T* V = (T*)w.V;
   T* Z = (T*)w.Z;
@@ -919,7 +921,7 @@ void arnoldi_cycle(mdnp_sys* s, int m, bool any_fb, double* x, hipStream_t strea
   double* pA = P.pA;
   double* pB = P.pB;
   double* pW = P.pW;
-  for (int j = 0; j < m; ++j) {
+  for (int j = j0; j < j1; ++j) {
     apply_prec<T>(s, V + j * nt, Z + j * nt, w.st, any_fb, stream);
     launch_spmv<T>(s, Z + j * nt, V + (j + 1) * nt, w.st, true, stream);
     const int np = mgs_passes(j);
@@ -931,8 +933,14 @@ void arnoldi_cycle(mdnp_sys* s, int m, bool any_fb, double* x, hipStream_t strea
     double* last = ((np - 1) % 2 == 0) ? pA : pB;
     launch_mgs_finish<T>(s, V, j, last, pW, w.H, w.cs, w.sn, w.g, w.hist, w.hist_cap, w.m, w.st, stream);
   }
+}
+
+// End of a restart cycle: y from the triangular system, x += Z y.
+template <typename T>
+void cycle_end(mdnp_sys* s, double* x, hipStream_t stream) {
+  SolveWork& w = s->work;
   launch_solve_y(s, w.H, w.g, w.y, w.m, w.st, stream);
-  launch_update_x<T>(s, Z, w.y, x, w.m, w.st, stream);
+  launch_update_x<T>(s, (T*)w.Z, w.y, x, w.m, w.st, stream);
 }
 
 template <typename T>
@@ -990,23 +998,36 @@ void solve_impl(mdnp_ctx* ctx, mdnp_sys* s, const double* d_b, double* d_x, cons
     if (!any_active || ++cycles > max_cycles) break;
     const int m = all_fb ? mf : m0;
     launch_scale_to<T>(s, w.r, (T*)w.V, w.st, stream);
-    if (o.use_graph) {
-      if (!w.graph || w.graph_m != m || w.graph_fb != (int)any_fb) {
-        if (w.graph) HIPCHK(hipGraphExecDestroy(w.graph));
-        w.graph = nullptr;
+    // the cycle in chunks of kCycleChunk steps; after each chunk the host reads
+    // the instance states and stops once none takes part any more (the
+    // remaining steps would only launch masked kernels)
+    const int nch = (m + kCycleChunk - 1) / kCycleChunk;
+    if (o.use_graph && (w.graph_m != m || w.graph_fb != (int)any_fb)) {
+      drop_graphs(w);
+      for (int c = 0; c < nch; ++c) {
         hipGraph_t g;
         HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
-        arnoldi_cycle<T>(s, m, any_fb, d_x, stream);
+        arnoldi_steps<T>(s, c * kCycleChunk, std::min(m, (c + 1) * kCycleChunk), any_fb, stream);
         HIPCHK(hipStreamEndCapture(stream, &g));
-        HIPCHK(hipGraphInstantiate(&w.graph, g, nullptr, nullptr, 0));
+        hipGraphExec_t ge = nullptr;
+        HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
         HIPCHK(hipGraphDestroy(g));
-        w.graph_m = m;
-        w.graph_fb = (int)any_fb;
+        w.graphs.push_back(ge);
       }
-      HIPCHK(hipGraphLaunch(w.graph, stream));
-    } else {
-      arnoldi_cycle<T>(s, m, any_fb, d_x, stream);
+      w.graph_m = m;
+      w.graph_fb = (int)any_fb;
     }
+    for (int c = 0; c < nch; ++c) {
+      if (o.use_graph) HIPCHK(hipGraphLaunch(w.graphs[c], stream));
+      else arnoldi_steps<T>(s, c * kCycleChunk, std::min(m, (c + 1) * kCycleChunk), any_fb, stream);
+      if (c + 1 == nch) break;
+      HIPCHK(hipMemcpyAsync(w.h_st, w.st, sizeof(InstState) * ni, hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      bool any = false;
+      for (int i = 0; i < ni; ++i) any = any || (w.h_st[i].active && !w.h_st[i].done);
+      if (!any) break;
+    }
+    cycle_end<T>(s, d_x, stream);
     HIPCHK(hipGetLastError());
   }
   // history and statistics

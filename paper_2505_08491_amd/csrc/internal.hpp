@@ -122,8 +122,11 @@ struct SolveWork {
   double* part = nullptr;      // partial sums: 3 x blk, blk3, mblk, mblk3
   double* hist = nullptr;      // n_inst x hist_cap
   InstState* st = nullptr;     // n_inst
-  hipGraphExec_t graph = nullptr;
+  // one restart cycle as graphs of at most kCycleChunk Arnoldi steps each, so
+  // the host can stop launching once no instance takes part any more
+  std::vector<hipGraphExec_t> graphs;
   int graph_m = -1, graph_fb = -1;
+  InstState* h_st = nullptr;   // pinned host copy of st, read between chunks
   std::vector<double> h_hist;
   std::vector<int32_t> h_nhist;
 };
