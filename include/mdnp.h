@@ -87,7 +87,8 @@ typedef struct {
   int32_t fallback_max_iters; /* extra steps allowed on the Jacobi fallback (0 = none)       */
   double tol;                 /* stop when ||b - A x|| <= tol ||b||                          */
   int32_t record_history;     /* keep rho_j / ||b|| per step for mdnp_history               */
-  int32_t use_graph;          /* capture one restart cycle in a HIP graph and replay it      */
+  int32_t use_graph;          /* capture a restart cycle as HIP graphs of 5 Arnoldi steps and
+                                 replay them (the next one only while an instance is active) */
 } mdnp_solve_opts;
 
 typedef struct {
