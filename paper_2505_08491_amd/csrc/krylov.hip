@@ -166,8 +166,8 @@ __device__ __forceinline__ Tacc stencil_row(const Tv* __restrict__ x, int64_t ba
 // Planes are loaded SW_PD steps ahead into a ring of register sets; the loop
 // is unrolled over the ring, so no set is copied and a step waits only for its
 // own plane.  No LDS, no barriers.  The x = 0 boundary column is copied by
-// extra waves of the same launch (the first tile ids, one per instance and
-// SW_FZ planes).
+// extra waves of the same launch (one per instance and SW_FZ planes, placed
+// with that instance's row strips).
 constexpr int SW_TY = 5;      // output rows per wave
 constexpr int SW_PD = 3;      // planes in flight (register sets)
 constexpr int SW_FZ = 8;      // planes per x = 0 copy wave
@@ -201,7 +201,7 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 template <typename Tv, typename Tacc, int SUM = 0, int NX = 1>
 __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict__ stencil, const Tv* __restrict__ x,
                                                        Tv* __restrict__ y, const int64_t* __restrict__ off, int n,
-                                                       int ytiles, int zc, int nface, int ntile, const InstState* st,
+                                                       int ytiles, int zc, int nfz, int ntile, const InstState* st,
                                                        int mask, const Tv* __restrict__ x2 = nullptr) {
   constexpr int NR = SW_TY + 2;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -210,24 +210,39 @@ __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict_
   const int tid = lb * 4 + wave;
   if (tid >= ntile) return;
   const int64_t nn = (int64_t)n * n;
-  if (tid < nface) {  // x = 0 column of planes zf .. zf + SW_FZ - 1
-    const int nzf = (n + SW_FZ - 1) / SW_FZ;
-    const int i = tid / nzf, zf = (tid - i * nzf) * SW_FZ;
-    if (mask && !st[i].active) return;
+  // tiles of an instance: nfz x = 0 column tiles, then its row strips, so that
+  // both kinds of an instance run on the XCD that holds its vector in L2
+  const int nz = (n + zc - 1) / zc;
+  const int per = nfz + ytiles * nz;
+  const int i = tid / per, t0 = tid - i * per;
+  if (mask && !st[i].active) return;
+  if (t0 < nfz) {  // x = 0 column of planes zf .. zf + SW_FZ - 1, rows lane + 64 h
+    constexpr int RG = NX + 1;  // row groups of 64: n <= 64 NX + 1
+    const int zf = t0 * SW_FZ;
     const Tv* X = x + off[i];
     const Tv* X2 = SUM ? x2 + off[i] : nullptr;
     Tv* Y = y + off[i];
-    for (int z = zf; z < min(n, zf + SW_FZ); ++z)
-      for (int gy = lane; gy < n; gy += 64) {
-        const int64_t v = z * nn + (int64_t)gy * n;
-        Y[v] = SUM ? (Tv)((Tacc)X[v] + (Tacc)X2[v]) : X[v];
+    // every load first (clamped to a valid address), then the stores: one
+    // memory round trip per wave instead of one per row group and plane
+    Tv cv[SW_FZ][RG];
+#pragma unroll
+    for (int zz = 0; zz < SW_FZ; ++zz)
+#pragma unroll
+      for (int h = 0; h < RG; ++h) {
+        const int z = zf + zz, gy = lane + 64 * h;
+        const int64_t v = z < n && gy < n ? z * nn + (int64_t)gy * n : 0;
+        cv[zz][h] = SUM ? (Tv)((Tacc)X[v] + (Tacc)X2[v]) : X[v];
+      }
+#pragma unroll
+    for (int zz = 0; zz < SW_FZ; ++zz)
+#pragma unroll
+      for (int h = 0; h < RG; ++h) {
+        const int z = zf + zz, gy = lane + 64 * h;
+        if (z < n && gy < n) Y[z * nn + (int64_t)gy * n] = cv[zz][h];
       }
     return;
   }
-  const int nz = (n + zc - 1) / zc;
-  const int t0 = tid - nface;
-  const int i = t0 / (ytiles * nz), rem = t0 - i * (ytiles * nz);
-  if (mask && !st[i].active) return;
+  const int rem = t0 - nfz;
   const int y0 = (rem % ytiles) * SW_TY, z0 = (rem / ytiles) * zc;
   const int zend = min(n, z0 + zc);
   const Tv* X = x + off[i];
@@ -1475,15 +1490,15 @@ void launch_sweep(mdnp_sys* s, const T* x, T* y, const T* x2, const InstState* s
   nz = std::max(1, std::min(nz, n));
   const int zc = (n + nz - 1) / nz;
   nz = (n + zc - 1) / zc;
-  const int nface = s->n_inst * ((n + SW_FZ - 1) / SW_FZ);
-  const int ntile = nface + ytiles * nz * s->n_inst;
+  const int nfz = (n + SW_FZ - 1) / SW_FZ;
+  const int ntile = (nfz + ytiles * nz) * s->n_inst;
   const dim3 grid(xcd_grid((ntile + 3) / 4));
   if (n <= 65)
     hipLaunchKernelGGL((k_stencil_sweep<T, T, SUM, 1>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, nface, ntile, st, mk, x2);
+                       ytiles, zc, nfz, ntile, st, mk, x2);
   else
     hipLaunchKernelGGL((k_stencil_sweep<T, T, SUM, 2>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, nface, ntile, st, mk, x2);
+                       ytiles, zc, nfz, ntile, st, mk, x2);
 }
 
 template <typename T>
