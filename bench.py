@@ -91,27 +91,23 @@ def unet_flops(n):
     return tot
 
 
-def spmv_traffic(S):
-    """HBM bytes per batched SpMV launch from the committed rocprofv3 PMC
-    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel), or None when the
-    kernel source changed since the counters were taken."""
+def spmv_traffic(target):
+    """HBM bytes per batched SpMV launch at the stencil sweep's z-split target
+    `target` (0: the default 2048) from the committed rocprofv3 PMC summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel), or None when the kernel
+    source changed since the counters were taken."""
     import hashlib
+    import re
     path = os.path.join(ROOT, "profiles", "spmv_64x16_traffic.txt")
     src = os.path.join(ROOT, "paper_2505_08491_amd", "csrc", "krylov.hip")
     if not os.path.exists(path):
         return None
-    fields = {}
-    for line in open(path):
-        if ":" in line and not line.startswith(" "):
-            k, v = line.split(":", 1)
-            fields[k.strip()] = v.strip()
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("krylov.hip sha256") != digest:
+    text = open(path).read()
+    m = re.search(r"^krylov.hip sha256: ([0-9a-f]+)$", text, re.M)
+    if not m or m.group(1) != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
-    try:
-        return float(fields["traffic bytes per launch"])
-    except (KeyError, ValueError):
-        return None
+    m = re.search(r"^traffic bytes per launch \[%d\]: (\d+)$" % (target or 2048), text, re.M)
+    return float(m.group(1)) if m else None
 
 
 def time_kernel(ctx, fn, reps):
@@ -341,7 +337,8 @@ def main():
         "jacobi": jac,
         "roofline": {"bound": "hbm", "kernel": "k_stencil_sweep + k_mrows (batched y = (S + M) x, FP32)",
                      "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
-                     "traffic": spmv_traffic(S) if (a.workload, a.n_cells, a.count) == ("transfer", 64, 16) else None,
+                     "traffic": (spmv_traffic(tuned[11] if tuned else 0)
+                                 if (a.workload, a.n_cells, a.count) == ("transfer", 64, 16) else None),
                      "algorithmic_bytes": spmv_bytes(S), "ms_per_launch": ms_spmv,
                      "copy_gbps": copy_gbps},
         "unet": {"bound": "mfma", "dtype": a.cnn_dtype, "gflop_per_forward": cnn_flop / 1e9,
