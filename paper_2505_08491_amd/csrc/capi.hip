@@ -122,7 +122,7 @@ void drop_graphs(SolveWork& w) {
 
 void free_work(SolveWork& w) {
   dfree(w.V); dfree(w.Z); dfree(w.r); dfree(w.H); dfree(w.cs); dfree(w.sn); dfree(w.g); dfree(w.y);
-  dfree(w.part); dfree(w.hist); dfree(w.st);
+  dfree(w.part); dfree(w.hist); dfree(w.st); dfree(w.xs);
   drop_graphs(w);
   if (w.h_st) (void)hipHostFree(w.h_st);
   w = SolveWork();
@@ -857,6 +857,7 @@ void ensure_work(mdnp_sys* s, int m, int hist_cap) {
   w.part = dalloc<double>(parts_size(s));
   w.hist = dalloc<double>(ni * hist_cap);
   w.st = dalloc<InstState>(ni);
+  w.xs = dalloc<double>(nt);
   if (hipHostMalloc((void**)&w.h_st, sizeof(InstState) * ni, hipHostMallocDefault) != hipSuccess) {
     w.h_st = nullptr;
     fail(MDNP_E_OOM, "pinned host copy of the instance states");
@@ -935,10 +936,13 @@ void arnoldi_steps(mdnp_sys* s, int j0, int j1, bool any_fb, hipStream_t stream)
   }
 }
 
-// End of a restart cycle: y from the triangular system, x += Z y.
+// End of a restart cycle: y from the triangular system, x += Z y.  The x of
+// the cycle start (finite: its true residual was) is kept in xs first, so an
+// instance whose update turns non-finite can restart from it.
 template <typename T>
 void cycle_end(mdnp_sys* s, double* x, hipStream_t stream) {
   SolveWork& w = s->work;
+  HIPCHK(hipMemcpyAsync(w.xs, x, sizeof(double) * s->ntot, hipMemcpyDeviceToDevice, stream));
   launch_solve_y(s, w.H, w.g, w.y, w.m, w.st, stream);
   launch_update_x<T>(s, (T*)w.Z, w.y, x, w.m, w.st, stream);
 }
@@ -955,14 +959,21 @@ void solve_impl(mdnp_ctx* ctx, mdnp_sys* s, const double* d_b, double* d_x, cons
   ensure_work(s, mmax, hist_cap);
   SolveWork& w = s->work;
   const int ni = s->n_inst;
-  launch_norm2_partials(s, d_b, w.part, stream);
-  launch_init_state(s, w.st, w.part, o.tol, o.max_iters, stream);
+  {
+    const Parts P = parts(s, w.part);
+    launch_norm2_partials(s, d_b, P.pA, stream);
+    launch_norm2_partials(s, d_x, P.pB, stream);
+    launch_init_state(s, w.st, P.pA, P.pB, o.tol, o.max_iters, stream);
+  }
   std::vector<InstState> hs(ni);
   HIPCHK(hipMemcpyAsync(hs.data(), w.st, sizeof(InstState) * ni, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
+  for (int i = 0; i < ni; ++i)
+    if (hs[i].bad_input) fail(MDNP_E_NONFINITE, "non-finite entry in b or x0 of instance " + std::to_string(i));
   for (int i = 0; i < ni; ++i)  // b = 0: the solution is 0
     if (hs[i].done)
       HIPCHK(hipMemsetAsync(d_x + s->off[i], 0, sizeof(double) * (s->off[i + 1] - s->off[i]), stream));
+  HIPCHK(hipMemcpyAsync(w.xs, d_x, sizeof(double) * s->ntot, hipMemcpyDeviceToDevice, stream));
   std::vector<char> used_fb(ni, 0);
   int cycles = 0;
   const int max_cycles = total_cap + 4;
@@ -973,10 +984,32 @@ void solve_impl(mdnp_ctx* ctx, mdnp_sys* s, const double* d_b, double* d_x, cons
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(hs.data(), w.st, sizeof(InstState) * ni, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
-    bool changed = false, any_active = false, any_fb = false, all_fb = true;
+    bool changed = false, any_active = false, any_fb = false, all_fb = true, pending = false;
     for (int i = 0; i < ni; ++i) {
       InstState& z = hs[i];
-      if (z.done || !z.active) continue;
+      if (z.done) continue;
+      if (z.stalled == 2) {  // (the cycle-start kernel leaves such an instance inactive)
+        // the last update made x non-finite: go back to the x of the previous
+        // cycle start (true relative residual prev_rel) before the fallback or
+        // before giving up; the instance sits this cycle out and its residual
+        // is recomputed at the next cycle start
+        HIPCHK(hipMemcpyAsync(d_x + s->off[i], w.xs + s->off[i], sizeof(double) * (s->off[i + 1] - s->off[i]),
+                              hipMemcpyDeviceToDevice, stream));
+        z.rel = z.prev_rel;
+        z.active = 0;
+        changed = true;
+        if (z.mode == 0 && fb_allowed) {
+          z.mode = 1;
+          z.max_iters = o.fallback_max_iters;
+          z.stalled = 0;
+          used_fb[i] = 1;
+          pending = true;
+        } else {
+          z.done = 1;
+        }
+        continue;
+      }
+      if (!z.active) continue;
       if (z.stalled) {
         if (z.mode == 0 && fb_allowed) {
           z.mode = 1;
@@ -984,7 +1017,7 @@ void solve_impl(mdnp_ctx* ctx, mdnp_sys* s, const double* d_b, double* d_x, cons
           z.stalled = 0;
           used_fb[i] = 1;
           changed = true;
-        } else if (z.stalled >= 2) {  // non-finite or out of steps
+        } else if (z.stalled == 3) {  // out of steps
           z.done = 1;
           z.active = 0;
           changed = true;
@@ -995,7 +1028,8 @@ void solve_impl(mdnp_ctx* ctx, mdnp_sys* s, const double* d_b, double* d_x, cons
       if (z.mode == 1) any_fb = true; else all_fb = false;
     }
     if (changed) HIPCHK(hipMemcpyAsync(w.st, hs.data(), sizeof(InstState) * ni, hipMemcpyHostToDevice, stream));
-    if (!any_active || ++cycles > max_cycles) break;
+    if ((!any_active && !pending) || ++cycles > max_cycles) break;
+    if (!any_active) continue;  // only restarted instances: recompute their residuals
     const int m = all_fb ? mf : m0;
     launch_scale_to<T>(s, w.r, (T*)w.V, w.st, stream);
     // the cycle in chunks of kCycleChunk steps; after each chunk the host reads

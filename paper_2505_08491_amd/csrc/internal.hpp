@@ -29,7 +29,7 @@ struct InstState {
   int32_t nhist;       // entries written to the history
   int32_t cycles;
   int32_t max_iters;   // step cap of the current mode
-  int32_t pad;
+  int32_t bad_input;   // ||b|| or ||x0|| is not finite (the solve is refused)
   double bnorm;        // ||b||
   double beta;         // ||r|| at the start of the current cycle
   double rel;          // true relative residual at the start of the current cycle
@@ -122,6 +122,7 @@ struct SolveWork {
   double* part = nullptr;      // partial sums: 3 x blk, blk3, mblk, mblk3
   double* hist = nullptr;      // n_inst x hist_cap
   InstState* st = nullptr;     // n_inst
+  double* xs = nullptr;        // ntot: x at the start of the last cycle (the last finite iterate)
   // one restart cycle as graphs of at most kCycleChunk Arnoldi steps each, so
   // the host can stop launching once no instance takes part any more
   std::vector<hipGraphExec_t> graphs;

@@ -21,8 +21,8 @@ void launch_residual(mdnp_sys* s, const double* b, const double* x, double* r, d
                      const InstState* st, hipStream_t stream);
 // per-block partial sums of x^2 over whole vectors
 void launch_norm2_partials(mdnp_sys* s, const double* x, double* part, hipStream_t stream);
-void launch_init_state(mdnp_sys* s, InstState* st, const double* part, double tol, int max_iters,
-                       hipStream_t stream);
+void launch_init_state(mdnp_sys* s, InstState* st, const double* part, const double* partx, double tol,
+                       int max_iters, hipStream_t stream);
 void launch_cycle_start(mdnp_sys* s, InstState* st, const double* part, const double* partm, double* g,
                         double* hist, int hist_cap, int m, hipStream_t stream);
 template <typename T>

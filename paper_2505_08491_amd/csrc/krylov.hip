@@ -487,11 +487,15 @@ __global__ void __launch_bounds__(BS) k_norm2_part(const double* __restrict__ x,
 // ---------------------------------------------------------------- cycle control
 
 // One wavefront per instance (grid = n_inst, 64 threads).
-__global__ void k_init_state(InstState* st, const double* part, const int32_t* first, int n_inst,
-                             double tol, int max_iters) {
+// part holds the per-chunk squares of b, partx those of x0: a non-finite norm
+// of either marks the instance as bad input (the host refuses the solve); a
+// zero b has the exact solution x = 0.
+__global__ void k_init_state(InstState* st, const double* part, const double* partx, const int32_t* first,
+                             int n_inst, double tol, int max_iters) {
   const int i = blockIdx.x;
   if (i >= n_inst) return;
   const double s = wave_inst_sum(part, first, i);
+  const double sx = wave_inst_sum(partx, first, i);
   if (threadIdx.x != 0) return;
   InstState z{};
   z.bnorm = sqrt(s);
@@ -499,9 +503,14 @@ __global__ void k_init_state(InstState* st, const double* part, const int32_t* f
   z.max_iters = max_iters;
   z.rel = 1.0;
   z.prev_rel = 1.0;
-  if (!(z.bnorm > 0.0)) {  // b = 0: x = 0 is exact
+  if (!isfinite(z.bnorm) || !isfinite(sx)) {
+    z.bad_input = 1;
+    z.done = 1;
+    z.rel = NAN;
+  } else if (z.bnorm == 0.0) {
     z.done = 1;
     z.converged = 1;
+    z.rel = 0.0;
   }
   st[i] = z;
 }
@@ -1725,9 +1734,9 @@ void launch_norm2_partials(mdnp_sys* s, const double* x, double* part, hipStream
   hipLaunchKernelGGL(k_norm2_part, dim3(s->blk.nblk), dim3(BS), 0, stream, x, s->blk.start, s->blk.end, part);
 }
 
-void launch_init_state(mdnp_sys* s, InstState* st, const double* part, double tol, int max_iters,
-                       hipStream_t stream) {
-  hipLaunchKernelGGL(k_init_state, dim3(s->n_inst), dim3(64), 0, stream, st, part, s->blk.first,
+void launch_init_state(mdnp_sys* s, InstState* st, const double* part, const double* partx, double tol,
+                       int max_iters, hipStream_t stream) {
+  hipLaunchKernelGGL(k_init_state, dim3(s->n_inst), dim3(64), 0, stream, st, part, partx, s->blk.first,
                      s->n_inst, tol, max_iters);
 }
 

@@ -29,6 +29,7 @@ import torch
 
 from . import weights as W
 from .api import Context, System
+from .autograd import residual_loss, unet
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -107,7 +108,7 @@ def train(steps=2000, batch=32, graphs=128, n_cells=32, lr=1e-3, lr_min=1e-5, dt
     dmask = torch.from_numpy(dist_weight_mask()).cuda() if no_dist else None
     if dmask is not None:
         w[dmask] = 0.0
-    saved = torch.empty(ctx.saved_bytes(batch, n, dtype), dtype=torch.uint8, device="cuda")
+    w.requires_grad_(True)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed + 1)
     history = []
@@ -129,23 +130,25 @@ def train(steps=2000, batch=32, graphs=128, n_cells=32, lr=1e-3, lr_min=1e-5, dt
     def evaluate(wt):
         inst, r = sample(batch, vbank, SV.n_inst)
         X = SV.pack_input(inst, r)
-        y = ctx.cnn_forward(wt, X, n, dtype)
-        loss, _ = SV.loss_grad(inst, r, y)
+        with torch.no_grad():
+            y = ctx.cnn_forward(wt.detach(), X, n, dtype)
+            loss, _ = SV.loss_grad(inst, r, y)
         return float(loss.mean())
 
     for step in range(step0 + 1, steps + 1):
         inst, r = sample(batch, bank, S.n_inst)
         X = S.pack_input(inst, r)
-        y = ctx.cnn_forward(w, X, n, dtype, saved=saved)
-        loss, du = S.loss_grad(inst, r, y)
-        dw, _ = ctx.cnn_backward(w, saved, du, batch, n, dtype)
+        # forward, loss and adjoint through the library's kernels, chained by autograd
+        loss = residual_loss(unet(w, X, ctx, n, dtype), r, inst, S)
+        w.grad = None
+        loss.sum().backward()
         frac = (step - 1) / max(1, steps - 1)
         lr_t = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * frac))
-        ctx.adam_step(w, dw, m, v, lr_t, step)
+        ctx.adam_step(w.data, w.grad, m, v, lr_t, step)
         if dmask is not None:
-            w[dmask] = 0.0
+            w.data[dmask] = 0.0
         if step % log_every == 0 or step == step0 + 1 or step == steps:
-            lv = float(loss.mean())
+            lv = float(loss.detach().mean())
             vl = evaluate(w)
             el = time.time() - tstart
             history.append({"step": step, "loss": lv, "val_loss": vl, "lr": lr_t, "time_s": el})
@@ -154,7 +157,7 @@ def train(steps=2000, batch=32, graphs=128, n_cells=32, lr=1e-3, lr_min=1e-5, dt
                 raise RuntimeError("training diverged")
     torch.cuda.synchronize()
     elapsed = time.time() - tstart
-    wn = w.cpu().numpy()
+    wn = w.detach().cpu().numpy()
     meta = {"step": steps, "batch": batch, "graphs": graphs, "n_cells": n_cells, "lr": lr, "lr_min": lr_min,
             "schedule": "cosine", "dtype": dtype, "seed": seed, "p_random": p_random, "p_rhs": p_rhs,
             "no_dist": bool(no_dist), "train_seconds": elapsed, "history": history}

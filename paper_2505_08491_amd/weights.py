@@ -5,7 +5,9 @@ L0a L0b L1a L1b L2a L2b U1 D1 U0 D0 H, each stored as [Cout][kz][ky][kx][Cin]
 followed by its bias; 353,713 FP32 values in total.
 
 A checkpoint is a raw little-endian FP32 file `<name>.bin` plus `<name>.json`
-with the architecture, the training configuration and the Adam state file.
+with the architecture, the storage format ("storage"), the training
+configuration (its "dtype" is the arithmetic of the training forward pass)
+and the Adam state file.
 """
 from __future__ import annotations
 
@@ -48,7 +50,7 @@ def save(path_stem: str, w: np.ndarray, meta: dict, adam: tuple | None = None) -
     w = np.ascontiguousarray(w, dtype="<f4")
     assert w.size == N_PARAMS
     w.tofile(path_stem + ".bin")
-    meta = dict(meta, n_params=N_PARAMS, layers=[list(l) for l in LAYERS], dtype="float32-le")
+    meta = dict(meta, n_params=N_PARAMS, layers=[list(l) for l in LAYERS], storage="float32-le")
     if adam is not None:
         np.concatenate([np.asarray(adam[0], "<f4"), np.asarray(adam[1], "<f4")]).tofile(path_stem + ".adam.bin")
         meta["adam_file"] = os.path.basename(path_stem) + ".adam.bin"

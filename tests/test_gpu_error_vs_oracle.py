@@ -1,0 +1,112 @@
+"""Error of every measured configuration against the FP64 oracle, per instance.
+
+Each test solves a whole workload on the GPU in the launch configuration the
+benchmark times (FP32 vectors and SpMV, FP64 Gram-Schmidt / Givens / x / true
+residual, restart cycles as HIP graphs, launch shapes from the autotuner) and
+then, on CPU processes, assembles every instance with the oracle, computes its
+reference solution x* to FP64 true relative residual 1e-12 and checks, for
+every instance:
+  ||F - A x|| / ||F|| <= 1e-8 on the oracle's own A (the stopping rule of
+      Section 5.1 with x0 = 0, recomputed independently of the library),
+  ||x - x*|| / ||x*|| <= 1e-6 and max|x - x*| / max|x*| <= 1e-6.
+The per-instance figures are printed (pytest -s) as the stated error of each
+result.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import reference
+
+pytestmark = pytest.mark.gpu
+
+OPTS = dict(restart=30, max_iters=3000, fallback_restart=50, fallback_max_iters=20000, tol=1e-8, use_graph=True)
+
+
+def _P():
+    import paper_2505_08491_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = _P().Context(0)
+    yield c
+    c.close()
+
+
+def _weights():
+    from paper_2505_08491_amd import weights as W
+    wpath = W.default_path()
+    if not os.path.exists(wpath + ".bin"):
+        pytest.skip("trained weights not present")
+    return W.load(wpath)[0]
+
+
+def _solve_all(ctx, insts, dtypes, tune=True):
+    """GPU solutions of the whole batch for each network dtype: {dtype: (x, stats)}."""
+    S = _P().System(ctx, insts, vec_dtype="f32")
+    w = _weights()
+    b = torch.from_numpy(S.rhs()).cuda()
+    out = {}
+    for dt in dtypes:
+        S.set_preconditioner("neural", weights=w, cnn_dtype=dt)
+        if tune and dt in ("bf16", "fp8"):
+            S.autotune()
+        x = torch.zeros_like(b)
+        st = S.solve_device(b, x, **OPTS)
+        out[dt] = (x.cpu().numpy(), st)
+        print(f"  {dt}: solved, iterations {[q['iters'] + q['fallback_iters'] for q in st]}", flush=True)
+    offsets = S.offsets
+    S.free()
+    return out, offsets
+
+
+def _check(insts, sols, offsets, label):
+    dts = list(sols)
+    cands = [[sols[dt][0][offsets[k]:offsets[k + 1]] for dt in dts] for k in range(len(insts))]
+    print(f"{label}: oracle reference solutions of {len(insts)} instances on "
+          f"{reference.pool_size(len(insts))} CPU processes", flush=True)
+    res = reference.errors_vs_oracle(insts, cands)
+    worst = {dt: [0.0, 0.0, 0.0] for dt in dts}
+    for k, r in enumerate(res):
+        assert r["ref_converged"] and r["ref_rel_res"] <= 1e-12, (k, r)
+        for j, dt in enumerate(dts):
+            c = r["cands"][j]
+            st = sols[dt][1][k]
+            print(f"{label} inst {k:3d} {dt:5s} iters {st['iters']:4d}+{st['fallback_iters']:<3d} "
+                  f"rel_res {c['rel_res']:.2e} err {c['err']:.2e} err_max {c['err_max']:.2e}")
+            assert st["converged"], (label, dt, k, st)
+            assert c["rel_res"] <= 1e-8, (label, dt, k, c)
+            assert c["err"] <= 1e-6 and c["err_max"] <= 1e-6, (label, dt, k, c)
+            w = worst[dt]
+            worst[dt] = [max(w[0], c["rel_res"]), max(w[1], c["err"]), max(w[2], c["err_max"])]
+    for dt, w in worst.items():
+        print(f"{label} {dt}: worst rel_res {w[0]:.2e}, err {w[1]:.2e}, err_max {w[2]:.2e} over {len(insts)} instances")
+
+
+def test_error_vs_oracle_transfer64(ctx):
+    """All 16 instances of the 64^3 benchmark workload (512 segments x 16
+    elements, R = 0.002), network in BF16, with E4M3 weights and in FP32."""
+    insts = synth.workload_transfer(64, 16)
+    sols, offs = _solve_all(ctx, insts, ("bf16", "fp8", "f32"))
+    _check(insts, sols, offs, "64^3x16")
+
+
+def test_error_vs_oracle_transfer128(ctx):
+    """Both instances of the 128^3 resolution-transfer workload (2.15M 3D
+    unknowns each, network trained at 32^3), BF16 and E4M3 weights."""
+    insts = synth.workload_transfer(128, 2)
+    sols, offs = _solve_all(ctx, insts, ("bf16", "fp8"))
+    _check(insts, sols, offs, "128^3x2")
+
+
+def test_error_vs_oracle_batched32(ctx):
+    """All 256 instances of the batched 32^3 workload (trees of 8-128
+    segments, R ~ U[0.003, 0.01]) in one batched solve, BF16 network."""
+    insts = synth.workload_batched_32(256)
+    sols, offs = _solve_all(ctx, insts, ("bf16",))
+    _check(insts, sols, offs, "32^3x256")

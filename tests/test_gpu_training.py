@@ -1,0 +1,274 @@
+"""GPU parity of the training path (Section 5.1) and the gain of the trained
+network, through the C ABI, against the FP64 oracle.
+
+Covers the adjoint (backward) kernels in FP32 and BF16, the autograd wrapper
+around the forward and backward kernels, the loss and its gradient chained by
+autograd, Adam on FP32 master weights, the input packing, the solver-generated
+Arnoldi samples, a short training run, and what the trained network gains
+over the method without it.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import cnn as ocnn
+from oracle import fem, krylov
+
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    import paper_2505_08491_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = _P().Context(0)
+    yield c
+    c.close()
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def _theta(seed, bias=0.05):
+    th = ocnn.init_params(seed)
+    rng = np.random.default_rng(seed)
+    off = 0
+    for a, b in ocnn.layer_sizes():
+        th[off + a:off + a + b] = rng.uniform(-bias, bias, b)
+        off += a + b
+    return th.astype(np.float32).astype(np.float64)
+
+
+def _inputs(n, batch, seed):
+    rng = np.random.default_rng(seed)
+    X = np.stack([np.stack([rng.normal(size=(n, n, n)) / n ** 1.5, rng.uniform(0, 0.5, (n, n, n))], axis=-1)
+                  for _ in range(batch)])
+    G = rng.normal(size=(batch, n, n, n))
+    return X.astype(np.float32).astype(np.float64), G.astype(np.float32).astype(np.float64)
+
+
+def _oracle_grads(th, X, G):
+    gref = np.zeros(ocnn.n_params())
+    dxs = []
+    for k in range(X.shape[0]):
+        _, cache = ocnn.forward(th, X[k])
+        g, dX = ocnn.backward(th, cache, G[k])
+        gref += g
+        dxs.append(dX)
+    return gref, np.stack(dxs)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _layer_errors(dw, gref):
+    out, off = [], 0
+    for nw, nb in ocnn.layer_sizes():
+        out.append(_rel(dw[off:off + nw + nb], gref[off:off + nw + nb]))
+        off += nw + nb
+    return out
+
+
+# ---------------------------------------------------------------- adjoint kernels
+
+@pytest.mark.parametrize("dtype,n,tol", [("bf16", 9, 5e-2), ("bf16", 33, 5e-2), ("f32", 33, 1e-4)])
+def test_cnn_backward_matches_oracle(ctx, dtype, n, tol):
+    """Weight and input gradients of the whole network for an upstream
+    gradient G, from the activations the forward kernel stored (BF16 or
+    FP32), against the oracle's FP64 adjoint on the same weights and inputs."""
+    batch = 2
+    th = _theta(11 + n)
+    X, G = _inputs(n, batch, 30 + n)
+    w = dev(th, torch.float32)
+    saved = torch.empty(ctx.saved_bytes(batch, n, dtype), dtype=torch.uint8, device="cuda")
+    ctx.cnn_forward(w, dev(X.reshape(batch, -1, 2), torch.float32), n, dtype, saved=saved)
+    dw, dx = ctx.cnn_backward(w, saved, dev(G.reshape(batch, -1), torch.float32), batch, n, dtype, want_dx=True)
+    gref, dxref = _oracle_grads(th, X, G)
+    dw = dw.cpu().double().numpy()
+    dx = dx.cpu().double().numpy().reshape(dxref.shape)
+    layers = _layer_errors(dw, gref)
+    print(dtype, n, "dw", _rel(dw, gref), "dx", _rel(dx, dxref), "per layer", np.round(layers, 4))
+    assert _rel(dw, gref) <= tol
+    assert _rel(dx, dxref) <= tol
+    assert max(layers) <= 2 * tol, layers
+
+
+# ---------------------------------------------------------------- autograd wrapper
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("bf16", 5e-2)])
+def test_autograd_function_gradient_matches_oracle(ctx, dtype, tol):
+    """The torch.autograd.Function around the library's forward and backward:
+    loss.backward() gives the weight and input gradients of sum(G * U(X; w))
+    equal to the oracle's FP64 adjoint (itself pinned by central differences
+    and torch autograd in the CPU tests), on an 8^3-cell grid."""
+    from paper_2505_08491_amd.autograd import unet
+    n, batch = 9, 2
+    th = _theta(21)
+    X, G = _inputs(n, batch, 22)
+    w = dev(th, torch.float32).requires_grad_(True)
+    Xt = dev(X.reshape(batch, -1, 2), torch.float32).requires_grad_(True)
+    y = unet(w, Xt, ctx, n, dtype)
+    (y * dev(G.reshape(batch, -1), torch.float32)).sum().backward()
+    gref, dxref = _oracle_grads(th, X, G)
+    assert _rel(w.grad.cpu().double().numpy(), gref) <= tol
+    assert _rel(Xt.grad.cpu().double().numpy().reshape(dxref.shape), dxref) <= tol
+    # forward value equals the plain library call
+    with torch.no_grad():
+        assert torch.equal(y, ctx.cnn_forward(w.detach(), Xt.detach(), n, dtype))
+
+
+def test_autograd_training_loss_gradient_matches_oracle(ctx):
+    """The Section 5.1 risk chained by autograd (pack -> network -> loss), FP32:
+    per-sample losses and the weight gradient of their sum against the oracle's
+    sample_loss on each instance's own A00 and alpha."""
+    from paper_2505_08491_amd.autograd import residual_loss, unet
+    P = _P()
+    insts = [synth.make_instance(760 + i, 8, n_segments=5, elems_per_segment=3, radius=0.01, beta=1.0)
+             for i in range(2)]
+    S = P.System(ctx, insts, vec_dtype="f32")
+    sy = [fem.assemble(i) for i in insts]
+    slots = np.array([1, 0, 1], dtype=np.int32)
+    r = np.zeros((len(slots), S.n3d))
+    for k, i in enumerate(slots):
+        r[k] = synth.fast_normal(40 + k, S.n3d)
+        r[k, sy[i].boundary] = 0
+        r[k] /= np.linalg.norm(r[k])
+    r = r.astype(np.float32).astype(np.float64)
+    th = _theta(23)
+    w = dev(th, torch.float32).requires_grad_(True)
+    inst_t = dev(slots, torch.int32)
+    rt = dev(r, torch.float32)
+    X = S.pack_input(inst_t, rt)
+    loss = residual_loss(unet(w, X, ctx, 9, "f32"), rt, inst_t, S)
+    loss.sum().backward()
+    lref, gref = [], np.zeros(ocnn.n_params())
+    for k, i in enumerate(slots):
+        s = sy[i]
+        l, g = ocnn.sample_loss(th, s.blocks()[0], r[k], krylov.distance_input(s), s.alpha, s.boundary)
+        lref.append(l)
+        gref += g
+    assert np.allclose(loss.detach().cpu().numpy(), lref, rtol=1e-4)
+    assert _rel(w.grad.cpu().double().numpy(), gref) <= 1e-4
+    S.free()
+
+
+# ---------------------------------------------------------------- Adam, packing, Arnoldi samples
+
+def test_adam_matches_oracle(ctx):
+    """Three Adam steps (bias-corrected, FP32 masters) on 353,713 parameters
+    with gradients spanning six decades, against the oracle's FP64 Adam from
+    the same FP32 start, element by element."""
+    rng = np.random.default_rng(3)
+    nparam = ocnn.n_params()
+    w0 = rng.uniform(-0.5, 0.5, nparam).astype(np.float32)
+    w, m, v = dev(w0, torch.float32), torch.zeros(nparam, device="cuda"), torch.zeros(nparam, device="cuda")
+    wo, mo, vo = w0.astype(np.float64), np.zeros(nparam), np.zeros(nparam)
+    for step, lr in ((1, 1e-3), (2, 7e-4), (3, 1e-3)):
+        g = (rng.normal(size=nparam) * 10.0 ** rng.uniform(-6, 0, nparam)).astype(np.float32)
+        ctx.adam_step(w, dev(g, torch.float32), m, v, lr, step)
+        wo, mo, vo = ocnn.adam_step(wo, g.astype(np.float64), mo, vo, step, lr=lr)
+        wg, mg, vg = (t.cpu().double().numpy() for t in (w, m, v))
+        assert np.max(np.abs(wg - wo)) <= 1e-6, step
+        assert np.allclose(mg, mo, rtol=1e-6, atol=0), step
+        assert np.allclose(vg, vo, rtol=1e-6, atol=0), step
+    # the update is the oracle's: the change of w, not only w, agrees
+    assert np.allclose(wg - w0, wo - w0, rtol=1e-3, atol=2e-7)
+
+
+def test_pack_input_matches_oracle(ctx):
+    """X[k] = [r_k, d_{inst[k]} / ||d||]: the residual channel copied exactly,
+    the distance channel equal to the oracle's unit-norm distance field."""
+    P = _P()
+    insts = [synth.make_instance(770 + i, 12, n_segments=s, elems_per_segment=3, radius=0.01, beta=1.0)
+             for i, s in enumerate((3, 8, 5))]
+    S = P.System(ctx, insts, vec_dtype="f32")
+    slots = np.array([2, 0, 1, 2], dtype=np.int32)
+    r = np.stack([synth.fast_normal(50 + k, S.n3d) for k in range(len(slots))]).astype(np.float32)
+    X = S.pack_input(dev(slots, torch.int32), dev(r, torch.float32)).cpu().numpy()
+    assert X.shape == (len(slots), S.n3d, 2)
+    assert np.array_equal(X[:, :, 0], r)
+    for k, i in enumerate(slots):
+        d = krylov.distance_input(fem.assemble(insts[i]))
+        assert np.allclose(X[k, :, 1], d, rtol=2e-7, atol=1e-9 * np.max(d)), k
+    S.free()
+
+
+@pytest.mark.parametrize("vec,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_export_basis_matches_oracle(ctx, vec, tol):
+    """The solver-generated training samples: Arnoldi vectors v_0..v_8 of an
+    8-step Jacobi-GMRES cycle on the coupled system, against the oracle's
+    basis of the same cycle, per instance (2-norm and max-norm)."""
+    P = _P()
+    insts = [synth.make_instance(780 + i, 12, n_segments=s, elems_per_segment=3, radius=0.01, beta=1.0)
+             for i, s in enumerate((6, 9))]
+    S = P.System(ctx, insts, vec_dtype=vec)
+    S.set_preconditioner("jacobi")
+    S.solve(S.rhs(), restart=8, max_iters=8, tol=1e-30)
+    for i, inst in enumerate(insts):
+        s = fem.assemble(inst)
+        ref = krylov.fgmres(s.A, s.F, precond=krylov.jacobi(s.A), restart=9, tol=1e-30, max_iters=9,
+                            keep_arnoldi=True)
+        V = ref.V[0]
+        o0, o1 = S.offsets[i], S.offsets[i + 1]
+        for k in range(9):
+            got = S.export_basis(k).cpu().double().numpy()[o0:o1]
+            assert _rel(got, V[k]) <= tol, (i, k)
+            assert np.max(np.abs(got - V[k])) <= tol * np.max(np.abs(V[k])), (i, k)
+    with pytest.raises(P.MdnpError):
+        S.export_basis(9)
+    S.free()
+
+
+# ---------------------------------------------------------------- training run and gain
+
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_short_training_run_lowers_loss(dtype):
+    """30 steps of the trainer at 16^3 (6 graphs, batch 8): the training and
+    validation losses fall from about 1 (the untrained network) by a margin."""
+    from paper_2505_08491_amd import train as T
+    _, meta = T.train(steps=30, batch=8, graphs=6, n_cells=16, val_graphs=3, log_every=10, dtype=dtype)
+    h = meta["history"]
+    print(dtype, [(q["step"], round(q["loss"], 4), round(q["val_loss"], 4)) for q in h])
+    assert h[0]["step"] == 1 and h[-1]["step"] == 30
+    assert all(np.isfinite(q["loss"]) for q in h)
+    assert h[-1]["loss"] < 0.7 * h[0]["loss"]
+    assert h[-1]["val_loss"] < 0.7 * h[0]["val_loss"]
+
+
+def test_trained_network_gain(ctx):
+    """What the trained network gains (the None vs U3 rows of the paper's
+    tables): on 16 instances of the batched 32^3 workload, FGMRES(30) with the
+    trained network needs fewer than half the iterations of the same block
+    preconditioner with diag(A00)^-1 for the 3D block (the method without the
+    network) and fewer than with an untrained (Kaiming-initialised) network;
+    every solve reaches rel-res 1e-8."""
+    from paper_2505_08491_amd import weights as W
+    wpath = W.default_path()
+    if not os.path.exists(wpath + ".bin"):
+        pytest.skip("trained weights not present")
+    P = _P()
+    S = P.System(ctx, synth.workload_batched_32(16), vec_dtype="f32")
+    b = S.rhs()
+    opts = dict(restart=30, max_iters=3000, tol=1e-8, use_graph=True)
+    res = {}
+    for name in ("trained", "untrained", "none"):
+        if name == "none":
+            S.set_preconditioner("block_jacobi")
+        else:
+            w = W.load(wpath)[0] if name == "trained" else W.init(0)
+            S.set_preconditioner("neural", weights=w, cnn_dtype="bf16")
+        _, st = S.solve(b, **opts)
+        assert all(q["converged"] and not q["used_fallback"] for q in st), (name, st)
+        res[name] = float(np.mean([q["iters"] for q in st]))
+    print("mean FGMRES(30) iterations", res)
+    assert res["trained"] < 0.5 * res["none"]
+    assert res["trained"] < res["untrained"]
+    S.free()

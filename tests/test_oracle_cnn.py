@@ -221,3 +221,112 @@ def test_adam_first_step_closed_form():
     g = np.array([0.3, -2.0, 1e-3, 0.0])
     th, m, v = cnn.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=0.01)
     assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+class _TorchUNet(torch.nn.Module):
+    """The U-net of Section 4.2 as a torch.nn composition in float64, written
+    from the layer table (three levels of 16 / 32 / 64 channels, 3x3x3 kernels
+    with padding 1, stride-2 convolutions down, stride-2 transposed
+    convolutions up, skip connections by stacking [upsampled | skip] on the
+    channel axis, ReLU after every convolution except the transposed ones and
+    the 1x1 head).  It shares nothing with the oracle's loops: a library pin of
+    the whole wiring."""
+
+    def __init__(self):
+        super().__init__()
+        C3 = lambda ci, co, s: torch.nn.Conv3d(ci, co, 3, stride=s, padding=1, dtype=torch.float64)
+        T3 = lambda ci, co: torch.nn.ConvTranspose3d(ci, co, 3, stride=2, padding=1, dtype=torch.float64)
+        self.l0a, self.l0b = C3(2, 16, 1), C3(16, 16, 1)
+        self.l1a, self.l1b = C3(16, 32, 2), C3(32, 32, 1)
+        self.l2a, self.l2b = C3(32, 64, 2), C3(64, 64, 1)
+        self.u1, self.d1 = T3(64, 32), C3(64, 32, 1)
+        self.u0, self.d0 = T3(32, 16), C3(32, 16, 1)
+        self.head = torch.nn.Conv3d(16, 1, 1, dtype=torch.float64)
+
+    def load_flat(self, theta):
+        """Flat order: per layer [Cout][kz][ky][kx][Cin] then the bias."""
+        off = 0
+        for m in (self.l0a, self.l0b, self.l1a, self.l1b, self.l2a, self.l2b, self.u1, self.d1, self.u0,
+                  self.d0, self.head):
+            if isinstance(m, torch.nn.ConvTranspose3d):
+                ci, co, k = m.weight.shape[0], m.weight.shape[1], m.weight.shape[2]
+            else:
+                co, ci, k = m.weight.shape[0], m.weight.shape[1], m.weight.shape[2]
+            nw = co * k ** 3 * ci
+            w = torch.from_numpy(np.asarray(theta[off:off + nw]).reshape(co, k, k, k, ci).copy())
+            off += nw
+            with torch.no_grad():
+                if isinstance(m, torch.nn.ConvTranspose3d):
+                    m.weight.copy_(w.permute(4, 0, 1, 2, 3))   # [Cin][Cout][kz][ky][kx]
+                else:
+                    m.weight.copy_(w.permute(0, 4, 1, 2, 3))   # [Cout][Cin][kz][ky][kx]
+                m.bias.copy_(torch.from_numpy(np.asarray(theta[off:off + co]).copy()))
+            off += co
+        assert off == theta.size
+
+    def forward(self, x):                      # x [B, 2, z, y, x]
+        r = torch.relu
+        s0 = r(self.l0b(r(self.l0a(x))))
+        s1 = r(self.l1b(r(self.l1a(s0))))
+        bott = r(self.l2b(r(self.l2a(s1))))
+        d1 = r(self.d1(torch.cat([self.u1(bott), s1], dim=1)))
+        d0 = r(self.d0(torch.cat([self.u0(d1), s0], dim=1)))
+        return self.head(d0)[:, 0]
+
+
+@pytest.mark.parametrize("n", [5, 9, 13])
+def test_network_wiring_matches_torch_composition(n):
+    """Whole-network forward of the oracle against the torch.nn composition on
+    random weights with non-zero biases (every layer's bias and the
+    concatenation order of both skips matter: swapping [up | skip] or dropping
+    a ReLU changes the output by far more than the tolerance)."""
+    rng = np.random.default_rng(100 + n)
+    theta = cnn.init_params(n)
+    off = 0
+    for nw, nb in cnn.layer_sizes():
+        theta[off + nw:off + nw + nb] = rng.uniform(-0.1, 0.1, nb)
+        off += nw + nb
+    X = np.stack([rng.normal(size=(n, n, n)), rng.uniform(0, 1, (n, n, n))], axis=-1)
+    net = _TorchUNet()
+    net.load_flat(theta)
+    with torch.no_grad():
+        ref = net(torch.from_numpy(X.transpose(3, 0, 1, 2)[None].copy()))[0].numpy()
+    got = cnn.forward(theta, X)[0]
+    assert got.shape == (n, n, n)
+    assert np.allclose(got, ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+    # a wrong wiring is visible: the composition with swapped skip order differs
+    W = net.d0.weight.detach().clone()
+    with torch.no_grad():
+        net.d0.weight.copy_(torch.cat([W[:, 16:], W[:, :16]], dim=1))
+        bad = net(torch.from_numpy(X.transpose(3, 0, 1, 2)[None].copy()))[0].numpy()
+    assert np.linalg.norm(bad - got) > 1e-3 * np.linalg.norm(got)
+
+
+def test_network_gradient_matches_torch_autograd():
+    """Backward of the oracle (weights and input) against torch autograd
+    through the same torch.nn composition, float64."""
+    n = 9
+    rng = np.random.default_rng(5)
+    theta = cnn.init_params(3)
+    off = 0
+    for nw, nb in cnn.layer_sizes():
+        theta[off + nw:off + nw + nb] = rng.uniform(-0.1, 0.1, nb)
+        off += nw + nb
+    X = np.stack([rng.normal(size=(n, n, n)), rng.uniform(0, 1, (n, n, n))], axis=-1)
+    G = rng.normal(size=(n, n, n))
+    net = _TorchUNet()
+    net.load_flat(theta)
+    xt = torch.from_numpy(X.transpose(3, 0, 1, 2)[None].copy()).requires_grad_(True)
+    y = net(xt)[0]
+    (y * torch.from_numpy(G)).sum().backward()
+    _, cache = cnn.forward(theta, X)
+    dtheta, dX = cnn.backward(theta, cache, G)
+    assert np.allclose(dX, xt.grad[0].numpy().transpose(1, 2, 3, 0), rtol=1e-10, atol=1e-12)
+    off = 0
+    for m, (nw, nb) in zip((net.l0a, net.l0b, net.l1a, net.l1b, net.l2a, net.l2b, net.u1, net.d1, net.u0,
+                            net.d0, net.head), cnn.layer_sizes()):
+        g = m.weight.grad
+        g = g.permute(1, 2, 3, 4, 0) if isinstance(m, torch.nn.ConvTranspose3d) else g.permute(0, 2, 3, 4, 1)
+        assert np.allclose(dtheta[off:off + nw], g.reshape(-1).numpy(), rtol=1e-10, atol=1e-12)
+        assert np.allclose(dtheta[off + nw:off + nw + nb], m.bias.grad.numpy(), rtol=1e-10, atol=1e-12)
+        off += nw + nb

@@ -331,3 +331,78 @@ def test_manufactured_solution_convergence():
     assert min(s1) >= 0.9, (h1, s1)
     assert min(s2) >= 1.7, (l2, s2)
     assert errs[-1][2] < 0.05
+
+
+# ---------------------------------------------------------------- network normalisation alpha (Section 5.1)
+
+@pytest.mark.parametrize("k_omega,sigma", [(1.0, 0.0), (2.5, 0.0), (1.0, 30.0)])
+def test_alpha_closed_form_without_coupling(k_omega, sigma):
+    """alpha = RMS of diag(A00) over the free 3D nodes.  With beta = 0 the
+    coupling vanishes and every free node has the trilinear diagonal
+    k h 8/3 + sigma (2h/3)^3 (stiffness 8 x h/3 per cell around the node; the
+    mass diagonal is the cube of the 1D value 2h/3), so alpha equals it."""
+    N = 8
+    h = 1.0 / N
+    s = fem.assemble(small_instance(n_cells=N, beta=0.0, k_omega=k_omega, sigma_omega=sigma))
+    expect = k_omega * h * 8.0 / 3.0 + sigma * (2.0 * h / 3.0) ** 3
+    assert s.alpha == pytest.approx(expect, rel=1e-14)
+
+
+def _brute_coupling_diagonal(inst):
+    """Diagonal of the coupling block M00 = Pi^T W Pi by direct loops: for each
+    P1 element, its two Gauss points, the n_circle points of the wall circle
+    (frame n1 = tau x e_a / |.|, a = argmin |tau_k|, n2 = tau x n1), the
+    trilinear weights of the containing cell, then W_q (Pi_qj)^2 per node."""
+    N = inst.n_cells
+    n = N + 1
+    h = 1.0 / N
+    diag = np.zeros(n ** 3)
+    E = inst.elems_per_segment
+    g = 0.5 / math.sqrt(3.0)
+    for s_id, (p, q) in enumerate(inst.seg):
+        P, Q = inst.vertex_xyz[p], inst.vertex_xyz[q]
+        R, beta = inst.radius[s_id], inst.beta[s_id]
+        tau = (Q - P) / np.linalg.norm(Q - P)
+        a = int(np.argmin(np.abs(tau)))
+        e = np.zeros(3)
+        e[a] = 1.0
+        n1 = np.cross(tau, e)
+        n1 /= np.linalg.norm(n1)
+        n2 = np.cross(tau, n1)
+        ell = np.linalg.norm(Q - P) / E
+        for el in range(E):
+            for tq in (0.5 - g, 0.5 + g):
+                c = P + (el + tq) / E * (Q - P)
+                W = 2.0 * math.pi * R * beta * ell / 2.0
+                pi = {}
+                for k in range(inst.n_circle):
+                    th = 2.0 * math.pi * k / inst.n_circle
+                    x = c + R * (math.cos(th) * n1 + math.sin(th) * n2)
+                    cell = [min(int(math.floor(x[d] / h)), N - 1) for d in range(3)]
+                    xi = [x[d] / h - cell[d] for d in range(3)]
+                    for dz in (0, 1):
+                        for dy in (0, 1):
+                            for dx in (0, 1):
+                                wgt = ((xi[0] if dx else 1 - xi[0]) * (xi[1] if dy else 1 - xi[1])
+                                       * (xi[2] if dz else 1 - xi[2]))
+                                node = (cell[0] + dx) + n * (cell[1] + dy) + n * n * (cell[2] + dz)
+                                pi[node] = pi.get(node, 0.0) + wgt / inst.n_circle
+                for node, v in pi.items():
+                    diag[node] += W * v * v
+    return diag
+
+
+def test_alpha_with_coupling_brute_force():
+    """alpha on an 8^3 instance with coupling: RMS over the free nodes of
+    k h 8/3 + the brute-force coupling diagonal."""
+    inst = small_instance(n_cells=8, n_segments=5, radius=0.03, beta=3.0)
+    s = fem.assemble(inst)
+    h = 1.0 / 8
+    free = ~fem.boundary_mask(8)
+    d = h * 8.0 / 3.0 + _brute_coupling_diagonal(inst)
+    expect = math.sqrt(float(np.mean(d[free] ** 2)))
+    assert s.alpha == pytest.approx(expect, rel=1e-13)
+    # the coupling is large enough here to move alpha well away from 8h/3
+    assert s.alpha > (1 + 1e-4) * h * 8.0 / 3.0
+    # and the assembled diagonal itself agrees node by node
+    assert np.allclose(s.A.diagonal()[:s.n3d][free], d[free], rtol=1e-13)

@@ -1,4 +1,5 @@
 """Pins of the oracle FGMRES and block preconditioner (Sections 2.2 and 4)."""
+import math
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -220,3 +221,120 @@ def test_distance_input_is_the_unit_norm_distance_field():
     assert abs(np.linalg.norm(d) - 1.0) < 1e-12
     k = np.argmax(s.dist)
     assert np.allclose(d * (s.dist[k] / d[k]), s.dist, rtol=1e-12, atol=0)
+
+
+def test_neural_3d_solve_scaling_and_dirichlet_rule():
+    """P3D(b) = ||b|| alpha^-1 U([b/||b||, d/||d||]) with Dirichlet rows z = b
+    (Section 4.1: the network sees unit-norm inputs; Section 5.1: alpha).  With
+    stub networks that return one input channel, the result is fixed by hand:
+    U = channel 0 gives z = b / alpha on the free rows; U = channel 1 gives
+    ||b|| / alpha * d / ||d||; every Dirichlet row returns b whatever U is."""
+    s = _c1()
+    n = s.n_cells + 1
+    bnd = s.boundary
+    rng = np.random.default_rng(21)
+    b = rng.normal(size=s.n3d)
+    dg = s.A.diagonal()[:s.n3d][~bnd]
+    alpha = math.sqrt(float(np.sum(dg * dg)) / dg.size)
+    z = krylov.p3d_neural(s, lambda X: X[..., 0])(b)
+    assert np.allclose(z[~bnd], b[~bnd] / alpha, rtol=1e-13, atol=0)
+    assert np.array_equal(z[bnd], b[bnd])
+    z = krylov.p3d_neural(s, lambda X: X[..., 1])(b)
+    d = np.asarray(s.dist, dtype=np.float64)
+    expect = np.linalg.norm(b) / alpha * d / np.linalg.norm(d)
+    assert np.allclose(z[~bnd], expect[~bnd], rtol=1e-13, atol=0)
+    assert np.array_equal(z[bnd], b[bnd])
+    # the input tensor is laid out [z][y][x][channel] on the n^3 grid
+    seen = {}
+
+    def spy(X):
+        seen["X"] = X.copy()
+        return np.zeros(X.shape[:3])
+    z = krylov.p3d_neural(s, spy)(b)
+    assert seen["X"].shape == (n, n, n, 2)
+    assert np.allclose(seen["X"][..., 0].ravel(), b / np.linalg.norm(b), rtol=1e-15, atol=0)
+    assert np.all(z[~bnd] == 0.0)
+    # zero input maps to zero without calling the network
+    assert not np.any(krylov.p3d_neural(s, lambda X: 1 / 0)(np.zeros(s.n3d)))
+
+
+def test_neural_3d_solve_positively_homogeneous():
+    """For the real (nonlinear) network P3D(c b) = c P3D(b) for c > 0: the
+    input is normalised and the output rescaled by ||b||."""
+    s = _c1()
+    theta = cnn.init_params(4)
+    p = krylov.p3d_neural(s, lambda X: cnn.forward(theta, X)[0])
+    b = np.random.default_rng(22).normal(size=s.n3d)
+    z1 = p(b)
+    for c in (1e-6, 0.37, 250.0):
+        assert np.allclose(p(c * b), c * z1, rtol=1e-12, atol=0)
+    # not odd: the network is not linear, so P(-b) differs from -P(b)
+    assert np.linalg.norm(p(-b) + z1) > 1e-3 * np.linalg.norm(z1)
+
+
+@pytest.mark.parametrize("k_omega,sigma", [(1.0, 0.0), (1.7, 25.0)])
+def test_stiffness_eigenvalues_match_dense(k_omega, sigma):
+    """The sine-mode eigenvalues of the free-node 3D block (no coupling)
+    against a dense symmetric eigensolver on a 6^3 grid."""
+    inst = synth.make_instance(3, 6, n_segments=2, elems_per_segment=2, radius=0.02, beta=0.0,
+                               k_omega=k_omega, sigma_omega=sigma)
+    s = fem.assemble(inst)
+    A00 = s.blocks()[0].toarray()
+    free = ~s.boundary
+    ev = np.sort(np.linalg.eigvalsh(A00[np.ix_(free, free)]))
+    lam = np.sort(krylov.stiffness_eigenvalues(6, k_omega, sigma).ravel())
+    assert np.allclose(lam, ev, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("N,k_omega,sigma", [(8, 1.0, 0.0), (12, 2.0, 7.0)])
+def test_stiffness_inverse_solves_uncoupled_block(N, k_omega, sigma):
+    """With beta = 0 the 3D block is the stiffness-plus-mass matrix alone and
+    the sine-transform solve is its exact inverse: A00 z = b to rounding, equal
+    to a sparse LU solve, and the identity on the Dirichlet rows."""
+    inst = synth.make_instance(5, N, n_segments=3, elems_per_segment=3, radius=0.02, beta=0.0,
+                               k_omega=k_omega, sigma_omega=sigma)
+    s = fem.assemble(inst)
+    A00 = s.blocks()[0].tocsc()
+    b = np.random.default_rng(N).normal(size=s.n3d)
+    z = krylov.p3d_stiffness_inverse(s, k_omega, sigma)(b)
+    assert np.linalg.norm(A00 @ z - b) <= 1e-12 * np.linalg.norm(b)
+    zd = spla_solve(A00, b)
+    assert np.linalg.norm(z - zd) <= 1e-12 * np.linalg.norm(zd)
+    assert np.array_equal(z[s.boundary], b[s.boundary])
+
+
+def spla_solve(A, b):
+    import scipy.sparse.linalg as spla
+    return spla.spsolve(A, b)
+
+
+def test_reference_solution_equals_direct_solve():
+    """The reference solution (FGMRES with the stiffness-inverse block
+    preconditioner, tol 1e-13) equals the sparse LU solution of the coupled
+    system within 1e-11 on a 12^3 instance with strong coupling, in few steps."""
+    inst = synth.make_instance(8, 12, n_segments=9, elems_per_segment=3, radius=0.02, beta=2.0)
+    s = fem.assemble(inst)
+    r = krylov.reference_solution(s, tol=1e-13)
+    xd = krylov.direct_solve(s)
+    assert r.converged and r.iters <= 40
+    assert np.linalg.norm(r.x - xd) <= 1e-11 * np.linalg.norm(xd)
+
+
+def test_reference_pool_reports_errors():
+    """The per-instance error helper on two worker processes: the direct
+    solution has error ~1e-12 and residual ~1e-13; a perturbed one reports the
+    perturbation it carries, in both norms."""
+    from oracle import reference
+    insts = [synth.make_instance(30 + i, 8, n_segments=3 + i, elems_per_segment=3, radius=0.02, beta=1.0)
+             for i in range(2)]
+    xd = [krylov.direct_solve(fem.assemble(i)) for i in insts]
+    bad = [x.copy() for x in xd]
+    for x in bad:
+        x[3] += 1e-3 * np.max(np.abs(x))
+    res = reference.errors_vs_oracle(insts, [[x, y] for x, y in zip(xd, bad)], workers=2)
+    for r, x in zip(res, xd):
+        assert r["ref_converged"] and r["ref_rel_res"] <= 1e-12
+        good, off = r["cands"]
+        assert good["rel_res"] <= 1e-12 and good["err"] <= 1e-10 and good["err_max"] <= 1e-10
+        assert off["err_max"] == pytest.approx(1e-3, rel=1e-6)
+        assert off["err"] == pytest.approx(1e-3 * np.max(np.abs(x)) / np.linalg.norm(x), rel=1e-6)
