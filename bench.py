@@ -91,6 +91,29 @@ def unet_flops(n):
     return tot
 
 
+STAGES = ("L0a", "L0b", "L1a", "L1b", "L2a", "L2b", "U1", "D1", "U0", "D0+H")
+
+
+def stage_costs(n):
+    """Per instance, for each stage of the in-solver network at grid side n:
+    algorithmic FLOPs (as in `unet_flops`; D0 carries the 1x1 head) and
+    compulsory HBM bytes (each input read once and each output written once:
+    BF16 activations, FP32 Krylov vector and distance field in L0a, FP32 z0
+    out of D0 + H)."""
+    n1, n2 = (n + 1) // 2, (n + 3) // 4
+    c0, c1, c2 = n ** 3, n1 ** 3, n2 ** 3
+    ne = (n1 + 1) // 2
+    t2_1 = (ne + 2 * (n1 - ne)) ** 3          # U1 output taps (64 -> 32 at n1)
+    ne0 = (n + 1) // 2
+    t2_0 = (ne0 + 2 * (n - ne0)) ** 3         # U0 output taps (32 -> 16 at n)
+    fl = [2 * 27 * 2 * 16 * c0, 2 * 27 * 16 * 16 * c0, 2 * 27 * 16 * 32 * c1, 2 * 27 * 32 * 32 * c1,
+          2 * 27 * 32 * 64 * c2, 2 * 27 * 64 * 64 * c2, 2 * t2_1 * 64 * 32, 2 * 27 * 64 * 32 * c1,
+          2 * t2_0 * 32 * 16, 2 * 27 * 32 * 16 * c0 + 2 * 16 * c0]
+    by = [8 * c0 + 32 * c0, 64 * c0, 32 * c0 + 64 * c1, 128 * c1, 64 * c1 + 128 * c2, 256 * c2, 128 * c2 + 64 * c1,
+          192 * c1, 64 * c1 + 32 * c0, 64 * c0 + 4 * c0]
+    return fl, by
+
+
 def spmv_traffic(target):
     """HBM bytes per batched SpMV launch at the stencil sweep's z-split target
     `target` (0: the default 2048) from the committed rocprofv3 PMC summary
@@ -110,6 +133,43 @@ def spmv_traffic(target):
     return float(m.group(1)) if m else None
 
 
+def stage_traffic(stage):
+    """HBM bytes per launch of one network stage at 64^3 x 16 from the
+    committed rocprofv3 PMC summary, or None when the convolution sources
+    changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "unet_64x16_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    for name in ("conv_mfma.hip", "conv.hip"):
+        src = os.path.join(ROOT, "paper_2505_08491_amd", "csrc", name)
+        m = re.search(r"^%s sha256: ([0-9a-f]+)$" % re.escape(name), text, re.M)
+        if not m or m.group(1) != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+    m = re.search(r"^traffic bytes per launch \[%s\]: (\d+)$" % re.escape(stage), text, re.M)
+    return float(m.group(1)) if m else None
+
+
+def host_cpu():
+    """Cores this process may run on and the CPU model name of the host."""
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        nproc = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    return nproc, model
+
+
 def time_kernel(ctx, fn, reps):
     """Average duration (ms) of `fn` launches measured with HIP events on the
     library's stream."""
@@ -126,11 +186,15 @@ def time_kernel(ctx, fn, reps):
     return start.elapsed_time(end) / reps
 
 
-def cpu_baseline(inst, gpu_neural_iters, gpu_jacobi_iters, weights, n_neural, n_jacobi):
+def cpu_baseline(inst, gpu_neural_iters, gpu_jacobi_iters, weights, n_neural, n_jacobi, x_gpu=None):
     """The FP64 oracle on the host cores: a bounded sample of the same solve
     (n_neural FGMRES iterations with the FP64 network and n_jacobi
     Jacobi-GMRES iterations on instance 0), scaled to solves/s with the
-    per-solve iteration counts the GPU needed."""
+    per-solve iteration counts the GPU needed.  With x_gpu (the GPU's
+    solution of instance 0) it also states that solution's error against the
+    oracle: the oracle's reference solution x* to FP64 true relative residual
+    1e-12, ||x - x*|| / ||x*||, max |x - x*| / max |x*| and the true relative
+    residual of x on the oracle's own A."""
     import numpy as np
     from oracle import cnn as ocnn
     from oracle import fem, krylov
@@ -139,9 +203,20 @@ def cpu_baseline(inst, gpu_neural_iters, gpu_jacobi_iters, weights, n_neural, n_
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
+    nproc, model = host_cpu()
     t0 = time.time()
     s = fem.assemble(inst)
     t_asm = time.time() - t0
+    err = None
+    if x_gpu is not None:
+        t0 = time.time()
+        ref = krylov.reference_solution(s, tol=1e-12, k_omega=inst.k_omega, sigma_omega=inst.sigma_omega)
+        xs = ref.x
+        err = {"instance": 0, "oracle_ref_rel_res": float(ref.rel_res),
+               "err": float(np.linalg.norm(x_gpu - xs) / np.linalg.norm(xs)),
+               "err_max": float(np.max(np.abs(x_gpu - xs)) / np.max(np.abs(xs))),
+               "true_rel_res_on_oracle_A": float(np.linalg.norm(s.F - s.A @ x_gpu) / np.linalg.norm(s.F)),
+               "s": time.time() - t0}
     th = weights.astype(np.float64)
     net = lambda X: ocnn.forward(th, X)[0]
     Q = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))
@@ -152,6 +227,7 @@ def cpu_baseline(inst, gpu_neural_iters, gpu_jacobi_iters, weights, n_neural, n_
     krylov.fgmres(s.A, s.F, precond=krylov.jacobi(s.A), restart=50, tol=1e-30, max_iters=n_jacobi)
     t_jac = (time.time() - t0) / n_jacobi
     return {"value": 1.0 / (t_neu * gpu_neural_iters), "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+            "host_nproc": int(nproc), "host_cpu_model": model, "error_vs_oracle": err,
             "sample": (f"instance 0 of the workload: {n_neural} neural FGMRES(30) iterations (FP64 network, "
                        f"{t_neu:.2f} s/iter) and {n_jacobi} Jacobi-GMRES(50) iterations ({t_jac * 1e3:.1f} ms/iter), "
                        f"scaled by the GPU's mean iterations per solve ({gpu_neural_iters:.1f} neural, "
@@ -225,25 +301,58 @@ def main():
         t_tune = time.time() - t0
     T, st = run(neural_opts, a.steps, a.warmup)
     rel_n = true_rel()
+    x0_neural = x[S.offsets[0]:S.offsets[1]].cpu().numpy()   # instance 0, for the error against the oracle
     neural_iters = [s["iters"] + s["fallback_iters"] for s in st]
     conv_all = all(s["converged"] for s in st)
     n_fb = sum(s["used_fallback"] for s in st)
 
-    # roofline of the batched FP32 SpMV (HBM-bound), events on the library stream
+    # the network stage by stage as the solver applies it (HIP events between
+    # the stages on the library stream, launch shapes as tuned)
+    n = a.n_cells + 1
+    stage_ms = S.layer_times(reps=10)
+    fl, by = stage_costs(n)
+    stages = []
+    for k, name in enumerate(STAGES):
+        f, b_ = fl[k] * S.n_inst, by[k] * S.n_inst
+        floor = max(b_ / (HBM_PEAK_GBPS * 1e9), f / (BF16_PEAK_TFLOPS * 1e12)) * 1e3
+        stages.append({"stage": name, "ms": stage_ms[k], "gflop": f / 1e9, "algorithmic_mb": b_ / 1e6,
+                       "tflops": f / (stage_ms[k] * 1e-3) / 1e12,
+                       "frac_bf16_peak": f / (stage_ms[k] * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+                       "floor_ms": floor, "frac_of_floor": floor / stage_ms[k],
+                       "bound": "hbm" if b_ / (HBM_PEAK_GBPS * 1e9) > f / (BF16_PEAK_TFLOPS * 1e12) else "mfma"})
+    dom = max(range(len(STAGES)), key=lambda k: stage_ms[k])
+
+    # the batched FP32 SpMV (HBM-bound): every timed launch starts after a
+    # 1 GiB read, which evicts the 256 MB last-level cache (MALL) without
+    # leaving dirty lines to write back, so operator and vectors come from
+    # HBM; events on the library stream around each launch
     xs = torch.randn(S.ntot, device="cuda")
     ys = torch.empty_like(xs)
-    reps = 50  # launches back to back inside one library call: no host time between them
-    ms_spmv = time_kernel(ctx, lambda: S.spmv_repeat(xs, ys, reps), 3) / reps
+    flush = torch.ones(1 << 28, device="cuda")
+    fsum = torch.empty(20, device="cuda")
+    e0 = [torch.cuda.Event(enable_timing=True) for _ in range(20)]
+    e1 = [torch.cuda.Event(enable_timing=True) for _ in range(20)]
+    S.spmv_repeat(xs, ys, 1)
+    with torch.cuda.stream(ctx.stream):
+        for k in range(20):
+            torch.sum(flush, dim=0, out=fsum[k])
+            e0[k].record(ctx.stream)
+            S.spmv_repeat(xs, ys, 1)
+            e1[k].record(ctx.stream)
+    e1[-1].synchronize()
+    ms_spmv = sum(e0[k].elapsed_time(e1[k]) for k in range(20)) / 20
     gbps = spmv_bytes(S) / (ms_spmv * 1e-3) / 1e9
+    # the same launches back to back (operator partly resident in the MALL)
+    reps = 50
+    ms_spmv_warm = time_kernel(ctx, lambda: S.spmv_repeat(xs, ys, reps), 3) / reps
     # practical copy bandwidth (1 GiB device-to-device) on the same stream
     cbuf = torch.empty(2, 1 << 28, device="cuda")
     with torch.cuda.stream(ctx.stream):
         ms_copy = time_kernel(ctx, lambda: cbuf[1].copy_(cbuf[0]), 10)
     copy_gbps = 2 * cbuf[0].numel() * 4 / (ms_copy * 1e-3) / 1e9
-    del cbuf
+    del cbuf, flush, fsum
     # preconditioner application (1D solve + extension + U-net + unscale) on the batch
     ms_prec = time_kernel(ctx, lambda: S.precond_apply(xs), 5)
-    n = a.n_cells + 1
     cnn_flop = unet_flops(n) * S.n_inst
     # the network alone (stored activations, BF16 MFMA) on the same batch
     wd = torch.from_numpy(np.ascontiguousarray(w, dtype=np.float32)).cuda()
@@ -323,9 +432,10 @@ def main():
         "metric": "solves/s to rel-res 1e-8 at 64^3: neural FGMRES vs Jacobi GMRES; HBM GB/s",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": T / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "bf16/f32/f64", "data": "synthetic",
         "config": {"workload": f"{wl_desc}, FP32 vectors and SpMV, FP64 MGS/Givens/x/true residual, "
-                               f"{a.cnn_dtype} U-net", "instances": a.count, "n_cells": a.n_cells,
+                               f"{a.cnn_dtype} U-net with FP32 accumulation", "instances": a.count,
+                   "n_cells": a.n_cells,
                    "restart": 30, "tol": 1e-8, "cnn_dtype": a.cnn_dtype,
                    "weights": os.path.relpath(wpath, ROOT) if trained else "untrained (Kaiming init)"},
         "neural": {"iters_mean": float(np.mean(neural_iters)), "iters_max": int(max(neural_iters)),
@@ -335,13 +445,26 @@ def main():
         "neural_no_distance": nodist,
         "neural_precision": precision or None,
         "jacobi": jac,
-        "roofline": {"bound": "hbm", "kernel": "k_stencil_sweep + k_mrows (batched y = (S + M) x, FP32)",
-                     "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
-                     "traffic": (spmv_traffic(tuned[11] if tuned else 0)
-                                 if (a.workload, a.n_cells, a.count) == ("transfer", 64, 16) else None),
-                     "algorithmic_bytes": spmv_bytes(S), "ms_per_launch": ms_spmv,
-                     "copy_gbps": copy_gbps},
+        "roofline": {"bound": stages[dom]["bound"],
+                     "kernel": f"network stage {STAGES[dom]} (BF16 MFMA convolution launch, in-solver shape)",
+                     "achieved": stages[dom]["tflops"], "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": stages[dom]["frac_bf16_peak"],
+                     "traffic": (stage_traffic(STAGES[dom])
+                                 if (a.workload, a.n_cells, a.count, a.cnn_dtype) == ("transfer", 64, 16, "bf16")
+                                 else None),
+                     "algorithmic_flops": fl[dom] * S.n_inst, "algorithmic_bytes": by[dom] * S.n_inst,
+                     "ms_per_launch": stage_ms[dom]},
+        "unet_stages": stages,
+        "spmv": {"bound": "hbm", "kernel": "k_stencil_sweep + k_mrows (batched y = (S + M) x, FP32)",
+                 "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+                 "timing": "each launch after a 1 GiB read that evicts the last-level cache",
+                 "traffic": (spmv_traffic(tuned[11] if tuned else 0)
+                             if (a.workload, a.n_cells, a.count) == ("transfer", 64, 16) else None),
+                 "algorithmic_bytes": spmv_bytes(S), "ms_per_launch": ms_spmv,
+                 "ms_per_launch_back_to_back": ms_spmv_warm, "copy_gbps": copy_gbps},
         "unet": {"bound": "mfma", "dtype": a.cnn_dtype, "gflop_per_forward": cnn_flop / 1e9,
+                 "ms_in_solver": sum(stage_ms), "frac_in_solver": cnn_flop / (sum(stage_ms) * 1e-3) / 1e12 /
+                 BF16_PEAK_TFLOPS,
                  "ms_per_forward": ms_cnn, "achieved": cnn_flop / (ms_cnn * 1e-3) / 1e12,
                  "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                  "frac": cnn_flop / (ms_cnn * 1e-3) / 1e12 / BF16_PEAK_TFLOPS},
@@ -355,7 +478,7 @@ def main():
     if not a.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(insts[0], float(np.mean(neural_iters)),
                                            jac["iters_mean"] if jac else 0.0, w, a.cpu_neural_iters,
-                                           a.cpu_jacobi_iters)
+                                           a.cpu_jacobi_iters, x_gpu=x0_neural)
     print(json.dumps(out), flush=True)
 
 

@@ -129,7 +129,7 @@ mdnp_status mdnp_sys_sizes(const mdnp_sys* sys, int32_t inst, int32_t* n3d, int3
 
 /* Sizes of the split operator of instance `inst` on the device, A = S + M
  * (Section 2.1: S the trilinear stiffness/mass stencil of the free 3D nodes,
- * identical at every interior node; M the coupling terms of Eq. (2.3)-(2.5)
+ * identical at every interior node; M the coupling terms of eq. "mainsys"
  * and the 1D rows): entries stored for M and rows of M that hold any entry
  * (3D rows touched by the coupling plus every 1D row). */
 mdnp_status mdnp_sys_split_sizes(const mdnp_sys* sys, int32_t inst, int64_t* m_nnz, int64_t* m_rows);
@@ -215,6 +215,17 @@ mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* sys, int32_t steps);
  * (the defaults are kept). */
 mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* sys, int32_t* chosen);
 
+/* Time the network as the solver applies it (Section 4.2 U-net inside the
+ * 3D block of eq. "twosteps"), stage by stage, on this system's batch and
+ * grid with the launch shapes currently chosen: `reps` applications to a
+ * fixed vector, HIP events on the context's stream between the stages.
+ * ms (host, [10]) receives the average duration in milliseconds of L0a, L0b,
+ * L1a, L1b, L2a, L2b, U1, D1, U0 and D0 (which includes the 1x1 head and the
+ * unscaling).  Allocates two vectors of the system's size for the duration of
+ * the call.  Errors: MDNP_E_ARG, MDNP_E_STATE (no neural preconditioner),
+ * MDNP_E_OOM. */
+mdnp_status mdnp_cnn_layer_times(mdnp_ctx* ctx, mdnp_sys* sys, int32_t reps, float* ms);
+
 /* ---------------------------------------------------------------- solve */
 
 /* Restarted right-preconditioned FGMRES(m) on every instance at once (Section
@@ -243,7 +254,8 @@ mdnp_status mdnp_history(const mdnp_sys* sys, int32_t inst, double* out, int32_t
 /* Copy Arnoldi vector v_k (0 <= k <= restart) of the last cycle of the last
  * solve into d_out (device, vec_dtype, concatenated length): the
  * solver-generated residual samples used to train the network (Section 4.1,
- * Krylov augmentation).  Errors: MDNP_E_STATE before any solve. */
+ * Krylov augmentation).  Errors: MDNP_E_STATE before any solve, MDNP_E_ARG
+ * for k outside [0, restart of that last cycle]. */
 mdnp_status mdnp_export_basis(mdnp_ctx* ctx, const mdnp_sys* sys, int32_t k, void* d_out, void* hip_stream);
 
 /* ---------------------------------------------------------------- path steps (device) */
@@ -260,8 +272,11 @@ mdnp_status mdnp_spmv(mdnp_ctx* ctx, mdnp_sys* sys, int32_t block, const void* d
 mdnp_status mdnp_spmv_repeat(mdnp_ctx* ctx, mdnp_sys* sys, const void* d_x, void* d_y, mdnp_dtype dtype,
                              int32_t reps, void* hip_stream);
 
-/* z1 = A11^-1 v1 for every instance: the exact 1D solve of eq. "twosteps" by a
- * leaves-first LDL^T factorisation of the tree matrix (no fill).  d_v and d_z
+/* z1 = A11^-1 v1 for every instance: the exact 1D solve of eq. "twosteps".
+ * The tree matrix is factored without fill in chain-compressed form (each
+ * segment's interior nodes as a tridiagonal block, then the Schur complement
+ * on the tree vertices) when every segment has at most 32 interior nodes,
+ * else as a leaves-first LDL^T of the whole tree.  d_v and d_z
  * are full concatenated vectors of the system's vec_dtype; only the 1D parts
  * are read and written. */
 mdnp_status mdnp_tree_solve(mdnp_ctx* ctx, mdnp_sys* sys, const void* d_v, void* d_z,

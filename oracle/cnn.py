@@ -175,20 +175,49 @@ def check_grid(n):
         raise ValueError(f"grid side n={n} must satisfy n = 1 (mod 4), n >= 5")
 
 
-def forward(theta, X):
-    """U(X) for one sample X [n, n, n, 2]; returns ([n, n, n], cache)."""
+def round_bf16(x):
+    """Round to the nearest bfloat16 value (the upper half of an IEEE binary32:
+    8 exponent bits, 8 significand bits), ties to an even significand, by way
+    of the nearest binary32.  Finite inputs only."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    bits = f.view(np.uint32).astype(np.uint64)
+    low = bits & 0xFFFF
+    keep = bits >> 16
+    up = (low > 0x8000) | ((low == 0x8000) & ((keep & 1) == 1))
+    out = ((keep + up.astype(np.uint64)) << 16).astype(np.uint32)
+    return out.view(np.float32).astype(np.float64)
+
+
+def forward(theta, X, emulate=None):
+    """U(X) for one sample X [n, n, n, 2]; returns ([n, n, n], cache).
+
+    emulate="bf16" evaluates the network as the mixed-precision kernels do, so
+    that both sides take their ReLU decisions on the same values: the input
+    channels and the weights of the ten 3x3x3 layers are rounded to bfloat16
+    (biases and the 1x1 head stay in full precision) and every layer's output,
+    after its ReLU, is rounded to bfloat16 before the next layer reads it; the
+    arithmetic itself stays FP64.  The cache then holds the rounded tensors,
+    and `backward` gives the adjoint of that network at those points (the
+    rounding passed straight through, the weights of the adjoint unrounded).
+    """
     n = X.shape[0]
     check_grid(n)
     P = unflatten(theta)
+    rnd = (lambda t: t) if emulate is None else round_bf16
+    if emulate not in (None, "bf16"):
+        raise ValueError(emulate)
+    Pf = [(w if LAYERS[i][1] == "point" else rnd(w), b) for i, (w, b) in enumerate(P)]
+    X = rnd(X)
     cache = {"X": X}
     idx = {name: i for i, (name, *_r) in enumerate(LAYERS)}
 
     def run(name, inp):
         i = idx[name]
         _, kind, _, _, relu = LAYERS[i]
-        z = _apply(kind, inp, *P[i])
+        z = _apply(kind, inp, *Pf[i])
         cache[name] = (inp, z)
-        return np.maximum(z, 0.0) if relu else z
+        out = np.maximum(z, 0.0) if relu else z
+        return out if kind == "point" else rnd(out)
 
     a = run("L0a", X)
     s0 = run("L0b", a)

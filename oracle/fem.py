@@ -29,6 +29,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
+from typing import Optional
 
 import numpy as np
 import scipy.sparse as sp
@@ -164,7 +165,7 @@ class System:
     A: sp.csr_matrix          # full block matrix after Dirichlet elimination
     F: np.ndarray             # right-hand side [0; f_1]
     boundary: np.ndarray      # bool [n3d]
-    dist: np.ndarray          # distance field d_h at the 3D nodes
+    dist: Optional[np.ndarray]  # distance field d_h at the 3D nodes (None if not tabulated)
     alpha: float              # RMS of diag(A00) over free 3D nodes
     Pi: sp.csr_matrix         # averaging operator, [n_gauss, n3d] (before BCs)
     Phi: sp.csr_matrix        # 1D evaluation at Gauss points, [n_gauss, n1d]
@@ -232,8 +233,11 @@ def distance_field(n_cells, vertex_xyz, seg) -> np.ndarray:
     return d
 
 
-def assemble(inst) -> System:
+def assemble(inst, with_distance: bool = True) -> System:
     """Assemble A = K + M and F for one instance (eq. "mainsys").
+
+    with_distance=False leaves System.dist as None: the distance field is only
+    an input of the network and costs O(nodes x segments) to tabulate.
 
     K00: trilinear stiffness k_Omega (grad u, grad v) plus sigma_Omega mass.
     K11: k_Lambda pi R^2 (u', v') on the P1 graph mesh.
@@ -327,7 +331,7 @@ def assemble(inst) -> System:
     F = np.zeros(n3d + n1d)
     F[n3d:] = F1
 
-    dist = distance_field(N, inst.vertex_xyz, inst.seg)
+    dist = distance_field(N, inst.vertex_xyz, inst.seg) if with_distance else None
     dg = A.diagonal()[:n3d][~bnd]
     alpha = float(np.sqrt(np.mean(dg ** 2)))
     return System(n_cells=N, n3d=n3d, n1d=n1d, A=A, F=F, boundary=bnd, dist=dist, alpha=alpha,

@@ -24,7 +24,7 @@ import numpy as np
 def _worker(args):
     inst, cands, tol = args
     from oracle import fem, krylov
-    s = fem.assemble(inst)
+    s = fem.assemble(inst, with_distance=False)
     ref = krylov.reference_solution(s, tol=tol, k_omega=inst.k_omega, sigma_omega=inst.sigma_omega)
     xs = ref.x
     F = s.F

@@ -251,6 +251,14 @@ class System:
         self.ctx._check(lib.mdnp_autotune(self.ctx.h, self.h, out))
         return list(out)
 
+    def layer_times(self, reps: int = 5):
+        """Average milliseconds of each stage of the in-solver network
+        application (L0a, L0b, L1a, L1b, L2a, L2b, U1, D1, U0, D0 + head),
+        HIP events on the library stream."""
+        out = (C.c_float * 10)()
+        self.ctx._check(lib.mdnp_cnn_layer_times(self.ctx.h, self.h, int(reps), out))
+        return list(out)
+
     def set_inner_steps(self, steps: int):
         """Inner FGMRES(steps) 3D solve with the network as preconditioner (0: off)."""
         self.ctx._check(lib.mdnp_set_inner_steps(self.ctx.h, self.h, int(steps)))

@@ -772,6 +772,19 @@ extern "C" mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* s, int32_t* chosen
   });
 }
 
+extern "C" mdnp_status mdnp_cnn_layer_times(mdnp_ctx* ctx, mdnp_sys* s, int32_t reps, float* ms) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !ms) fail(MDNP_E_ARG, "null argument");
+    if (reps < 1) fail(MDNP_E_ARG, "reps must be >= 1");
+    if (s->kind != MDNP_PREC_NEURAL || !s->prec_set) fail(MDNP_E_STATE, "no neural preconditioner set");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!cnn_layer_times(s, ctx->stream, reps, ms)) fail(MDNP_E_OOM, "layer timing: buffers or events");
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
 extern "C" mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* s, int32_t steps) {
   if (!ctx) return MDNP_E_ARG;
   return guarded(ctx, [&] {
@@ -1031,6 +1044,7 @@ void solve_impl(mdnp_ctx* ctx, mdnp_sys* s, const double* d_b, double* d_x, cons
     if ((!any_active && !pending) || ++cycles > max_cycles) break;
     if (!any_active) continue;  // only restarted instances: recompute their residuals
     const int m = all_fb ? mf : m0;
+    w.last_m = m;
     launch_scale_to<T>(s, w.r, (T*)w.V, w.st, stream);
     // the cycle in chunks of kCycleChunk steps; after each chunk the host reads
     // the instance states and stops once none takes part any more (the
@@ -1156,8 +1170,9 @@ extern "C" mdnp_status mdnp_export_basis(mdnp_ctx* ctx, const mdnp_sys* s, int32
   if (!ctx) return MDNP_E_ARG;
   return guarded(ctx, [&] {
     if (!s || !d_out) fail(MDNP_E_ARG, "null argument");
-    if (!s->work.V) fail(MDNP_E_STATE, "no solve has run on this system");
-    if (k < 0 || k > s->work.m) fail(MDNP_E_ARG, "basis index out of range");
+    if (!s->work.V || s->work.last_m < 0) fail(MDNP_E_STATE, "no solve has run on this system");
+    if (k < 0 || k > s->work.last_m)
+      fail(MDNP_E_ARG, "basis index out of range (the last cycle had restart " + std::to_string(s->work.last_m) + ")");
     HIPCHK(hipSetDevice(ctx->device));
     const size_t es = vsize(s->vec_dtype);
     HIPCHK(hipMemcpyAsync(d_out, (const char*)s->work.V + es * (size_t)s->ntot * k, es * (size_t)s->ntot,

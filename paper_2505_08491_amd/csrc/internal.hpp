@@ -110,6 +110,7 @@ struct InnerState {
 
 struct SolveWork {
   int m = 0;                   // restart the buffers were sized for
+  int last_m = -1;             // restart of the last cycle run (-1: no solve yet)
   int hist_cap = 0;
   void* V = nullptr;           // (m+1) x ntot vectors
   void* Z = nullptr;           // m x ntot

@@ -54,11 +54,11 @@ def _inputs(n, batch, seed):
     return X.astype(np.float32).astype(np.float64), G.astype(np.float32).astype(np.float64)
 
 
-def _oracle_grads(th, X, G):
+def _oracle_grads(th, X, G, emulate=None):
     gref = np.zeros(ocnn.n_params())
     dxs = []
     for k in range(X.shape[0]):
-        _, cache = ocnn.forward(th, X[k])
+        _, cache = ocnn.forward(th, X[k], emulate=emulate)
         g, dX = ocnn.backward(th, cache, G[k])
         gref += g
         dxs.append(dX)
@@ -83,7 +83,16 @@ def _layer_errors(dw, gref):
 def test_cnn_backward_matches_oracle(ctx, dtype, n, tol):
     """Weight and input gradients of the whole network for an upstream
     gradient G, from the activations the forward kernel stored (BF16 or
-    FP32), against the oracle's FP64 adjoint on the same weights and inputs."""
+    FP32), against the oracle's FP64 adjoint on the same weights and inputs.
+    The BF16 path is compared with the oracle's network evaluated at the
+    kernels' precision (BF16 inputs, weights and stored activations, FP64
+    arithmetic), so that both sides take the same ReLU decisions.  The two
+    still part where FP32 and FP64 sums round to neighbouring BF16 values
+    (a few in 10^5 of the first layer's outputs at 33^3), and these one-step
+    differences spread and grow through the later layers (measured: 0.2%
+    relative in the last activations, 2.5% in the gradients at 33^3), hence
+    the 5e-2 bound for BF16; the
+    distance from the all-FP64 network is the effect of BF16 and is printed."""
     batch = 2
     th = _theta(11 + n)
     X, G = _inputs(n, batch, 30 + n)
@@ -91,11 +100,15 @@ def test_cnn_backward_matches_oracle(ctx, dtype, n, tol):
     saved = torch.empty(ctx.saved_bytes(batch, n, dtype), dtype=torch.uint8, device="cuda")
     ctx.cnn_forward(w, dev(X.reshape(batch, -1, 2), torch.float32), n, dtype, saved=saved)
     dw, dx = ctx.cnn_backward(w, saved, dev(G.reshape(batch, -1), torch.float32), batch, n, dtype, want_dx=True)
-    gref, dxref = _oracle_grads(th, X, G)
+    emulate = "bf16" if dtype == "bf16" else None
+    gref, dxref = _oracle_grads(th, X, G, emulate)
     dw = dw.cpu().double().numpy()
     dx = dx.cpu().double().numpy().reshape(dxref.shape)
     layers = _layer_errors(dw, gref)
-    print(dtype, n, "dw", _rel(dw, gref), "dx", _rel(dx, dxref), "per layer", np.round(layers, 4))
+    print(dtype, n, "dw", _rel(dw, gref), "dx", _rel(dx, dxref), "per layer", np.round(layers, 6))
+    if emulate:
+        g64, dx64 = _oracle_grads(th, X, G)
+        print(dtype, n, "against the all-FP64 network: dw", _rel(dw, g64), "dx", _rel(dx, dx64))
     assert _rel(dw, gref) <= tol
     assert _rel(dx, dxref) <= tol
     assert max(layers) <= 2 * tol, layers
@@ -108,7 +121,8 @@ def test_autograd_function_gradient_matches_oracle(ctx, dtype, tol):
     """The torch.autograd.Function around the library's forward and backward:
     loss.backward() gives the weight and input gradients of sum(G * U(X; w))
     equal to the oracle's FP64 adjoint (itself pinned by central differences
-    and torch autograd in the CPU tests), on an 8^3-cell grid."""
+    and torch autograd in the CPU tests), on an 8^3-cell grid; for BF16 the
+    oracle's network at the kernels' precision."""
     from paper_2505_08491_amd.autograd import unet
     n, batch = 9, 2
     th = _theta(21)
@@ -117,7 +131,7 @@ def test_autograd_function_gradient_matches_oracle(ctx, dtype, tol):
     Xt = dev(X.reshape(batch, -1, 2), torch.float32).requires_grad_(True)
     y = unet(w, Xt, ctx, n, dtype)
     (y * dev(G.reshape(batch, -1), torch.float32)).sum().backward()
-    gref, dxref = _oracle_grads(th, X, G)
+    gref, dxref = _oracle_grads(th, X, G, "bf16" if dtype == "bf16" else None)
     assert _rel(w.grad.cpu().double().numpy(), gref) <= tol
     assert _rel(Xt.grad.cpu().double().numpy().reshape(dxref.shape), dxref) <= tol
     # forward value equals the plain library call
@@ -171,14 +185,26 @@ def test_adam_matches_oracle(ctx):
     w0 = rng.uniform(-0.5, 0.5, nparam).astype(np.float32)
     w, m, v = dev(w0, torch.float32), torch.zeros(nparam, device="cuda"), torch.zeros(nparam, device="cuda")
     wo, mo, vo = w0.astype(np.float64), np.zeros(nparam), np.zeros(nparam)
+    f32 = lambda t: float(np.float32(t))
+    u32 = 2.0 ** -24
+    em = ev = 0.0      # error bounds of the FP32 moments, carried from step to step
     for step, lr in ((1, 1e-3), (2, 7e-4), (3, 1e-3)):
         g = (rng.normal(size=nparam) * 10.0 ** rng.uniform(-6, 0, nparam)).astype(np.float32)
         ctx.adam_step(w, dev(g, torch.float32), m, v, lr, step)
-        wo, mo, vo = ocnn.adam_step(wo, g.astype(np.float64), mo, vo, step, lr=lr)
+        # the library receives lr, beta1, beta2, eps as FP32 values: the oracle gets the same values
+        b1, b2 = f32(0.9), f32(0.999)
+        g64 = g.astype(np.float64)
+        # FP32 moments m <- b1 m + (1 - b1) g: two products and a sum, each
+        # rounded once (at most 3 u of the terms' magnitudes), plus the
+        # previous step's error scaled by b1 (the moments may cancel: a bound
+        # on the error, not on the ratio); the same for v
+        em = b1 * em + 4 * u32 * (b1 * np.abs(mo) + (1 - b1) * np.abs(g64))
+        ev = b2 * ev + 4 * u32 * (b2 * vo + (1 - b2) * g64 * g64)
+        wo, mo, vo = ocnn.adam_step(wo, g64, mo, vo, step, lr=f32(lr), b1=b1, b2=b2, eps=f32(1e-8))
         wg, mg, vg = (t.cpu().double().numpy() for t in (w, m, v))
         assert np.max(np.abs(wg - wo)) <= 1e-6, step
-        assert np.allclose(mg, mo, rtol=1e-6, atol=0), step
-        assert np.allclose(vg, vo, rtol=1e-6, atol=0), step
+        assert np.all(np.abs(mg - mo) <= em), step
+        assert np.all(np.abs(vg - vo) <= ev), step
     # the update is the oracle's: the change of w, not only w, agrees
     assert np.allclose(wg - w0, wo - w0, rtol=1e-3, atol=2e-7)
 
@@ -265,9 +291,11 @@ def test_trained_network_gain(ctx):
         else:
             w = W.load(wpath)[0] if name == "trained" else W.init(0)
             S.set_preconditioner("neural", weights=w, cnn_dtype="bf16")
-        _, st = S.solve(b, **opts)
-        assert all(q["converged"] and not q["used_fallback"] for q in st), (name, st)
+        _, st = S.solve(b, **dict(opts, max_iters=600 if name == "untrained" else 3000))
+        if name != "untrained":   # the untrained network may stall: its count is then the cap
+            assert all(q["converged"] and not q["used_fallback"] for q in st), (name, st)
         res[name] = float(np.mean([q["iters"] for q in st]))
+        print(name, "converged", sum(q["converged"] for q in st), "of", len(st), flush=True)
     print("mean FGMRES(30) iterations", res)
     assert res["trained"] < 0.5 * res["none"]
     assert res["trained"] < res["untrained"]

@@ -330,3 +330,47 @@ def test_network_gradient_matches_torch_autograd():
         assert np.allclose(dtheta[off:off + nw], g.reshape(-1).numpy(), rtol=1e-10, atol=1e-12)
         assert np.allclose(dtheta[off + nw:off + nw + nb], m.bias.grad.numpy(), rtol=1e-10, atol=1e-12)
         off += nw + nb
+
+
+def test_round_bf16_matches_torch_conversion():
+    """The oracle's bfloat16 rounding against PyTorch's own float32 -> bfloat16
+    conversion: 200k random values over many decades, every exact tie between
+    two neighbouring bfloat16 values (both parities) and signed zeros."""
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=200_000) * 10.0 ** rng.uniform(-30, 30, 200_000)
+    x = x.astype(np.float32).astype(np.float64)
+    hi = rng.integers(0, 0x7F7F, 5000, dtype=np.uint32) << 16                  # finite, below the largest
+    ties = (hi | 0x8000).view(np.float32).astype(np.float64)          # halfway between two bf16 values
+    vals = np.concatenate([x, ties, -ties, [0.0, -0.0, 1.0, 3.0e38]])
+    want = torch.from_numpy(vals.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    got = cnn.round_bf16(vals)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_bf16_emulation_rounds_where_stated():
+    """forward(emulate="bf16"): every stored activation except the head output
+    is a bfloat16 value, the network input is rounded, the result stays within
+    a few BF16 rounding steps of the FP64 network, and the adjoint of the
+    emulated network passes the same central-difference check in the weights
+    of the 1x1 head (linear there, so the check is exact up to FP64 rounding)."""
+    n = 9
+    rng = np.random.default_rng(9)
+    th = cnn.init_params(4)
+    X = np.stack([rng.normal(size=(n, n, n)), rng.uniform(0, 1, (n, n, n))], axis=-1)
+    y64, _ = cnn.forward(th, X)
+    y16, cache = cnn.forward(th, X, emulate="bf16")
+    assert np.array_equal(cache["X"], cnn.round_bf16(X))
+    for name, *_r in cnn.LAYERS[:-1]:
+        inp, z = cache[name]
+        assert np.array_equal(inp, cnn.round_bf16(inp)), name
+    rel = np.linalg.norm(y16 - y64) / np.linalg.norm(y64)
+    assert 1e-5 < rel < 5e-2, rel
+    G = rng.normal(size=(n, n, n))
+    g, _ = cnn.backward(th, cache, G)
+    off = cnn.n_params() - 17                      # head weights (16) and bias (1)
+    for j in range(17):
+        e = np.zeros_like(th)
+        e[off + j] = 1e-3
+        fp = np.sum(G * cnn.forward(th + e, X, emulate="bf16")[0])
+        fm = np.sum(G * cnn.forward(th - e, X, emulate="bf16")[0])
+        assert (fp - fm) / 2e-3 == pytest.approx(g[off + j], rel=1e-9, abs=1e-9)
