@@ -314,6 +314,21 @@ mdnp_status mdnp_loss_grad(mdnp_ctx* ctx, mdnp_sys* sys, const int32_t* d_inst, 
                            const float* d_r, const float* d_u, float* d_du, double* d_loss,
                            void* hip_stream);
 
+/* The same loss and gradient as mdnp_loss_grad without any device allocation,
+ * for callers that cannot allocate: code under HIP graph capture, training
+ * loops that must not call hipMalloc.  Its scratch (the masked outputs, C e
+ * and the partial sums: n_slots * n3d * 8 + n_slots * 512 bytes) lives in a
+ * fixed workspace of 32 MiB that the library holds on every GPU it runs on
+ * until the process ends; larger requests fail with MDNP_E_ARG and change
+ * nothing.  Results are bit-identical to mdnp_loss_grad's.  All calls on one
+ * GPU share that workspace: calls that overlap in time on one GPU (other
+ * streams, other contexts, other threads) race and must be serialised by the
+ * caller.  No part of the workspace needs clearing between calls.  Errors:
+ * MDNP_E_ARG, MDNP_E_STATE (workspace address not resolved), MDNP_E_HIP. */
+mdnp_status mdnp_loss_grad_noalloc(mdnp_ctx* ctx, mdnp_sys* sys, const int32_t* d_inst, int32_t n_slots,
+                                   const float* d_r, const float* d_u, float* d_du, double* d_loss,
+                                   void* hip_stream);
+
 /* Network input for training slots: X[k] = [r_k, d_{inst[k]}] as
  * [n_slots][n][n][n][2] FP32. */
 mdnp_status mdnp_pack_input(mdnp_ctx* ctx, mdnp_sys* sys, const int32_t* d_inst, int32_t n_slots,

@@ -70,6 +70,7 @@ SIGNATURES = [
     ("mdnp_cnn_saved_bytes", C.c_int64, [C.c_int32, C.c_int32, C.c_int]),
     ("mdnp_cnn_backward", C.c_int, [VP, VP, VP, VP, VP, VP, C.c_int32, C.c_int32, C.c_int, VP]),
     ("mdnp_loss_grad", C.c_int, [VP, VP, VP, C.c_int32, VP, VP, VP, VP, VP]),
+    ("mdnp_loss_grad_noalloc", C.c_int, [VP, VP, VP, C.c_int32, VP, VP, VP, VP, VP]),
     ("mdnp_pack_input", C.c_int, [VP, VP, VP, C.c_int32, VP, VP, VP]),
     ("mdnp_adam_step", C.c_int, [VP, VP, VP, VP, VP, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
                                  C.c_int32, VP]),

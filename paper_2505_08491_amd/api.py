@@ -339,6 +339,13 @@ class System:
                      _ptr(loss), _stream(self.ctx.stream))
         return loss, du
 
+    def loss_grad_noalloc(self, inst: torch.Tensor, r: torch.Tensor, u: torch.Tensor, du: torch.Tensor,
+                          loss: torch.Tensor):
+        """`loss_grad` into caller-owned du and loss, with the library's fixed
+        workspace (no device allocation in the library)."""
+        self.ctx.run(lib.mdnp_loss_grad_noalloc, self.ctx.h, self.h, _ptr(inst), inst.numel(), _ptr(r), _ptr(u),
+                     _ptr(du), _ptr(loss), _stream(self.ctx.stream))
+
     def pack_input(self, inst: torch.Tensor, r: torch.Tensor) -> torch.Tensor:
         x = torch.empty(inst.numel(), self.n3d, 2, device=r.device, dtype=torch.float32)
         self.ctx.run(lib.mdnp_pack_input, self.ctx.h, self.h, _ptr(inst), inst.numel(), _ptr(r), _ptr(x),

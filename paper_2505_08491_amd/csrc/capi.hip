@@ -202,6 +202,8 @@ extern "C" mdnp_status mdnp_create(mdnp_ctx** out, int hip_device, void* hip_str
     if (hip_device < 0 || hip_device >= ndev) fail(MDNP_E_ARG, "no such HIP device");
     HIPCHK(hipSetDevice(hip_device));
     ctx->device = hip_device;
+    if (!loss_scratch_resolve(hip_device, &ctx->loss_scratch))
+      fail(MDNP_E_HIP, "could not resolve the device address of the fixed loss workspace");
     if (hip_stream) {
       ctx->stream = (hipStream_t)hip_stream;
     } else {
@@ -1297,6 +1299,23 @@ extern "C" mdnp_status mdnp_loss_grad(mdnp_ctx* ctx, mdnp_sys* s, const int32_t*
     HIPCHK(hipSetDevice(ctx->device));
     launch_loss_grad(s, d_inst, n_slots, d_r, d_u, d_du, d_loss, pick(ctx, hip_stream));
     if (!s->cnn.loss) fail(MDNP_E_OOM, "loss scratch allocation failed");
+    HIPCHK(hipGetLastError());
+  });
+}
+
+extern "C" mdnp_status mdnp_loss_grad_noalloc(mdnp_ctx* ctx, mdnp_sys* s, const int32_t* d_inst, int32_t n_slots,
+                                              const float* d_r, const float* d_u, float* d_du, double* d_loss,
+                                              void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !d_inst || !d_r || !d_u || !d_du || !d_loss || n_slots < 1) fail(MDNP_E_ARG, "bad argument");
+    const size_t need = loss_grad_scratch_bytes(s->n3d, n_slots);
+    if (need > kLossScratchBytes)
+      fail(MDNP_E_ARG, "n_slots x n3d too large for the fixed workspace: needs " + std::to_string(need) +
+                           " bytes, the maximum is " + std::to_string(kLossScratchBytes));
+    if (!ctx->loss_scratch) fail(MDNP_E_STATE, "fixed loss workspace not resolved");
+    HIPCHK(hipSetDevice(ctx->device));
+    launch_loss_grad_fixed(s, d_inst, n_slots, d_r, d_u, d_du, d_loss, ctx->loss_scratch, pick(ctx, hip_stream));
     HIPCHK(hipGetLastError());
   });
 }

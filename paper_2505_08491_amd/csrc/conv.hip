@@ -8,6 +8,7 @@
 // every network, for the backward pass, the loss and Adam.  The matrix-core
 // kernels of the BF16 network live in conv_mfma.hip.
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "conv_common.hpp"
@@ -970,19 +971,22 @@ void cnn_backward_batch(CnnState& c, const void* saved, const float* dy, float* 
   else backward_t<float>(c, saved, dy, dx, dw, batch, n, dtype, stream);
 }
 
-void launch_loss_grad(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u, float* du,
-                      double* loss, hipStream_t stream) {
+namespace {
+constexpr int kLossParts = 64;  // partial sums per slot of the loss reduction
+}
+
+size_t loss_grad_scratch_bytes(int64_t n3d, int n_slots) {
+  return (size_t)n_slots * n3d * 2 * sizeof(float) + (size_t)n_slots * kLossParts * sizeof(double);
+}
+
+// The loss and its gradient with the scratch at `buf` (loss_grad_scratch_bytes
+// of it): the masked output and C e per slot, then the partial sums.  Every
+// scratch word is written before it is read.
+static void loss_grad_core(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u,
+                           float* du, double* loss, void* scratch_buf, hipStream_t stream) {
   const int64_t n3d = s->n3d;
-  const int nbx = 64;
-  const size_t need = (size_t)n_slots * n3d * 2 * sizeof(float) + (size_t)n_slots * nbx * sizeof(double);
-  CnnState& c = s->cnn;
-  if (c.loss_bytes < need) {
-    if (c.loss) hipFree(c.loss);
-    c.loss = nullptr;
-    if (hipMalloc(&c.loss, need) != hipSuccess) { c.loss = nullptr; c.loss_bytes = 0; return; }
-    c.loss_bytes = need;
-  }
-  float* buf = (float*)c.loss;
+  const int nbx = kLossParts;
+  float* buf = (float*)scratch_buf;
   float* um = buf;
   float* ce = buf + (size_t)n_slots * n3d;
   double* part = (double*)(buf + (size_t)n_slots * n3d * 2);
@@ -993,6 +997,51 @@ void launch_loss_grad(mdnp_sys* s, const int32_t* inst, int n_slots, const float
   hipLaunchKernelGGL(k_loss_sum, dim3((n_slots + 63) / 64), dim3(64), 0, stream, part, nbx, n_slots, loss);
   launch_spmv_a00_slots(s, inst, n_slots, ce, um, stream);
   hipLaunchKernelGGL(k_loss_grad_fin, g2, dim3(BS), 0, stream, um, du, inst, s->d_alpha, s->n, n3d);
+}
+
+void launch_loss_grad(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u, float* du,
+                      double* loss, hipStream_t stream) {
+  const size_t need = loss_grad_scratch_bytes(s->n3d, n_slots);
+  CnnState& c = s->cnn;
+  if (c.loss_bytes < need) {
+    if (c.loss) hipFree(c.loss);
+    c.loss = nullptr;
+    if (hipMalloc(&c.loss, need) != hipSuccess) { c.loss = nullptr; c.loss_bytes = 0; return; }
+    c.loss_bytes = need;
+  }
+  loss_grad_core(s, inst, n_slots, r, u, du, loss, c.loss, stream);
+}
+
+// ---------------------------------------------------------------- allocation-free loss
+
+// Fixed workspace of mdnp_loss_grad_noalloc, one copy per GPU the library runs
+// on, held until the process ends.  Host code never passes `scratch` itself to
+// a kernel (on the host it names a stand-in, not device memory): it uses the
+// per-device address resolved once by loss_scratch_resolve.
+static __device__ __align__(256) unsigned char scratch[kLossScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+bool loss_scratch_resolve(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return false;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return false;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return true;
+}
+
+void launch_loss_grad_fixed(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u,
+                            float* du, double* loss, void* scratch_ptr, hipStream_t stream) {
+  loss_grad_core(s, inst, n_slots, r, u, du, loss, scratch_ptr, stream);
 }
 
 void launch_pack_input(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, float* x,

@@ -142,6 +142,7 @@ struct mdnp_ctx {
   std::string err;
   std::vector<mdnp_sys*> systems;
   mdnp::CnnState cnn;              // state of the stand-alone network calls
+  void* loss_scratch = nullptr;    // this device's fixed loss workspace (mdnp_loss_grad_noalloc)
 };
 
 struct mdnp_sys {

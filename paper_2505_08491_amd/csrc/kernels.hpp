@@ -123,6 +123,15 @@ bool spmv_autotune(mdnp_sys* s, hipStream_t stream);
 void cnn_release(CnnState& c);
 void launch_loss_grad(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u,
                       float* du, double* loss, hipStream_t stream);
+// Bytes of scratch one loss/gradient evaluation needs.
+size_t loss_grad_scratch_bytes(int64_t n3d, int n_slots);
+// The allocation-free variant's fixed per-device workspace: its size, the
+// one-time resolution of its device address on `device` (which must be
+// current), and the launch with that address.
+constexpr size_t kLossScratchBytes = size_t(32) << 20;
+bool loss_scratch_resolve(int device, void** out);
+void launch_loss_grad_fixed(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u,
+                            float* du, double* loss, void* scratch_ptr, hipStream_t stream);
 void launch_pack_input(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, float* x,
                        hipStream_t stream);
 void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
