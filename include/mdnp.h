@@ -217,8 +217,9 @@ mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* sys, int32_t* chosen);
 
 /* Time the network as the solver applies it (Section 4.2 U-net inside the
  * 3D block of eq. "twosteps"), stage by stage, on this system's batch and
- * grid with the launch shapes currently chosen: `reps` applications to a
- * fixed vector, HIP events on the context's stream between the stages.
+ * grid with the launch shapes currently chosen: after one application to a
+ * fixed vector, each stage is launched `reps` times back to back on its own
+ * inputs between two HIP events on the context's stream.
  * ms (host, [10]) receives the average duration in milliseconds of L0a, L0b,
  * L1a, L1b, L2a, L2b, U1, D1, U0 and D0 (which includes the 1x1 head and the
  * unscaling).  Allocates two vectors of the system's size for the duration of

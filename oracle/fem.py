@@ -14,7 +14,12 @@ Readings taken where the paper leaves a choice (listed in the design notes):
   * 3D space: trilinear (Q1) elements on a uniform grid of N^3 cells of the
     unit cube (the paper allows "tetrahedrons or bricks" on a uniform mesh);
     homogeneous Dirichlet conditions by symmetric elimination, boundary rows
-    and columns replaced by the identity, boundary nodes kept as unknowns.
+    and columns replaced by the identity, boundary nodes kept as unknowns;
+    or (instance boundary "neumann", the setup of the paper's Section 5) the
+    natural condition: every node free, nothing eliminated.
+  * The 3D-block problem of Section 5 (instance problem "block3d"): C = A00
+    alone with b = -A01 A11^-1 f_1 (eq. "matrixC", eq. "setB"), written as
+    [C 0; 0 I] [u0; u1] = [b; 0] so that it shares the coupled layout.
   * 1D diffusion carries the cross-section area: k_Lambda * pi R^2 (weak form
     a_Lambda with the |D| weight).
   * One perimeter factor in the coupling: c = 2 pi R beta, i.e. the block
@@ -33,6 +38,7 @@ from typing import Optional
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 GAUSS2 = (0.5 - 0.5 / math.sqrt(3.0), 0.5 + 0.5 / math.sqrt(3.0))
 
@@ -162,7 +168,7 @@ class System:
     n_cells: int
     n3d: int
     n1d: int
-    A: sp.csr_matrix          # full block matrix after Dirichlet elimination
+    A: sp.csr_matrix          # full block matrix after Dirichlet elimination (if Dirichlet)
     F: np.ndarray             # right-hand side [0; f_1]
     boundary: np.ndarray      # bool [n3d]
     dist: Optional[np.ndarray]  # distance field d_h at the 3D nodes (None if not tabulated)
@@ -315,15 +321,19 @@ def assemble(inst, with_distance: bool = True) -> System:
     cols = np.concatenate([c3, n3d + c11] + cc)
     vals = np.concatenate([v3, v11] + vc)
 
-    # symmetric Dirichlet elimination on the 3D boundary
-    bnd = boundary_mask(N)
-    isb = np.zeros(n3d + n1d, dtype=bool)
-    isb[:n3d] = bnd
-    keep = ~(isb[rows] | isb[cols])
-    bidx = np.nonzero(bnd)[0]
-    rows = np.concatenate([rows[keep], bidx])
-    cols = np.concatenate([cols[keep], bidx])
-    vals = np.concatenate([vals[keep], np.ones(bidx.size)])
+    # symmetric Dirichlet elimination on the 3D boundary; with the natural
+    # (Neumann) condition every 3D node stays free and nothing is removed
+    if getattr(inst, "boundary", "dirichlet") == "neumann":
+        bnd = np.zeros(n3d, dtype=bool)
+    else:
+        bnd = boundary_mask(N)
+        isb = np.zeros(n3d + n1d, dtype=bool)
+        isb[:n3d] = bnd
+        keep = ~(isb[rows] | isb[cols])
+        bidx = np.nonzero(bnd)[0]
+        rows = np.concatenate([rows[keep], bidx])
+        cols = np.concatenate([cols[keep], bidx])
+        vals = np.concatenate([vals[keep], np.ones(bidx.size)])
     A = sp.coo_matrix((vals, (rows, cols)), shape=(n3d + n1d, n3d + n1d)).tocsr()
     A.sum_duplicates()
     A.sort_indices()
@@ -334,7 +344,40 @@ def assemble(inst, with_distance: bool = True) -> System:
     dist = distance_field(N, inst.vertex_xyz, inst.seg) if with_distance else None
     dg = A.diagonal()[:n3d][~bnd]
     alpha = float(np.sqrt(np.mean(dg ** 2)))
-    return System(n_cells=N, n3d=n3d, n1d=n1d, A=A, F=F, boundary=bnd, dist=dist, alpha=alpha,
-                  Pi=Pi, Phi=Phi, W=W, K11=K11, gauss_xyz=gauss_xyz,
-                  extra={"pos1d": pos1d, "elems": elems, "eseg": eseg, "gauss_tau": gauss_tau,
-                         "gauss_R": gauss_R})
+    out = System(n_cells=N, n3d=n3d, n1d=n1d, A=A, F=F, boundary=bnd, dist=dist, alpha=alpha,
+                 Pi=Pi, Phi=Phi, W=W, K11=K11, gauss_xyz=gauss_xyz,
+                 extra={"pos1d": pos1d, "elems": elems, "eseg": eseg, "gauss_tau": gauss_tau,
+                        "gauss_R": gauss_R})
+    if getattr(inst, "problem", "coupled") == "block3d":
+        return block3d_system(out)
+    return out
+
+
+def block3d_rhs(system):
+    """Right-hand side of the 3D block problem (eq. "decoupled_3d_problem" with
+    z = F, eq. "setB"): b = -A01 x with A11 x = f_1, i.e. the 3D forcing that the
+    1D solution exerts through the coupling (A01 = 2 pi eps M01, A11 = K11 +
+    2 pi eps M11)."""
+    A00, A01, A10, A11 = system.blocks()
+    x1 = spla.spsolve(A11.tocsc(), system.F[system.n3d:])
+    return -(A01 @ x1)
+
+
+def block3d_system(system):
+    """The 3D block C = K00 + 2 pi eps M00 alone (eq. "matrixC"), written in
+    the coupled layout as [C 0; 0 I] [u0; u1] = [b; 0] with b from
+    `block3d_rhs`: the 1D unknowns are decoupled identities whose part of every
+    Krylov vector stays zero, so any solver of the coupled layout solves
+    C u0 = b.  The coupling operators Pi, Phi, W describe the tree as before."""
+    m = system.n3d
+    A00 = system.blocks()[0]
+    b = block3d_rhs(system)
+    A = sp.bmat([[A00, None], [None, sp.identity(system.n1d, format="csr")]], format="csr")
+    A.sort_indices()
+    F = np.concatenate([b, np.zeros(system.n1d)])
+    extra = dict(system.extra)
+    extra["coupled_A"] = system.A
+    extra["coupled_F"] = system.F
+    return System(n_cells=system.n_cells, n3d=m, n1d=system.n1d, A=A, F=F, boundary=system.boundary,
+                  dist=system.dist, alpha=system.alpha, Pi=system.Pi, Phi=system.Phi, W=system.W,
+                  K11=system.K11, gauss_xyz=system.gauss_xyz, extra=extra)

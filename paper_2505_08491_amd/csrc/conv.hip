@@ -523,7 +523,7 @@ static void conv_layer(const ConvP& p, int kind, int batch, mdnp_dtype dtype, in
 // Layers 1..9 (L0b .. D0) on activations of type T, given the buffer set.
 template <typename T>
 static void unet_middle(CnnState& c, const float* d_w, void* const* act, int batch, int n, mdnp_dtype dtype,
-                        const InstState* st, hipStream_t stream, int last_layer = 9, hipEvent_t* marks = nullptr) {
+                        const InstState* st, hipStream_t stream, int last_layer = 9, int first_layer = 1) {
   const int n1 = (n + 1) / 2, n2 = (n1 + 1) / 2;
   const int nn[3] = {n, n1, n2};
   // act indices: 1 a0, 2 s0, 3 a1, 4 s1, 5 a2, 6 b2, 7 u1, 8 d1, 9 u0, 10 d0
@@ -533,6 +533,7 @@ static void unet_middle(CnnState& c, const float* d_w, void* const* act, int bat
                         {9, 9, 2, 10, 0, 0}};
   for (const Step& s : steps) {
     if (s.layer > last_layer) break;
+    if (s.layer < first_layer) continue;
     const LayerSpec& L = kLayers[s.layer];
     ConvP p{};
     const int ca = s.src_b >= 0 ? L.cin / 2 : L.cin;
@@ -558,7 +559,6 @@ static void unet_middle(CnnState& c, const float* d_w, void* const* act, int bat
     p.st = st;
     p.want_mode = 0;
     conv_layer<T, T>(p, L.kind, batch, dtype, s.layer, c, stream);
-    if (marks) (void)hipEventRecord(marks[s.layer], stream);
   }
 }
 
@@ -668,7 +668,7 @@ void cnn_forward_batch(CnnState& c, const float* in, float* out, void* saved, in
 
 template <typename Tv>
 void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, const InstState* st, hipStream_t stream,
-                         const double* scales, hipEvent_t* marks) {
+                         const double* scales, int only_stage) {
   CnnState& c = s->cnn;
   const double* isc = scales ? scales : c.inv_s;
   const int n = s->n, batch = s->n_inst;
@@ -678,40 +678,42 @@ void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, const InstState* st,
   void* act[12];
   for (int k = 0; k < 12; ++k) act[k] = (char*)c.act[0] + offs[k];
   const dim3 grid((unsigned)((cube(n) + BS - 1) / BS), 1, batch);
-  if (marks) (void)hipEventRecord(marks[0], stream);
-  hipEvent_t* after = marks ? marks + 1 : nullptr;  // after[l]: end of layer l
+  const bool all = only_stage < 0;
+  const int mid_lo = all ? 1 : only_stage, mid_hi = all ? 9 : only_stage;
   if (c.dtype == MDNP_BF16) {
     // first layer reads the Krylov vector directly; D0, ReLU, the 1x1 head and the
     // unscaling are one kernel writing z0
-    conv_mfma_in0<Tv>(c, zin, s->d_off, isc, s->d_dist, n, batch, (bf16*)act[1], st, stream);
-    if (after) (void)hipEventRecord(after[0], stream);
-    unet_middle<bf16>(c, c.w, act, batch, n, c.dtype, st, stream, 8, after);
-    conv_mfma_d0_head<Tv>(c, (const bf16*)act[9], (const bf16*)act[2], n, batch, z, s->d_off, s->d_alpha,
-                          s->alpha_override, isc + s->n_inst, st, stream);
+    if (all || only_stage == 0)
+      conv_mfma_in0<Tv>(c, zin, s->d_off, isc, s->d_dist, n, batch, (bf16*)act[1], st, stream);
+    unet_middle<bf16>(c, c.w, act, batch, n, c.dtype, st, stream, std::min(mid_hi, 8), mid_lo);
+    if (all || only_stage == 9)
+      conv_mfma_d0_head<Tv>(c, (const bf16*)act[9], (const bf16*)act[2], n, batch, z, s->d_off, s->d_alpha,
+                            s->alpha_override, isc + s->n_inst, st, stream);
   } else {
-    hipLaunchKernelGGL((k_conv_in0<Tv, float>), grid, dim3(BS), 0, stream, zin, s->d_off, isc, s->d_dist,
-                       c.wt + c.wt_off[0], c.w + c.b_off[0], n, (float*)act[1], st);
-    if (after) (void)hipEventRecord(after[0], stream);
-    unet_middle<float>(c, c.w, act, batch, n, c.dtype, st, stream, 9, after);
-    hipLaunchKernelGGL((k_head_out<Tv, float>), grid, dim3(BS), 0, stream, (const float*)act[10],
-                       c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override, isc + s->n_inst, st);
+    if (all || only_stage == 0)
+      hipLaunchKernelGGL((k_conv_in0<Tv, float>), grid, dim3(BS), 0, stream, zin, s->d_off, isc, s->d_dist,
+                         c.wt + c.wt_off[0], c.w + c.b_off[0], n, (float*)act[1], st);
+    unet_middle<float>(c, c.w, act, batch, n, c.dtype, st, stream, mid_hi, mid_lo);
+    if (all || only_stage == 9)
+      hipLaunchKernelGGL((k_head_out<Tv, float>), grid, dim3(BS), 0, stream, (const float*)act[10],
+                         c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override,
+                         isc + s->n_inst, st);
   }
-  if (after) (void)hipEventRecord(after[9], stream);
 }
 template void cnn_apply_in_solver<float>(mdnp_sys*, const float*, float*, const InstState*, hipStream_t,
-                                         const double*, hipEvent_t*);
+                                         const double*, int);
 template void cnn_apply_in_solver<double>(mdnp_sys*, const double*, double*, const InstState*, hipStream_t,
-                                          const double*, hipEvent_t*);
+                                          const double*, int);
 
 template <typename Tv>
 static bool layer_times_t(mdnp_sys* s, hipStream_t stream, int reps, float* ms) {
   Tv* tmp = nullptr;  // [2][ntot]: fixed input, output
   double* ones = nullptr;
-  hipEvent_t ev[11] = {};
+  hipEvent_t ev[2] = {};
   const size_t nt = (size_t)s->ntot;
   bool ok = hipMalloc(&tmp, sizeof(Tv) * 2 * nt) == hipSuccess &&
             hipMalloc(&ones, sizeof(double) * 2 * s->n_inst) == hipSuccess;
-  for (int k = 0; k < 11 && ok; ++k) ok = hipEventCreate(&ev[k]) == hipSuccess;
+  for (int k = 0; k < 2 && ok; ++k) ok = hipEventCreate(&ev[k]) == hipSuccess;
   if (ok) {
     std::vector<Tv> h(nt, (Tv)1e-3);
     std::vector<double> o(2 * (size_t)s->n_inst, 1.0);
@@ -720,19 +722,20 @@ static bool layer_times_t(mdnp_sys* s, hipStream_t stream, int reps, float* ms) 
          hipStreamSynchronize(stream) == hipSuccess;
   }
   if (ok) {
-    for (int l = 0; l < 10; ++l) ms[l] = 0.f;
-    cnn_apply_in_solver<Tv>(s, tmp, tmp + nt, nullptr, stream, ones);  // warm-up
-    for (int r = 0; r < reps && ok; ++r) {
-      cnn_apply_in_solver<Tv>(s, tmp, tmp + nt, nullptr, stream, ones, ev);
-      ok = hipEventSynchronize(ev[10]) == hipSuccess;
-      for (int l = 0; l < 10 && ok; ++l) {
-        float t = 0.f;
-        ok = hipEventElapsedTime(&t, ev[l], ev[l + 1]) == hipSuccess;
-        ms[l] += t / (float)reps;
-      }
+    // one whole application puts every stage's inputs in place; then each
+    // stage alone, `reps` launches back to back between two events
+    cnn_apply_in_solver<Tv>(s, tmp, tmp + nt, nullptr, stream, ones);
+    for (int l = 0; l < 10 && ok; ++l) {
+      cnn_apply_in_solver<Tv>(s, tmp, tmp + nt, nullptr, stream, ones, l);  // warm-up of this stage
+      ok = hipEventRecord(ev[0], stream) == hipSuccess;
+      for (int r = 0; r < reps && ok; ++r) cnn_apply_in_solver<Tv>(s, tmp, tmp + nt, nullptr, stream, ones, l);
+      float t = 0.f;
+      ok = ok && hipEventRecord(ev[1], stream) == hipSuccess && hipEventSynchronize(ev[1]) == hipSuccess &&
+           hipEventElapsedTime(&t, ev[0], ev[1]) == hipSuccess;
+      ms[l] = t / (float)reps;
     }
   }
-  for (int k = 0; k < 11; ++k)
+  for (int k = 0; k < 2; ++k)
     if (ev[k]) (void)hipEventDestroy(ev[k]);
   if (tmp) (void)hipFree(tmp);
   if (ones) (void)hipFree(ones);

@@ -101,14 +101,16 @@ void cnn_backward_batch(CnnState& c, const void* saved, const float* dy, float* 
 // zin0 * inv_s and the distance field, writes z0 = s / alpha * U on the free
 // nodes of z (zin and z may be the same vector).  scales = [inv_s; s] per
 // instance (null: the context's, set by launch_inv_scale).
-// marks (nullable, 11 events): recorded before the first layer and after each
-// of L0a, L0b, L1a, L1b, L2a, L2b, U1, D1, U0 and D0 (with the head).
+// only_stage in [0, 10): launch only that stage of L0a, L0b, L1a, L1b, L2a,
+// L2b, U1, D1, U0, D0 (with the head), reading the activations a previous
+// whole application left (for timing); -1: the whole network.
 template <typename T>
 void cnn_apply_in_solver(mdnp_sys* s, const T* zin, T* z, const InstState* st, hipStream_t stream,
-                         const double* scales = nullptr, hipEvent_t* marks = nullptr);
-// Average duration (ms) of each of those ten stages over `reps` in-solver
-// applications to a fixed vector (HIP events on `stream`); false if its
-// buffers or events could not be created.
+                         const double* scales = nullptr, int only_stage = -1);
+// Average duration (ms) of each of those ten stages: `reps` launches of the
+// stage back to back between two HIP events on `stream`, after one whole
+// application to a fixed vector; false if its buffers or events could not
+// be created.
 bool cnn_layer_times(mdnp_sys* s, hipStream_t stream, int reps, float* ms);
 // Per-layer z split of the BF16 sweep convolutions chosen by timing on the
 // system's batch and grid (CnnState::sweep_blocks); false if its timing

@@ -88,6 +88,8 @@ class Instance:
     n_circle: int = 16
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    boundary: str = "dirichlet"    # cube faces: "dirichlet" (u = 0) or "neumann" (natural)
+    problem: str = "coupled"       # "coupled" system, or "block3d": the 3D block alone
 
     @property
     def n_segments(self) -> int:
@@ -185,6 +187,27 @@ def workload_transfer(n_cells: int = 64, count: int | None = None):
         base, cnt = 3_000_000, 2 if count is None else count
     return [make_instance(base + i, n_cells, n_segments=512, elems_per_segment=16,
                           radius=0.002, beta=1.0) for i in range(cnt)]
+
+
+def workload_block3d(n_cells: int = 20, count: int = 16, base: int = 4_000_000):
+    """The 3D-block problem of the paper's Section 5 setup: unit cube with
+    natural (Neumann) boundary, k_Omega = sigma_Omega = 1e-3, vessel radius
+    eps = 1e-3 (beta = 1), trees of 2-96 segments (O(1) to O(10^2) branches),
+    P1 elements of about the grid spacing (n_cells / 5 per segment); grids of
+    21^3, 41^3, 81^3 nodes for n_cells = 20, 40, 80."""
+    E = max(2, n_cells // 5)
+    return [make_instance(base + 1000 * n_cells + i, n_cells, seg_range=(2, 96), elems_per_segment=E,
+                          radius=1e-3, beta=1.0, k_omega=1e-3, sigma_omega=1e-3, boundary="neumann",
+                          problem="block3d") for i in range(count)]
+
+
+def workload_training_block3d(count: int, n_cells: int = 20, base: int = 30_000):
+    """Training graphs of the 3D-block problem (disjoint seeds from the test
+    graphs of `workload_block3d`)."""
+    E = max(2, n_cells // 5)
+    return [make_instance(base + k, n_cells, seg_range=(2, 96), elems_per_segment=E, radius=1e-3, beta=1.0,
+                          k_omega=1e-3, sigma_omega=1e-3, boundary="neumann", problem="block3d")
+            for k in range(count)]
 
 
 def workload_training(count: int, n_cells: int = 32, base: int = 10_000):

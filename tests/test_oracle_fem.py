@@ -406,3 +406,128 @@ def test_alpha_with_coupling_brute_force():
     assert s.alpha > (1 + 1e-4) * h * 8.0 / 3.0
     # and the assembled diagonal itself agrees node by node
     assert np.allclose(s.A.diagonal()[:s.n3d][free], d[free], rtol=1e-13)
+
+
+# ---------------------------------------------------------------- natural (Neumann) boundary and the 3D block (Section 5)
+
+def _neumann(n_cells=6, **kw):
+    kw.setdefault("seed", 7)
+    return small_instance(n_cells=n_cells, boundary="neumann", **kw)
+
+
+def test_neumann_stiffness_kernel_and_symmetry():
+    """With the natural boundary every node is free; the stiffness annihilates
+    constants on every row (also the boundary rows), is symmetric and
+    positive semi-definite with exactly one zero eigenvalue."""
+    s = fem.assemble(_neumann(beta=0.0, sigma_omega=0.0))
+    assert not s.boundary.any()
+    A00 = s.blocks()[0]
+    assert np.max(np.abs(A00 @ np.ones(s.n3d))) < 1e-14
+    assert abs(A00 - A00.T).max() < 1e-15
+    ev = np.linalg.eigvalsh(A00.toarray())
+    assert abs(ev[0]) < 1e-12 and ev[1] > 1e-3
+
+
+def test_neumann_mass_integrates_volume_and_node_counts():
+    """k = 0, sigma = 1: 1^T M 1 = 1 (the unit cube's volume) and every row sum
+    is the volume of the node's support (h^3 times 1, 1/2, 1/4, 1/8 for
+    interior, face, edge and corner nodes); the stiffness diagonal scales with
+    the same counts: k h 8/3 x (cells around the node) / 8."""
+    N = 6
+    h = 1.0 / N
+    s = fem.assemble(_neumann(n_cells=N, beta=0.0, k_omega=0.0, sigma_omega=1.0))
+    M = s.blocks()[0]
+    assert float(np.ones(s.n3d) @ (M @ np.ones(s.n3d))) == pytest.approx(1.0, rel=1e-13)
+    X = np.rint(fem.grid_node_xyz(N) * N).astype(int)
+    on_face = ((X == 0) | (X == N)).sum(axis=1)          # 0 interior, 1 face, 2 edge, 3 corner
+    cells = 8 / 2 ** on_face
+    assert np.allclose(M @ np.ones(s.n3d), cells / 8 * h ** 3, rtol=1e-13)
+    K = fem.assemble(_neumann(n_cells=N, beta=0.0, k_omega=1.0, sigma_omega=0.0)).blocks()[0]
+    assert np.allclose(K.diagonal(), h * 8 / 3 * cells / 8, rtol=1e-13)
+
+
+def test_neumann_coupled_system_spd():
+    """With sigma > 0 the Neumann 3D block, the coupled matrix and C = A00 are
+    SPD (dense Cholesky), at the paper's coefficients k = sigma = 1e-3."""
+    s = fem.assemble(_neumann(n_cells=6, radius=1e-3, k_omega=1e-3, sigma_omega=1e-3))
+    assert abs(s.A - s.A.T).max() < 1e-18
+    sla.cholesky(s.A.toarray())
+    sla.cholesky(s.blocks()[0].toarray())
+
+
+def _neumann_manufactured_errors(N):
+    """-k Lap u + sigma u = f in the unit cube with du/dn = 0 on its faces:
+    u = cos(pi x) cos(pi y) cos(pi z), f = (3 pi^2 k + sigma) u, k = sigma = 1;
+    no coupling (beta = 0).  Returns the H1-seminorm and L2 errors of the
+    Galerkin solution of A00 u = int f phi."""
+    s = fem.assemble(_neumann(n_cells=N, seed=11, beta=0.0, k_omega=1.0, sigma_omega=1.0))
+    h = 1.0 / N
+    c = lambda t: np.cos(np.pi * t)
+    sn = lambda t: np.sin(np.pi * t)
+    uex = lambda P: c(P[..., 0]) * c(P[..., 1]) * c(P[..., 2])
+    p, w = _gauss3()
+    ids = fem.cell_node_ids(N)
+    cz, cy, cx = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    org = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1) * h
+    F0 = np.zeros(s.n3d)
+    for a in range(3):
+        for b in range(3):
+            for cc in range(3):
+                xi = np.array([p[a], p[b], p[cc]])
+                phi = fem.trilinear_values(xi[None, :])[0]
+                val = (3 * np.pi ** 2 + 1.0) * uex(org + h * xi) * w[a] * w[b] * w[cc] * h ** 3
+                for l in range(8):
+                    np.add.at(F0, ids[:, l], val * phi[l])
+    U = spla.spsolve(s.blocks()[0].tocsc(), F0)[ids]
+    corners = [(l & 1, (l >> 1) & 1, (l >> 2) & 1) for l in range(8)]
+    eh1 = el2 = 0.0
+    for a in range(3):
+        for b in range(3):
+            for cc in range(3):
+                xi = np.array([p[a], p[b], p[cc]])
+                wt = w[a] * w[b] * w[cc] * h ** 3
+                phi = fem.trilinear_values(xi[None, :])[0]
+                grad = np.zeros((8, 3))
+                for l, co in enumerate(corners):
+                    f = [xi[d] if co[d] else 1 - xi[d] for d in range(3)]
+                    df = [1.0 if co[d] else -1.0 for d in range(3)]
+                    grad[l] = [df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]]
+                P = org + h * xi
+                gx = -np.pi * sn(P[:, 0]) * c(P[:, 1]) * c(P[:, 2])
+                gy = -np.pi * c(P[:, 0]) * sn(P[:, 1]) * c(P[:, 2])
+                gz = -np.pi * c(P[:, 0]) * c(P[:, 1]) * sn(P[:, 2])
+                gh = U @ grad / h
+                eh1 += wt * np.sum((gx - gh[:, 0]) ** 2 + (gy - gh[:, 1]) ** 2 + (gz - gh[:, 2]) ** 2)
+                el2 += wt * np.sum((uex(P) - U @ phi) ** 2)
+    return math.sqrt(eh1), math.sqrt(el2)
+
+
+def test_neumann_manufactured_solution_convergence():
+    """Natural boundary: H1-seminorm error O(h) (slope >= 0.9), L2 O(h^2) (>= 1.7)."""
+    errs = [_neumann_manufactured_errors(N) for N in (8, 16, 32)]
+    s1 = [math.log2(errs[i][0] / errs[i + 1][0]) for i in range(2)]
+    s2 = [math.log2(errs[i][1] / errs[i + 1][1]) for i in range(2)]
+    assert min(s1) >= 0.9, (errs, s1)
+    assert min(s2) >= 1.7, (errs, s2)
+
+
+def test_block3d_rhs_is_the_back_substitution_of_twosteps():
+    """b = -A01 A11^-1 f1: solving the block upper-triangular system
+    [C A01; 0 A11] [u0; u1] = [0; f1] (eq. "twosteps") by a generic sparse LU
+    gives u0 = C^-1 b; and the block-3D layout is [C 0; 0 I] with F = [b; 0]."""
+    inst = _neumann(n_cells=8, radius=5e-3, k_omega=1e-3, sigma_omega=1e-3)
+    s = fem.assemble(inst)
+    A00, A01, A10, A11 = s.blocks()
+    U = sp.bmat([[A00, A01], [None, A11]], format="csc")
+    u = spla.spsolve(U, s.F)
+    b = fem.block3d_rhs(s)
+    assert np.linalg.norm(b) > 0
+    u0 = spla.spsolve(A00.tocsc(), b)
+    assert np.allclose(u[:s.n3d], u0, rtol=1e-10, atol=1e-12 * np.max(np.abs(u0)))
+    inst.problem = "block3d"
+    t = fem.assemble(inst)
+    assert (abs(t.A[:t.n3d, :t.n3d] - A00)).max() == 0.0
+    assert t.A[:t.n3d, t.n3d:].nnz == 0 and t.A[t.n3d:, :t.n3d].nnz == 0
+    assert (abs(t.A[t.n3d:, t.n3d:] - sp.identity(t.n1d))).max() == 0.0
+    assert np.array_equal(t.F[:t.n3d], b) and not np.any(t.F[t.n3d:])
+    assert t.alpha == s.alpha

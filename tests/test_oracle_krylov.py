@@ -338,3 +338,24 @@ def test_reference_pool_reports_errors():
         assert good["rel_res"] <= 1e-12 and good["err"] <= 1e-10 and good["err_max"] <= 1e-10
         assert off["err_max"] == pytest.approx(1e-3, rel=1e-6)
         assert off["err"] == pytest.approx(1e-3 * np.max(np.abs(x)) / np.linalg.norm(x), rel=1e-6)
+
+
+def test_block3d_layout_runs_fgmres_on_c_alone():
+    """FGMRES on the block-3D layout [C 0; 0 I] [u0; u1] = [b; 0] with the block
+    preconditioner (exact solve of the identity block, no extension term)
+    takes the same steps as FGMRES on C u0 = b with the 3D preconditioner
+    alone (Section 5 setup: FGMRES(20) to 1e-6): same step count, same
+    history, same u0, and u1 stays zero."""
+    inst = synth.make_instance(5, 8, n_segments=5, elems_per_segment=3, radius=1e-3, beta=1.0, k_omega=1e-3,
+                               sigma_omega=1e-3, boundary="neumann", problem="block3d")
+    t = fem.assemble(inst)
+    C = t.A[:t.n3d, :t.n3d].tocsr()
+    b = t.F[:t.n3d]
+    p3d = krylov.p3d_jacobi(t)
+    ref = krylov.fgmres(C, b, precond=p3d, restart=20, tol=1e-6, max_iters=1000)
+    got = krylov.fgmres(t.A, t.F, precond=krylov.BlockPreconditioner(t, p3d), restart=20, tol=1e-6,
+                        max_iters=1000)
+    assert ref.converged and got.converged and got.iters == ref.iters
+    assert np.allclose(got.history, ref.history, rtol=1e-9, atol=0)
+    assert np.allclose(got.x[:t.n3d], ref.x, rtol=1e-9, atol=1e-12 * np.max(np.abs(ref.x)))
+    assert not np.any(got.x[t.n3d:])
