@@ -53,6 +53,9 @@ def parse():
                     help="time and fix the launch shapes (SpMV sweep, BF16 sweep layers) before the timed solves (0: defaults)")
     ap.add_argument("--precision-runs", default="fp8,f32",
                     help="network dtypes also timed on the same workload (comma list of f32/bf16/fp8; empty: none)")
+    ap.add_argument("--block3d", type=int, default=1,
+                    help="also run the paper's 3D-block workload (Neumann, k = sigma = eps = 1e-3, FGMRES(20) to "
+                         "1e-6 at 21^3 / 41^3 / 81^3 nodes; 0: skip)")
     ap.add_argument("--cpu-neural-iters", type=int, default=3)
     ap.add_argument("--cpu-jacobi-iters", type=int, default=50)
     return ap.parse_args()
@@ -184,6 +187,58 @@ def time_kernel(ctx, fn, reps):
         end.record(ctx.stream)
     end.synchronize()
     return start.elapsed_time(end) / reps
+
+
+# the paper's mean FGMRES(20) iterations to 1e-6 on its own 3D-block test sets
+# (k = sigma = 1e-3; 100 unseen graphs each; Section 5, iteration/time table),
+# quoted as context: other graphs, other elements, other hardware
+PAPER_BLOCK3D = {"none": {"21^3": 147.72, "41^3": 431.91, "81^3": ">1000"},
+                 "U3hf(21^3)": {"21^3": 17.38, "41^3": 37.24, "81^3": 100.73}}
+
+
+def block3d_runs(ctx, count=16):
+    """The 3D-block problem of Section 5 at 21^3, 41^3 and 81^3 nodes: C u0 = b
+    by FGMRES(20) to relative residual 1e-6 (cap 1000) for `count` seeded
+    graphs per size, with no preconditioner, with diag(C)^-1 and with the
+    networks trained on the GPU at 21^3 and at 41^3 (BF16); mean steps and
+    solves/s."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2505_08491_amd as P
+    from paper_2505_08491_amd import weights as W
+    nets = {}
+    for nc in (20, 40):
+        wpath = os.path.join(os.path.dirname(W.default_path()), f"unet{nc}_block3d")
+        if os.path.exists(wpath + ".bin"):
+            nets[f"neural_trained_{nc + 1}^3"] = W.load(wpath)[0]
+    out = {"tol": 1e-6, "restart": 20, "cap": 1000, "graphs_per_size": count,
+           "weights": {k: f"paper_2505_08491_amd/weights/unet{int(k.split('_')[-1][:-2]) - 1}_block3d"
+                       for k in nets}, "paper_context": PAPER_BLOCK3D}
+    for n_cells in (20, 40, 80):
+        S = P.System(ctx, synth.workload_block3d(n_cells, count), vec_dtype="f32")
+        b = torch.from_numpy(S.rhs()).cuda()
+        row = {}
+        for name in ["none", "block_jacobi"] + list(nets):
+            if name in nets:
+                S.set_preconditioner("neural", weights=nets[name], cnn_dtype="bf16")
+            else:
+                S.set_preconditioner(name)
+            x = torch.zeros_like(b)
+            S.solve_device(b, x, restart=20, max_iters=1000, tol=1e-6, use_graph=True)   # warm-up
+            torch.cuda.synchronize()
+            x.zero_()
+            t = time.perf_counter()
+            st = S.solve_device(b, x, restart=20, max_iters=1000, tol=1e-6, use_graph=True)
+            torch.cuda.synchronize()
+            T = time.perf_counter() - t
+            row[name] = {"iters_mean": float(np.mean([q["iters"] for q in st])),
+                         "converged": int(sum(q["converged"] for q in st)), "ms_per_batch": T * 1e3,
+                         "solves_per_s": S.n_inst / T}
+        out[f"{n_cells + 1}^3"] = row
+        S.free()
+    return out
 
 
 def cpu_baseline(inst, gpu_neural_iters, gpu_jacobi_iters, weights, n_neural, n_jacobi, x_gpu=None):
@@ -418,6 +473,8 @@ def main():
                          "used_fallback": int(sum(q["used_fallback"] for q in stp)), "max_true_rel_res": max(rel_p),
                          "ms_per_apply": time_kernel(ctx, lambda: S.precond_apply(xs), 3)}
 
+    block3d = block3d_runs(ctx) if a.block3d else None
+
     jac = None
     if not a.skip_jacobi:
         S.set_preconditioner("jacobi")
@@ -444,6 +501,7 @@ def main():
         "neural_inner_fgmres": inner,
         "neural_no_distance": nodist,
         "neural_precision": precision or None,
+        "paper_block3d": block3d,
         "jacobi": jac,
         "roofline": {"bound": stages[dom]["bound"],
                      "kernel": f"network stage {STAGES[dom]} (BF16 MFMA convolution launch, in-solver shape)",

@@ -61,6 +61,21 @@ typedef enum {
 
 typedef enum { MDNP_F64 = 0, MDNP_F32 = 1, MDNP_BF16 = 2, MDNP_FP8E4M3 = 3 } mdnp_dtype;
 
+/* Condition on the faces of the unit cube for the 3D unknowns. */
+typedef enum {
+  MDNP_BC_DIRICHLET = 0,  /* u = 0: boundary rows and columns eliminated symmetrically, unit rows kept */
+  MDNP_BC_NEUMANN = 1     /* natural (homogeneous Neumann) condition, the setup of Section 5: all nodes free */
+} mdnp_boundary;
+
+/* Which linear system an instance stands for. */
+typedef enum {
+  MDNP_PROBLEM_COUPLED = 0,  /* the coupled 3D-1D system A u = F of eq. "mainsys"                      */
+  MDNP_PROBLEM_BLOCK3D = 1   /* the 3D block alone, C u0 = b with C = K00 + 2 pi eps M00 (eq. "matrixC")
+                                and b = -A01 A11^-1 f1 (eq. "setB"), the problem of Section 5; stored in
+                                the coupled layout as [C 0; 0 I] [u0; u1] = [b; 0], so the 1D parts of
+                                all vectors stay zero and every solver call solves C u0 = b */
+} mdnp_problem;
+
 /* One parameter instance mu (Section 2.1).  All arrays are host memory, copied
  * by mdnp_upload.  The segments must form a tree rooted at vertex 0 with
  * seg_vertices[2s] the parent end and seg_vertices[2s+1] the child end of
@@ -78,6 +93,8 @@ typedef struct {
   double k_lambda;                 /* 1D diffusion; the 1D operator carries the area pi R^2     */
   double f_lambda;                 /* line source on the tree; F = [0; int f phi]               */
   int32_t n_circle;                /* points of the cross-section average T_Lambda (>= 3)       */
+  int32_t boundary;                /* mdnp_boundary; every instance of a system the same        */
+  int32_t problem;                 /* mdnp_problem                                              */
 } mdnp_instance_desc;
 
 typedef struct {
@@ -175,7 +192,8 @@ mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* sys, mdnp_prec_kind
  * the next solve or preconditioner application; allocates three vectors of
  * the system's length and type, freed with the system or by sweeps = 0.
  * Errors: MDNP_E_ARG (sweeps outside [0, 16], omega outside (0, 2)),
- * MDNP_E_STATE (inner FGMRES steps are on). */
+ * MDNP_E_STATE (inner FGMRES steps are on, or the system has the natural
+ * boundary condition). */
 mdnp_status mdnp_set_smoothing(mdnp_ctx* ctx, mdnp_sys* sys, int32_t sweeps, double omega);
 
 /* Inner Krylov 3D solve (Section 6): with steps > 0 the MDNP_PREC_NEURAL
@@ -185,7 +203,8 @@ mdnp_status mdnp_set_smoothing(mdnp_ctx* ctx, mdnp_sys* sys, int32_t sweeps, dou
  * place of one network application.  steps = 0 switches it off (the
  * default).  Allocates 2 steps + 1 vectors of the system's length and type,
  * freed with the system or by steps = 0.  Errors: MDNP_E_ARG (steps outside
- * [0, 8]), MDNP_E_STATE (smoothing is on). */
+ * [0, 8]), MDNP_E_STATE (smoothing is on, or the system has the natural
+ * boundary condition). */
 mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* sys, int32_t steps);
 
 /* Autotuner of the launch shapes, timed on this system's own batch and grid

@@ -26,7 +26,7 @@ class InstanceDesc(C.Structure):
                 ("n_segments", C.c_int32), ("seg_vertices", C.POINTER(C.c_int32)),
                 ("seg_radius", C.POINTER(C.c_double)), ("seg_beta", C.POINTER(C.c_double)),
                 ("elems_per_segment", C.c_int32), ("k_lambda", C.c_double), ("f_lambda", C.c_double),
-                ("n_circle", C.c_int32)]
+                ("n_circle", C.c_int32), ("boundary", C.c_int32), ("problem", C.c_int32)]
 
 
 class SolveOpts(C.Structure):

@@ -52,6 +52,8 @@ def _desc(inst, keep: list) -> InstanceDesc:
     d.k_lambda = float(inst.k_lambda)
     d.f_lambda = float(inst.f_lambda)
     d.n_circle = int(inst.n_circle)
+    d.boundary = {"dirichlet": 0, "neumann": 1}[getattr(inst, "boundary", "dirichlet")]
+    d.problem = {"coupled": 0, "block3d": 1}[getattr(inst, "problem", "coupled")]
     return d
 
 

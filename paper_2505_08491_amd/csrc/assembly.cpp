@@ -55,12 +55,16 @@ void wall_frame(const double tau[3], double n1[3], double n2[3]) {
 
 }  // namespace
 
+static std::string factor_1d(const mdnp_instance_desc& d, HostInstance& H);
+
 std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool& geom) {
   geom = false;
   if (d.n_cells < 2 || d.n_cells > 1024) return "n_cells must be in [2, 1024]";
   if (!d.vertex_xyz || !d.seg_vertices || !d.seg_radius || !d.seg_beta) return "null geometry array";
   if (d.elems_per_segment < 1 || d.elems_per_segment > 4096) return "elems_per_segment must be in [1, 4096]";
   if (d.n_circle < 3 || d.n_circle > 4096) return "n_circle must be in [3, 4096]";
+  if (d.boundary != MDNP_BC_DIRICHLET && d.boundary != MDNP_BC_NEUMANN) return "boundary must be MDNP_BC_DIRICHLET or MDNP_BC_NEUMANN";
+  if (d.problem != MDNP_PROBLEM_COUPLED && d.problem != MDNP_PROBLEM_BLOCK3D) return "problem must be MDNP_PROBLEM_COUPLED or MDNP_PROBLEM_BLOCK3D";
   if (!(std::isfinite(d.k_omega) && std::isfinite(d.sigma_omega) && std::isfinite(d.k_lambda) &&
         std::isfinite(d.f_lambda)) || d.k_omega < 0 || d.sigma_omega < 0 || d.k_lambda < 0)
     return "coefficients must be finite and non-negative";
@@ -117,6 +121,9 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
     int i = r % n, j = (r / n) % n, k = r / (n * n);
     return i == 0 || j == 0 || k == 0 || i == n - 1 || j == n - 1 || k == n - 1;
   };
+  // Dirichlet: boundary nodes are eliminated; Neumann: every node is free
+  const bool dir = d.boundary == MDNP_BC_DIRICHLET;
+  auto elim = [&](int r) -> bool { return dir && is_bnd(r); };
 
   // 1D mesh: vertices, then segment interiors from the parent end
   std::vector<double> pos((size_t)n1d * 3);
@@ -217,9 +224,9 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
       nodes.push_back(B1); coef.push_back(-t);
       const int m = (int)nodes.size();
       for (int u = 0; u < m; ++u) {
-        if (is_bnd(nodes[u])) continue;
+        if (elim(nodes[u])) continue;
         for (int v = 0; v < m; ++v) {
-          if (is_bnd(nodes[v])) continue;
+          if (elim(nodes[v])) continue;
           trips.push_back({nodes[u], nodes[v], W * (coef[u] * coef[v])});
         }
       }
@@ -237,10 +244,15 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
   }
   std::vector<Trip>().swap(trips);
 
-  // stencil values
+  // stencil values at an interior node (sums over its 8 cells) and one cell's
+  // share (node pairs differing in 0..3 coordinates; a pair shares 2^(3 - nd)
+  // cells around an interior node, fewer on the boundary)
   const double kh = d.k_omega * h, sh3 = d.sigma_omega * h * h * h;
   const double kst[4] = {kh * (8.0 / 3.0), 0.0, kh * (-1.0 / 6.0), kh * (-1.0 / 12.0)};
   const double mst[4] = {sh3 * (8.0 / 27.0), sh3 * (2.0 / 27.0), sh3 * (1.0 / 54.0), sh3 * (1.0 / 216.0)};
+  const double kel[4] = {kh * (1.0 / 3.0), 0.0, kh * (-1.0 / 12.0), kh * (-1.0 / 12.0)};
+  const double mel[4] = {sh3 * (1.0 / 27.0), sh3 * (1.0 / 54.0), sh3 * (1.0 / 108.0), sh3 * (1.0 / 216.0)};
+  H.neumann = !dir;
 
   H.row_ptr.assign((size_t)nt + 1, 0);
   H.col.clear();
@@ -254,58 +266,89 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
   H.m_col.clear();
   H.m_val.clear();
   H.m_a01.assign(n3d, 0);
-  std::vector<std::pair<int32_t, double>> merged;
+  typedef std::vector<std::pair<int32_t, double>> RowEntries;
+  // sum of two column-sorted entry lists, columns merged
+  auto merge_rows = [](const RowEntries& a, const RowEntries& b, RowEntries& out) {
+    out.clear();
+    out.reserve(a.size() + b.size());
+    size_t i = 0, j = 0;
+    while (i < a.size() || j < b.size()) {
+      const int32_t ca = i < a.size() ? a[i].first : INT32_MAX;
+      const int32_t cb = j < b.size() ? b[j].first : INT32_MAX;
+      const int32_t cmin = std::min(ca, cb);
+      double acc = 0.0;
+      if (ca == cmin) acc += a[i++].second;
+      if (cb == cmin) acc += b[j++].second;
+      out.push_back({cmin, acc});
+    }
+  };
+  RowEntries merged, cpl, stn, corr, mrow;
   for (int r = 0; r < nt; ++r) {
     auto b0 = rowt.begin() + tptr[r], b1 = rowt.begin() + tptr[r + 1];
     std::sort(b0, b1, [](const std::pair<int32_t, double>& u, const std::pair<int32_t, double>& v) {
       return u.first < v.first;
     });
     // coupling / 1D part of the row on its own (duplicates merged)
-    bool m01 = false;
+    cpl.clear();
     for (auto it = b0; it != b1;) {
       const int32_t cc = it->first;
       double acc = 0.0;
       while (it != b1 && it->first == cc) acc += (it++)->second;
-      if (r < n3d && !m01 && cc >= n3d) {
-        H.m_a01[r] = (int32_t)H.m_col.size();
-        m01 = true;
-      }
-      H.m_col.push_back(cc);
-      H.m_val.push_back(acc);
+      cpl.push_back({cc, acc});
     }
-    if (r < n3d && !m01) H.m_a01[r] = (int32_t)H.m_col.size();
-    H.m_ptr[r + 1] = (int32_t)H.m_col.size();
-    merged.clear();
-    if (r < n3d && is_bnd(r)) {
-      merged.push_back({r, 1.0});
-    } else {
-      if (r < n3d) {
-        const int i = r % n, j = (r / n) % n, k = r / (n * n);
-        (void)i; (void)j; (void)k;
+    // stencil part of a 3D row (stn), and the entries of it that the device's
+    // stencil kernels leave to M (corr): with the natural boundary those
+    // kernels still skip boundary nodes (a boundary row yields 0, boundary
+    // columns are left out), so M carries every boundary row's stencil
+    // entries and the boundary columns of the rows next to the boundary
+    stn.clear();
+    corr.clear();
+    if (r < n3d) {
+      if (elim(r)) {
+        stn.push_back({r, 1.0});
+      } else {
+        const int ix[3] = {r % n, (r / n) % n, r / (n * n)};
+        const bool rb = is_bnd(r);
         for (int dz = -1; dz <= 1; ++dz)
           for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
-              int c = r + dx + n * dy + n * n * dz;
-              if (is_bnd(c)) continue;
-              int nd = (dx != 0) + (dy != 0) + (dz != 0);
-              merged.push_back({c, kst[nd] + mst[nd]});
+              const int dd[3] = {dx, dy, dz};
+              bool inside = true;
+              for (int a = 0; a < 3; ++a) inside = inside && ix[a] + dd[a] >= 0 && ix[a] + dd[a] <= n - 1;
+              if (!inside) continue;
+              const int c = r + dx + n * dy + n * n * dz;
+              if (elim(c)) continue;
+              const int nd = (dx != 0) + (dy != 0) + (dz != 0);
+              double v;
+              if (!rb) {
+                v = kst[nd] + mst[nd];
+              } else {  // cells shared with the neighbour: 1 or 2 along each axis where it does not move
+                int cells = 1;
+                for (int a = 0; a < 3; ++a)
+                  if (dd[a] == 0) cells *= (ix[a] > 0) + (ix[a] < n - 1);
+                v = (kel[nd] + mel[nd]) * cells;
+              }
+              stn.push_back({c, v});
+              if (rb || is_bnd(c)) corr.push_back({c, v});
             }
       }
-      // merge the (sorted) coupling entries of the row into the (sorted) stencil entries
-      std::vector<std::pair<int32_t, double>> out;
-      out.reserve(merged.size() + (b1 - b0));
-      size_t a = 0;
-      auto it = b0;
-      while (a < merged.size() || it != b1) {
-        int32_t ca = a < merged.size() ? merged[a].first : INT32_MAX;
-        int32_t cb = it != b1 ? it->first : INT32_MAX;
-        int32_t cmin = std::min(ca, cb);
-        double acc = 0.0;
-        if (ca == cmin) acc += merged[a++].second;
-        while (it != b1 && it->first == cmin) acc += (it++)->second;
-        out.push_back({cmin, acc});
+    }
+    merge_rows(cpl, corr, mrow);
+    bool m01 = false;
+    for (const auto& e : mrow) {
+      if (r < n3d && !m01 && e.first >= n3d) {
+        H.m_a01[r] = (int32_t)H.m_col.size();
+        m01 = true;
       }
-      merged.swap(out);
+      H.m_col.push_back(e.first);
+      H.m_val.push_back(e.second);
+    }
+    if (r < n3d && !m01) H.m_a01[r] = (int32_t)H.m_col.size();
+    H.m_ptr[r + 1] = (int32_t)H.m_col.size();
+    if (r < n3d && elim(r)) {
+      merged = stn;
+    } else {
+      merge_rows(stn, cpl, merged);
     }
     bool found01 = false;
     for (const auto& e : merged) {
@@ -327,7 +370,7 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
     double acc = 0.0;
     int64_t cnt = 0;
     for (int r = 0; r < n3d; ++r)
-      if (!is_bnd(r)) { acc += H.diag[r] * H.diag[r]; ++cnt; }
+      if (!elim(r)) { acc += H.diag[r] * H.diag[r]; ++cnt; }
     H.alpha = cnt ? std::sqrt(acc / cnt) : 1.0;
   }
 
@@ -349,6 +392,67 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
     H.dist[r] = (float)std::sqrt(best);
   }
 
+  std::string err = factor_1d(d, H);
+  if (!err.empty() || d.problem != MDNP_PROBLEM_BLOCK3D) return err;
+
+  // the 3D block alone: b = -A01 x with A11 x = f1 (exact tree solve in FP64),
+  // then the layout [C 0; 0 I] [u0; u1] = [b; 0]
+  {
+    const TreeFactor& T = H.tree;
+    std::vector<double> y(H.F.begin() + n3d, H.F.end());
+    std::vector<int32_t> order;  // root first (BFS)
+    order.reserve(n1d);
+    order.push_back(0);
+    for (size_t k = 0; k < order.size(); ++k)
+      for (int32_t e = T.child_ptr[order[k]]; e < T.child_ptr[order[k] + 1]; ++e) order.push_back(T.child_idx[e]);
+    for (int k = n1d - 1; k >= 0; --k) {  // L y = f, leaves first
+      const int c = order[k];
+      if (T.parent[c] >= 0) y[T.parent[c]] -= T.lval[c] * y[c];
+    }
+    for (int c = 0; c < n1d; ++c) y[c] *= T.dinv[c];
+    for (int k = 0; k < n1d; ++k) {  // L^T x = D^-1 y, root first
+      const int c = order[k];
+      if (T.parent[c] >= 0) y[c] -= T.lval[c] * y[T.parent[c]];
+    }
+    std::vector<double> b(n3d, 0.0);
+    for (int r = 0; r < n3d; ++r)
+      for (int32_t e = H.a01_start[r]; e < H.row_ptr[r + 1]; ++e) b[r] -= H.val[e] * y[H.col[e] - n3d];
+    // drop the A01 / A10 entries, unit 1D rows, in A and in M
+    auto strip = [&](std::vector<int32_t>& ptr, std::vector<int32_t>& col, std::vector<double>& val,
+                     std::vector<int32_t>* a01) {
+      std::vector<int32_t> p2(ptr.size(), 0), c2;
+      std::vector<double> v2;
+      c2.reserve(col.size());
+      v2.reserve(val.size());
+      for (int r = 0; r < nt; ++r) {
+        if (r < n3d) {
+          for (int32_t e = ptr[r]; e < ptr[r + 1]; ++e)
+            if (col[e] < n3d) { c2.push_back(col[e]); v2.push_back(val[e]); }
+          if (a01) (*a01)[r] = (int32_t)c2.size();
+        } else {
+          c2.push_back(r);
+          v2.push_back(1.0);
+        }
+        p2[r + 1] = (int32_t)c2.size();
+      }
+      ptr.swap(p2);
+      col.swap(c2);
+      val.swap(v2);
+    };
+    strip(H.row_ptr, H.col, H.val, &H.a01_start);
+    strip(H.m_ptr, H.m_col, H.m_val, &H.m_a01);
+    for (int r = n3d; r < nt; ++r) H.diag[r] = 1.0;
+    for (int r = 0; r < n3d; ++r) H.F[r] = b[r];
+    for (int r = n3d; r < nt; ++r) H.F[r] = 0.0;
+    return factor_1d(d, H);
+  }
+}
+
+// Factorisations of the 1D block A11 held in H's CSR (no fill): leaves-first
+// LDL^T of the whole tree and the chain-compressed form.
+static std::string factor_1d(const mdnp_instance_desc& d, HostInstance& H) {
+  const int V = d.n_vertices, S = d.n_segments, E = d.elems_per_segment;
+  const int n3d = H.n3d, n1d = H.n1d;
   // tree factorisation of A11 (1D block incl. coupling mass), leaves first
   TreeFactor& T = H.tree;
   T.parent.assign(n1d, -1);

@@ -46,9 +46,13 @@ struct HostInstance {
   std::vector<double> val;
   std::vector<int32_t> a01_start;      // per 3D row: first entry with a 1D column
   // Split form used by the device: A = S + M with S the constant 27-point
-  // stencil on the free 3D nodes (identity on Dirichlet nodes) and M the
-  // coupling entries of the 3D rows plus the whole 1D rows (CSR, sorted).
+  // stencil on the interior 3D nodes (boundary neighbours left out; identity
+  // on Dirichlet nodes, zero on Neumann boundary nodes) and M the coupling
+  // entries of the 3D rows, the stencil entries S leaves out under the
+  // natural boundary, and the whole 1D rows (CSR, sorted).
   double stencil[4] = {0, 0, 0, 0};    // stencil value by number of differing coordinates
+  bool neumann = false;                // natural boundary: the stencil kernels yield 0 on boundary
+                                       // rows (M holds those rows), Dirichlet: the unit row
   std::vector<int32_t> m_ptr, m_col;
   std::vector<double> m_val;
   std::vector<int32_t> m_a01;          // per 3D row: first M entry with a 1D column

@@ -372,8 +372,11 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
   mdnp_status st = guarded(ctx, [&] {
     if (!descs || !out || n_inst < 1) fail(MDNP_E_ARG, "mdnp_upload: null argument or n_inst < 1");
     if (vec_dtype != MDNP_F64 && vec_dtype != MDNP_F32) fail(MDNP_E_ARG, "vec_dtype must be MDNP_F64 or MDNP_F32");
-    for (int i = 1; i < n_inst; ++i)
+    for (int i = 1; i < n_inst; ++i) {
       if (descs[i].n_cells != descs[0].n_cells) fail(MDNP_E_ARG, "all instances of a system must share n_cells");
+      if (descs[i].boundary != descs[0].boundary)
+        fail(MDNP_E_ARG, "all instances of a system must share the boundary condition");
+    }
     HIPCHK(hipSetDevice(ctx->device));
     s = new mdnp_sys();
     s->ctx = ctx;
@@ -404,6 +407,7 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
       if (!errs[i].empty()) fail(geoms[i] ? MDNP_E_GEOM : MDNP_E_ARG, "instance " + std::to_string(i) + ": " + errs[i]);
     const HostInstance& h0 = s->host[0];
     s->n_cells = h0.n_cells;
+    s->neumann = h0.neumann;
     s->n = h0.n;
     s->n3d = h0.n3d;
     // offsets
@@ -424,7 +428,7 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
     for (int i = 0; i < n_inst; ++i) s->mnz_tot += (int64_t)s->host[i].m_col.size();
     if (s->mnz_tot >= INT32_MAX) fail(MDNP_E_ARG, "coupling block too large for 32-bit indices");
     std::vector<int32_t> mp(s->ntot + 1), mc(s->mnz_tot), ma01((size_t)n_inst * s->n3d);
-    std::vector<double> mv64(s->mnz_tot), dinv(s->ntot), alpha(n_inst), stn((size_t)n_inst * 4);
+    std::vector<double> mv64(s->mnz_tot), dinv(s->ntot), alpha(n_inst), stn((size_t)n_inst * kStencilStride);
     std::vector<float> mv32(s->mnz_tot), dist((size_t)n_inst * s->n3d);
     int64_t mo = 0;
     for (int i = 0; i < n_inst; ++i) {
@@ -449,7 +453,8 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
         for (int r = 0; r < h.n3d; ++r) dist[(size_t)i * s->n3d + r] = (float)((double)h.dist[r] * sc);
       }
       alpha[i] = h.alpha;
-      for (int q = 0; q < 4; ++q) stn[(size_t)i * 4 + q] = h.stencil[q];
+      for (int q = 0; q < 4; ++q) stn[(size_t)i * kStencilStride + q] = h.stencil[q];
+      stn[(size_t)i * kStencilStride + 4] = h.neumann ? 0.0 : 1.0;  // a boundary row of S
     }
     s->d_off = dupload(s->off, stream);
     s->d_stencil = dupload(stn, stream);
@@ -793,6 +798,7 @@ extern "C" mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* s, int32_t 
     if (!s) fail(MDNP_E_ARG, "null system");
     if (steps < 0 || steps > 8) fail(MDNP_E_ARG, "steps must be in [0, 8]");
     if (steps > 0 && s->smooth.sweeps > 0) fail(MDNP_E_STATE, "switch the smoothing off first");
+    if (steps > 0 && s->neumann) fail(MDNP_E_STATE, "inner FGMRES steps are built for the Dirichlet condition only");
     HIPCHK(hipSetDevice(ctx->device));
     drop_graphs(s->work);
     free_inner(s->inner);
@@ -825,6 +831,7 @@ extern "C" mdnp_status mdnp_set_smoothing(mdnp_ctx* ctx, mdnp_sys* s, int32_t sw
     if (sweeps < 0 || sweeps > 16) fail(MDNP_E_ARG, "sweeps must be in [0, 16]");
     if (sweeps > 0 && !(omega > 0.0 && omega < 2.0)) fail(MDNP_E_ARG, "omega must be in (0, 2)");
     if (sweeps > 0 && s->inner.steps > 0) fail(MDNP_E_STATE, "switch the inner FGMRES steps off first");
+    if (sweeps > 0 && s->neumann) fail(MDNP_E_STATE, "smoothing is built for the Dirichlet condition only");
     HIPCHK(hipSetDevice(ctx->device));
     drop_graphs(s->work);
     SmoothState& m = s->smooth;

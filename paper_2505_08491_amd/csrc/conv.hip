@@ -137,18 +137,19 @@ __global__ void __launch_bounds__(BS) k_conv_in0(const Tv* __restrict__ z, const
 }
 
 // Last layer inside the solver: 1x1 16 -> 1, then z0 = s / alpha * U on the free
-// nodes (Dirichlet nodes are left alone).
+// nodes (with the Dirichlet condition, boundary nodes are left alone; with the
+// natural one, all_nodes = 1, every node is free).
 template <typename Tv, typename Tin>
 __global__ void __launch_bounds__(BS) k_head_out(const Tin* __restrict__ d0, const float* __restrict__ wt,
                                                  const float* __restrict__ bias, int n, Tv* __restrict__ z,
                                                  const int64_t* off, const double* alpha, double alpha_override,
-                                                 const double* scale, const InstState* st) {
+                                                 const double* scale, const InstState* st, int all_nodes) {
   const int64_t nvox = (int64_t)n * n * n;
   const int64_t v = (int64_t)blockIdx.x * BS + threadIdx.x;
   const int i = blockIdx.z;
   if (st && !(st[i].active && st[i].mode == 0)) return;
   if (v >= nvox) return;
-  if (is_bnd((int)v, n)) return;
+  if (!all_nodes && is_bnd((int)v, n)) return;
   const Tin* x = d0 + ((int64_t)i * nvox + v) * 16;
   float out = bias[0];
 #pragma unroll
@@ -306,13 +307,15 @@ __global__ void __launch_bounds__(BS) k_db(const float* __restrict__ dz, int cou
 
 // ---------------------------------------------------------------- training objective
 
+// The network output on the free nodes: zero on the Dirichlet boundary (none
+// is fixed under the natural condition, dirichlet = 0).
 __global__ void __launch_bounds__(BS) k_mask_bnd(const float* __restrict__ u, float* __restrict__ um, int n,
-                                                 int64_t n3d) {
+                                                 int64_t n3d, int dirichlet) {
   const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
   const int slot = blockIdx.y;
   if (k >= n3d) return;
   const int64_t g = (int64_t)slot * n3d + k;
-  um[g] = is_bnd((int)k, n) ? 0.0f : u[g];
+  um[g] = dirichlet && is_bnd((int)k, n) ? 0.0f : u[g];
 }
 
 // e = r - Cu / alpha, partial sums of e^2 (one row of partials per slot).
@@ -351,12 +354,12 @@ __global__ void k_loss_sum(const double* part, int nbx, int n_slots, double* los
 // du = -2 C e / alpha on the free nodes, 0 on the Dirichlet nodes.
 __global__ void __launch_bounds__(BS) k_loss_grad_fin(const float* __restrict__ ce, float* __restrict__ du,
                                                       const int32_t* inst, const double* alpha, int n,
-                                                      int64_t n3d) {
+                                                      int64_t n3d, int dirichlet) {
   const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
   const int slot = blockIdx.y;
   if (k >= n3d) return;
   const int64_t g = (int64_t)slot * n3d + k;
-  du[g] = is_bnd((int)k, n) ? 0.0f : (float)(-2.0 * (double)ce[g] / alpha[inst[slot]]);
+  du[g] = dirichlet && is_bnd((int)k, n) ? 0.0f : (float)(-2.0 * (double)ce[g] / alpha[inst[slot]]);
 }
 
 __global__ void __launch_bounds__(BS) k_pack_input(const float* __restrict__ r, const float* __restrict__ dist,
@@ -680,15 +683,25 @@ void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, const InstState* st,
   const dim3 grid((unsigned)((cube(n) + BS - 1) / BS), 1, batch);
   const bool all = only_stage < 0;
   const int mid_lo = all ? 1 : only_stage, mid_hi = all ? 9 : only_stage;
-  if (c.dtype == MDNP_BF16) {
+  if (c.dtype == MDNP_BF16 && !s->neumann) {
     // first layer reads the Krylov vector directly; D0, ReLU, the 1x1 head and the
-    // unscaling are one kernel writing z0
+    // unscaling are one kernel writing z0 on the free (interior) nodes
     if (all || only_stage == 0)
       conv_mfma_in0<Tv>(c, zin, s->d_off, isc, s->d_dist, n, batch, (bf16*)act[1], st, stream);
     unet_middle<bf16>(c, c.w, act, batch, n, c.dtype, st, stream, std::min(mid_hi, 8), mid_lo);
     if (all || only_stage == 9)
       conv_mfma_d0_head<Tv>(c, (const bf16*)act[9], (const bf16*)act[2], n, batch, z, s->d_off, s->d_alpha,
                             s->alpha_override, isc + s->n_inst, st, stream);
+  } else if (c.dtype == MDNP_BF16) {
+    // natural boundary: every node is free, so D0 writes its whole grid and
+    // the head and the unscaling write z0 everywhere
+    if (all || only_stage == 0)
+      conv_mfma_in0<Tv>(c, zin, s->d_off, isc, s->d_dist, n, batch, (bf16*)act[1], st, stream);
+    unet_middle<bf16>(c, c.w, act, batch, n, c.dtype, st, stream, mid_hi, mid_lo);
+    if (all || only_stage == 9)
+      hipLaunchKernelGGL((k_head_out<Tv, bf16>), grid, dim3(BS), 0, stream, (const bf16*)act[10],
+                         c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override,
+                         isc + s->n_inst, st, 1);
   } else {
     if (all || only_stage == 0)
       hipLaunchKernelGGL((k_conv_in0<Tv, float>), grid, dim3(BS), 0, stream, zin, s->d_off, isc, s->d_dist,
@@ -697,7 +710,7 @@ void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, const InstState* st,
     if (all || only_stage == 9)
       hipLaunchKernelGGL((k_head_out<Tv, float>), grid, dim3(BS), 0, stream, (const float*)act[10],
                          c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override,
-                         isc + s->n_inst, st);
+                         isc + s->n_inst, st, s->neumann ? 1 : 0);
   }
 }
 template void cnn_apply_in_solver<float>(mdnp_sys*, const float*, float*, const InstState*, hipStream_t,
@@ -994,12 +1007,13 @@ static void loss_grad_core(mdnp_sys* s, const int32_t* inst, int n_slots, const 
   float* ce = buf + (size_t)n_slots * n3d;
   double* part = (double*)(buf + (size_t)n_slots * n3d * 2);
   const dim3 g2((unsigned)((n3d + BS - 1) / BS), n_slots);
-  hipLaunchKernelGGL(k_mask_bnd, g2, dim3(BS), 0, stream, u, um, s->n, n3d);
+  hipLaunchKernelGGL(k_mask_bnd, g2, dim3(BS), 0, stream, u, um, s->n, n3d, s->neumann ? 0 : 1);
   launch_spmv_a00_slots(s, inst, n_slots, um, ce, stream);
   hipLaunchKernelGGL(k_loss_e, dim3(nbx, n_slots), dim3(BS), 0, stream, r, ce, inst, s->d_alpha, n3d, part, nbx);
   hipLaunchKernelGGL(k_loss_sum, dim3((n_slots + 63) / 64), dim3(64), 0, stream, part, nbx, n_slots, loss);
   launch_spmv_a00_slots(s, inst, n_slots, ce, um, stream);
-  hipLaunchKernelGGL(k_loss_grad_fin, g2, dim3(BS), 0, stream, um, du, inst, s->d_alpha, s->n, n3d);
+  hipLaunchKernelGGL(k_loss_grad_fin, g2, dim3(BS), 0, stream, um, du, inst, s->d_alpha, s->n, n3d,
+                     s->neumann ? 0 : 1);
 }
 
 void launch_loss_grad(mdnp_sys* s, const int32_t* inst, int n_slots, const float* r, const float* u, float* du,

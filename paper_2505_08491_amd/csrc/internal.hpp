@@ -15,6 +15,10 @@ namespace mdnp {
 
 typedef __hip_bfloat16 bf16;
 
+// Doubles per instance in the stencil array: the four stencil values by the
+// number of differing coordinates, then the diagonal of a boundary row of S.
+constexpr int kStencilStride = 5;
+
 // Per-instance solver state, kept in device memory and read by every kernel of
 // an Arnoldi step (masking of converged or inactive instances).
 struct InstState {
@@ -159,7 +163,9 @@ struct mdnp_sys {
   int64_t* d_off = nullptr;
   // operator A = S + M: S the constant 27-point stencil of the free 3D nodes
   // (unit rows on the Dirichlet nodes), M the coupling / 1D part in CSR
-  double* d_stencil = nullptr;     // [n_inst * 4] stencil value by differing coordinates
+  double* d_stencil = nullptr;     // [n_inst * kStencilStride] stencil value by differing coordinates,
+                                   // then the value of a boundary row of S (1 Dirichlet, 0 Neumann)
+  bool neumann = false;            // natural boundary on the cube faces (every instance)
   int sweep_target = 0;            // workgroups aimed at by the stencil sweep's z split (0: 2048)
   int32_t* d_mptr = nullptr;       // [ntot + 1], global entry offsets
   int32_t* d_mcol = nullptr;       // global column indices

@@ -127,14 +127,17 @@ inline unsigned xcd_grid(int nlog) { return (unsigned)(8 * ((nlog + 7) / 8)); }
 
 // (S x)[r] for 3D row r of the instance whose vector starts at x + base: the
 // constant 27-point stencil grouped by the number of differing coordinates
-// (centre, 6 faces, 12 edges, 8 corners); neighbours on the Dirichlet boundary
-// are eliminated, and a Dirichlet row is the unit row.
+// (centre, 6 faces, 12 edges, 8 corners); neighbours on the boundary are left
+// out, and a boundary row is st4[4] times the unit row (1 for the Dirichlet
+// condition; 0 for the natural one, whose boundary rows the coupling-row part
+// holds).
 template <typename Tv, typename Tacc>
 __device__ __forceinline__ Tacc stencil_row(const Tv* __restrict__ x, int64_t base, int r, int n,
                                             const double* __restrict__ st4) {
   const int ix = r % n, iy = (r / n) % n, iz = r / (n * n);
   const Tv* xc = x + base + r;
-  if (ix == 0 || iy == 0 || iz == 0 || ix == n - 1 || iy == n - 1 || iz == n - 1) return (Tacc)xc[0];
+  if (ix == 0 || iy == 0 || iz == 0 || ix == n - 1 || iy == n - 1 || iz == n - 1)
+    return (Tacc)st4[4] * (Tacc)xc[0];
   const bool vx[3] = {ix > 1, true, ix < n - 2};
   const bool vy[3] = {iy > 1, true, iy < n - 2};
   const bool vz[3] = {iz > 1, true, iz < n - 2};
@@ -157,17 +160,19 @@ __device__ __forceinline__ Tacc stencil_row(const Tv* __restrict__ x, int64_t ba
 // instance, lane l holding columns x = l + 1 + 64 k for k < NX (the interior
 // columns and the x = n - 1 boundary column; NX = 1 up to 65 nodes, 2 up to
 // 129).  For every input plane it loads rows y0 - 1 .. y0 + SW_TY, zeroes the
-// nodes on the Dirichlet boundary (their columns are eliminated), takes the
+// nodes on the boundary (Dirichlet: their columns are eliminated; natural
+// condition: the coupling-row part adds those columns), takes the
 // x-neighbour sums by lane shifts (the neighbours across the two column
 // blocks by lane reads) and forms per output row the 2D partials centre,
 // 4 in-plane faces and 4 in-plane corners.  Output plane z gathers them from
 // z' = z (offsets 0, 1, 2 differing coordinates) and z' = z +- 1 (1, 2, 3), so
-// two accumulators per row ride along the sweep.  Dirichlet rows copy x.
-// Planes are loaded SW_PD steps ahead into a ring of register sets; the loop
-// is unrolled over the ring, so no set is copied and a step waits only for its
-// own plane.  No LDS, no barriers.  The x = 0 boundary column is copied by
-// extra waves of the same launch (one per instance and SW_FZ planes, placed
-// with that instance's row strips).
+// two accumulators per row ride along the sweep.  Boundary rows get wb x
+// (wb = 1: Dirichlet unit rows; wb = 0: natural condition, the coupling-row
+// part holds those rows).  Planes are loaded SW_PD steps ahead into a ring of
+// register sets; the loop is unrolled over the ring, so no set is copied and a
+// step waits only for its own plane.  No LDS, no barriers.  The x = 0
+// boundary column is written by extra waves of the same launch (one per
+// instance and SW_FZ planes, placed with that instance's row strips).
 constexpr int SW_TY = 5;      // output rows per wave
 constexpr int SW_PD = 3;      // planes in flight (register sets)
 constexpr int SW_FZ = 8;      // planes per x = 0 copy wave
@@ -224,6 +229,7 @@ __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict_
     Tv* Y = y + off[i];
     // every load first (clamped to a valid address), then the stores: one
     // memory round trip per wave instead of one per row group and plane
+    const Tacc wb = (Tacc)stencil[kStencilStride * i + 4];
     Tv cv[SW_FZ][RG];
 #pragma unroll
     for (int zz = 0; zz < SW_FZ; ++zz)
@@ -231,7 +237,7 @@ __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict_
       for (int h = 0; h < RG; ++h) {
         const int z = zf + zz, gy = lane + 64 * h;
         const int64_t v = z < n && gy < n ? z * nn + (int64_t)gy * n : 0;
-        cv[zz][h] = SUM ? (Tv)((Tacc)X[v] + (Tacc)X2[v]) : X[v];
+        cv[zz][h] = (Tv)(wb * (SUM ? (Tacc)X[v] + (Tacc)X2[v] : (Tacc)X[v]));
       }
 #pragma unroll
     for (int zz = 0; zz < SW_FZ; ++zz)
@@ -248,8 +254,9 @@ __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict_
   const Tv* X = x + off[i];
   const Tv* X2 = SUM ? x2 + off[i] : nullptr;  // SUM = 1: S (x + x2)
   Tv* Y = y + off[i];
-  const Tacc w0 = (Tacc)stencil[4 * i], w1 = (Tacc)stencil[4 * i + 1], w2 = (Tacc)stencil[4 * i + 2],
-             w3 = (Tacc)stencil[4 * i + 3];
+  const double* st5 = stencil + kStencilStride * i;
+  const Tacc w0 = (Tacc)st5[0], w1 = (Tacc)st5[1], w2 = (Tacc)st5[2], w3 = (Tacc)st5[3];
+  const Tacc wb = (Tacc)st5[4];  // boundary rows: wb x (unit rows, or zero rows whose entries M holds)
   int xx[NX];
   bool xact[NX], xin[NX];
 #pragma unroll
@@ -334,8 +341,8 @@ __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict_
           const Tacc mid = w0 * c + w1 * f + w2 * e;  // contribution to plane zp
           const int gy = y0 + t;
           if (st_ok && gy < n && xact[k]) {
-            const bool bnd = bz || gy == 0 || gy == n - 1 || !xin[k];  // Dirichlet row: copy
-            Y[zo * nn + (int64_t)gy * n + xx[k]] = (Tv)(bnd ? prev[k][t] : accp[k][t] + up);
+            const bool bnd = bz || gy == 0 || gy == n - 1 || !xin[k];  // boundary row: wb x
+            Y[zo * nn + (int64_t)gy * n + xx[k]] = (Tv)(bnd ? wb * prev[k][t] : accp[k][t] + up);
           }
           accp[k][t] = accc[k][t] + mid;  // output plane zp: planes zp - 1 and zp so far
           accc[k][t] = up;                // output plane zp + 1: plane zp so far
@@ -364,7 +371,7 @@ __global__ void __launch_bounds__(BS) k_stencil(const double* __restrict__ stenc
     return;
   }
   const int64_t base = off[i];
-  const double* st4 = stencil + 4 * i;
+  const double* st4 = stencil + kStencilStride * i;
   double loc = 0.0;
   for (int64_t row = bstart[b] + threadIdx.x; row < bend[b]; row += BS) {
     const int r = (int)(row - base);
@@ -468,7 +475,7 @@ __global__ void __launch_bounds__(BS) k_apply_a00(const double* __restrict__ ste
   const T* xs = x + (int64_t)slot * n3d;
   const int r = blockIdx.x * BS + threadIdx.x;
   if (r >= n3d) return;
-  double acc = stencil_row<T, double>(xs, 0, r, n, stencil + 4 * i);
+  double acc = stencil_row<T, double>(xs, 0, r, n, stencil + kStencilStride * i);
   const int e = ma01[(int64_t)i * n3d + r];  // 3D columns end where the 1D ones start
   for (int k = mptr[base + r]; k < e; ++k) acc += (double)mval[k] * (double)xs[mcol[k] - base];
   y[(int64_t)slot * n3d + r] = (T)acc;

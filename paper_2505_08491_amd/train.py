@@ -13,7 +13,14 @@ v5..v8 of a Jacobi-GMRES cycle on the coupled system (3D parts), and fresh
 random unit vectors r = v / ||v||, v ~ N(0, I) (the high-frequency
 augmentation), all vanishing on the Dirichlet boundary.
 
+With --workload block3d the network is trained for the 3D-block problem of
+Section 5 (natural boundary, k = sigma = 1e-3, eps = 1e-3, C = A00 alone): the
+Arnoldi vectors are those of an unpreconditioned GMRES cycle on C u0 = b, an
+orthonormal basis of the Krylov space K_8(C, b) of Section 5.1, and no entry
+is fixed on the boundary.
+
     python -m paper_2505_08491_amd.train --steps 2000 --batch 32 --graphs 128
+    python -m paper_2505_08491_amd.train --workload block3d --n-cells 20 --out weights/unet20_block3d
 """
 from __future__ import annotations
 
@@ -40,23 +47,30 @@ def boundary_mask(n: int, device) -> torch.Tensor:
     return (e[None, None, :] | e[None, :, None] | e[:, None, None]).reshape(-1)
 
 
-def build_bank(ctx: Context, S: System, krylov_ids=(5, 6, 7, 8)) -> torch.Tensor:
+def build_bank(ctx: Context, S: System, krylov_ids=(5, 6, 7, 8), block3d=False) -> torch.Tensor:
     """[G][1 + len(krylov_ids)][n3d] unit vectors: b/||b|| and Arnoldi vectors."""
     G, n3d, dev = S.n_inst, S.n3d, "cuda"
     F = torch.from_numpy(S.rhs()).to(dev, torch.float32)
-    v = torch.zeros_like(F)
-    for i in range(G):                       # v = [0; f1]
-        o0, o1 = S.offsets[i], S.offsets[i + 1]
-        v[o0 + n3d:o1] = F[o0 + n3d:o1]
-    z = S.tree_solve(v)                      # [0; A11^-1 f1]
-    y = S.spmv(z)                            # [A01 A11^-1 f1; ...]
     bank = torch.zeros(G, 1 + len(krylov_ids), n3d, device=dev)
-    for i in range(G):
-        o0 = S.offsets[i]
-        b = -y[o0:o0 + n3d]
-        bank[i, 0] = b / b.norm()
-    # one Jacobi-GMRES cycle on the coupled system; its Arnoldi vectors are the samples
-    S.set_preconditioner("jacobi")
+    if block3d:                              # F = [b; 0] already
+        for i in range(G):
+            o0 = S.offsets[i]
+            b = F[o0:o0 + n3d]
+            bank[i, 0] = b / b.norm()
+    else:
+        v = torch.zeros_like(F)
+        for i in range(G):                   # v = [0; f1]
+            o0, o1 = S.offsets[i], S.offsets[i + 1]
+            v[o0 + n3d:o1] = F[o0 + n3d:o1]
+        z = S.tree_solve(v)                  # [0; A11^-1 f1]
+        y = S.spmv(z)                        # [A01 A11^-1 f1; ...]
+        for i in range(G):
+            o0 = S.offsets[i]
+            b = -y[o0:o0 + n3d]
+            bank[i, 0] = b / b.norm()
+    # one GMRES cycle (Jacobi-preconditioned on the coupled system, plain on
+    # C for the 3D block); its Arnoldi vectors are the samples
+    S.set_preconditioner("none" if block3d else "jacobi")
     m = max(krylov_ids)
     S.solve(S.rhs(), restart=m, max_iters=m, tol=1e-30)
     for c, k in enumerate(krylov_ids):
@@ -75,22 +89,30 @@ def dist_weight_mask() -> np.ndarray:
 
 
 def train(steps=2000, batch=32, graphs=128, n_cells=32, lr=1e-3, lr_min=1e-5, dtype="bf16", seed=0,
-          p_random=0.5, p_rhs=0.25, out=None, log_every=50, val_graphs=16, resume=None, no_dist=False):
+          p_random=0.5, p_rhs=0.25, out=None, log_every=50, val_graphs=16, resume=None, no_dist=False,
+          workload="coupled"):
     """no_dist: the first layer's distance-channel weights are held at zero, so
-    the network never sees the distance field (parameterisation ablation)."""
+    the network never sees the distance field (parameterisation ablation).
+    workload: "coupled" (Dirichlet, k = 1, the coupled system's 3D block) or
+    "block3d" (the 3D-block problem of Section 5, natural boundary)."""
     torch.manual_seed(seed)
     ctx = Context(0)
     t0 = time.time()
     import synth
-    pool = synth.workload_training(graphs, n_cells=n_cells)
+    block3d = workload == "block3d"
+    if block3d:
+        pool = synth.workload_training_block3d(graphs, n_cells=n_cells)
+        val = synth.workload_training_block3d(val_graphs, n_cells=n_cells, base=40_000)
+    else:
+        pool = synth.workload_training(graphs, n_cells=n_cells)
+        val = synth.workload_training(val_graphs, n_cells=n_cells, base=20_000)
     S = System(ctx, pool, vec_dtype="f32")
-    bank = build_bank(ctx, S)
-    val = synth.workload_training(val_graphs, n_cells=n_cells, base=20_000)
+    bank = build_bank(ctx, S, block3d=block3d)
     SV = System(ctx, val, vec_dtype="f32")
-    vbank = build_bank(ctx, SV)
+    vbank = build_bank(ctx, SV, block3d=block3d)
     n = n_cells + 1
     n3d = S.n3d
-    bnd = boundary_mask(n, "cuda")
+    bnd = boundary_mask(n, "cuda") if not block3d else torch.zeros(n3d, dtype=torch.bool, device="cuda")
     print(f"setup {time.time() - t0:.1f}s: {graphs} graphs at {n_cells}^3, bank {tuple(bank.shape)}", flush=True)
 
     w = torch.from_numpy(W.init(seed)).cuda()
@@ -160,7 +182,7 @@ def train(steps=2000, batch=32, graphs=128, n_cells=32, lr=1e-3, lr_min=1e-5, dt
     wn = w.detach().cpu().numpy()
     meta = {"step": steps, "batch": batch, "graphs": graphs, "n_cells": n_cells, "lr": lr, "lr_min": lr_min,
             "schedule": "cosine", "dtype": dtype, "seed": seed, "p_random": p_random, "p_rhs": p_rhs,
-            "no_dist": bool(no_dist), "train_seconds": elapsed, "history": history}
+            "no_dist": bool(no_dist), "workload": workload, "train_seconds": elapsed, "history": history}
     if out:
         os.makedirs(os.path.dirname(out), exist_ok=True)
         W.save(out, wn, meta, adam=(m.cpu().numpy(), v.cpu().numpy()))
@@ -185,12 +207,15 @@ def main(argv=None):
     ap.add_argument("--p-random", type=float, default=0.5, help="share of random unit samples")
     ap.add_argument("--p-rhs", type=float, default=0.25, help="share of b/||b|| samples (the rest: Arnoldi vectors)")
     ap.add_argument("--no-dist", action="store_true", help="keep the distance-channel weights at zero")
+    ap.add_argument("--workload", default="coupled", choices=["coupled", "block3d"],
+                    help="coupled: the coupled system (Dirichlet, k = 1); block3d: the 3D block of Section 5 "
+                         "(natural boundary, k = sigma = eps = 1e-3)")
     a = ap.parse_args(argv)
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
     train(steps=a.steps, batch=a.batch, graphs=a.graphs, n_cells=a.n_cells, lr=a.lr, dtype=a.dtype, seed=a.seed,
           p_random=a.p_random, p_rhs=a.p_rhs, out=a.out, log_every=a.log_every, resume=a.resume,
-          no_dist=a.no_dist)
+          no_dist=a.no_dist, workload=a.workload)
 
 
 if __name__ == "__main__":
