@@ -896,6 +896,11 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
   constexpr int CIN = CA + CB;
   typedef RowsTile<CIN, 0> T;
   constexpr int CLP = T::CLP;
+  // 32-channel tile voxels (64-byte stride) are read 16 voxels by 16 lanes
+  // for one 16-byte slot: without a permutation the lanes of a read collide
+  // on LDS banks.  Slot s of tile voxel v is stored at position s ^ swz(v).
+  constexpr bool SWZ = T::SLOTS == 4 && T::CPV == 4;
+  auto swz = [](int v) { return (v >> 2) & 3; };
   constexpr int KCT = RowsK<CIN, 0>::KCT;
   constexpr int KH = KS ? (KCT + 1) / 2 : KCT;   // chunk slots per wave
   constexpr int TYR = KS ? MB : 2 * MB;          // output rows per workgroup
@@ -956,7 +961,8 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
     int64_t o = zero_off;
     int st = 0;
     if (L < nload && it < plane_items) {
-      const int vt = it / T::SLOTS, ch = it - vt * T::SLOTS;
+      const int vt = it / T::SLOTS, chp = it - vt * T::SLOTS;
+      const int ch = SWZ ? chp ^ swz(vt) : chp;  // the channel slot stored at this position
       const int row = vt / XW, xx = vt - row * XW;
       const int gx = x0 + xx - 1, gy = y0 + row - 1;
       if (ch < T::CPV && gy >= 0 && gy < n && gx >= 0 && gx < n) {
@@ -1039,11 +1045,23 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
 #pragma unroll
     for (int m = 0; m < MB; ++m) acc[m] = {0.f, 0.f, 0.f, 0.f};
     auto fetch = [&](int i, bf16x8 (&xf)[MB + 2]) {
-      const unsigned short* base = ring + (size_t)((s0 + ltz[i]) % NR) * plane_elems +
-                                   ((size_t)rb0 * XW + xl) * CLP + lofs[i];
+      if constexpr (SWZ) {
+        // lofs = tx * CLP + slot * 8: tile voxel (rb0 + j) XW + xl + tx, slot permuted
+        const unsigned short* pl = ring + (size_t)((s0 + ltz[i]) % NR) * plane_elems;
+        const int tx = lofs[i] / CLP, sl = (lofs[i] - tx * CLP) >> 3;
 #pragma unroll
-      for (int j = 0; j < MB + 2; ++j)
-        xf[j] = lok[i] ? __builtin_bit_cast(bf16x8, *(const u32x4*)(base + (size_t)j * XW * CLP)) : zero8();
+        for (int j = 0; j < MB + 2; ++j) {
+          const int v = (rb0 + j) * XW + xl + tx;
+          xf[j] = lok[i] ? __builtin_bit_cast(bf16x8, *(const u32x4*)(pl + (size_t)v * CLP + ((sl ^ swz(v)) << 3)))
+                         : zero8();
+        }
+      } else {
+        const unsigned short* base = ring + (size_t)((s0 + ltz[i]) % NR) * plane_elems +
+                                     ((size_t)rb0 * XW + xl) * CLP + lofs[i];
+#pragma unroll
+        for (int j = 0; j < MB + 2; ++j)
+          xf[j] = lok[i] ? __builtin_bit_cast(bf16x8, *(const u32x4*)(base + (size_t)j * XW * CLP)) : zero8();
+      }
     };
     auto mma = [&](int i, const bf16x8 (&xf)[MB + 2]) {
 #pragma unroll

@@ -39,6 +39,18 @@ def oracle_block(systems):
     return A, F
 
 
+def maxrel(got, ref):
+    """max |got - ref| / max |ref|: the element-wise companion of the 2-norm checks."""
+    return float(np.max(np.abs(np.asarray(got) - np.asarray(ref))) / np.max(np.abs(ref)))
+
+
+def mtol(tol):
+    """Max-norm bound beside a 2-norm bound: the same for the exact-arithmetic
+    paths; twice it for the BF16 network (bounds of 1e-2 and above), whose
+    largest deviations sit where its output is largest."""
+    return 2 * tol if tol >= 1e-2 else tol
+
+
 def dev(x, dtype):
     return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
 
@@ -57,6 +69,7 @@ def test_spmv_matches_oracle(ctx, vec):
     ref = A @ (x if vec == "f64" else x.astype(np.float32).astype(np.float64))
     err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
     assert err <= (1e-14 if vec == "f64" else 1e-6), err
+    assert maxrel(y, ref) <= mtol((1e-14 if vec == "f64" else 1e-6)), err
     # exported CSR is the uploaded one
     for i, inst in enumerate(insts):
         rp, col, val = S.export_csr(i)
@@ -104,6 +117,7 @@ def test_spmv_a00_block(ctx):
         A00 = s.blocks()[0]
         ref = A00 @ x[k * S.n3d:(k + 1) * S.n3d]
         assert np.linalg.norm(y[k * S.n3d:(k + 1) * S.n3d] - ref) <= 1e-14 * np.linalg.norm(ref)
+        assert maxrel(y[k * S.n3d:(k + 1) * S.n3d], ref) <= 1e-14
 
 
 # ---------------------------------------------------------------- 1D solve and extension (rows a2, a3)
@@ -123,6 +137,7 @@ def test_tree_solve_matches_oracle(ctx, vec):
         ref = krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s)).solve_1d(v1)
         err = np.linalg.norm(z[o:o + s.n1d] - ref) / np.linalg.norm(ref)
         assert err <= (1e-12 if vec == "f64" else 1e-5), err
+        assert maxrel(z[o:o + s.n1d], ref) <= mtol((1e-12 if vec == "f64" else 1e-5)), err
 
 
 def test_tree_solve_large_tree(ctx):
@@ -135,6 +150,7 @@ def test_tree_solve_large_tree(ctx):
     z = S.tree_solve(dev(v, torch.float64)).cpu().numpy()
     ref = krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s)).solve_1d(v[s.n3d:])
     assert np.linalg.norm(z[s.n3d:] - ref) / np.linalg.norm(ref) <= 1e-12
+    assert maxrel(z[s.n3d:], ref) <= 1e-12
 
 
 def test_block_jacobi_preconditioner(ctx):
@@ -150,6 +166,7 @@ def test_block_jacobi_preconditioner(ctx):
         o0, o1 = S.offsets[k], S.offsets[k + 1]
         ref = krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s))(v[o0:o1])
         assert np.linalg.norm(z[o0:o1] - ref) <= 1e-13 * np.linalg.norm(ref)
+        assert maxrel(z[o0:o1], ref) <= 1e-13
 
 
 # ---------------------------------------------------------------- network (row a4, a5)
@@ -180,6 +197,7 @@ def test_cnn_forward_matches_oracle(ctx, dtype, tol, n):
         ref = ocnn.forward(th.astype(np.float32).astype(np.float64), X[k].astype(np.float32).astype(np.float64))[0]
         err = np.linalg.norm(y[k] - ref.ravel()) / np.linalg.norm(ref)
         assert err <= tol, (k, err)
+        assert maxrel(y[k], ref.ravel()) <= mtol(tol), (k, err, maxrel(y[k], ref.ravel()))
 
 
 def test_cnn_backward_matches_oracle(ctx):
@@ -203,9 +221,11 @@ def test_cnn_backward_matches_oracle(ctx):
         dxref.append(dX)
     dw = dw.cpu().double().numpy()
     assert np.linalg.norm(dw - gref) / np.linalg.norm(gref) <= 1e-4
+    assert maxrel(dw, gref) <= 1e-4
     dx = dx.cpu().double().numpy().reshape(batch, n, n, n, 2)
     dxref = np.stack(dxref)
     assert np.linalg.norm(dx - dxref) / np.linalg.norm(dxref) <= 1e-4
+    assert maxrel(dx, dxref) <= 1e-4
 
 
 @pytest.mark.parametrize("vec,cnn_dtype,tol", [("f64", "f32", 2e-5), ("f32", "f32", 2e-5), ("f32", "bf16", 5e-2)])
@@ -229,6 +249,7 @@ def test_neural_block_preconditioner(ctx, vec, cnn_dtype, tol):
         ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(vk)
         err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
         assert err <= tol, (k, err)
+        assert maxrel(z[o0:o1], ref) <= mtol(tol), (k, err)
 
 
 @pytest.mark.parametrize("vec,cnn_dtype,tol", [("f64", "f32", 2e-5), ("f32", "f32", 2e-5), ("f32", "bf16", 5e-2)])
@@ -257,6 +278,7 @@ def test_smoothed_neural_block_preconditioner(ctx, vec, cnn_dtype, tol, sweeps, 
         ref = krylov.BlockPreconditioner(s, p3)(vk)
         err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
         assert err <= tol, (k, err)
+        assert maxrel(z[o0:o1], ref) <= mtol(tol), (k, err)
     # switching it off restores the plain preconditioner
     S.set_smoothing(0)
     z0 = S.precond_apply(dev(v, td)).cpu().double().numpy()
@@ -264,6 +286,7 @@ def test_smoothed_neural_block_preconditioner(ctx, vec, cnn_dtype, tol, sweeps, 
     vk = v[:S.offsets[1]] if vec == "f64" else v[:S.offsets[1]].astype(np.float32).astype(np.float64)
     ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(vk)
     assert np.linalg.norm(z0[:S.offsets[1]] - ref) / np.linalg.norm(ref) <= tol
+    assert maxrel(z0[:S.offsets[1]], ref) <= tol
     S.free()
 
 
@@ -292,6 +315,7 @@ def test_inner_fgmres_block_preconditioner(ctx, vec, cnn_dtype, tol, steps):
         ref = krylov.BlockPreconditioner(s, p3)(vk)
         err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
         assert err <= tol, (k, err)
+        assert maxrel(z[o0:o1], ref) <= mtol(tol), (k, err)
     with pytest.raises(Exception):
         S.set_smoothing(1, 0.8)  # one 3D-solve variant at a time
     S.set_inner_steps(0)
@@ -337,6 +361,7 @@ def test_jacobi_gmres_fp64_matches_oracle(ctx):
     ref_k = krylov.fgmres(s.A, s.F, precond=krylov.jacobi(s.A), restart=50, tol=1e-30, max_iters=k)
     xk, _ = S.solve(s.F, restart=50, max_iters=k, tol=1e-30)
     assert np.linalg.norm(xk - ref_k.x) / np.linalg.norm(ref_k.x) <= 1e-8
+    assert maxrel(xk, ref_k.x) <= 1e-8
     h = S.history(0)
     steps = h[h >= 0]
     assert np.allclose(steps[:len(ref_k.history)], ref_k.history, rtol=1e-6)
@@ -369,6 +394,7 @@ def test_batched_masked_solve(ctx, graph):
         assert st[k]["converged"] and rel <= 1e-8, (k, st[k], rel)
         xd = krylov.direct_solve(s)
         assert np.linalg.norm(x[o0:o1] - xd) / np.linalg.norm(xd) <= 1e-6
+        assert maxrel(x[o0:o1], xd) <= 1e-6
         ref = krylov.fgmres(s.A, s.F, precond=krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s)), restart=20,
                             tol=1e-8, max_iters=5000)
         assert abs(st[k]["iters"] - ref.iters) <= 2, (k, st[k]["iters"], ref.iters)
@@ -415,6 +441,7 @@ def test_fp8_weights_match_oracle_quantisation(ctx):
         ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(v[o0:o1].astype(np.float64))
         err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
         assert err <= 5e-2, (k, err)
+        assert maxrel(z[o0:o1], ref) <= mtol(5e-2), (k, err)
 
 
 def test_neural_fgmres_solve(ctx):
@@ -428,6 +455,7 @@ def test_neural_fgmres_solve(ctx):
     assert st[0]["converged"] and rel <= 1e-8, (st, rel)
     xd = krylov.direct_solve(s)
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 1e-6
+    assert maxrel(x, xd) <= 1e-6
 
 
 # ---------------------------------------------------------------- training objective (row a10)
@@ -460,6 +488,7 @@ def test_loss_grad_matches_oracle(ctx):
         g = -2 * (A00 @ e) / s.alpha
         g[s.boundary] = 0
         assert np.linalg.norm(du[k] - g) <= 1e-5 * np.linalg.norm(g)
+        assert maxrel(du[k], g) <= 1e-5
 
 
 # ---------------------------------------------------------------- bench configuration (64^3 cells, 512 x 16 trees)
@@ -484,6 +513,7 @@ def test_spmv_bench_config(ctx, bench64):
     y = S.spmv(dev(x, torch.float32)).cpu().double().numpy()
     ref = A @ x.astype(np.float64)
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) <= 1e-6
+    assert maxrel(y, ref) <= 1e-6
 
 
 def test_spmv_repeat_equals_spmv(ctx, bench64):
@@ -506,6 +536,7 @@ def test_tree_solve_bench_config(ctx, bench64):
         Q = krylov.BlockPreconditioner(s, krylov.p3d_jacobi(s))
         ref = Q.solve_1d(v1)
         assert np.linalg.norm(z[o0:o0 + s.n1d] - ref) / np.linalg.norm(ref) <= 1e-6, k
+        assert maxrel(z[o0:o0 + s.n1d], ref) <= 1e-6, k
 
 
 def test_cnn_forward_bench_grid(ctx):
@@ -523,6 +554,7 @@ def test_cnn_forward_bench_grid(ctx):
         ref = ocnn.forward(th64, X[k].astype(np.float32).astype(np.float64))[0]
         err = np.linalg.norm(y[k] - ref.ravel()) / np.linalg.norm(ref)
         assert err <= 4e-2, (k, err)
+        assert maxrel(y[k], ref.ravel()) <= mtol(4e-2), (k, err, maxrel(y[k], ref.ravel()))
 
 
 def test_neural_precond_bench_config(ctx, bench64):
@@ -543,6 +575,7 @@ def test_neural_precond_bench_config(ctx, bench64):
         ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(v[o0:o1].astype(np.float64))
         err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
         assert err <= 5e-2, (k, err)
+        assert maxrel(z[o0:o1], ref) <= mtol(5e-2), (k, err)
 
 
 def test_fp8_precond_and_solve_bench_config(ctx, bench64):
@@ -564,6 +597,7 @@ def test_fp8_precond_and_solve_bench_config(ctx, bench64):
         ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(v[o0:o1].astype(np.float64))
         err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
         assert err <= 5e-2, (k, err)
+        assert maxrel(z[o0:o1], ref) <= mtol(5e-2), (k, err)
     b = np.concatenate([s.F for s in systems])
     x, st = S.solve(b, restart=30, max_iters=600, tol=1e-8)
     assert all(q["converged"] and not q["used_fallback"] for q in st), st
@@ -592,6 +626,7 @@ def test_inner_fgmres_precond_bench_config(ctx, bench64):
     ref = krylov.BlockPreconditioner(s, p3)(v[o0:o1].astype(np.float64))
     err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
     assert err <= 5e-2, err
+    assert maxrel(z[o0:o1], ref) <= mtol(5e-2), err
 
 
 def test_smoothed_precond_bench_config(ctx, bench64):
@@ -614,6 +649,7 @@ def test_smoothed_precond_bench_config(ctx, bench64):
     ref = krylov.BlockPreconditioner(s, p3)(v[o0:o1].astype(np.float64))
     err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
     assert err <= 5e-2, err
+    assert maxrel(z[o0:o1], ref) <= mtol(5e-2), err
 
 
 def test_autotune_keeps_preconditioner_output(ctx, bench64):
@@ -644,6 +680,35 @@ def test_autotune_keeps_preconditioner_output(ctx, bench64):
     b = np.concatenate([s.F for s in systems])
     _, st = S.solve(b, restart=50, max_iters=300, tol=1e-6)
     assert all(x["converged"] for x in st)
+
+
+def test_neural_precond_tuned_bench_system(ctx):
+    """Q(v) of the whole 16-instance benchmark system after the autotuner has
+    chosen its launch shapes (the configuration the benchmark times), for the
+    first and the last instance, against the FP64 oracle: every launch shape
+    of the batch, the instance offsets at both ends."""
+    from paper_2505_08491_amd import weights as W
+    P = _P()
+    insts = synth.workload_transfer(64, 16)
+    S = P.System(ctx, insts, vec_dtype="f32")
+    wpath = W.default_path()
+    th = W.load(wpath)[0] if __import__("os").path.exists(wpath + ".bin") else _theta(5).astype(np.float32)
+    S.set_preconditioner("neural", weights=th, cnn_dtype="bf16")
+    chosen = S.autotune()
+    print("tuned", chosen, flush=True)
+    th64 = np.asarray(th, dtype=np.float32).astype(np.float64)
+    net = lambda X: ocnn.forward(th64, X)[0]
+    v = synth.fast_normal(21, S.ntot).astype(np.float32)
+    z = S.precond_apply(dev(v, torch.float32)).cpu().double().numpy()
+    for k in (0, 15):
+        s = fem.assemble(insts[k])
+        o0, o1 = S.offsets[k], S.offsets[k + 1]
+        ref = krylov.BlockPreconditioner(s, krylov.p3d_neural(s, net))(v[o0:o1].astype(np.float64))
+        err = np.linalg.norm(z[o0:o1] - ref) / np.linalg.norm(ref)
+        print("instance", k, "err", err, "max", maxrel(z[o0:o1], ref), flush=True)
+        assert err <= 5e-2, (k, err)
+        assert maxrel(z[o0:o1], ref) <= mtol(5e-2), (k, err)
+    S.free()
 
 
 # ---------------------------------------------------------------- single 32^3 instance, FP32 network
@@ -682,6 +747,7 @@ def test_single32_fp32_network_config(ctx):
             assert np.allclose(steps, refh[:k], rtol=1e-3), (steps, refh[:k])
         assert np.linalg.norm(s.F - s.A @ x) <= 1e-8 * np.linalg.norm(s.F), vec
         assert np.linalg.norm(x - xd) <= 1e-6 * np.linalg.norm(xd), vec
+        assert maxrel(x, xd) <= 1e-6, vec
         S.free()
 
 
@@ -721,6 +787,7 @@ def test_batched32_full_config(ctx):
     xd = krylov.direct_solve(s)
     o0, o1 = S.offsets[k], S.offsets[k + 1]
     assert np.linalg.norm(x[o0:o1] - xd) <= 1e-6 * np.linalg.norm(xd), k
+    assert maxrel(x[o0:o1], xd) <= 1e-6, k
 
 
 # ---------------------------------------------------------------- 128^3 (resolution transfer, 2.15M 3D unknowns)
@@ -746,6 +813,7 @@ def test_spmv_128(ctx, bench128):
     y = S.spmv(dev(x, torch.float32)).cpu().double().numpy()
     ref = A @ x.astype(np.float64)
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) <= 1e-6
+    assert maxrel(y, ref) <= 1e-6
 
 
 def test_cnn_forward_129(ctx):
@@ -803,3 +871,4 @@ def test_3d_solve_variants_batched_129(ctx, variant):
     S2.free()
     S1.free()
     assert np.linalg.norm(z2 - z1) <= 1e-6 * np.linalg.norm(z1)
+    assert maxrel(z2, z1) <= 1e-6
