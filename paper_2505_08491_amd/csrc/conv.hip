@@ -492,8 +492,139 @@ int64_t cnn_saved_bytes(int batch, int n, mdnp_dtype dtype) {
   return offs[12];
 }
 
+// ---------------------------------------------------------------- FP32 convolutions on the matrix cores
+
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+// FP32 implicit-GEMM convolution on v_mfma_f32_16x16x4_f32 (FP32 products and
+// sums): per output voxel block of 16 consecutive flattened voxels and per
+// block of 16 output channels, D[co][v] = sum over (tap, ci) of W[co][t][ci]
+// X[in(v, t)][ci] in chunks of 16 input channels.  Lane l of a wave reads
+// input channels 4 (l / 16) .. + 3 of voxel l % 16 as one 16-byte load and
+// issues four MFMAs with them (k = l / 16 of MFMA m is channel 4 (l / 16) + m;
+// the weight operand follows the same order), so each wave owns MBV voxel
+// blocks x NB channel blocks of accumulators; lane l ends with output
+// channels 4 (l / 16) .. + 3 of voxel l % 16 and stores them as one 16-byte
+// write.  Zero padding and the transposed stride by in_coord, as in the
+// direct kernel; weights [taps][cin][cout].  Needs ca, cb, cout and the
+// leading dimensions multiples of 16.
+template <int MODE, int NB, int MBV>
+__global__ void __launch_bounds__(256) k_conv_f32m(ConvP p) {
+  const int64_t nvox = (int64_t)p.n_out * p.n_out * p.n_out;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int bt = blockIdx.z;
+  if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
+  const int64_t vb0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * MBV);  // first voxel of this wave
+  if (vb0 >= nvox) return;
+  const int co0 = blockIdx.y * 16 * NB;
+  const int cin = p.ca + p.cb;
+  const int r16 = lane & 15, kq = lane >> 4;
+  int oz[MBV], oy[MBV], ox[MBV];
+  bool vin_ok[MBV];
+#pragma unroll
+  for (int m = 0; m < MBV; ++m) {
+    const int64_t v = vb0 + m * 16 + r16;
+    vin_ok[m] = v < nvox;
+    const int64_t vv = vin_ok[m] ? v : 0;
+    ox[m] = (int)(vv % p.n_out);
+    oy[m] = (int)((vv / p.n_out) % p.n_out);
+    oz[m] = (int)(vv / ((int64_t)p.n_out * p.n_out));
+  }
+  f32x4v acc[NB][MBV];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int m = 0; m < MBV; ++m) acc[b][m] = f32x4v{0.f, 0.f, 0.f, 0.f};
+  const float* A = (const float*)p.a + (int64_t)bt * p.a_bs;
+  const float* B = p.cb ? (const float*)p.b + (int64_t)bt * p.b_bs : nullptr;
+  const int ntap = (MODE == KIND_PT) ? 1 : 27;
+  for (int t = 0; t < ntap; ++t) {
+    const int tz = t / 9, ty = (t / 3) % 3, tx = t % 3;
+    int64_t vin[MBV];
+    bool ok[MBV];
+#pragma unroll
+    for (int m = 0; m < MBV; ++m) {
+      const int iz = in_coord<MODE>(oz[m], tz, p.n_in);
+      const int iy = in_coord<MODE>(oy[m], ty, p.n_in);
+      const int ix = in_coord<MODE>(ox[m], tx, p.n_in);
+      ok[m] = vin_ok[m] && iz >= 0 && iy >= 0 && ix >= 0;
+      vin[m] = ok[m] ? ((int64_t)iz * p.n_in + iy) * p.n_in + ix : 0;
+    }
+    const float* wt = p.wt + (int64_t)t * cin * p.cout + co0 + r16;
+    for (int c0 = 0; c0 < cin; c0 += 16) {
+      const bool in_a = c0 < p.ca;
+      const float* src = in_a ? A : B;
+      const int ld = in_a ? p.lda : p.ldb;
+      const int cc = (in_a ? c0 : c0 - p.ca) + 4 * kq;
+      f32x4v xv[MBV];
+#pragma unroll
+      for (int m = 0; m < MBV; ++m)
+        xv[m] = ok[m] ? *(const f32x4v*)(src + vin[m] * ld + cc) : f32x4v{0.f, 0.f, 0.f, 0.f};
+      const float* wc = wt + (int64_t)(c0 + 4 * kq) * p.cout;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        float w4[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w4[j] = wc[(int64_t)j * p.cout + b * 16];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int m = 0; m < MBV; ++m)
+            acc[b][m] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[j], xv[m][j], acc[b][m], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < MBV; ++m) {
+    if (!vin_ok[m]) continue;
+    const int64_t v = vb0 + m * 16 + r16;
+    float* y = (float*)p.y + (int64_t)bt * p.y_bs + v * p.ldy + p.y_choff;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int co = co0 + b * 16 + 4 * kq;
+      f32x4v r = acc[b][m];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (p.bias) r[j] += p.bias[co + j];
+        if (p.relu) r[j] = fmaxf(r[j], 0.0f);
+      }
+      if (p.accumulate) r += *(const f32x4v*)(y + co);
+      *(f32x4v*)(y + co) = r;
+    }
+  }
+}
+
+static bool conv_f32m_fits(const ConvP& p, int kind) {
+  return kind != KIND_PT && p.ca % 16 == 0 && p.cb % 16 == 0 && p.cout % 16 == 0 && p.ca > 0 &&
+         p.lda % 4 == 0 && (p.cb == 0 || p.ldb % 4 == 0) && p.ldy % 4 == 0 && p.y_choff % 4 == 0;
+}
+
+template <int MODE>
+static void launch_f32m(const ConvP& p, int batch, hipStream_t stream) {
+  const int64_t nvox = cube(p.n_out);
+  constexpr int MBV = 2;
+  const int nb = p.cout % 64 == 0 ? 4 : p.cout % 32 == 0 ? 2 : 1;
+  const dim3 grid((unsigned)((nvox + 4 * 16 * MBV - 1) / (4 * 16 * MBV)), p.cout / (16 * nb), batch);
+  if (nb == 4) hipLaunchKernelGGL((k_conv_f32m<MODE, 4, MBV>), grid, dim3(256), 0, stream, p);
+  else if (nb == 2) hipLaunchKernelGGL((k_conv_f32m<MODE, 2, MBV>), grid, dim3(256), 0, stream, p);
+  else hipLaunchKernelGGL((k_conv_f32m<MODE, 1, MBV>), grid, dim3(256), 0, stream, p);
+}
+
+// FP32 layers whose channel counts are multiples of 16 run on the matrix cores
+// (k_conv_f32m); the others (2-channel first layer and its adjoint, the 1x1
+// head) and the BF16 fallback shapes on the direct kernel.
 template <typename Tin, typename Tout>
 static void conv_direct(const ConvP& p, int kind, int batch, hipStream_t stream) {
+  if constexpr (std::is_same<Tin, float>::value && std::is_same<Tout, float>::value) {
+    if (conv_f32m_fits(p, kind)) {
+      switch (kind) {
+        case KIND_S1: launch_f32m<KIND_S1>(p, batch, stream); return;
+        case KIND_S2: launch_f32m<KIND_S2>(p, batch, stream); return;
+        case KIND_T2: launch_f32m<KIND_T2>(p, batch, stream); return;
+        default: break;
+      }
+    }
+  }
   const int64_t nvox = cube(p.n_out);
   const int co_chunk = p.cout >= 16 ? 16 : 1;
   dim3 grid((unsigned)((nvox + BS - 1) / BS), p.cout / co_chunk, batch);

@@ -46,6 +46,33 @@ def _theta(seed, bias=0.05):
     return th.astype(np.float32).astype(np.float64)
 
 
+def _theta_margin(seed):
+    """Weights at 0.15 of the Kaiming scale and biases U[1, 1.5]: every
+    pre-activation of a ReLU layer stays well above zero, so FP32 and FP64
+    evaluations take the same ReLU decisions at any grid size (a single
+    decision that flips between the two moves a deep layer's weight gradient
+    by ~1e-3, far above FP32 rounding)."""
+    th = ocnn.init_params(seed)
+    rng = np.random.default_rng(seed)
+    off = 0
+    for a, b in ocnn.layer_sizes():
+        th[off:off + a] *= 0.15
+        th[off + a:off + a + b] = rng.uniform(1.0, 1.5, b)
+        off += a + b
+    return th.astype(np.float32).astype(np.float64)
+
+
+def _relu_margin(th, X):
+    """Smallest pre-activation of the ReLU layers over the scale of its layer (oracle)."""
+    _, cache = ocnn.forward(th, X)
+    out = 1.0
+    for name, _k, _ci, _co, relu in ocnn.LAYERS:
+        if relu:
+            z = cache[name][1]
+            out = min(out, float(np.min(z) / np.max(np.abs(z))))
+    return out
+
+
 def _inputs(n, batch, seed):
     rng = np.random.default_rng(seed)
     X = np.stack([np.stack([rng.normal(size=(n, n, n)) / n ** 1.5, rng.uniform(0, 0.5, (n, n, n))], axis=-1)
@@ -79,7 +106,7 @@ def _layer_errors(dw, gref):
 
 # ---------------------------------------------------------------- adjoint kernels
 
-@pytest.mark.parametrize("dtype,n,tol", [("bf16", 9, 5e-2), ("bf16", 33, 5e-2), ("f32", 33, 1e-4)])
+@pytest.mark.parametrize("dtype,n,tol", [("bf16", 9, 5e-2), ("bf16", 33, 5e-2), ("f32", 9, 1e-4), ("f32", 33, 1e-5)])
 def test_cnn_backward_matches_oracle(ctx, dtype, n, tol):
     """Weight and input gradients of the whole network for an upstream
     gradient G, from the activations the forward kernel stored (BF16 or
@@ -94,8 +121,14 @@ def test_cnn_backward_matches_oracle(ctx, dtype, n, tol):
     the 5e-2 bound for BF16; the
     distance from the all-FP64 network is the effect of BF16 and is printed."""
     batch = 2
-    th = _theta(11 + n)
     X, G = _inputs(n, batch, 30 + n)
+    if dtype == "f32" and n > 9:
+        # at 33^3 a random network holds pre-activations within FP32 rounding of
+        # zero; with every decision clear of the kink the comparison is tight
+        th = _theta_margin(11 + n)
+        assert min(_relu_margin(th, X[k]) for k in range(batch)) > 0.05
+    else:
+        th = _theta(11 + n)
     w = dev(th, torch.float32)
     saved = torch.empty(ctx.saved_bytes(batch, n, dtype), dtype=torch.uint8, device="cuda")
     ctx.cnn_forward(w, dev(X.reshape(batch, -1, 2), torch.float32), n, dtype, saved=saved)
