@@ -215,8 +215,9 @@ mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* sys, int32_t steps);
  * layers (L0a, L0b, L1b, L2b, D1, D0; from {256 .. 2048}) and the 16-voxel
  * M blocks per wave of the stride-2 and transposed layers (L1a {2, 4, 8}, L2a
  * {1, 2, 4}, U1 {1, 2}, U0 {1, 2, 4}) and the output rows of the sweep
- * layers L1b {2, 3, 4, 6}, D1 {2, 3} (per workgroup), L0b {3, 4, 5, 6} and
- * D0 {3, 4, 5} (per wave pair), the workgroup count of U1 and U0
+ * layers L1b {2, 3, 4, 6}, D1 {2, 3} (per workgroup), L0b {3, 4, 5, 6} (per
+ * wave pair) and D0 (fused with the head; its three-plane z sweep with 4, 6
+ * or 8 rows per workgroup, codes {12, 13, 14}), the workgroup count of U1 and U0
  * ({256 .. 4096}; each workgroup stages its weights in LDS and loops over
  * voxel blocks) and the 16-column x blocks per workgroup of L0a, L0b, D0
  * {1, 2, 4} and L1b, D1 {1, 2} (rows wider than that split over workgroups);

@@ -911,7 +911,7 @@ static const TuneLayer kTune[] = {
     {1, 4, {3, 4, 5, 6}, 1},                         // L0b  output rows per workgroup (per wave pair)
     {3, 4, {2, 3, 4, 6}, 1},                         // L1b
     {7, 2, {2, 3}, 1},                               // D1
-    {9, 3, {3, 4, 5}, 1},                            // D0 (+ head)
+    {9, 3, {12, 13, 14}, 1},                         // D0 (+ head): rows of the three-plane z sweep
     {6, 5, {256, 512, 1024, 2048, 4096}, 1},         // U1   workgroups (each loops over voxel blocks)
     {0, 3, {1, 2, 4}, 2},                            // L0a  x blocks per workgroup
     {1, 3, {1, 2, 4}, 2},                            // L0b

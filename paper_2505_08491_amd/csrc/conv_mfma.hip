@@ -1145,6 +1145,249 @@ __global__ void __launch_bounds__(512) k_conv16_ks(MfmaArgs p, RowsGrid q) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// The last full-resolution layer inside the solver (D0: 32 stacked input
+// channels [U0 | skip], 16 outputs, ReLU, then the 1x1 head and the unscaling
+// z0 = ||b0|| / alpha * U), as a z sweep that keeps three output planes in
+// registers.  Input plane zi feeds output planes zi + 1, zi, zi - 1 (taps
+// tz = 0, 1, 2), so each 16-voxel fragment read from LDS serves up to nine
+// MFMAs (three tz x three ty) instead of three, and only the plane being read
+// and the two being loaded sit in LDS.  After input plane zi, output plane
+// zi - 1 is complete: its epilogue runs and its accumulators start plane
+// zi + 2.  A workgroup of 2 XB waves owns rows y0 .. y0 + 2 MB - 1 (wave w:
+// x block w % XB, rows (w / XB) MB ..) of the planes z0 .. z0 + zc - 1;
+// the ring holds rows y0 - 1 .. y0 + 2 MB and x = x0 - 1 .. x0 + 16 XB,
+// filled by direct global-to-LDS loads two planes ahead.  All 27 taps' weight
+// fragments stay in registers, ordered [tz][ty][tx].  Per output the taps
+// are summed in the order (tz, tx, ty), one accumulator: the order of a
+// single-wave k_conv16_ks chunk loop.
+template <int MB, typename Tv, int NLW>
+__global__ void __launch_bounds__(512) k_conv16_zb(MfmaArgs p, RowsGrid q) {
+  constexpr int CA = 16, CB = 16, CIN = CA + CB;
+  typedef RowsTile<CIN, 0> T;
+  constexpr int CLP = T::CLP;
+  static_assert(T::SLOTS == 4 && T::CPV == 4, "32-channel tile voxels");
+  constexpr int TYR = 2 * MB, YW = TYR + 2, NR = 3;
+  constexpr int CPA = CA / 8;
+  static_assert(NLW <= 8, "the end-of-plane wait covers at most 8 loads");
+  auto swz = [](int v) { return (v >> 2) & 3; };
+  extern __shared__ __attribute__((aligned(1024))) unsigned short ring[];
+  int bxr, bt;
+  xcd_remap(bxr, bt);
+  if (p.st && !(p.st[bt].active && p.st[bt].mode == p.want_mode)) return;
+  const int n = p.n_out;
+  const int XW = q.xw;
+  const int y0 = q.ylo + (bxr % q.ytiles) * TYR;
+  const int xh = (bxr / q.ytiles) % q.nxs;
+  const int z0 = q.zlo + (bxr / q.ytiles / q.nxs) * q.zc;
+  const int zend = min(q.zhi, z0 + q.zc);
+  const int64_t nn = (int64_t)n * n, nv = nn * n;
+  const int nwaves = blockDim.x >> 6, xbn = nwaves >> 1;
+  const int x0 = xh * 16 * xbn;
+  const int plane_elems = (int)(T::plane_bytes(TYR, XW - 1) / 2);
+  const int plane_items = YW * XW * T::SLOTS;
+  const int nload = (plane_items + 63) >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int g = lane >> 4, r = lane & 15;
+  const int hr = wave >= xbn, xq = hr ? wave - xbn : wave;
+  const int rb0 = hr * MB;
+  const int nlw = min(NLW, (nload - wave + nwaves - 1) / nwaves);
+  auto wait_vm_newest = [&]() {
+    switch (nlw) {
+      case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+      case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+      case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+      case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
+      case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+      case 5: asm volatile("s_waitcnt vmcnt(5)" ::: "memory"); break;
+      case 6: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
+      case 7: asm volatile("s_waitcnt vmcnt(7)" ::: "memory"); break;
+      default: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    }
+  };
+  const bf16* A = p.a + (int64_t)bt * nv * CA;
+  const bf16* B = p.b + (int64_t)bt * nv * CB;
+  const char* Ab = (const char*)A;
+  const int64_t zero_off = (const char*)p.zero16 - Ab;
+  const int64_t b_off = (const char*)B - Ab;
+  int64_t doff[NLW];
+  int dstr[NLW];
+#pragma unroll
+  for (int k = 0; k < NLW; ++k) {
+    const int L = wave + k * nwaves;
+    const int it = L * 64 + lane;
+    int64_t o = zero_off;
+    int st = 0;
+    if (L < nload && it < plane_items) {
+      const int vt = it >> 2, chp = it & 3;
+      const int ch = chp ^ swz(vt);  // the channel slot stored at this position
+      const int row = vt / XW, xx = vt - row * XW;
+      const int gx = x0 + xx - 1, gy = y0 + row - 1;
+      if (gy >= 0 && gy < n && gx >= 0 && gx < n) {
+        const int64_t vv = (int64_t)gy * n + gx;
+        if (ch < CPA) {
+          o = (vv * CA + ch * 8) * 2;
+          st = (int)(nn * CA * 2);
+        } else {
+          o = b_off + (vv * CB + (ch - CPA) * 8) * 2;
+          st = (int)(nn * CB * 2);
+        }
+      }
+    }
+    doff[k] = o;
+    dstr[k] = st;
+  }
+  auto dma_plane = [&](int gz, int slot) {
+    unsigned short* pl = ring + (size_t)slot * plane_elems;
+    const bool zok = gz >= 0 && gz < n;
+#pragma unroll
+    for (int k = 0; k < NLW; ++k) {
+      const int L = wave + k * nwaves;
+      if (L < nload) {
+        const int64_t o = zok ? doff[k] + (int64_t)gz * dstr[k] : zero_off;
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)(Ab + o), (lds_void_t*)(pl + L * 512), 16, 0, 0);
+      }
+    }
+  };
+  // weight fragments w[tz][ty][tx]: rows [16 cout][3 ty][9 (tz, tx) x 32 ci]
+  bf16x8 wr[3][3][3];
+  {
+    const unsigned short* wsrc = (const unsigned short*)p.wrows;
+#pragma unroll
+    for (int tz = 0; tz < 3; ++tz)
+#pragma unroll
+      for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+        for (int tx = 0; tx < 3; ++tx)
+          wr[tz][ty][tx] =
+              __builtin_bit_cast(bf16x8, *(const u32x4*)(wsrc + (r * 3 + ty) * (9 * 32) + (tz * 3 + tx) * 32 + g * 8));
+  }
+  const int xl = xq * 16 + r;
+  const int co = g * 4;
+  float bia[4], whv[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    bia[j] = p.bias[co + j];
+    whv[j] = p.wh[co + j];
+  }
+  const float bhv = p.bh[0];
+  const double aa = p.alpha_override > 0.0 ? p.alpha_override : p.alpha[bt];
+  const float fsc = (float)(p.scale[bt] / aa);
+  Tv* zo_ = (Tv*)p.zout + p.off[bt];
+  // tile voxel of row j and tap tx for this lane, and its slot position
+  f32x4 acc[3][MB];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int m = 0; m < MB; ++m) acc[a][m] = {0.f, 0.f, 0.f, 0.f};
+  const int zi0 = z0 - 1, zi1 = zend;  // input planes zi0 .. zi1
+  dma_plane(zi0, 0);
+  dma_plane(zi0 + 1, 1);
+  wait_vm_newest();
+  lds_barrier();
+  // one input plane: its fragments feed the accumulators of the planes
+  // zi + 1 (slot A0, tz = 0), zi (A1, tz = 1), zi - 1 (A2, tz = 2); then the
+  // epilogue of plane zi - 1 and its slot cleared for plane zi + 2
+  auto step = [&](int zi, int s, auto a0c, auto a1c, auto a2c) {
+    constexpr int A0 = decltype(a0c)::value, A1 = decltype(a1c)::value, A2 = decltype(a2c)::value;
+    const bool more = zi + 2 <= zi1;
+    if (more) dma_plane(zi + 2, (s + 2) % NR);
+    const unsigned short* pl = ring + (size_t)s * plane_elems;
+#pragma unroll
+    for (int tx = 0; tx < 3; ++tx) {
+      bf16x8 xf[MB + 2];
+#pragma unroll
+      for (int j = 0; j < MB + 2; ++j) {
+        const int v = (rb0 + j) * XW + xl + tx;
+        xf[j] = __builtin_bit_cast(bf16x8, *(const u32x4*)(pl + (size_t)v * CLP + ((g ^ swz(v)) << 3)));
+      }
+#pragma unroll
+      for (int j = 0; j < MB + 2; ++j)
+#pragma unroll
+        for (int ty = 0; ty < 3; ++ty) {
+          const int m = j - ty;
+          if (m >= 0 && m < MB) {
+            acc[A0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[0][ty][tx], xf[j], acc[A0][m], 0, 0, 0);
+            acc[A1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[1][ty][tx], xf[j], acc[A1][m], 0, 0, 0);
+            acc[A2][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[2][ty][tx], xf[j], acc[A2][m], 0, 0, 0);
+          }
+        }
+    }
+    const int zo = zi - 1;
+    if (zo >= z0 && zo < zend) {
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        float h = 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float yj = __bfloat162float(__float2bfloat16(fmaxf(acc[A2][m][j] + bia[j], 0.f)));
+          h = fmaf(whv[j], yj, h);
+        }
+        h += __shfl_xor(h, 16, 64);
+        h += __shfl_xor(h, 32, 64);
+        const int y = y0 + rb0 + m;
+        // Dirichlet nodes keep the value set before the network runs
+        if (g == 0 && y < q.yhi && y > 0 && y < n - 1 && x0 + xl > 0 && zo > 0 && zo < n - 1)
+          zo_[((int64_t)zo * n + y) * n + x0 + xl] = (Tv)(fsc * (h + bhv));
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < MB; ++m) acc[A2][m] = {0.f, 0.f, 0.f, 0.f};
+    // plane zi + 1 has landed (zi + 2 may still be in flight: its loads and
+    // the epilogue stores are this wave's newest memory operations, and they
+    // complete in issue order); every wave is done with plane zi before the
+    // next step's loads overwrite its slot
+    if (more) wait_vm_newest();
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    lds_barrier();
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  // accumulator slot of output plane zo: (zo - zi0 + 2) % 3, so that input
+  // plane zi = zi0 + 3 k + ph uses slots (ph + 0, 1, 2) % 3 for zi + 1, zi, zi - 1
+  for (int zi = zi0; zi <= zi1; zi += 3) {
+    const int s = (zi - zi0) % NR;  // ring slot of plane zi: (zi - zi0) % 3
+    step(zi, s, I0{}, I2{}, I1{});
+    if (zi + 1 <= zi1) step(zi + 1, (s + 1) % NR, I1{}, I0{}, I2{});
+    if (zi + 2 <= zi1) step(zi + 2, (s + 2) % NR, I2{}, I1{}, I0{});
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// Launch of k_conv16_zb over the interior planes and rows (x < n - 1); false
+// when the grid or the LDS does not fit (then the caller keeps k_conv16_ks).
+template <int MB, typename Tv>
+bool launch_zb16(const MfmaArgs& a, int batch, hipStream_t stream, int target, int xbmax) {
+  constexpr int NLW = 8;
+  constexpr int TYR = 2 * MB;
+  typedef RowsTile<32, 0> T;
+  const int n = a.n_out;
+  const int xb = (n - 1) / 16;
+  int xbw = std::min(std::max(xb, 1), xbmax > 0 ? std::min(xbmax, 4) : 4);
+  while (xb % xbw) --xbw;
+  const int nxs = xb / xbw;
+  const int xw = 16 * xbw + 2;
+  const size_t lds = 3 * T::plane_bytes(TYR, xw - 1);
+  const int nload = ((TYR + 2) * xw * T::SLOTS + 63) / 64;
+  if (!((n - 1) % 16 == 0 && xb >= 1 && lds <= 160 * 1024 && a.zero16 && nload <= NLW * 2 * xbw)) return false;
+  RowsGrid q;
+  q.ylo = q.zlo = 1;
+  q.yhi = q.zhi = n - 1;
+  q.ytiles = (q.yhi - q.ylo + TYR - 1) / TYR;
+  q.nxs = nxs;
+  q.xw = xw;
+  const int planes = q.zhi - q.zlo;
+  int nz = (target + q.ytiles * nxs * batch - 1) / (q.ytiles * nxs * batch);
+  nz = std::max(1, std::min(nz, planes));
+  q.zc = (planes + nz - 1) / nz;
+  nz = (planes + q.zc - 1) / q.zc;
+  q.nedge = 0;
+  auto kern = k_conv16_zb<MB, Tv, NLW>;
+  if (lds > 65536) hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(q.ytiles * nxs * nz), 1, batch), dim3(2 * xbw * 64), lds, stream, a, q);
+  return true;
+}
+
 // Stride-1 convolution with COUT = 32 or 64 (the coarse levels), z-sweep with
 // a three-plane LDS ring over rows y0 - 1 .. y0 + MB (x = -1 .. n - 1, zero
 // outside), the next plane staged in registers while the current one is
@@ -1857,8 +2100,16 @@ void conv_mfma_d0_head(const CnnState& c, const bf16* u0, const bf16* s0, int n,
   (void)nmb;
   const int t = sweep_target(c, 9, kSweepBlocksD0);
   const int xm = c.tile_xb[9];
-  if (c.tile_mb[9] == 3) launch_ks16<16, 16, 3, 1, 1, Tv>(a, batch, stream, t, xm);
-  else if (c.tile_mb[9] == 5) launch_ks16<16, 16, 5, 1, 1, Tv>(a, batch, stream, t, xm);
+  // the three-plane z sweep with 4, 6 or 8 rows per workgroup (codes 12, 13,
+  // 14; 0 = the default, 8 rows); every choice sums each output's taps in the
+  // same order.  Grids it does not fit take the K-split sweep (codes 3, 4, 5
+  // select that kernel's rows per wave pair directly).
+  const int code = c.tile_mb[9] ? c.tile_mb[9] : 14;
+  if (code == 12 && launch_zb16<2, Tv>(a, batch, stream, t, xm)) return;
+  if (code == 13 && launch_zb16<3, Tv>(a, batch, stream, t, xm)) return;
+  if (code == 14 && launch_zb16<4, Tv>(a, batch, stream, t, xm)) return;
+  if (code == 3) launch_ks16<16, 16, 3, 1, 1, Tv>(a, batch, stream, t, xm);
+  else if (code == 5) launch_ks16<16, 16, 5, 1, 1, Tv>(a, batch, stream, t, xm);
   else launch_ks16<16, 16, 4, 1, 1, Tv>(a, batch, stream, t, xm);
 }
 template void conv_mfma_d0_head<float>(const CnnState&, const bf16*, const bf16*, int, int, float*, const int64_t*,
