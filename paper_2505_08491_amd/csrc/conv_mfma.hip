@@ -597,8 +597,11 @@ __global__ void __launch_bounds__(512) k_conv_lds(MfmaArgs p) {
 // (IN = 0) fill the ring with direct global-to-LDS loads (16 bytes per lane,
 // lane l landing at base + 16 l): a ring of four planes lets plane z + 2
 // arrive while the matrix cores work on plane z.  The first layer (IN = 1)
-// builds its two channels on the fly, staging plane z + 2 in registers over a
-// ring of three planes.
+// builds its two channels on the fly over a ring of three planes: the raw
+// input values of the next two planes sit in registers (two register sets
+// used in turn, so no copy waits for a load) and are converted to BF16 only
+// when their plane enters the ring, so every load has a whole plane of work
+// to land.
 //
 // The weights stay in registers for the whole launch, ordered [ty][tz, tx, ci]
 // so that one K chunk of 32 belongs to a single ty: an input fragment (input
@@ -703,29 +706,38 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
       __builtin_amdgcn_global_load_lds((gbl_void_t*)src, (lds_void_t*)(pl + L * 512), 16, 0, 0);
     }
   };
-  // ---- first layer: stage in registers
-  auto load_plane = [&](int gz, u32x4 (&buf)[NPF]) {
+  // ---- first layer: raw values of a plane in registers, converted on entry to
+  // the ring.  The loads are unconditional (voxels outside the grid read
+  // voxel 0 and are zeroed by the mask at conversion), so that the compiler can
+  // count the loads in flight and wait for the older plane only.
+  struct RawPlane {
+    Tv zv[NPF];
+    float dv[NPF];
+    unsigned ok;
+  };
+  auto load_plane = [&](int gz, RawPlane& buf) {
+    buf.ok = 0u;
 #pragma unroll
     for (int k = 0; k < NPF; ++k) {
       const int it = threadIdx.x + k * nthr;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (it < plane_items) {
-        const int row = it / XW, xx = it - row * XW;
-        const int gx = x0 + xx - 1, gy = y0 + row - 1;
-        if (gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n) {
-          const int64_t vv = ((int64_t)gz * n + gy) * n + gx;
-          v.x = (unsigned)f2bf((float)Z[vv] * sc) | ((unsigned)f2bf(D[vv]) << 16);
-        }
-      }
-      buf[k] = v;
+      const int row = it / XW, xx = it - row * XW;
+      const int gx = x0 + xx - 1, gy = y0 + row - 1;
+      const bool ok = it < plane_items && gz >= 0 && gz < n && gy >= 0 && gy < n && gx >= 0 && gx < n;
+      const int64_t vv = ok ? ((int64_t)gz * n + gy) * n + gx : 0;
+      buf.zv[k] = Z[vv];
+      buf.dv[k] = D[vv];
+      buf.ok |= ok ? (1u << k) : 0u;
     }
   };
-  auto store_plane = [&](int slot, const u32x4 (&buf)[NPF]) {
+  auto store_plane = [&](int slot, const RawPlane& buf) {
     unsigned short* pl = ring + (size_t)slot * plane_elems;
 #pragma unroll
     for (int k = 0; k < NPF; ++k) {
       const int it = threadIdx.x + k * nthr;
-      if (it < plane_items) *(unsigned*)(pl + (size_t)it * CLP) = buf[k].x;
+      const unsigned v = (buf.ok >> k) & 1u
+                             ? (unsigned)f2bf((float)buf.zv[k] * sc) | ((unsigned)f2bf(buf.dv[k]) << 16)
+                             : 0u;
+      if (it < plane_items) *(unsigned*)(pl + (size_t)it * CLP) = v;
     }
   };
   // weights [16 cout][3 ty][KCT * 32], lane (g, r) holds cout r, k = c * 32 + g * 8 ..
@@ -756,13 +768,33 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
     }
   }
   const int xl = wave * 16 + r;
-  u32x4 pf[NPF];
+  // epilogue parameters, loaded before the sweep so that no load of the
+  // epilogue has to wait behind the input loads in flight
+  const int co = g * 4;
+  float bia[4], whv[4] = {0.f, 0.f, 0.f, 0.f}, bhv = 0.f, fsc = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bia[j] = p.bias[co + j];
+  if (EPI) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) whv[j] = p.wh[co + j];
+    bhv = p.bh[0];
+    const double a = p.alpha_override > 0.0 ? p.alpha_override : p.alpha[bt];
+    fsc = (float)(p.scale[bt] / a);
+  }
+  bf16* Y = EPI ? nullptr : p.y + (int64_t)bt * nv * 16;
+  Tv* zo = EPI ? (Tv*)p.zout + p.off[bt] : nullptr;
+  const int relu = p.relu;
+  // first layer: qa holds the raw values of planes z0 + 1, z0 + 3, ..., qb
+  // those of z0 + 2, z0 + 4, ...; plane p is requested at the end of the step
+  // of plane p - 3 and enters the ring at the start of the step of plane p - 1
+  RawPlane qa, qb;
   if (IN) {
-    load_plane(z0 - 1, pf);
-    store_plane(0, pf);
-    load_plane(z0, pf);
-    store_plane(1, pf);
-    load_plane(z0 + 1, pf);
+    load_plane(z0 - 1, qa);
+    store_plane(0, qa);
+    load_plane(z0, qa);
+    store_plane(1, qa);
+    load_plane(z0 + 1, qa);
+    load_plane(z0 + 2, qb);
   } else {
     dma_plane(z0 - 1, 0);
     dma_plane(z0, 1);
@@ -770,13 +802,17 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
   }
-  for (int z = z0; z < zend; ++z) {
+  auto plane_step = [&](int z, RawPlane& cur) __attribute__((always_inline)) {
     // ring slots: plane z - 1 at s0, z at s0 + 1, z + 1 at s0 + 2 (mod NR)
     const int s0 = (z - z0) % NR;
     if (IN) {
-      store_plane((s0 + 2) % NR, pf);
+      store_plane((s0 + 2) % NR, cur);
       __syncthreads();
-      if (z + 1 < zend) load_plane(z + 2, pf);
+      // plane z + 3 into the register set just emptied (on every step, also
+      // past the sweep's last plane, where the values are never used); the
+      // epilogue's stores are unconditional too, so the wait before the next
+      // conversion of this set leaves everything issued after it in flight
+      load_plane(z + 3, cur);
     } else {
       if (z + 1 < zend) dma_plane(z + 2, (s0 + 3) % NR);
     }
@@ -828,46 +864,62 @@ __global__ void __launch_bounds__(256) k_conv16_rows(MfmaArgs p, RowsGrid q) {
     }
     // epilogue for plane z
     if (EPI == 0) {
-      bf16* Y = p.y + (int64_t)bt * nv * 16;
-      const int co = g * 4;
+      // rows past the grid repeat the store of the last row inside it (the
+      // same value to the same place), so that every step issues MB stores
+      uint2 pkl = {0u, 0u};
+      int64_t vl = 0;
 #pragma unroll
       for (int m = 0; m < MB; ++m) {
         const int y = y0 + m;
-        if (y >= q.yhi) continue;
         const int64_t v = ((int64_t)z * n + y) * n + x0 + xl;
-        float y0v = acc[m][0] + p.bias[co], y1v = acc[m][1] + p.bias[co + 1];
-        float y2v = acc[m][2] + p.bias[co + 2], y3v = acc[m][3] + p.bias[co + 3];
-        if (p.relu) {
+        float y0v = acc[m][0] + bia[0], y1v = acc[m][1] + bia[1];
+        float y2v = acc[m][2] + bia[2], y3v = acc[m][3] + bia[3];
+        if (relu) {
           y0v = fmaxf(y0v, 0.f); y1v = fmaxf(y1v, 0.f); y2v = fmaxf(y2v, 0.f); y3v = fmaxf(y3v, 0.f);
         }
         uint2 pk;
         pk.x = (unsigned)f2bf(y0v) | ((unsigned)f2bf(y1v) << 16);
         pk.y = (unsigned)f2bf(y2v) | ((unsigned)f2bf(y3v) << 16);
-        *(uint2*)(Y + v * 16 + co) = pk;
+        const bool in = m == 0 || y < q.yhi;  // row y0 is always inside
+        pkl.x = in ? pk.x : pkl.x;
+        pkl.y = in ? pk.y : pkl.y;
+        vl = in ? v : vl;
+        *(uint2*)(Y + vl * 16 + co) = pkl;
       }
     } else {
-      const double a = p.alpha_override > 0.0 ? p.alpha_override : p.alpha[bt];
-      const float f = (float)(p.scale[bt] / a);
-      Tv* zo = (Tv*)p.zout + p.off[bt];
-      const int co = g * 4;
 #pragma unroll
       for (int m = 0; m < MB; ++m) {
         float h = 0.f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float yj = __bfloat162float(__float2bfloat16(fmaxf(acc[m][j] + p.bias[co + j], 0.f)));
-          h = fmaf(p.wh[co + j], yj, h);
+          const float yj = __bfloat162float(__float2bfloat16(fmaxf(acc[m][j] + bia[j], 0.f)));
+          h = fmaf(whv[j], yj, h);
         }
         h += __shfl_xor(h, 16, 64);
         h += __shfl_xor(h, 32, 64);
         const int y = y0 + m;
         // Dirichlet nodes keep the value set before the network runs
         if (g == 0 && y < q.yhi && y > 0 && y < n - 1 && x0 + xl > 0 && z > 0 && z < n - 1)
-          zo[((int64_t)z * n + y) * n + x0 + xl] = (Tv)(f * (h + p.bh[0]));
+          zo[((int64_t)z * n + y) * n + x0 + xl] = (Tv)(fsc * (h + bhv));
       }
     }
     if (!IN) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
+  };
+  if (IN) {
+    // the first step, then pairs of steps: every path into a step has issued
+    // the same loads and stores since that step's register set was requested,
+    // so the compiler's wait for the set leaves the newer ones in flight
+    // (the grid gives every workgroup at least one plane: z0 < zend)
+    int z = z0;
+    plane_step(z++, qa);
+    for (; z + 1 < zend; z += 2) {
+      plane_step(z, qb);
+      plane_step(z + 1, qa);
+    }
+    if (z < zend) plane_step(z, qb);
+  } else {
+    for (int z = z0; z < zend; ++z) plane_step(z, qa);
   }
 }
 
@@ -1394,8 +1446,9 @@ bool launch_zb16(const MfmaArgs& a, int batch, hipStream_t stream, int target, i
 // computed.  XB * KG waves: wave (xq, kg) owns x block xq and the K chunks
 // [kg KPG, (kg + 1) KPG) for all NB = COUT / 16 output blocks, with those
 // weights in registers; as in the 16-channel kernels one input fragment (row
-// j) serves the output rows j - 2 .. j.  The KG partial sums meet in LDS and
-// each wave finishes (sum, bias, ReLU, store) every KG-th output fragment.
+// j) serves the output rows j - 2 .. j (chunk slots past the K range are
+// skipped).  The KG partial sums meet in LDS and each wave finishes (sum,
+// bias, ReLU, store) every KG-th output fragment.
 template <int CA, int CB, int COUT, int MB, int KG, int NPF>
 __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
   constexpr int CIN = CA + CB;
@@ -1405,6 +1458,8 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
   constexpr int NB = COUT / 16;
   constexpr int KCT = RowsK<CIN, 0>::KCT;
   constexpr int KPG = (KCT + KG - 1) / KG;   // chunk slots per wave
+  // chunks of the one group with fewer than KPG but more than none (0: no such group)
+  constexpr int KREM = KCT % KPG;
   constexpr int YW = MB + 2;
   constexpr int NF = MB * NB;                // output fragments per x block
   constexpr int CPA = CA / 8;
@@ -1432,6 +1487,10 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
   const int g = lane >> 4, r = lane & 15;
   const int xq = wave % xbn, kg = wave / xbn;
   f32x4* red = (f32x4*)(ring + (size_t)3 * plane_elems);  // [KG][xbn][NF][64]
+  // the bias in LDS: a global load in the epilogue would wait for the plane
+  // loads in flight
+  float* sbias = (float*)(red + (size_t)KG * xbn * NF * 64);
+  for (int i = threadIdx.x; i < COUT; i += nthr) sbias[i] = p.bias[i];
   const bf16* A = p.a + (int64_t)bt * nv * CA;
   const bf16* B = CB ? p.b + (int64_t)bt * nv * CB : nullptr;
   auto load_plane = [&](int gz, u32x4 (&buf)[NPF]) {
@@ -1488,7 +1547,7 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
       lofs[i] = (lok[i] ? pp % 3 : 0) * CLP + ci;
     }
   }
-  const int nch = min(KPG, KCT - cb);  // chunks of this wave (wave-uniform)
+  const int nch = max(0, min(KPG, KCT - cb));  // chunks of this wave (wave-uniform)
   const int xl = xq * 16 + r;
   u32x4 pf[NPF];
   load_plane(z0 - 1, pf);
@@ -1525,20 +1584,27 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
           }
         }
     };
-    if (nch > 0) {
+    // the chunk loop with a compile-time count (a branch per chunk would make
+    // each MFMA wait for the fragment loads issued after its own)
+    auto run = [&](auto nchc) {
+      constexpr int NCH = decltype(nchc)::value;
       bf16x8 xa[MB + 2], xb[MB + 2];
       fetch(0, xa);
 #pragma unroll
-      for (int i = 0; i < KPG; i += 2) {
-        if (i + 1 < KPG) fetch(i + 1, xb);
+      for (int i = 0; i < NCH; i += 2) {
+        if (i + 1 < NCH) fetch(i + 1, xb);
         __builtin_amdgcn_sched_barrier(0);
         mma(i, xa);
         __builtin_amdgcn_sched_barrier(0);
-        if (i + 2 < KPG) fetch(i + 2, xa);
+        if (i + 2 < NCH) fetch(i + 2, xa);
         __builtin_amdgcn_sched_barrier(0);
-        if (i + 1 < KPG) mma(i + 1, xb);
+        if (i + 1 < NCH) mma(i + 1, xb);
         __builtin_amdgcn_sched_barrier(0);
       }
+    };
+    if (nch == KPG) run(std::integral_constant<int, KPG>{});
+    else if constexpr (KREM > 0) {
+      if (nch == KREM) run(std::integral_constant<int, KREM>{});
     }
     // partial sums to LDS: red[kg][xq][f][lane], f = m * NB + nb
 #pragma unroll
@@ -1559,8 +1625,8 @@ __global__ void __launch_bounds__(512) k_convw(MfmaArgs p, RowsGrid q) {
       const int y = y0 + m;
       if (y >= q.yhi) continue;
       const int co = nb * 16 + g * 4;
-      float y0v = sum[0] + p.bias[co], y1v = sum[1] + p.bias[co + 1];
-      float y2v = sum[2] + p.bias[co + 2], y3v = sum[3] + p.bias[co + 3];
+      float y0v = sum[0] + sbias[co], y1v = sum[1] + sbias[co + 1];
+      float y2v = sum[2] + sbias[co + 2], y3v = sum[3] + sbias[co + 3];
       if (p.relu) {
         y0v = fmaxf(y0v, 0.f); y1v = fmaxf(y1v, 0.f); y2v = fmaxf(y2v, 0.f); y3v = fmaxf(y3v, 0.f);
       }
@@ -1845,7 +1911,8 @@ void launch_convw(const MfmaArgs& a, int batch, hipStream_t stream, int target =
   while (xb % xbw) --xbw;
   const int nxs = xb / xbw;
   const int xw = 16 * xbw + 2;
-  const size_t lds = 3 * T::plane_bytes(MB, xw - 1) + (size_t)KG * xbw * NF * 1024;
+  // ring, partial sums, bias
+  const size_t lds = 3 * T::plane_bytes(MB, xw - 1) + (size_t)KG * xbw * NF * 1024 + 256;
   const bool fits = (n - 1) % 16 == 0 && xb >= 1 && xbw * KG <= 8 && lds <= 160 * 1024 &&
                     (MB + 2) * xw * T::CPV <= NPF * xbw * KG * 64;
   if (!fits) {
@@ -2143,12 +2210,13 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
     case 3: {                                                             // L1b
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_l1b;
+      a.zero16 = mfma_extra(c).zeros;
       const int t = sweep_target(c, 3, 1024);
       const int xm = c.tile_xb[3];
-      if (c.tile_mb[3] == 2) launch_convw<32, 0, 32, 2, 4, 2>(a, batch, stream, t, xm);
-      else if (c.tile_mb[3] == 4) launch_convw<32, 0, 32, 4, 4, 2>(a, batch, stream, t, xm);
-      else if (c.tile_mb[3] == 6) launch_convw<32, 0, 32, 6, 4, 3>(a, batch, stream, t, xm);
-      else launch_convw<32, 0, 32, 3, 4, 2>(a, batch, stream, t, xm);
+      if (c.tile_mb[3] == 2) launch_convw<32, 0, 32, 2, 3, 2>(a, batch, stream, t, xm);
+      else if (c.tile_mb[3] == 4) launch_convw<32, 0, 32, 4, 3, 3>(a, batch, stream, t, xm);
+      else if (c.tile_mb[3] == 6) launch_convw<32, 0, 32, 6, 3, 3>(a, batch, stream, t, xm);
+      else launch_convw<32, 0, 32, 3, 3, 2>(a, batch, stream, t, xm);
       break;
     }
     case 4:  // L2a
@@ -2159,6 +2227,7 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
     case 5: {                                                             // L2b
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_l2b;
+      a.zero16 = mfma_extra(c).zeros;
       launch_convw<64, 0, 64, 2, 8, 2>(a, batch, stream, sweep_target(c, 5, kSweepBlocksL2b));
       break;
     }
@@ -2169,6 +2238,7 @@ void conv_mfma_layer(const ConvP& p, int kind, int batch, int layer, CnnState& c
     case 7: {                                                             // D1
       MfmaArgs a = args_from(p, w);
       a.wrows = mfma_extra(c).rows_d1;
+      a.zero16 = mfma_extra(c).zeros;
       const int t = sweep_target(c, 7, 1024);
       if (c.tile_mb[7] == 2) launch_convw<32, 32, 32, 2, 4, 3>(a, batch, stream, t, c.tile_xb[7]);
       else launch_convw<32, 32, 32, 3, 4, 3>(a, batch, stream, t, c.tile_xb[7]);
