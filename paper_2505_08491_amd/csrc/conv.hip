@@ -22,6 +22,7 @@ constexpr int BS = 256;
 
 __device__ __forceinline__ float ld(const float* p) { return *p; }
 __device__ __forceinline__ float ld(const bf16* p) { return __bfloat162float(*p); }
+typedef float f32x4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void st_(float* p, float v) { *p = v; }
 __device__ __forceinline__ void st_(bf16* p, float v) { *p = __float2bfloat16(v); }
 
@@ -205,105 +206,297 @@ __global__ void k_relu_mask(float* __restrict__ g, const void* __restrict__ out,
   if (!(o > 0.0f)) g[k] = 0.0f;
 }
 
-// Weight gradient dW[co][t][ci] = sum over batch and voxels of dz[p][co] * x_in(p, t)[ci]
-// for one 16x16 (co, ci) tile and one tap per block; the voxel range is split
-// over blockIdx.z and the partial tiles are summed in a second kernel.
-template <typename Tin, int MODE>
-__global__ void __launch_bounds__(BS) k_dw(const float* __restrict__ dz, int cout, const void* xa_, int ca, int lda,
-                                           const void* xb_, int cb, int ldb, int n_in, int n_out, int batch,
-                                           int64_t a_bs, int64_t b_bs, float* __restrict__ part, int nsplit) {
-  __shared__ float sdz[64][17];
-  __shared__ float sx[64][17];
-  const int ntap = MODE == KIND_PT ? 1 : 27;
-  const int t = blockIdx.x % ntap;
-  const int tile = blockIdx.x / ntap;
+// Weight gradient on v_mfma_f32_16x16x4_f32 (FP32 products and sums) for
+// layers whose channel counts are multiples of 16.  An element is an output
+// voxel of one instance (an input voxel for the transposed convolution, whose
+// output o = 2 i + t - 1 then depends on the tap).  A wave owns NTG tap
+// groups (the taps with one tz: 9 each; the 1x1 layer has one tap), NBO x NBI
+// tiles of 16 x 16 (co, ci) and a range of elements.  Per step of 4 elements
+// lane l holds element l / 16 and channel l % 16: the operand fixed over the
+// taps (dz for the stride-1/2 and 1x1 layers, x for the transposed one) is
+// loaded once, the other per tap, and the MFMA of tap t and tile (bo, bi) adds
+// D[co][ci] += sum over the 4 elements of dz[e][co] x[in(e, t)][ci] (lane l
+// ends with co = 4 (l / 16) .. + 3, ci = l % 16).  The element's input
+// coordinates and their bounds are worked out once per step; a tap adds a
+// constant offset.  Partial tiles go to part [split][cout][27 or 1][cin] and
+// are summed in a second kernel.
+template <typename Tin, int MODE, int NTG, int NBO, int NBI>
+__global__ void __launch_bounds__(64) k_dw_m(const float* __restrict__ dz, int cout, const void* xa_, int ca,
+                                             int lda, const void* xb_, int cb, int ldb, int n_in, int n_out,
+                                             int batch, int64_t a_bs, int64_t b_bs, float* __restrict__ part,
+                                             int nsplit) {
+  constexpr int TPG = MODE == KIND_PT ? 1 : 9;   // taps per group
+  constexpr int NTAP = MODE == KIND_PT ? 1 : 27;
+  constexpr int NT = NTG * TPG;                  // taps of this wave
   const int cin = ca + cb;
-  const int nci_t = (cin + 15) / 16;
-  const int co0 = (tile / nci_t) * 16, ci0 = (tile % nci_t) * 16;
+  const int nbi = cin / (16 * NBI);
+  const int nwt = (cout / (16 * NBO)) * nbi;     // tile groups
+  const int tgw = blockIdx.x / nwt, tl = blockIdx.x - tgw * nwt;
+  const int co0 = (tl / nbi) * 16 * NBO, ci0 = (tl % nbi) * 16 * NBI;
+  const int tz0 = tgw * NTG;                     // first tz of this wave
   const int split = blockIdx.z;
-  const int tz = t / 9, ty = (t / 3) % 3, tx = t % 3;
-  const int64_t nvo = (int64_t)n_out * n_out * n_out;
-  // for the transposed convolution iterate over input voxels (o = 2 i + t - 1)
-  const int64_t nit = (MODE == KIND_T2) ? (int64_t)n_in * n_in * n_in : nvo;
-  const int64_t total = nit * batch;
-  const int64_t per = (total + nsplit - 1) / nsplit;
-  const int64_t e0 = (int64_t)split * per, e1 = min(total, e0 + per);
-  const int tco = threadIdx.x / 16, tci = threadIdx.x % 16;
-  const Tin* xa = (const Tin*)xa_;
-  const Tin* xb = (const Tin*)xb_;
-  float acc = 0.0f;
-  for (int64_t base = e0; base < e1; base += 64) {
-    // stage 64 (dz, x) voxel pairs
-    for (int q = threadIdx.x; q < 64 * 16; q += BS) {
-      const int vv = q / 16, c = q % 16;
-      const int64_t e = base + vv;
-      float dv = 0.0f, xv = 0.0f;
-      if (e < e1) {
-        const int bt = (int)(e / nit);
-        const int64_t u = e % nit;
-        int64_t vo = -1, vi = -1;
-        if (MODE == KIND_T2) {
-          const int ix = (int)(u % n_in), iy = (int)((u / n_in) % n_in), iz = (int)(u / ((int64_t)n_in * n_in));
-          const int ox = 2 * ix + tx - 1, oy = 2 * iy + ty - 1, oz = 2 * iz + tz - 1;
-          if (ox >= 0 && oy >= 0 && oz >= 0 && ox < n_out && oy < n_out && oz < n_out) {
-            vo = ((int64_t)oz * n_out + oy) * n_out + ox;
-            vi = u;
-          }
-        } else {
-          const int ox = (int)(u % n_out), oy = (int)((u / n_out) % n_out), oz = (int)(u / ((int64_t)n_out * n_out));
-          int ix, iy, iz;
-          if (MODE == KIND_PT) { ix = ox; iy = oy; iz = oz; }
-          else {
-            const int s = MODE == KIND_S2 ? 2 : 1;
-            ix = s * ox + tx - 1; iy = s * oy + ty - 1; iz = s * oz + tz - 1;
-          }
-          if (ix >= 0 && iy >= 0 && iz >= 0 && ix < n_in && iy < n_in && iz < n_in) {
-            vo = u;
-            vi = ((int64_t)iz * n_in + iy) * n_in + ix;
-          }
-        }
-        if (vo >= 0) {
-          const int co = co0 + c, ci = ci0 + c;
-          if (co < cout) dv = dz[((int64_t)bt * nvo + vo) * cout + co];
-          if (ci < ca) xv = ld(xa + (int64_t)bt * a_bs + vi * lda + ci);
-          else if (ci < cin) xv = ld(xb + (int64_t)bt * b_bs + vi * ldb + (ci - ca));
+  const int lane = threadIdx.x;
+  const int ke = lane >> 4, c = lane & 15;
+  const int nvo = n_out * n_out * n_out, nvi = n_in * n_in * n_in;
+  const int nit = MODE == KIND_T2 ? nvi : nvo;   // elements per instance
+  const int total = nit * batch;
+  const int per = ((total + nsplit - 1) / nsplit + 7) & ~7;
+  const int e0 = split * per, e1 = min(total, e0 + per);
+  // the input channel of this lane in each ci tile (a 16-channel tile lies in one source)
+  const Tin* xs[NBI];
+  int xl[NBI];
+  int64_t xbsv[NBI];
+#pragma unroll
+  for (int bi = 0; bi < NBI; ++bi) {
+    const int cib = ci0 + 16 * bi;
+    const bool in_a = cib < ca;
+    xs[bi] = (const Tin*)(in_a ? xa_ : xb_) + (in_a ? cib : cib - ca) + c;
+    xl[bi] = in_a ? lda : ldb;
+    xbsv[bi] = in_a ? a_bs : b_bs;
+  }
+  const float* dzc = dz + co0 + c;
+  f32x4v acc[NT][NBO][NBI];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int bo = 0; bo < NBO; ++bo)
+#pragma unroll
+      for (int bi = 0; bi < NBI; ++bi) acc[t][bo][bi] = f32x4v{0.f, 0.f, 0.f, 0.f};
+  // one step of 4 elements: raw operands as loaded (every load is issued, at a
+  // valid address; entries outside the grid or the range are zeroed by the
+  // mask when the MFMAs use them), so that the loads of the next step stay in
+  // flight while this step's MFMAs run
+  constexpr bool T2 = MODE == KIND_T2;
+  // x as stored (BF16 bits or FP32): converted only when used, so that no
+  // instruction waits for a load before the MFMAs need it
+  typedef typename std::conditional<std::is_same<Tin, bf16>::value, unsigned short, float>::type XRaw;
+  auto xf = [](XRaw r) -> float {
+    if constexpr (std::is_same<XRaw, float>::value) return r;
+    else return __uint_as_float((unsigned)r << 16);
+  };
+  struct Step {
+    float d[T2 ? NT : 1][NBO];   // dz: per tap (transposed layer) or per element
+    XRaw x[T2 ? 1 : NT][NBI];    // x: per element (transposed layer) or per tap
+    unsigned ok;                 // bit t: tap t inside; bit 31: element inside
+  };
+  auto load = [&](int eb, Step& st) {
+    const int e = eb + ke;
+    const bool eok = e < e1;
+    const int ee = eok ? e : e0;
+    const int bt = ee / nit, u = ee - bt * nit;
+    const float* dzb = dzc + (int64_t)bt * nvo * cout;
+    unsigned ok = eok ? 0x80000000u : 0u;
+    if constexpr (T2) {
+      const int ix = u % n_in, iy = (u / n_in) % n_in, iz = u / (n_in * n_in);
+#pragma unroll
+      for (int bi = 0; bi < NBI; ++bi) st.x[0][bi] = *(const XRaw*)(xs[bi] + (int64_t)bt * xbsv[bi] + (int64_t)u * xl[bi]);
+      const int ox0 = 2 * ix - 1, oy0 = 2 * iy - 1, oz0 = 2 * iz - 1;
+      const int obase = (oz0 * n_out + oy0) * n_out + ox0;
+      unsigned bx = 0, by = 0, bz = 0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        bx |= (ox0 + d >= 0 && ox0 + d < n_out) ? 1u << d : 0u;
+        by |= (oy0 + d >= 0 && oy0 + d < n_out) ? 1u << d : 0u;
+        bz |= (oz0 + d >= 0 && oz0 + d < n_out) ? 1u << d : 0u;
+      }
+#pragma unroll
+      for (int g = 0; g < NTG; ++g) {
+        const int tz = tz0 + g;
+#pragma unroll
+        for (int t9 = 0; t9 < 9; ++t9) {
+          const int ty = t9 / 3, tx = t9 % 3;
+          const bool in = (bz >> tz) & (by >> ty) & (bx >> tx) & 1u;
+          const int off = in ? obase + (tz * n_out + ty) * n_out + tx : 0;
+          ok |= in ? 1u << (g * 9 + t9) : 0u;
+#pragma unroll
+          for (int bo = 0; bo < NBO; ++bo) st.d[g * 9 + t9][bo] = dzb[(int64_t)off * cout + 16 * bo];
         }
       }
-      sdz[vv][c] = dv;
-      sx[vv][c] = xv;
+    } else {
+      const int ox = u % n_out, oy = (u / n_out) % n_out, oz = u / (n_out * n_out);
+#pragma unroll
+      for (int bo = 0; bo < NBO; ++bo) st.d[0][bo] = dzb[(int64_t)u * cout + 16 * bo];
+      constexpr int S = MODE == KIND_S2 ? 2 : 1;
+      constexpr int SH = MODE == KIND_PT ? 0 : 1;  // tap offset of the first tap
+      const int ix0 = S * ox - SH, iy0 = S * oy - SH, iz0 = S * oz - SH;
+      const int ibase = (iz0 * n_in + iy0) * n_in + ix0;
+      unsigned bx = 0, by = 0, bz = 0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        bx |= (ix0 + d >= 0 && ix0 + d < n_in) ? 1u << d : 0u;
+        by |= (iy0 + d >= 0 && iy0 + d < n_in) ? 1u << d : 0u;
+        bz |= (iz0 + d >= 0 && iz0 + d < n_in) ? 1u << d : 0u;
+      }
+#pragma unroll
+      for (int g = 0; g < NTG; ++g) {
+        const int tz = tz0 + g;
+#pragma unroll
+        for (int t9 = 0; t9 < TPG; ++t9) {
+          const int ty = t9 / 3, tx = t9 % 3;
+          const bool in = (bz >> tz) & (by >> ty) & (bx >> tx) & 1u;
+          const int off = in ? ibase + (tz * n_in + ty) * n_in + tx : 0;
+          ok |= in ? 1u << (g * TPG + t9) : 0u;
+#pragma unroll
+          for (int bi = 0; bi < NBI; ++bi)
+            st.x[g * TPG + t9][bi] = *(const XRaw*)(xs[bi] + (int64_t)bt * xbsv[bi] + (int64_t)off * xl[bi]);
+        }
+      }
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int vv = 0; vv < 64; ++vv) acc = fmaf(sdz[vv][tco], sx[vv][tci], acc);
-    __syncthreads();
+    st.ok = ok;
+  };
+  auto mma = [&](const Step& st) {
+    const bool eok = st.ok >> 31;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const bool in = (st.ok >> t) & 1u;
+#pragma unroll
+      for (int bo = 0; bo < NBO; ++bo)
+#pragma unroll
+        for (int bi = 0; bi < NBI; ++bi) {
+          // the element's own operand is zeroed outside the range, the tap's outside the grid
+          const float a = T2 ? (in ? st.d[t][bo] : 0.0f) : (eok ? st.d[0][bo] : 0.0f);
+          const float b = T2 ? (eok ? xf(st.x[0][bi]) : 0.0f) : (in ? xf(st.x[t][bi]) : 0.0f);
+          acc[t][bo][bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t][bo][bi], 0, 0, 0);
+        }
+    }
+  };
+  // two steps per pass (the range is a multiple of 8 elements), each step's
+  // loads issued before the previous step's MFMAs
+  if (e0 < e1) {
+    Step sa, sb;
+    load(e0, sa);
+    for (int eb = e0; eb < e1; eb += 8) {
+      load(eb + 4, sb);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(sa);
+      __builtin_amdgcn_sched_barrier(0);
+      load(eb + 8, sa);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(sb);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
-  // part layout [split][cout][ntap][cin]
-  const int co = co0 + tco, ci = ci0 + tci;
-  if (co < cout && ci < cin) part[(((int64_t)split * cout + co) * ntap + t) * cin + ci] = acc;
+  // part layout [split][cout][ntap][cin]; lane: co = co0 + 16 bo + 4 ke + q, ci = ci0 + 16 bi + c
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int tap = tz0 * TPG + t;
+#pragma unroll
+    for (int bo = 0; bo < NBO; ++bo)
+#pragma unroll
+      for (int bi = 0; bi < NBI; ++bi)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int co = co0 + 16 * bo + 4 * ke + q;
+          part[(((int64_t)split * cout + co) * NTAP + tap) * cin + ci0 + 16 * bi + c] = acc[t][bo][bi][q];
+        }
+  }
 }
 
-__global__ void k_sum_splits(const float* __restrict__ part, float* __restrict__ out, int64_t n, int nsplit) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  float s = 0.0f;
-  for (int q = 0; q < nsplit; ++q) s += part[(int64_t)q * n + k];
-  out[k] = s;
+// Weight gradient of the first layer (2 FP32 input channels, 16 outputs,
+// stride 1) on the same MFMA: the 54 (tap, input channel) pairs are the
+// columns of four 16-wide tiles (column j: tap j / 2, channel j % 2; columns
+// 54 .. 63 stay zero), dz[e][co] the rows.
+__global__ void __launch_bounds__(64) k_dw_first(const float* __restrict__ dz, const float* __restrict__ x, int n,
+                                                 int batch, float* __restrict__ part, int nsplit) {
+  const int lane = threadIdx.x;
+  const int ke = lane >> 4, c = lane & 15;
+  const int nv = n * n * n, total = nv * batch;
+  const int per = ((total + nsplit - 1) / nsplit + 3) & ~3;
+  const int split = blockIdx.x;
+  const int e0 = split * per, e1 = min(total, e0 + per);
+  // this lane's column in each tile: tap offsets and channel
+  int toff[4], tci[4], tmask[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int j = 16 * nt + c, tap = j >> 1;
+    const int tz = tap / 9, ty = (tap / 3) % 3, tx = tap % 3;
+    toff[nt] = ((tz - 1) * n + (ty - 1)) * n + (tx - 1);
+    tci[nt] = j & 1;
+    tmask[nt] = tap < 27 ? (1 << (tz * 9 + ty * 3 + tx)) : 0;
+  }
+  f32x4v acc[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4v{0.f, 0.f, 0.f, 0.f};
+  for (int eb = e0; eb < e1; eb += 4) {
+    const int e = eb + ke;
+    const bool eok = e < e1;
+    const int ee = eok ? e : e0;
+    const int bt = ee / nv, u = ee - bt * nv;
+    const int ox = u % n, oy = (u / n) % n, oz = u / (n * n);
+    // taps inside the grid as a 27-bit mask
+    unsigned in = 0;
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+      const int ix = ox + t % 3 - 1, iy = oy + (t / 3) % 3 - 1, iz = oz + t / 9 - 1;
+      in |= (ix >= 0 && iy >= 0 && iz >= 0 && ix < n && iy < n && iz < n) ? 1u << t : 0u;
+    }
+    const float dv = eok ? dz[((int64_t)bt * nv + u) * 16 + c] : 0.0f;
+    const float* xb = x + (int64_t)bt * nv * 2;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const bool ok = eok && (in & (unsigned)tmask[nt]);
+      const float xv = ok ? xb[(int64_t)(u + toff[nt]) * 2 + tci[nt]] : 0.0f;
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(dv, xv, acc[nt], 0, 0, 0);
+    }
+  }
+  // part layout [split][16][27][2]
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int j = 16 * nt + c;
+    if (j >= 54) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int co = 4 * ke + q;
+      part[(((int64_t)split * 16 + co) * 27 + (j >> 1)) * 2 + (j & 1)] = acc[nt][q];
+    }
+  }
 }
 
-// db[co] = sum over batch and voxels of dz[.][co]; one block per channel.
-__global__ void __launch_bounds__(BS) k_db(const float* __restrict__ dz, int cout, int64_t nrows, float* __restrict__ db) {
-  __shared__ float sh[BS];
-  const int co = blockIdx.x;
+// Bias gradient (x = nullptr) or weight gradient of the 1x1 head with one
+// output (x: [rows][cin]), first pass: block b sums its row range per channel,
+// sum of dz[r][co] (bias; cout <= 64) or of dz[r] x[r][ci] (head), into part[b][.].
+template <typename Tin>
+__global__ void __launch_bounds__(256) k_rows_part(const float* __restrict__ dz, const Tin* __restrict__ x, int nch,
+                                                   int64_t nrows, float* __restrict__ part) {
+  __shared__ float sh[256];
+  const int64_t per = (nrows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(nrows, r0 + per);
+  const int ch = threadIdx.x % nch, rs = threadIdx.x / nch, nrs = 256 / nch;
   float s = 0.0f;
-  for (int64_t r = threadIdx.x; r < nrows; r += BS) s += dz[r * cout + co];
+  if (x) {
+    for (int64_t r = r0 + rs; r < r1; r += nrs) s = fmaf(dz[r], ld(x + r * nch + ch), s);
+  } else {
+    for (int64_t r = r0 + rs; r < r1; r += nrs) s += dz[r * nch + ch];
+  }
   sh[threadIdx.x] = s;
   __syncthreads();
-  for (int o = BS / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
+  if (threadIdx.x < nch) {
+    float t = 0.0f;
+    for (int k = 0; k < nrs; ++k) t += sh[k * nch + threadIdx.x];
+    part[(int64_t)blockIdx.x * nch + threadIdx.x] = t;
   }
-  if (threadIdx.x == 0) db[co] = sh[0];
 }
+
+// out[k] = sum over q of part[q][k] (q ascending per split lane, then the 8
+// lanes in order): 32 consecutive k per block, 8 split lanes.
+__global__ void __launch_bounds__(256) k_sum_parts(const float* __restrict__ part, float* __restrict__ out,
+                                                   int64_t n, int nsplit) {
+  __shared__ float sh[8][32];
+  const int kx = threadIdx.x & 31, sq = threadIdx.x >> 5;
+  const int64_t k = (int64_t)blockIdx.x * 32 + kx;
+  float s = 0.0f;
+  if (k < n)
+    for (int q = sq; q < nsplit; q += 8) s += part[(int64_t)q * n + k];
+  sh[sq][kx] = s;
+  __syncthreads();
+  if (sq == 0 && k < n) {
+    float t = sh[0][kx];
+    for (int j = 1; j < 8; ++j) t += sh[j][kx];
+    out[k] = t;
+  }
+}
+
+
 
 // ---------------------------------------------------------------- training objective
 
@@ -494,7 +687,6 @@ int64_t cnn_saved_bytes(int batch, int n, mdnp_dtype dtype) {
 
 // ---------------------------------------------------------------- FP32 convolutions on the matrix cores
 
-typedef float f32x4v __attribute__((ext_vector_type(4)));
 
 // FP32 implicit-GEMM convolution on v_mfma_f32_16x16x4_f32 (FP32 products and
 // sums): per output voxel block of 16 consecutive flattened voxels and per
@@ -1057,27 +1249,61 @@ static void backward_t(CnnState& c, const void* saved, const float* dy, float* d
     const int ca = s.in_b >= 0 ? L.cin / 2 : L.cin;
     const int cb = L.cin - ca;
     const bool in_fp32 = (s.in_a == 0);  // X is stored in FP32
-    const int ntiles = ((L.cout + 15) / 16) * ((L.cin + 15) / 16);
-    dim3 g((unsigned)(taps * ntiles), 1, nsplit);
-#define DW_LAUNCH(TIN, MODE)                                                                                   \
-  hipLaunchKernelGGL((k_dw<TIN, MODE>), g, dim3(BS), 0, stream, dz, L.cout, act[s.in_a], ca, ca,                \
-                     s.in_b >= 0 ? act[s.in_b] : nullptr, cb, cb, nn[lin], nn[lout], batch,                    \
-                     cube(nn[lin]) * ca, cube(nn[lin]) * cb, part, nsplit)
-    if (in_fp32) {
-      DW_LAUNCH(float, KIND_S1);
-    } else {
-      switch (L.kind) {
-        case KIND_S1: DW_LAUNCH(T, KIND_S1); break;
-        case KIND_S2: DW_LAUNCH(T, KIND_S2); break;
-        case KIND_T2: DW_LAUNCH(T, KIND_T2); break;
-        default: DW_LAUNCH(T, KIND_PT); break;
-      }
-    }
-#undef DW_LAUNCH
     const int64_t nw = (int64_t)L.cout * taps * L.cin;
-    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, stream, part,
-                       dw + c.w_off[s.layer], nw, nsplit);
-    hipLaunchKernelGGL(k_db, dim3(L.cout), dim3(BS), 0, stream, dz, L.cout, nout_vox, dw + c.b_off[s.layer]);
+    // about 4096 waves over element ranges (splits), within the partial buffer
+    auto splits = [&](int waves_per_split) {
+      return (int)std::max<int64_t>(1, std::min<int64_t>(4096 / waves_per_split, part_n / nw));
+    };
+    int ns;
+    if (in_fp32) {
+      // the first layer: 2 FP32 input channels, 16 outputs, stride 1
+      ns = splits(1);
+      hipLaunchKernelGGL(k_dw_first, dim3((unsigned)ns), dim3(64), 0, stream, dz, (const float*)act[0], n, batch,
+                         part, ns);
+    } else if (L.cout == 1) {
+      // the 1x1 head with one output: a weighted row sum
+      ns = 512;
+      hipLaunchKernelGGL((k_rows_part<T>), dim3((unsigned)ns), dim3(256), 0, stream, dz, (const T*)act[s.in_a],
+                         L.cin, nout_vox, part);
+    } else {
+      // channel counts in multiples of 16 on the matrix cores: the 9 taps of
+      // one tz per wave (the 1x1 layer: its one tap), and two 16-channel blocks
+      // of the operand loaded once per element where there are two (co for the
+      // stride-1/2 layers, ci for the transposed ones)
+      const bool t2 = L.kind == KIND_T2;
+      const int nbo = (!t2 && L.cout >= 32) ? 2 : 1, nbi = (t2 && L.cin >= 32) ? 2 : 1;
+      const int ntg = L.kind == KIND_PT ? 1 : 3;  // wave groups along tz
+      const int nwt = (L.cout / (16 * nbo)) * (L.cin / (16 * nbi));
+      ns = splits(ntg * nwt);
+      const dim3 g((unsigned)(ntg * nwt), 1, (unsigned)ns);
+#define DWM_ARGS                                                                                              \
+  g, dim3(64), 0, stream, dz, L.cout, act[s.in_a], ca, ca, s.in_b >= 0 ? act[s.in_b] : nullptr, cb, cb, nn[lin], \
+      nn[lout], batch, cube(nn[lin]) * ca, cube(nn[lin]) * cb, part, ns
+      if (t2) {
+        if (nbi == 2) hipLaunchKernelGGL((k_dw_m<T, KIND_T2, 1, 1, 2>), DWM_ARGS);
+        else hipLaunchKernelGGL((k_dw_m<T, KIND_T2, 1, 1, 1>), DWM_ARGS);
+      } else if (nbo == 2) {
+        switch (L.kind) {
+          case KIND_S1: hipLaunchKernelGGL((k_dw_m<T, KIND_S1, 1, 2, 1>), DWM_ARGS); break;
+          case KIND_S2: hipLaunchKernelGGL((k_dw_m<T, KIND_S2, 1, 2, 1>), DWM_ARGS); break;
+          default: hipLaunchKernelGGL((k_dw_m<T, KIND_PT, 1, 2, 1>), DWM_ARGS); break;
+        }
+      } else {
+        switch (L.kind) {
+          case KIND_S1: hipLaunchKernelGGL((k_dw_m<T, KIND_S1, 1, 1, 1>), DWM_ARGS); break;
+          case KIND_S2: hipLaunchKernelGGL((k_dw_m<T, KIND_S2, 1, 1, 1>), DWM_ARGS); break;
+          default: hipLaunchKernelGGL((k_dw_m<T, KIND_PT, 1, 1, 1>), DWM_ARGS); break;
+        }
+      }
+#undef DWM_ARGS
+    }
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((nw + 31) / 32)), dim3(256), 0, stream, part,
+                       dw + c.w_off[s.layer], nw, ns);
+    // bias gradient: 512 row ranges, then their sum (the partials reuse `part`)
+    hipLaunchKernelGGL((k_rows_part<float>), dim3(512), dim3(256), 0, stream, dz, (const float*)nullptr, L.cout,
+                       nout_vox, part);
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((L.cout + 31) / 32)), dim3(256), 0, stream, part,
+                       dw + c.b_off[s.layer], (int64_t)L.cout, 512);
     // data gradient: adjoint layer (input channels = cout, output channels = cin)
     if (s.layer == 0 && !dx) continue;
     const int flip = L.kind == KIND_S1 ? 1 : 0;
