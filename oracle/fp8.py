@@ -89,3 +89,77 @@ def quantize_weights(theta):
             wq[o] = round_e4m3(w[o] / sc) * sc
         out.append((wq, b.copy()))
     return cnn.flatten(out)
+
+
+# ---------------------------------------------------------------- E4M3 activations
+#
+# Further readings for the variant that also stores the network's activations
+# in E4M3 (again the paper fixes none of this):
+#   * every tensor a 3x3x3 layer reads is quantised: the input X and the
+#     output of each of the ten 3x3x3 layers (after its ReLU), each with one
+#     power-of-two scale per tensor: t -> round_e4m3(t / s) * s;
+#   * the two tensors stacked into one layer input share one scale (the
+#     up-sampled U1 with the skip L1b, U0 with L0b);
+#   * the 1x1 head reads the quantised D0 output and stays in full precision,
+#     as do the biases and the products and sums of every layer;
+#   * calibration: s is the smallest power of two with 2 amax / s <= 448, amax
+#     the largest magnitude of the tensor in the full-precision network on a
+#     sample input (for a stacked pair: over both tensors), leaving a factor two
+#     of headroom for inputs whose activations are larger than the sample's.
+
+ACT_NAMES = ("X", "L0a", "L0b", "L1a", "L1b", "L2a", "L2b", "U1", "D1", "U0", "D0")
+TIED = (("L1b", "U1"), ("L0b", "U0"))
+HEADROOM = 2.0
+
+
+def quantize_act(t, s):
+    """t -> E4M3 code * s for a tensor with scale s."""
+    return round_e4m3(np.asarray(t, dtype=np.float64) / s) * s
+
+
+def forward_fp8(theta_q, X, scales, quant=quantize_act):
+    """U(X) for one sample X [n, n, n, 2] with E4M3 activations: theta_q is
+    already on the per-channel E4M3 grid (`quantize_weights`), `scales` holds
+    one scale per name in ACT_NAMES; returns [n, n, n].  `quant(t, s)` is the
+    quantiser (replaceable, so that tests can check the wiring without it)."""
+    n = X.shape[0]
+    cnn.check_grid(n)
+    P = cnn.unflatten(np.asarray(theta_q, dtype=np.float64))
+    sc = dict(zip(ACT_NAMES, scales))
+    idx = {name: i for i, (name, *_r) in enumerate(cnn.LAYERS)}
+
+    def run(name, inp):
+        i = idx[name]
+        _, kind, _, _, relu = cnn.LAYERS[i]
+        z = cnn._apply(kind, inp, *P[i])
+        out = np.maximum(z, 0.0) if relu else z
+        return out if kind == "point" else quant(out, sc[name])
+
+    a = run("L0a", quant(X, sc["X"]))
+    s0 = run("L0b", a)
+    a = run("L1a", s0)
+    s1 = run("L1b", a)
+    a = run("L2a", s1)
+    a = run("L2b", a)
+    u1 = run("U1", a)
+    d1 = run("D1", np.concatenate([u1, s1], axis=-1))
+    u0 = run("U0", d1)
+    d0 = run("D0", np.concatenate([u0, s0], axis=-1))
+    return run("H", d0)[..., 0]
+
+
+def activation_scales(theta_q, Xs, headroom=HEADROOM):
+    """Calibrated scales (one per ACT_NAMES entry) from the full-precision
+    network on the sample inputs Xs (a list of [n, n, n, 2] arrays)."""
+    amax = dict.fromkeys(ACT_NAMES, 0.0)
+    for X in Xs:
+        _, cache = cnn.forward(np.asarray(theta_q, dtype=np.float64), X)
+        amax["X"] = max(amax["X"], float(np.max(np.abs(cache["X"]))))
+        for name in ACT_NAMES[1:]:
+            relu = next(r for (nm, _k, _ci, _co, r) in cnn.LAYERS if nm == name)
+            z = cache[name][1]
+            out = np.maximum(z, 0.0) if relu else z
+            amax[name] = max(amax[name], float(np.max(np.abs(out))))
+    for a, b in TIED:
+        amax[a] = amax[b] = max(amax[a], amax[b])
+    return [channel_scale(headroom * amax[name]) for name in ACT_NAMES]

@@ -61,3 +61,66 @@ def test_quantize_weights():
         # exact in BF16: the BF16 network computes with the E4M3 values themselves
         bf = torch.tensor(wq.ravel()).to(torch.bfloat16).to(torch.float64).numpy()
         assert np.array_equal(bf, wq.ravel())
+
+
+# ---------------------------------------------------------------- E4M3 activations
+
+def _net9():
+    th = cnn.init_params(3)
+    thq = fp8.quantize_weights(th)
+    X = np.random.default_rng(0).standard_normal((9, 9, 9, 2)) * 0.05
+    return thq, X
+
+
+def test_forward_fp8_without_rounding_is_the_network():
+    """With the quantiser replaced by the identity, the E4M3-activation
+    forward is exactly the full-precision network (wiring pin)."""
+    thq, X = _net9()
+    sc = fp8.activation_scales(thq, [X])
+    y_id = fp8.forward_fp8(thq, X, sc, quant=lambda t, s: t)
+    y = cnn.forward(thq, X)[0]
+    assert np.array_equal(y_id, y)
+
+
+def test_forward_fp8_quantises_every_read_tensor_with_its_scale():
+    """The quantiser is called once per tensor a 3x3x3 layer reads, in the
+    order X, L0a, ..., D0, each with its own scale."""
+    thq, X = _net9()
+    sc = [2.0 ** -(k + 1) for k in range(len(fp8.ACT_NAMES))]
+    seen = []
+
+    def rec(t, s):
+        seen.append(s)
+        return fp8.quantize_act(t, s)
+    fp8.forward_fp8(thq, X, sc, quant=rec)
+    assert seen == sc
+
+
+def test_activation_scales_rule():
+    """Scales are powers of two, the stacked pairs share one, and each is the
+    smallest with 2 amax / s <= 448 (amax from the full-precision network)."""
+    thq, X = _net9()
+    sc = dict(zip(fp8.ACT_NAMES, fp8.activation_scales(thq, [X])))
+    _, cache = cnn.forward(thq, X)
+    relu = {nm: r for (nm, _k, _ci, _co, r) in cnn.LAYERS}
+    amax = {"X": float(np.abs(X).max())}
+    for nm in fp8.ACT_NAMES[1:]:
+        z = cache[nm][1]
+        amax[nm] = float(np.abs(np.maximum(z, 0.0) if relu[nm] else z).max())
+    for a, b in fp8.TIED:
+        amax[a] = amax[b] = max(amax[a], amax[b])
+        assert sc[a] == sc[b]
+    for nm, s in sc.items():
+        k = np.log2(s)
+        assert k == np.round(k)
+        assert 2 * amax[nm] / s <= 448.0 < 2 * amax[nm] / (s / 2)
+
+
+def test_forward_fp8_error_bound():
+    """E4M3 activations and weights stay within the 1e-1 relative (2-norm)
+    error budget of an 8-bit network against the full-precision one."""
+    thq, X = _net9()
+    sc = fp8.activation_scales(thq, [X])
+    y8 = fp8.forward_fp8(thq, X, sc)
+    y = cnn.forward(thq, X)[0]
+    assert np.linalg.norm(y8 - y) / np.linalg.norm(y) <= 1e-1
