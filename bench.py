@@ -51,7 +51,7 @@ def parse():
                     help="inner FGMRES steps of the extra inner-solve run (0: skip it)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="time and fix the launch shapes (SpMV sweep, BF16 sweep layers) before the timed solves (0: defaults)")
-    ap.add_argument("--precision-runs", default="fp8,f32",
+    ap.add_argument("--precision-runs", default="fp8,fp8a,f32",
                     help="network dtypes also timed on the same workload (comma list of f32/bf16/fp8; empty: none)")
     ap.add_argument("--block3d", type=int, default=1,
                     help="also run the paper's 3D-block workload (Neumann, k = sigma = eps = 1e-3, FGMRES(20) to "
@@ -460,11 +460,14 @@ def main():
                   "converged_all": all(q["converged"] for q in stn),
                   "used_fallback": int(sum(q["used_fallback"] for q in stn)), "max_true_rel_res": max(rel_nd)}
 
-    # the same network in other arithmetic: FP32 (direct kernels) and E4M3
-    # weights with per-channel power-of-two scales on the BF16 kernels
+    # the same network in other arithmetic: FP32 (FP32 matrix cores), E4M3
+    # weights with per-channel power-of-two scales on the BF16 kernels (fp8),
+    # and E4M3 weights and activations on the FP8 matrix cores (fp8a, its
+    # activation scales calibrated on the right-hand side)
     precision = {}
     for dt in [d for d in a.precision_runs.split(",") if d and d != a.cnn_dtype]:
         S.set_preconditioner("neural", weights=w, cnn_dtype=dt)
+        fp8_scales = S.fp8_calibrate(b.to(torch.float32)) if dt == "fp8a" else None
         Tp, stp = run(neural_opts, 1, 1)
         rel_p = true_rel()
         precision[dt] = {"solves_per_s": S.n_inst / Tp, "ms_per_solve": Tp * 1e3,
@@ -472,6 +475,8 @@ def main():
                          "converged_all": all(q["converged"] for q in stp),
                          "used_fallback": int(sum(q["used_fallback"] for q in stp)), "max_true_rel_res": max(rel_p),
                          "ms_per_apply": time_kernel(ctx, lambda: S.precond_apply(xs), 3)}
+        if fp8_scales:
+            precision[dt]["activation_scales"] = fp8_scales
 
     block3d = block3d_runs(ctx) if a.block3d else None
 

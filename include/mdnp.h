@@ -59,7 +59,7 @@ typedef enum {
                                  (the method without the network)                          */
 } mdnp_prec_kind;
 
-typedef enum { MDNP_F64 = 0, MDNP_F32 = 1, MDNP_BF16 = 2, MDNP_FP8E4M3 = 3 } mdnp_dtype;
+typedef enum { MDNP_F64 = 0, MDNP_F32 = 1, MDNP_BF16 = 2, MDNP_FP8E4M3 = 3, MDNP_FP8E4M3_ACT = 4 } mdnp_dtype;
 
 /* Condition on the faces of the unit cube for the 3D unknowns. */
 typedef enum {
@@ -175,12 +175,38 @@ mdnp_status mdnp_export_rhs(const mdnp_sys* sys, int32_t inst, double* F, double
  * one power-of-two scale per output channel (the smallest 2^k with
  * max|w| / 2^k <= 448; round to nearest, ties to even) and runs the network
  * with them on the BF16 kernels, where those values are exact: E4M3 weights,
- * BF16 activations, FP32 accumulation.  alpha <= 0 keeps each
+ * BF16 activations, FP32 accumulation.  MDNP_FP8E4M3_ACT rounds the weights
+ * the same way and also stores every tensor a 3x3x3 layer reads (the input
+ * and each 3x3x3 layer's output) as E4M3 codes of value / s, one power-of-two
+ * scale s per tensor, on the FP8 matrix cores (E4M3 x E4M3 products, FP32
+ * accumulation; the 1x1 head in FP32 on the E4M3 grid of D0's output); its
+ * scales must be set (mdnp_fp8_calibrate, mdnp_set_fp8_scales) before a solve
+ * or an application, else those return MDNP_E_STATE.  alpha <= 0 keeps each
  * instance's own alpha.  Requires n_cells divisible by 4.  Errors: MDNP_E_ARG,
  * MDNP_E_NONFINITE. */
 mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* sys, mdnp_prec_kind kind,
                                     const float* weights, int64_t n_weights, double alpha,
                                     mdnp_dtype cnn_dtype);
+
+/* Activation scales of the MDNP_FP8E4M3_ACT network (an 8-bit variant of the
+ * network of Section 4.2; the paper runs it in full precision): scales[11]
+ * (host) for X, L0a, L0b, L1a, L1b, L2a, L2b, U1, D1, U0, D0, each a positive
+ * power of two; the stacked pairs (L1b, U1) and (L0b, U0) need equal scales.
+ * Captured cycle graphs are rebuilt.  Errors: MDNP_E_ARG (count != 11, a scale
+ * not a power of two, a pair unequal), MDNP_E_STATE (no MDNP_FP8E4M3_ACT
+ * network set). */
+mdnp_status mdnp_set_fp8_scales(mdnp_ctx* ctx, mdnp_sys* sys, const float* scales, int32_t count);
+/* The scales in use (0 where not set), scales[11] host. */
+mdnp_status mdnp_get_fp8_scales(mdnp_ctx* ctx, const mdnp_sys* sys, float* scales, int32_t count);
+/* Calibrate the scales on a sample: apply the preconditioner to the device
+ * vector d_v (the system's vector type and length, e.g. a right-hand side)
+ * with the network in FP32, take the largest magnitude of the network input
+ * and of every 3x3x3 layer output over all instances (a stacked pair: over
+ * both), and set each scale to the smallest power of two s with
+ * 2 amax / s <= 448.  Synchronises the stream.  Errors: MDNP_E_ARG,
+ * MDNP_E_STATE (as mdnp_set_fp8_scales), MDNP_E_NONFINITE (a non-finite
+ * activation), MDNP_E_OOM. */
+mdnp_status mdnp_fp8_calibrate(mdnp_ctx* ctx, mdnp_sys* sys, const void* d_v, void* hip_stream);
 
 /* Jacobi pre- and post-smoothing of the network's 3D solve (Section 5, "Effect
  * of pre- and post-smoothing"): with sweeps > 0 the MDNP_PREC_NEURAL

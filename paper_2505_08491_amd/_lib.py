@@ -17,7 +17,7 @@ MDNP_OK, MDNP_E_ARG, MDNP_E_HIP, MDNP_E_OOM, MDNP_E_GEOM, MDNP_E_NONFINITE, MDNP
 STATUS_NAMES = {0: "MDNP_OK", -1: "MDNP_E_ARG", -2: "MDNP_E_HIP", -3: "MDNP_E_OOM", -4: "MDNP_E_GEOM",
                 -5: "MDNP_E_NONFINITE", -6: "MDNP_E_STATE"}
 PREC = {"none": 0, "jacobi": 1, "neural": 2, "block_jacobi": 3}
-DTYPE = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
+DTYPE = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3, "fp8a": 4}
 
 
 class InstanceDesc(C.Structure):
@@ -66,6 +66,9 @@ SIGNATURES = [
     ("mdnp_spmv_repeat", C.c_int, [VP, VP, VP, VP, C.c_int, C.c_int32, VP]),
     ("mdnp_tree_solve", C.c_int, [VP, VP, VP, VP, VP]),
     ("mdnp_precond_apply", C.c_int, [VP, VP, VP, VP, VP]),
+    ("mdnp_set_fp8_scales", C.c_int, [VP, VP, VP, C.c_int32]),
+    ("mdnp_get_fp8_scales", C.c_int, [VP, VP, VP, C.c_int32]),
+    ("mdnp_fp8_calibrate", C.c_int, [VP, VP, VP, VP]),
     ("mdnp_cnn_forward", C.c_int, [VP, VP, VP, VP, VP, C.c_int32, C.c_int32, C.c_int, VP]),
     ("mdnp_cnn_saved_bytes", C.c_int64, [C.c_int32, C.c_int32, C.c_int]),
     ("mdnp_cnn_backward", C.c_int, [VP, VP, VP, VP, VP, VP, C.c_int32, C.c_int32, C.c_int, VP]),

@@ -243,6 +243,23 @@ class System:
                                                     w.ctypes.data if w is not None else None, n, alpha,
                                                     DTYPE[cnn_dtype]))
 
+    def set_fp8_scales(self, scales):
+        """Activation scales of the cnn_dtype "fp8a" network (X, L0a, L0b, L1a,
+        L1b, L2a, L2b, U1, D1, U0, D0; powers of two)."""
+        a = np.ascontiguousarray(np.asarray(scales, dtype=np.float32))
+        self.ctx._check(lib.mdnp_set_fp8_scales(self.ctx.h, self.h, a.ctypes.data, a.size))
+
+    def fp8_scales(self):
+        out = (C.c_float * 11)()
+        self.ctx._check(lib.mdnp_get_fp8_scales(self.ctx.h, self.h, out, 11))
+        return list(out)
+
+    def fp8_calibrate(self, v: torch.Tensor):
+        """Set the "fp8a" activation scales from the FP32 network on the
+        preconditioner input of v (a device vector of the system's type)."""
+        self.ctx.run(lib.mdnp_fp8_calibrate, self.ctx.h, self.h, _ptr(v), _stream(self.ctx.stream))
+        return self.fp8_scales()
+
     def autotune(self):
         """Time and fix the launch shapes: the z split / M blocks of each BF16
         layer ([0..10], by layer), the SpMV stencil sweep's z split ([11]) and

@@ -725,8 +725,9 @@ extern "C" mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* s, mdnp_
       np += (int64_t)kLayers[l].cout * taps * kLayers[l].cin + kLayers[l].cout;
     }
     if (n_weights != np) fail(MDNP_E_ARG, "expected " + std::to_string(np) + " weights");
-    if (cnn_dtype != MDNP_F32 && cnn_dtype != MDNP_BF16 && cnn_dtype != MDNP_FP8E4M3)
-      fail(MDNP_E_ARG, "cnn_dtype must be MDNP_F32, MDNP_BF16 or MDNP_FP8E4M3");
+    if (cnn_dtype != MDNP_F32 && cnn_dtype != MDNP_BF16 && cnn_dtype != MDNP_FP8E4M3 &&
+        cnn_dtype != MDNP_FP8E4M3_ACT)
+      fail(MDNP_E_ARG, "cnn_dtype must be MDNP_F32, MDNP_BF16, MDNP_FP8E4M3 or MDNP_FP8E4M3_ACT");
     if (s->n_cells % 4 != 0 || s->n_cells < 4) fail(MDNP_E_ARG, "the network needs n_cells divisible by 4");
     for (int64_t k = 0; k < n_weights; ++k)
       if (!std::isfinite(weights[k])) fail(MDNP_E_NONFINITE, "non-finite network weight");
@@ -735,15 +736,20 @@ extern "C" mdnp_status mdnp_set_preconditioner(mdnp_ctx* ctx, mdnp_sys* s, mdnp_
     HIPCHK(hipMemcpyAsync(c.w_own, weights, sizeof(float) * np, hipMemcpyHostToDevice, ctx->stream));
     c.w = c.w_own;
     // FP8: the weights become E4M3 codes x per-channel powers of two, exact in
-    // BF16, and the network runs on the BF16 kernels
-    c.fp8_weights = cnn_dtype == MDNP_FP8E4M3;
-    if (c.fp8_weights) {
-      cnn_quantize_e4m3(c.w_own, ctx->stream);
-      cnn_dtype = MDNP_BF16;
-    }
+    // BF16; MDNP_FP8E4M3 runs the network with them on the BF16 kernels,
+    // MDNP_FP8E4M3_ACT on the FP8 kernels with E4M3 activations
+    c.fp8_weights = cnn_dtype == MDNP_FP8E4M3 || cnn_dtype == MDNP_FP8E4M3_ACT;
+    if (c.fp8_weights) cnn_quantize_e4m3(c.w_own, ctx->stream);
+    if (cnn_dtype == MDNP_FP8E4M3) cnn_dtype = MDNP_BF16;
     c.dtype = cnn_dtype;
     if (!c.inv_s) c.inv_s = dalloc<double>(2 * (size_t)s->n_inst);
     cnn_prepare_weights(c, c.w, ctx->stream);
+    if (cnn_dtype == MDNP_FP8E4M3_ACT) {
+      // packed E4M3 fragments; the activation scales are set by
+      // mdnp_fp8_calibrate or mdnp_set_fp8_scales before the network runs
+      if (!fp8_prepare_weights(c, ctx->stream)) fail(MDNP_E_OOM, "FP8 weight fragments");
+      for (float& v : c.act8_scale) v = 0.0f;
+    }
     if (!cnn_reserve(c, s->n_inst, s->n, cnn_dtype)) fail(MDNP_E_OOM, "network activation buffers");
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1106,6 +1112,12 @@ void solve_impl(mdnp_ctx* ctx, mdnp_sys* s, const double* d_b, double* d_x, cons
   (void)ctx;
 }
 
+// the E4M3 network needs its activation scales
+void check_fp8_scales(const mdnp_sys* s) {
+  if (s->kind == MDNP_PREC_NEURAL && s->cnn.dtype == MDNP_FP8E4M3_ACT && !(s->cnn.act8_scale[0] > 0.0f))
+    fail(MDNP_E_STATE, "FP8 activation scales not set (mdnp_fp8_calibrate or mdnp_set_fp8_scales)");
+}
+
 void check_opts(const mdnp_solve_opts* o) {
   if (!o) fail(MDNP_E_ARG, "null options");
   if (o->restart < 1 || o->restart > 512) fail(MDNP_E_ARG, "restart must be in [1, 512]");
@@ -1124,6 +1136,7 @@ extern "C" mdnp_status mdnp_solve_device(mdnp_ctx* ctx, mdnp_sys* s, const doubl
     if (!s || !d_b || !d_x) fail(MDNP_E_ARG, "null argument");
     check_opts(opts);
     if (!s->prec_set) fail(MDNP_E_STATE, "no preconditioner set (mdnp_set_preconditioner)");
+    check_fp8_scales(s);
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t stream = pick(ctx, hip_stream);
     if (s->vec_dtype == MDNP_F64) solve_impl<double>(ctx, s, d_b, d_x, *opts, stats, stream);
@@ -1245,6 +1258,7 @@ extern "C" mdnp_status mdnp_precond_apply(mdnp_ctx* ctx, mdnp_sys* s, const void
   return guarded(ctx, [&] {
     if (!s || !d_v || !d_z) fail(MDNP_E_ARG, "null argument");
     if (!s->prec_set) fail(MDNP_E_STATE, "no preconditioner set");
+    check_fp8_scales(s);
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t stream = pick(ctx, hip_stream);
     if (!s->work.part) s->work.part = dalloc<double>(parts_size(s));
@@ -1253,6 +1267,70 @@ extern "C" mdnp_status mdnp_precond_apply(mdnp_ctx* ctx, mdnp_sys* s, const void
     else apply_prec<float>(s, (const float*)d_v, (float*)d_z, nullptr, false, stream);
     HIPCHK(hipGetLastError());
   });
+}
+
+extern "C" mdnp_status mdnp_set_fp8_scales(mdnp_ctx* ctx, mdnp_sys* s, const float* scales, int32_t count) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !scales) fail(MDNP_E_ARG, "null argument");
+    if (count != 11) fail(MDNP_E_ARG, "expected 11 scales (X, L0a, L0b, L1a, L1b, L2a, L2b, U1, D1, U0, D0)");
+    if (!(s->kind == MDNP_PREC_NEURAL && s->prec_set && s->cnn.dtype == MDNP_FP8E4M3_ACT))
+      fail(MDNP_E_STATE, "no neural preconditioner with MDNP_FP8E4M3_ACT set");
+    for (int k = 0; k < 11; ++k) {
+      int e = 0;
+      if (!(scales[k] > 0.0f) || !std::isfinite(scales[k]) || std::frexp(scales[k], &e) != 0.5f)
+        fail(MDNP_E_ARG, "scales must be positive powers of two");
+    }
+    if (scales[4] != scales[7] || scales[2] != scales[9])
+      fail(MDNP_E_ARG, "the stacked pairs (L1b, U1) and (L0b, U0) need one scale each");
+    for (int k = 0; k < 11; ++k) s->cnn.act8_scale[k] = scales[k];
+    drop_graphs(s->work);  // captured with the old scales
+  });
+}
+
+extern "C" mdnp_status mdnp_get_fp8_scales(mdnp_ctx* ctx, const mdnp_sys* s, float* scales, int32_t count) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !scales) fail(MDNP_E_ARG, "null argument");
+    if (count != 11) fail(MDNP_E_ARG, "expected 11 scales");
+    for (int k = 0; k < 11; ++k) scales[k] = s->cnn.act8_scale[k];
+  });
+}
+
+extern "C" mdnp_status mdnp_fp8_calibrate(mdnp_ctx* ctx, mdnp_sys* s, const void* d_v, void* hip_stream) {
+  if (!ctx) return MDNP_E_ARG;
+  void* z = nullptr;
+  mdnp_status st = guarded(ctx, [&] {
+    if (!s || !d_v) fail(MDNP_E_ARG, "null argument");
+    if (!(s->kind == MDNP_PREC_NEURAL && s->prec_set && s->cnn.dtype == MDNP_FP8E4M3_ACT))
+      fail(MDNP_E_STATE, "no neural preconditioner with MDNP_FP8E4M3_ACT set");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t stream = pick(ctx, hip_stream);
+    CnnState& c = s->cnn;
+    if (!s->work.part) s->work.part = dalloc<double>(parts_size(s));
+    if (!c.inv_s) c.inv_s = dalloc<double>(2 * (size_t)s->n_inst);
+    if (!c.fp8_amax) c.fp8_amax = dalloc<unsigned>(16);
+    z = dalloc<char>(vsize(s->vec_dtype) * (size_t)s->ntot);
+    fp8_zero_amax(c.fp8_amax, stream);
+    // the preconditioner on v with the network in FP32, recording the largest
+    // magnitude of its input and of every layer output
+    c.fp8_calibrating = true;
+    if (s->vec_dtype == MDNP_F64) apply_prec<double>(s, (const double*)d_v, (double*)z, nullptr, false, stream);
+    else apply_prec<float>(s, (const float*)d_v, (float*)z, nullptr, false, stream);
+    c.fp8_calibrating = false;
+    unsigned bits[11];
+    HIPCHK(hipMemcpyAsync(bits, c.fp8_amax, sizeof(bits), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    float amax[11];
+    for (int k = 0; k < 11; ++k) std::memcpy(&amax[k], &bits[k], 4);
+    for (int k = 0; k < 11; ++k)
+      if (!std::isfinite(amax[k])) fail(MDNP_E_NONFINITE, "non-finite activation in the calibration run");
+    fp8_scales_from_amax(amax, c.act8_scale);
+    drop_graphs(s->work);
+  });
+  if (s) s->cnn.fp8_calibrating = false;
+  dfree(z);
+  return st;
 }
 
 extern "C" int64_t mdnp_cnn_saved_bytes(int32_t batch, int32_t n, mdnp_dtype dtype) {

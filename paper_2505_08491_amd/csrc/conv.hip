@@ -998,9 +998,16 @@ void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, const InstState* st,
   CnnState& c = s->cnn;
   const double* isc = scales ? scales : c.inv_s;
   const int n = s->n, batch = s->n_inst;
-  if (!ensure_scratch(c, (size_t)cnn_saved_bytes(batch, n, c.dtype))) return;
+  // the E4M3 network (its calibration runs the FP32 one and records magnitudes)
+  const bool fp8 = c.dtype == MDNP_FP8E4M3_ACT;
+  const mdnp_dtype dt = fp8 ? MDNP_F32 : c.dtype;
+  if (!ensure_scratch(c, (size_t)cnn_saved_bytes(batch, n, dt))) return;
+  if (fp8 && !c.fp8_calibrating) {
+    cnn_apply_fp8<Tv>(s, zin, z, st, stream, isc);
+    return;
+  }
   int64_t offs[13];
-  saved_layout(batch, n, c.dtype, offs);
+  saved_layout(batch, n, dt, offs);
   void* act[12];
   for (int k = 0; k < 12; ++k) act[k] = (char*)c.act[0] + offs[k];
   const dim3 grid((unsigned)((cube(n) + BS - 1) / BS), 1, batch);
@@ -1029,7 +1036,8 @@ void cnn_apply_in_solver(mdnp_sys* s, const Tv* zin, Tv* z, const InstState* st,
     if (all || only_stage == 0)
       hipLaunchKernelGGL((k_conv_in0<Tv, float>), grid, dim3(BS), 0, stream, zin, s->d_off, isc, s->d_dist,
                          c.wt + c.wt_off[0], c.w + c.b_off[0], n, (float*)act[1], st);
-    unet_middle<float>(c, c.w, act, batch, n, c.dtype, st, stream, mid_hi, mid_lo);
+    unet_middle<float>(c, c.w, act, batch, n, dt, st, stream, mid_hi, mid_lo);
+    if (fp8) fp8_record_amax<Tv>(s, zin, isc, act, c.fp8_amax, stream);
     if (all || only_stage == 9)
       hipLaunchKernelGGL((k_head_out<Tv, float>), grid, dim3(BS), 0, stream, (const float*)act[10],
                          c.wt + c.wt_off[10], c.w + c.b_off[10], n, z, s->d_off, s->d_alpha, s->alpha_override,
@@ -1443,6 +1451,9 @@ void cnn_release(CnnState& c) {
   if (c.split) hipFree(c.split);
   if (c.std_off) hipFree(c.std_off);
   if (c.std_ones) hipFree(c.std_ones);
+  if (c.w8) hipFree(c.w8);
+  if (c.w8s) hipFree(c.w8s);
+  if (c.fp8_amax) hipFree(c.fp8_amax);
   c = CnnState();
 }
 

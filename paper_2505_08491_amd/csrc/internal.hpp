@@ -87,6 +87,19 @@ struct CnnState {
   // 16-column x blocks per workgroup of the sweep layers L0a, L0b, L1b, D1, D0
   // (0: as many as fit; fewer splits each row over more workgroups)
   int tile_xb[11] = {};
+  // E4M3 weights and activations on the FP8 matrix cores (MDNP_FP8E4M3_ACT):
+  // packed weight fragments and per-output-channel scales of the ten 3x3x3
+  // layers, and the activation scales of X, L0a, L0b, L1a, L1b, L2a, L2b, U1,
+  // D1, U0, D0 (0: not set)
+  uint8_t* w8 = nullptr;
+  std::vector<int64_t> w8_off;
+  float* w8s = nullptr;
+  std::vector<int64_t> w8s_off;
+  float act8_scale[11] = {};
+  // set while mdnp_fp8_calibrate runs the network in FP32 to record the
+  // largest magnitude of every tensor into fp8_amax (device, 11 words)
+  bool fp8_calibrating = false;
+  unsigned* fp8_amax = nullptr;
 };
 
 // Jacobi pre/post-smoothing of the neural 3D solve (sweeps = 0: off) and its

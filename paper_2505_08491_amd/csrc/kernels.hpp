@@ -111,6 +111,19 @@ void cnn_apply_in_solver(mdnp_sys* s, const T* zin, T* z, const InstState* st, h
 // stage back to back between two HIP events on `stream`, after one whole
 // application to a fixed vector; false if its buffers or events could not
 // be created.
+// E4M3 network (conv_fp8.hip): weight packing from the (already quantised)
+// master weights, the in-solver application, and the calibration helpers
+bool fp8_prepare_weights(CnnState& c, hipStream_t stream);
+int64_t fp8_act_bytes(int batch, int n);
+template <typename Tv>
+void cnn_apply_fp8(mdnp_sys* s, const Tv* zin, Tv* z, const InstState* st, hipStream_t stream, const double* isc);
+void fp8_zero_amax(unsigned* d_amax, hipStream_t stream);
+template <typename Tv>
+void fp8_record_amax(mdnp_sys* s, const Tv* zin, const double* isc, void* const act[12], unsigned* d_amax,
+                     hipStream_t stream);
+// scales from the largest magnitudes (X, L0a, ..., D0): stacked pairs share
+// one; each the smallest power of two with 2 amax / s <= 448
+void fp8_scales_from_amax(const float amax[11], float out[11]);
 bool cnn_layer_times(mdnp_sys* s, hipStream_t stream, int reps, float* ms);
 // Per-layer z split of the BF16 sweep convolutions chosen by timing on the
 // system's batch and grid (CnnState::sweep_blocks); false if its timing

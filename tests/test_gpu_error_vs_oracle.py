@@ -56,6 +56,8 @@ def _solve_all(ctx, insts, dtypes, tune=True):
         S.set_preconditioner("neural", weights=w, cnn_dtype=dt)
         if tune and dt in ("bf16", "fp8"):
             S.autotune()
+        if dt == "fp8a":
+            S.fp8_calibrate(b.to(torch.float32))
         x = torch.zeros_like(b)
         st = S.solve_device(b, x, **OPTS)
         out[dt] = (x.cpu().numpy(), st)
@@ -90,9 +92,10 @@ def _check(insts, sols, offsets, label):
 
 def test_error_vs_oracle_transfer64(ctx):
     """All 16 instances of the 64^3 benchmark workload (512 segments x 16
-    elements, R = 0.002), network in BF16, with E4M3 weights and in FP32."""
+    elements, R = 0.002), network in BF16, with E4M3 weights, with E4M3
+    weights and activations (FP8 matrix cores) and in FP32."""
     insts = synth.workload_transfer(64, 16)
-    sols, offs = _solve_all(ctx, insts, ("bf16", "fp8", "f32"))
+    sols, offs = _solve_all(ctx, insts, ("bf16", "fp8", "fp8a", "f32"))
     _check(insts, sols, offs, "64^3x16")
 
 
