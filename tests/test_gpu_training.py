@@ -302,6 +302,28 @@ def test_short_training_run_lowers_loss(dtype):
     assert h[-1]["val_loss"] < 0.7 * h[0]["val_loss"]
 
 
+def test_trainer_variants():
+    """The trainer variants of the ablation (Section 5.1 augmentation and the
+    distance input): with the distance input off the first layer's weights on
+    that channel stay exactly zero; trained on random samples only, or on the
+    right-hand-side samples only, a short run still lowers its loss; the
+    3D-block workload trains on its own bank."""
+    from paper_2505_08491_amd import train as T
+    kw = dict(steps=20, batch=8, graphs=6, n_cells=16, val_graphs=3, log_every=10)
+    w, meta = T.train(no_dist=True, **kw)
+    assert np.all(w[T.dist_weight_mask()] == 0.0)
+    assert np.any(w[T.dist_weight_mask() - 1] != 0.0)       # the residual channel is trained
+    assert meta["no_dist"] and meta["history"][-1]["loss"] < meta["history"][0]["loss"]
+    for pr, ph in ((1.0, 0.0), (0.0, 1.0)):
+        _, meta = T.train(p_random=pr, p_rhs=ph, **kw)
+        h = meta["history"]
+        assert (meta["p_random"], meta["p_rhs"]) == (pr, ph)
+        assert h[-1]["loss"] < h[0]["loss"], (pr, ph, h)
+    _, meta = T.train(workload="block3d", **dict(kw, n_cells=20))
+    h = meta["history"]
+    assert meta["workload"] == "block3d" and h[-1]["loss"] < h[0]["loss"], h
+
+
 def test_trained_network_gain(ctx):
     """What the trained network gains (the None vs U3 rows of the paper's
     tables): on 16 instances of the batched 32^3 workload, FGMRES(30) with the
