@@ -62,16 +62,21 @@ def parse():
 
 
 def spmv_bytes(S, vec_bytes=4):
-    """Algorithmic bytes of one batched y = A x with A = S + M: x read once and
-    y written once; the stencil S has a handful of constants per instance and
-    no stored entries; M streams its values and column indices once, plus a row
-    index and a row pointer per non-empty row."""
-    m_nnz = m_rows = 0
+    """Algorithmic bytes of one batched y = A x with A = S + M and M applied in
+    its factored form B^T W B + R: x read once and y written once; the stencil
+    S has a handful of constants per instance and no stored entries; the
+    entries of W B (one row per Gauss point, with a row pointer each) and of
+    the row-wise B^T | R (with a row index and a row pointer per listed row)
+    streamed once each, values and column indices.  The intermediate t = W B x
+    (one value per Gauss point) is not counted."""
+    nb = ns = nq = rows = 0
     for i in range(S.n_inst):
-        e, r = S.split_sizes(i)
-        m_nnz += e
-        m_rows += r
-    return 2 * S.ntot * vec_bytes + m_nnz * (vec_bytes + 4) + m_rows * 8
+        q, b, e = S.coupling_sizes(i)
+        nq += q
+        nb += b
+        ns += e
+        rows += S.split_sizes(i)[1]
+    return 2 * S.ntot * vec_bytes + (nb + ns) * (vec_bytes + 4) + nq * 4 + rows * 8
 
 
 def unet_flops(n):
@@ -518,7 +523,7 @@ def main():
                      "algorithmic_flops": fl[dom] * S.n_inst, "algorithmic_bytes": by[dom] * S.n_inst,
                      "ms_per_launch": stage_ms[dom]},
         "unet_stages": stages,
-        "spmv": {"bound": "hbm", "kernel": "k_stencil_sweep + k_mrows (batched y = (S + M) x, FP32)",
+        "spmv": {"bound": "hbm", "kernel": "k_cgather + k_stencil_sweep + k_cscatter (batched y = (S + B^T W B + R) x, FP32)",
                  "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
                  "timing": "each launch after a 1 GiB read that evicts the last-level cache",
                  "traffic": (spmv_traffic(tuned[11] if tuned else 0)

@@ -151,6 +151,16 @@ mdnp_status mdnp_sys_sizes(const mdnp_sys* sys, int32_t inst, int32_t* n3d, int3
  * (3D rows touched by the coupling plus every 1D row). */
 mdnp_status mdnp_sys_split_sizes(const mdnp_sys* sys, int32_t inst, int64_t* m_nnz, int64_t* m_rows);
 
+/* Sizes of the coupling of instance `inst` in the factored form the stencil-
+ * sweep path applies, M = B^T W B + R (eq. "mainsys": each Gauss point q of the
+ * 1D mesh contributes W_q (Pi_q u0 - Phi_q u1)(Pi_q v0 - Phi_q v1), Section
+ * 2.1): Gauss points (rows of B), stored entries of W B, and stored entries of
+ * the row-wise B^T | R the second pass reads (R: the 1D stiffness rows, or
+ * unit 1D rows in the 3D-block layout, and the natural-boundary stencil
+ * entries). */
+mdnp_status mdnp_sys_coupling_sizes(const mdnp_sys* sys, int32_t inst, int64_t* n_gauss, int64_t* b_nnz,
+                                    int64_t* s_nnz);
+
 /* Host copy of the assembled matrix of one instance in CSR with local indices
  * (row_ptr [n+1], col [nnz], val [nnz], n = n3d + n1d): columns ascending,
  * duplicates merged, zero values kept where the pattern has them, Dirichlet
@@ -399,6 +409,17 @@ mdnp_status mdnp_host_sizes(const mdnp_host_sys* hs, int32_t* n3d, int32_t* n1d,
 /* CSR (local indices) as in mdnp_export_csr, F [n], dist [n3d], alpha; any may be NULL. */
 mdnp_status mdnp_host_export(const mdnp_host_sys* hs, int32_t* row_ptr, int32_t* col, double* val,
                              double* F, float* dist, double* alpha);
+/* The factored coupling of a host assembly, M = B^T W B + R (eq. "mainsys",
+ * Section 2.1), local indices.  B: one row per Gauss point (b_ptr [n_gauss+1],
+ * b_col / b_val [b_nnz]): the cross-section average Pi_q on the free 3D nodes,
+ * columns ascending, then from b_split[q] the entries -Phi_q of the element's
+ * two 1D nodes (none in the 3D-block layout); w [n_gauss] the weights
+ * W_q = 2 pi R beta |e| / 2.  R: CSR over all n3d + n1d rows (r_ptr [n+1],
+ * r_col / r_val [r_nnz]).  Sizes from mdnp_host_coupling_sizes; any pointer
+ * may be NULL. */
+mdnp_status mdnp_host_coupling_sizes(const mdnp_host_sys* hs, int32_t* n_gauss, int64_t* b_nnz, int64_t* r_nnz);
+mdnp_status mdnp_host_coupling(const mdnp_host_sys* hs, int32_t* b_ptr, int32_t* b_split, int32_t* b_col,
+                               double* b_val, double* w, int32_t* r_ptr, int32_t* r_col, double* r_val);
 /* z1 = A11^-1 v1 on the host with the factorisation used by the GPU 1D solve
  * (v1, z1 of length n1d): the chain-compressed form (segment interiors as
  * tridiagonal blocks, then the vertex Schur complement) when every segment has

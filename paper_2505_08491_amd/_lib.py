@@ -51,6 +51,7 @@ SIGNATURES = [
     ("mdnp_sys_free", C.c_int, [VP, VP]),
     ("mdnp_sys_sizes", C.c_int, [VP, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_int64), P(C.c_int64)]),
     ("mdnp_sys_split_sizes", C.c_int, [VP, C.c_int32, P(C.c_int64), P(C.c_int64)]),
+    ("mdnp_sys_coupling_sizes", C.c_int, [VP, C.c_int32, P(C.c_int64), P(C.c_int64), P(C.c_int64)]),
     ("mdnp_export_csr", C.c_int, [VP, C.c_int32, VP, VP, VP]),
     ("mdnp_export_rhs", C.c_int, [VP, C.c_int32, VP, VP, P(C.c_double)]),
     ("mdnp_set_preconditioner", C.c_int, [VP, VP, C.c_int, VP, C.c_int64, C.c_double, C.c_int]),
@@ -80,6 +81,8 @@ SIGNATURES = [
     ("mdnp_host_assemble", C.c_int, [P(InstanceDesc), P(VP), C.c_char_p, C.c_int32]),
     ("mdnp_host_sizes", C.c_int, [VP, P(C.c_int32), P(C.c_int32), P(C.c_int64), P(C.c_int32)]),
     ("mdnp_host_export", C.c_int, [VP, VP, VP, VP, VP, VP, P(C.c_double)]),
+    ("mdnp_host_coupling_sizes", C.c_int, [VP, P(C.c_int32), P(C.c_int64), P(C.c_int64)]),
+    ("mdnp_host_coupling", C.c_int, [VP, VP, VP, VP, VP, VP, VP, VP, VP]),
     ("mdnp_host_tree_solve", C.c_int, [VP, VP, VP]),
     ("mdnp_host_free", None, [VP]),
 ]

@@ -80,6 +80,31 @@ class HostSystem:
             raise MdnpError(st, "host tree solve failed")
         return z
 
+    def coupling(self):
+        """The factored coupling M = B^T W B + R of this assembly as SciPy CSR
+        matrices (B: one row per Gauss point, columns over all n3d + n1d
+        unknowns), the weights W and, per Gauss point, where its 1D entries
+        start in B's entry arrays."""
+        import scipy.sparse as sp
+        nq, nb, nr = C.c_int32(), C.c_int64(), C.c_int64()
+        lib.mdnp_host_coupling_sizes(self._handle, C.byref(nq), C.byref(nb), C.byref(nr))
+        n = self.n3d + self.n1d
+        bp = np.empty(nq.value + 1, np.int32)
+        bs = np.empty(nq.value, np.int32)
+        bc = np.empty(nb.value, np.int32)
+        bv = np.empty(nb.value, np.float64)
+        w = np.empty(nq.value, np.float64)
+        rp = np.empty(n + 1, np.int32)
+        rc = np.empty(nr.value, np.int32)
+        rv = np.empty(nr.value, np.float64)
+        st = lib.mdnp_host_coupling(self._handle, bp.ctypes.data, bs.ctypes.data, bc.ctypes.data, bv.ctypes.data,
+                                    w.ctypes.data, rp.ctypes.data, rc.ctypes.data, rv.ctypes.data)
+        if st != 0:
+            raise MdnpError(st, "host coupling export failed")
+        B = sp.csr_matrix((bv, bc, bp), shape=(nq.value, n))
+        R = sp.csr_matrix((rv, rc, rp), shape=(n, n))
+        return B, w, R, bs
+
     def __del__(self):
         if self._handle is not None and lib is not None:
             lib.mdnp_host_free(self._handle)
@@ -208,6 +233,13 @@ class System:
         a, b = C.c_int64(), C.c_int64()
         self.ctx._check(lib.mdnp_sys_split_sizes(self.h, i, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def coupling_sizes(self, i):
+        """(Gauss points, entries of W B, entries of B^T | R) of the factored
+        coupling M = B^T W B + R that the stencil-sweep path applies."""
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self.ctx._check(lib.mdnp_sys_coupling_sizes(self.h, i, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
 
     def free(self):
         if getattr(self, "h", None) is not None and self.ctx.h is not None:

@@ -162,6 +162,13 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
   std::vector<std::pair<int32_t, double>> pis;
   std::vector<int32_t> nodes;
   std::vector<double> coef;
+  std::vector<Trip> k11;  // the 1D stiffness triplets again, for R
+  k11.reserve((size_t)ne * 4);
+  H.b_ptr.assign(1, 0);
+  H.b_col.clear();
+  H.b_val.clear();
+  H.b_split.clear();
+  H.b_w.clear();
   for (int e = 0; e < ne; ++e) {
     const double* Pa = &pos[3 * (size_t)ea[e]];
     const double* Pb = &pos[3 * (size_t)eb[e]];
@@ -178,6 +185,8 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
     const int A1 = n3d + ea[e], B1 = n3d + eb[e];
     trips.push_back({A1, A1, kk}); trips.push_back({A1, B1, -kk});
     trips.push_back({B1, A1, -kk}); trips.push_back({B1, B1, kk});
+    k11.push_back({A1, A1, kk}); k11.push_back({A1, B1, -kk});
+    k11.push_back({B1, A1, -kk}); k11.push_back({B1, B1, kk});
     H.F[A1] += d.f_lambda * ell / 2;
     H.F[B1] += d.f_lambda * ell / 2;
     for (int qi = 0; qi < 2; ++qi) {
@@ -223,6 +232,15 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
       nodes.push_back(A1); coef.push_back(-(1.0 - t));
       nodes.push_back(B1); coef.push_back(-t);
       const int m = (int)nodes.size();
+      // row q of B: the free 3D nodes (ascending), then the two 1D nodes
+      for (int u = 0; u < m; ++u) {
+        if (u == m - 2) H.b_split.push_back((int32_t)H.b_col.size());
+        if (elim(nodes[u])) continue;
+        H.b_col.push_back(nodes[u]);
+        H.b_val.push_back(coef[u]);
+      }
+      H.b_ptr.push_back((int32_t)H.b_col.size());
+      H.b_w.push_back(W);
       for (int u = 0; u < m; ++u) {
         if (elim(nodes[u])) continue;
         for (int v = 0; v < m; ++v) {
@@ -243,6 +261,19 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
     for (const Trip& t : trips) rowt[fill[t.row]++] = {t.col, t.v};
   }
   std::vector<Trip>().swap(trips);
+  // the 1D stiffness by row (1D rows only), for R
+  std::vector<int64_t> kptr((size_t)n1d + 1, 0);
+  for (const Trip& t : k11) ++kptr[t.row - n3d + 1];
+  for (int r = 0; r < n1d; ++r) kptr[r + 1] += kptr[r];
+  std::vector<std::pair<int32_t, double>> krow(k11.size());
+  {
+    std::vector<int64_t> fill(kptr.begin(), kptr.end() - 1);
+    for (const Trip& t : k11) krow[fill[t.row - n3d]++] = {t.col, t.v};
+  }
+  std::vector<Trip>().swap(k11);
+  H.r_ptr.assign((size_t)nt + 1, 0);
+  H.r_col.clear();
+  H.r_val.clear();
 
   // stencil values at an interior node (sums over its 8 cells) and one cell's
   // share (node pairs differing in 0..3 coordinates; a pair shares 2^(3 - nd)
@@ -334,6 +365,27 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
       }
     }
     merge_rows(cpl, corr, mrow);
+    // row r of R: the natural-boundary stencil entries of a 3D row, the 1D
+    // stiffness of a 1D row (duplicates merged)
+    if (r < n3d) {
+      for (const auto& e : corr) {
+        H.r_col.push_back(e.first);
+        H.r_val.push_back(e.second);
+      }
+    } else {
+      auto k0 = krow.begin() + kptr[r - n3d], k1 = krow.begin() + kptr[r - n3d + 1];
+      std::sort(k0, k1, [](const std::pair<int32_t, double>& u, const std::pair<int32_t, double>& v) {
+        return u.first < v.first;
+      });
+      for (auto it = k0; it != k1;) {
+        const int32_t cc = it->first;
+        double acc = 0.0;
+        while (it != k1 && it->first == cc) acc += (it++)->second;
+        H.r_col.push_back(cc);
+        H.r_val.push_back(acc);
+      }
+    }
+    H.r_ptr[r + 1] = (int32_t)H.r_col.size();
     bool m01 = false;
     for (const auto& e : mrow) {
       if (r < n3d && !m01 && e.first >= n3d) {
@@ -441,6 +493,22 @@ std::string assemble_instance(const mdnp_instance_desc& d, HostInstance& H, bool
     };
     strip(H.row_ptr, H.col, H.val, &H.a01_start);
     strip(H.m_ptr, H.m_col, H.m_val, &H.m_a01);
+    strip(H.r_ptr, H.r_col, H.r_val, nullptr);
+    {  // B keeps its 3D columns only
+      std::vector<int32_t> p2(1, 0), c2;
+      std::vector<double> v2;
+      for (size_t q = 0; q + 1 < H.b_ptr.size(); ++q) {
+        for (int32_t e = H.b_ptr[q]; e < H.b_split[q]; ++e) {
+          c2.push_back(H.b_col[e]);
+          v2.push_back(H.b_val[e]);
+        }
+        p2.push_back((int32_t)c2.size());
+        H.b_split[q] = p2.back();
+      }
+      H.b_ptr.swap(p2);
+      H.b_col.swap(c2);
+      H.b_val.swap(v2);
+    }
     for (int r = n3d; r < nt; ++r) H.diag[r] = 1.0;
     for (int r = 0; r < n3d; ++r) H.F[r] = b[r];
     for (int r = n3d; r < nt; ++r) H.F[r] = 0.0;

@@ -56,6 +56,15 @@ struct HostInstance {
   std::vector<int32_t> m_ptr, m_col;
   std::vector<double> m_val;
   std::vector<int32_t> m_a01;          // per 3D row: first M entry with a 1D column
+  // M in factored form (eq. "mainsys"): M = B^T W B + R with one row of B per
+  // Gauss point q, B_q = [Pi_q | -Phi_q] on the free nodes (its 3D columns
+  // first, the two 1D columns from b_split[q]), W_q its weight, and R the rest
+  // of M: the 1D stiffness rows (unit 1D rows in the 3D-block layout, which
+  // has no 1D columns in B) and the natural-boundary stencil entries.
+  std::vector<int32_t> b_ptr, b_col, b_split;
+  std::vector<double> b_val, b_w;
+  std::vector<int32_t> r_ptr, r_col;   // R in CSR over all rows, sorted columns
+  std::vector<double> r_val;
   std::vector<double> F;               // right-hand side [n3d + n1d]
   std::vector<float> dist;             // distance field at the 3D nodes
   std::vector<double> diag;            // diag(A)

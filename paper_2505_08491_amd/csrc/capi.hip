@@ -142,7 +142,9 @@ void free_sys(mdnp_sys* s) {
   free_smooth(s->smooth);
   free_inner(s->inner);
   void* ptrs[] = {s->d_off, s->d_stencil, s->d_mptr, s->d_mcol, s->d_mval64, s->d_mval32, s->d_ma01, s->d_mrows, s->d_mlp,
-                  s->d_a01p, s->d_a01c, s->d_a01v64, s->d_a01v32, s->d_m3e, s->d_dinv, s->d_dinv32, s->d_dist,
+                  s->d_a01p, s->d_a01c, s->d_a01v64, s->d_a01v32, s->d_m3e, s->d_gp, s->d_gsplit, s->d_gcol,
+                  s->d_gval64, s->d_gval32, s->d_sp, s->d_scol, s->d_sval64, s->d_sval32, s->d_ct,
+                  s->d_dinv, s->d_dinv32, s->d_dist,
                   s->d_alpha, s->d_t_off, s->d_t_lvloff, s->d_t_lvlptr, s->d_t_lvlnodes, s->d_t_parent,
                   s->d_t_childptr, s->d_t_childidx, s->d_t_lval, s->d_t_dinv};
   for (void* p : ptrs) dfree(p);
@@ -156,6 +158,7 @@ void free_sys(mdnp_sys* s) {
   free_blocks(s->blk3);
   free_blocks(s->mblk);
   free_blocks(s->mblk3);
+  free_blocks(s->gblk);
   free_work(s->work);
   cnn_release(s->cnn);
   delete s;
@@ -291,6 +294,34 @@ extern "C" mdnp_status mdnp_host_export(const mdnp_host_sys* hs, int32_t* row_pt
   if (F) std::memcpy(F, h.F.data(), h.F.size() * sizeof(double));
   if (dist) std::memcpy(dist, h.dist.data(), h.dist.size() * sizeof(float));
   if (alpha) *alpha = h.alpha;
+  return MDNP_OK;
+}
+
+extern "C" mdnp_status mdnp_host_coupling_sizes(const mdnp_host_sys* hs, int32_t* n_gauss, int64_t* b_nnz,
+                                                int64_t* r_nnz) {
+  if (!hs) return MDNP_E_ARG;
+  const HostInstance& h = hs->h;
+  if (n_gauss) *n_gauss = (int32_t)h.b_w.size();
+  if (b_nnz) *b_nnz = (int64_t)h.b_col.size();
+  if (r_nnz) *r_nnz = (int64_t)h.r_col.size();
+  return MDNP_OK;
+}
+
+extern "C" mdnp_status mdnp_host_coupling(const mdnp_host_sys* hs, int32_t* b_ptr, int32_t* b_split, int32_t* b_col,
+                                          double* b_val, double* w, int32_t* r_ptr, int32_t* r_col, double* r_val) {
+  if (!hs) return MDNP_E_ARG;
+  const HostInstance& h = hs->h;
+  auto put = [](auto* dst, const auto& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+  };
+  put(b_ptr, h.b_ptr);
+  put(b_split, h.b_split);
+  put(b_col, h.b_col);
+  put(b_val, h.b_val);
+  put(w, h.b_w);
+  put(r_ptr, h.r_ptr);
+  put(r_col, h.r_col);
+  put(r_val, h.r_val);
   return MDNP_OK;
 }
 
@@ -526,6 +557,80 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
     // coupling rows: short chunks (a few rows per lane group) for latency hiding
     build_blocks(s->mblk, ms, ml, (int64_t)mrows.size(), stream, 64, 8192);
     build_blocks(s->mblk3, ms, ml3, (int64_t)mrows.size(), stream, 64, 8192);
+    // M in factored form: W B by Gauss point, and over the listed rows (in
+    // their order) each row's B^T entries, Gauss points ascending, then its R
+    // entries
+    {
+      std::vector<int32_t> gp(1, 0), gsplit, gcol, sp(mrows.size() + 1, 0), scol;
+      std::vector<double> gv, sv;
+      std::vector<int64_t> gs(n_inst), gl(n_inst);
+      int64_t nq = 0;
+      for (int i = 0; i < n_inst; ++i) {
+        const HostInstance& h = s->host[i];
+        const int nqi = (int)h.b_w.size();
+        const int nr = h.n3d + h.n1d;
+        const int64_t o = s->off[i];
+        if (nq + nqi >= INT32_MAX || (int64_t)gcol.size() + h.b_ptr[nqi] >= INT32_MAX)
+          fail(MDNP_E_ARG, "too many coupling entries for 32-bit indices");
+        gs[i] = nq;
+        gl[i] = nqi;
+        for (int q = 0; q < nqi; ++q) {
+          gsplit.push_back(gp.back() + (h.b_split[q] - h.b_ptr[q]));
+          for (int32_t e = h.b_ptr[q]; e < h.b_ptr[q + 1]; ++e) {
+            gcol.push_back((int32_t)(o + h.b_col[e]));
+            gv.push_back(h.b_w[q] * h.b_val[e]);
+          }
+          gp.push_back((int32_t)gcol.size());
+        }
+        std::vector<int32_t> tp((size_t)nr + 1, 0);
+        for (int32_t e = 0; e < h.b_ptr[nqi]; ++e) ++tp[h.b_col[e] + 1];
+        for (int r = 0; r < nr; ++r) tp[r + 1] += tp[r];
+        std::vector<int32_t> tq(tp[nr]);
+        std::vector<double> tv(tp[nr]);
+        {
+          std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
+          for (int q = 0; q < nqi; ++q)
+            for (int32_t e = h.b_ptr[q]; e < h.b_ptr[q + 1]; ++e) {
+              const int r = h.b_col[e];
+              tq[fill[r]] = q;
+              tv[fill[r]++] = h.b_val[e];
+            }
+        }
+        const size_t s0 = scol.size();
+        for (int64_t k = ms[i]; k < ms[i] + ml[i]; ++k) {
+          const int r = (int)(mrows[k] - o);
+          sp[k] = (int32_t)scol.size();
+          for (int32_t e = tp[r]; e < tp[r + 1]; ++e) {
+            scol.push_back((int32_t)(nq + tq[e]));
+            sv.push_back(tv[e]);
+          }
+          for (int32_t e = h.r_ptr[r]; e < h.r_ptr[r + 1]; ++e) {
+            scol.push_back(~(int32_t)(o + h.r_col[e]));
+            sv.push_back(h.r_val[e]);
+          }
+          if (scol.size() >= (size_t)INT32_MAX) fail(MDNP_E_ARG, "too many coupling entries for 32-bit indices");
+        }
+        // every row with an entry of B^T or R is listed
+        if ((int64_t)(scol.size() - s0) != (int64_t)tp[nr] + h.r_ptr[nr])
+          fail(MDNP_E_ARG, "internal error: a row of the factored coupling is not listed");
+        s->c_gauss.push_back(nqi);
+        s->c_bnnz.push_back(h.b_ptr[nqi]);
+        s->c_snnz.push_back((int64_t)(scol.size() - s0));
+        nq += nqi;
+      }
+      sp[mrows.size()] = (int32_t)scol.size();
+      s->d_gp = dupload(gp, stream);
+      s->d_gsplit = dupload(gsplit, stream);
+      s->d_gcol = dupload(gcol, stream);
+      s->d_gval64 = dupload(gv, stream);
+      s->d_gval32 = dupload(std::vector<float>(gv.begin(), gv.end()), stream);
+      s->d_sp = dupload(sp, stream);
+      s->d_scol = dupload(scol, stream);
+      s->d_sval64 = dupload(sv, stream);
+      s->d_sval32 = dupload(std::vector<float>(sv.begin(), sv.end()), stream);
+      s->d_ct = dalloc<double>((size_t)nq);
+      build_blocks(s->gblk, gs, gl, nq, stream, 64, 8192);
+    }
     // tree factorisation
     std::vector<int32_t> toff(n_inst + 1, 0), lvloff(n_inst + 1, 0), lvlptr, lvlnodes, parent, childptr, childidx;
     std::vector<double> lval, tdinv;
@@ -681,6 +786,15 @@ extern "C" mdnp_status mdnp_sys_split_sizes(const mdnp_sys* s, int32_t inst, int
   if (!s || inst < 0 || inst >= s->n_inst) return MDNP_E_ARG;
   if (m_nnz) *m_nnz = s->m_nnz[inst];
   if (m_rows) *m_rows = s->m_rows[inst];
+  return MDNP_OK;
+}
+
+extern "C" mdnp_status mdnp_sys_coupling_sizes(const mdnp_sys* s, int32_t inst, int64_t* n_gauss, int64_t* b_nnz,
+                                               int64_t* s_nnz) {
+  if (!s || inst < 0 || inst >= s->n_inst) return MDNP_E_ARG;
+  if (n_gauss) *n_gauss = s->c_gauss[inst];
+  if (b_nnz) *b_nnz = s->c_bnnz[inst];
+  if (s_nnz) *s_nnz = s->c_snnz[inst];
   return MDNP_OK;
 }
 

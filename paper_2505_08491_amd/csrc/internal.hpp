@@ -171,6 +171,7 @@ struct mdnp_sys {
   std::vector<int64_t> nnz_off;    // [n_inst + 1]
   int64_t ntot = 0, nnz_tot = 0, mnz_tot = 0;
   std::vector<int64_t> m_nnz, m_rows;  // per instance: entries and non-empty rows of M
+  std::vector<int64_t> c_gauss, c_bnnz, c_snnz;  // per instance: Gauss points, entries of W B and of B^T | R
   int max_n1d = 0;
   // device arrays
   int64_t* d_off = nullptr;
@@ -192,6 +193,18 @@ struct mdnp_sys {
   double* d_a01v64 = nullptr;
   float* d_a01v32 = nullptr;
   int32_t* d_m3e = nullptr;        // [rows listed] end of each listed row's 3D-column M entries
+  // M in factored form, M = B^T W B + R (the stencil-sweep path): a first pass
+  // t = W B x over the Gauss points, then B^T t + R x over the listed rows
+  int32_t* d_gp = nullptr;         // [Gauss points + 1] entry offsets of W B
+  int32_t* d_gsplit = nullptr;     // [Gauss points] end of each point's 3D-column entries
+  int32_t* d_gcol = nullptr;       // global x indices
+  double* d_gval64 = nullptr;      // W_q B_q entries
+  float* d_gval32 = nullptr;
+  int32_t* d_sp = nullptr;         // [rows listed + 1] entry offsets of B^T | R
+  int32_t* d_scol = nullptr;       // >= 0: a Gauss point (global index into t), < 0: ~(global x index)
+  double* d_sval64 = nullptr;
+  float* d_sval32 = nullptr;
+  double* d_ct = nullptr;          // [Gauss points] t, FP64 or FP32 as the vectors
   double* d_dinv = nullptr;        // [ntot] 1 / diag(A)
   float* d_dinv32 = nullptr;       // the same in FP32 (relaxation steps of the smoothing)
   float* d_dist = nullptr;         // [n_inst * n3d]
@@ -238,6 +251,7 @@ struct mdnp_sys {
   mdnp::Blocks blk3;               // 3D parts only
   mdnp::Blocks mblk;               // coupling-row lists
   mdnp::Blocks mblk3;              // coupling-row lists, 3D rows only
+  mdnp::Blocks gblk;               // Gauss-point lists
   // preconditioner
   mdnp_prec_kind kind = MDNP_PREC_NONE;
   bool prec_set = false;

@@ -203,12 +203,90 @@ __device__ __forceinline__ double lane_value(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-template <typename Tv, typename Tacc, int SUM = 0, int NX = 1>
+// The coupling M = B^T W B + R in factored form (eq. "mainsys": every Gauss
+// point q contributes W_q (Pi_q u - Phi_q u1)(Pi_q v - Phi_q v1)).  First
+// pass: t[q] = W_q B_q x over the Gauss points (W_q folded into the stored
+// entries); for A00 the 3D-column entries only, W_q Pi_q x (on x + x2 when x2
+// is given).  It runs in workgroups appended to the stencil sweep's grid.
+struct CgArgs {
+  const int32_t* gp = nullptr;      // [points + 1] entry offsets
+  const int32_t* gsplit = nullptr;  // [points] end of each point's 3D-column entries
+  const int32_t* gcol = nullptr;    // global x indices
+  const void* gval = nullptr;       // W_q B_q entries (the vector type)
+  void* t = nullptr;                // [points] out
+  const int32_t* binst = nullptr;   // Gauss-point lists
+  const int64_t* bstart = nullptr;
+  const int64_t* bend = nullptr;
+  int nblk = 0;
+};
+
+constexpr int CG_G = 4;  // lanes per Gauss point
+constexpr int CS_G = 4;  // lanes per listed row of the second pass
+
+// Logical block of physical workgroup p (as xcd_logical_block, for a range of
+// the grid that starts at a multiple of 8).
+__device__ __forceinline__ int xcd_logical_block_at(int nlog, int p) {
+  const int per = (nlog + 7) / 8;
+  const int b = (p % 8) * per + p / 8;
+  return b < nlog ? b : -1;
+}
+
+// G lanes per Gauss point, U = 16 / G entries per lane per pass with the
+// loads of a pass in flight together (indices clamped into the point's range).
+template <typename T, int G, int A00>
+__device__ __forceinline__ void cgather_block(const CgArgs& a, int b, const T* __restrict__ x,
+                                              const T* __restrict__ x2, const InstState* st, int mask) {
+  const int i = a.binst[b];
+  if (mask == 1 && !st[i].active) return;
+  const int32_t* __restrict__ gcol = a.gcol;
+  const T* __restrict__ gval = (const T*)a.gval;
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = 256 / G;
+  constexpr int U = 16 / G;
+  for (int64_t q = a.bstart[b] + grp; q < a.bend[b]; q += ng) {
+    T acc = 0;
+    const int e = A00 ? a.gsplit[q] : a.gp[q + 1];
+    for (int k0 = a.gp[q] + lane; k0 < e; k0 += U * G) {
+      int c[U];
+      T v[U], xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = min(k0 + u * G, e - 1);
+        c[u] = gcol[k];
+        v[u] = gval[k];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+      if (A00 && x2) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] += x2[c[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (k0 + u * G < e) acc += v[u] * xv[u];
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+    if (lane == 0) ((T*)a.t)[q] = acc;
+  }
+}
+
+// CG = 1 or 2: workgroups past the sweep's (a multiple of 8) run the first
+// pass of the factored coupling, t = W B x (1) or W Pi x (2, A00).
+template <typename Tv, typename Tacc, int SUM = 0, int NX = 1, int CG = 0>
 __global__ void __launch_bounds__(256) k_stencil_sweep(const double* __restrict__ stencil, const Tv* __restrict__ x,
                                                        Tv* __restrict__ y, const int64_t* __restrict__ off, int n,
                                                        int ytiles, int zc, int nfz, int ntile, const InstState* st,
-                                                       int mask, const Tv* __restrict__ x2 = nullptr) {
+                                                       int mask, const Tv* __restrict__ x2 = nullptr,
+                                                       CgArgs cg = CgArgs()) {
   constexpr int NR = SW_TY + 2;
+  if (CG) {
+    const int nsw = (int)(8 * ((((ntile + 3) >> 2) + 7) / 8));
+    if ((int)blockIdx.x >= nsw) {
+      const int b = xcd_logical_block_at(cg.nblk, (int)blockIdx.x - nsw);
+      if (b >= 0) cgather_block<Tv, CG_G, CG == 2>(cg, b, x, x2, st, mask);
+      return;
+    }
+  }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int lb = xcd_logical_block((ntile + 3) >> 2);
   if (lb < 0) return;
@@ -460,6 +538,60 @@ __global__ void __launch_bounds__(BS) k_mrows(const int32_t* __restrict__ mrows,
   if (RES == 1) {
     const double t = block_sum(loc, sh);
     if (threadIdx.x == 0) part[b] = t;
+  }
+}
+
+// Second pass over the listed coupling rows, G lanes per row: the row's
+// entries of B^T (column >= 0: a Gauss point, read from t) and of R (column
+// < 0: ~index into x; x + x2 when x2 is given).  RES = 2: the sum overwrites
+// a 1D row and is added to a 3D row (y holds its stencil part); RES = 3 (3D
+// rows only): added.
+template <typename T, int G, int RES>
+__global__ void __launch_bounds__(BS) k_cscatter(const int32_t* __restrict__ mrows, const int32_t* __restrict__ sp,
+                                                 const int32_t* __restrict__ scol, const T* __restrict__ sval,
+                                                 const T* __restrict__ t, const T* __restrict__ x,
+                                                 const T* __restrict__ x2, T* __restrict__ y, const int32_t* binst,
+                                                 const int64_t* bstart, const int64_t* bend, const InstState* st,
+                                                 int mask, int nblk, const int64_t* off, int n3d) {
+  const int b = xcd_logical_block(nblk);
+  if (b < 0) return;
+  const int i = binst[b];
+  if (mask == 1 && !st[i].active) return;
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G, ng = BS / G;
+  constexpr int U = 8 / G;
+  for (int64_t q = bstart[b] + grp; q < bend[b]; q += ng) {
+    const int row = mrows[q];
+    T acc = 0;
+    const int e = sp[q + 1];
+    for (int k0 = sp[q] + lane; k0 < e; k0 += U * G) {
+      int c[U];
+      T v[U], xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = min(k0 + u * G, e - 1);
+        c[u] = scol[k];
+        v[u] = sval[k];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const T* src = c[u] >= 0 ? t + c[u] : x + ~c[u];
+        xv[u] = *src;
+      }
+      if (x2) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (c[u] < 0) xv[u] += x2[~c[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (k0 + u * G < e) acc += v[u] * xv[u];
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+    if (lane == 0) {
+      if (RES == 2 && row - off[i] >= n3d) y[row] = acc;
+      else y[row] += acc;
+    }
   }
 }
 
@@ -1497,7 +1629,7 @@ __global__ void __launch_bounds__(BS) k_update_x(const T* __restrict__ Z, int64_
 // The stencil sweep over the batch: waves of SW_TY rows x a z range, the z
 // split aimed at s->sweep_target waves (default 2048), plus the x = 0 copy
 // waves.  Only for n <= SW_NMAX.
-template <typename T, int SUM>
+template <typename T, int SUM, int CG = 0>
 void launch_sweep(mdnp_sys* s, const T* x, T* y, const T* x2, const InstState* st, int mk, hipStream_t stream) {
   const int n = s->n;
   const int ytiles = (n + SW_TY - 1) / SW_TY;
@@ -1508,13 +1640,42 @@ void launch_sweep(mdnp_sys* s, const T* x, T* y, const T* x2, const InstState* s
   nz = (n + zc - 1) / zc;
   const int nfz = (n + SW_FZ - 1) / SW_FZ;
   const int ntile = (nfz + ytiles * nz) * s->n_inst;
-  const dim3 grid(xcd_grid((ntile + 3) / 4));
+  CgArgs cg;
+  if (CG) {
+    cg.gp = s->d_gp;
+    cg.gsplit = s->d_gsplit;
+    cg.gcol = s->d_gcol;
+    cg.gval = sizeof(T) == 8 ? (const void*)s->d_gval64 : (const void*)s->d_gval32;
+    cg.t = s->d_ct;
+    cg.binst = s->gblk.inst;
+    cg.bstart = s->gblk.start;
+    cg.bend = s->gblk.end;
+    cg.nblk = s->gblk.nblk;
+  }
+  const dim3 grid(xcd_grid((ntile + 3) / 4) + (CG ? xcd_grid(cg.nblk) : 0u));
   if (n <= 65)
-    hipLaunchKernelGGL((k_stencil_sweep<T, T, SUM, 1>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, nfz, ntile, st, mk, x2);
+    hipLaunchKernelGGL((k_stencil_sweep<T, T, SUM, 1, CG>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off,
+                       n, ytiles, zc, nfz, ntile, st, mk, x2, cg);
   else
-    hipLaunchKernelGGL((k_stencil_sweep<T, T, SUM, 2>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off, n,
-                       ytiles, zc, nfz, ntile, st, mk, x2);
+    hipLaunchKernelGGL((k_stencil_sweep<T, T, SUM, 2, CG>), grid, dim3(256), 0, stream, s->d_stencil, x, y, s->d_off,
+                       n, ytiles, zc, nfz, ntile, st, mk, x2, cg);
+}
+
+// Second pass of the factored coupling over the listed rows (all, or the 3D
+// rows for A00).  Its input t is one buffer per system: calls on one system
+// are serialised on its stream.
+template <typename T>
+void launch_coupling_rows(mdnp_sys* s, const T* x, T* y, const InstState* st, int mk, bool a00, hipStream_t stream,
+                          const T* x2 = nullptr) {
+  const T* sv = sizeof(T) == 8 ? (const T*)s->d_sval64 : (const T*)s->d_sval32;
+  if (a00)
+    hipLaunchKernelGGL((k_cscatter<T, CS_G, 3>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream, s->d_mrows,
+                       s->d_sp, s->d_scol, sv, (const T*)s->d_ct, x, x2, y, MBLK3(s), st, mk, s->mblk3.nblk, s->d_off,
+                       s->n3d);
+  else
+    hipLaunchKernelGGL((k_cscatter<T, CS_G, 2>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
+                       s->d_sp, s->d_scol, sv, (const T*)s->d_ct, x, (const T*)nullptr, y, MBLK(s), st, mk,
+                       s->mblk.nblk, s->d_off, s->n3d);
 }
 
 template <typename T>
@@ -1535,15 +1696,8 @@ void launch_spmv(mdnp_sys* s, const T* x, T* y, const InstState* st, bool mask, 
     }
     return;
   }
-  if (sizeof(T) == 8) {
-    launch_sweep<T, 0>(s, x, y, (const T*)nullptr, st, mk, stream);
-    hipLaunchKernelGGL((k_mrows<T, double, double, 4, 2>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
-                       s->d_mlp, s->d_mcol, s->d_mval64, x, y, MBLK(s), st, mk, (double*)nullptr, s->mblk.nblk, s->d_off, s->n3d);
-  } else {
-    launch_sweep<T, 0>(s, x, y, (const T*)nullptr, st, mk, stream);
-    hipLaunchKernelGGL((k_mrows<T, float, float, 4, 2>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
-                       s->d_mlp, s->d_mcol, s->d_mval32, x, y, MBLK(s), st, mk, (double*)nullptr, s->mblk.nblk, s->d_off, s->n3d);
-  }
+  launch_sweep<T, 0, 1>(s, x, y, (const T*)nullptr, st, mk, stream);
+  launch_coupling_rows<T>(s, x, y, st, mk, false, stream);
 }
 template void launch_spmv<float>(mdnp_sys*, const float*, float*, const InstState*, bool, hipStream_t);
 template void launch_spmv<double>(mdnp_sys*, const double*, double*, const InstState*, bool, hipStream_t);
@@ -1611,11 +1765,9 @@ void launch_a00(mdnp_sys* s, const T* x, T* y, const InstState* st, hipStream_t 
                        s->n3d, s->d_m3e, (const T*)nullptr);
     return;
   }
-  if (x2) launch_sweep<T, 1>(s, x, y, x2, st, mk, stream);
-  else launch_sweep<T, 0>(s, x, y, (const T*)nullptr, st, mk, stream);
-  hipLaunchKernelGGL((k_mrows<T, Tm, Tm, 4, 3>), dim3(xcd_grid(s->mblk3.nblk)), dim3(BS), 0, stream, s->d_mrows,
-                     s->d_mlp, s->d_mcol, mv, x, y, MBLK3(s), st, mk, (double*)nullptr, s->mblk3.nblk, s->d_off,
-                     s->n3d, s->d_m3e, x2);
+  if (x2) launch_sweep<T, 1, 2>(s, x, y, x2, st, mk, stream);
+  else launch_sweep<T, 0, 2>(s, x, y, (const T*)nullptr, st, mk, stream);
+  launch_coupling_rows<T>(s, x, y, st, mk, true, stream, x2);
 }
 
 template void launch_a00<float>(mdnp_sys*, const float*, float*, const InstState*, hipStream_t, const float*);

@@ -63,6 +63,76 @@ def test_pattern_and_values_match_oracle(which):
     assert np.max(np.abs(h.dist - s.dist)) < 1e-7           # stored in FP32
 
 
+@pytest.mark.parametrize("which", ["single16", "batched", "neumann20", "block3d20"])
+def test_factored_coupling_matches_oracle(which):
+    """The factored coupling M = B^T W B + R (eq. "mainsys") that the
+    stencil-sweep path applies, against the oracle's Pi, Phi and W: B =
+    [Pi | -Phi] on the free nodes (no 1D columns in the 3D-block layout), the
+    Gauss weights, R = the 1D stiffness (unit 1D rows in the 3D-block layout)
+    plus, under the natural boundary only, stencil entries on boundary rows or
+    columns.  What is left of A, A - B^T W B - R, has no 1D entry and is the
+    27-point stencil: translation invariant between interior nodes."""
+    import scipy.sparse as sp
+
+    def neumann20():
+        i = synth.workload_block3d(20, 1)[0]
+        i.problem = "coupled"
+        return i
+    inst = {"single16": lambda: synth.workload_single_fp64()[0],
+            "batched": lambda: synth.workload_batched_32(5)[4],
+            "neumann20": neumann20,
+            "block3d20": lambda: synth.workload_block3d(20, 1)[0]}[which]()
+    blk3d = getattr(inst, "problem", "coupled") == "block3d"
+    dirichlet = getattr(inst, "boundary", "dirichlet") == "dirichlet"
+    h = _lib().host_assemble(inst)
+    s = fem.assemble(inst)
+    n3d, n1d = s.n3d, s.n1d
+    B, w, R, bsplit = h.coupling()
+    assert B.shape[0] == s.Pi.shape[0] == w.size
+    elim = s.boundary if dirichlet else np.zeros(n3d, dtype=bool)
+    Pi_free = (s.Pi @ sp.diags((~elim).astype(np.float64))).tocsr()
+    assert abs(B[:, :n3d] - Pi_free).max() <= 1e-14 * abs(s.Pi).max()
+    if blk3d:
+        assert B[:, n3d:].nnz == 0
+    else:
+        assert abs(B[:, n3d:] + s.Phi).max() <= 1e-15
+    assert np.allclose(w, s.W, rtol=1e-14, atol=0)
+    # row layout: the 3D columns ascending, then the 1D ones from bsplit
+    for q in range(0, B.shape[0], max(1, B.shape[0] // 97)):
+        c3 = B.indices[B.indptr[q]:bsplit[q]]
+        c1 = B.indices[bsplit[q]:B.indptr[q + 1]]
+        assert np.all(np.diff(c3) > 0) and np.all(c3 < n3d) and np.all(c1 >= n3d)
+    # R
+    R1 = R[n3d:, :]
+    if blk3d:
+        assert abs(R1 - sp.hstack([sp.csr_matrix((n1d, n3d)), sp.identity(n1d)])).max() == 0
+    else:
+        ref = sp.hstack([sp.csr_matrix((n1d, n3d)), s.K11])
+        assert abs(R1 - ref).max() <= 1e-14 * abs(s.K11).max()
+    R3 = R[:n3d, :].tocoo()
+    n = s.n_cells + 1
+    ijk = np.stack(np.unravel_index(np.arange(n3d), (n, n, n)), axis=1)
+    geo_bnd = np.any((ijk == 0) | (ijk == n - 1), axis=1)
+    if dirichlet:
+        assert R3.nnz == 0
+    else:
+        assert R3.nnz > 0 and np.all(geo_bnd[R3.row] | geo_bnd[R3.col])
+    # the remainder
+    scale = abs(s.A).max()
+    D = (s.A - B.T @ sp.diags(w) @ B - R).tocoo()
+    big = np.abs(D.data) > 1e-13 * scale
+    r, c, v = D.row[big], D.col[big], D.data[big]
+    assert np.all(r < n3d) and np.all(c < n3d)
+    d = np.abs(ijk[r] - ijk[c])
+    assert np.all(d <= 1)
+    inner = ~geo_bnd[r] & ~geo_bnd[c]
+    nd = d.sum(axis=1)[inner]
+    for k in range(4):
+        vk = v[inner][nd == k]
+        if vk.size:
+            assert np.ptp(vk) <= 1e-12 * scale, (k, vk.min(), vk.max())
+
+
 def test_tree_factorisation_solves_a11():
     """The leaves-first LDL^T used by the GPU 1D solve reproduces A11^-1 (P3: 1e-12)."""
     for inst in (synth.workload_single_fp64()[0], synth.workload_transfer(64, 1)[0]):
