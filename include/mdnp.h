@@ -271,6 +271,14 @@ mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* sys, int32_t steps);
  * (the defaults are kept). */
 mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* sys, int32_t* chosen);
 
+/* Sets the launch shapes directly, in the layout mdnp_autotune reports
+ * (`chosen` [23], host; 0 = the built-in default): to restore a tuning
+ * without timing it again, or to pick one shape.  Any code is safe (codes
+ * outside the candidate sets select the default shape); every choice gives
+ * the same results.  Errors: MDNP_E_ARG for a null pointer or a negative
+ * code. */
+mdnp_status mdnp_set_tuning(mdnp_ctx* ctx, mdnp_sys* sys, const int32_t* chosen);
+
 /* Time the network as the solver applies it (Section 4.2 U-net inside the
  * 3D block of eq. "twosteps"), stage by stage, on this system's batch and
  * grid with the launch shapes currently chosen: after one application to a

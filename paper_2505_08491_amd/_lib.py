@@ -58,6 +58,7 @@ SIGNATURES = [
     ("mdnp_set_smoothing", C.c_int, [VP, VP, C.c_int32, C.c_double]),
     ("mdnp_set_inner_steps", C.c_int, [VP, VP, C.c_int32]),
     ("mdnp_autotune", C.c_int, [VP, VP, P(C.c_int32)]),
+    ("mdnp_set_tuning", C.c_int, [VP, VP, P(C.c_int32)]),
     ("mdnp_cnn_layer_times", C.c_int, [VP, VP, C.c_int32, P(C.c_float)]),
     ("mdnp_solve", C.c_int, [VP, VP, VP, VP, P(SolveOpts), P(InstStats)]),
     ("mdnp_solve_device", C.c_int, [VP, VP, VP, VP, P(SolveOpts), P(InstStats), VP]),

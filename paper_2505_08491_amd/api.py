@@ -302,6 +302,11 @@ class System:
         self.ctx._check(lib.mdnp_autotune(self.ctx.h, self.h, out))
         return list(out)
 
+    def set_tuning(self, chosen):
+        """Set the launch shapes in the layout `autotune` returns."""
+        arr = (C.c_int32 * 23)(*[int(v) for v in chosen])
+        self.ctx._check(lib.mdnp_set_tuning(self.ctx.h, self.h, arr))
+
     def layer_times(self, reps: int = 5):
         """Average milliseconds of each stage of the in-solver network
         application (L0a, L0b, L1a, L1b, L2a, L2b, U1, D1, U0, D0 + head),

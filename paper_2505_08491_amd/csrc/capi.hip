@@ -899,6 +899,27 @@ extern "C" mdnp_status mdnp_autotune(mdnp_ctx* ctx, mdnp_sys* s, int32_t* chosen
   });
 }
 
+extern "C" mdnp_status mdnp_set_tuning(mdnp_ctx* ctx, mdnp_sys* s, const int32_t* chosen) {
+  if (!ctx) return MDNP_E_ARG;
+  return guarded(ctx, [&] {
+    if (!s || !chosen) fail(MDNP_E_ARG, "null argument");
+    for (int k = 0; k < 23; ++k)
+      if (chosen[k] < 0) fail(MDNP_E_ARG, "launch-shape codes are >= 0");
+    HIPCHK(hipSetDevice(ctx->device));
+    drop_graphs(s->work);  // captured with the old launch shapes
+    for (int l = 0; l < 11; ++l) s->cnn.sweep_blocks[l] = chosen[l];
+    s->sweep_target = chosen[11];
+    s->cnn.tile_mb[3] = chosen[12];
+    s->cnn.tile_mb[7] = chosen[13];
+    s->cnn.tile_mb[1] = chosen[14];
+    s->cnn.tile_mb[9] = chosen[15];
+    s->cnn.tile_mb[6] = chosen[16];
+    s->cnn.tile_mb[8] = chosen[17];
+    const int xl[5] = {0, 1, 3, 7, 9};
+    for (int k = 0; k < 5; ++k) s->cnn.tile_xb[xl[k]] = chosen[18 + k];
+  });
+}
+
 extern "C" mdnp_status mdnp_cnn_layer_times(mdnp_ctx* ctx, mdnp_sys* s, int32_t reps, float* ms) {
   if (!ctx) return MDNP_E_ARG;
   return guarded(ctx, [&] {

@@ -848,6 +848,38 @@ def test_neural_solve_128(ctx, bench128):
     assert st[0]["converged"] and not st[0]["used_fallback"] and rel <= 1e-8
 
 
+@pytest.mark.parametrize("n_cells,count", [(32, 3), (64, 2), (128, 1)])
+def test_launch_shapes_keep_output(ctx, n_cells, count):
+    """Launch shapes set directly (the codes the autotuner reports): every
+    choice of output rows per wave pair of L0b and of the three-plane D0 sweep,
+    x blocks per workgroup and z splits gives Q(v) bit for bit equal to the
+    defaults, at 33^3, 65^3 (the benchmark grid) and 129^3 (two workgroups
+    across x)."""
+    from paper_2505_08491_amd import weights as W
+    P = _P()
+    S = P.System(ctx, synth.workload_transfer(n_cells, count), vec_dtype="f32")
+    try:
+        wpath = W.default_path()
+        th = W.load(wpath)[0] if __import__("os").path.exists(wpath + ".bin") else _theta(5).astype(np.float32)
+        S.set_preconditioner("neural", weights=th, cnn_dtype="bf16")
+        v = dev(synth.fast_normal(40 + n_cells, S.ntot).astype(np.float32), torch.float32)
+        S.set_tuning([0] * 23)
+        z0 = S.precond_apply(v).clone()
+        for l0b, d0, xb, zs in ((3, 12, 1, 256), (4, 13, 2, 2048), (6, 14, 4, 768), (5, 12, 2, 384)):
+            t = [0] * 23
+            t[14], t[15] = l0b, d0
+            t[18:23] = [xb] * 5
+            for layer in (0, 1, 3, 5, 7, 9):
+                t[layer] = zs
+            S.set_tuning(t)
+            z = S.precond_apply(v)
+            assert torch.equal(z, z0), t
+        with pytest.raises(P.MdnpError):
+            S.set_tuning([-1] + [0] * 22)
+    finally:
+        S.free()
+
+
 @pytest.mark.parametrize("variant", ["smooth", "inner"])
 def test_3d_solve_variants_batched_129(ctx, variant):
     """At 129^3 (general-size A00 kernels) the smoothed and the inner-FGMRES
