@@ -257,7 +257,7 @@ mdnp_status mdnp_set_inner_steps(mdnp_ctx* ctx, mdnp_sys* sys, int32_t steps);
  * ({256 .. 4096}; each workgroup stages its weights in LDS and loops over
  * voxel blocks) and the 16-column x blocks per workgroup of L0a, L0b, D0
  * {1, 2, 4} and L1b, D1 {1, 2} (rows wider than that split over workgroups);
- * coordinate descent, best of 5 whole network applications.
+ * two rounds of coordinate descent, best of 5 whole network applications.
  * The choices only move output planes between waves and workgroups: results
  * are unchanged.  They are kept with the system; `chosen` (nullable, [23])
  * receives them: [0 .. 10] the z split or M blocks of the convolution layers

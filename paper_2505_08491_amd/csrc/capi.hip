@@ -141,7 +141,7 @@ void free_inner(InnerState& q) {
 void free_sys(mdnp_sys* s) {
   free_smooth(s->smooth);
   free_inner(s->inner);
-  void* ptrs[] = {s->d_off, s->d_stencil, s->d_mptr, s->d_mcol, s->d_mval64, s->d_mval32, s->d_ma01, s->d_mrows, s->d_mlp,
+  void* ptrs[] = {s->d_off, s->d_stencil, s->d_mptr, s->d_mfree, s->d_mcol, s->d_mval64, s->d_mval32, s->d_ma01, s->d_mrows, s->d_mlp,
                   s->d_a01p, s->d_a01c, s->d_a01v64, s->d_a01v32, s->d_m3e, s->d_gp, s->d_gsplit, s->d_gcol,
                   s->d_gval64, s->d_gval32, s->d_sp, s->d_scol, s->d_sval64, s->d_sval32, s->d_ct,
                   s->d_dinv, s->d_dinv32, s->d_dist,
@@ -490,6 +490,11 @@ extern "C" mdnp_status mdnp_upload(mdnp_ctx* ctx, const mdnp_instance_desc* desc
     s->d_off = dupload(s->off, stream);
     s->d_stencil = dupload(stn, stream);
     s->d_mptr = dupload(mp, stream);
+    {
+      std::vector<uint8_t> mf(mp.size() - 1);
+      for (size_t r = 0; r + 1 < mp.size(); ++r) mf[r] = mp[r + 1] == mp[r] ? 1 : 0;
+      s->d_mfree = dupload(mf, stream);
+    }
     s->d_mcol = dupload(mc, stream);
     s->d_mval64 = dupload(mv64, stream);
     s->d_mval32 = dupload(mv32, stream);

@@ -1098,7 +1098,7 @@ bool cnn_layer_times(mdnp_sys* s, hipStream_t stream, int reps, float* ms) {
 // their output rows per workgroup, for the stride-2 and transposed layers the
 // 16-voxel M blocks per wave, for the transposed layers also the workgroup
 // count (each workgroup stages its weights once and loops over voxel blocks).
-// Coordinate descent over the layers, each candidate timed as the best of
+// Two rounds of coordinate descent over the layers, each candidate timed as the best of
 // `reps` whole in-solver network applications with HIP events.  The shape only
 // decides which wave computes which outputs, in the same order of
 // accumulation, so results are the same for every choice.
@@ -1163,21 +1163,25 @@ static bool autotune_t(mdnp_sys* s, hipStream_t stream, int reps) {
   };
   if (ok) {
     time_once();  // warm-up
-    for (const TuneLayer& tl : kTune) {
-      const int layer = tl.layer;
-      int* slot = tl.rows == 1 ? &c.tile_mb[layer] : tl.rows == 2 ? &c.tile_xb[layer] : &c.sweep_blocks[layer];
-      int best_t = *slot;
-      float best = 1e30f;
-      for (int q = 0; q < tl.n; ++q) {
-        const int t = tl.cand[q];
-        *slot = t;
-        const float ms = time_once();
-        if (ms < best) {
-          best = ms;
-          best_t = t;
+    // two rounds of coordinate descent: the second revisits each layer with
+    // the others at their tuned shapes
+    for (int round = 0; round < 2; ++round) {
+      for (const TuneLayer& tl : kTune) {
+        const int layer = tl.layer;
+        int* slot = tl.rows == 1 ? &c.tile_mb[layer] : tl.rows == 2 ? &c.tile_xb[layer] : &c.sweep_blocks[layer];
+        int best_t = *slot;
+        float best = 1e30f;
+        for (int q = 0; q < tl.n; ++q) {
+          const int t = tl.cand[q];
+          *slot = t;
+          const float ms = time_once();
+          if (ms < best) {
+            best = ms;
+            best_t = t;
+          }
         }
+        *slot = best_t;
       }
-      *slot = best_t;
     }
   }
   if (e0) (void)hipEventDestroy(e0);

@@ -182,6 +182,7 @@ struct mdnp_sys {
   bool neumann = false;            // natural boundary on the cube faces (every instance)
   int sweep_target = 0;            // workgroups aimed at by the stencil sweep's z split (0: 2048)
   int32_t* d_mptr = nullptr;       // [ntot + 1], global entry offsets
+  uint8_t* d_mfree = nullptr;      // [ntot] 1 where the row has no M entry
   int32_t* d_mcol = nullptr;       // global column indices
   double* d_mval64 = nullptr;
   float* d_mval32 = nullptr;

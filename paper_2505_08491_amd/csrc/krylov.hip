@@ -958,7 +958,7 @@ __global__ void __launch_bounds__(64) k_chain_back(const T* __restrict__ v, T* _
 // written by exactly one block.
 template <typename T, typename Tm, int G>
 __global__ void __launch_bounds__(BS) k_ext(const T* __restrict__ v, T* __restrict__ z,
-                                            const int32_t* __restrict__ mptr, const int64_t* off,
+                                            const uint8_t* __restrict__ mfree, const int64_t* off,
                                             const int32_t* cinst, const int64_t* cstart, const int64_t* cend, int ncopy,
                                             const int32_t* __restrict__ mrows, const int32_t* __restrict__ ap,
                                             const int32_t* __restrict__ ac, const Tm* __restrict__ av,
@@ -984,7 +984,7 @@ __global__ void __launch_bounds__(BS) k_ext(const T* __restrict__ v, T* __restri
       for (int u = 0; u < U; ++u) {
         const int64_t g = base + min(r0 + (int64_t)u * BS, r1 - 1);
         vl[u] = v[g];
-        free_row[u] = mptr[g + 1] == mptr[g];
+        free_row[u] = mfree[g] != 0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -1977,11 +1977,11 @@ void launch_extension(mdnp_sys* s, const T* v, T* z, double* part3, double* part
   T* sb = smooth_first ? (T*)s->smooth.sb : nullptr;
   const double om = s->smooth.omega;
   if (sizeof(T) == 8)
-    hipLaunchKernelGGL((k_ext<T, double, 4>), dim3(nb), dim3(BS), 0, stream, v, z, s->d_mptr, s->d_off, BLK3(s),
+    hipLaunchKernelGGL((k_ext<T, double, 4>), dim3(nb), dim3(BS), 0, stream, v, z, s->d_mfree, s->d_off, BLK3(s),
                        s->blk3.nblk, s->d_mrows, s->d_a01p, s->d_a01c, s->d_a01v64, MBLK3(s), st, want_mode, part3,
                        part3m, sb, s->d_dinv32, om);
   else
-    hipLaunchKernelGGL((k_ext<T, float, 4>), dim3(nb), dim3(BS), 0, stream, v, z, s->d_mptr, s->d_off, BLK3(s),
+    hipLaunchKernelGGL((k_ext<T, float, 4>), dim3(nb), dim3(BS), 0, stream, v, z, s->d_mfree, s->d_off, BLK3(s),
                        s->blk3.nblk, s->d_mrows, s->d_a01p, s->d_a01c, s->d_a01v32, MBLK3(s), st, want_mode, part3,
                        part3m, sb, s->d_dinv32, om);
 }
