@@ -623,6 +623,32 @@ __global__ void __launch_bounds__(BS) k_norm2_part(const double* __restrict__ x,
   if (threadIdx.x == 0) part[b] = t;
 }
 
+// r = b - r over whole vectors (r holding A x), with the partial sums of r^2
+// per block; instances already done (mask 2) are skipped with a zero partial.
+// The partials of the coupling-row blocks (partm, nm of them), which this form
+// of the residual does not use, are cleared by the same launch.
+__global__ void __launch_bounds__(BS) k_residual_part(const double* __restrict__ b, double* __restrict__ r,
+                                                      const int32_t* binst, const int64_t* bstart,
+                                                      const int64_t* bend, const InstState* st, int mask,
+                                                      double* part, double* partm, int nm) {
+  __shared__ double sh[BS / 64];
+  const int blk = blockIdx.x;
+  for (int k = blk * BS + threadIdx.x; k < nm; k += gridDim.x * BS) partm[k] = 0.0;
+  const int i = binst[blk];
+  if (mask == 2 && st[i].done) {
+    if (threadIdx.x == 0) part[blk] = 0.0;
+    return;
+  }
+  double loc = 0.0;
+  for (int64_t e = bstart[blk] + threadIdx.x; e < bend[blk]; e += blockDim.x) {
+    const double v = b[e] - r[e];
+    r[e] = v;
+    loc += v * v;
+  }
+  const double t = block_sum(loc, sh);
+  if (threadIdx.x == 0) part[blk] = t;
+}
+
 // ---------------------------------------------------------------- cycle control
 
 // One wavefront per instance (grid = n_inst, 64 threads).
@@ -1883,6 +1909,14 @@ template void launch_spmv_a00_all<double>(mdnp_sys*, const double*, double*, hip
 void launch_residual(mdnp_sys* s, const double* b, const double* x, double* r, double* part, double* partm,
                      const InstState* st, hipStream_t stream) {
   const int mk = st ? 2 : 0;
+  if (s->n <= SW_NMAX) {
+    // the FP64 operator in its split form (stencil sweep, factored coupling)
+    // over every instance, then r = b - A x and its squares
+    launch_spmv<double>(s, x, r, nullptr, false, stream);
+    hipLaunchKernelGGL(k_residual_part, dim3(s->blk.nblk), dim3(BS), 0, stream, b, r, BLK(s), st, mk, part, partm,
+                       s->mblk.nblk);
+    return;
+  }
   hipLaunchKernelGGL((k_stencil<double, double, 1>), dim3(s->blk.nblk), dim3(BS), 0, stream, s->d_stencil, s->d_mptr,
                      x, b, r, s->d_off, s->n, s->n3d, BLK(s), st, mk, part);
   hipLaunchKernelGGL((k_mrows<double, double, double, 8, 1>), dim3(xcd_grid(s->mblk.nblk)), dim3(BS), 0, stream, s->d_mrows,
