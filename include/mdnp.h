@@ -327,7 +327,10 @@ mdnp_status mdnp_export_basis(mdnp_ctx* ctx, const mdnp_sys* sys, int32_t k, voi
 
 /* y = A x (block 0) or y = A00 x on the 3D unknowns only (block 1, vectors of
  * length n_inst * n3d), for every instance.  dtype MDNP_F64 or MDNP_F32 selects
- * the value array and the vector type. */
+ * the value array and the vector type.  Block 0 applies the coupling through a
+ * per-system intermediate (one value per Gauss point), as the solver does:
+ * calls on one system, this one included, must not overlap in time (issue
+ * them on one stream). */
 mdnp_status mdnp_spmv(mdnp_ctx* ctx, mdnp_sys* sys, int32_t block, const void* d_x, void* d_y,
                       mdnp_dtype dtype, void* hip_stream);
 
